@@ -1,0 +1,229 @@
+"""Seeded synthetic workloads at the benchmark configurations.
+
+The paper measures on 22 programs from public suites (section 7); none of
+them is reproduced here.  These seeded workloads stand in for them, with the
+access shapes the paper shows (affine 1-D/2-D indexing, thread-id division
+and modulo, host-fixed parameters and launch extents, guards; section 4,
+Figures 1-5).
+
+Every generator is deterministic in its seed (numpy PCG64).  Races are
+planted structurally (a non-injective thread-to-address map); race freedom is
+planted by range separation or by an injective map.  Nothing here evaluates an
+expression: the labels used by the tests come from the oracle.
+"""
+import numpy as np
+
+from .expr import bid, bdim, tid, param, loop, c, lt, ge, emin, ne
+from .model import (Access, Array, Launch, Loop, Model, Workload, GLOBAL,
+                    SHARED, READ, WRITE, ALL_CLASSES)
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ---------------------------------------------------------------------------
+# tiny plain config: one model, 64 pairs
+
+def tiny(seed=1001, n_pairs=64):
+    """One model, 64 access pairs, grid 4 x block 64 (1-D), warp 32,
+    loop i in [0, 8), addr = c0 + c1*tid + c2*bid + c3*i + c4*N with every
+    coefficient drawn from [-4, 4], N = 256, one tuple.
+
+    Pairs: half on a shared array, half on a global one; 8 self-pairs
+    (writes), the rest drawn from {W/W, W/R, R/W}.  16 pairs are racy by
+    construction, 48 race-free by construction:
+      * racy: both sides use the same coefficient vector with c1 = 0 (all
+        threads of a block meet at one address in each iteration), or, for
+        shared arrays, c1 != 0 and c3 != 0 (thread t at iteration i meets
+        thread t' at iteration i' whenever c1*(t - t') = c3*(i' - i));
+      * race-free cross pairs: |c4_i - c4_j| >= 3, so the address ranges
+        (each within c4*256 +- 296) are disjoint;
+      * race-free self-pairs: an injective thread map with c3 = 0
+        (shared: c1 != 0; global: c1 = +-4 and c2 odd, so c1*t + c2*b is
+        injective for b < 4).
+    """
+    rng = _rng(seed)
+    G, B, I, N = 4, 64, 8, 256
+    arrays = [Array(SHARED, 32), Array(GLOBAL, 32)]
+    loops = [Loop(0, "lt", I, "add", 1)]
+    accs, pairs, labels = [], [], []
+
+    def coef():
+        return [int(x) for x in rng.integers(-4, 5, size=5)]
+
+    def mk(arr, kind, cf):
+        c0, c1, c2, c3, c4 = cf
+        addr = (c(c0) + c(c1) * tid(0) + c(c2) * bid(0) + c(c3) * loop(0)
+                + c(c4) * param(0))
+        accs.append(Access(arr, kind, addr, None, [0],
+                           name="%s a%d %r" % (kind[0].upper(), arr, cf)))
+        return len(accs) - 1
+
+    def racy_cf(arr):
+        cf = coef()
+        if arr == 0 and rng.random() < 0.5:
+            cf[1] = int(rng.choice([-4, -3, -2, -1, 1, 2, 3, 4]))
+            cf[3] = int(rng.choice([-4, -3, -2, -1, 1, 2, 3, 4]))
+        else:
+            cf[1] = 0
+        return cf
+
+    def free_self_cf(arr):
+        cf = coef()
+        cf[3] = 0
+        if arr == 0:
+            cf[1] = int(rng.choice([-4, -3, -2, -1, 1, 2, 3, 4]))
+        else:
+            cf[1] = int(rng.choice([-4, 4]))
+            cf[2] = int(rng.choice([-3, -1, 1, 3]))
+        return cf
+
+    # plan: per array 4 self-pairs (1 racy) and 28 cross pairs (7 racy)
+    plan = []
+    for arr in (0, 1):
+        plan += [(arr, "self", True)] + [(arr, "self", False)] * 3
+        plan += [(arr, "cross", True)] * 7 + [(arr, "cross", False)] * 21
+    order = rng.permutation(len(plan))
+    kinds = [(WRITE, WRITE), (WRITE, READ), (READ, WRITE)]
+    for k in order:
+        arr, form, racy = plan[k]
+        if form == "self":
+            cf = racy_cf(arr) if racy else free_self_cf(arr)
+            a = mk(arr, WRITE, cf)
+            pairs.append((0, a, a, ALL_CLASSES))
+        else:
+            ka, kb = kinds[int(rng.integers(0, 3))]
+            if racy:
+                cf = racy_cf(arr)
+                a, b = mk(arr, ka, cf), mk(arr, kb, list(cf))
+            else:
+                ci = coef()
+                while True:
+                    cj = coef()
+                    if abs(ci[4] - cj[4]) >= 3:
+                        break
+                a, b = mk(arr, ka, ci), mk(arr, kb, cj)
+            pairs.append((0, a, b, ALL_CLASSES))
+        labels.append(bool(racy))
+    m = Model(1, arrays, accs, Launch((G, 1, 1), (B, 1, 1), 32), [[N]],
+              loops=loops, name="tiny")
+    return Workload([m], pairs[:n_pairs], name="tiny",
+                    meta={"seed": seed, "planted_racy": labels[:n_pairs]})
+
+
+# ---------------------------------------------------------------------------
+# batched uneven config: 256 models x 16 pairs
+
+def _log_uniform_int(rng, lo, hi):
+    return int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+
+
+def batched(seed=2002, n_models=256, pairs_per_model=16, max_grid=1024,
+            max_iters=64, max_sets=16, scale=1.0):
+    """256 models x 16 pairs = 4096 queries of uneven size.
+
+    Per model: grid log-uniform in [1, max_grid] blocks (1-D or 2-D), block
+    of 32..256 threads (1-D or 2-D), one loop of 1..max_iters iterations,
+    parameters (W, N) as joint tuples from a host-derived set of 1..16
+    values (W a power of two or a multiple of the row width, N derived from
+    W: host class 3).  Address terms: tid/32, tid % W, row*W + col, affine
+    in the global thread id and the loop variable.  Guards tid < N - k.
+    int32 addresses.  Shared and global arrays alternate by model.  About
+    30% of pairs are planted racy (non-injective maps or equal bases);
+    labels come from the oracle.  ``scale`` shrinks the grids (for tests).
+    """
+    rng = _rng(seed)
+    models, pairs = [], []
+    for mi in range(n_models):
+        two_d_grid = rng.random() < 0.4
+        nblk = max(1, int(_log_uniform_int(rng, 1, max_grid) * scale))
+        if two_d_grid and nblk >= 4:
+            gx = 1 << int(rng.integers(1, max(2, int(np.log2(nblk)))))
+            gx = min(gx, nblk)
+            gy = max(1, nblk // gx)
+        else:
+            gx, gy = nblk, 1
+        bt = int(rng.choice([32, 64, 128, 256]))
+        two_d_block = rng.random() < 0.4 and bt >= 64
+        if two_d_block:
+            bx = int(rng.choice([16, 32]))
+            by = bt // bx
+        else:
+            bx, by = bt, 1
+        iters = max(1, _log_uniform_int(rng, 1, max_iters))
+        space = SHARED if mi % 2 == 1 else GLOBAL
+        nsets = int(rng.integers(1, max_sets + 1))
+        # host-derived parameter set: W from powers of two or row widths,
+        # N derived jointly from W (one host variable feeds both)
+        Ws = sorted(set(int(x) for x in rng.choice(
+            [1, 2, 4, 8, 16, 32, 64, 128, bx, bx * gx], size=nsets)))
+        sets = [[w, w * int(rng.integers(1, 5)) + bt // 2] for w in Ws]
+        W, Np = param(0), param(1)
+        row = bid(1) * bdim(1) + tid(1)
+        col = bid(0) * bdim(0) + tid(0)
+        tl = tid(0) + bdim(0) * tid(1)
+        blin = bid(0) + c(gx) * bid(1)
+        gid = blin * bt + tl
+        i = loop(0)
+        # per-block extent used to separate bases
+        span_t = 2 * bt * iters + 4096
+        accs = []
+        arr = [Array(space, 32)]
+        for p in range(pairs_per_model):
+            racy = rng.random() < 0.30
+            form = int(rng.integers(0, 4))
+            selfp = rng.random() < 0.25
+            k = int(rng.integers(0, 4))
+            guard = lt(tl, Np - k) if rng.random() < 0.5 else None
+            if space == SHARED:
+                # shared memory is per block: addresses need not name the block
+                if form == 0:
+                    e_ok = tl * iters + i            # injective in (t, i)
+                    e_bad = tl // 32 + i * 8        # 32 threads share
+                elif form == 1:
+                    e_ok = tl + bt * i
+                    e_bad = tl % W + i             # W-periodic
+                elif form == 2:
+                    e_ok = tid(1) * (bx * iters) + tid(0) * iters + i
+                    e_bad = tid(1) * W + tid(0)
+                else:
+                    e_ok = tl * 2 + i * (2 * bt)
+                    e_bad = tl * 2 + i
+            else:
+                if form == 0:
+                    e_ok = gid * iters + i
+                    e_bad = gid // 32 + i * 4
+                elif form == 1:
+                    e_ok = gid + c(gx * gy * bt) * i
+                    e_bad = tl % W + blin * W + i
+                elif form == 2:
+                    e_ok = (row * c(bx * gx) + col) * iters + i
+                    e_bad = row * W + col
+                else:
+                    e_ok = blin * (bt * iters) + tl * iters + i
+                    e_bad = tl + i * 16
+            kinds = [(WRITE, WRITE), (WRITE, READ), (READ, WRITE)]
+            ka, kb = kinds[int(rng.integers(0, 3))]
+            if selfp:
+                e = e_bad if racy else e_ok
+                accs.append(Access(0, WRITE, e, guard, [0]))
+                a = len(accs) - 1
+                pairs.append((mi, a, a, ALL_CLASSES))
+                continue
+            if racy:
+                ea, eb = e_bad, e_bad
+                base_b = 0
+            else:
+                ea, eb = e_ok, e_ok
+                base_b = int(rng.integers(2, 6)) * (span_t * max(1, gx * gy) + (1 << 16))
+                if space == SHARED:
+                    base_b = int(rng.integers(2, 6)) * span_t
+            accs.append(Access(0, ka, ea, guard, [0]))
+            accs.append(Access(0, kb, eb + base_b, guard, [0]))
+            pairs.append((mi, len(accs) - 2, len(accs) - 1, ALL_CLASSES))
+        models.append(Model(2, arr, accs, Launch((gx, gy, 1), (bx, by, 1), 32),
+                            sets, loops=[Loop(0, "lt", iters, "add", 1)],
+                            name="batched%d" % mi))
+    return Workload(models, pairs, name="batched",
+                    meta={"seed": seed, "scale": scale})
