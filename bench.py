@@ -1,0 +1,130 @@
+"""Benchmark: exact race queries per second on one MI355X.
+
+One step = one rd_check_pairs call over the whole batched-uneven workload
+(256 kernel models x 16 access pairs = 4096 queries, seed 2002): host
+lowering, descriptor upload, every generate/partition/join kernel, witness
+pass 2, results back.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, budget_s=20.0, seed=7):
+    """The oracle (sort + prefix groups) on a bounded random sample of pairs,
+    on every host core; scaled to queries/s."""
+    import numpy as np
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(seed))
+    order = rng.permutation(len(wl.pairs))
+    threads = os.cpu_count() or 1
+    done, t_used, used = 0, 0.0, 1
+    step = max(threads, 16)
+    evals = 0
+    while done < len(order) and t_used < budget_s:
+        idx = [int(i) for i in order[done:done + step]]
+        sub = wl.subset(idx)
+        t0 = time.perf_counter()
+        res, used = oracle.check_pairs(sub, "B", threads=threads)
+        t_used += time.perf_counter() - t0
+        evals += sum(r["evals"] for r in res)
+        done += len(idx)
+    return {"value": done / t_used, "unit": "queries/s", "cores": used,
+            "kind": "oracle",
+            "sample": "%d of %d pairs drawn at random (seed %d), %.1f s, %.3g evals"
+                      % (done, len(wl.pairs), seed, t_used, evals),
+            "evals_per_s": evals / t_used}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scale", type=float, default=1.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported "
+              "(queries shard across GPUs without exchange, see the design "
+              "notes)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2604_02106_amd as hg
+    from workloads import configs
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    wl = configs.batched(seed=2002, scale=args.scale)
+    log("workload: %d models, %d pairs" % (len(wl.models), len(wl.pairs)))
+    ctx = hg.Context(0)
+    packed = hg.Packed(wl)
+    for i in range(args.warmup):
+        res = hg.rd_check_pairs(ctx, wl, packed=packed)
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = hg.rd_check_pairs(ctx, wl, packed=packed)
+        stats.append(ctx.stats())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log("timed %d steps in %.3f s" % (args.steps, dt))
+    n = len(wl.pairs)
+    evals = stats[-1]["evals"]
+    racy = sum(r["verdict"] for r in res)
+    line = {
+        "metric": "race queries/sec and thread-access evals/sec (G/s) at 100% oracle agreement",
+        "value": n * args.steps / dt,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1000 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "batched uneven queries: 256 kernel models x 16 "
+                               "access pairs, seed 2002, grids up to 1024 blocks "
+                               "x 256 threads, loops up to 64 iterations, "
+                               "1-16 parameter tuples",
+                   "queries": n, "evals_per_step": evals, "racy": racy,
+                   "scale": args.scale},
+        "evals_per_s_G": evals * args.steps / dt / 1e9,
+        "kernel_ms": {k: sum(s[k] for s in stats) / len(stats)
+                      for k in ("device_ms", "scatter_ms", "join_ms",
+                                "witness_ms", "total_ms")},
+        "items": {k: stats[-1][k] for k in ("small_items", "hbm_items",
+                                            "overflow_items", "buckets",
+                                            "records")},
+    }
+    sc = stats[-1]
+    if sc["scatter_ms"] > 0 and sc["records"]:
+        rec_bytes = 8  # (int32 address, point id) per record
+        achieved = sc["records"] * rec_bytes / (sc["scatter_ms"] / 1e3) / 1e9
+        line["roofline"] = {"bound": "hbm", "kernel": "k_scatter",
+                            "achieved": achieved, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                            "traffic": None}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

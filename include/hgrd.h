@@ -1,0 +1,235 @@
+/*
+ * hgrd.h -- C ABI of the MI355X exact per-access-pair race query.
+ *
+ * The query (sections 2 and 6.1-6.4 of "Towards an Accurate GPU Data Race
+ * Detector"; Table 2): for two accesses to the same array, at least one a
+ * write, can two distinct threads of one launch reach the same address with
+ * both guards true, in the same barrier interval when they share a block?
+ * The paper encodes this as constraints and asks a SAT solver per access
+ * pair (section 6.4).  This library decides it exactly by enumerating the
+ * finite domains the host code fixes (launch extents, loop ranges and the
+ * parameter tuples of section 6.3), on the GPU, and also returns exact
+ * per-race-type counts and the lexicographically smallest witness.
+ *
+ * Conventions
+ *   - All integers are little-endian host integers.  Every input array is
+ *     owned by the caller, read-only to the library, and may be freed when
+ *     the call returns.  Outputs are caller-owned.
+ *   - Calls are synchronous on the stream given in the options (NULL: the
+ *     null stream).  A context must not be used by two host threads at once.
+ *   - A call returns RD_OK unless an argument is structurally unusable
+ *     (RD_EINVAL: NULL pointer with a nonzero count, bad options), device
+ *     memory runs out (RD_ENOMEM) or the device fails (RD_EDEVICE).  Errors
+ *     that belong to one pair go to that pair's result (`status`), with
+ *     verdict, counts and witness cleared; other pairs are unaffected.
+ *   - EXACT mode is deterministic: every field is identical for any tiling,
+ *     batching, tile order or graph replay.
+ */
+#ifndef HGRD_H
+#define HGRD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes (pair statuses use the first five) ---------------- */
+enum {
+  RD_OK = 0,
+  RD_EINVAL = -1,       /* malformed model, expression or pair */
+  RD_EUNSUPPORTED = -2, /* outside the supported limits (below) */
+  RD_ERANGE = -3,       /* an int64 operation overflowed, or a 32-bit
+                           array's address left int32 */
+  RD_EDIVZERO = -4,     /* division or remainder by zero */
+  RD_ENOMEM = -5,
+  RD_EDEVICE = -6,
+  RD_ECAPACITY = -7     /* a caller buffer is too small */
+};
+/* When a pair has several errors the reported one is, strongest first:
+ * EINVAL, EUNSUPPORTED, EDIVZERO, ERANGE. */
+
+/* ---- expressions ----------------------------------------------------
+ * Postfix integer bytecode.  Leaves: a constant (imm), kernel parameter
+ * `arg`, threadIdx/blockIdx/blockDim/gridDim component `arg` (0=x, 1=y,
+ * 2=z), or the value of model loop `arg`.  Operators follow C on int64:
+ * '/' truncates toward zero, '%' takes the sign of the dividend, '>>' is
+ * arithmetic, comparisons and logical operators give 0 or 1 and evaluate
+ * both operands.  An operation that overflows int64, divides by zero, or
+ * shifts by a count outside [0, 63] records an error and yields 0;
+ * evaluation continues (so the set of errors is well defined).
+ * Where each leaf may appear:
+ *   launch extents          : CONST, PARAM
+ *   loop init/bound/step    : + BDIM, GDIM
+ *   bint, wint              : + LOOP (loops enclosing the access)
+ *   addr, guard             : + TID, BID
+ * Limits: at most 256 instructions and a stack depth of 16. */
+enum {
+  RD_OP_CONST = 1, RD_OP_PARAM = 2, RD_OP_TID = 3, RD_OP_BID = 4,
+  RD_OP_BDIM = 5, RD_OP_GDIM = 6, RD_OP_LOOP = 7,
+  RD_OP_ADD = 16, RD_OP_SUB, RD_OP_MUL, RD_OP_DIV, RD_OP_MOD, RD_OP_SHL,
+  RD_OP_SHR, RD_OP_AND, RD_OP_OR, RD_OP_XOR, RD_OP_MIN, RD_OP_MAX,
+  RD_OP_LT, RD_OP_LE, RD_OP_EQ, RD_OP_NE, RD_OP_GE, RD_OP_GT,
+  RD_OP_LAND, RD_OP_LOR,
+  RD_OP_NEG = 48, RD_OP_LNOT = 49
+};
+
+typedef struct {
+  uint16_t op;   /* RD_OP_* */
+  uint16_t arg;  /* parameter index, axis, or model loop index */
+  uint32_t pad;
+  int64_t imm;   /* RD_OP_CONST value */
+} rd_insn;
+
+typedef struct {
+  uint32_t first; /* index into the model's instruction pool */
+  uint32_t count; /* 0 = absent: guard true, bint/wint 0; addr required */
+} rd_expr;
+
+/* ---- kernel model ---------------------------------------------------- */
+enum { RD_GLOBAL = 0, RD_SHARED = 1 };          /* array space (section 2) */
+enum { RD_READ = 0, RD_WRITE = 1, RD_ATOMIC = 2 };
+enum { RD_SCOPE_BLOCK = 0, RD_SCOPE_DEVICE = 1 }; /* atomic scope (app. A) */
+enum { RD_CMP_LT = 0, RD_CMP_LE, RD_CMP_GT, RD_CMP_GE, RD_CMP_NE };
+enum { RD_UPD_ADD = 0, RD_UPD_SUB, RD_UPD_MUL, RD_UPD_DIV, RD_UPD_SHL,
+       RD_UPD_SHR };
+
+typedef struct {
+  uint32_t space;     /* RD_GLOBAL or RD_SHARED (shared: one per block) */
+  uint32_t addr_bits; /* 32: addresses must fit int32; 64 */
+} rd_array;
+
+/* for (v = init; v <cmp> bound; v = v <upd> step); init, bound and step
+ * are evaluated once per parameter tuple.  At most 65536 iterations. */
+typedef struct {
+  rd_expr init, bound, step;
+  uint32_t cmp, upd;
+} rd_loop;
+
+/* One static load, store or atomic (section 6.1, "Generating access
+ * pairs").  `loops` lists the enclosing model loops, outermost first (at
+ * most 4); the iteration index is row-major over them.  `bint` and `wint`
+ * are barrier-interval ids in [0, 65536): two points of one block can race
+ * only if their bint are equal (a block barrier between them otherwise,
+ * section 6.1), and within one warp only if their wint are also equal. */
+typedef struct {
+  uint32_t array, kind, scope, n_loops;
+  uint32_t loops[4];
+  rd_expr addr, guard, bint, wint;
+} rd_access;
+
+typedef struct {
+  const rd_insn* insns; uint32_t n_insns;
+  const rd_array* arrays; uint32_t n_arrays;
+  const rd_loop* loops; uint32_t n_loops;
+  const rd_access* acc; uint32_t n_acc;
+  uint32_t n_params;
+} rd_kernel_model;
+
+/* Launch geometry of a model (section 6.3 class 2): grid and block extents
+ * as expressions (in the model's instruction pool) over parameters, and
+ * the warp size of the analysed program (1..1024; 32 for CUDA).  A tuple
+ * whose extents are not all >= 1 launches nothing.  Limits: a block of at
+ * most 1024 threads, a grid of fewer than 2^26 blocks, fewer than 2^31
+ * points (block x thread x iteration) per access and tuple. */
+typedef struct {
+  rd_expr grid[3], block[3];
+  uint32_t warp_size;
+  uint32_t pad;
+} rd_launch_domain;
+
+/* Host-fixed parameter tuples (section 6.3 classes 1-5): n_sets rows of
+ * n_params values, row-major.  Each row is one launch; conflicts never
+ * cross rows.  At most 4096 rows. */
+typedef struct {
+  uint32_t n_sets;
+  uint32_t pad;
+  const int64_t* values;
+} rd_param_sets;
+
+/* Race classes (Table 2). */
+enum { RD_INTER = 1, RD_INTRA_BLOCK = 2, RD_INTRA_WARP = 4 };
+
+/* An access pair: two accesses of one model on the same array, and the
+ * classes the caller wants checked (RD_INTER | RD_INTRA_BLOCK | ...). */
+typedef struct {
+  uint32_t model, a, b;
+  uint32_t class_mask;
+} rd_access_pair;
+
+/* ---- options ---------------------------------------------------------- */
+enum { RD_MODE_EXACT = 0, RD_MODE_VERDICT = 1 };
+enum { RD_ORDER_LEX = 0, RD_ORDER_MLP = 1 };
+
+typedef struct {
+  uint32_t mode;       /* RD_MODE_EXACT (default) */
+  uint32_t order;      /* RD_ORDER_LEX (default) */
+  uint32_t batched;    /* reserved; 0 */
+  uint32_t log_level;  /* 0 silent, 1 summary, 2 per-launch (stderr) */
+  uint32_t lds_cap;    /* records per LDS join tile; 0 = autotuned */
+  uint32_t pad;
+  uint64_t max_device_bytes; /* working-set cap; 0 = library default */
+  void* stream;        /* hipStream_t; NULL = null stream */
+} rd_options;
+
+/* ---- results ----------------------------------------------------------
+ * count_by_class: ordered point pairs (p from access a, q from access b)
+ * of each class, summed over tuples (modulo 2^64); count = their sum;
+ * verdict = count > 0; classes = bits of the nonzero classes.  Witness:
+ * the smallest (set, b1, t1, i1, b2, t2, i2) in lexicographic order over
+ * conflicting point pairs, with linear block, thread and iteration ids
+ * (x fastest); witness_class is its class and w_addr its address.  The
+ * witness fields are 0xFFFFFFFF (w_addr 0) when verdict is 0.
+ * flags: bit 0 = trivially race-free (empty class mask, section 6.1).
+ * evals: launch-box points of both accesses over all tuples (before
+ * guards; a self-pair counts its box twice). */
+typedef struct {
+  uint64_t count, count_by_class[3];
+  int32_t status;
+  uint8_t verdict, classes, witness_class, flags;
+  uint32_t w_set, w_b1, w_t1, w_i1, w_b2, w_t2, w_i2;
+  int64_t w_addr;
+  uint64_t evals;
+} rd_pair_result;
+
+typedef struct rd_context rd_context;
+
+/* Creates a context on HIP device `hip_device`.  Returns RD_OK,
+ * RD_EDEVICE or RD_ENOMEM.  *ctx is NULL on failure. */
+int rd_context_create(rd_context** ctx, int hip_device);
+void rd_context_destroy(rd_context* ctx);
+
+/* Decides every pair (see the conventions above).  `launch` and `params`
+ * are per model.  `opt` may be NULL.  `out` has n_pairs entries. */
+int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
+                   uint32_t n_models, const rd_access_pair* pairs,
+                   uint32_t n_pairs, const rd_launch_domain* launch,
+                   const rd_param_sets* params, const rd_options* opt,
+                   rd_pair_result* out);
+
+/* Timing and size figures of the last rd_check_pairs call. */
+typedef struct {
+  double total_ms;        /* host entry to results copied back */
+  double device_ms;       /* first to last kernel, HIP events */
+  double join_ms;         /* LDS/bucket join kernels */
+  double scatter_ms;      /* generate-and-partition kernels */
+  double witness_ms;      /* witness pass 2 */
+  uint64_t evals;         /* sum of the pairs' evals */
+  uint64_t records;       /* points written to HBM partitions */
+  uint64_t small_items, hbm_items, overflow_items, buckets;
+  uint64_t join_launches; /* launches of the dominant (join) kernel */
+  double join_kernel_ms;  /* summed duration of those launches */
+} rd_stats;
+
+int rd_get_stats(const rd_context* ctx, rd_stats* out);
+
+const char* rd_strerror(int status);
+
+/* Host-side self-checks of the library's integer helpers (no device work).
+ * Returns 0 when they pass. */
+int rd_selftest(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HGRD_H */

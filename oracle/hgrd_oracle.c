@@ -244,9 +244,14 @@ static int check_expr(const OModel* m, OExpr e, int ctx, const OAccess* a) {
 static int check_access(const OModel* m, const OAccess* a) {
   int err = 0;
   if (a->array < 0 || a->array >= m->n_arrays) return E_INVAL;
+  const OArray* arr = &m->arrays[a->array];
+  if ((arr->space != SP_GLOBAL && arr->space != SP_SHARED) ||
+      (arr->addr_bits != 32 && arr->addr_bits != 64)) return E_INVAL;
   if (a->kind < K_READ || a->kind > K_ATOMIC) return E_INVAL;
   if (a->scope != SC_BLOCK && a->scope != SC_DEVICE) return E_INVAL;
-  if (a->n_loops < 0 || a->n_loops > 8) return E_INVAL;
+  if (a->n_loops < 0) return E_INVAL;
+  /* the interface holds at most four enclosing loops; more is checked first */
+  if (a->n_loops > MAX_LOOPS) return E_UNSUP;
   for (int i = 0; i < a->n_loops; ++i) {
     if (a->loops[i] < 0 || a->loops[i] >= m->n_loops || a->loops[i] >= 64) return E_INVAL;
     for (int j = 0; j < i; ++j) if (a->loops[j] == a->loops[i]) return E_INVAL;
@@ -265,7 +270,6 @@ static int check_access(const OModel* m, const OAccess* a) {
     err |= check_expr(m, l->step, 1, a);
   }
   if (err & E_INVAL) return E_INVAL;
-  if (a->n_loops > MAX_LOOPS) err |= E_UNSUP;
   return err;
 }
 

@@ -1,0 +1,292 @@
+"""MI355X exact per-access-pair race query: Python binding.
+
+A thin ctypes layer over ``libhgrd.so`` (declared in ``include/hgrd.h``).  It
+only marshals a ``workloads.Workload`` into the C structures and passes the
+current torch stream; every step of the query runs in the library's gfx950
+kernels.  There is no CPU fallback: without the built library or a GPU the
+calls raise.
+"""
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgrd.so")
+
+RD_OK, RD_EINVAL, RD_EUNSUPPORTED, RD_ERANGE, RD_EDIVZERO = 0, -1, -2, -3, -4
+RD_ENOMEM, RD_EDEVICE, RD_ECAPACITY = -5, -6, -7
+MODE_EXACT, MODE_VERDICT = 0, 1
+ORDER_LEX, ORDER_MLP = 0, 1
+
+# opcode numbers of include/hgrd.h
+_OP = {"const": 1, "param": 2, "tid": 3, "bid": 4, "bdim": 5, "gdim": 6,
+       "loop": 7, "add": 16, "sub": 17, "mul": 18, "div": 19, "mod": 20,
+       "shl": 21, "shr": 22, "and": 23, "or": 24, "xor": 25, "min": 26,
+       "max": 27, "lt": 28, "le": 29, "eq": 30, "ne": 31, "ge": 32, "gt": 33,
+       "land": 34, "lor": 35, "neg": 48, "lnot": 49}
+_KIND = {"read": 0, "write": 1, "atomic": 2}
+_SCOPE = {"block": 0, "device": 1}
+_SPACE = {"global": 0, "shared": 1}
+_CMP = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "ne": 4}
+_UPD = {"add": 0, "sub": 1, "mul": 2, "div": 3, "shl": 4, "shr": 5}
+
+
+class rd_insn(C.Structure):
+    _fields_ = [("op", C.c_uint16), ("arg", C.c_uint16), ("pad", C.c_uint32),
+                ("imm", C.c_int64)]
+
+
+class rd_expr(C.Structure):
+    _fields_ = [("first", C.c_uint32), ("count", C.c_uint32)]
+
+
+class rd_array(C.Structure):
+    _fields_ = [("space", C.c_uint32), ("addr_bits", C.c_uint32)]
+
+
+class rd_loop(C.Structure):
+    _fields_ = [("init", rd_expr), ("bound", rd_expr), ("step", rd_expr),
+                ("cmp", C.c_uint32), ("upd", C.c_uint32)]
+
+
+class rd_access(C.Structure):
+    _fields_ = [("array", C.c_uint32), ("kind", C.c_uint32),
+                ("scope", C.c_uint32), ("n_loops", C.c_uint32),
+                ("loops", C.c_uint32 * 4), ("addr", rd_expr),
+                ("guard", rd_expr), ("bint", rd_expr), ("wint", rd_expr)]
+
+
+class rd_kernel_model(C.Structure):
+    _fields_ = [("insns", C.POINTER(rd_insn)), ("n_insns", C.c_uint32),
+                ("arrays", C.POINTER(rd_array)), ("n_arrays", C.c_uint32),
+                ("loops", C.POINTER(rd_loop)), ("n_loops", C.c_uint32),
+                ("acc", C.POINTER(rd_access)), ("n_acc", C.c_uint32),
+                ("n_params", C.c_uint32)]
+
+
+class rd_launch_domain(C.Structure):
+    _fields_ = [("grid", rd_expr * 3), ("block", rd_expr * 3),
+                ("warp_size", C.c_uint32), ("pad", C.c_uint32)]
+
+
+class rd_param_sets(C.Structure):
+    _fields_ = [("n_sets", C.c_uint32), ("pad", C.c_uint32),
+                ("values", C.POINTER(C.c_int64))]
+
+
+class rd_access_pair(C.Structure):
+    _fields_ = [("model", C.c_uint32), ("a", C.c_uint32), ("b", C.c_uint32),
+                ("class_mask", C.c_uint32)]
+
+
+class rd_options(C.Structure):
+    _fields_ = [("mode", C.c_uint32), ("order", C.c_uint32),
+                ("batched", C.c_uint32), ("log_level", C.c_uint32),
+                ("lds_cap", C.c_uint32), ("pad", C.c_uint32),
+                ("max_device_bytes", C.c_uint64), ("stream", C.c_void_p)]
+
+
+class rd_pair_result(C.Structure):
+    _fields_ = [("count", C.c_uint64), ("count_by_class", C.c_uint64 * 3),
+                ("status", C.c_int32), ("verdict", C.c_uint8),
+                ("classes", C.c_uint8), ("witness_class", C.c_uint8),
+                ("flags", C.c_uint8), ("w_set", C.c_uint32),
+                ("w_b1", C.c_uint32), ("w_t1", C.c_uint32),
+                ("w_i1", C.c_uint32), ("w_b2", C.c_uint32),
+                ("w_t2", C.c_uint32), ("w_i2", C.c_uint32),
+                ("w_addr", C.c_int64), ("evals", C.c_uint64)]
+
+
+class rd_stats(C.Structure):
+    _fields_ = [("total_ms", C.c_double), ("device_ms", C.c_double),
+                ("join_ms", C.c_double), ("scatter_ms", C.c_double),
+                ("witness_ms", C.c_double), ("evals", C.c_uint64),
+                ("records", C.c_uint64), ("small_items", C.c_uint64),
+                ("hbm_items", C.c_uint64), ("overflow_items", C.c_uint64),
+                ("buckets", C.c_uint64), ("join_launches", C.c_uint64),
+                ("join_kernel_ms", C.c_double)]
+
+
+assert C.sizeof(rd_pair_result) == 88
+
+EXPORTS = ("rd_context_create", "rd_context_destroy", "rd_check_pairs",
+           "rd_get_stats", "rd_strerror")
+
+_lib = None
+
+
+def lib():
+    """Loads libhgrd.so (built by ``paper_2604_02106_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhgrd.so is not built: run "
+                               "python -m paper_2604_02106_amd.build")
+        L = C.CDLL(LIB_PATH)
+        L.rd_context_create.restype = C.c_int
+        L.rd_context_create.argtypes = [C.POINTER(C.c_void_p), C.c_int]
+        L.rd_context_destroy.restype = None
+        L.rd_context_destroy.argtypes = [C.c_void_p]
+        L.rd_check_pairs.restype = C.c_int
+        L.rd_check_pairs.argtypes = [
+            C.c_void_p, C.POINTER(rd_kernel_model), C.c_uint32,
+            C.POINTER(rd_access_pair), C.c_uint32, C.POINTER(rd_launch_domain),
+            C.POINTER(rd_param_sets), C.POINTER(rd_options),
+            C.POINTER(rd_pair_result)]
+        L.rd_get_stats.restype = C.c_int
+        L.rd_get_stats.argtypes = [C.c_void_p, C.POINTER(rd_stats)]
+        L.rd_strerror.restype = C.c_char_p
+        L.rd_strerror.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def rd_strerror(status):
+    return lib().rd_strerror(int(status)).decode()
+
+
+class Context:
+    """An rd_context on one HIP device."""
+
+    def __init__(self, device=0):
+        self.h = C.c_void_p()
+        st = lib().rd_context_create(C.byref(self.h), int(device))
+        if st != RD_OK:
+            raise RuntimeError("rd_context_create failed: %s" % rd_strerror(st))
+
+    def close(self):
+        if self.h:
+            lib().rd_context_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self):
+        s = rd_stats()
+        lib().rd_get_stats(self.h, C.byref(s))
+        return {k: getattr(s, k) for k, _ in rd_stats._fields_}
+
+
+class Packed:
+    """C image of a workload's models, launch domains and parameter tuples."""
+
+    def __init__(self, workload):
+        n = len(workload.models)
+        self.keep = []
+        self.models = (rd_kernel_model * max(1, n))()
+        self.launch = (rd_launch_domain * max(1, n))()
+        self.params = (rd_param_sets * max(1, n))()
+        for mi, m in enumerate(workload.models):
+            insns = []
+
+            def put(e):
+                if e is None:
+                    return rd_expr(0, 0)
+                first = len(insns)
+                for t in e.code:
+                    op = _OP.get(t[0], 0)
+                    if t[0] == "const":
+                        insns.append((op, 0, int(t[1])))
+                    else:
+                        insns.append((op, int(t[1]) if len(t) > 1 else 0, 0))
+                return rd_expr(first, len(e.code))
+
+            arrays = (rd_array * max(1, len(m.arrays)))(
+                *[rd_array(_SPACE[a.space], a.addr_bits) for a in m.arrays])
+            loops = (rd_loop * max(1, len(m.loops)))()
+            for k, l in enumerate(m.loops):
+                loops[k] = rd_loop(put(l.init), put(l.bound), put(l.step),
+                                   _CMP[l.cmp], _UPD[l.upd])
+            accs = (rd_access * max(1, len(m.accesses)))()
+            for k, a in enumerate(m.accesses):
+                x = accs[k]
+                x.array, x.kind, x.scope = a.array, _KIND[a.kind], _SCOPE[a.scope]
+                x.n_loops = len(a.loops)
+                for i, lk in enumerate(a.loops[:4]):
+                    x.loops[i] = lk
+                x.addr, x.guard = put(a.addr), put(a.guard)
+                x.bint, x.wint = put(a.bint), put(a.wint)
+            ld = self.launch[mi]
+            for d in range(3):
+                ld.grid[d] = put(m.launch.grid[d])
+                ld.block[d] = put(m.launch.block[d])
+            ld.warp_size = m.launch.warp
+            ins = (rd_insn * max(1, len(insns)))(
+                *[rd_insn(o, a & 0xFFFF, 0, v) for (o, a, v) in insns])
+            flat = [v for row in m.param_sets for v in row]
+            vals = (C.c_int64 * max(1, len(flat)))(*flat)
+            self.params[mi] = rd_param_sets(len(m.param_sets), 0, vals)
+            md = self.models[mi]
+            md.insns, md.n_insns = ins, len(insns)
+            md.arrays, md.n_arrays = arrays, len(m.arrays)
+            md.loops, md.n_loops = loops, len(m.loops)
+            md.acc, md.n_acc = accs, len(m.accesses)
+            md.n_params = m.n_params
+            self.keep += [ins, arrays, loops, accs, vals]
+        self.n_models = n
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return int(stream)
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+def rd_check_pairs(ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
+                   lds_cap=0, max_device_bytes=0, log_level=0, stream=None,
+                   packed=None):
+    """Decides every pair of ``workload`` on the GPU.
+
+    Returns a list of result dicts (same fields as rd_pair_result).
+    """
+    pk = packed or Packed(workload)
+    n = len(workload.pairs)
+    pairs = (rd_access_pair * max(1, n))(
+        *[rd_access_pair(m, a, b, k) for (m, a, b, k) in workload.pairs])
+    out = (rd_pair_result * max(1, n))()
+    opt = rd_options(mode, order, 0, log_level, lds_cap, 0, max_device_bytes,
+                     _stream_handle(stream))
+    st = lib().rd_check_pairs(ctx.h, pk.models, pk.n_models, pairs, n,
+                              pk.launch, pk.params, C.byref(opt), out)
+    if st != RD_OK:
+        raise RuntimeError("rd_check_pairs failed: %s" % rd_strerror(st))
+    return [result_dict(out[k]) for k in range(n)]
+
+
+def result_dict(r):
+    none = 0xFFFFFFFF
+    w = (r.w_set, r.w_b1, r.w_t1, r.w_i1, r.w_b2, r.w_t2, r.w_i2)
+    w = tuple(-1 if x == none else x for x in w)
+    return {"status": r.status, "verdict": r.verdict, "count": r.count,
+            "by_class": [r.count_by_class[0], r.count_by_class[1],
+                         r.count_by_class[2]],
+            "classes": r.classes, "witness_class": r.witness_class,
+            "flags": r.flags, "witness": w, "w_addr": r.w_addr,
+            "evals": r.evals}
+
+
+_default_ctx = None
+
+
+def check_pairs(workload, **kw):
+    """rd_check_pairs on a process-wide context for device 0."""
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context(0)
+    return rd_check_pairs(_default_ctx, workload, **kw)
+
+
+def default_context():
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context(0)
+    return _default_ctx

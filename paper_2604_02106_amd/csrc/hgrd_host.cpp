@@ -1,0 +1,1053 @@
+// Host side of the exact per-access-pair race query: argument validation,
+// class masks (section 6.1, appendix A.2), evaluation of the uniform parts
+// of a model (launch extents, loop value lists; section 6.3 classes 2 and
+// 4), compilation of address/guard/interval expressions to device code,
+// work planning, launches, and results.
+//
+// Work planning.  A query (one access pair) under one parameter tuple has
+// |D_a| + |D_b| launch-box points.  When they fit one workgroup's LDS the
+// workgroup generates and joins them itself (for shared-memory arrays, per
+// block range: shared memory belongs to one block).  Larger ones are
+// generated once and scattered into fixed-capacity HBM buckets by an
+// address hash, then each bucket is joined in LDS.  Buckets that overflow
+// (many points on few addresses) send their query through an HBM hash
+// aggregation instead.  The lexicographically smallest witness is found in
+// two passes: the smallest p with a partner comes out of the joins, then
+// one pass over the other access finds the smallest partner q.
+#include "../../include/hgrd.h"
+#include "hgrd_internal.h"
+#include "hgrd_launch.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace hgrd;
+using u64 = unsigned long long;
+
+namespace {
+
+constexpr uint32_t kMaxInsns = 256;
+constexpr uint32_t kMaxDepth = 16;
+constexpr uint32_t kMaxLoopsPerAccess = 4;
+constexpr uint32_t kMaxIters = 65536;
+constexpr uint32_t kMaxSets = 4096;
+constexpr int64_t kMaxBlock = 1024;
+constexpr int64_t kMaxGrid = 1ll << 26;
+constexpr int64_t kMaxPoints = 1ll << 31;
+constexpr uint32_t kChunkPts = 8192;
+
+// ---------------------------------------------------------------------------
+// checked int64 arithmetic on the host (errors yield 0, evaluation goes on)
+
+int64_t hop(uint16_t op, int64_t a, int64_t b, uint32_t& err) {
+  int64_t r;
+  switch (op) {
+    case RD_OP_ADD:
+      if (__builtin_add_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
+      return r;
+    case RD_OP_SUB:
+      if (__builtin_sub_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
+      return r;
+    case RD_OP_MUL:
+      if (__builtin_mul_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
+      return r;
+    case RD_OP_DIV:
+    case RD_OP_MOD:
+      if (b == 0) { err |= ERR_DIVZERO; return 0; }
+      if (a == INT64_MIN && b == -1) { err |= ERR_RANGE; return 0; }
+      return op == RD_OP_DIV ? a / b : a % b;
+    case RD_OP_SHL: {
+      if (b < 0 || b > 63) { err |= ERR_RANGE; return 0; }
+      int64_t s = (int64_t)((uint64_t)a << b);
+      if ((s >> b) != a) { err |= ERR_RANGE; return 0; }
+      return s;
+    }
+    case RD_OP_SHR:
+      if (b < 0 || b > 63) { err |= ERR_RANGE; return 0; }
+      return a >> b;
+    case RD_OP_AND: return a & b;
+    case RD_OP_OR: return a | b;
+    case RD_OP_XOR: return a ^ b;
+    case RD_OP_MIN: return std::min(a, b);
+    case RD_OP_MAX: return std::max(a, b);
+    case RD_OP_LT: return a < b;
+    case RD_OP_LE: return a <= b;
+    case RD_OP_EQ: return a == b;
+    case RD_OP_NE: return a != b;
+    case RD_OP_GE: return a >= b;
+    case RD_OP_GT: return a > b;
+    case RD_OP_LAND: return (a != 0) && (b != 0);
+    case RD_OP_LOR: return (a != 0) || (b != 0);
+  }
+  err |= ERR_INVAL;
+  return 0;
+}
+
+bool is_leaf(uint16_t op) { return op >= RD_OP_CONST && op <= RD_OP_LOOP; }
+bool is_binary(uint16_t op) { return op >= RD_OP_ADD && op <= RD_OP_LOR; }
+bool is_unary(uint16_t op) { return op == RD_OP_NEG || op == RD_OP_LNOT; }
+
+// where leaves may appear
+enum Ctx { CTX_LAUNCH = 0, CTX_LOOP = 1, CTX_IV = 2, CTX_POINT = 3 };
+
+int loop_pos(const rd_access* a, uint32_t loop) {
+  if (!a) return -1;
+  for (uint32_t i = 0; i < a->n_loops && i < 8; ++i)
+    if (a->loops[i] == loop) return (int)i;
+  return -1;
+}
+
+// Structural check: ERR_INVAL for malformed, ERR_UNSUP for over-limit.
+uint32_t check_expr(const rd_kernel_model& m, rd_expr e, int ctx,
+                    const rd_access* a) {
+  if (e.count == 0) return 0;
+  if ((uint64_t)e.first + e.count > m.n_insns || !m.insns) return ERR_INVAL;
+  uint32_t depth = 0, maxd = 0;
+  for (uint32_t k = 0; k < e.count; ++k) {
+    const rd_insn& t = m.insns[e.first + k];
+    if (is_leaf(t.op)) {
+      switch (t.op) {
+        case RD_OP_CONST: break;
+        case RD_OP_PARAM:
+          if (t.arg >= m.n_params) return ERR_INVAL;
+          break;
+        case RD_OP_BDIM:
+        case RD_OP_GDIM:
+          if (ctx < CTX_LOOP || t.arg > 2) return ERR_INVAL;
+          break;
+        case RD_OP_TID:
+        case RD_OP_BID:
+          if (ctx < CTX_POINT || t.arg > 2) return ERR_INVAL;
+          break;
+        case RD_OP_LOOP:
+          if (ctx < CTX_IV || loop_pos(a, t.arg) < 0) return ERR_INVAL;
+          break;
+      }
+      ++depth;
+    } else if (is_unary(t.op)) {
+      if (depth < 1) return ERR_INVAL;
+    } else if (is_binary(t.op)) {
+      if (depth < 2) return ERR_INVAL;
+      --depth;
+    } else {
+      return ERR_INVAL;
+    }
+    maxd = std::max(maxd, depth);
+  }
+  if (depth != 1) return ERR_INVAL;
+  if (e.count > kMaxInsns || maxd > kMaxDepth) return ERR_UNSUP;
+  return 0;
+}
+
+uint32_t check_access(const rd_kernel_model& m, const rd_access& a) {
+  if (a.array >= m.n_arrays || !m.arrays) return ERR_INVAL;
+  const rd_array& arr = m.arrays[a.array];
+  if (arr.space > RD_SHARED || (arr.addr_bits != 32 && arr.addr_bits != 64))
+    return ERR_INVAL;
+  if (a.kind > RD_ATOMIC) return ERR_INVAL;
+  if (a.scope > RD_SCOPE_DEVICE) return ERR_INVAL;
+  if (a.n_loops > kMaxLoopsPerAccess) {
+    return ERR_UNSUP;
+  }
+  for (uint32_t i = 0; i < a.n_loops; ++i) {
+    if (a.loops[i] >= m.n_loops || !m.loops) return ERR_INVAL;
+    for (uint32_t j = 0; j < i; ++j)
+      if (a.loops[j] == a.loops[i]) return ERR_INVAL;
+  }
+  if (a.addr.count == 0) return ERR_INVAL;
+  uint32_t err = check_expr(m, a.addr, CTX_POINT, &a) |
+                 check_expr(m, a.guard, CTX_POINT, &a) |
+                 check_expr(m, a.bint, CTX_IV, &a) |
+                 check_expr(m, a.wint, CTX_IV, &a);
+  for (uint32_t i = 0; i < a.n_loops; ++i) {
+    const rd_loop& l = m.loops[a.loops[i]];
+    if (!l.init.count || !l.bound.count || !l.step.count) return ERR_INVAL;
+    if (l.cmp > RD_CMP_NE || l.upd > RD_UPD_SHR) return ERR_INVAL;
+    err |= check_expr(m, l.init, CTX_LOOP, &a) |
+           check_expr(m, l.bound, CTX_LOOP, &a) |
+           check_expr(m, l.step, CTX_LOOP, &a);
+  }
+  return (err & ERR_INVAL) ? ERR_INVAL : err;
+}
+
+// Host evaluation of a uniform expression.  dims = {gx, gy, gz, bx, by, bz}.
+int64_t heval(const rd_kernel_model& m, rd_expr e, const int64_t* params,
+              const int64_t* dims, int64_t dflt, uint32_t& err) {
+  if (e.count == 0) return dflt;
+  int64_t st[kMaxDepth + 1];
+  int sp = 0;
+  for (uint32_t k = 0; k < e.count; ++k) {
+    const rd_insn& t = m.insns[e.first + k];
+    switch (t.op) {
+      case RD_OP_CONST: st[sp++] = t.imm; break;
+      case RD_OP_PARAM: st[sp++] = params[t.arg]; break;
+      case RD_OP_GDIM: st[sp++] = dims ? dims[t.arg] : 0; break;
+      case RD_OP_BDIM: st[sp++] = dims ? dims[3 + t.arg] : 0; break;
+      case RD_OP_NEG:
+        if (st[sp - 1] == INT64_MIN) { err |= ERR_RANGE; st[sp - 1] = 0; }
+        else st[sp - 1] = -st[sp - 1];
+        break;
+      case RD_OP_LNOT: st[sp - 1] = st[sp - 1] == 0; break;
+      default: {
+        int64_t b = st[--sp];
+        st[sp - 1] = hop(t.op, st[sp - 1], b, err);
+      }
+    }
+  }
+  return st[0];
+}
+
+// Compiles a postfix expression to device three-address code.
+// Leaves stay operand descriptors; only intermediate values take a stack
+// register, so the register index of a value is its stack position.
+Prog compile(const rd_kernel_model& m, rd_expr e, const rd_access& a,
+             std::vector<DInsn>& pool) {
+  Prog p;
+  memset(&p, 0, sizeof p);
+  if (e.count == 0) {
+    p.absent = 1;
+    return p;
+  }
+  p.off = (uint32_t)pool.size();
+  struct Opnd {
+    uint8_t mode;
+    uint16_t idx;
+    int64_t imm;
+  };
+  std::vector<Opnd> st;
+  auto emit = [&](uint8_t op, uint8_t dst, Opnd x, Opnd y) {
+    DInsn in;
+    in.op = op;
+    in.dst = dst;
+    in.ma = x.mode;
+    in.mb = y.mode;
+    in.a = x.idx;
+    in.b = y.idx;
+    in.imm = x.mode == M_IMM ? x.imm : y.imm;
+    pool.push_back(in);
+  };
+  static const uint8_t kBin[] = {D_ADD, D_SUB, D_MUL, D_DIV, D_MOD, D_SHL,
+                                 D_SHR, D_AND, D_OR,  D_XOR, D_MIN, D_MAX,
+                                 D_LT,  D_LE,  D_EQ,  D_NE,  D_GE,  D_GT,
+                                 D_LAND, D_LOR};
+  const uint16_t np = (uint16_t)m.n_params;
+  for (uint32_t k = 0; k < e.count; ++k) {
+    const rd_insn& t = m.insns[e.first + k];
+    switch (t.op) {
+      case RD_OP_CONST: st.push_back({M_IMM, 0, t.imm}); break;
+      case RD_OP_PARAM: st.push_back({M_PARAM, t.arg, 0}); break;
+      case RD_OP_GDIM: st.push_back({M_PARAM, (uint16_t)(np + t.arg), 0}); break;
+      case RD_OP_BDIM: st.push_back({M_PARAM, (uint16_t)(np + 3 + t.arg), 0}); break;
+      case RD_OP_TID: st.push_back({M_COORD, (uint16_t)(kCoordTid + t.arg), 0}); break;
+      case RD_OP_BID: st.push_back({M_COORD, (uint16_t)(kCoordBid + t.arg), 0}); break;
+      case RD_OP_LOOP:
+        st.push_back({M_COORD, (uint16_t)(kCoordLoop + loop_pos(&a, t.arg)), 0});
+        break;
+      case RD_OP_NEG:
+      case RD_OP_LNOT: {
+        Opnd x = st.back();
+        st.pop_back();
+        uint8_t d = (uint8_t)st.size();
+        emit(t.op == RD_OP_NEG ? D_NEG : D_LNOT, d, x, {M_IMM, 0, x.imm});
+        st.push_back({M_REG, d, 0});
+        break;
+      }
+      default: {
+        Opnd y = st.back();
+        st.pop_back();
+        Opnd x = st.back();
+        st.pop_back();
+        uint8_t d = (uint8_t)st.size();
+        if (x.mode == M_IMM && y.mode == M_IMM) {
+          emit(D_MOV, d, x, x);
+          x = {M_REG, d, 0};
+        }
+        emit(kBin[t.op - RD_OP_ADD], d, x, y);
+        st.push_back({M_REG, d, 0});
+      }
+    }
+  }
+  Opnd r = st.back();
+  if (r.mode != M_REG) {
+    emit(D_MOV, 0, r, r);
+    p.res = 0;
+  } else {
+    p.res = (uint8_t)r.idx;
+  }
+  p.n = (uint16_t)(pool.size() - p.off);
+  return p;
+}
+
+bool cmp_holds(uint32_t cmp, int64_t v, int64_t bound) {
+  switch (cmp) {
+    case RD_CMP_LT: return v < bound;
+    case RD_CMP_LE: return v <= bound;
+    case RD_CMP_GT: return v > bound;
+    case RD_CMP_GE: return v >= bound;
+    default: return v != bound;
+  }
+}
+
+const uint16_t kUpdOp[] = {RD_OP_ADD, RD_OP_SUB, RD_OP_MUL, RD_OP_DIV,
+                           RD_OP_SHL, RD_OP_SHR};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+struct rd_context {
+  int device = 0;
+  std::map<std::string, DevBuf> bufs;
+  rd_stats stats;
+  int cfg = 1;
+  hipEvent_t ev[16];
+  void* ensure(const char* name, size_t bytes, int* err) {
+    DevBuf& b = bufs[name];
+    if (bytes == 0) bytes = 256;
+    if (b.cap < bytes) {
+      if (b.p) hipFree(b.p);
+      b.p = nullptr;
+      size_t want = std::max(bytes, b.cap + b.cap / 2);
+      if (hipMalloc(&b.p, want) != hipSuccess) {
+        b.cap = 0;
+        if (hipMalloc(&b.p, bytes) != hipSuccess) {
+          b.p = nullptr;
+          *err = RD_ENOMEM;
+          return nullptr;
+        }
+        want = bytes;
+      }
+      b.cap = want;
+    }
+    return b.p;
+  }
+};
+
+namespace {
+
+// Per (model, tuple): launch extents.
+struct DimInfo {
+  bool done = false;
+  uint32_t err = 0;
+  bool ok = false;       // non-empty and within limits
+  int64_t d[6];
+  uint32_t params_off;   // offset of [params..., gx, gy, gz, bx, by, bz]
+};
+
+struct LoopInfo {
+  bool done = false;
+  uint32_t err = 0;
+  bool ok = false;
+  uint32_t off = 0, n = 0;
+};
+
+struct InstInfo {
+  bool done = false;
+  uint32_t err = 0;   // errors from extents and loops of this access
+  int32_t idx = -1;   // device instance, -1: no points
+  uint64_t box = 0;   // points counted in evals
+  uint32_t npts = 0;
+};
+
+struct Planner {
+  const rd_kernel_model* models;
+  const rd_launch_domain* launch;
+  const rd_param_sets* params;
+  std::vector<std::vector<DimInfo>> dims;                 // [model][set]
+  std::map<std::pair<uint32_t, uint32_t>, std::vector<LoopInfo>> loops;  // (model, loop) -> per set
+  std::map<std::pair<uint32_t, uint32_t>, std::vector<InstInfo>> insts;  // (model, acc) -> per set
+  std::map<std::pair<uint32_t, uint32_t>, Prog> progs[4];
+  std::vector<DInsn> code;
+  std::vector<int64_t> pool_params;
+  std::vector<int64_t> pool_loops;
+  std::vector<AccInst> dev_insts;
+
+  DimInfo& dim(uint32_t m, uint32_t s) {
+    DimInfo& d = dims[m][s];
+    if (d.done) return d;
+    d.done = true;
+    const rd_kernel_model& M = models[m];
+    const rd_launch_domain& L = launch[m];
+    const int64_t* pv = params[m].values + (uint64_t)s * M.n_params;
+    bool nonempty = true;
+    for (int k = 0; k < 3; ++k) {
+      d.d[k] = heval(M, L.grid[k], pv, nullptr, 1, d.err);
+      d.d[3 + k] = heval(M, L.block[k], pv, nullptr, 1, d.err);
+      if (d.d[k] < 1 || d.d[3 + k] < 1) nonempty = false;
+    }
+    if (!nonempty) return d;
+    for (int k = 3; k < 6; ++k)
+      if (d.d[k] > kMaxBlock) { d.err |= ERR_UNSUP; return d; }
+    if (d.d[3] * d.d[4] > kMaxBlock || d.d[3] * d.d[4] * d.d[5] > kMaxBlock) {
+      d.err |= ERR_UNSUP;
+      return d;
+    }
+    for (int k = 0; k < 3; ++k)
+      if (d.d[k] >= kMaxGrid) { d.err |= ERR_UNSUP; return d; }
+    if (d.d[0] * d.d[1] >= kMaxGrid || d.d[0] * d.d[1] * d.d[2] >= kMaxGrid) {
+      d.err |= ERR_UNSUP;
+      return d;
+    }
+    d.ok = true;
+    d.params_off = (uint32_t)pool_params.size();
+    for (uint32_t k = 0; k < M.n_params; ++k) pool_params.push_back(pv[k]);
+    for (int k = 0; k < 6; ++k) pool_params.push_back(d.d[k]);
+    return d;
+  }
+
+  LoopInfo& loop(uint32_t m, uint32_t l, uint32_t s, const DimInfo& d) {
+    auto& v = loops[{m, l}];
+    if (v.empty()) v.resize(params[m].n_sets);
+    LoopInfo& li = v[s];
+    if (li.done) return li;
+    li.done = true;
+    const rd_kernel_model& M = models[m];
+    const rd_loop& L = M.loops[l];
+    const int64_t* pv = params[m].values + (uint64_t)s * M.n_params;
+    uint32_t e = 0;
+    int64_t x = heval(M, L.init, pv, d.d, 0, e);
+    int64_t bound = heval(M, L.bound, pv, d.d, 0, e);
+    int64_t step = heval(M, L.step, pv, d.d, 0, e);
+    if (e) { li.err = e; return li; }
+    li.off = (uint32_t)pool_loops.size();
+    uint32_t n = 0;
+    while (cmp_holds(L.cmp, x, bound)) {
+      if (n == kMaxIters) {
+        li.err |= ERR_UNSUP;
+        pool_loops.resize(li.off);
+        return li;
+      }
+      pool_loops.push_back(x);
+      ++n;
+      uint32_t ue = 0;
+      x = hop(kUpdOp[L.upd], x, step, ue);
+      if (ue) {
+        li.err |= ue;
+        pool_loops.resize(li.off);
+        return li;
+      }
+    }
+    li.n = n;
+    li.ok = true;
+    return li;
+  }
+
+  Prog prog(uint32_t m, uint32_t a, int which) {
+    auto key = std::make_pair(m, a);
+    auto it = progs[which].find(key);
+    if (it != progs[which].end()) return it->second;
+    const rd_access& A = models[m].acc[a];
+    rd_expr e = which == 0 ? A.addr : which == 1 ? A.guard : which == 2 ? A.bint : A.wint;
+    Prog p = compile(models[m], e, A, code);
+    progs[which][key] = p;
+    return p;
+  }
+
+  InstInfo& inst(uint32_t m, uint32_t a, uint32_t s) {
+    auto& v = insts[{m, a}];
+    if (v.empty()) v.resize(params[m].n_sets);
+    InstInfo& ii = v[s];
+    if (ii.done) return ii;
+    ii.done = true;
+    DimInfo& d = dim(m, s);
+    ii.err |= d.err;
+    if (!d.ok) return ii;
+    const rd_kernel_model& M = models[m];
+    const rd_access& A = M.acc[a];
+    uint64_t niota = 1;
+    uint32_t ln[4] = {1, 1, 1, 1}, lo[4] = {0, 0, 0, 0};
+    for (uint32_t k = 0; k < A.n_loops; ++k) {
+      LoopInfo& li = loop(m, A.loops[k], s, d);
+      ii.err |= li.err;
+      if (!li.ok) return ii;
+      ln[k] = li.n;
+      lo[k] = li.off;
+      niota *= li.n;
+      if (niota > kMaxIters) {
+        ii.err |= ERR_UNSUP;
+        return ii;
+      }
+    }
+    uint64_t nblk = (uint64_t)(d.d[0] * d.d[1] * d.d[2]);
+    uint64_t nthr = (uint64_t)(d.d[3] * d.d[4] * d.d[5]);
+    uint64_t box = nblk * nthr * niota;
+    if (box >= (uint64_t)kMaxPoints) {
+      ii.err |= ERR_UNSUP;
+      return ii;
+    }
+    ii.box = box;
+    if (box == 0) return ii;
+    AccInst I;
+    memset(&I, 0, sizeof I);
+    I.addr = prog(m, a, 0);
+    I.guard = prog(m, a, 1);
+    I.bint = prog(m, a, 2);
+    I.wint = prog(m, a, 3);
+    for (int k = 0; k < 6; ++k) I.dims[k] = (int32_t)d.d[k];
+    I.nblk = (uint32_t)nblk;
+    I.nthr = (uint32_t)nthr;
+    I.niota = (uint32_t)niota;
+    I.n_loops = A.n_loops;
+    for (int k = 0; k < 4; ++k) {
+      I.loop_n[k] = ln[k];
+      I.loop_off[k] = lo[k];
+    }
+    I.params_off = d.params_off;
+    I.is32 = M.arrays[A.array].addr_bits == 32;
+    I.npts = (uint32_t)box;
+    I.tpb = (uint32_t)(nthr * niota);
+    ii.idx = (int32_t)dev_insts.size();
+    ii.npts = (uint32_t)box;
+    dev_insts.push_back(I);
+    return ii;
+  }
+};
+
+uint32_t class_mask(const rd_kernel_model& m, const rd_access& x,
+                    const rd_access& y, uint32_t caller) {
+  uint32_t mask = caller & 7u;
+  if (x.kind == RD_READ && y.kind == RD_READ) return 0;  // section 6.1
+  if (x.kind == RD_ATOMIC && y.kind == RD_ATOMIC) {      // appendix A.2
+    if (x.scope == RD_SCOPE_DEVICE && y.scope == RD_SCOPE_DEVICE) return 0;
+    mask &= RD_INTER;
+  }
+  if (m.arrays[x.array].space == RD_SHARED) mask &= ~(uint32_t)RD_INTER;
+  return mask;
+}
+
+struct QPlan {
+  uint32_t host_err = 0;
+  uint8_t trivial = 0;
+  bool work = false;
+  QDesc qd;
+  uint64_t evals = 0;
+  std::vector<std::pair<int32_t, int32_t>> inst;  // per set
+};
+
+#define TRY_HIP(x)                  \
+  do {                              \
+    if ((x) != hipSuccess) {        \
+      return RD_EDEVICE;            \
+    }                               \
+  } while (0)
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* rd_strerror(int s) {
+  switch (s) {
+    case RD_OK: return "ok";
+    case RD_EINVAL: return "invalid argument or malformed model";
+    case RD_EUNSUPPORTED: return "outside the supported limits";
+    case RD_ERANGE: return "integer overflow or address outside its width";
+    case RD_EDIVZERO: return "division by zero";
+    case RD_ENOMEM: return "out of device memory";
+    case RD_EDEVICE: return "device error";
+    case RD_ECAPACITY: return "buffer too small";
+  }
+  return "unknown status";
+}
+
+int rd_context_create(rd_context** ctx, int hip_device) {
+  if (!ctx) return RD_EINVAL;
+  *ctx = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n)
+    return RD_EDEVICE;
+  if (hipSetDevice(hip_device) != hipSuccess) return RD_EDEVICE;
+  rd_context* c = new rd_context();
+  c->device = hip_device;
+  memset(&c->stats, 0, sizeof c->stats);
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return RD_EDEVICE;
+    }
+  const char* cfg = getenv("HGRD_LDS_CFG");
+  if (cfg) c->cfg = atoi(cfg) % 3;
+  *ctx = c;
+  return RD_OK;
+}
+
+void rd_context_destroy(rd_context* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  for (auto& kv : ctx->bufs)
+    if (kv.second.p) hipFree(kv.second.p);
+  for (auto& e : ctx->ev) hipEventDestroy(e);
+  delete ctx;
+}
+
+int rd_get_stats(const rd_context* ctx, rd_stats* out) {
+  if (!ctx || !out) return RD_EINVAL;
+  *out = ctx->stats;
+  return RD_OK;
+}
+
+int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
+                   uint32_t n_models, const rd_access_pair* pairs,
+                   uint32_t n_pairs, const rd_launch_domain* launch,
+                   const rd_param_sets* params, const rd_options* opt,
+                   rd_pair_result* out) {
+  if (!ctx) return RD_EINVAL;
+  if (n_pairs && (!pairs || !out)) return RD_EINVAL;
+  if (n_models && (!models || !launch || !params)) return RD_EINVAL;
+  rd_options o;
+  memset(&o, 0, sizeof o);
+  if (opt) o = *opt;
+  if (o.mode > RD_MODE_VERDICT || o.order > RD_ORDER_MLP) return RD_EINVAL;
+  const double t_start = now_ms();
+  if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
+  hipStream_t st = (hipStream_t)o.stream;
+  int cfg = ctx->cfg;
+  if (o.lds_cap) cfg = o.lds_cap <= 1024 ? 0 : o.lds_cap <= 1536 ? 1 : 2;
+  const uint32_t cap = (uint32_t)join_cap(cfg);
+  rd_stats& S = ctx->stats;
+  memset(&S, 0, sizeof S);
+
+  Planner P;
+  P.models = models;
+  P.launch = launch;
+  P.params = params;
+  P.dims.resize(n_models);
+  std::vector<uint32_t> model_err(n_models, 0);
+  for (uint32_t m = 0; m < n_models; ++m) {
+    const rd_kernel_model& M = models[m];
+    uint32_t e = 0;
+    if (launch[m].warp_size < 1 || launch[m].warp_size > 1024) e |= ERR_INVAL;
+    if (params[m].n_sets && !params[m].values) e |= ERR_INVAL;
+    if (M.n_acc && !M.acc) e |= ERR_INVAL;
+    if (!(e & ERR_INVAL)) {
+      for (int k = 0; k < 3; ++k)
+        e |= check_expr(M, launch[m].grid[k], CTX_LAUNCH, nullptr) |
+             check_expr(M, launch[m].block[k], CTX_LAUNCH, nullptr);
+      if (params[m].n_sets > kMaxSets) e |= ERR_UNSUP;
+    }
+    model_err[m] = e;
+    P.dims[m].resize(e ? 0 : params[m].n_sets);
+  }
+
+  // ---- per pair: validation, masks, instances -----------------------------
+  std::vector<QPlan> Q(n_pairs);
+  for (uint32_t k = 0; k < n_pairs; ++k) {
+    QPlan& q = Q[k];
+    const rd_access_pair& pr = pairs[k];
+    q.qd.mask = 0;
+    q.qd.self = 0;
+    q.qd.warp = 32;
+    q.qd.shared = 0;
+    if (pr.model >= n_models) { q.host_err = ERR_INVAL; continue; }
+    const rd_kernel_model& M = models[pr.model];
+    if (pr.a >= M.n_acc || pr.b >= M.n_acc) { q.host_err = ERR_INVAL; continue; }
+    const rd_access& A = M.acc[pr.a];
+    const rd_access& B = M.acc[pr.b];
+    uint32_t e = check_access(M, A) | check_access(M, B);
+    if (!(e & ERR_INVAL) && A.array != B.array) e |= ERR_INVAL;
+    if (!(e & ERR_INVAL)) e |= model_err[pr.model];
+    if (e & ERR_INVAL) e = ERR_INVAL;
+    q.host_err = e;
+    if (e) continue;
+    q.qd.mask = class_mask(M, A, B, pr.class_mask);
+    q.qd.self = pr.a == pr.b;
+    q.qd.warp = launch[pr.model].warp_size;
+    q.qd.shared = M.arrays[A.array].space == RD_SHARED;
+    if (q.qd.mask == 0) { q.trivial = 1; continue; }
+    const uint32_t ns = params[pr.model].n_sets;
+    q.inst.assign(ns, {-1, -1});
+    for (uint32_t s = 0; s < ns; ++s) {
+      InstInfo& ia = P.inst(pr.model, pr.a, s);
+      q.host_err |= ia.err;
+      q.evals += ia.box;
+      int32_t ib_idx = ia.idx;
+      if (q.qd.self) {
+        q.evals += ia.box;
+      } else {
+        InstInfo& ib = P.inst(pr.model, pr.b, s);
+        q.host_err |= ib.err;
+        q.evals += ib.box;
+        ib_idx = ib.idx;
+      }
+      q.inst[s] = {ia.idx, ib_idx};
+    }
+    q.work = !(q.host_err & (ERR_INVAL | ERR_UNSUP));
+  }
+
+  // ---- items ----------------------------------------------------------------
+  struct HPlan {
+    HItem h;
+    uint64_t R;
+  };
+  std::vector<SItem> sitems;
+  std::vector<HPlan> hplans;
+  auto npts_of = [&](int32_t idx) -> uint64_t {
+    return idx < 0 ? 0 : P.dev_insts[idx].npts;
+  };
+  for (uint32_t k = 0; k < n_pairs; ++k) {
+    QPlan& q = Q[k];
+    if (!q.work) continue;
+    for (uint32_t s = 0; s < q.inst.size(); ++s) {
+      int32_t ia = q.inst[s].first, ib = q.inst[s].second;
+      if (ia < 0 && ib < 0) continue;
+      // a side without points still has its points checked for errors; the
+      // missing side is replaced by the present one with an empty range
+      uint64_t na = npts_of(ia), nb = q.qd.self ? 0 : npts_of(ib);
+      int32_t ref = ia >= 0 ? ia : ib;
+      const AccInst& R0 = P.dev_insts[ref];
+      if (ia < 0 || ib < 0) {
+        // one side has no points because its loops failed: the pair already
+        // carries that error, but the other side's points are still scanned
+        // for errors (a stronger one may be among them); nothing is joined
+        HPlan hp;
+        memset(&hp, 0, sizeof hp);
+        hp.h.q = k;
+        hp.h.sigma = s;
+        hp.h.inst_i = (uint32_t)ref;
+        hp.h.inst_j = (uint32_t)ref;
+        hp.h.is32 = R0.is32;
+        hp.R = npts_of(ref);
+        hp.h.shared = 2;  // error scan only: never joined
+        hplans.push_back(hp);
+        continue;
+      }
+      const uint64_t tot = na + nb;
+      const uint64_t per_block =
+          (uint64_t)P.dev_insts[ia].tpb + (q.qd.self ? 0 : P.dev_insts[ib].tpb);
+      if (tot <= cap) {
+        SItem it;
+        memset(&it, 0, sizeof it);
+        it.q = k;
+        it.sigma = s;
+        it.inst_i = (uint32_t)ia;
+        it.inst_j = (uint32_t)ib;
+        it.b0 = 0;
+        it.b1 = R0.nblk;
+        sitems.push_back(it);
+      } else if (q.qd.shared && per_block <= cap) {
+        uint32_t bpi = (uint32_t)(cap / per_block);
+        for (uint32_t b0 = 0; b0 < R0.nblk; b0 += bpi) {
+          SItem it;
+          memset(&it, 0, sizeof it);
+          it.q = k;
+          it.sigma = s;
+          it.inst_i = (uint32_t)ia;
+          it.inst_j = (uint32_t)ib;
+          it.b0 = b0;
+          it.b1 = std::min(R0.nblk, b0 + bpi);
+          sitems.push_back(it);
+        }
+      } else {
+        HPlan hp;
+        memset(&hp, 0, sizeof hp);
+        hp.h.q = k;
+        hp.h.sigma = s;
+        hp.h.inst_i = (uint32_t)ia;
+        hp.h.inst_j = (uint32_t)ib;
+        hp.h.shared = q.qd.shared;
+        hp.h.is32 = R0.is32;
+        hp.R = tot;
+        hplans.push_back(hp);
+      }
+    }
+  }
+  S.small_items = sitems.size();
+
+  // ---- upload -------------------------------------------------------------
+  int merr = 0;
+  const size_t isz = devinst_size();
+  std::vector<unsigned char> dinst(isz * std::max<size_t>(1, P.dev_insts.size()));
+  for (size_t i = 0; i < P.dev_insts.size(); ++i)
+    fill_devinst(dinst.data() + i * isz, P.dev_insts[i]);
+  std::vector<QDesc> qd(n_pairs);
+  std::vector<uint32_t> herr(n_pairs);
+  std::vector<uint8_t> triv(n_pairs);
+  std::vector<u64> evals(n_pairs);
+  std::vector<QAcc> acc0(n_pairs);
+  for (uint32_t k = 0; k < n_pairs; ++k) {
+    qd[k] = Q[k].qd;
+    herr[k] = Q[k].host_err;
+    triv[k] = Q[k].trivial;
+    evals[k] = Q[k].evals;
+    S.evals += Q[k].evals;
+    QAcc& a = acc0[k];
+    memset(&a, 0, sizeof a);
+    a.pmin = kNoKey;
+    a.qmin = kNoKey;
+  }
+  auto up = [&](const char* name, const void* src, size_t bytes) -> void* {
+    void* d = ctx->ensure(name, bytes, &merr);
+    if (d && bytes) hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, st);
+    return d;
+  };
+  if (P.code.empty()) P.code.push_back(DInsn{});
+  if (P.pool_params.empty()) P.pool_params.push_back(0);
+  if (P.pool_loops.empty()) P.pool_loops.push_back(0);
+  const DInsn* d_code = (const DInsn*)up("code", P.code.data(), P.code.size() * sizeof(DInsn));
+  const int64_t* d_params = (const int64_t*)up("params", P.pool_params.data(), P.pool_params.size() * 8);
+  const int64_t* d_loops = (const int64_t*)up("loops", P.pool_loops.data(), P.pool_loops.size() * 8);
+  const void* d_insts = up("insts", dinst.data(), dinst.size());
+  const QDesc* d_qd = (const QDesc*)up("qdesc", qd.data(), n_pairs * sizeof(QDesc));
+  QAcc* d_acc = (QAcc*)up("qacc", acc0.data(), n_pairs * sizeof(QAcc));
+  const uint32_t* d_herr = (const uint32_t*)up("herr", herr.data(), n_pairs * 4);
+  const uint8_t* d_triv = (const uint8_t*)up("triv", triv.data(), n_pairs);
+  const u64* d_evals = (const u64*)up("evals", evals.data(), n_pairs * 8);
+  rd_pair_result* d_out = (rd_pair_result*)ctx->ensure("out", n_pairs * sizeof(rd_pair_result), &merr);
+  const SItem* d_sitems = (const SItem*)up("sitems", sitems.data(), sitems.size() * sizeof(SItem));
+  if (merr) return merr;
+
+  hipEvent_t* ev = ctx->ev;
+  TRY_HIP(hipEventRecord(ev[0], st));
+  // ---- small items: generate and join in LDS ------------------------------
+  if (!sitems.empty()) {
+    TRY_HIP(hipEventRecord(ev[2], st));
+    if (launch_small(cfg, st, d_sitems, (uint32_t)sitems.size(), d_insts, d_code,
+                     d_params, d_loops, d_qd, d_acc))
+      return RD_EDEVICE;
+    TRY_HIP(hipEventRecord(ev[3], st));
+    S.join_launches += 1;
+  }
+
+  // ---- HBM items, in waves bounded by memory -------------------------------
+  const uint64_t budget = o.max_device_bytes ? o.max_device_bytes : (24ull << 30);
+  double scatter_ms = 0, bucket_ms = 0, small_ms = 0, fallback_ms = 0;
+  if (!sitems.empty()) {
+    TRY_HIP(hipEventSynchronize(ev[3]));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev[2], ev[3]);
+    small_ms = ms;
+  }
+  size_t pos = 0;
+  std::vector<uint32_t> fallback;  // hplan indices
+  while (pos < hplans.size()) {
+    // choose a wave
+    size_t end = pos;
+    uint64_t bytes = 0, nbk = 0;
+    std::vector<Chunk> chunks;
+    std::vector<uint32_t> bucket_item;
+    while (end < hplans.size()) {
+      HPlan& hp = hplans[end];
+      uint64_t nbuckets = hp.h.shared == 2 ? 0
+                          : std::max<uint64_t>(1, (hp.R * 100 + cap * 55 - 1) / (cap * 55));
+      uint64_t ksz = hp.h.is32 ? 4 : 8;
+      uint64_t need = nbuckets * cap * (ksz + 4);
+      if (end > pos && bytes + need > budget) break;
+      hp.h.nbuckets = (uint32_t)nbuckets;
+      hp.h.bucket0 = (uint32_t)nbk;
+      hp.h.key_off = bytes;
+      bytes += (nbuckets * cap * ksz + 255) / 256 * 256;
+      hp.h.pid_off = 0;  // filled below
+      nbk += nbuckets;
+      ++end;
+    }
+    // point ids follow all keys; element offsets
+    uint64_t pid_base = 0;
+    for (size_t i = pos; i < end; ++i) {
+      hplans[i].h.pid_off = pid_base;
+      pid_base += (uint64_t)hplans[i].h.nbuckets * cap;
+    }
+    std::vector<HItem> hitems;
+    for (size_t i = pos; i < end; ++i) {
+      const HItem& h = hplans[i].h;
+      uint32_t li = (uint32_t)hitems.size();
+      hitems.push_back(h);
+      for (uint32_t b = 0; b < h.nbuckets; ++b) bucket_item.push_back(li);
+      const QPlan& q = Q[h.q];
+      for (int side = 0; side < (q.qd.self || h.shared == 2 ? 1 : 2); ++side) {
+        uint32_t inst = side ? h.inst_j : h.inst_i;
+        uint32_t np = P.dev_insts[inst].npts;
+        for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
+          chunks.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+      }
+    }
+    S.hbm_items += hitems.size();
+    S.buckets += nbk;
+    const HItem* d_hitems = (const HItem*)up("hitems", hitems.data(), hitems.size() * sizeof(HItem));
+    const Chunk* d_chunks = (const Chunk*)up("chunks", chunks.data(), chunks.size() * sizeof(Chunk));
+    const uint32_t* d_bitem = (const uint32_t*)up("bitem", bucket_item.data(), bucket_item.size() * 4);
+    unsigned char* d_keys = (unsigned char*)ctx->ensure("keys", bytes, &merr);
+    uint32_t* d_pids = (uint32_t*)ctx->ensure("pids", pid_base * 4, &merr);
+    uint32_t* d_cursor = (uint32_t*)ctx->ensure("cursor", nbk * 4, &merr);
+    uint32_t* d_ovf = (uint32_t*)ctx->ensure("ovf", hitems.size() * 4, &merr);
+    if (merr) return merr;
+    TRY_HIP(hipMemsetAsync(d_cursor, 0, nbk * 4, st));
+    TRY_HIP(hipMemsetAsync(d_ovf, 0, hitems.size() * 4, st));
+    TRY_HIP(hipEventRecord(ev[4], st));
+    if (launch_scatter(st, d_chunks, (uint32_t)chunks.size(), d_hitems, d_insts,
+                       d_code, d_params, d_loops, d_acc, d_keys, d_pids,
+                       d_cursor, d_ovf, cap))
+      return RD_EDEVICE;
+    TRY_HIP(hipEventRecord(ev[5], st));
+    if (nbk && launch_bucket(cfg, st, (uint32_t)nbk, 0, d_bitem, d_hitems, d_insts,
+                             d_code, d_params, d_loops, d_qd, d_acc, d_keys,
+                             d_pids, d_cursor, d_ovf))
+      return RD_EDEVICE;
+    TRY_HIP(hipEventRecord(ev[6], st));
+    if (nbk) S.join_launches += 1;
+    std::vector<uint32_t> ovf(hitems.size());
+    TRY_HIP(hipMemcpyAsync(ovf.data(), d_ovf, hitems.size() * 4, hipMemcpyDeviceToHost, st));
+    TRY_HIP(hipStreamSynchronize(st));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev[4], ev[5]);
+    scatter_ms += ms;
+    (void)hipEventElapsedTime(&ms, ev[5], ev[6]);
+    bucket_ms += ms;
+    for (size_t i = 0; i < hitems.size(); ++i) {
+      if (hitems[i].shared != 2) S.records += hplans[pos + i].R;
+      if (ovf[i] && hitems[i].shared != 2) fallback.push_back((uint32_t)(pos + i));
+    }
+    pos = end;
+  }
+
+  // ---- fallback: HBM hash aggregation per overflowed item ------------------
+  S.overflow_items = fallback.size();
+  for (uint32_t fi : fallback) {
+    HItem h = hplans[fi].h;
+    const QPlan& q = Q[h.q];
+    uint64_t R = hplans[fi].R;
+    GRecPtrs g;
+    g.addr = ctx->ensure("g_addr", R * 8, &merr);
+    g.blin = (uint32_t*)ctx->ensure("g_blin", R * 4, &merr);
+    g.tli = (uint32_t*)ctx->ensure("g_tli", R * 4, &merr);
+    g.bw = (uint32_t*)ctx->ensure("g_bw", R * 4, &merr);
+    g.w = (uint32_t*)ctx->ensure("g_w", R * 4, &merr);
+    g.slot = (uint32_t*)ctx->ensure("g_slot", R * 4, &merr);
+    g.part = ctx->ensure("g_part", R * 8, &merr);
+    uint32_t tbl = 1;
+    while (tbl < 2 * R) tbl <<= 1;
+    uint32_t* owner = (uint32_t*)ctx->ensure("g_owner", (size_t)tbl * 4, &merr);
+    void* cnt = ctx->ensure("g_cnt", (size_t)tbl * 8, &merr);
+    void* gS = ctx->ensure("g_S", 64, &merr);
+    uint32_t* gcount = (uint32_t*)ctx->ensure("g_count", 4, &merr);
+    if (merr) return merr;
+    std::vector<Chunk> chunks;
+    for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
+      uint32_t np = P.dev_insts[side ? h.inst_j : h.inst_i].npts;
+      for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
+        chunks.push_back({0, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+    }
+    const HItem* d_h = (const HItem*)up("fb_item", &h, sizeof h);
+    const Chunk* d_ch = (const Chunk*)up("fb_chunks", chunks.data(), chunks.size() * sizeof(Chunk));
+    if (merr) return merr;
+    TRY_HIP(hipMemsetAsync(gcount, 0, 4, st));
+    TRY_HIP(hipMemsetAsync(gS, 0, 64, st));
+    TRY_HIP(hipEventRecord(ev[7], st));
+    if (launch_gen_linear(st, d_ch, (uint32_t)chunks.size(), d_h, d_insts, d_code,
+                          d_params, d_loops, d_qd, g, gcount))
+      return RD_EDEVICE;
+    uint32_t n = 0;
+    TRY_HIP(hipMemcpyAsync(&n, gcount, 4, hipMemcpyDeviceToHost, st));
+    TRY_HIP(hipStreamSynchronize(st));
+    if (launch_glevels(st, g, n, q.qd.self, q.qd.mask, h.sigma, owner, cnt, tbl,
+                       gS, d_acc + h.q))
+      return RD_EDEVICE;
+    TRY_HIP(hipEventRecord(ev[8], st));
+    TRY_HIP(hipEventSynchronize(ev[8]));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev[7], ev[8]);
+    fallback_ms += ms;
+  }
+
+  // ---- witness pass 2 -------------------------------------------------------
+  std::vector<QAcc> acc(n_pairs);
+  if (n_pairs)
+    TRY_HIP(hipMemcpyAsync(acc.data(), d_acc, n_pairs * sizeof(QAcc), hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipStreamSynchronize(st));
+  struct W2 {
+    uint32_t q, inst_i, inst_j, p0, p1, pad0, pad1, pad2;
+  };
+  std::vector<W2> w2;
+  for (uint32_t k = 0; k < n_pairs; ++k) {
+    if (!Q[k].work || acc[k].err || acc[k].pmin == kNoKey || Q[k].host_err) continue;
+    uint32_t s = (uint32_t)(acc[k].pmin >> 52);
+    if (s >= Q[k].inst.size()) continue;
+    int32_t ia = Q[k].inst[s].first, ib = Q[k].inst[s].second;
+    if (ia < 0 || ib < 0) continue;
+    uint32_t np = P.dev_insts[ib].npts;
+    for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
+      w2.push_back({k, (uint32_t)ia, (uint32_t)ib, p0, std::min(np, p0 + kChunkPts), 0, 0, 0});
+  }
+  double w2_ms = 0;
+  if (!w2.empty()) {
+    const void* d_w2 = up("w2", w2.data(), w2.size() * sizeof(W2));
+    if (merr) return merr;
+    TRY_HIP(hipEventRecord(ev[9], st));
+    if (launch_witness2(st, d_w2, (uint32_t)w2.size(), d_insts, d_code, d_params,
+                        d_loops, d_qd, d_acc))
+      return RD_EDEVICE;
+    TRY_HIP(hipEventRecord(ev[10], st));
+  }
+  if (launch_finalize(st, n_pairs, d_acc, d_qd, d_herr, d_triv, d_evals, d_out))
+    return RD_EDEVICE;
+  TRY_HIP(hipEventRecord(ev[1], st));
+  if (n_pairs)
+    TRY_HIP(hipMemcpyAsync(out, d_out, n_pairs * sizeof(rd_pair_result), hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipStreamSynchronize(st));
+  float ms = 0;
+  if (!w2.empty()) {
+    (void)hipEventElapsedTime(&ms, ev[9], ev[10]);
+    w2_ms = ms;
+  }
+  (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+  S.device_ms = ms;
+  S.scatter_ms = scatter_ms;
+  S.join_ms = small_ms + bucket_ms;
+  S.join_kernel_ms = small_ms + bucket_ms;
+  S.witness_ms = w2_ms;
+  S.total_ms = now_ms() - t_start;
+  (void)fallback_ms;
+  if (o.log_level)
+    fprintf(stderr,
+            "[hgrd] pairs=%u small=%llu hbm=%llu buckets=%llu overflow=%llu "
+            "small=%.3fms scatter=%.3fms bucket=%.3fms fallback=%.3fms w2=%.3fms "
+            "device=%.3fms total=%.3fms\n",
+            n_pairs, (u64)S.small_items, (u64)S.hbm_items, (u64)S.buckets,
+            (u64)S.overflow_items, small_ms, scatter_ms, bucket_ms, fallback_ms,
+            w2_ms, S.device_ms, S.total_ms);
+  return RD_OK;
+}
+
+int rd_selftest(void) {
+  // constant-divisor helper used by the kernels: numerators below 2^31
+  static const uint32_t ds[] = {1, 2, 3, 5, 7, 10, 31, 32, 33, 63, 64, 100,
+                                255, 256, 257, 1000, 1023, 1024, 4095, 65535,
+                                65536, 65537, 1000003, 16777216, 67108863};
+  static const uint32_t ns[] = {0, 1, 2, 3, 1023, 1024, 65535, 65536,
+                                1000000, 16777215, 2147483646u, 2147483647u};
+  for (uint32_t d : ds) {
+    for (uint32_t n : ns)
+      if (!fastdiv_check(n, d)) return -1;
+    for (uint32_t k = 0; k < 4096; ++k) {
+      uint64_t n = (uint64_t)k * d + (k % 3 == 0 ? 0 : k % 3 == 1 ? d - 1 : d / 2);
+      if (n < (1ull << 31) && !fastdiv_check((uint32_t)n, d)) return -1;
+    }
+  }
+  uint64_t x = 88172645463325252ull;
+  for (int k = 0; k < 1000000; ++k) {
+    x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+    uint32_t d = (uint32_t)(x % 67108863u) + 1;
+    uint32_t n = (uint32_t)(x >> 33);
+    if (!fastdiv_check(n, d)) return -1;
+  }
+  return 0;
+}
+
+}  // extern "C"

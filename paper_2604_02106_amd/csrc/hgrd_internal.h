@@ -1,0 +1,117 @@
+// Internal layouts shared by the host driver (hgrd_host.cpp) and the gfx950
+// kernels (hgrd_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace hgrd {
+
+// ---------------------------------------------------------------------------
+// Device expression code.  The host compiles each postfix expression into
+// three-address code over a register file of kMaxStack int64 slots (small
+// enough to stay in VGPRs); every lane of a wavefront runs the same
+// instruction stream (one access instance per wavefront), so dispatch is a
+// uniform branch and register indices are uniform.  Operands are a stack
+// register, an immediate, a parameter of the tuple (launch extents follow
+// the parameters in the pool) or a point coordinate.
+constexpr int kCoordTid = 0;   // tx, ty, tz
+constexpr int kCoordBid = 3;   // bx, by, bz
+constexpr int kCoordLoop = 6;  // loop values, position 0..3 in the access
+constexpr int kNumCoords = 10;
+constexpr int kMaxStack = 16;
+
+enum DOp : uint8_t {
+  D_MOV = 0, D_ADD, D_SUB, D_MUL, D_DIV, D_MOD, D_SHL, D_SHR, D_AND, D_OR,
+  D_XOR, D_MIN, D_MAX, D_LT, D_LE, D_EQ, D_NE, D_GE, D_GT, D_LAND, D_LOR,
+  D_NEG, D_LNOT
+};
+enum DMode : uint8_t { M_REG = 0, M_IMM = 1, M_PARAM = 2, M_COORD = 3 };
+
+struct DInsn {
+  uint8_t op, dst, ma, mb;  // opcode, destination register, operand modes
+  uint16_t a, b;            // register / parameter / coordinate index
+  int64_t imm;              // immediate operand (mode M_IMM)
+};
+static_assert(sizeof(DInsn) == 16, "DInsn layout");
+
+// A compiled expression: `n` instructions at `off`; the value ends in
+// register `res`.  absent != 0: no expression (the default value).
+struct Prog {
+  uint32_t off;
+  uint16_t n;
+  uint8_t res;
+  uint8_t absent;
+};
+
+// Error bits (same meaning on host and device).
+constexpr uint32_t ERR_DIVZERO = 1, ERR_RANGE = 2, ERR_UNSUP = 4, ERR_INVAL = 8;
+// a tile received more records than planned (a library bug, never an input
+// property); reported as RD_EDEVICE for the pair
+constexpr uint32_t ERR_INTERNAL = 16;
+
+// One access under one parameter tuple.
+struct alignas(16) AccInst {
+  Prog addr, guard, bint, wint;  // 32 B
+  int32_t dims[6];               // gx gy gz bx by bz
+  uint32_t nblk, nthr, niota;    // |grid|, |block|, |iterations|
+  uint32_t n_loops;
+  uint32_t loop_n[4];            // iteration counts per enclosing loop
+  uint32_t loop_off[4];          // offsets into the loop-value pool
+  uint32_t params_off;           // offset into the parameter pool
+  uint32_t is32;                 // 32-bit array
+  uint32_t npts;                 // nblk * nthr * niota (< 2^31)
+  uint32_t tpb;                  // nthr * niota (points per block)
+};
+
+// Per-query description and accumulators.
+struct QDesc {
+  uint32_t mask;     // classes to check (bit 0 inter, 1 block, 2 warp)
+  uint32_t self;     // access a == access b
+  uint32_t warp;     // warp size of the analysed program
+  uint32_t shared;   // shared-memory array
+};
+
+struct QAcc {
+  unsigned long long cnt[3];  // ordered pair counts per class
+  unsigned long long pmin;    // smallest p key with a partner
+  unsigned long long qmin;    // smallest q key for pmin (pass 2)
+  unsigned int err;           // error bits seen on the device
+  unsigned int qclass;        // class of the witness (pass 2)
+  long long waddr;            // address of the witness
+};
+
+// A point key for the lexicographic witness order:
+// set (12 bits) | blin (26) | tlin (10) | ilin (16).
+__host__ __device__ inline unsigned long long pkey(uint32_t s, uint32_t b,
+                                                   uint32_t t, uint32_t i) {
+  return ((unsigned long long)s << 52) | ((unsigned long long)b << 26) |
+         ((unsigned long long)t << 16) | (unsigned long long)i;
+}
+constexpr unsigned long long kNoKey = ~0ull;
+
+// Work item joined in one workgroup's LDS: both sides of query q under
+// tuple `sigma`, blocks [b0, b1).
+struct SItem {
+  uint32_t q, sigma, inst_i, inst_j;
+  uint32_t b0, b1;
+  uint32_t pad0, pad1;
+};
+
+// Work item partitioned through HBM.
+struct HItem {
+  uint32_t q, sigma, inst_i, inst_j;
+  uint32_t nbuckets;      // number of buckets
+  uint32_t bucket0;       // first global bucket index
+  uint32_t shared;        // hash (addr, blin) instead of addr
+  uint32_t is32;          // 32-bit keys
+  unsigned long long key_off;  // byte offset of bucket 0's keys
+  unsigned long long pid_off;  // element offset of bucket 0's point ids
+};
+
+// A slice of one side's points, generated and scattered by one workgroup.
+struct Chunk {
+  uint32_t item, side;
+  uint32_t p0, p1;  // point index range
+};
+
+}  // namespace hgrd

@@ -1,0 +1,168 @@
+"""GPU path against the CPU oracle, field by field (EXACT mode is bit-exact:
+statuses, verdicts, per-class u64 counts, lexicographically smallest witness,
+witness class and address, evals).
+
+Every case prints its name before it runs so a failing device step names its
+case.  All inputs are seeded.
+"""
+import sys
+
+import pytest
+
+import oracle
+from workloads import (Access, Array, Launch, Loop, Model, Workload, c, param,
+                       tid, bid, bdim, loop, div, lt, GLOBAL, SHARED, WRITE,
+                       READ, ATOMIC, SCOPE_BLOCK)
+from workloads import families as F, configs
+from workloads.random_models import rand_workload
+
+pytestmark = pytest.mark.gpu
+
+I64MAX = (1 << 63) - 1
+
+
+@pytest.fixture(scope="module")
+def hg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2604_02106_amd as hg
+    hg.default_context()
+    return hg
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def compare(got, want, name=""):
+    assert len(got) == len(want)
+    for k, (g, w) in enumerate(zip(got, want)):
+        assert g == w, "%s pair %d:\n gpu    %r\n oracle %r" % (name, k, g, w)
+
+
+def run_both(hg, wl, name, **kw):
+    say(name, "pairs=%d" % len(wl.pairs), kw)
+    got = hg.check_pairs(wl, **kw)
+    want, _ = oracle.check_pairs(wl, "B", threads=8)
+    compare(got, want, name)
+    return got
+
+
+def test_tiny_config(hg):
+    wl = configs.tiny()
+    got = run_both(hg, wl, "tiny")
+    assert sum(r["verdict"] for r in got) == 16
+
+
+@pytest.mark.parametrize("cfg", [1024, 1536, 3072])
+def test_tiny_every_tile_shape(hg, cfg):
+    run_both(hg, configs.tiny(), "tiny lds_cap=%d" % cfg, lds_cap=cfg)
+
+
+def test_families(hg):
+    cases = [
+        ("F1", F.single(F.f1_neighbour(4, 64, 32), 0, 1)),
+        ("F1 big", F.single(F.f1_neighbour(300, 256, 32), 0, 1)),
+        ("F1 self", F.single(F.f1_neighbour(40, 128, 32), 0, 0)),
+        ("F2", F.single(F.f2_tree_reduction(64), 0, 1)),
+        ("F2 1024", F.single(F.f2_tree_reduction(1024), 0, 1)),
+        ("F2 barrier", F.single(F.f2_tree_reduction(256, barrier=True), 0, 1)),
+        ("F3", F.single(F.f3_stride_mod(64, (16, 48, 64, 100)), 0, 0)),
+        ("F3 shared", F.single(F.f3_stride_mod(1024, (16, 3), space=SHARED), 0, 0)),
+        ("F4", F.single(F.f4_guard_halves(64), 0, 0)),
+        ("F4+1", F.single(F.f4_guard_halves(64, extra=1), 0, 0)),
+        ("F4 none", F.single(F.f4_guard_halves(1024, guarded=False), 0, 0)),
+    ]
+    for name, wl in cases:
+        run_both(hg, wl, name)
+
+
+def test_paper_examples(hg):
+    cases = [
+        ("K1 square", F.k1_copy_upp_low([[16, 16], [32, 32], [48, 48]]), (1, 1)),
+        ("K1 32x1", F.k1_copy_upp_low([[32, 1]]), (1, 1)),
+        ("K1 rw", F.k1_copy_upp_low([[32, 32], [32, 1]]), (1, 0)),
+        ("K2", F.k2_reduce_final([[1], [2], [7]]), (0, 0)),
+        ("K3", F.k3_tone_mapping([[16, 1, 2], [32, 2, 2], [16, 2, 2]]), (0, 0)),
+        ("K4", F.k4_lud_internal([[64, 0], [64, 16], [64, -47]]), (0, 0)),
+        ("K5", F.k5_shift([[512], [0], [3]]), (0, 0)),
+    ]
+    for name, m, (a, b) in cases:
+        run_both(hg, F.single(m, a, b), name)
+
+
+@pytest.mark.parametrize("seed", range(0, 60))
+def test_random_models(hg, seed):
+    run_both(hg, rand_workload(seed), "rand seed=%d" % seed)
+
+
+def test_random_models_batched(hg):
+    # many random models in one call: LDS items, HBM items and masks together
+    models, pairs = [], []
+    for seed in range(100, 140):
+        wl = rand_workload(seed)
+        base = len(models)
+        models += wl.models
+        pairs += [(m + base, a, b, k) for (m, a, b, k) in wl.pairs]
+    run_both(hg, Workload(models, pairs), "rand batch")
+
+
+def test_heavy_hitter_fallback(hg):
+    """Every thread of a big grid writes one address: buckets overflow and
+    the query goes through the HBM hash aggregation."""
+    m = Model(0, [Array(GLOBAL, 32), Array(SHARED, 32)],
+              [Access(0, WRITE, c(5)), Access(0, READ, c(5) + tid() % 2),
+               Access(1, WRITE, tid() // 64), Access(0, WRITE, tid() // 4 + bid() * 2)],
+              Launch((64, 1, 1), (256, 1, 1), 32), [[]])
+    wl = Workload([m], [(0, 0, 0, 7), (0, 0, 1, 7), (0, 2, 2, 7), (0, 3, 3, 7),
+                        (0, 3, 1, 7), (0, 0, 3, 5)])
+    run_both(hg, wl, "heavy")
+
+
+def test_statuses(hg):
+    ms = []
+
+    def one(accs, launch=None, sets=([3],), loops=(), arrays=None):
+        arrays = arrays or [Array(GLOBAL, 64), Array(SHARED, 32)]
+        ms.append(Model(1, arrays, accs, launch or Launch((2, 1, 1), (8, 1, 1), 4),
+                        [list(s) for s in sets], loops=loops))
+        return len(ms) - 1
+
+    pairs = []
+    pairs.append((one([Access(0, WRITE, tid(), div(tid(), param(0) - 3))]), 0, 0, 7))
+    pairs.append((one([Access(0, WRITE, div(c(1), tid() - 7), lt(tid(), 7))]), 0, 0, 7))
+    pairs.append((one([Access(0, WRITE, c(I64MAX) + tid())]), 0, 0, 7))
+    pairs.append((one([Access(0, WRITE, div(c(I64MAX) + param(0), param(0) - 3))],
+                      sets=([1], [3])), 0, 0, 7))
+    pairs.append((one([Access(1, WRITE, c(1 << 31) + tid())]), 0, 0, 7))
+    pairs.append((one([Access(0, WRITE, tid())], launch=Launch((1, 1, 1), (2048, 1, 1))), 0, 0, 7))
+    pairs.append((one([Access(0, WRITE, tid(), bint=c(-1))]), 0, 0, 7))
+    pairs.append((one([Access(0, WRITE, tid()), Access(1, WRITE, tid())]), 0, 1, 7))
+    pairs.append((one([Access(0, WRITE, loop(0), loops=[0])], loops=[Loop(0, "lt", 1 << 20)]), 0, 0, 7))
+    pairs.append((one([Access(0, WRITE, c(0))], launch=Launch((param(0) - 3, 1, 1), (8, 1, 1))), 0, 0, 7))
+    pairs.append((one([Access(0, READ, c(0)), Access(0, READ, c(0))]), 0, 1, 7))
+    pairs.append((one([Access(0, ATOMIC, c(0), scope=SCOPE_BLOCK), Access(0, ATOMIC, c(0))]), 0, 1, 7))
+    # a loop whose update overflows on one side only: the other side's
+    # points are still scanned for a stronger error
+    pairs.append((one([Access(0, WRITE, loop(0), loops=[0]),
+                       Access(0, WRITE, tid(), bint=c(70000))],
+                      loops=[Loop(1, "lt", I64MAX, "mul", 3)]), 0, 1, 7))
+    run_both(hg, Workload(ms, pairs), "statuses")
+
+
+def test_batched_config_subset(hg):
+    """Batched uneven config at reduced grid scale, all pairs."""
+    wl = configs.batched(seed=2002, n_models=48, scale=0.05, max_iters=16)
+    got = run_both(hg, wl, "batched small")
+    assert any(r["verdict"] for r in got) and not all(r["verdict"] for r in got)
+
+
+def test_invariance_tile_shapes(hg):
+    wl = configs.batched(seed=77, n_models=16, scale=0.1, max_iters=8)
+    say("invariance")
+    base = hg.check_pairs(wl)
+    for cap in (1024, 3072):
+        compare(hg.check_pairs(wl, lds_cap=cap), base, "lds_cap=%d" % cap)
+    # a tiny device budget forces many HBM waves
+    compare(hg.check_pairs(wl, max_device_bytes=1 << 22), base, "waves")
