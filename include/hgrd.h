@@ -168,7 +168,9 @@ typedef struct {
   uint32_t log_level;  /* 0 silent, 1 summary, 2 per-launch (stderr) */
   uint32_t lds_cap;    /* records per LDS join tile; 0 = autotuned */
   uint32_t pad;
-  uint64_t max_device_bytes; /* working-set cap; 0 = library default */
+  uint64_t max_device_bytes; /* HBM bucket bytes per partition wave;
+                                0 = library default (96 MiB, sized to stay
+                                in the last-level cache) */
   void* stream;        /* hipStream_t; NULL = null stream */
 } rd_options;
 
@@ -207,18 +209,40 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
                    const rd_param_sets* params, const rd_options* opt,
                    rd_pair_result* out);
 
-/* Timing and size figures of the last rd_check_pairs call. */
+/* Two-step use of the same query: rd_prepare validates, lowers and plans
+ * the batch and copies every descriptor to device memory; rd_execute runs
+ * the kernels and returns the results, and may be called any number of
+ * times on one plan (the results are identical each time).  The plan owns
+ * its device memory until rd_plan_destroy.  rd_check_pairs is rd_prepare,
+ * rd_execute and rd_plan_destroy in one call.  Statuses as for
+ * rd_check_pairs.  A plan belongs to the context it was prepared on. */
+typedef struct rd_plan rd_plan;
+int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
+               uint32_t n_models, const rd_access_pair* pairs,
+               uint32_t n_pairs, const rd_launch_domain* launch,
+               const rd_param_sets* params, const rd_options* opt,
+               rd_plan** plan);
+int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out);
+void rd_plan_destroy(rd_plan* plan);
+
+/* Timing and size figures of the last rd_execute (or rd_check_pairs). */
 typedef struct {
   double total_ms;        /* host entry to results copied back */
   double device_ms;       /* first to last kernel, HIP events */
-  double join_ms;         /* LDS/bucket join kernels */
+  double join_ms;         /* LDS join kernels (small items + buckets) */
   double scatter_ms;      /* generate-and-partition kernels */
   double witness_ms;      /* witness pass 2 */
   uint64_t evals;         /* sum of the pairs' evals */
-  uint64_t records;       /* points written to HBM partitions */
+  uint64_t records;       /* point bound of the HBM-partitioned items */
   uint64_t small_items, hbm_items, overflow_items, buckets;
-  uint64_t join_launches; /* launches of the dominant (join) kernel */
+  uint64_t join_launches; /* launches of the join kernels */
   double join_kernel_ms;  /* summed duration of those launches */
+  double small_ms;        /* k_small_join */
+  double bucket_ms;       /* k_bucket_join */
+  double fallback_ms;     /* HBM aggregation of overflowed items */
+  double retry_ms;        /* re-partitioning of overflowed items */
+  uint64_t retry_items;   /* items re-partitioned with more buckets */
+  double waves_ms;        /* all partition waves (scatter + bucket join) */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

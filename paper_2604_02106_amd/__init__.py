@@ -103,13 +103,17 @@ class rd_stats(C.Structure):
                 ("records", C.c_uint64), ("small_items", C.c_uint64),
                 ("hbm_items", C.c_uint64), ("overflow_items", C.c_uint64),
                 ("buckets", C.c_uint64), ("join_launches", C.c_uint64),
-                ("join_kernel_ms", C.c_double)]
+                ("join_kernel_ms", C.c_double), ("small_ms", C.c_double),
+                ("bucket_ms", C.c_double), ("fallback_ms", C.c_double),
+                ("retry_ms", C.c_double), ("retry_items", C.c_uint64),
+                ("waves_ms", C.c_double)]
 
 
 assert C.sizeof(rd_pair_result) == 88
 
 EXPORTS = ("rd_context_create", "rd_context_destroy", "rd_check_pairs",
-           "rd_get_stats", "rd_strerror")
+           "rd_prepare", "rd_execute", "rd_plan_destroy", "rd_get_stats",
+           "rd_strerror", "rd_selftest")
 
 _lib = None
 
@@ -132,6 +136,18 @@ def lib():
             C.POINTER(rd_access_pair), C.c_uint32, C.POINTER(rd_launch_domain),
             C.POINTER(rd_param_sets), C.POINTER(rd_options),
             C.POINTER(rd_pair_result)]
+        L.rd_prepare.restype = C.c_int
+        L.rd_prepare.argtypes = [
+            C.c_void_p, C.POINTER(rd_kernel_model), C.c_uint32,
+            C.POINTER(rd_access_pair), C.c_uint32, C.POINTER(rd_launch_domain),
+            C.POINTER(rd_param_sets), C.POINTER(rd_options),
+            C.POINTER(C.c_void_p)]
+        L.rd_execute.restype = C.c_int
+        L.rd_execute.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(rd_pair_result)]
+        L.rd_plan_destroy.restype = None
+        L.rd_plan_destroy.argtypes = [C.c_void_p]
+        L.rd_selftest.restype = C.c_int
+        L.rd_selftest.argtypes = []
         L.rd_get_stats.restype = C.c_int
         L.rd_get_stats.argtypes = [C.c_void_p, C.POINTER(rd_stats)]
         L.rd_strerror.restype = C.c_char_p
@@ -241,6 +257,54 @@ def _stream_handle(stream):
     return None
 
 
+def _options(mode, order, lds_cap, max_device_bytes, log_level, stream):
+    return rd_options(mode, order, 0, log_level, lds_cap, 0, max_device_bytes,
+                      _stream_handle(stream))
+
+
+def _pairs(workload):
+    n = len(workload.pairs)
+    return (rd_access_pair * max(1, n))(
+        *[rd_access_pair(m, a, b, k) for (m, a, b, k) in workload.pairs])
+
+
+class Plan:
+    """rd_prepare'd batch: descriptors resident in device memory."""
+
+    def __init__(self, ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
+                 lds_cap=0, max_device_bytes=0, log_level=0, stream=None):
+        self.ctx = ctx
+        self.n = len(workload.pairs)
+        pk = Packed(workload)
+        pairs = _pairs(workload)
+        opt = _options(mode, order, lds_cap, max_device_bytes, log_level, stream)
+        self.h = C.c_void_p()
+        st = lib().rd_prepare(ctx.h, pk.models, pk.n_models, pairs, self.n,
+                              pk.launch, pk.params, C.byref(opt), C.byref(self.h))
+        if st != RD_OK:
+            raise RuntimeError("rd_prepare failed: %s" % rd_strerror(st))
+        self.out = (rd_pair_result * max(1, self.n))()
+
+    def execute(self, raw=False):
+        st = lib().rd_execute(self.ctx.h, self.h, self.out)
+        if st != RD_OK:
+            raise RuntimeError("rd_execute failed: %s" % rd_strerror(st))
+        if raw:
+            return self.out
+        return [result_dict(self.out[k]) for k in range(self.n)]
+
+    def close(self):
+        if self.h:
+            lib().rd_plan_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def rd_check_pairs(ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
                    lds_cap=0, max_device_bytes=0, log_level=0, stream=None,
                    packed=None):
@@ -250,11 +314,9 @@ def rd_check_pairs(ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
     """
     pk = packed or Packed(workload)
     n = len(workload.pairs)
-    pairs = (rd_access_pair * max(1, n))(
-        *[rd_access_pair(m, a, b, k) for (m, a, b, k) in workload.pairs])
+    pairs = _pairs(workload)
     out = (rd_pair_result * max(1, n))()
-    opt = rd_options(mode, order, 0, log_level, lds_cap, 0, max_device_bytes,
-                     _stream_handle(stream))
+    opt = _options(mode, order, lds_cap, max_device_bytes, log_level, stream)
     st = lib().rd_check_pairs(ctx.h, pk.models, pk.n_models, pairs, n,
                               pk.launch, pk.params, C.byref(opt), out)
     if st != RD_OK:

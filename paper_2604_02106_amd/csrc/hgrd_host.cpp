@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,8 @@ constexpr int64_t kMaxBlock = 1024;
 constexpr int64_t kMaxGrid = 1ll << 26;
 constexpr int64_t kMaxPoints = 1ll << 31;
 constexpr uint32_t kChunkPts = 8192;
+constexpr uint64_t kWaveBytes = 96ull << 20;
+constexpr uint64_t kFallbackRecords = 256ull << 20;
 
 // ---------------------------------------------------------------------------
 // checked int64 arithmetic on the host (errors yield 0, evaluation goes on)
@@ -322,7 +325,7 @@ struct rd_context {
     DevBuf& b = bufs[name];
     if (bytes == 0) bytes = 256;
     if (b.cap < bytes) {
-      if (b.p) hipFree(b.p);
+      if (b.p) (void)hipFree(b.p);
       b.p = nullptr;
       size_t want = std::max(bytes, b.cap + b.cap / 2);
       if (hipMalloc(&b.p, want) != hipSuccess) {
@@ -591,10 +594,10 @@ int rd_context_create(rd_context** ctx, int hip_device) {
 
 void rd_context_destroy(rd_context* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   for (auto& kv : ctx->bufs)
-    if (kv.second.p) hipFree(kv.second.p);
-  for (auto& e : ctx->ev) hipEventDestroy(e);
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto& e : ctx->ev) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -604,26 +607,77 @@ int rd_get_stats(const rd_context* ctx, rd_stats* out) {
   return RD_OK;
 }
 
-int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
-                   uint32_t n_models, const rd_access_pair* pairs,
-                   uint32_t n_pairs, const rd_launch_domain* launch,
-                   const rd_param_sets* params, const rd_options* opt,
-                   rd_pair_result* out) {
-  if (!ctx) return RD_EINVAL;
-  if (n_pairs && (!pairs || !out)) return RD_EINVAL;
+// A prepared batch: everything rd_execute needs, already in device memory.
+struct rd_plan_impl {
+  uint32_t n_pairs = 0;
+  int cfg = 1;
+  uint32_t cap = 1536;
+  uint32_t log_level = 0;
+  hipStream_t st = nullptr;
+  std::vector<QPlan> Q;
+  std::vector<uint32_t> npts;  // per device instance
+  uint64_t evals = 0;
+  uint32_t n_sitems = 0;
+  struct Wave {
+    uint32_t first_item, n_items, n_chunks, n_buckets;
+    uint64_t key_bytes, pid_elems;
+    uint64_t hitem_off, chunk_off, bitem_off;  // element offsets in the plan pools
+  };
+  std::vector<Wave> waves;
+  std::vector<HItem> hitems;   // all waves, wave-local bucket numbering
+  std::vector<uint64_t> hR;    // records bound per HBM item
+  std::vector<uint8_t> herr_scan;  // error-scan-only items
+  uint64_t max_key_bytes = 0, max_pid_elems = 0, max_buckets = 0, max_items = 0;
+  uint64_t wave_budget = 0;
+  std::map<std::string, DevBuf> dev;
+  void* buf(const char* name, size_t bytes, int* err) {
+    DevBuf& b = dev[name];
+    if (bytes == 0) bytes = 256;
+    if (b.cap < bytes) {
+      if (b.p) (void)hipFree(b.p);
+      b.p = nullptr;
+      b.cap = 0;
+      if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        b.p = nullptr;
+        *err = RD_ENOMEM;
+        return nullptr;
+      }
+      b.cap = bytes;
+    }
+    return b.p;
+  }
+  ~rd_plan_impl() {
+    for (auto& kv : dev)
+      if (kv.second.p) (void)hipFree(kv.second.p);
+  }
+};
+
+struct rd_plan : rd_plan_impl {};
+
+int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
+               uint32_t n_models, const rd_access_pair* pairs,
+               uint32_t n_pairs, const rd_launch_domain* launch,
+               const rd_param_sets* params, const rd_options* opt,
+               rd_plan** plan_out) {
+  if (!ctx || !plan_out) return RD_EINVAL;
+  *plan_out = nullptr;
+  if (n_pairs && !pairs) return RD_EINVAL;
   if (n_models && (!models || !launch || !params)) return RD_EINVAL;
   rd_options o;
   memset(&o, 0, sizeof o);
   if (opt) o = *opt;
   if (o.mode > RD_MODE_VERDICT || o.order > RD_ORDER_MLP) return RD_EINVAL;
-  const double t_start = now_ms();
   if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
-  hipStream_t st = (hipStream_t)o.stream;
+  rd_plan* plan = new rd_plan();
+  std::unique_ptr<rd_plan> guard(plan);
+  plan->n_pairs = n_pairs;
+  plan->st = (hipStream_t)o.stream;
+  plan->log_level = o.log_level;
   int cfg = ctx->cfg;
   if (o.lds_cap) cfg = o.lds_cap <= 1024 ? 0 : o.lds_cap <= 1536 ? 1 : 2;
+  plan->cfg = cfg;
   const uint32_t cap = (uint32_t)join_cap(cfg);
-  rd_stats& S = ctx->stats;
-  memset(&S, 0, sizeof S);
+  plan->cap = cap;
 
   Planner P;
   P.models = models;
@@ -648,7 +702,8 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
   }
 
   // ---- per pair: validation, masks, instances -----------------------------
-  std::vector<QPlan> Q(n_pairs);
+  std::vector<QPlan>& Q = plan->Q;
+  Q.resize(n_pairs);
   for (uint32_t k = 0; k < n_pairs; ++k) {
     QPlan& q = Q[k];
     const rd_access_pair& pr = pairs[k];
@@ -708,27 +763,25 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
     for (uint32_t s = 0; s < q.inst.size(); ++s) {
       int32_t ia = q.inst[s].first, ib = q.inst[s].second;
       if (ia < 0 && ib < 0) continue;
-      // a side without points still has its points checked for errors; the
-      // missing side is replaced by the present one with an empty range
-      uint64_t na = npts_of(ia), nb = q.qd.self ? 0 : npts_of(ib);
-      int32_t ref = ia >= 0 ? ia : ib;
-      const AccInst& R0 = P.dev_insts[ref];
       if (ia < 0 || ib < 0) {
         // one side has no points because its loops failed: the pair already
         // carries that error, but the other side's points are still scanned
         // for errors (a stronger one may be among them); nothing is joined
+        int32_t ref = ia >= 0 ? ia : ib;
         HPlan hp;
         memset(&hp, 0, sizeof hp);
         hp.h.q = k;
         hp.h.sigma = s;
         hp.h.inst_i = (uint32_t)ref;
         hp.h.inst_j = (uint32_t)ref;
-        hp.h.is32 = R0.is32;
+        hp.h.is32 = P.dev_insts[ref].is32;
         hp.R = npts_of(ref);
-        hp.h.shared = 2;  // error scan only: never joined
+        hp.h.shared = 2;  // error scan only
         hplans.push_back(hp);
         continue;
       }
+      const AccInst& R0 = P.dev_insts[ia];
+      const uint64_t na = npts_of(ia), nb = q.qd.self ? 0 : npts_of(ib);
       const uint64_t tot = na + nb;
       const uint64_t per_block =
           (uint64_t)P.dev_insts[ia].tpb + (q.qd.self ? 0 : P.dev_insts[ib].tpb);
@@ -769,201 +822,384 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
       }
     }
   }
-  S.small_items = sitems.size();
+  plan->n_sitems = (uint32_t)sitems.size();
 
-  // ---- upload -------------------------------------------------------------
-  int merr = 0;
-  const size_t isz = devinst_size();
-  std::vector<unsigned char> dinst(isz * std::max<size_t>(1, P.dev_insts.size()));
-  for (size_t i = 0; i < P.dev_insts.size(); ++i)
-    fill_devinst(dinst.data() + i * isz, P.dev_insts[i]);
-  std::vector<QDesc> qd(n_pairs);
-  std::vector<uint32_t> herr(n_pairs);
-  std::vector<uint8_t> triv(n_pairs);
-  std::vector<u64> evals(n_pairs);
-  std::vector<QAcc> acc0(n_pairs);
-  for (uint32_t k = 0; k < n_pairs; ++k) {
-    qd[k] = Q[k].qd;
-    herr[k] = Q[k].host_err;
-    triv[k] = Q[k].trivial;
-    evals[k] = Q[k].evals;
-    S.evals += Q[k].evals;
-    QAcc& a = acc0[k];
-    memset(&a, 0, sizeof a);
-    a.pmin = kNoKey;
-    a.qmin = kNoKey;
-  }
-  auto up = [&](const char* name, const void* src, size_t bytes) -> void* {
-    void* d = ctx->ensure(name, bytes, &merr);
-    if (d && bytes) hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, st);
-    return d;
-  };
-  if (P.code.empty()) P.code.push_back(DInsn{});
-  if (P.pool_params.empty()) P.pool_params.push_back(0);
-  if (P.pool_loops.empty()) P.pool_loops.push_back(0);
-  const DInsn* d_code = (const DInsn*)up("code", P.code.data(), P.code.size() * sizeof(DInsn));
-  const int64_t* d_params = (const int64_t*)up("params", P.pool_params.data(), P.pool_params.size() * 8);
-  const int64_t* d_loops = (const int64_t*)up("loops", P.pool_loops.data(), P.pool_loops.size() * 8);
-  const void* d_insts = up("insts", dinst.data(), dinst.size());
-  const QDesc* d_qd = (const QDesc*)up("qdesc", qd.data(), n_pairs * sizeof(QDesc));
-  QAcc* d_acc = (QAcc*)up("qacc", acc0.data(), n_pairs * sizeof(QAcc));
-  const uint32_t* d_herr = (const uint32_t*)up("herr", herr.data(), n_pairs * 4);
-  const uint8_t* d_triv = (const uint8_t*)up("triv", triv.data(), n_pairs);
-  const u64* d_evals = (const u64*)up("evals", evals.data(), n_pairs * 8);
-  rd_pair_result* d_out = (rd_pair_result*)ctx->ensure("out", n_pairs * sizeof(rd_pair_result), &merr);
-  const SItem* d_sitems = (const SItem*)up("sitems", sitems.data(), sitems.size() * sizeof(SItem));
-  if (merr) return merr;
-
-  hipEvent_t* ev = ctx->ev;
-  TRY_HIP(hipEventRecord(ev[0], st));
-  // ---- small items: generate and join in LDS ------------------------------
-  if (!sitems.empty()) {
-    TRY_HIP(hipEventRecord(ev[2], st));
-    if (launch_small(cfg, st, d_sitems, (uint32_t)sitems.size(), d_insts, d_code,
-                     d_params, d_loops, d_qd, d_acc))
-      return RD_EDEVICE;
-    TRY_HIP(hipEventRecord(ev[3], st));
-    S.join_launches += 1;
-  }
-
-  // ---- HBM items, in waves bounded by memory -------------------------------
-  const uint64_t budget = o.max_device_bytes ? o.max_device_bytes : (24ull << 30);
-  double scatter_ms = 0, bucket_ms = 0, small_ms = 0, fallback_ms = 0;
-  if (!sitems.empty()) {
-    TRY_HIP(hipEventSynchronize(ev[3]));
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, ev[2], ev[3]);
-    small_ms = ms;
-  }
+  // ---- waves of HBM items, bounded by the device budget --------------------
+  // A wave's buckets are small enough to stay in the last-level cache while
+  // they are filled and joined, so HBM sees whole lines.
+  const uint64_t budget = o.max_device_bytes ? o.max_device_bytes : kWaveBytes;
+  plan->wave_budget = budget;
+  std::vector<Chunk> all_chunks;
+  std::vector<uint32_t> all_bitem;
   size_t pos = 0;
-  std::vector<uint32_t> fallback;  // hplan indices
   while (pos < hplans.size()) {
-    // choose a wave
+    rd_plan_impl::Wave W;
+    memset(&W, 0, sizeof W);
+    W.first_item = (uint32_t)plan->hitems.size();
+    W.hitem_off = plan->hitems.size();
+    W.chunk_off = all_chunks.size();
+    W.bitem_off = all_bitem.size();
     size_t end = pos;
-    uint64_t bytes = 0, nbk = 0;
-    std::vector<Chunk> chunks;
-    std::vector<uint32_t> bucket_item;
+    uint64_t bytes = 0, nbk = 0, pid_base = 0;
     while (end < hplans.size()) {
       HPlan& hp = hplans[end];
-      uint64_t nbuckets = hp.h.shared == 2 ? 0
-                          : std::max<uint64_t>(1, (hp.R * 100 + cap * 55 - 1) / (cap * 55));
+      uint64_t nbuckets =
+          hp.h.shared == 2 ? 0
+                           : std::max<uint64_t>(1, (hp.R * 100 + cap * 55 - 1) / (cap * 55));
       uint64_t ksz = hp.h.is32 ? 4 : 8;
       uint64_t need = nbuckets * cap * (ksz + 4);
-      if (end > pos && bytes + need > budget) break;
+      if (end > pos && bytes + pid_base * 4 + need > budget) break;
       hp.h.nbuckets = (uint32_t)nbuckets;
       hp.h.bucket0 = (uint32_t)nbk;
       hp.h.key_off = bytes;
+      hp.h.pid_off = pid_base;
       bytes += (nbuckets * cap * ksz + 255) / 256 * 256;
-      hp.h.pid_off = 0;  // filled below
+      pid_base += nbuckets * cap;
       nbk += nbuckets;
       ++end;
     }
-    // point ids follow all keys; element offsets
-    uint64_t pid_base = 0;
-    for (size_t i = pos; i < end; ++i) {
-      hplans[i].h.pid_off = pid_base;
-      pid_base += (uint64_t)hplans[i].h.nbuckets * cap;
-    }
-    std::vector<HItem> hitems;
     for (size_t i = pos; i < end; ++i) {
       const HItem& h = hplans[i].h;
-      uint32_t li = (uint32_t)hitems.size();
-      hitems.push_back(h);
-      for (uint32_t b = 0; b < h.nbuckets; ++b) bucket_item.push_back(li);
+      uint32_t li = (uint32_t)plan->hitems.size();  // global item index
+      plan->hitems.push_back(h);
+      plan->hR.push_back(hplans[i].R);
+      for (uint32_t b = 0; b < h.nbuckets; ++b) all_bitem.push_back(li);
       const QPlan& q = Q[h.q];
       for (int side = 0; side < (q.qd.self || h.shared == 2 ? 1 : 2); ++side) {
         uint32_t inst = side ? h.inst_j : h.inst_i;
         uint32_t np = P.dev_insts[inst].npts;
         for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
-          chunks.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+          all_chunks.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
       }
     }
-    S.hbm_items += hitems.size();
-    S.buckets += nbk;
-    const HItem* d_hitems = (const HItem*)up("hitems", hitems.data(), hitems.size() * sizeof(HItem));
-    const Chunk* d_chunks = (const Chunk*)up("chunks", chunks.data(), chunks.size() * sizeof(Chunk));
-    const uint32_t* d_bitem = (const uint32_t*)up("bitem", bucket_item.data(), bucket_item.size() * 4);
-    unsigned char* d_keys = (unsigned char*)ctx->ensure("keys", bytes, &merr);
-    uint32_t* d_pids = (uint32_t*)ctx->ensure("pids", pid_base * 4, &merr);
-    uint32_t* d_cursor = (uint32_t*)ctx->ensure("cursor", nbk * 4, &merr);
-    uint32_t* d_ovf = (uint32_t*)ctx->ensure("ovf", hitems.size() * 4, &merr);
-    if (merr) return merr;
-    TRY_HIP(hipMemsetAsync(d_cursor, 0, nbk * 4, st));
-    TRY_HIP(hipMemsetAsync(d_ovf, 0, hitems.size() * 4, st));
-    TRY_HIP(hipEventRecord(ev[4], st));
-    if (launch_scatter(st, d_chunks, (uint32_t)chunks.size(), d_hitems, d_insts,
-                       d_code, d_params, d_loops, d_acc, d_keys, d_pids,
-                       d_cursor, d_ovf, cap))
-      return RD_EDEVICE;
-    TRY_HIP(hipEventRecord(ev[5], st));
-    if (nbk && launch_bucket(cfg, st, (uint32_t)nbk, 0, d_bitem, d_hitems, d_insts,
-                             d_code, d_params, d_loops, d_qd, d_acc, d_keys,
-                             d_pids, d_cursor, d_ovf))
-      return RD_EDEVICE;
-    TRY_HIP(hipEventRecord(ev[6], st));
-    if (nbk) S.join_launches += 1;
-    std::vector<uint32_t> ovf(hitems.size());
-    TRY_HIP(hipMemcpyAsync(ovf.data(), d_ovf, hitems.size() * 4, hipMemcpyDeviceToHost, st));
-    TRY_HIP(hipStreamSynchronize(st));
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, ev[4], ev[5]);
-    scatter_ms += ms;
-    (void)hipEventElapsedTime(&ms, ev[5], ev[6]);
-    bucket_ms += ms;
-    for (size_t i = 0; i < hitems.size(); ++i) {
-      if (hitems[i].shared != 2) S.records += hplans[pos + i].R;
-      if (ovf[i] && hitems[i].shared != 2) fallback.push_back((uint32_t)(pos + i));
-    }
+    W.n_items = (uint32_t)(end - pos);
+    W.n_chunks = (uint32_t)(all_chunks.size() - W.chunk_off);
+    W.n_buckets = (uint32_t)nbk;
+    W.key_bytes = bytes;
+    W.pid_elems = pid_base;
+    plan->max_key_bytes = std::max(plan->max_key_bytes, bytes);
+    plan->max_pid_elems = std::max(plan->max_pid_elems, pid_base);
+    plan->max_buckets = std::max(plan->max_buckets, nbk);
+    plan->max_items = std::max<uint64_t>(plan->max_items, W.n_items);
+    plan->waves.push_back(W);
     pos = end;
   }
 
-  // ---- fallback: HBM hash aggregation per overflowed item ------------------
-  S.overflow_items = fallback.size();
-  for (uint32_t fi : fallback) {
-    HItem h = hplans[fi].h;
-    const QPlan& q = Q[h.q];
-    uint64_t R = hplans[fi].R;
-    GRecPtrs g;
-    g.addr = ctx->ensure("g_addr", R * 8, &merr);
-    g.blin = (uint32_t*)ctx->ensure("g_blin", R * 4, &merr);
-    g.tli = (uint32_t*)ctx->ensure("g_tli", R * 4, &merr);
-    g.bw = (uint32_t*)ctx->ensure("g_bw", R * 4, &merr);
-    g.w = (uint32_t*)ctx->ensure("g_w", R * 4, &merr);
-    g.slot = (uint32_t*)ctx->ensure("g_slot", R * 4, &merr);
-    g.part = ctx->ensure("g_part", R * 8, &merr);
-    uint32_t tbl = 1;
-    while (tbl < 2 * R) tbl <<= 1;
-    uint32_t* owner = (uint32_t*)ctx->ensure("g_owner", (size_t)tbl * 4, &merr);
-    void* cnt = ctx->ensure("g_cnt", (size_t)tbl * 8, &merr);
-    void* gS = ctx->ensure("g_S", 64, &merr);
-    uint32_t* gcount = (uint32_t*)ctx->ensure("g_count", 4, &merr);
-    if (merr) return merr;
-    std::vector<Chunk> chunks;
-    for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
-      uint32_t np = P.dev_insts[side ? h.inst_j : h.inst_i].npts;
-      for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
-        chunks.push_back({0, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
-    }
-    const HItem* d_h = (const HItem*)up("fb_item", &h, sizeof h);
-    const Chunk* d_ch = (const Chunk*)up("fb_chunks", chunks.data(), chunks.size() * sizeof(Chunk));
-    if (merr) return merr;
-    TRY_HIP(hipMemsetAsync(gcount, 0, 4, st));
-    TRY_HIP(hipMemsetAsync(gS, 0, 64, st));
-    TRY_HIP(hipEventRecord(ev[7], st));
-    if (launch_gen_linear(st, d_ch, (uint32_t)chunks.size(), d_h, d_insts, d_code,
-                          d_params, d_loops, d_qd, g, gcount))
+  // ---- upload descriptors -----------------------------------------------------
+  int merr = 0;
+  const size_t isz = devinst_size();
+  std::vector<unsigned char> dinst(isz * std::max<size_t>(1, P.dev_insts.size()));
+  for (size_t i = 0; i < P.dev_insts.size(); ++i)
+    fill_devinst(dinst.data() + i * isz, P.dev_insts[i]);
+  plan->npts.resize(P.dev_insts.size());
+  for (size_t i = 0; i < P.dev_insts.size(); ++i) plan->npts[i] = P.dev_insts[i].npts;
+  std::vector<QDesc> qd(n_pairs);
+  std::vector<uint32_t> herr(n_pairs);
+  std::vector<uint8_t> triv(n_pairs);
+  std::vector<u64> evals(n_pairs);
+  for (uint32_t k = 0; k < n_pairs; ++k) {
+    qd[k] = Q[k].qd;
+    herr[k] = Q[k].host_err;
+    triv[k] = Q[k].trivial;
+    evals[k] = Q[k].evals;
+    plan->evals += Q[k].evals;
+  }
+  auto up = [&](const char* name, const void* src, size_t bytes) -> void* {
+    void* d = plan->buf(name, bytes, &merr);
+    if (d && bytes && hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+      merr = RD_EDEVICE;
+    return d;
+  };
+  if (P.code.empty()) P.code.push_back(DInsn{});
+  if (P.pool_params.empty()) P.pool_params.push_back(0);
+  if (P.pool_loops.empty()) P.pool_loops.push_back(0);
+  up("code", P.code.data(), P.code.size() * sizeof(DInsn));
+  up("params", P.pool_params.data(), P.pool_params.size() * 8);
+  up("loops", P.pool_loops.data(), P.pool_loops.size() * 8);
+  up("insts", dinst.data(), dinst.size());
+  up("qdesc", qd.data(), n_pairs * sizeof(QDesc));
+  up("herr", herr.data(), n_pairs * 4);
+  up("triv", triv.data(), n_pairs);
+  up("evals", evals.data(), n_pairs * 8);
+  up("sitems", sitems.data(), sitems.size() * sizeof(SItem));
+  up("hitems", plan->hitems.data(), plan->hitems.size() * sizeof(HItem));
+  up("chunks", all_chunks.data(), all_chunks.size() * sizeof(Chunk));
+  up("bitem", all_bitem.data(), all_bitem.size() * 4);
+  plan->buf("qacc", std::max<size_t>(1, n_pairs) * sizeof(QAcc), &merr);
+  plan->buf("out", std::max<size_t>(1, n_pairs) * sizeof(rd_pair_result), &merr);
+  if (merr) return merr;
+  *plan_out = guard.release();
+  return RD_OK;
+}
+
+void rd_plan_destroy(rd_plan* plan) { delete plan; }
+
+int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
+  if (!ctx || !plan) return RD_EINVAL;
+  const uint32_t n_pairs = plan->n_pairs;
+  if (n_pairs && !out) return RD_EINVAL;
+  const double t_start = now_ms();
+  if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
+  hipStream_t st = plan->st;
+  const int cfg = plan->cfg;
+  const uint32_t cap = plan->cap;
+  rd_stats& S = ctx->stats;
+  memset(&S, 0, sizeof S);
+  S.evals = plan->evals;
+  S.small_items = plan->n_sitems;
+  int merr = 0;
+  auto D = [&](const char* name) { return plan->dev[name].p; };
+  const DInsn* d_code = (const DInsn*)D("code");
+  const int64_t* d_params = (const int64_t*)D("params");
+  const int64_t* d_loops = (const int64_t*)D("loops");
+  const void* d_insts = D("insts");
+  const QDesc* d_qd = (const QDesc*)D("qdesc");
+  QAcc* d_acc = (QAcc*)D("qacc");
+  const uint32_t* d_herr = (const uint32_t*)D("herr");
+  const uint8_t* d_triv = (const uint8_t*)D("triv");
+  const u64* d_evals = (const u64*)D("evals");
+  rd_pair_result* d_out = (rd_pair_result*)D("out");
+  const SItem* d_sitems = (const SItem*)D("sitems");
+  const HItem* d_hitems_all = (const HItem*)D("hitems");
+  const Chunk* d_chunks_all = (const Chunk*)D("chunks");
+  const uint32_t* d_bitem_all = (const uint32_t*)D("bitem");
+  // scratch shared by all plans of the context
+  unsigned char* d_keys = (unsigned char*)ctx->ensure("keys", plan->max_key_bytes, &merr);
+  uint32_t* d_pids = (uint32_t*)ctx->ensure("pids", plan->max_pid_elems * 4, &merr);
+  uint32_t* d_cursor = (uint32_t*)ctx->ensure("cursor", plan->max_buckets * 4, &merr);
+  uint32_t* d_ovf = (uint32_t*)ctx->ensure("ovf", plan->max_items * 4, &merr);
+  if (merr) return merr;
+
+  hipEvent_t* ev = ctx->ev;
+  TRY_HIP(hipEventRecord(ev[0], st));
+  if (launch_init_acc(st, n_pairs, d_acc)) return RD_EDEVICE;
+  double small_ms = 0, scatter_ms = 0, bucket_ms = 0, fallback_ms = 0, retry_ms = 0;
+  if (plan->n_sitems) {
+    TRY_HIP(hipEventRecord(ev[2], st));
+    if (launch_small(cfg, st, d_sitems, plan->n_sitems, d_insts, d_code,
+                     d_params, d_loops, d_qd, d_acc))
       return RD_EDEVICE;
-    uint32_t n = 0;
-    TRY_HIP(hipMemcpyAsync(&n, gcount, 4, hipMemcpyDeviceToHost, st));
+    TRY_HIP(hipEventRecord(ev[3], st));
+    S.join_launches += 1;
+  }
+  if (plan->n_sitems) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev[2], ev[3]);
+    small_ms = ms;
+  }
+
+  // ---- HBM waves: no host round trip between waves; the scratch buckets
+  // are reused by the next wave in stream order.
+  const bool timing = plan->log_level >= 2 || getenv("HGRD_TIMING") != nullptr;
+  const uint32_t nh = (uint32_t)plan->hitems.size();
+  uint32_t* d_ovf_all = (uint32_t*)ctx->ensure("ovf", std::max<size_t>(1, nh) * 4, &merr);
+  if (merr) return merr;
+  auto run_waves = [&](const std::vector<rd_plan_impl::Wave>& waves,
+                       const HItem* d_hit, const Chunk* d_chk,
+                       const uint32_t* d_bit, uint32_t* d_ovf) -> int {
+    for (const auto& W : waves) {
+      if (launch_fill_u32(st, d_cursor, W.n_buckets, 0)) return RD_EDEVICE;
+      TRY_HIP(hipEventRecord(ev[4], st));
+      if (launch_scatter(st, d_chk + W.chunk_off, W.n_chunks, d_hit, d_insts,
+                         d_code, d_params, d_loops, d_acc, d_keys, d_pids,
+                         d_cursor, d_ovf, cap))
+        return RD_EDEVICE;
+      TRY_HIP(hipEventRecord(ev[5], st));
+      if (W.n_buckets &&
+          launch_bucket(cfg, st, W.n_buckets, 0, d_bit + W.bitem_off, d_hit,
+                        d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_keys,
+                        d_pids, d_cursor, d_ovf))
+        return RD_EDEVICE;
+      TRY_HIP(hipEventRecord(ev[6], st));
+      if (W.n_buckets) S.join_launches += 1;
+      S.buckets += W.n_buckets;
+      if (timing) {
+        TRY_HIP(hipEventSynchronize(ev[6]));
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ev[4], ev[5]);
+        scatter_ms += ms;
+        (void)hipEventElapsedTime(&ms, ev[5], ev[6]);
+        bucket_ms += ms;
+      }
+    }
+    return RD_OK;
+  };
+  if (nh) {
+    if (launch_fill_u32(st, d_ovf_all, nh, 0)) return RD_EDEVICE;
+    TRY_HIP(hipEventRecord(ev[11], st));
+    int rc = run_waves(plan->waves, d_hitems_all, d_chunks_all, d_bitem_all, d_ovf_all);
+    if (rc) return rc;
+    TRY_HIP(hipEventRecord(ev[12], st));
+  }
+  S.hbm_items = nh;
+  for (uint32_t i = 0; i < nh; ++i)
+    if (plan->hitems[i].shared != 2) S.records += plan->hR[i];
+  std::vector<uint32_t> ovf(nh);
+  if (nh) TRY_HIP(hipMemcpyAsync(ovf.data(), d_ovf_all, nh * 4, hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipStreamSynchronize(st));
+  double waves_ms = 0;
+  if (nh) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev[11], ev[12]);
+    waves_ms = ms;  // scatter and bucket joins together
+  }
+
+  // ---- retry overflowed items with more buckets ----------------------------
+  std::vector<uint32_t> retry;  // global item indices
+  for (uint32_t i = 0; i < nh; ++i)
+    if (ovf[i] && plan->hitems[i].shared != 2) retry.push_back(i);
+  std::vector<HItem> rh;
+  std::vector<uint64_t> rR;
+  std::vector<rd_plan_impl::Wave> rwaves;
+  std::vector<Chunk> rchunks;
+  std::vector<uint32_t> rbitem;
+  if (!retry.empty()) {
+    size_t pos = 0;
+    uint64_t max_bytes = 0, max_pids = 0, max_nbk = 0;
+    while (pos < retry.size()) {
+      rd_plan_impl::Wave W;
+      memset(&W, 0, sizeof W);
+      W.first_item = (uint32_t)rh.size();
+      W.chunk_off = rchunks.size();
+      W.bitem_off = rbitem.size();
+      uint64_t bytes = 0, nbk = 0, pid_base = 0;
+      size_t end = pos;
+      while (end < retry.size()) {
+        HItem h = plan->hitems[retry[end]];
+        uint64_t need_f = (ovf[retry[end]] * 10ull + cap * 6 - 1) / (cap * 6);
+        need_f = std::min<uint64_t>(std::max<uint64_t>(need_f, 2), 64);
+        uint64_t nbuckets = (uint64_t)h.nbuckets * need_f;
+        uint64_t ksz = h.is32 ? 4 : 8;
+        uint64_t need = nbuckets * cap * (ksz + 4);
+        if (end > pos && bytes + pid_base * 4 + need > plan->wave_budget) break;
+        h.nbuckets = (uint32_t)nbuckets;
+        h.bucket0 = (uint32_t)nbk;
+        h.key_off = bytes;
+        h.pid_off = pid_base;
+        bytes += (nbuckets * cap * ksz + 255) / 256 * 256;
+        pid_base += nbuckets * cap;
+        nbk += nbuckets;
+        uint32_t li = (uint32_t)rh.size();
+        rh.push_back(h);
+        rR.push_back(plan->hR[retry[end]]);
+        for (uint32_t b = 0; b < h.nbuckets; ++b) rbitem.push_back(li);
+        const QPlan& q = plan->Q[h.q];
+        for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
+          uint32_t np = plan->npts[side ? h.inst_j : h.inst_i];
+          for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
+            rchunks.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+        }
+        ++end;
+      }
+      W.n_items = (uint32_t)(end - pos);
+      W.n_chunks = (uint32_t)(rchunks.size() - W.chunk_off);
+      W.n_buckets = (uint32_t)nbk;
+      W.key_bytes = bytes;
+      W.pid_elems = pid_base;
+      rwaves.push_back(W);
+      max_bytes = std::max(max_bytes, bytes);
+      max_pids = std::max(max_pids, pid_base);
+      max_nbk = std::max(max_nbk, nbk);
+      pos = end;
+    }
+    d_keys = (unsigned char*)ctx->ensure("keys", std::max<uint64_t>(max_bytes, plan->max_key_bytes), &merr);
+    d_pids = (uint32_t*)ctx->ensure("pids", std::max<uint64_t>(max_pids, plan->max_pid_elems) * 4, &merr);
+    d_cursor = (uint32_t*)ctx->ensure("cursor", std::max<uint64_t>(max_nbk, plan->max_buckets) * 4, &merr);
+    const uint32_t nr = (uint32_t)rh.size();
+    HItem* d_rh = (HItem*)ctx->ensure("r_hitems", nr * sizeof(HItem), &merr);
+    Chunk* d_rc = (Chunk*)ctx->ensure("r_chunks", rchunks.size() * sizeof(Chunk), &merr);
+    uint32_t* d_rb = (uint32_t*)ctx->ensure("r_bitem", rbitem.size() * 4, &merr);
+    uint32_t* d_rovf = (uint32_t*)ctx->ensure("r_ovf", nr * 4, &merr);
+    if (merr) return merr;
+    TRY_HIP(hipMemcpyAsync(d_rh, rh.data(), nr * sizeof(HItem), hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemcpyAsync(d_rc, rchunks.data(), rchunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemcpyAsync(d_rb, rbitem.data(), rbitem.size() * 4, hipMemcpyHostToDevice, st));
+    if (launch_fill_u32(st, d_rovf, nr, 0)) return RD_EDEVICE;
+    TRY_HIP(hipEventRecord(ev[13], st));
+    int rc = run_waves(rwaves, d_rh, d_rc, d_rb, d_rovf);
+    if (rc) return rc;
+    TRY_HIP(hipEventRecord(ev[14], st));
+    ovf.assign(nr, 0);
+    TRY_HIP(hipMemcpyAsync(ovf.data(), d_rovf, nr * 4, hipMemcpyDeviceToHost, st));
     TRY_HIP(hipStreamSynchronize(st));
-    if (launch_glevels(st, g, n, q.qd.self, q.qd.mask, h.sigma, owner, cnt, tbl,
-                       gS, d_acc + h.q))
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev[13], ev[14]);
+    retry_ms = ms;
+  }
+  S.retry_items = rh.size();
+
+  // ---- fallback: HBM aggregation of items that still overflow --------------
+  std::vector<FItem> fall;
+  for (size_t i = 0; i < rh.size(); ++i) {
+    if (!ovf[i]) continue;
+    const HItem& h = rh[i];
+    const QPlan& q = plan->Q[h.q];
+    FItem f;
+    memset(&f, 0, sizeof f);
+    f.q = h.q;
+    f.sigma = h.sigma;
+    f.inst_i = h.inst_i;
+    f.inst_j = h.inst_j;
+    f.self = q.qd.self;
+    f.mask = q.qd.mask;
+    f.warp = q.qd.warp;
+    f.cap = (uint32_t)rR[i];
+    fall.push_back(f);
+  }
+  S.overflow_items = fall.size();
+  size_t fpos = 0;
+  while (fpos < fall.size()) {
+    size_t fend = fpos;
+    uint64_t n = 0;
+    uint32_t used = 0;
+    while (fend < fall.size() && (fend == fpos || n + fall[fend].cap <= kFallbackRecords)) {
+      fall[fend].off = n;
+      n += fall[fend].cap;
+      uint32_t m = fall[fend].mask;
+      used |= (m & 1 ? 0x03u : 0) | (m & 2 ? 0x0Cu : 0) | (m & 4 ? 0x30u : 0);
+      ++fend;
+    }
+    const uint32_t nf = (uint32_t)(fend - fpos);
+    std::vector<Chunk> chunks;
+    for (uint32_t i = 0; i < nf; ++i) {
+      const FItem& f = fall[fpos + i];
+      for (int side = 0; side < (f.self ? 1 : 2); ++side) {
+        uint32_t np = plan->npts[side ? f.inst_j : f.inst_i];
+        for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
+          chunks.push_back({i, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+      }
+    }
+    uint64_t tbl = 1;
+    while (tbl < 2 * n) tbl <<= 1;
+    GRecPtrs g;
+    g.addr = ctx->ensure("g_addr", n * 8, &merr);
+    g.blin = (uint32_t*)ctx->ensure("g_blin", n * 4, &merr);
+    g.tli = (uint32_t*)ctx->ensure("g_tli", n * 4, &merr);
+    g.bw = (uint32_t*)ctx->ensure("g_bw", n * 4, &merr);
+    g.w = (uint32_t*)ctx->ensure("g_w", n * 4, &merr);
+    g.item = (uint32_t*)ctx->ensure("g_item", n * 4, &merr);
+    g.slot = (uint32_t*)ctx->ensure("g_slot", n * 4, &merr);
+    g.part = ctx->ensure("g_part", n * 8, &merr);
+    uint32_t* owner = (uint32_t*)ctx->ensure("g_owner", tbl * 4, &merr);
+    void* cnt = ctx->ensure("g_cnt", tbl * 8, &merr);
+    void* gS = ctx->ensure("g_S", (size_t)nf * 64, &merr);
+    uint32_t* gcount = (uint32_t*)ctx->ensure("g_count", (size_t)nf * 4, &merr);
+    FItem* d_f = (FItem*)ctx->ensure("fb_items", nf * sizeof(FItem), &merr);
+    Chunk* d_ch = (Chunk*)ctx->ensure("fb_chunks", chunks.size() * sizeof(Chunk), &merr);
+    if (merr) return merr;
+    TRY_HIP(hipMemcpyAsync(d_f, fall.data() + fpos, nf * sizeof(FItem), hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemcpyAsync(d_ch, chunks.data(), chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
+    TRY_HIP(hipEventRecord(ev[7], st));
+    if (launch_fallback(st, d_ch, (uint32_t)chunks.size(), d_f, nf, used, d_insts,
+                        d_code, d_params, d_loops, g, n, gcount, owner, cnt, tbl,
+                        gS, d_acc))
       return RD_EDEVICE;
     TRY_HIP(hipEventRecord(ev[8], st));
     TRY_HIP(hipEventSynchronize(ev[8]));
     float ms = 0;
     (void)hipEventElapsedTime(&ms, ev[7], ev[8]);
     fallback_ms += ms;
+    fpos = fend;
   }
 
   // ---- witness pass 2 -------------------------------------------------------
@@ -976,19 +1212,21 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
   };
   std::vector<W2> w2;
   for (uint32_t k = 0; k < n_pairs; ++k) {
-    if (!Q[k].work || acc[k].err || acc[k].pmin == kNoKey || Q[k].host_err) continue;
+    const QPlan& q = plan->Q[k];
+    if (!q.work || acc[k].err || acc[k].pmin == kNoKey || q.host_err) continue;
     uint32_t s = (uint32_t)(acc[k].pmin >> 52);
-    if (s >= Q[k].inst.size()) continue;
-    int32_t ia = Q[k].inst[s].first, ib = Q[k].inst[s].second;
+    if (s >= q.inst.size()) continue;
+    int32_t ia = q.inst[s].first, ib = q.inst[s].second;
     if (ia < 0 || ib < 0) continue;
-    uint32_t np = P.dev_insts[ib].npts;
+    uint32_t np = plan->npts[ib];
     for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
       w2.push_back({k, (uint32_t)ia, (uint32_t)ib, p0, std::min(np, p0 + kChunkPts), 0, 0, 0});
   }
   double w2_ms = 0;
   if (!w2.empty()) {
-    const void* d_w2 = up("w2", w2.data(), w2.size() * sizeof(W2));
+    void* d_w2 = ctx->ensure("w2", w2.size() * sizeof(W2), &merr);
     if (merr) return merr;
+    TRY_HIP(hipMemcpyAsync(d_w2, w2.data(), w2.size() * sizeof(W2), hipMemcpyHostToDevice, st));
     TRY_HIP(hipEventRecord(ev[9], st));
     if (launch_witness2(st, d_w2, (uint32_t)w2.size(), d_insts, d_code, d_params,
                         d_loops, d_qd, d_acc))
@@ -1011,18 +1249,36 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
   S.scatter_ms = scatter_ms;
   S.join_ms = small_ms + bucket_ms;
   S.join_kernel_ms = small_ms + bucket_ms;
+  S.small_ms = small_ms;
+  S.bucket_ms = bucket_ms;
+  S.fallback_ms = fallback_ms;
+  S.retry_ms = retry_ms;
+  S.waves_ms = waves_ms;
   S.witness_ms = w2_ms;
   S.total_ms = now_ms() - t_start;
-  (void)fallback_ms;
-  if (o.log_level)
+  if (plan->log_level)
     fprintf(stderr,
             "[hgrd] pairs=%u small=%llu hbm=%llu buckets=%llu overflow=%llu "
-            "small=%.3fms scatter=%.3fms bucket=%.3fms fallback=%.3fms w2=%.3fms "
-            "device=%.3fms total=%.3fms\n",
+            "retry=%llu small=%.3fms waves=%.3fms (scatter %.3f bucket %.3f) "
+            "retry=%.3fms fallback=%.3fms w2=%.3fms device=%.3fms total=%.3fms\n",
             n_pairs, (u64)S.small_items, (u64)S.hbm_items, (u64)S.buckets,
-            (u64)S.overflow_items, small_ms, scatter_ms, bucket_ms, fallback_ms,
-            w2_ms, S.device_ms, S.total_ms);
+            (u64)S.overflow_items, (u64)S.retry_items, small_ms, waves_ms,
+            scatter_ms, bucket_ms, retry_ms, fallback_ms, w2_ms, S.device_ms, S.total_ms);
   return RD_OK;
+}
+
+int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
+                   uint32_t n_models, const rd_access_pair* pairs,
+                   uint32_t n_pairs, const rd_launch_domain* launch,
+                   const rd_param_sets* params, const rd_options* opt,
+                   rd_pair_result* out) {
+  if (n_pairs && !out) return RD_EINVAL;
+  rd_plan* plan = nullptr;
+  int rc = rd_prepare(ctx, models, n_models, pairs, n_pairs, launch, params, opt, &plan);
+  if (rc != RD_OK) return rc;
+  rc = rd_execute(ctx, plan, out);
+  rd_plan_destroy(plan);
+  return rc;
 }
 
 int rd_selftest(void) {

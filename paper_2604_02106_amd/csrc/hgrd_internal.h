@@ -108,6 +108,14 @@ struct HItem {
   unsigned long long pid_off;  // element offset of bucket 0's point ids
 };
 
+// A query/tuple aggregated in HBM (fallback for heavy keys): its records
+// occupy [off, off + cap) of the flat record arrays.
+struct FItem {
+  uint32_t q, sigma, inst_i, inst_j;
+  uint32_t self, mask, warp, cap;
+  unsigned long long off;
+};
+
 // A slice of one side's points, generated and scattered by one workgroup.
 struct Chunk {
   uint32_t item, side;

@@ -554,11 +554,12 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
       pids[h.pid_off + slot] = (ch.side << 31) | pidx;
     } else {
       over = true;
+      atomicMax(&ovf[ch.item], pos + 1);  // largest bucket load seen
     }
   }
   err = wave_or(err);
   if ((threadIdx.x & 63) == 0 && err) atomicOr(&acc[h.q].err, err);
-  if (over) atomicOr(&ovf[ch.item], 1u);
+  (void)over;
 }
 
 // ---------------------------------------------------------------------------
@@ -625,11 +626,12 @@ k_bucket_join(const uint32_t* __restrict__ bucket_item,
 }
 
 // ---------------------------------------------------------------------------
-// Fallback for items whose buckets overflowed (many points on few
-// addresses): records go to a flat HBM array and every prefix level is
-// aggregated in an HBM hash table with global atomics.  Lanes of one
-// wavefront that carry the same level key are merged first (a match loop
-// built from ballots), so hot keys cost one atomic per wavefront.
+// Fallback for items that still overflow after a retry with more buckets
+// (a single address, or a single (address, block), carries more points than
+// one LDS tile holds).  Records of all such items go to one flat HBM array;
+// every prefix level is aggregated in an HBM hash table keyed by (item,
+// level key).  Each workgroup first merges its tile of records in an LDS
+// table, so a hot key costs one global atomic per workgroup, not per point.
 
 struct GRec {
   u64* addr;
@@ -637,21 +639,21 @@ struct GRec {
   uint32_t* tli;
   uint32_t* bw;
   uint32_t* w;
+  uint32_t* item;  // fallback item index, 0xFFFFFFFF: empty slot
   uint32_t* slot;
   long long* part;
 };
 
 __global__ void __launch_bounds__(256)
-k_gen_linear(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
+k_gen_linear(const Chunk* __restrict__ chunks, const FItem* __restrict__ fitems,
              const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
              const int64_t* __restrict__ params,
-             const int64_t* __restrict__ loopvals, const QDesc* __restrict__ qd,
-             GRec rec, uint32_t* __restrict__ count) {
+             const int64_t* __restrict__ loopvals, GRec rec,
+             uint32_t* __restrict__ count) {
   const Chunk ch = chunks[blockIdx.x];
-  const HItem h = hitems[ch.item];
-  const QDesc q = qd[h.q];
+  const FItem f = fitems[ch.item];
   DevInst I;
-  load_inst(I, insts, ch.side ? h.inst_j : h.inst_i);
+  load_inst(I, insts, ch.side ? f.inst_j : f.inst_i);
   uint32_t err = 0;
   for (uint32_t base = ch.p0; base < ch.p1; base += blockDim.x) {
     uint32_t pidx = base + threadIdx.x;
@@ -669,22 +671,26 @@ k_gen_linear(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
     uint32_t lane = threadIdx.x & 63;
     uint32_t leader = __ffsll((long long)bal) - 1;
     uint32_t b0 = 0;
-    if (lane == leader) b0 = atomicAdd(count, (uint32_t)__popcll(bal));
+    if (lane == leader) b0 = atomicAdd(&count[ch.item], (uint32_t)__popcll(bal));
     b0 = __shfl(b0, leader, 64);
     if (valid) {
-      uint32_t r = b0 + __popcll(bal & ((1ull << lane) - 1));
-      rec.addr[r] = (u64)pt.addr;
-      rec.blin[r] = id.blin;
-      rec.tli[r] = (id.ilin << 16) | (ch.side << 15) | id.tlin;
-      rec.bw[r] = (pt.bint << 16) | pt.wint;
-      rec.w[r] = id.tlin / q.warp;
-      rec.part[r] = 0;
+      uint32_t k = b0 + __popcll(bal & ((1ull << lane) - 1));
+      if (k < f.cap) {
+        u64 r = f.off + k;
+        rec.addr[r] = (u64)pt.addr;
+        rec.blin[r] = id.blin;
+        rec.tli[r] = (id.ilin << 16) | (ch.side << 15) | id.tlin;
+        rec.bw[r] = (pt.bint << 16) | pt.wint;
+        rec.w[r] = id.tlin / f.warp;
+        rec.item[r] = ch.item;
+        rec.part[r] = 0;
+      }
     }
   }
 }
 
-__device__ __forceinline__ bool g_level_eq(const GRec& g, int L, uint32_t x,
-                                           uint32_t y) {
+__device__ __forceinline__ bool g_level_eq(const GRec& g, int L, u64 x, u64 y) {
+  if (g.item[x] != g.item[y]) return false;
   if (g.addr[x] != g.addr[y]) return false;
   if (L >= 1 && g.blin[x] != g.blin[y]) return false;
   if (L >= 2 && (g.bw[x] >> 16) != (g.bw[y] >> 16)) return false;
@@ -694,124 +700,140 @@ __device__ __forceinline__ bool g_level_eq(const GRec& g, int L, uint32_t x,
   return true;
 }
 
-__global__ void __launch_bounds__(256)
-k_gclear(uint32_t* __restrict__ owner, u64* __restrict__ cnt, uint32_t tbl) {
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < tbl;
-       k += gridDim.x * blockDim.x) {
-    owner[k] = kEmpty;
-    cnt[k] = 0;
-  }
+__device__ __forceinline__ uint32_t g_hash(const GRec& g, int L, u64 r) {
+  return level_hash(L, g.addr[r] ^ ((u64)g.item[r] * 0x2545F4914F6CDD1Dull),
+                    g.blin[r], g.bw[r], g.w[r], g.tli[r] & 0x3FF);
 }
 
-// Inserts every record at level L; S += sum of pair contributions.
+__device__ __forceinline__ bool uses_level(uint32_t mask, int L) {
+  return (mask >> (L >> 1)) & 1;
+}
+
+constexpr int kGTile = 1024;  // records per workgroup step
+constexpr int kGLocal = 2048; // LDS table slots
+
+// Inserts every record at level L.  S[item * 8 + L] += pair contributions.
 __global__ void __launch_bounds__(256)
-k_ginsert(GRec g, uint32_t n, int L, uint32_t self, uint32_t* __restrict__ owner,
-          u64* __restrict__ cnt, uint32_t tbl_mask, u64* __restrict__ S) {
-  u64 s = 0;
-  const uint32_t lane = threadIdx.x & 63;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n;
-       base += gridDim.x * blockDim.x) {
-    uint32_t r = base + threadIdx.x;
-    bool active = r < n;
-    uint32_t side = 0;
-    uint32_t h = 0;
-    if (active) {
-      side = (g.tli[r] >> 15) & 1;
-      h = level_hash(L, g.addr[r], g.blin[r], g.bw[r], g.w[r],
-                     g.tli[r] & 0x3FF) & tbl_mask;
+k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
+          uint32_t* __restrict__ owner, u64* __restrict__ cnt, u64 tbl_mask,
+          u64* __restrict__ S) {
+  __shared__ uint32_t lown[kGLocal];
+  __shared__ uint32_t lcnt[kGLocal];
+  __shared__ uint32_t lgs[kGLocal];
+  const uint32_t tid = threadIdx.x;
+  for (u64 t0 = (u64)blockIdx.x * kGTile; t0 < n; t0 += (u64)gridDim.x * kGTile) {
+    for (uint32_t k = tid; k < kGLocal; k += blockDim.x) {
+      lown[k] = kEmpty;
+      lcnt[k] = 0;
     }
-    // wavefront match: lanes with the leader's key join one atomic, while
-    // the leader's key has duplicates; the rest insert one by one
-    u64 pending = __ballot(active);
-    while (pending) {
-      uint32_t leader = __ffsll((long long)pending) - 1;
-      uint32_t lr = __shfl(r, leader, 64);
-      bool same = active && ((pending >> lane) & 1) && g_level_eq(g, L, lr, r);
-      u64 grp = __ballot(same);
-      if (__popcll(grp) == 1) break;
-      uint32_t na = __popcll(__ballot(same && side == 0));
-      uint32_t nb = __popcll(grp) - na;
-      uint32_t slot = 0;
-      u64 old = 0;
-      if (lane == leader) {
-        uint32_t hh = h;
-        for (;;) {
-          uint32_t o = atomicCAS(&owner[hh], kEmpty, r);
-          if (o == kEmpty || g_level_eq(g, L, o, r)) break;
-          hh = (hh + 1) & tbl_mask;
-        }
-        slot = hh;
-        u64 inc = self ? (u64)(na + nb) : ((u64)na | ((u64)nb << 32));
-        old = atomicAdd(&cnt[hh], inc);
-      }
-      slot = __shfl(slot, leader, 64);
-      old = __shfl(old, leader, 64);
-      if (lane == leader) {
-        if (self) {
-          u64 m0 = old, k = na + nb;
-          s += 2 * m0 * k + k * k;  // (m0 + k)^2 - m0^2
-        } else {
-          u64 oa = old & 0xFFFFFFFFull, ob = old >> 32;
-          s += (u64)na * ob + (u64)nb * oa + (u64)na * nb;
-        }
-      }
-      if (same) g.slot[r] = slot;
-      pending &= ~grp;
-    }
-    if ((pending >> lane) & 1) {
-      uint32_t hh = h;
+    __syncthreads();
+    uint16_t ls[kGTile / 256];
+#pragma unroll
+    for (int j = 0; j < kGTile / 256; ++j) {
+      ls[j] = 0xFFFF;
+      u64 r = t0 + j * 256 + tid;
+      if (r >= n) continue;
+      uint32_t it = g.item[r];
+      if (it == kEmpty) continue;
+      const FItem f = fitems[it];
+      if (!uses_level(f.mask, L)) continue;
+      uint32_t h = g_hash(g, L, r) & (kGLocal - 1);
+      const uint32_t lr = (uint32_t)(r - t0);
       for (;;) {
-        uint32_t o = atomicCAS(&owner[hh], kEmpty, r);
-        if (o == kEmpty || g_level_eq(g, L, o, r)) break;
-        hh = (hh + 1) & tbl_mask;
+        uint32_t o = atomicCAS(&lown[h], kEmpty, lr);
+        if (o == kEmpty || g_level_eq(g, L, t0 + o, r)) break;
+        h = (h + 1) & (kGLocal - 1);
       }
-      u64 inc = (self || side == 0) ? 1ull : (1ull << 32);
-      u64 old = atomicAdd(&cnt[hh], inc);
-      if (self) s += 2 * old + 1;
-      else s += side ? (old & 0xFFFFFFFFull) : (old >> 32);
-      g.slot[r] = hh;
+      uint32_t side = (g.tli[r] >> 15) & 1;
+      atomicAdd(&lcnt[h], (f.self || !side) ? 1u : 0x10000u);
+      ls[j] = (uint16_t)h;
     }
+    __syncthreads();
+    // merge each local group into the global table
+    for (uint32_t k = tid; k < kGLocal; k += blockDim.x) {
+      uint32_t lr = lown[k];
+      if (lr == kEmpty) continue;
+      u64 r = t0 + lr;
+      const uint32_t it = g.item[r];
+      const FItem f = fitems[it];
+      u64 h = g_hash(g, L, r) & tbl_mask;
+      for (;;) {
+        uint32_t o = atomicCAS(&owner[h], kEmpty, (uint32_t)r);
+        if (o == kEmpty || g_level_eq(g, L, o, r)) break;
+        h = (h + 1) & tbl_mask;
+      }
+      uint32_t c = lcnt[k];
+      u64 li = c & 0xFFFF, lj = c >> 16;
+      u64 old = atomicAdd(&cnt[h], f.self ? li : (li | (lj << 32)));
+      u64 contrib;
+      if (f.self) contrib = 2 * old * li + li * li;  // (old + k)^2 - old^2
+      else contrib = li * (old >> 32) + lj * (old & 0xFFFFFFFFull) + li * lj;
+      if (contrib) atomicAdd(&S[(u64)it * 8 + L], contrib);
+      lgs[k] = (uint32_t)h;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kGTile / 256; ++j) {
+      u64 r = t0 + j * 256 + tid;
+      if (ls[j] != 0xFFFF) g.slot[r] = lgs[ls[j]];
+    }
+    __syncthreads();
   }
-  s = wave_sum(s);
-  if (lane == 0 && s) atomicAdd(S, s);
 }
 
 // Adds +-(partners at level L) to every record of side a (self: all).
 __global__ void __launch_bounds__(256)
-k_gpartner(GRec g, uint32_t n, int L, uint32_t self,
+k_gpartner(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
            const u64* __restrict__ cnt) {
   const long long sign = (L & 1) ? -1 : 1;
-  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n;
-       r += gridDim.x * blockDim.x) {
+  for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (u64)gridDim.x * blockDim.x) {
+    uint32_t it = g.item[r];
+    if (it == kEmpty) continue;
+    const FItem f = fitems[it];
+    if (!uses_level(f.mask, L)) continue;
     uint32_t side = (g.tli[r] >> 15) & 1;
-    if (!self && side) continue;
+    if (!f.self && side) continue;
     u64 c = cnt[g.slot[r]];
-    long long nj = self ? (long long)c : (long long)(c >> 32);
+    long long nj = f.self ? (long long)c : (long long)(c >> 32);
     g.part[r] += sign * nj;
   }
 }
 
-// Witness candidates and class counts of a fallback item.
+// Witness candidates of the fallback records.
 __global__ void __launch_bounds__(256)
-k_gfinish(GRec g, uint32_t n, uint32_t self, uint32_t sigma,
-          const u64* __restrict__ S, uint32_t mask, QAcc* __restrict__ acc) {
-  u64 best = kNoKey;
-  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n;
-       r += gridDim.x * blockDim.x) {
+k_gfinish(GRec g, u64 n, const FItem* __restrict__ fitems,
+          QAcc* __restrict__ acc) {
+  for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (u64)gridDim.x * blockDim.x) {
+    uint32_t it = g.item[r];
+    if (it == kEmpty) continue;
+    const FItem f = fitems[it];
     uint32_t tl = g.tli[r];
-    if (!self && (tl & kSide)) continue;
+    if (!f.self && (tl & kSide)) continue;
     if (g.part[r] > 0) {
-      u64 k = pkey(sigma, g.blin[r], tl & 0x3FF, tl >> 16);
-      best = k < best ? k : best;
+      u64 k = pkey(f.sigma, g.blin[r], tl & 0x3FF, tl >> 16);
+      if (k < acc[f.q].pmin) atomicMin(&acc[f.q].pmin, k);
     }
   }
-  best = wave_min(best);
-  if ((threadIdx.x & 63) == 0 && best != kNoKey) atomicMin(&acc->pmin, best);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (mask & 1) atomicAdd(&acc->cnt[0], S[0] - S[1]);
-    if (mask & 2) atomicAdd(&acc->cnt[1], S[2] - S[3]);
-    if (mask & 4) atomicAdd(&acc->cnt[2], S[4] - S[5]);
-  }
+}
+
+// Class counts of each fallback item from its level sums.
+__global__ void k_gcounts(uint32_t nitems, const FItem* __restrict__ fitems,
+                          const u64* __restrict__ S, QAcc* __restrict__ acc) {
+  uint32_t it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitems) return;
+  const FItem f = fitems[it];
+  const u64* s = S + (u64)it * 8;
+  if (f.mask & 1) atomicAdd(&acc[f.q].cnt[0], s[0] - s[1]);
+  if (f.mask & 2) atomicAdd(&acc[f.q].cnt[1], s[2] - s[3]);
+  if (f.mask & 4) atomicAdd(&acc[f.q].cnt[2], s[4] - s[5]);
+}
+
+__global__ void k_fill_u64(u64* __restrict__ p, u64 n, u64 v) {
+  for (u64 k = (u64)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (u64)gridDim.x * blockDim.x)
+    p[k] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -878,6 +900,31 @@ k_witness2(const W2Item* __restrict__ items, const DevInst* __restrict__ insts,
   if ((threadIdx.x & 63) == 0 && best != kNoKey) atomicMin(&acc[it.q].qmin, best);
 }
 
+
+
+// ---------------------------------------------------------------------------
+// Small fills (used instead of memset nodes so that a captured graph
+// replays correctly).
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += gridDim.x * blockDim.x)
+    p[k] = v;
+}
+
+__global__ void k_init_acc(QAcc* __restrict__ acc, uint32_t n) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += gridDim.x * blockDim.x) {
+    QAcc a;
+    a.cnt[0] = a.cnt[1] = a.cnt[2] = 0;
+    a.pmin = kNoKey;
+    a.qmin = kNoKey;
+    a.err = 0;
+    a.qclass = 0;
+    a.waddr = 0;
+    acc[k] = a;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Results: status by precedence, counts, verdict and the decoded witness.
@@ -1060,44 +1107,49 @@ int launch_bucket(int cfg, hipStream_t st, uint32_t nb, uint32_t base,
   }
 }
 
-int launch_gen_linear(hipStream_t st, const Chunk* chunks, uint32_t n,
-                      const HItem* hitems, const void* insts,
-                      const DInsn* code, const int64_t* params,
-                      const int64_t* loopvals, const QDesc* qd, GRecPtrs g,
-                      uint32_t* count) {
-  GRec r{(u64*)g.addr, g.blin, g.tli, g.bw, g.w, g.slot, (long long*)g.part};
-  hipLaunchKernelGGL(k_gen_linear, dim3(n), dim3(256), 0, st, chunks, hitems,
-                     (const DevInst*)insts, code, params, loopvals, qd, r,
-                     count);
-  HGRD_CHECK(hipGetLastError());
-  return 0;
+static uint32_t grid_for(u64 n, uint32_t per) {
+  u64 g = (n + per - 1) / per;
+  if (g > 8192) g = 8192;
+  if (g == 0) g = 1;
+  return (uint32_t)g;
 }
 
-int launch_glevels(hipStream_t st, GRecPtrs g, uint32_t n, uint32_t self,
-                   uint32_t mask, uint32_t sigma, uint32_t* owner, void* cnt,
-                   uint32_t tbl, void* S, QAcc* acc) {
-  GRec r{(u64*)g.addr, g.blin, g.tli, g.bw, g.w, g.slot, (long long*)g.part};
-  uint32_t used = 0;
-  if (mask & 1) used |= 0x03;
-  if (mask & 2) used |= 0x0C;
-  if (mask & 4) used |= 0x30;
-  uint32_t gridn = (n + 255) / 256;
-  if (gridn > 4096) gridn = 4096;
-  if (gridn == 0) gridn = 1;
-  uint32_t gridt = (tbl + 255) / 256;
-  if (gridt > 4096) gridt = 4096;
+int launch_fallback(hipStream_t st, const Chunk* chunks, uint32_t nchunks,
+                    const FItem* fitems, uint32_t nitems, uint32_t used_levels,
+                    const void* insts, const DInsn* code, const int64_t* params,
+                    const int64_t* loopvals, GRecPtrs gp, u64 n,
+                    uint32_t* count, uint32_t* owner, void* cnt, u64 tbl,
+                    void* S, QAcc* acc) {
+  GRec g{(u64*)gp.addr, gp.blin, gp.tli, gp.bw, gp.w, gp.item, gp.slot,
+         (long long*)gp.part};
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, st,
+                     gp.item, (uint32_t)n, kEmpty);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, count, nitems, 0u);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((u64)nitems * 8, 256)), dim3(256),
+                     0, st, (u64*)S, (u64)nitems * 8, 0ull);
+  for (uint32_t off = 0; off < nchunks; off += 1u << 20) {
+    uint32_t m = nchunks - off < (1u << 20) ? nchunks - off : (1u << 20);
+    hipLaunchKernelGGL(k_gen_linear, dim3(m), dim3(256), 0, st, chunks + off,
+                       fitems, (const DevInst*)insts, code, params, loopvals, g,
+                       count);
+  }
+  HGRD_CHECK(hipGetLastError());
   for (int L = 0; L < 6; ++L) {
-    if (!((used >> L) & 1)) continue;
-    hipLaunchKernelGGL(k_gclear, dim3(gridt), dim3(256), 0, st, owner, (u64*)cnt, tbl);
-    hipLaunchKernelGGL(k_ginsert, dim3(gridn), dim3(256), 0, st, r, n, L, self,
-                       owner, (u64*)cnt, tbl - 1, (u64*)S + L);
-    if ((mask >> (L / 2)) & 1)
-      hipLaunchKernelGGL(k_gpartner, dim3(gridn), dim3(256), 0, st, r, n, L,
-                         self, (const u64*)cnt);
+    if (!((used_levels >> L) & 1)) continue;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(tbl, 256)), dim3(256), 0, st,
+                       owner, (uint32_t)tbl, kEmpty);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(tbl, 256)), dim3(256), 0, st,
+                       (u64*)cnt, tbl, 0ull);
+    hipLaunchKernelGGL(k_ginsert, dim3(grid_for(n, kGTile)), dim3(256), 0, st, g,
+                       n, L, fitems, owner, (u64*)cnt, tbl - 1, (u64*)S);
+    hipLaunchKernelGGL(k_gpartner, dim3(grid_for(n, 256)), dim3(256), 0, st, g,
+                       n, L, fitems, (const u64*)cnt);
     HGRD_CHECK(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_gfinish, dim3(gridn), dim3(256), 0, st, r, n, self,
-                     sigma, (const u64*)S, mask, acc);
+  hipLaunchKernelGGL(k_gfinish, dim3(grid_for(n, 256)), dim3(256), 0, st, g, n,
+                     fitems, acc);
+  hipLaunchKernelGGL(k_gcounts, dim3((nitems + 255) / 256), dim3(256), 0, st,
+                     nitems, fitems, (const u64*)S, acc);
   HGRD_CHECK(hipGetLastError());
   return 0;
 }
@@ -1116,6 +1168,24 @@ int launch_witness2(hipStream_t st, const void* items, uint32_t n,
 }
 
 size_t w2item_size() { return sizeof(W2Item); }
+
+int launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t n, uint32_t v) {
+  if (n == 0) return 0;
+  uint32_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, st, p, n, v);
+  HGRD_CHECK(hipGetLastError());
+  return 0;
+}
+
+int launch_init_acc(hipStream_t st, uint32_t n, QAcc* acc) {
+  if (n == 0) return 0;
+  uint32_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_init_acc, dim3(g), dim3(256), 0, st, acc, n);
+  HGRD_CHECK(hipGetLastError());
+  return 0;
+}
 
 int launch_finalize(hipStream_t st, uint32_t n, const QAcc* acc,
                     const QDesc* qd, const uint32_t* host_err,

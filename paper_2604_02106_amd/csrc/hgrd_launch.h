@@ -14,6 +14,7 @@ struct GRecPtrs {
   uint32_t* tli;
   uint32_t* bw;
   uint32_t* w;
+  uint32_t* item;
   uint32_t* slot;
   void* part;
 };
@@ -39,17 +40,17 @@ int launch_bucket(int cfg, hipStream_t st, uint32_t nb, uint32_t base,
                   const int64_t* loopvals, const QDesc* qd, QAcc* acc,
                   const unsigned char* keys, const uint32_t* pids,
                   const uint32_t* cursor, const uint32_t* ovf);
-int launch_gen_linear(hipStream_t st, const Chunk* chunks, uint32_t n,
-                      const HItem* hitems, const void* insts,
-                      const DInsn* code, const int64_t* params,
-                      const int64_t* loopvals, const QDesc* qd, GRecPtrs g,
-                      uint32_t* count);
-int launch_glevels(hipStream_t st, GRecPtrs g, uint32_t n, uint32_t self,
-                   uint32_t mask, uint32_t sigma, uint32_t* owner, void* cnt,
-                   uint32_t tbl, void* S, QAcc* acc);
+int launch_fallback(hipStream_t st, const Chunk* chunks, uint32_t nchunks,
+                    const FItem* fitems, uint32_t nitems, uint32_t used_levels,
+                    const void* insts, const DInsn* code, const int64_t* params,
+                    const int64_t* loopvals, GRecPtrs gp, unsigned long long n,
+                    uint32_t* count, uint32_t* owner, void* cnt,
+                    unsigned long long tbl, void* S, QAcc* acc);
 int launch_witness2(hipStream_t st, const void* items, uint32_t n,
                     const void* insts, const DInsn* code, const int64_t* params,
                     const int64_t* loopvals, const QDesc* qd, QAcc* acc);
+int launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t n, uint32_t v);
+int launch_init_acc(hipStream_t st, uint32_t n, QAcc* acc);
 int launch_finalize(hipStream_t st, uint32_t n, const QAcc* acc,
                     const QDesc* qd, const uint32_t* host_err,
                     const uint8_t* trivial, const unsigned long long* evals,
