@@ -83,7 +83,7 @@ def main():
     plan = hg.Plan(ctx, wl)
     prep_s = time.perf_counter() - t0
     log("prepared in %.3f s (end-to-end call %.3f s)" % (prep_s, e2e_s))
-    for i in range(args.warmup):
+    for i in range(max(1, args.warmup)):
         res = plan.execute()
         log("warmup %d done" % i)
     assert res == e2e

@@ -161,13 +161,23 @@ typedef struct {
 enum { RD_MODE_EXACT = 0, RD_MODE_VERDICT = 1 };
 enum { RD_ORDER_LEX = 0, RD_ORDER_MLP = 1 };
 
+/* The tile-scoring network of VERDICT mode: 32 tile features -> 64 -> 64 ->
+ * 1 logit, ReLU, fp32.  Row-major, output-major weight matrices. */
 typedef struct {
-  uint32_t mode;       /* RD_MODE_EXACT (default) */
-  uint32_t order;      /* RD_ORDER_LEX (default) */
+  float w1[64 * 32], b1[64];
+  float w2[64 * 64], b2[64];
+  float w3[64], b3;
+} rd_mlp;
+
+typedef struct {
+  uint32_t mode;       /* RD_MODE_EXACT (default) or RD_MODE_VERDICT */
+  uint32_t order;      /* VERDICT tile order: RD_ORDER_LEX or RD_ORDER_MLP */
   uint32_t batched;    /* reserved; 0 */
   uint32_t log_level;  /* 0 silent, 1 summary, 2 per-launch (stderr) */
   uint32_t lds_cap;    /* records per LDS join tile; 0 = autotuned */
-  uint32_t pad;
+  uint32_t tile_budget;/* VERDICT: tiles searched per (pair, tuple) before
+                          the exact path; 0 = 256 */
+  const rd_mlp* mlp;   /* weights for RD_ORDER_MLP (copied at prepare) */
   uint64_t max_device_bytes; /* HBM bucket bytes per partition wave;
                                 0 = library default (96 MiB, sized to stay
                                 in the last-level cache) */
@@ -182,7 +192,9 @@ typedef struct {
  * conflicting point pairs, with linear block, thread and iteration ids
  * (x fastest); witness_class is its class and w_addr its address.  The
  * witness fields are 0xFFFFFFFF (w_addr 0) when verdict is 0.
- * flags: bit 0 = trivially race-free (empty class mask, section 6.1).
+ * flags: bit 0 = trivially race-free (empty class mask, section 6.1);
+ * bit 1 = VERDICT mode stopped at a conflicting tile (count is a lower
+ * bound, witness valid but not necessarily the smallest).
  * evals: launch-box points of both accesses over all tuples (before
  * guards; a self-pair counts its box twice). */
 typedef struct {
@@ -190,6 +202,8 @@ typedef struct {
   int32_t status;
   uint8_t verdict, classes, witness_class, flags;
   uint32_t w_set, w_b1, w_t1, w_i1, w_b2, w_t2, w_i2;
+  uint32_t tiles;  /* VERDICT mode: rank + 1 of the tile that stopped the
+                      search (tiles examined in order); 0 otherwise */
   int64_t w_addr;
   uint64_t evals;
 } rd_pair_result;
@@ -243,9 +257,53 @@ typedef struct {
   double retry_ms;        /* re-partitioning of overflowed items */
   uint64_t retry_items;   /* items re-partitioned with more buckets */
   double waves_ms;        /* all partition waves (scatter + bucket join) */
+  double verdict_ms;      /* VERDICT mode: bounds, scores, order, tile search */
+  uint64_t verdict_units; /* (query, tuple) units searched tile by tile */
+  double split_ms;        /* items split by (address, block) */
+  uint64_t split_items;
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);
+
+/* ---- learned tile order (VERDICT mode) -----------------------------------
+ * A tile is block b1 of access a against block b2 of access b under one
+ * tuple.  VERDICT mode searches the tiles of each eligible (pair, tuple) in
+ * rounds of 1, 4, 16, ... tiles in LEX order (b1 * G + b2) or by descending
+ * network score (ties by index), up to tile_budget tiles, and stops a pair at
+ * its first conflicting tile: verdict 1, a valid (not necessarily smallest)
+ * witness from that tile, counts = the conflicts inside that tile (flags bit
+ * 1: count is a lower bound).  Pairs with no conflict in the searched tiles,
+ * and pairs not eligible (shared arrays, more than 2^20 tiles, tiles larger
+ * than one LDS join), get the EXACT result.  Statuses are the EXACT ones. */
+
+/* Features (32 floats per tile) and labels (1: the tile holds a conflict,
+ * 0: not, -1: the pair has an evaluation error) of every tile of every
+ * eligible (pair, tuple), computed by the exact checker; `ids` gets (pair,
+ * tuple, b1, b2) per row.  *n_rows is set to the number of rows; returns
+ * RD_ECAPACITY (and writes nothing) when it exceeds max_rows. */
+int rd_tile_data(rd_context* ctx, const rd_kernel_model* models,
+                 uint32_t n_models, const rd_access_pair* pairs,
+                 uint32_t n_pairs, const rd_launch_domain* launch,
+                 const rd_param_sets* params, const rd_options* opt,
+                 uint64_t max_rows, float* feats, float* labels, uint32_t* ids,
+                 uint64_t* n_rows);
+
+/* Network logits of n feature rows (n x 32, row-major). */
+int rd_mlp_forward(rd_context* ctx, const rd_mlp* w, const float* x,
+                   uint64_t n, float* logits, void* stream);
+
+/* Mean binary cross-entropy on logits over n rows with labels y (0/1), and
+ * its gradient with respect to every weight (same layout as rd_mlp). */
+int rd_mlp_grad(rd_context* ctx, const rd_mlp* w, const float* x,
+                const float* y, uint64_t n, rd_mlp* grad, float* loss,
+                void* stream);
+
+/* Trains w in place with Adam (learning rate lr, betas 0.9/0.999) on
+ * minibatches of `batch` rows, `epochs` passes over a permutation drawn
+ * from `seed`; epoch_loss[e] (optional) gets each epoch's mean loss. */
+int rd_mlp_train(rd_context* ctx, rd_mlp* w, const float* x, const float* y,
+                 uint64_t n, uint32_t epochs, uint32_t batch, float lr,
+                 uint64_t seed, float* epoch_loss, void* stream);
 
 const char* rd_strerror(int status);
 

@@ -78,10 +78,15 @@ class rd_access_pair(C.Structure):
                 ("class_mask", C.c_uint32)]
 
 
+N_MLP = 6337  # 32*64 + 64 + 64*64 + 64 + 64 + 1
+rd_mlp = C.c_float * N_MLP  # w1, b1, w2, b2, w3, b3 (include/hgrd.h)
+
+
 class rd_options(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("order", C.c_uint32),
                 ("batched", C.c_uint32), ("log_level", C.c_uint32),
-                ("lds_cap", C.c_uint32), ("pad", C.c_uint32),
+                ("lds_cap", C.c_uint32), ("tile_budget", C.c_uint32),
+                ("mlp", C.c_void_p),
                 ("max_device_bytes", C.c_uint64), ("stream", C.c_void_p)]
 
 
@@ -93,6 +98,7 @@ class rd_pair_result(C.Structure):
                 ("w_b1", C.c_uint32), ("w_t1", C.c_uint32),
                 ("w_i1", C.c_uint32), ("w_b2", C.c_uint32),
                 ("w_t2", C.c_uint32), ("w_i2", C.c_uint32),
+                ("tiles", C.c_uint32),
                 ("w_addr", C.c_int64), ("evals", C.c_uint64)]
 
 
@@ -106,14 +112,17 @@ class rd_stats(C.Structure):
                 ("join_kernel_ms", C.c_double), ("small_ms", C.c_double),
                 ("bucket_ms", C.c_double), ("fallback_ms", C.c_double),
                 ("retry_ms", C.c_double), ("retry_items", C.c_uint64),
-                ("waves_ms", C.c_double)]
+                ("waves_ms", C.c_double), ("verdict_ms", C.c_double),
+                ("verdict_units", C.c_uint64), ("split_ms", C.c_double),
+                ("split_items", C.c_uint64)]
 
 
 assert C.sizeof(rd_pair_result) == 88
 
 EXPORTS = ("rd_context_create", "rd_context_destroy", "rd_check_pairs",
            "rd_prepare", "rd_execute", "rd_plan_destroy", "rd_get_stats",
-           "rd_strerror", "rd_selftest")
+           "rd_strerror", "rd_selftest", "rd_tile_data", "rd_mlp_forward",
+           "rd_mlp_grad", "rd_mlp_train")
 
 _lib = None
 
@@ -146,6 +155,22 @@ def lib():
         L.rd_execute.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(rd_pair_result)]
         L.rd_plan_destroy.restype = None
         L.rd_plan_destroy.argtypes = [C.c_void_p]
+        L.rd_tile_data.restype = C.c_int
+        L.rd_tile_data.argtypes = [
+            C.c_void_p, C.POINTER(rd_kernel_model), C.c_uint32,
+            C.POINTER(rd_access_pair), C.c_uint32, C.POINTER(rd_launch_domain),
+            C.POINTER(rd_param_sets), C.POINTER(rd_options), C.c_uint64,
+            C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)]
+        L.rd_mlp_forward.restype = C.c_int
+        L.rd_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_uint64, C.c_void_p, C.c_void_p]
+        L.rd_mlp_grad.restype = C.c_int
+        L.rd_mlp_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rd_mlp_train.restype = C.c_int
+        L.rd_mlp_train.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_uint64, C.c_uint32, C.c_uint32, C.c_float,
+                                   C.c_uint64, C.c_void_p, C.c_void_p]
         L.rd_selftest.restype = C.c_int
         L.rd_selftest.argtypes = []
         L.rd_get_stats.restype = C.c_int
@@ -257,9 +282,23 @@ def _stream_handle(stream):
     return None
 
 
-def _options(mode, order, lds_cap, max_device_bytes, log_level, stream):
-    return rd_options(mode, order, 0, log_level, lds_cap, 0, max_device_bytes,
-                      _stream_handle(stream))
+def _as_f32(a, n=None):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if n is not None:
+        assert a.size == n, (a.size, n)
+    return a
+
+
+def _options(mode, order, lds_cap, max_device_bytes, log_level, stream,
+             mlp=None, tile_budget=0):
+    o = rd_options(mode, order, 0, log_level, lds_cap, tile_budget, None,
+                   max_device_bytes, _stream_handle(stream))
+    keep = None
+    if mlp is not None:
+        keep = _as_f32(mlp, N_MLP)
+        o.mlp = keep.ctypes.data
+    return o, keep
 
 
 def _pairs(workload):
@@ -272,12 +311,14 @@ class Plan:
     """rd_prepare'd batch: descriptors resident in device memory."""
 
     def __init__(self, ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
-                 lds_cap=0, max_device_bytes=0, log_level=0, stream=None):
+                 lds_cap=0, max_device_bytes=0, log_level=0, stream=None,
+                 mlp=None, tile_budget=0):
         self.ctx = ctx
         self.n = len(workload.pairs)
         pk = Packed(workload)
         pairs = _pairs(workload)
-        opt = _options(mode, order, lds_cap, max_device_bytes, log_level, stream)
+        opt, keep = _options(mode, order, lds_cap, max_device_bytes, log_level,
+                             stream, mlp, tile_budget)
         self.h = C.c_void_p()
         st = lib().rd_prepare(ctx.h, pk.models, pk.n_models, pairs, self.n,
                               pk.launch, pk.params, C.byref(opt), C.byref(self.h))
@@ -293,6 +334,11 @@ class Plan:
             return self.out
         return [result_dict(self.out[k]) for k in range(self.n)]
 
+    def tiles(self):
+        """Per pair: tiles examined before VERDICT mode stopped (0: not
+        stopped by the tile search)."""
+        return [self.out[k].tiles for k in range(self.n)]
+
     def close(self):
         if self.h:
             lib().rd_plan_destroy(self.h)
@@ -307,7 +353,7 @@ class Plan:
 
 def rd_check_pairs(ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
                    lds_cap=0, max_device_bytes=0, log_level=0, stream=None,
-                   packed=None):
+                   packed=None, mlp=None, tile_budget=0):
     """Decides every pair of ``workload`` on the GPU.
 
     Returns a list of result dicts (same fields as rd_pair_result).
@@ -316,7 +362,8 @@ def rd_check_pairs(ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
     n = len(workload.pairs)
     pairs = _pairs(workload)
     out = (rd_pair_result * max(1, n))()
-    opt = _options(mode, order, lds_cap, max_device_bytes, log_level, stream)
+    opt, keep = _options(mode, order, lds_cap, max_device_bytes, log_level,
+                         stream, mlp, tile_budget)
     st = lib().rd_check_pairs(ctx.h, pk.models, pk.n_models, pairs, n,
                               pk.launch, pk.params, C.byref(opt), out)
     if st != RD_OK:
@@ -336,6 +383,7 @@ def result_dict(r):
             "evals": r.evals}
 
 
+
 _default_ctx = None
 
 
@@ -352,3 +400,73 @@ def default_context():
     if _default_ctx is None:
         _default_ctx = Context(0)
     return _default_ctx
+
+
+def rd_tile_data(ctx, workload, max_rows=None, stream=None):
+    """Features (n x 32 float32), labels (n, 1/0/-1) and ids (n x 4: pair,
+    tuple, b1, b2) of every tile of every eligible (pair, tuple)."""
+    import numpy as np
+    pk = Packed(workload)
+    pairs = _pairs(workload)
+    opt, _ = _options(MODE_VERDICT, ORDER_LEX, 0, 0, 0, stream)
+    n = C.c_uint64(0)
+    st = lib().rd_tile_data(ctx.h, pk.models, pk.n_models, pairs,
+                            len(workload.pairs), pk.launch, pk.params,
+                            C.byref(opt), 0, None, None, None, C.byref(n))
+    if st not in (RD_OK, RD_ECAPACITY):
+        raise RuntimeError("rd_tile_data failed: %s" % rd_strerror(st))
+    rows = n.value
+    if max_rows is not None and rows > max_rows:
+        raise RuntimeError("%d tile rows exceed %d" % (rows, max_rows))
+    X = np.zeros((rows, 32), dtype=np.float32)
+    Y = np.zeros(rows, dtype=np.float32)
+    ids = np.zeros((rows, 4), dtype=np.uint32)
+    st = lib().rd_tile_data(ctx.h, pk.models, pk.n_models, pairs,
+                            len(workload.pairs), pk.launch, pk.params,
+                            C.byref(opt), rows, X.ctypes.data, Y.ctypes.data,
+                            ids.ctypes.data, C.byref(n))
+    if st != RD_OK:
+        raise RuntimeError("rd_tile_data failed: %s" % rd_strerror(st))
+    return X, Y, ids
+
+
+def rd_mlp_forward(ctx, w, X, stream=None):
+    import numpy as np
+    w = _as_f32(w, N_MLP)
+    X = _as_f32(X)
+    n = X.shape[0]
+    out = np.zeros(n, dtype=np.float32)
+    st = lib().rd_mlp_forward(ctx.h, w.ctypes.data, X.ctypes.data, n,
+                              out.ctypes.data, _stream_handle(stream))
+    if st != RD_OK:
+        raise RuntimeError("rd_mlp_forward failed: %s" % rd_strerror(st))
+    return out
+
+
+def rd_mlp_grad(ctx, w, X, Y, stream=None):
+    import numpy as np
+    w = _as_f32(w, N_MLP)
+    X, Y = _as_f32(X), _as_f32(Y)
+    g = np.zeros(N_MLP, dtype=np.float32)
+    loss = np.zeros(1, dtype=np.float32)
+    st = lib().rd_mlp_grad(ctx.h, w.ctypes.data, X.ctypes.data, Y.ctypes.data,
+                           X.shape[0], g.ctypes.data, loss.ctypes.data,
+                           _stream_handle(stream))
+    if st != RD_OK:
+        raise RuntimeError("rd_mlp_grad failed: %s" % rd_strerror(st))
+    return g, float(loss[0])
+
+
+def rd_mlp_train(ctx, w, X, Y, epochs=10, batch=4096, lr=1e-3, seed=0,
+                 stream=None):
+    """Returns (trained weights, per-epoch mean loss)."""
+    import numpy as np
+    w = _as_f32(w, N_MLP).copy()
+    X, Y = _as_f32(X), _as_f32(Y)
+    losses = np.zeros(epochs, dtype=np.float32)
+    st = lib().rd_mlp_train(ctx.h, w.ctypes.data, X.ctypes.data, Y.ctypes.data,
+                            X.shape[0], epochs, batch, lr, seed,
+                            losses.ctypes.data, _stream_handle(stream))
+    if st != RD_OK:
+        raise RuntimeError("rd_mlp_train failed: %s" % rd_strerror(st))
+    return w, losses

@@ -1,0 +1,453 @@
+// Device building blocks shared by the gfx950 kernel files: expression
+// interpreter, point decoding and evaluation, reductions, and the LDS
+// prefix-group join.  See hgrd_kernels.hip for the method.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+#include "hgrd_internal.h"
+
+namespace hgrd {
+
+using u64 = unsigned long long;
+
+// ---------------------------------------------------------------------------
+// Division by a uniform 32-bit divisor for numerators below 2^31, by a
+// multiply-high and a shift (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", PLDI 1994, section 4).
+struct FastDiv {
+  uint32_t d, m, s, pad;
+};
+
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t l = 0;
+  while (l < 32 && (1ull << l) < d) ++l;
+  f.s = l;
+  // m = floor(2^32 * (2^l - d) / d) + 1
+  f.m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+  f.pad = 0;
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  uint32_t t = __umulhi(f.m, n);
+  return (t + n) >> f.s;
+}
+
+// ---------------------------------------------------------------------------
+// Checked int64 arithmetic: on error set a bit and yield 0 (C semantics
+// otherwise: truncating '/', '%' with the dividend's sign, arithmetic '>>').
+__device__ __forceinline__ int64_t alu(uint8_t op, int64_t a, int64_t b,
+                                       uint32_t& err) {
+  int64_t r;
+  switch (op) {
+    case D_MOV: return a;
+    case D_ADD:
+      if (__builtin_add_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
+      return r;
+    case D_SUB:
+      if (__builtin_sub_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
+      return r;
+    case D_MUL:
+      if (__builtin_mul_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
+      return r;
+    case D_DIV:
+      if (b == 0) { err |= ERR_DIVZERO; return 0; }
+      if (a == INT64_MIN && b == -1) { err |= ERR_RANGE; return 0; }
+      return a / b;
+    case D_MOD:
+      if (b == 0) { err |= ERR_DIVZERO; return 0; }
+      if (a == INT64_MIN && b == -1) { err |= ERR_RANGE; return 0; }
+      return a % b;
+    case D_SHL: {
+      if (b < 0 || b > 63) { err |= ERR_RANGE; return 0; }
+      int64_t s = (int64_t)((uint64_t)a << b);
+      if ((s >> b) != a) { err |= ERR_RANGE; return 0; }
+      return s;
+    }
+    case D_SHR:
+      if (b < 0 || b > 63) { err |= ERR_RANGE; return 0; }
+      return a >> b;
+    case D_AND: return a & b;
+    case D_OR: return a | b;
+    case D_XOR: return a ^ b;
+    case D_MIN: return a < b ? a : b;
+    case D_MAX: return a > b ? a : b;
+    case D_LT: return a < b;
+    case D_LE: return a <= b;
+    case D_EQ: return a == b;
+    case D_NE: return a != b;
+    case D_GE: return a >= b;
+    case D_GT: return a > b;
+    case D_LAND: return (a != 0) & (b != 0);
+    case D_LOR: return (a != 0) | (b != 0);
+    case D_NEG:
+      if (a == INT64_MIN) { err |= ERR_RANGE; return 0; }
+      return -a;
+    case D_LNOT: return a == 0;
+  }
+  return 0;
+}
+
+// Point coordinates live in named fields (read through a uniform switch);
+// only the stack slots form an indexed array, which keeps it in VGPRs.
+struct Regs {
+  int64_t c0, c1, c2, c3, c4, c5, c6, c7, c8, c9;
+};
+typedef int64_t Stack[kMaxStack];
+
+__device__ __forceinline__ int64_t coord(const Regs& R, uint32_t i) {
+  switch (i) {
+    case 0: return R.c0;
+    case 1: return R.c1;
+    case 2: return R.c2;
+    case 3: return R.c3;
+    case 4: return R.c4;
+    case 5: return R.c5;
+    case 6: return R.c6;
+    case 7: return R.c7;
+    case 8: return R.c8;
+    default: return R.c9;
+  }
+}
+
+struct DevInst {
+  AccInst a;
+  FastDiv f_nthr, f_niota, f_gx, f_gxy, f_bx, f_bxy;
+  FastDiv f_loop[4];
+};
+
+// Runs one compiled expression.  `code`, `p`, `params` and `dims` are
+// uniform across the wavefront.
+__device__ __forceinline__ int64_t run_prog(const DInsn* __restrict__ code,
+                                            const Prog p, const Regs& R,
+                                            const int64_t* __restrict__ params,
+                                            int64_t dflt, uint32_t& err) {
+  if (p.absent) return dflt;
+  Stack st;
+  for (uint32_t k = 0; k < p.n; ++k) {
+    const DInsn in = code[p.off + k];
+    int64_t a, b;
+    // launch extents follow the parameters of the tuple in the pool
+    if (in.ma == M_REG) a = st[in.a];
+    else if (in.ma == M_IMM) a = in.imm;
+    else if (in.ma == M_PARAM) a = params[in.a];
+    else a = coord(R, in.a);
+    if (in.mb == M_REG) b = st[in.b];
+    else if (in.mb == M_IMM) b = in.imm;
+    else if (in.mb == M_PARAM) b = params[in.b];
+    else b = coord(R, in.b);
+    st[in.dst] = alu(in.op, a, b, err);
+  }
+  return st[p.res];
+}
+
+// Point coordinates of point index `pidx` = (blin * niota + ilin) * nthr + tlin.
+struct PointIds {
+  uint32_t blin, tlin, ilin;
+};
+
+__device__ __forceinline__ PointIds decode(const DevInst& I, uint32_t pidx) {
+  PointIds o;
+  uint32_t rest = fdiv(pidx, I.f_nthr);
+  o.tlin = pidx - rest * I.a.nthr;
+  o.blin = fdiv(rest, I.f_niota);
+  o.ilin = rest - o.blin * I.a.niota;
+  return o;
+}
+
+__device__ __forceinline__ void set_coords(const DevInst& I, const PointIds& p,
+                                           const int64_t* __restrict__ loopvals,
+                                           Regs& R) {
+  uint32_t t1 = fdiv(p.tlin, I.f_bx);
+  R.c0 = p.tlin - t1 * (uint32_t)I.a.dims[3];
+  uint32_t t2 = fdiv(p.tlin, I.f_bxy);
+  R.c1 = t1 - t2 * (uint32_t)I.a.dims[4];
+  R.c2 = t2;
+  uint32_t b1 = fdiv(p.blin, I.f_gx);
+  R.c3 = p.blin - b1 * (uint32_t)I.a.dims[0];
+  uint32_t b2 = fdiv(p.blin, I.f_gxy);
+  R.c4 = b1 - b2 * (uint32_t)I.a.dims[1];
+  R.c5 = b2;
+  R.c6 = R.c7 = R.c8 = R.c9 = 0;
+  uint32_t rem = p.ilin;
+  const uint32_t nl = I.a.n_loops;
+  if (nl > 3) {
+    uint32_t q = fdiv(rem, I.f_loop[3]);
+    R.c9 = loopvals[I.a.loop_off[3] + (rem - q * I.a.loop_n[3])];
+    rem = q;
+  }
+  if (nl > 2) {
+    uint32_t q = fdiv(rem, I.f_loop[2]);
+    R.c8 = loopvals[I.a.loop_off[2] + (rem - q * I.a.loop_n[2])];
+    rem = q;
+  }
+  if (nl > 1) {
+    uint32_t q = fdiv(rem, I.f_loop[1]);
+    R.c7 = loopvals[I.a.loop_off[1] + (rem - q * I.a.loop_n[1])];
+    rem = q;
+  }
+  if (nl > 0) {
+    uint32_t q = fdiv(rem, I.f_loop[0]);
+    R.c6 = loopvals[I.a.loop_off[0] + (rem - q * I.a.loop_n[0])];
+  }
+}
+
+struct Point {
+  int64_t addr;
+  uint32_t bint, wint;
+};
+
+// Evaluates guard, then (if it holds) address and interval ids, recording
+// errors exactly as the C-level semantics say.  Returns the guard.
+__device__ __forceinline__ bool eval_point(const DevInst& I,
+                                           const DInsn* __restrict__ code,
+                                           const int64_t* __restrict__ params,
+                                           Regs& R, Point& pt, uint32_t& err) {
+  const int64_t* pr = params + I.a.params_off;
+  int64_t g = run_prog(code, I.a.guard, R, pr, 1, err);
+  if (g == 0) return false;
+  uint32_t e = 0;
+  pt.addr = run_prog(code, I.a.addr, R, pr, 0, e);
+  int64_t bi = run_prog(code, I.a.bint, R, pr, 0, e);
+  int64_t wi = run_prog(code, I.a.wint, R, pr, 0, e);
+  if (I.a.is32 && (pt.addr < INT32_MIN || pt.addr > INT32_MAX)) e |= ERR_RANGE;
+  if (bi < 0 || bi > 65535 || wi < 0 || wi > 65535) e |= ERR_UNSUP;
+  err |= e;
+  pt.bint = (uint32_t)bi & 0xFFFF;
+  pt.wint = (uint32_t)wi & 0xFFFF;
+  return e == 0;
+}
+
+__device__ __forceinline__ void load_inst(DevInst& D,
+                                          const DevInst* __restrict__ insts,
+                                          uint32_t k) {
+  k = __builtin_amdgcn_readfirstlane(k);
+  D = insts[k];
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.
+
+__device__ __forceinline__ u64 wave_sum(u64 v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ u64 wave_min(u64 v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    u64 w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// LDS join of up to CAP records (both sides of one query under one tuple).
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kInactive = 1u << 14;  // in tli
+constexpr uint32_t kSide = 1u << 15;      // in tli
+
+template <int CAP, int TBL>
+struct JoinLds {
+  u64 addr[CAP];
+  uint32_t blin[CAP];
+  uint32_t tli[CAP];  // ilin << 16 | side << 15 | inactive << 14 | tlin
+  uint32_t bw[CAP];   // bint << 16 | wint
+  uint16_t w[CAP];    // warp of the analysed program
+  uint16_t slot[CAP];
+  int32_t part[CAP];
+  uint32_t owner[TBL];
+  uint32_t cnt[TBL];
+  u64 red[8];
+  uint32_t n;
+  uint32_t err;
+};
+
+__device__ __forceinline__ uint32_t level_hash(int L, u64 addr, uint32_t blin,
+                                               uint32_t bw, uint32_t w,
+                                               uint32_t t) {
+  u64 h = addr * 0x9E3779B97F4A7C15ull;
+  if (L >= 1) h ^= (u64)(blin + 1) * 0xC2B2AE3D27D4EB4Full;
+  if (L >= 2) h ^= (u64)((bw >> 16) + 1) * 0x165667B19E3779F9ull;
+  if (L >= 3) h ^= (u64)(w + 1) * 0x27D4EB2F165667C5ull;
+  if (L >= 4) h ^= (u64)((bw & 0xFFFF) + 1) * 0x94D049BB133111EBull;
+  if (L >= 5) h ^= (u64)(t + 1) * 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 31;
+  h *= 0x9E3779B97F4A7C15ull;
+  h ^= h >> 29;
+  return (uint32_t)(h >> 32);
+}
+
+template <int CAP, int TBL>
+__device__ __forceinline__ bool level_eq(const JoinLds<CAP, TBL>& S, int L,
+                                         uint32_t x, uint32_t y) {
+  if (S.addr[x] != S.addr[y]) return false;
+  if (L >= 1 && S.blin[x] != S.blin[y]) return false;
+  if (L >= 2 && (S.bw[x] >> 16) != (S.bw[y] >> 16)) return false;
+  if (L >= 3 && S.w[x] != S.w[y]) return false;
+  if (L >= 4 && (S.bw[x] & 0xFFFF) != (S.bw[y] & 0xFFFF)) return false;
+  if (L >= 5 && (S.tli[x] & 0x3FF) != (S.tli[y] & 0x3FF)) return false;
+  return true;
+}
+
+// Joins the S.n records in LDS.  Leaves the class counts in S.red[0..2] and
+// the smallest p key with a partner in S.red[3] (kNoKey: none); the caller
+// sets S.red to (0, 0, 0, kNoKey) and synchronises before the call.  All
+// threads of the block must call it; it ends with a barrier.
+//
+// l0ext: the records hold whole (address, block) groups but not whole
+// address groups; level 0 (S_0, the address-only sums) is counted elsewhere
+// and the caller has put each side-a record's level-0 partner count in
+// S.part.  Then S.red[0] gets -S_1 (inter = S_0 - S_1 modulo 2^64) and no
+// record is filtered out.
+template <int CAP, int TBL>
+__device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
+                         bool l0ext = false) {
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t n = S.n;
+  const uint32_t mask = qd.mask;
+  const bool self = qd.self != 0;
+  uint32_t used = 0;
+  if (mask & 1) used |= l0ext ? 0x02 : 0x03;
+  if (mask & 2) used |= 0x0C;
+  if (mask & 4) used |= 0x30;
+  if (used == 0 || n == 0) return;
+  const int f = l0ext ? 99 : __ffs(used) - 1;  // filter level (none: 99)
+  u64 Sl[6] = {0, 0, 0, 0, 0, 0};
+  if (!l0ext)
+    for (uint32_t r = tid; r < n; r += nt) S.part[r] = 0;
+  bool any = true;
+  for (int L = 0; L < 6; ++L) {
+    if (!((used >> L) & 1)) continue;
+    for (uint32_t k = tid; k < TBL; k += nt) {
+      S.owner[k] = kEmpty;
+      S.cnt[k] = 0;
+    }
+    __syncthreads();
+    u64 s = 0;
+    for (uint32_t r = tid; r < n; r += nt) {
+      uint32_t tl = S.tli[r];
+      if (tl & kInactive) continue;
+      uint32_t h = level_hash(L, S.addr[r], S.blin[r], S.bw[r], S.w[r],
+                              tl & 0x3FF) & (TBL - 1);
+      for (;;) {
+        uint32_t o = atomicCAS(&S.owner[h], kEmpty, r);
+        if (o == kEmpty || level_eq(S, L, o, r)) break;
+        h = (h + 1) & (TBL - 1);
+      }
+      uint32_t side = (tl & kSide) ? 1u : 0u;
+      uint32_t old = atomicAdd(&S.cnt[h], (self || !side) ? 1u : 0x10000u);
+      if (self) s += 2ull * (old & 0xFFFF) + 1;
+      else s += side ? (old & 0xFFFF) : (old >> 16);
+      S.slot[r] = (uint16_t)h;
+    }
+    __syncthreads();
+    const int sign = (L & 1) ? -1 : 1;
+    const uint32_t cls = L < 2 ? 1u : (L < 4 ? 2u : 4u);
+    bool any_local = false;
+    for (uint32_t r = tid; r < n; r += nt) {
+      uint32_t tl = S.tli[r];
+      if (tl & kInactive) continue;
+      uint32_t c = S.cnt[S.slot[r]];
+      if (L == f) {
+        bool cand = self ? ((c & 0xFFFF) >= 2) : ((c & 0xFFFF) && (c >> 16));
+        if (!cand) {
+          S.tli[r] = tl | kInactive;
+          if (self) s -= 1;  // a lone record pairs only with itself
+          continue;
+        }
+        any_local = true;
+      }
+      if (!self && (tl & kSide)) continue;
+      if (cls & mask) {
+        int32_t nj = (int32_t)(self ? (c & 0xFFFF) : (c >> 16));
+        S.part[r] += sign * nj;
+      }
+    }
+    Sl[L] = s;
+    if (L == f) {
+      any = __syncthreads_or(any_local);
+      if (!any) break;
+    } else {
+      __syncthreads();
+    }
+  }
+  if (!any) return;
+  // class counts: reduce S_L over the block
+  u64 c0 = (mask & 1) ? Sl[0] - Sl[1] : 0;  // l0ext: Sl[0] = 0, so -S_1
+  u64 c1 = (mask & 2) ? Sl[2] - Sl[3] : 0;
+  u64 c2 = (mask & 4) ? Sl[4] - Sl[5] : 0;
+  u64 best = kNoKey;
+  for (uint32_t r = tid; r < n; r += nt) {
+    uint32_t tl = S.tli[r];
+    if ((tl & kInactive) || (!self && (tl & kSide))) continue;
+    if (S.part[r] > 0) {
+      u64 k = pkey(sigma, S.blin[r], tl & 0x3FF, tl >> 16);
+      best = k < best ? k : best;
+    }
+  }
+  __syncthreads();
+  c0 = wave_sum(c0);
+  c1 = wave_sum(c1);
+  c2 = wave_sum(c2);
+  best = wave_min(best);
+  if ((tid & 63) == 0) {
+    if (c0) atomicAdd(&S.red[0], c0);
+    if (c1) atomicAdd(&S.red[1], c1);
+    if (c2) atomicAdd(&S.red[2], c2);
+    if (best != kNoKey) atomicMin(&S.red[3], best);
+  }
+  __syncthreads();
+}
+
+// Adds a join's results (S.red) to a query's accumulators (thread 0).
+template <int CAP, int TBL>
+__device__ __forceinline__ void commit_join(const JoinLds<CAP, TBL>& S,
+                                            QAcc* __restrict__ acc) {
+  if (threadIdx.x == 0) {
+    if (S.red[0]) atomicAdd(&acc->cnt[0], S.red[0]);
+    if (S.red[1]) atomicAdd(&acc->cnt[1], S.red[1]);
+    if (S.red[2]) atomicAdd(&acc->cnt[2], S.red[2]);
+    if (S.red[3] != kNoKey) atomicMin(&acc->pmin, S.red[3]);
+  }
+}
+
+template <int CAP, int TBL>
+__device__ __forceinline__ void init_red(JoinLds<CAP, TBL>& S) {
+  if (threadIdx.x < 8) S.red[threadIdx.x] = (threadIdx.x == 3 || threadIdx.x == 4) ? kNoKey : 0;
+}
+
+// Appends a record to the LDS arrays (wavefront-aggregated slot claim).
+template <int CAP, int TBL>
+__device__ __forceinline__ void lds_append(JoinLds<CAP, TBL>& S, bool valid,
+                                           const Point& pt, const PointIds& id,
+                                           uint32_t side, uint32_t warp_w) {
+  u64 bal = __ballot(valid);
+  if (bal == 0) return;
+  uint32_t lane = threadIdx.x & 63;
+  uint32_t leader = __ffsll((long long)bal) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(&S.n, (uint32_t)__popcll(bal));
+  base = __shfl(base, leader, 64);
+  if (valid) {
+    uint32_t r = base + __popcll(bal & ((1ull << lane) - 1));
+    if (r >= CAP) {  // the planner never lets this happen; never write past
+      atomicOr(&S.err, ERR_INTERNAL);
+      return;
+    }
+    S.addr[r] = (u64)pt.addr;
+    S.blin[r] = id.blin;
+    S.tli[r] = (id.ilin << 16) | (side << 15) | id.tlin;
+    S.bw[r] = (pt.bint << 16) | pt.wint;
+    S.w[r] = (uint16_t)warp_w;
+  }
+}
+
+}  // namespace hgrd

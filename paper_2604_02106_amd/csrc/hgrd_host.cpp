@@ -629,6 +629,15 @@ struct rd_plan_impl {
   std::vector<uint8_t> herr_scan;  // error-scan-only items
   uint64_t max_key_bytes = 0, max_pid_elems = 0, max_buckets = 0, max_items = 0;
   uint64_t wave_budget = 0;
+  // VERDICT mode
+  bool verdict = false, use_mlp = false;
+  uint32_t K = 0;                  // tiles searched per search unit
+  uint32_t n_vq = 0, n_bitems = 0, n_tchunks = 0, max_tiles = 0;
+  uint64_t n_tiles = 0;
+  std::vector<std::pair<uint32_t, uint32_t>> rounds;  // [item lo, item hi)
+  uint32_t n_titems = 0;
+  uint32_t n_vqueries_pairs = 0;
+  std::vector<VQuery> vqs;
   std::map<std::string, DevBuf> dev;
   void* buf(const char* name, size_t bytes, int* err) {
     DevBuf& b = dev[name];
@@ -824,6 +833,88 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   }
   plan->n_sitems = (uint32_t)sitems.size();
 
+  // ---- VERDICT mode: search units, their blocks, tiles and rounds ----------
+  std::vector<VQuery> vqs;
+  std::vector<BItem> bitems;
+  std::vector<TChunk> tchunks;
+  std::vector<TItem> titems;
+  if (o.mode == RD_MODE_VERDICT) {
+    plan->verdict = true;
+    plan->use_mlp = o.order == RD_ORDER_MLP;
+    if (plan->use_mlp && !o.mlp) return RD_EINVAL;
+    plan->K = o.tile_budget ? o.tile_budget : 256;
+    for (uint32_t k = 0; k < n_pairs; ++k) {
+      QPlan& q = Q[k];
+      if (!q.work || q.host_err || q.trivial || q.qd.shared || q.inst.empty()) continue;
+      bool ok = true;
+      for (auto& pr : q.inst) {
+        if (pr.first < 0 || pr.second < 0) { ok = false; break; }
+        const AccInst& A = P.dev_insts[pr.first];
+        const AccInst& B = P.dev_insts[pr.second];
+        uint64_t tiles = (uint64_t)A.nblk * A.nblk;
+        uint64_t per = q.qd.self ? 2ull * A.tpb : (uint64_t)A.tpb + B.tpb;
+        if (tiles > (1u << 20) || per > cap || A.nblk != B.nblk) { ok = false; break; }
+      }
+      if (!ok) continue;
+      const rd_access_pair& pr = pairs[k];
+      const rd_kernel_model& M = models[pr.model];
+      uint32_t kinds = M.acc[pr.a].kind * 3 + M.acc[pr.b].kind;
+      plan->n_vqueries_pairs++;
+      for (uint32_t s = 0; s < q.inst.size(); ++s) {
+        const AccInst& A = P.dev_insts[q.inst[s].first];
+        const AccInst& B = P.dev_insts[q.inst[s].second];
+        VQuery v;
+        memset(&v, 0, sizeof v);
+        v.q = k;
+        v.sigma = s;
+        v.inst_i = (uint32_t)q.inst[s].first;
+        v.inst_j = (uint32_t)q.inst[s].second;
+        v.G = A.nblk;
+        v.bb_i = (uint32_t)bitems.size();
+        for (uint32_t b = 0; b < A.nblk; ++b) bitems.push_back({v.inst_i, b, k, 0});
+        if (q.qd.self) {
+          v.bb_j = v.bb_i;
+        } else {
+          v.bb_j = (uint32_t)bitems.size();
+          for (uint32_t b = 0; b < B.nblk; ++b) bitems.push_back({v.inst_j, b, k, 0});
+        }
+        v.self = q.qd.self;
+        v.tile0 = (uint32_t)plan->n_tiles;
+        v.tpb_i = A.tpb;
+        v.tpb_j = B.tpb;
+        v.nthr = A.nthr;
+        v.kinds = kinds;
+        v.shared = 0;
+        v.is64 = A.is32 ? 0 : 1;
+        v.nsets = (uint32_t)q.inst.size();
+        uint32_t nt = v.G * v.G;
+        for (uint32_t t0 = 0; t0 < nt; t0 += 4096)
+          tchunks.push_back({(uint32_t)vqs.size(), t0, std::min(nt, t0 + 4096), 0});
+        plan->n_tiles += nt;
+        plan->max_tiles = std::max(plan->max_tiles, nt);
+        vqs.push_back(v);
+      }
+    }
+    // rounds of geometrically growing rank ranges: [0,1), [1,4), [4,16) ...
+    uint32_t lo = 0, width = 1;
+    while (lo < plan->K) {
+      uint32_t hi = std::min(plan->K, lo + width);
+      uint32_t i0 = (uint32_t)titems.size();
+      for (uint32_t v = 0; v < vqs.size(); ++v) {
+        uint32_t nt = vqs[v].G * vqs[v].G;
+        for (uint32_t r = lo; r < std::min(hi, nt); ++r) titems.push_back({v, r});
+      }
+      if (titems.size() > i0) plan->rounds.push_back({i0, (uint32_t)titems.size()});
+      lo = hi;
+      width *= 4;
+    }
+    plan->n_vq = (uint32_t)vqs.size();
+    plan->vqs = vqs;
+    plan->n_bitems = (uint32_t)bitems.size();
+    plan->n_tchunks = (uint32_t)tchunks.size();
+    plan->n_titems = (uint32_t)titems.size();
+  }
+
   // ---- waves of HBM items, bounded by the device budget --------------------
   // A wave's buckets are small enough to stay in the last-level cache while
   // they are filled and joined, so HBM sees whole lines.
@@ -925,6 +1016,20 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   up("hitems", plan->hitems.data(), plan->hitems.size() * sizeof(HItem));
   up("chunks", all_chunks.data(), all_chunks.size() * sizeof(Chunk));
   up("bitem", all_bitem.data(), all_bitem.size() * 4);
+  if (plan->verdict) {
+    up("vq", vqs.data(), vqs.size() * sizeof(VQuery));
+    up("bitems", bitems.data(), bitems.size() * sizeof(BItem));
+    up("tchunks", tchunks.data(), tchunks.size() * sizeof(TChunk));
+    up("titems", titems.data(), titems.size() * sizeof(TItem));
+    plan->buf("bbounds", std::max<size_t>(1, bitems.size()) * sizeof(BBound), &merr);
+    plan->buf("scores", std::max<size_t>(1, plan->n_tiles) * 4, &merr);
+    if (plan->use_mlp) {
+      plan->buf("order", std::max<size_t>(1, (size_t)vqs.size() * plan->K) * 4, &merr);
+      up("mlp_w", o.mlp, (size_t)mlp_num_weights() * 4);
+    }
+    plan->buf("tout", std::max<size_t>(1, titems.size()) * sizeof(TOut), &merr);
+    plan->buf("claim", std::max<size_t>(1, n_pairs) * 8, &merr);
+  }
   plan->buf("qacc", std::max<size_t>(1, n_pairs) * sizeof(QAcc), &merr);
   plan->buf("out", std::max<size_t>(1, n_pairs) * sizeof(rd_pair_result), &merr);
   if (merr) return merr;
@@ -970,14 +1075,52 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   uint32_t* d_ovf = (uint32_t*)ctx->ensure("ovf", plan->max_items * 4, &merr);
   if (merr) return merr;
 
+  uint32_t* d_done = (uint32_t*)ctx->ensure("done", std::max<size_t>(1, n_pairs) * 4, &merr);
+  if (merr) return merr;
   hipEvent_t* ev = ctx->ev;
   TRY_HIP(hipEventRecord(ev[0], st));
   if (launch_init_acc(st, n_pairs, d_acc)) return RD_EDEVICE;
+  if (launch_fill_u32(st, d_done, n_pairs, 0)) return RD_EDEVICE;
+  double verdict_ms = 0;
+  if (plan->verdict && plan->n_vq) {
+    VQuery* d_vq = (VQuery*)D("vq");
+    BBound* d_bb = (BBound*)D("bbounds");
+    float* d_sc = (float*)D("scores");
+    uint32_t* d_order = plan->use_mlp ? (uint32_t*)D("order") : nullptr;
+    TOut* d_tout = (TOut*)D("tout");
+    u64* d_claim = (u64*)D("claim");
+    TRY_HIP(hipEventRecord(ev[15], st));
+    if (launch_fill_u64(st, d_claim, n_pairs, kNoKey) ||
+        launch_block_bounds(st, (const BItem*)D("bitems"), plan->n_bitems, d_insts,
+                            d_code, d_params, d_loops, d_acc, d_bb) ||
+        launch_vq_span(st, d_vq, plan->n_vq, d_bb))
+      return RD_EDEVICE;
+    if (plan->use_mlp) {
+      if (launch_tile_scores(st, (const TChunk*)D("tchunks"), plan->n_tchunks, d_vq,
+                             d_bb, (const float*)D("mlp_w"), 1, d_sc) ||
+          launch_topk(st, d_vq, plan->n_vq, d_sc, plan->K, plan->max_tiles, d_order))
+        return RD_EDEVICE;
+    }
+    for (auto& rr : plan->rounds) {
+      if (launch_tile_join(cfg, st, (const TItem*)D("titems"), rr.first,
+                           rr.second - rr.first, d_vq, d_order, plan->K, d_insts,
+                           d_code, d_params, d_loops, d_qd, d_done, d_tout, d_claim) ||
+          launch_verdict_commit(st, n_pairs, d_claim, d_tout, d_acc, d_done))
+        return RD_EDEVICE;
+    }
+    TRY_HIP(hipEventRecord(ev[1], st));
+    TRY_HIP(hipEventSynchronize(ev[1]));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev[15], ev[1]);
+    verdict_ms = ms;
+  }
   double small_ms = 0, scatter_ms = 0, bucket_ms = 0, fallback_ms = 0, retry_ms = 0;
+  double split_ms = 0;
+  std::vector<uint32_t> skip;  // kept alive until the stream is synchronised
   if (plan->n_sitems) {
     TRY_HIP(hipEventRecord(ev[2], st));
     if (launch_small(cfg, st, d_sitems, plan->n_sitems, d_insts, d_code,
-                     d_params, d_loops, d_qd, d_acc))
+                     d_params, d_loops, d_qd, d_acc, d_done))
       return RD_EDEVICE;
     TRY_HIP(hipEventRecord(ev[3], st));
     S.join_launches += 1;
@@ -996,19 +1139,21 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   if (merr) return merr;
   auto run_waves = [&](const std::vector<rd_plan_impl::Wave>& waves,
                        const HItem* d_hit, const Chunk* d_chk,
-                       const uint32_t* d_bit, uint32_t* d_ovf) -> int {
+                       const uint32_t* d_bit, uint32_t* d_ovf, int wcfg,
+                       const u64* l0k, const u64* l0c) -> int {
+    const uint32_t wcap = (uint32_t)join_cap(wcfg);
     for (const auto& W : waves) {
       if (launch_fill_u32(st, d_cursor, W.n_buckets, 0)) return RD_EDEVICE;
       TRY_HIP(hipEventRecord(ev[4], st));
       if (launch_scatter(st, d_chk + W.chunk_off, W.n_chunks, d_hit, d_insts,
                          d_code, d_params, d_loops, d_acc, d_keys, d_pids,
-                         d_cursor, d_ovf, cap))
+                         d_cursor, d_ovf, wcap, d_done))
         return RD_EDEVICE;
       TRY_HIP(hipEventRecord(ev[5], st));
       if (W.n_buckets &&
-          launch_bucket(cfg, st, W.n_buckets, 0, d_bit + W.bitem_off, d_hit,
+          launch_bucket(wcfg, st, W.n_buckets, 0, d_bit + W.bitem_off, d_hit,
                         d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_keys,
-                        d_pids, d_cursor, d_ovf))
+                        d_pids, d_cursor, d_ovf, d_done, l0k, l0c))
         return RD_EDEVICE;
       TRY_HIP(hipEventRecord(ev[6], st));
       if (W.n_buckets) S.join_launches += 1;
@@ -1027,7 +1172,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   if (nh) {
     if (launch_fill_u32(st, d_ovf_all, nh, 0)) return RD_EDEVICE;
     TRY_HIP(hipEventRecord(ev[11], st));
-    int rc = run_waves(plan->waves, d_hitems_all, d_chunks_all, d_bitem_all, d_ovf_all);
+    int rc = run_waves(plan->waves, d_hitems_all, d_chunks_all, d_bitem_all, d_ovf_all,
+                       cfg, nullptr, nullptr);
     if (rc) return rc;
     TRY_HIP(hipEventRecord(ev[12], st));
   }
@@ -1044,59 +1190,58 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     waves_ms = ms;  // scatter and bucket joins together
   }
 
-  // ---- retry overflowed items with more buckets ----------------------------
-  std::vector<uint32_t> retry;  // global item indices
-  for (uint32_t i = 0; i < nh; ++i)
-    if (ovf[i] && plan->hitems[i].shared != 2) retry.push_back(i);
-  std::vector<HItem> rh;
-  std::vector<uint64_t> rR;
-  std::vector<rd_plan_impl::Wave> rwaves;
-  std::vector<Chunk> rchunks;
-  std::vector<uint32_t> rbitem;
-  if (!retry.empty()) {
-    size_t pos = 0;
+  // ---- re-partition overflowed items ---------------------------------------
+  // Round 1 retries with more buckets (bucket loads vary with how many points
+  // share an address).  Round 2 splits global items by (address, block) into
+  // bigger tiles, counting level 0 in address-count tables.  What still
+  // overflows goes to the HBM fallback.
+  struct RItem {
+    HItem h;
+    uint64_t R;
+  };
+  auto repartition = [&](std::vector<RItem>& items, int wcfg, const u64* l0k,
+                         const u64* l0c, std::vector<uint32_t>& ovf_out,
+                         float& ms_out) -> int {
+    const uint32_t wcap = (uint32_t)join_cap(wcfg);
+    std::vector<rd_plan_impl::Wave> waves;
+    std::vector<Chunk> chunks;
+    std::vector<uint32_t> bitem;
+    std::vector<HItem> hs;
     uint64_t max_bytes = 0, max_pids = 0, max_nbk = 0;
-    while (pos < retry.size()) {
+    size_t pos = 0;
+    while (pos < items.size()) {
       rd_plan_impl::Wave W;
       memset(&W, 0, sizeof W);
-      W.first_item = (uint32_t)rh.size();
-      W.chunk_off = rchunks.size();
-      W.bitem_off = rbitem.size();
+      W.chunk_off = chunks.size();
+      W.bitem_off = bitem.size();
       uint64_t bytes = 0, nbk = 0, pid_base = 0;
       size_t end = pos;
-      while (end < retry.size()) {
-        HItem h = plan->hitems[retry[end]];
-        uint64_t need_f = (ovf[retry[end]] * 10ull + cap * 6 - 1) / (cap * 6);
-        need_f = std::min<uint64_t>(std::max<uint64_t>(need_f, 2), 64);
-        uint64_t nbuckets = (uint64_t)h.nbuckets * need_f;
+      while (end < items.size()) {
+        HItem h = items[end].h;
         uint64_t ksz = h.is32 ? 4 : 8;
-        uint64_t need = nbuckets * cap * (ksz + 4);
+        uint64_t need = (uint64_t)h.nbuckets * wcap * (ksz + 4);
         if (end > pos && bytes + pid_base * 4 + need > plan->wave_budget) break;
-        h.nbuckets = (uint32_t)nbuckets;
         h.bucket0 = (uint32_t)nbk;
         h.key_off = bytes;
         h.pid_off = pid_base;
-        bytes += (nbuckets * cap * ksz + 255) / 256 * 256;
-        pid_base += nbuckets * cap;
-        nbk += nbuckets;
-        uint32_t li = (uint32_t)rh.size();
-        rh.push_back(h);
-        rR.push_back(plan->hR[retry[end]]);
-        for (uint32_t b = 0; b < h.nbuckets; ++b) rbitem.push_back(li);
+        bytes += ((uint64_t)h.nbuckets * wcap * ksz + 255) / 256 * 256;
+        pid_base += (uint64_t)h.nbuckets * wcap;
+        nbk += h.nbuckets;
+        uint32_t li = (uint32_t)hs.size();
+        hs.push_back(h);
+        for (uint32_t b = 0; b < h.nbuckets; ++b) bitem.push_back(li);
         const QPlan& q = plan->Q[h.q];
         for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
           uint32_t np = plan->npts[side ? h.inst_j : h.inst_i];
           for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
-            rchunks.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+            chunks.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
         }
         ++end;
       }
       W.n_items = (uint32_t)(end - pos);
-      W.n_chunks = (uint32_t)(rchunks.size() - W.chunk_off);
+      W.n_chunks = (uint32_t)(chunks.size() - W.chunk_off);
       W.n_buckets = (uint32_t)nbk;
-      W.key_bytes = bytes;
-      W.pid_elems = pid_base;
-      rwaves.push_back(W);
+      waves.push_back(W);
       max_bytes = std::max(max_bytes, bytes);
       max_pids = std::max(max_pids, pid_base);
       max_nbk = std::max(max_nbk, nbk);
@@ -1105,34 +1250,130 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     d_keys = (unsigned char*)ctx->ensure("keys", std::max<uint64_t>(max_bytes, plan->max_key_bytes), &merr);
     d_pids = (uint32_t*)ctx->ensure("pids", std::max<uint64_t>(max_pids, plan->max_pid_elems) * 4, &merr);
     d_cursor = (uint32_t*)ctx->ensure("cursor", std::max<uint64_t>(max_nbk, plan->max_buckets) * 4, &merr);
-    const uint32_t nr = (uint32_t)rh.size();
+    const uint32_t nr = (uint32_t)hs.size();
     HItem* d_rh = (HItem*)ctx->ensure("r_hitems", nr * sizeof(HItem), &merr);
-    Chunk* d_rc = (Chunk*)ctx->ensure("r_chunks", rchunks.size() * sizeof(Chunk), &merr);
-    uint32_t* d_rb = (uint32_t*)ctx->ensure("r_bitem", rbitem.size() * 4, &merr);
+    Chunk* d_rc = (Chunk*)ctx->ensure("r_chunks", chunks.size() * sizeof(Chunk), &merr);
+    uint32_t* d_rb = (uint32_t*)ctx->ensure("r_bitem", bitem.size() * 4, &merr);
     uint32_t* d_rovf = (uint32_t*)ctx->ensure("r_ovf", nr * 4, &merr);
     if (merr) return merr;
-    TRY_HIP(hipMemcpyAsync(d_rh, rh.data(), nr * sizeof(HItem), hipMemcpyHostToDevice, st));
-    TRY_HIP(hipMemcpyAsync(d_rc, rchunks.data(), rchunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
-    TRY_HIP(hipMemcpyAsync(d_rb, rbitem.data(), rbitem.size() * 4, hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemcpyAsync(d_rh, hs.data(), nr * sizeof(HItem), hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemcpyAsync(d_rc, chunks.data(), chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemcpyAsync(d_rb, bitem.data(), bitem.size() * 4, hipMemcpyHostToDevice, st));
     if (launch_fill_u32(st, d_rovf, nr, 0)) return RD_EDEVICE;
     TRY_HIP(hipEventRecord(ev[13], st));
-    int rc = run_waves(rwaves, d_rh, d_rc, d_rb, d_rovf);
+    int rc = run_waves(waves, d_rh, d_rc, d_rb, d_rovf, wcfg, l0k, l0c);
     if (rc) return rc;
     TRY_HIP(hipEventRecord(ev[14], st));
-    ovf.assign(nr, 0);
-    TRY_HIP(hipMemcpyAsync(ovf.data(), d_rovf, nr * 4, hipMemcpyDeviceToHost, st));
+    ovf_out.assign(nr, 0);
+    TRY_HIP(hipMemcpyAsync(ovf_out.data(), d_rovf, nr * 4, hipMemcpyDeviceToHost, st));
     TRY_HIP(hipStreamSynchronize(st));
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, ev[13], ev[14]);
-    retry_ms = ms;
+    (void)hipEventElapsedTime(&ms_out, ev[13], ev[14]);
+    return RD_OK;
+  };
+
+  std::vector<RItem> rit;
+  for (uint32_t i = 0; i < nh; ++i) {
+    if (!ovf[i] || plan->hitems[i].shared == 2) continue;
+    RItem r{plan->hitems[i], plan->hR[i]};
+    uint64_t need_f = (ovf[i] * 10ull + cap * 6 - 1) / (cap * 6);
+    need_f = std::min<uint64_t>(std::max<uint64_t>(need_f, 2), 64);
+    r.h.nbuckets = (uint32_t)((uint64_t)r.h.nbuckets * need_f);
+    rit.push_back(r);
   }
-  S.retry_items = rh.size();
+  S.retry_items = rit.size();
+  std::vector<uint32_t> rovf;
+  std::vector<RItem> still;
+  if (!rit.empty()) {
+    float ms = 0;
+    int rc = repartition(rit, cfg, nullptr, nullptr, rovf, ms);
+    if (rc) return rc;
+    retry_ms = ms;
+    for (size_t i = 0; i < rit.size(); ++i)
+      if (rovf[i]) still.push_back(rit[i]);
+  }
+
+  // round 2: split global items by (address, block); level 0 in tables
+  std::vector<RItem> split, direct;
+  for (auto& r : still) (r.h.shared == 0 ? split : direct).push_back(r);
+  S.split_items = split.size();
+  if (!split.empty()) {
+    const int scfg = 2;
+    const uint32_t scap = (uint32_t)join_cap(scfg);
+    std::vector<L0Item> l0;
+    uint64_t slots = 0;
+    std::vector<Chunk> l0chunks;
+    for (auto& r : split) {
+      const QPlan& q = plan->Q[r.h.q];
+      uint64_t t = 1;
+      while (t < 2 * r.R) t <<= 1;
+      r.h.shared = 3;
+      r.h.l0_off = slots;
+      r.h.l0_mask = (uint32_t)(t - 1);
+      r.h.nbuckets = (uint32_t)std::max<uint64_t>(1, (r.R * 100 + scap * 55 - 1) / (scap * 55));
+      L0Item li;
+      memset(&li, 0, sizeof li);
+      li.q = r.h.q;
+      li.inst_i = r.h.inst_i;
+      li.inst_j = r.h.inst_j;
+      li.self = q.qd.self;
+      li.off = slots;
+      li.mask = (uint32_t)(t - 1);
+      li.qmask = q.qd.mask;
+      if (q.qd.mask & 1) {
+        uint32_t idx = (uint32_t)l0.size();
+        for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
+          uint32_t np = plan->npts[side ? r.h.inst_j : r.h.inst_i];
+          for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
+            l0chunks.push_back({idx, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+        }
+        l0.push_back(li);
+      }
+      slots += t + 1;
+    }
+    u64* d_l0k = (u64*)ctx->ensure("l0_keys", slots * 8, &merr);
+    u64* d_l0c = (u64*)ctx->ensure("l0_cnt", slots * 8, &merr);
+    L0Item* d_l0i = (L0Item*)ctx->ensure("l0_items", std::max<size_t>(1, l0.size()) * sizeof(L0Item), &merr);
+    u64* d_s0 = (u64*)ctx->ensure("l0_s0", std::max<size_t>(1, l0.size()) * 8, &merr);
+    uint32_t* d_skip = (uint32_t*)ctx->ensure("l0_skip", std::max<size_t>(1, l0.size()) * 4, &merr);
+    Chunk* d_l0ch = (Chunk*)ctx->ensure("l0_chunks", std::max<size_t>(1, l0chunks.size()) * sizeof(Chunk), &merr);
+    if (merr) return merr;
+    TRY_HIP(hipEventRecord(ev[7], st));
+    if (launch_fill_u64(st, d_l0k, slots, kL0Empty) || launch_fill_u64(st, d_l0c, slots, 0))
+      return RD_EDEVICE;
+    if (!l0.empty()) {
+      TRY_HIP(hipMemcpyAsync(d_l0i, l0.data(), l0.size() * sizeof(L0Item), hipMemcpyHostToDevice, st));
+      TRY_HIP(hipMemcpyAsync(d_l0ch, l0chunks.data(), l0chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
+      if (launch_fill_u64(st, d_s0, l0.size(), 0) ||
+          launch_level0(st, d_l0ch, (uint32_t)l0chunks.size(), d_l0i, d_insts, d_code,
+                        d_params, d_loops, d_l0k, d_l0c, d_s0))
+        return RD_EDEVICE;
+    }
+    TRY_HIP(hipEventRecord(ev[8], st));
+    float ms = 0;
+    int rc = repartition(split, scfg, d_l0k, d_l0c, rovf, ms);
+    if (rc) return rc;
+    float ms0 = 0;
+    (void)hipEventElapsedTime(&ms0, ev[7], ev[8]);
+    split_ms = ms0 + ms;
+    // an overflowed split item joined none of its buckets; its S_0 is not
+    // applied and the fallback counts the whole item
+    for (size_t i = 0; i < split.size(); ++i) {
+      if (plan->Q[split[i].h.q].qd.mask & 1) skip.push_back(rovf[i] ? 1u : 0u);
+      if (!rovf[i]) continue;
+      direct.push_back(split[i]);
+      direct.back().h.shared = 0;
+    }
+    if (!l0.empty()) {
+      TRY_HIP(hipMemcpyAsync(d_skip, skip.data(), skip.size() * 4, hipMemcpyHostToDevice, st));
+      if (launch_apply_s0(st, (uint32_t)l0.size(), d_l0i, d_s0, d_skip, d_acc))
+        return RD_EDEVICE;
+    }
+  }
 
   // ---- fallback: HBM aggregation of items that still overflow --------------
   std::vector<FItem> fall;
-  for (size_t i = 0; i < rh.size(); ++i) {
-    if (!ovf[i]) continue;
-    const HItem& h = rh[i];
+  for (size_t i = 0; i < direct.size(); ++i) {
+    const HItem& h = direct[i].h;
     const QPlan& q = plan->Q[h.q];
     FItem f;
     memset(&f, 0, sizeof f);
@@ -1143,7 +1384,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     f.self = q.qd.self;
     f.mask = q.qd.mask;
     f.warp = q.qd.warp;
-    f.cap = (uint32_t)rR[i];
+    f.cap = (uint32_t)direct[i].R;
     fall.push_back(f);
   }
   S.overflow_items = fall.size();
@@ -1214,6 +1455,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   for (uint32_t k = 0; k < n_pairs; ++k) {
     const QPlan& q = plan->Q[k];
     if (!q.work || acc[k].err || acc[k].pmin == kNoKey || q.host_err) continue;
+    if (acc[k].qmin != kNoKey) continue;  // resolved by the tile search
     uint32_t s = (uint32_t)(acc[k].pmin >> 52);
     if (s >= q.inst.size()) continue;
     int32_t ia = q.inst[s].first, ib = q.inst[s].second;
@@ -1253,6 +1495,9 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   S.bucket_ms = bucket_ms;
   S.fallback_ms = fallback_ms;
   S.retry_ms = retry_ms;
+  S.split_ms = split_ms;
+  S.verdict_ms = verdict_ms;
+  S.verdict_units = plan->n_vq;
   S.waves_ms = waves_ms;
   S.witness_ms = w2_ms;
   S.total_ms = now_ms() - t_start;
@@ -1279,6 +1524,201 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
   rc = rd_execute(ctx, plan, out);
   rd_plan_destroy(plan);
   return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Tile data and the tile-scoring network.
+
+int rd_tile_data(rd_context* ctx, const rd_kernel_model* models,
+                 uint32_t n_models, const rd_access_pair* pairs,
+                 uint32_t n_pairs, const rd_launch_domain* launch,
+                 const rd_param_sets* params, const rd_options* opt,
+                 uint64_t max_rows, float* feats, float* labels, uint32_t* ids,
+                 uint64_t* n_rows) {
+  if (!ctx || !n_rows) return RD_EINVAL;
+  rd_options o;
+  memset(&o, 0, sizeof o);
+  if (opt) o = *opt;
+  o.mode = RD_MODE_VERDICT;
+  o.order = RD_ORDER_LEX;
+  o.tile_budget = 1u << 20;
+  rd_plan* plan = nullptr;
+  int rc = rd_prepare(ctx, models, n_models, pairs, n_pairs, launch, params, &o, &plan);
+  if (rc != RD_OK) return rc;
+  std::unique_ptr<rd_plan> guard(plan);
+  *n_rows = plan->n_tiles;
+  if (plan->n_tiles > max_rows) return RD_ECAPACITY;
+  if (!plan->n_tiles) return RD_OK;
+  hipStream_t st = plan->st;
+  auto D = [&](const char* name) { return plan->dev[name].p; };
+  int merr = 0;
+  uint32_t* d_done = (uint32_t*)ctx->ensure("done", std::max<size_t>(1, n_pairs) * 4, &merr);
+  float* d_feat = (float*)ctx->ensure("td_feats", plan->n_tiles * 32 * 4, &merr);
+  if (merr) return merr;
+  VQuery* d_vq = (VQuery*)D("vq");
+  BBound* d_bb = (BBound*)D("bbounds");
+  TOut* d_tout = (TOut*)D("tout");
+  QAcc* d_acc = (QAcc*)D("qacc");
+  if (launch_init_acc(st, n_pairs, d_acc) || launch_fill_u32(st, d_done, n_pairs, 0) ||
+      launch_fill_u64(st, (u64*)D("claim"), n_pairs, kNoKey) ||
+      launch_fill_u64(st, (u64*)d_tout, (u64)plan->n_titems * (sizeof(TOut) / 8), kNoKey) ||
+      launch_block_bounds(st, (const BItem*)D("bitems"), plan->n_bitems, D("insts"),
+                          (const DInsn*)D("code"), (const int64_t*)D("params"),
+                          (const int64_t*)D("loops"), d_acc, d_bb) ||
+      launch_vq_span(st, d_vq, plan->n_vq, d_bb) ||
+      launch_tile_features(st, (const TChunk*)D("tchunks"), plan->n_tchunks, d_vq, d_bb, d_feat))
+    return RD_EDEVICE;
+  // every tile is joined (no commit, so no query stops early)
+  for (auto& rr : plan->rounds)
+    if (launch_tile_join(plan->cfg, st, (const TItem*)D("titems"), rr.first,
+                         rr.second - rr.first, d_vq, nullptr, plan->K, D("insts"),
+                         (const DInsn*)D("code"), (const int64_t*)D("params"),
+                         (const int64_t*)D("loops"), (const QDesc*)D("qdesc"), d_done,
+                         d_tout, (u64*)D("claim")))
+      return RD_EDEVICE;
+  std::vector<TOut> tout(plan->n_titems);
+  std::vector<QAcc> acc(n_pairs);
+  TRY_HIP(hipMemcpyAsync(tout.data(), d_tout, tout.size() * sizeof(TOut), hipMemcpyDeviceToHost, st));
+  if (n_pairs) TRY_HIP(hipMemcpyAsync(acc.data(), d_acc, n_pairs * sizeof(QAcc), hipMemcpyDeviceToHost, st));
+  if (feats)
+    TRY_HIP(hipMemcpyAsync(feats, d_feat, plan->n_tiles * 32 * 4, hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipStreamSynchronize(st));
+  // tile items are (unit, rank = tile index); map each to its row
+  std::vector<int8_t> lab(plan->n_tiles, 0);
+  std::vector<uint32_t> tiles_of_item;
+  {
+    std::vector<TItem> titems(plan->n_titems);
+    TRY_HIP(hipMemcpy(titems.data(), D("titems"), titems.size() * sizeof(TItem), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < titems.size(); ++i) {
+      const VQuery& v = plan->vqs[titems[i].vq];
+      lab[v.tile0 + titems[i].rank] = tout[i].pkey != kNoKey ? 1 : 0;
+    }
+  }
+  for (const VQuery& v : plan->vqs) {
+    uint32_t nt = v.G * v.G;
+    bool bad = acc[v.q].err != 0;
+    for (uint32_t t = 0; t < nt; ++t) {
+      uint64_t row = (uint64_t)v.tile0 + t;
+      if (labels) labels[row] = bad ? -1.f : (float)lab[row];
+      if (ids) {
+        ids[row * 4 + 0] = v.q;
+        ids[row * 4 + 1] = v.sigma;
+        ids[row * 4 + 2] = t / v.G;
+        ids[row * 4 + 3] = t % v.G;
+      }
+    }
+  }
+  return RD_OK;
+}
+
+namespace {
+struct MlpDev {
+  float *w, *g, *m, *v, *loss;
+};
+int mlp_dev(rd_context* ctx, MlpDev& d) {
+  int merr = 0;
+  const size_t nw = (size_t)mlp_num_weights() * 4;
+  d.w = (float*)ctx->ensure("mlp_w", nw, &merr);
+  d.g = (float*)ctx->ensure("mlp_g", nw, &merr);
+  d.m = (float*)ctx->ensure("mlp_m", nw, &merr);
+  d.v = (float*)ctx->ensure("mlp_v", nw, &merr);
+  d.loss = (float*)ctx->ensure("mlp_loss", 256, &merr);
+  return merr;
+}
+}  // namespace
+
+int rd_mlp_forward(rd_context* ctx, const rd_mlp* w, const float* X, uint64_t n,
+                   float* logits, void* stream) {
+  if (!ctx || !w || (n && (!X || !logits))) return RD_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  MlpDev d;
+  int merr = mlp_dev(ctx, d);
+  float* dx = (float*)ctx->ensure("mlp_x", n * 32 * 4, &merr);
+  float* dz = (float*)ctx->ensure("mlp_z", n * 4, &merr);
+  if (merr) return merr;
+  TRY_HIP(hipMemcpyAsync(d.w, w, (size_t)mlp_num_weights() * 4, hipMemcpyHostToDevice, st));
+  if (n) TRY_HIP(hipMemcpyAsync(dx, X, n * 32 * 4, hipMemcpyHostToDevice, st));
+  if (launch_mlp_forward(st, dx, n, d.w, dz)) return RD_EDEVICE;
+  if (n) TRY_HIP(hipMemcpyAsync(logits, dz, n * 4, hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipStreamSynchronize(st));
+  return RD_OK;
+}
+
+int rd_mlp_grad(rd_context* ctx, const rd_mlp* w, const float* X, const float* Y,
+                uint64_t n, rd_mlp* grad, float* loss, void* stream) {
+  if (!ctx || !w || !grad || !loss || (n && (!X || !Y))) return RD_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  MlpDev d;
+  int merr = mlp_dev(ctx, d);
+  float* dx = (float*)ctx->ensure("mlp_x", n * 32 * 4, &merr);
+  float* dy = (float*)ctx->ensure("mlp_y", n * 4, &merr);
+  if (merr) return merr;
+  const size_t nw = (size_t)mlp_num_weights() * 4;
+  TRY_HIP(hipMemcpyAsync(d.w, w, nw, hipMemcpyHostToDevice, st));
+  TRY_HIP(hipMemsetAsync(d.g, 0, nw, st));
+  TRY_HIP(hipMemsetAsync(d.loss, 0, 4, st));
+  if (n) {
+    TRY_HIP(hipMemcpyAsync(dx, X, n * 32 * 4, hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemcpyAsync(dy, Y, n * 4, hipMemcpyHostToDevice, st));
+  }
+  if (launch_mlp_grad(st, dx, dy, n, d.w, d.g, d.loss)) return RD_EDEVICE;
+  TRY_HIP(hipMemcpyAsync(grad, d.g, nw, hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipMemcpyAsync(loss, d.loss, 4, hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipStreamSynchronize(st));
+  return RD_OK;
+}
+
+int rd_mlp_train(rd_context* ctx, rd_mlp* w, const float* X, const float* Y,
+                 uint64_t n, uint32_t epochs, uint32_t batch, float lr,
+                 uint64_t seed, float* epoch_loss, void* stream) {
+  if (!ctx || !w || !n || !X || !Y || !batch || !epochs) return RD_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  MlpDev d;
+  int merr = mlp_dev(ctx, d);
+  float* dx = (float*)ctx->ensure("mlp_x", n * 32 * 4, &merr);
+  float* dy = (float*)ctx->ensure("mlp_y", n * 4, &merr);
+  if (merr) return merr;
+  const size_t nw = (size_t)mlp_num_weights() * 4;
+  TRY_HIP(hipMemcpyAsync(d.w, w, nw, hipMemcpyHostToDevice, st));
+  TRY_HIP(hipMemsetAsync(d.g, 0, nw, st));
+  TRY_HIP(hipMemsetAsync(d.m, 0, nw, st));
+  TRY_HIP(hipMemsetAsync(d.v, 0, nw, st));
+  std::vector<uint64_t> perm(n);
+  for (uint64_t i = 0; i < n; ++i) perm[i] = i;
+  std::vector<float> xs(n * 32), ys(n);
+  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
+  int t = 0;
+  for (uint32_t e = 0; e < epochs; ++e) {
+    for (uint64_t i = n - 1; i > 0; --i) {  // Fisher-Yates with xorshift64
+      x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+      uint64_t j = x % (i + 1);
+      std::swap(perm[i], perm[j]);
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+      memcpy(&xs[i * 32], &X[perm[i] * 32], 32 * 4);
+      ys[i] = Y[perm[i]];
+    }
+    TRY_HIP(hipMemcpyAsync(dx, xs.data(), n * 32 * 4, hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemcpyAsync(dy, ys.data(), n * 4, hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemsetAsync(d.loss, 0, 4, st));
+    uint64_t nb = 0;
+    for (uint64_t off = 0; off < n; off += batch, ++nb) {
+      uint64_t m = std::min<uint64_t>(batch, n - off);
+      if (launch_mlp_grad(st, dx + off * 32, dy + off, m, d.w, d.g, d.loss) ||
+          launch_adam(st, d.w, d.g, d.m, d.v, lr, ++t))
+        return RD_EDEVICE;
+    }
+    float l = 0;
+    TRY_HIP(hipMemcpyAsync(&l, d.loss, 4, hipMemcpyDeviceToHost, st));
+    TRY_HIP(hipStreamSynchronize(st));
+    if (epoch_loss) epoch_loss[e] = l / (float)nb;
+  }
+  TRY_HIP(hipMemcpyAsync(w, d.w, nw, hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipStreamSynchronize(st));
+  return RD_OK;
 }
 
 int rd_selftest(void) {

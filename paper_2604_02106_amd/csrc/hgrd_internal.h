@@ -106,7 +106,22 @@ struct HItem {
   uint32_t is32;          // 32-bit keys
   unsigned long long key_off;  // byte offset of bucket 0's keys
   unsigned long long pid_off;  // element offset of bucket 0's point ids
+  unsigned long long l0_off;   // mode 3: the item's address-count table
+  uint32_t l0_mask, pad;       //   (slots l0_off .. l0_off + l0_mask + 1)
 };
+// HItem.shared: 0 global (hash of the address), 1 shared array (hash of
+// address and block), 2 error scan only (never joined), 3 global item split
+// by (address, block) with its level 0 counted in an address-count table.
+
+// An item whose level 0 is counted in an address-count table: slots
+// [off, off + mask + 1) hold (address, n_a | n_b << 32), slot off + mask + 1
+// the address INT64_MIN (the empty-slot marker).
+struct L0Item {
+  uint32_t q, inst_i, inst_j, self;
+  unsigned long long off;
+  uint32_t mask, qmask;
+};
+constexpr unsigned long long kL0Empty = 0x8000000000000000ull;
 
 // A query/tuple aggregated in HBM (fallback for heavy keys): its records
 // occupy [off, off + cap) of the flat record arrays.
@@ -120,6 +135,41 @@ struct FItem {
 struct Chunk {
   uint32_t item, side;
   uint32_t p0, p1;  // point index range
+};
+
+// ---- VERDICT mode (learned tile order) --------------------------------------
+
+// Block-bounds work item: block `block` of access instance `inst` (query q).
+struct BItem {
+  uint32_t inst, block, q, pad;
+};
+// Smallest and largest address of a block's guarded points, and their number.
+struct BBound {
+  long long mn, mx;
+  uint32_t cnt, pad;
+};
+// One search unit: a query under one tuple, with G blocks per side; its
+// tiles are (b1, b2) in [0, G)^2, tile index b1 * G + b2.
+struct VQuery {
+  uint32_t q, sigma, inst_i, inst_j;
+  uint32_t G, bb_i, bb_j, self;   // bb_*: first BBound of each side
+  uint32_t tile0, tpb_i, tpb_j, nthr;
+  uint32_t kinds, shared, is64, nsets;
+  long long amin, amax;           // address span over both sides
+};
+// Tiles [t0, t1) of search unit vq (scores / features).
+struct TChunk {
+  uint32_t vq, t0, t1, pad;
+};
+// One tile to search: the rank-th tile of search unit vq in its order.
+struct TItem {
+  uint32_t vq, rank;
+};
+// Result of a conflicting tile.
+struct TOut {
+  unsigned long long cnt[3];
+  unsigned long long pkey, qkey;
+  long long addr;
 };
 
 }  // namespace hgrd

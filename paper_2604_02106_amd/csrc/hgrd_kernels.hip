@@ -28,431 +28,12 @@
 #include <stdint.h>
 #include "hgrd_internal.h"
 #include "hgrd_launch.h"
+#include "hgrd_device.h"
 #include <string.h>
 
 namespace hgrd {
 
 using u64 = unsigned long long;
-
-// ---------------------------------------------------------------------------
-// Division by a uniform 32-bit divisor for numerators below 2^31, by a
-// multiply-high and a shift (Granlund and Montgomery, "Division by invariant
-// integers using multiplication", PLDI 1994, section 4).
-struct FastDiv {
-  uint32_t d, m, s, pad;
-};
-
-__host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
-  FastDiv f;
-  f.d = d;
-  uint32_t l = 0;
-  while (l < 32 && (1ull << l) < d) ++l;
-  f.s = l;
-  // m = floor(2^32 * (2^l - d) / d) + 1
-  f.m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
-  f.pad = 0;
-  return f;
-}
-
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
-  uint32_t t = __umulhi(f.m, n);
-  return (t + n) >> f.s;
-}
-
-// ---------------------------------------------------------------------------
-// Checked int64 arithmetic: on error set a bit and yield 0 (C semantics
-// otherwise: truncating '/', '%' with the dividend's sign, arithmetic '>>').
-__device__ __forceinline__ int64_t alu(uint8_t op, int64_t a, int64_t b,
-                                       uint32_t& err) {
-  int64_t r;
-  switch (op) {
-    case D_MOV: return a;
-    case D_ADD:
-      if (__builtin_add_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
-      return r;
-    case D_SUB:
-      if (__builtin_sub_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
-      return r;
-    case D_MUL:
-      if (__builtin_mul_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
-      return r;
-    case D_DIV:
-      if (b == 0) { err |= ERR_DIVZERO; return 0; }
-      if (a == INT64_MIN && b == -1) { err |= ERR_RANGE; return 0; }
-      return a / b;
-    case D_MOD:
-      if (b == 0) { err |= ERR_DIVZERO; return 0; }
-      if (a == INT64_MIN && b == -1) { err |= ERR_RANGE; return 0; }
-      return a % b;
-    case D_SHL: {
-      if (b < 0 || b > 63) { err |= ERR_RANGE; return 0; }
-      int64_t s = (int64_t)((uint64_t)a << b);
-      if ((s >> b) != a) { err |= ERR_RANGE; return 0; }
-      return s;
-    }
-    case D_SHR:
-      if (b < 0 || b > 63) { err |= ERR_RANGE; return 0; }
-      return a >> b;
-    case D_AND: return a & b;
-    case D_OR: return a | b;
-    case D_XOR: return a ^ b;
-    case D_MIN: return a < b ? a : b;
-    case D_MAX: return a > b ? a : b;
-    case D_LT: return a < b;
-    case D_LE: return a <= b;
-    case D_EQ: return a == b;
-    case D_NE: return a != b;
-    case D_GE: return a >= b;
-    case D_GT: return a > b;
-    case D_LAND: return (a != 0) & (b != 0);
-    case D_LOR: return (a != 0) | (b != 0);
-    case D_NEG:
-      if (a == INT64_MIN) { err |= ERR_RANGE; return 0; }
-      return -a;
-    case D_LNOT: return a == 0;
-  }
-  return 0;
-}
-
-// Point coordinates live in named fields (read through a uniform switch);
-// only the stack slots form an indexed array, which keeps it in VGPRs.
-struct Regs {
-  int64_t c0, c1, c2, c3, c4, c5, c6, c7, c8, c9;
-};
-typedef int64_t Stack[kMaxStack];
-
-__device__ __forceinline__ int64_t coord(const Regs& R, uint32_t i) {
-  switch (i) {
-    case 0: return R.c0;
-    case 1: return R.c1;
-    case 2: return R.c2;
-    case 3: return R.c3;
-    case 4: return R.c4;
-    case 5: return R.c5;
-    case 6: return R.c6;
-    case 7: return R.c7;
-    case 8: return R.c8;
-    default: return R.c9;
-  }
-}
-
-struct DevInst {
-  AccInst a;
-  FastDiv f_nthr, f_niota, f_gx, f_gxy, f_bx, f_bxy;
-  FastDiv f_loop[4];
-};
-
-// Runs one compiled expression.  `code`, `p`, `params` and `dims` are
-// uniform across the wavefront.
-__device__ __forceinline__ int64_t run_prog(const DInsn* __restrict__ code,
-                                            const Prog p, const Regs& R,
-                                            const int64_t* __restrict__ params,
-                                            int64_t dflt, uint32_t& err) {
-  if (p.absent) return dflt;
-  Stack st;
-  for (uint32_t k = 0; k < p.n; ++k) {
-    const DInsn in = code[p.off + k];
-    int64_t a, b;
-    // launch extents follow the parameters of the tuple in the pool
-    if (in.ma == M_REG) a = st[in.a];
-    else if (in.ma == M_IMM) a = in.imm;
-    else if (in.ma == M_PARAM) a = params[in.a];
-    else a = coord(R, in.a);
-    if (in.mb == M_REG) b = st[in.b];
-    else if (in.mb == M_IMM) b = in.imm;
-    else if (in.mb == M_PARAM) b = params[in.b];
-    else b = coord(R, in.b);
-    st[in.dst] = alu(in.op, a, b, err);
-  }
-  return st[p.res];
-}
-
-// Point coordinates of point index `pidx` = (blin * niota + ilin) * nthr + tlin.
-struct PointIds {
-  uint32_t blin, tlin, ilin;
-};
-
-__device__ __forceinline__ PointIds decode(const DevInst& I, uint32_t pidx) {
-  PointIds o;
-  uint32_t rest = fdiv(pidx, I.f_nthr);
-  o.tlin = pidx - rest * I.a.nthr;
-  o.blin = fdiv(rest, I.f_niota);
-  o.ilin = rest - o.blin * I.a.niota;
-  return o;
-}
-
-__device__ __forceinline__ void set_coords(const DevInst& I, const PointIds& p,
-                                           const int64_t* __restrict__ loopvals,
-                                           Regs& R) {
-  uint32_t t1 = fdiv(p.tlin, I.f_bx);
-  R.c0 = p.tlin - t1 * (uint32_t)I.a.dims[3];
-  uint32_t t2 = fdiv(p.tlin, I.f_bxy);
-  R.c1 = t1 - t2 * (uint32_t)I.a.dims[4];
-  R.c2 = t2;
-  uint32_t b1 = fdiv(p.blin, I.f_gx);
-  R.c3 = p.blin - b1 * (uint32_t)I.a.dims[0];
-  uint32_t b2 = fdiv(p.blin, I.f_gxy);
-  R.c4 = b1 - b2 * (uint32_t)I.a.dims[1];
-  R.c5 = b2;
-  R.c6 = R.c7 = R.c8 = R.c9 = 0;
-  uint32_t rem = p.ilin;
-  const uint32_t nl = I.a.n_loops;
-  if (nl > 3) {
-    uint32_t q = fdiv(rem, I.f_loop[3]);
-    R.c9 = loopvals[I.a.loop_off[3] + (rem - q * I.a.loop_n[3])];
-    rem = q;
-  }
-  if (nl > 2) {
-    uint32_t q = fdiv(rem, I.f_loop[2]);
-    R.c8 = loopvals[I.a.loop_off[2] + (rem - q * I.a.loop_n[2])];
-    rem = q;
-  }
-  if (nl > 1) {
-    uint32_t q = fdiv(rem, I.f_loop[1]);
-    R.c7 = loopvals[I.a.loop_off[1] + (rem - q * I.a.loop_n[1])];
-    rem = q;
-  }
-  if (nl > 0) {
-    uint32_t q = fdiv(rem, I.f_loop[0]);
-    R.c6 = loopvals[I.a.loop_off[0] + (rem - q * I.a.loop_n[0])];
-  }
-}
-
-struct Point {
-  int64_t addr;
-  uint32_t bint, wint;
-};
-
-// Evaluates guard, then (if it holds) address and interval ids, recording
-// errors exactly as the C-level semantics say.  Returns the guard.
-__device__ __forceinline__ bool eval_point(const DevInst& I,
-                                           const DInsn* __restrict__ code,
-                                           const int64_t* __restrict__ params,
-                                           Regs& R, Point& pt, uint32_t& err) {
-  const int64_t* pr = params + I.a.params_off;
-  int64_t g = run_prog(code, I.a.guard, R, pr, 1, err);
-  if (g == 0) return false;
-  uint32_t e = 0;
-  pt.addr = run_prog(code, I.a.addr, R, pr, 0, e);
-  int64_t bi = run_prog(code, I.a.bint, R, pr, 0, e);
-  int64_t wi = run_prog(code, I.a.wint, R, pr, 0, e);
-  if (I.a.is32 && (pt.addr < INT32_MIN || pt.addr > INT32_MAX)) e |= ERR_RANGE;
-  if (bi < 0 || bi > 65535 || wi < 0 || wi > 65535) e |= ERR_UNSUP;
-  err |= e;
-  pt.bint = (uint32_t)bi & 0xFFFF;
-  pt.wint = (uint32_t)wi & 0xFFFF;
-  return e == 0;
-}
-
-__device__ __forceinline__ void load_inst(DevInst& D,
-                                          const DevInst* __restrict__ insts,
-                                          uint32_t k) {
-  k = __builtin_amdgcn_readfirstlane(k);
-  D = insts[k];
-}
-
-// ---------------------------------------------------------------------------
-// Reductions.
-
-__device__ __forceinline__ u64 wave_sum(u64 v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ u64 wave_min(u64 v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    u64 w = __shfl_xor(v, o, 64);
-    v = w < v ? w : v;
-  }
-  return v;
-}
-__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-  return v;
-}
-
-// ---------------------------------------------------------------------------
-// LDS join of up to CAP records (both sides of one query under one tuple).
-
-constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-constexpr uint32_t kInactive = 1u << 14;  // in tli
-constexpr uint32_t kSide = 1u << 15;      // in tli
-
-template <int CAP, int TBL>
-struct JoinLds {
-  u64 addr[CAP];
-  uint32_t blin[CAP];
-  uint32_t tli[CAP];  // ilin << 16 | side << 15 | inactive << 14 | tlin
-  uint32_t bw[CAP];   // bint << 16 | wint
-  uint16_t w[CAP];    // warp of the analysed program
-  uint16_t slot[CAP];
-  int32_t part[CAP];
-  uint32_t owner[TBL];
-  uint32_t cnt[TBL];
-  u64 red[8];
-  uint32_t n;
-  uint32_t err;
-};
-
-__device__ __forceinline__ uint32_t level_hash(int L, u64 addr, uint32_t blin,
-                                               uint32_t bw, uint32_t w,
-                                               uint32_t t) {
-  u64 h = addr * 0x9E3779B97F4A7C15ull;
-  if (L >= 1) h ^= (u64)(blin + 1) * 0xC2B2AE3D27D4EB4Full;
-  if (L >= 2) h ^= (u64)((bw >> 16) + 1) * 0x165667B19E3779F9ull;
-  if (L >= 3) h ^= (u64)(w + 1) * 0x27D4EB2F165667C5ull;
-  if (L >= 4) h ^= (u64)((bw & 0xFFFF) + 1) * 0x94D049BB133111EBull;
-  if (L >= 5) h ^= (u64)(t + 1) * 0xBF58476D1CE4E5B9ull;
-  h ^= h >> 31;
-  h *= 0x9E3779B97F4A7C15ull;
-  h ^= h >> 29;
-  return (uint32_t)(h >> 32);
-}
-
-template <int CAP, int TBL>
-__device__ __forceinline__ bool level_eq(const JoinLds<CAP, TBL>& S, int L,
-                                         uint32_t x, uint32_t y) {
-  if (S.addr[x] != S.addr[y]) return false;
-  if (L >= 1 && S.blin[x] != S.blin[y]) return false;
-  if (L >= 2 && (S.bw[x] >> 16) != (S.bw[y] >> 16)) return false;
-  if (L >= 3 && S.w[x] != S.w[y]) return false;
-  if (L >= 4 && (S.bw[x] & 0xFFFF) != (S.bw[y] & 0xFFFF)) return false;
-  if (L >= 5 && (S.tli[x] & 0x3FF) != (S.tli[y] & 0x3FF)) return false;
-  return true;
-}
-
-// Joins the S.n records in LDS; adds class counts and the witness candidate
-// to the query accumulators.  All threads of the block must call it.
-template <int CAP, int TBL>
-__device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
-                         QAcc* __restrict__ acc) {
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t n = S.n;
-  const uint32_t mask = qd.mask;
-  const bool self = qd.self != 0;
-  uint32_t used = 0;
-  if (mask & 1) used |= 0x03;
-  if (mask & 2) used |= 0x0C;
-  if (mask & 4) used |= 0x30;
-  if (used == 0 || n == 0) return;
-  const int f = __ffs(used) - 1;
-  u64 Sl[6] = {0, 0, 0, 0, 0, 0};
-  for (uint32_t r = tid; r < n; r += nt) S.part[r] = 0;
-  bool any = true;
-  for (int L = f; L < 6; ++L) {
-    if (!((used >> L) & 1)) continue;
-    for (uint32_t k = tid; k < TBL; k += nt) {
-      S.owner[k] = kEmpty;
-      S.cnt[k] = 0;
-    }
-    __syncthreads();
-    u64 s = 0;
-    for (uint32_t r = tid; r < n; r += nt) {
-      uint32_t tl = S.tli[r];
-      if (tl & kInactive) continue;
-      uint32_t h = level_hash(L, S.addr[r], S.blin[r], S.bw[r], S.w[r],
-                              tl & 0x3FF) & (TBL - 1);
-      for (;;) {
-        uint32_t o = atomicCAS(&S.owner[h], kEmpty, r);
-        if (o == kEmpty || level_eq(S, L, o, r)) break;
-        h = (h + 1) & (TBL - 1);
-      }
-      uint32_t side = (tl & kSide) ? 1u : 0u;
-      uint32_t old = atomicAdd(&S.cnt[h], (self || !side) ? 1u : 0x10000u);
-      if (self) s += 2ull * (old & 0xFFFF) + 1;
-      else s += side ? (old & 0xFFFF) : (old >> 16);
-      S.slot[r] = (uint16_t)h;
-    }
-    __syncthreads();
-    const int sign = (L & 1) ? -1 : 1;
-    const uint32_t cls = L < 2 ? 1u : (L < 4 ? 2u : 4u);
-    bool any_local = false;
-    for (uint32_t r = tid; r < n; r += nt) {
-      uint32_t tl = S.tli[r];
-      if (tl & kInactive) continue;
-      uint32_t c = S.cnt[S.slot[r]];
-      if (L == f) {
-        bool cand = self ? ((c & 0xFFFF) >= 2) : ((c & 0xFFFF) && (c >> 16));
-        if (!cand) {
-          S.tli[r] = tl | kInactive;
-          if (self) s -= 1;  // a lone record pairs only with itself
-          continue;
-        }
-        any_local = true;
-      }
-      if (!self && (tl & kSide)) continue;
-      if (cls & mask) {
-        int32_t nj = (int32_t)(self ? (c & 0xFFFF) : (c >> 16));
-        S.part[r] += sign * nj;
-      }
-    }
-    Sl[L] = s;
-    if (L == f) {
-      any = __syncthreads_or(any_local);
-      if (!any) break;
-    } else {
-      __syncthreads();
-    }
-  }
-  if (!any) return;
-  // class counts: reduce S_L over the block
-  u64 c0 = (mask & 1) ? Sl[0] - Sl[1] : 0;
-  u64 c1 = (mask & 2) ? Sl[2] - Sl[3] : 0;
-  u64 c2 = (mask & 4) ? Sl[4] - Sl[5] : 0;
-  u64 best = kNoKey;
-  for (uint32_t r = tid; r < n; r += nt) {
-    uint32_t tl = S.tli[r];
-    if ((tl & kInactive) || (!self && (tl & kSide))) continue;
-    if (S.part[r] > 0) {
-      u64 k = pkey(sigma, S.blin[r], tl & 0x3FF, tl >> 16);
-      best = k < best ? k : best;
-    }
-  }
-  if (tid < 4) S.red[tid] = tid == 3 ? kNoKey : 0;
-  __syncthreads();
-  c0 = wave_sum(c0);
-  c1 = wave_sum(c1);
-  c2 = wave_sum(c2);
-  best = wave_min(best);
-  if ((tid & 63) == 0) {
-    if (c0) atomicAdd(&S.red[0], c0);
-    if (c1) atomicAdd(&S.red[1], c1);
-    if (c2) atomicAdd(&S.red[2], c2);
-    if (best != kNoKey) atomicMin(&S.red[3], best);
-  }
-  __syncthreads();
-  if (tid == 0) {
-    if (S.red[0]) atomicAdd(&acc->cnt[0], S.red[0]);
-    if (S.red[1]) atomicAdd(&acc->cnt[1], S.red[1]);
-    if (S.red[2]) atomicAdd(&acc->cnt[2], S.red[2]);
-    if (S.red[3] != kNoKey) atomicMin(&acc->pmin, S.red[3]);
-  }
-}
-
-// Appends a record to the LDS arrays (wavefront-aggregated slot claim).
-template <int CAP, int TBL>
-__device__ __forceinline__ void lds_append(JoinLds<CAP, TBL>& S, bool valid,
-                                           const Point& pt, const PointIds& id,
-                                           uint32_t side, uint32_t warp_w) {
-  u64 bal = __ballot(valid);
-  if (bal == 0) return;
-  uint32_t lane = threadIdx.x & 63;
-  uint32_t leader = __ffsll((long long)bal) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(&S.n, (uint32_t)__popcll(bal));
-  base = __shfl(base, leader, 64);
-  if (valid) {
-    uint32_t r = base + __popcll(bal & ((1ull << lane) - 1));
-    if (r >= CAP) {  // the planner never lets this happen; never write past
-      atomicOr(&S.err, ERR_INTERNAL);
-      return;
-    }
-    S.addr[r] = (u64)pt.addr;
-    S.blin[r] = id.blin;
-    S.tli[r] = (id.ilin << 16) | (side << 15) | id.tlin;
-    S.bw[r] = (pt.bint << 16) | pt.wint;
-    S.w[r] = (uint16_t)warp_w;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Kernel: generate both sides of a small item straight into LDS and join.
@@ -462,15 +43,17 @@ __global__ void __launch_bounds__(256)
 k_small_join(const SItem* __restrict__ items, const DevInst* __restrict__ insts,
              const DInsn* __restrict__ code, const int64_t* __restrict__ params,
              const int64_t* __restrict__ loopvals, const QDesc* __restrict__ qd,
-             QAcc* __restrict__ acc) {
+             QAcc* __restrict__ acc, const uint32_t* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem[];
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
   const SItem it = items[blockIdx.x];
+  if (done[it.q]) return;
   const QDesc q = qd[it.q];
   if (threadIdx.x == 0) {
     S.n = 0;
     S.err = 0;
   }
+  init_red(S);
   __syncthreads();
   uint32_t err = 0;
   const int nside = q.self ? 1 : 2;
@@ -500,7 +83,8 @@ k_small_join(const SItem* __restrict__ items, const DevInst* __restrict__ insts,
     if (threadIdx.x == 0) atomicOr(&acc[it.q].err, S.err);
     return;
   }
-  lds_join(S, q, it.sigma, &acc[it.q]);
+  lds_join(S, q, it.sigma);
+  commit_join(S, &acc[it.q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -524,9 +108,10 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
           const int64_t* __restrict__ loopvals, QAcc* __restrict__ acc,
           unsigned char* __restrict__ keys, uint32_t* __restrict__ pids,
           uint32_t* __restrict__ cursor, uint32_t* __restrict__ ovf,
-          uint32_t capb) {
+          uint32_t capb, const uint32_t* __restrict__ done) {
   const Chunk ch = chunks[blockIdx.x];
   const HItem h = hitems[ch.item];
+  if (done[h.q]) return;
   DevInst I;
   load_inst(I, insts, ch.side ? h.inst_j : h.inst_i);
   uint32_t err = 0;
@@ -541,7 +126,7 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
     if (!eval_point(I, code, params, R, pt, err)) continue;
     if (h.nbuckets == 0) continue;  // error scan only
     u64 hk = (u64)pt.addr;
-    if (h.shared) hk ^= (u64)(id.blin + 1) * 0x9E3779B97F4A7C15ull;
+    if (h.shared == 1 || h.shared == 3) hk ^= (u64)(id.blin + 1) * 0x9E3779B97F4A7C15ull;
     uint32_t b = (uint32_t)__umul64hi(mix64(hk), (u64)h.nbuckets);
     uint32_t g = h.bucket0 + b;
     uint32_t pos = atomicAdd(&cursor[g], 1u);
@@ -563,6 +148,126 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
 }
 
 // ---------------------------------------------------------------------------
+// Address-count tables (level 0 of split items): open addressing on the
+// 64-bit address with INT64_MIN as the empty marker; that address itself
+// has a slot of its own after the table.
+
+__device__ __forceinline__ u64 l0_hash(long long a) {
+  return mix64((u64)a * 0x9E3779B97F4A7C15ull);
+}
+
+__device__ __forceinline__ u64 l0_lookup(const u64* __restrict__ keys,
+                                         const u64* __restrict__ cnt, u64 off,
+                                         uint32_t mask, long long a, bool self) {
+  u64 slot;
+  if ((u64)a == kL0Empty) {
+    slot = off + mask + 1;
+  } else {
+    u64 h = l0_hash(a) & mask;
+    for (;;) {
+      u64 k = keys[off + h];
+      if (k == (u64)a) break;
+      if (k == kL0Empty) return 0;
+      h = (h + 1) & mask;
+    }
+    slot = off + h;
+  }
+  u64 c = cnt[slot];
+  return self ? c : (c >> 32);
+}
+
+// Level 0 of split items: every point is counted into its item's
+// address-count table.  Each workgroup first merges 1024 points at a time
+// in LDS by address, so a hot address costs one global atomic per
+// workgroup step.  Each item's S_0 is summed in s0[item].
+__global__ void __launch_bounds__(256)
+k_level0(const Chunk* __restrict__ chunks, const L0Item* __restrict__ items,
+         const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
+         const int64_t* __restrict__ params,
+         const int64_t* __restrict__ loopvals, u64* __restrict__ keys,
+         u64* __restrict__ cnt, u64* __restrict__ s0) {
+  constexpr int kT = 2048;
+  __shared__ u64 lkey[kT + 1];
+  __shared__ uint32_t lcnt[kT + 1];
+  __shared__ u64 lsum;
+  const Chunk ch = chunks[blockIdx.x];
+  const L0Item it = items[ch.item];
+  DevInst I;
+  load_inst(I, insts, ch.side ? it.inst_j : it.inst_i);
+  const uint32_t inc = (it.self || !ch.side) ? 1u : 0x10000u;
+  if (threadIdx.x == 0) lsum = 0;
+  u64 s = 0;
+  uint32_t err = 0;
+  for (uint32_t t0 = ch.p0; t0 < ch.p1; t0 += 1024) {
+    for (uint32_t k = threadIdx.x; k <= kT; k += blockDim.x) {
+      lkey[k] = kL0Empty;
+      lcnt[k] = 0;
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < 4; ++j) {
+      uint32_t pidx = t0 + j * 256 + threadIdx.x;
+      if (pidx >= ch.p1) break;
+      PointIds id = decode(I, pidx);
+      Regs R;
+      set_coords(I, id, loopvals, R);
+      Point pt;
+      if (!eval_point(I, code, params, R, pt, err)) continue;
+      uint32_t h;
+      if ((u64)pt.addr == kL0Empty) {
+        h = kT;
+      } else {
+        h = (uint32_t)l0_hash(pt.addr) & (kT - 1);
+        for (;;) {
+          u64 k = atomicCAS(&lkey[h], kL0Empty, (u64)pt.addr);
+          if (k == kL0Empty || k == (u64)pt.addr) break;
+          h = (h + 1) & (kT - 1);
+        }
+      }
+      atomicAdd(&lcnt[h], inc);
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k <= kT; k += blockDim.x) {
+      const uint32_t c = lcnt[k];
+      if (!c) continue;
+      const u64 a = lkey[k];
+      u64 slot;
+      if (k == kT) {
+        slot = it.off + it.mask + 1;
+      } else {
+        u64 h = l0_hash((long long)a) & it.mask;
+        for (;;) {
+          u64 kk = atomicCAS(&keys[it.off + h], kL0Empty, a);
+          if (kk == kL0Empty || kk == a) break;
+          h = (h + 1) & it.mask;
+        }
+        slot = it.off + h;
+      }
+      const u64 ni = c & 0xFFFF, nj = c >> 16;
+      const u64 old = atomicAdd(&cnt[slot], it.self ? ni : (ni | (nj << 32)));
+      if (it.self) s += 2 * old * ni + ni * ni;
+      else s += ni * (old >> 32) + nj * (old & 0xFFFFFFFFull) + ni * nj;
+    }
+    __syncthreads();
+  }
+  (void)err;  // the first partition pass has recorded evaluation errors
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(&lsum, s);
+  __syncthreads();
+  if (threadIdx.x == 0 && lsum) atomicAdd(&s0[ch.item], lsum);
+}
+
+// Adds each split item's S_0 to its inter-block count, unless the item's
+// split pass overflowed (its whole count is then redone by the fallback).
+__global__ void k_apply_s0(uint32_t n, const L0Item* __restrict__ items,
+                           const u64* __restrict__ s0,
+                           const uint32_t* __restrict__ skip,
+                           QAcc* __restrict__ acc) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n || skip[k] || !(items[k].qmask & 1) || !s0[k]) return;
+  atomicAdd(&acc[items[k].q].cnt[0], s0[k]);
+}
+
+// ---------------------------------------------------------------------------
 // Kernel: one workgroup per HBM bucket; load its records into LDS and join.
 
 template <int CAP, int TBL>
@@ -576,13 +281,15 @@ k_bucket_join(const uint32_t* __restrict__ bucket_item,
               const unsigned char* __restrict__ keys,
               const uint32_t* __restrict__ pids,
               const uint32_t* __restrict__ cursor,
-              const uint32_t* __restrict__ ovf, uint32_t bucket_base) {
+              const uint32_t* __restrict__ ovf, uint32_t bucket_base,
+              const uint32_t* __restrict__ done, const u64* __restrict__ l0keys,
+              const u64* __restrict__ l0cnt) {
   extern __shared__ __align__(16) unsigned char smem[];
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
   const uint32_t g = bucket_base + blockIdx.x;
   const uint32_t hi = bucket_item[g];
   const HItem h = hitems[hi];
-  if (ovf[hi]) return;
+  if (ovf[hi] || done[h.q]) return;
   uint32_t n = cursor[g];
   if (n == 0) return;
   if (n > CAP) n = CAP;  // cannot happen without the overflow flag
@@ -620,9 +327,23 @@ k_bucket_join(const uint32_t* __restrict__ bucket_item,
     }
   }
   (void)err;
+  const bool l0ext = h.shared == 3;
+  if (l0ext) {
+    // level-0 partners of each side-a record: the other side's count at its
+    // address in the item's address-count table
+    for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
+      int32_t nj = 0;
+      if ((q.mask & 1) && (q.self || !(S.tli[r] & kSide)))
+        nj = (int32_t)l0_lookup(l0keys, l0cnt, h.l0_off, h.l0_mask,
+                                (long long)S.addr[r], q.self != 0);
+      S.part[r] = nj;
+    }
+  }
   if (threadIdx.x == 0) S.n = n;
+  init_red(S);
   __syncthreads();
-  lds_join(S, q, h.sigma, &acc[h.q]);
+  lds_join(S, q, h.sigma, l0ext);
+  commit_join(S, &acc[h.q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,7 +441,16 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
   __shared__ uint32_t lown[kGLocal];
   __shared__ uint32_t lcnt[kGLocal];
   __shared__ uint32_t lgs[kGLocal];
+  // level sums of the items of this workgroup's records, merged in LDS so a
+  // big item does not serialise on one global counter
+  constexpr int kSlots = 16;
+  __shared__ uint32_t sitem[kSlots];
+  __shared__ u64 ssum[kSlots];
   const uint32_t tid = threadIdx.x;
+  if (tid < kSlots) {
+    sitem[tid] = kEmpty;
+    ssum[tid] = 0;
+  }
   for (u64 t0 = (u64)blockIdx.x * kGTile; t0 < n; t0 += (u64)gridDim.x * kGTile) {
     for (uint32_t k = tid; k < kGLocal; k += blockDim.x) {
       lown[k] = kEmpty;
@@ -768,7 +498,12 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
       u64 contrib;
       if (f.self) contrib = 2 * old * li + li * li;  // (old + k)^2 - old^2
       else contrib = li * (old >> 32) + lj * (old & 0xFFFFFFFFull) + li * lj;
-      if (contrib) atomicAdd(&S[(u64)it * 8 + L], contrib);
+      if (contrib) {
+        const uint32_t sl = it % kSlots;
+        uint32_t prev = atomicCAS(&sitem[sl], kEmpty, it);
+        if (prev == kEmpty || prev == it) atomicAdd(&ssum[sl], contrib);
+        else atomicAdd(&S[(u64)it * 8 + L], contrib);
+      }
       lgs[k] = (uint32_t)h;
     }
     __syncthreads();
@@ -779,6 +514,8 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
     }
     __syncthreads();
   }
+  if (tid < kSlots && sitem[tid] != kEmpty && ssum[tid])
+    atomicAdd(&S[(u64)sitem[tid] * 8 + L], ssum[tid]);
 }
 
 // Adds +-(partners at level L) to every record of side a (self: all).
@@ -950,6 +687,10 @@ k_finalize(uint32_t n, const QAcc* __restrict__ acc,
   else if (e & ERR_RANGE) r.status = RD_ERANGE;
   if (r.status == 0 && trivial[k]) r.flags = 1;
   if (r.status == 0 && !trivial[k]) {
+    r.flags = (uint8_t)(a.qclass & 2);
+    r.tiles = a.qclass >> 8;
+  }
+  if (r.status == 0 && !trivial[k]) {
     r.count_by_class[0] = a.cnt[0];
     r.count_by_class[1] = a.cnt[1];
     r.count_by_class[2] = a.cnt[2];
@@ -987,7 +728,7 @@ template <int CAP, int TBL>
 static int launch_small_t(hipStream_t st, const SItem* items, uint32_t n,
                           const DevInst* insts, const DInsn* code,
                           const int64_t* params, const int64_t* loopvals,
-                          const QDesc* qd, QAcc* acc) {
+                          const QDesc* qd, QAcc* acc, const uint32_t* done) {
   size_t lds = sizeof(JoinLds<CAP, TBL>);
   static bool attr = false;
   if (!attr) {
@@ -999,7 +740,7 @@ static int launch_small_t(hipStream_t st, const SItem* items, uint32_t n,
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
     hipLaunchKernelGGL((k_small_join<CAP, TBL>), dim3(m), dim3(256), lds, st,
-                       items + off, insts, code, params, loopvals, qd, acc);
+                       items + off, insts, code, params, loopvals, qd, acc, done);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -1012,7 +753,9 @@ static int launch_bucket_t(hipStream_t st, uint32_t nb, uint32_t base,
                            const int64_t* params, const int64_t* loopvals,
                            const QDesc* qd, QAcc* acc,
                            const unsigned char* keys, const uint32_t* pids,
-                           const uint32_t* cursor, const uint32_t* ovf) {
+                           const uint32_t* cursor, const uint32_t* ovf,
+                           const uint32_t* done, const u64* l0keys,
+                           const u64* l0cnt) {
   size_t lds = sizeof(JoinLds<CAP, TBL>);
   static bool attr = false;
   if (!attr) {
@@ -1023,7 +766,7 @@ static int launch_bucket_t(hipStream_t st, uint32_t nb, uint32_t base,
   }
   hipLaunchKernelGGL((k_bucket_join<CAP, TBL>), dim3(nb), dim3(256), lds, st,
                      bucket_item, hitems, insts, code, params, loopvals, qd,
-                     acc, keys, pids, cursor, ovf, base);
+                     acc, keys, pids, cursor, ovf, base, done, l0keys, l0cnt);
   HGRD_CHECK(hipGetLastError());
   return 0;
 }
@@ -1069,12 +812,13 @@ int join_cap(int cfg) { return cfg == 0 ? 1024 : cfg == 1 ? 1536 : 3072; }
 
 int launch_small(int cfg, hipStream_t st, const SItem* items, uint32_t n,
                  const void* insts, const DInsn* code, const int64_t* params,
-                 const int64_t* loopvals, const QDesc* qd, QAcc* acc) {
+                 const int64_t* loopvals, const QDesc* qd, QAcc* acc,
+                 const uint32_t* done) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_small_t<1024, 2048>(st, items, n, I, code, params, loopvals, qd, acc);
-    case 1: return launch_small_t<1536, 4096>(st, items, n, I, code, params, loopvals, qd, acc);
-    default: return launch_small_t<3072, 8192>(st, items, n, I, code, params, loopvals, qd, acc);
+    case 0: return launch_small_t<1024, 2048>(st, items, n, I, code, params, loopvals, qd, acc, done);
+    case 1: return launch_small_t<1536, 4096>(st, items, n, I, code, params, loopvals, qd, acc, done);
+    default: return launch_small_t<3072, 8192>(st, items, n, I, code, params, loopvals, qd, acc, done);
   }
 }
 
@@ -1082,12 +826,12 @@ int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n,
                    const HItem* hitems, const void* insts, const DInsn* code,
                    const int64_t* params, const int64_t* loopvals, QAcc* acc,
                    unsigned char* keys, uint32_t* pids, uint32_t* cursor,
-                   uint32_t* ovf, uint32_t capb) {
+                   uint32_t* ovf, uint32_t capb, const uint32_t* done) {
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
     hipLaunchKernelGGL(k_scatter, dim3(m), dim3(256), 0, st, chunks + off,
                        hitems, (const DevInst*)insts, code, params, loopvals,
-                       acc, keys, pids, cursor, ovf, capb);
+                       acc, keys, pids, cursor, ovf, capb, done);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -1098,12 +842,13 @@ int launch_bucket(int cfg, hipStream_t st, uint32_t nb, uint32_t base,
                   const void* insts, const DInsn* code, const int64_t* params,
                   const int64_t* loopvals, const QDesc* qd, QAcc* acc,
                   const unsigned char* keys, const uint32_t* pids,
-                  const uint32_t* cursor, const uint32_t* ovf) {
+                  const uint32_t* cursor, const uint32_t* ovf,
+                  const uint32_t* done, const u64* l0keys, const u64* l0cnt) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_bucket_t<1024, 2048>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, keys, pids, cursor, ovf);
-    case 1: return launch_bucket_t<1536, 4096>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, keys, pids, cursor, ovf);
-    default: return launch_bucket_t<3072, 8192>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, keys, pids, cursor, ovf);
+    case 0: return launch_bucket_t<1024, 2048>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, keys, pids, cursor, ovf, done, l0keys, l0cnt);
+    case 1: return launch_bucket_t<1536, 4096>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, keys, pids, cursor, ovf, done, l0keys, l0cnt);
+    default: return launch_bucket_t<3072, 8192>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, keys, pids, cursor, ovf, done, l0keys, l0cnt);
   }
 }
 
@@ -1168,6 +913,36 @@ int launch_witness2(hipStream_t st, const void* items, uint32_t n,
 }
 
 size_t w2item_size() { return sizeof(W2Item); }
+
+int launch_level0(hipStream_t st, const Chunk* chunks, uint32_t n,
+                  const L0Item* items, const void* insts, const DInsn* code,
+                  const int64_t* params, const int64_t* loopvals, u64* keys,
+                  u64* cnt, u64* s0) {
+  for (uint32_t off = 0; off < n; off += 1u << 20) {
+    uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
+    hipLaunchKernelGGL(k_level0, dim3(m), dim3(256), 0, st, chunks + off, items,
+                       (const DevInst*)insts, code, params, loopvals, keys, cnt,
+                       s0);
+    HGRD_CHECK(hipGetLastError());
+  }
+  return 0;
+}
+
+int launch_apply_s0(hipStream_t st, uint32_t n, const L0Item* items,
+                    const u64* s0, const uint32_t* skip, QAcc* acc) {
+  if (!n) return 0;
+  hipLaunchKernelGGL(k_apply_s0, dim3((n + 255) / 256), dim3(256), 0, st, n,
+                     items, s0, skip, acc);
+  HGRD_CHECK(hipGetLastError());
+  return 0;
+}
+
+int launch_fill_u64(hipStream_t st, u64* p, u64 n, u64 v) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  HGRD_CHECK(hipGetLastError());
+  return 0;
+}
 
 int launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t n, uint32_t v) {
   if (n == 0) return 0;

@@ -28,18 +28,29 @@ size_t w2item_size();
 
 int launch_small(int cfg, hipStream_t st, const SItem* items, uint32_t n,
                  const void* insts, const DInsn* code, const int64_t* params,
-                 const int64_t* loopvals, const QDesc* qd, QAcc* acc);
+                 const int64_t* loopvals, const QDesc* qd, QAcc* acc,
+                 const uint32_t* done);
 int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n,
                    const HItem* hitems, const void* insts, const DInsn* code,
                    const int64_t* params, const int64_t* loopvals, QAcc* acc,
                    unsigned char* keys, uint32_t* pids, uint32_t* cursor,
-                   uint32_t* ovf, uint32_t capb);
+                   uint32_t* ovf, uint32_t capb, const uint32_t* done);
 int launch_bucket(int cfg, hipStream_t st, uint32_t nb, uint32_t base,
                   const uint32_t* bucket_item, const HItem* hitems,
                   const void* insts, const DInsn* code, const int64_t* params,
                   const int64_t* loopvals, const QDesc* qd, QAcc* acc,
                   const unsigned char* keys, const uint32_t* pids,
-                  const uint32_t* cursor, const uint32_t* ovf);
+                  const uint32_t* cursor, const uint32_t* ovf,
+                  const uint32_t* done, const unsigned long long* l0keys,
+                  const unsigned long long* l0cnt);
+int launch_level0(hipStream_t st, const Chunk* chunks, uint32_t n,
+                  const L0Item* items, const void* insts, const DInsn* code,
+                  const int64_t* params, const int64_t* loopvals,
+                  unsigned long long* keys, unsigned long long* cnt,
+                  unsigned long long* s0);
+int launch_apply_s0(hipStream_t st, uint32_t n, const L0Item* items,
+                    const unsigned long long* s0, const uint32_t* skip,
+                    QAcc* acc);
 int launch_fallback(hipStream_t st, const Chunk* chunks, uint32_t nchunks,
                     const FItem* fitems, uint32_t nitems, uint32_t used_levels,
                     const void* insts, const DInsn* code, const int64_t* params,
@@ -55,5 +66,40 @@ int launch_finalize(hipStream_t st, uint32_t n, const QAcc* acc,
                     const QDesc* qd, const uint32_t* host_err,
                     const uint8_t* trivial, const unsigned long long* evals,
                     rd_pair_result* out);
+
+int launch_fill_u64(hipStream_t st, unsigned long long* p, unsigned long long n,
+                    unsigned long long v);
+
+// VERDICT mode and the tile-scoring network (hgrd_verdict.hip)
+int launch_block_bounds(hipStream_t st, const BItem* items, uint32_t n,
+                        const void* insts, const DInsn* code,
+                        const int64_t* params, const int64_t* loopvals,
+                        QAcc* acc, BBound* out);
+int launch_vq_span(hipStream_t st, VQuery* vq, uint32_t n, const BBound* bb);
+int launch_tile_scores(hipStream_t st, const TChunk* chunks, uint32_t n,
+                       const VQuery* vq, const BBound* bb, const float* w,
+                       uint32_t use_mlp, float* scores);
+int launch_tile_features(hipStream_t st, const TChunk* chunks, uint32_t n,
+                         const VQuery* vq, const BBound* bb, float* feats);
+int launch_topk(hipStream_t st, const VQuery* vq, uint32_t nvq,
+                const float* scores, uint32_t K, uint32_t max_tiles,
+                uint32_t* order);
+int launch_tile_join(int cfg, hipStream_t st, const TItem* items, uint32_t item0,
+                     uint32_t n, const VQuery* vq, const uint32_t* order,
+                     uint32_t K, const void* insts, const DInsn* code,
+                     const int64_t* params, const int64_t* loopvals,
+                     const QDesc* qd, uint32_t* done, TOut* tout,
+                     unsigned long long* claim);
+int launch_verdict_commit(hipStream_t st, uint32_t n,
+                          const unsigned long long* claim, const TOut* tout,
+                          QAcc* acc, uint32_t* done);
+int launch_mlp_forward(hipStream_t st, const float* X, unsigned long long n,
+                       const float* w, float* out);
+int launch_mlp_grad(hipStream_t st, const float* X, const float* Y,
+                    unsigned long long n, const float* w, float* grad,
+                    float* loss);
+int launch_adam(hipStream_t st, float* w, float* g, float* m, float* v,
+                float lr, int t);
+int mlp_num_weights();
 
 }  // namespace hgrd

@@ -120,6 +120,29 @@ def test_heavy_hitter_fallback(hg):
     run_both(hg, wl, "heavy")
 
 
+def test_skew_paths(hg):
+    """Hot addresses at three scales: groups that fit after re-bucketing,
+    groups that only fit once split by (address, block) with level 0
+    counted per address, and (address, block) groups too big for any tile
+    (HBM aggregation)."""
+    m = Model(1, [Array(GLOBAL, 32), Array(SHARED, 32)],
+              [Access(0, WRITE, tid() % 8, loops=[0]),                 # split
+               Access(0, READ, tid() % 8 + loop(0) * 0, loops=[0]),
+               Access(0, WRITE, tid() // 32 + bid() * 0, loops=[0]),    # split
+               Access(0, WRITE, c(0) + loop(0) * 0, loops=[0]),          # fallback
+               Access(0, WRITE, tid() + bid() * 64 + loop(0), loops=[0]),  # retry
+               Access(1, WRITE, tid() % 2 + loop(0), loops=[0])],       # shared
+              Launch((param(0), 1, 1), (256, 1, 1), 32), [[96], [40]],
+              loops=[Loop(0, "lt", 12)])
+    pairs = [(0, 0, 0, 7), (0, 0, 1, 7), (0, 2, 2, 7), (0, 3, 3, 7), (0, 3, 0, 7),
+             (0, 4, 4, 7), (0, 4, 0, 7), (0, 5, 5, 7), (0, 0, 1, 1), (0, 2, 2, 6)]
+    run_both(hg, Workload([m], pairs), "skew")
+    import paper_2604_02106_amd as H
+    st = H.default_context().stats()
+    say("skew stats", {k: st[k] for k in ("retry_items", "split_items", "overflow_items")})
+    assert st["split_items"] > 0 and st["overflow_items"] > 0
+
+
 def test_statuses(hg):
     ms = []
 

@@ -38,7 +38,8 @@ def test_struct_sizes():
     assert C.sizeof(hg.rd_pair_result) == 88
     assert C.sizeof(hg.rd_insn) == 16
     assert C.sizeof(hg.rd_access) == 64
-    assert C.sizeof(hg.rd_options) == 40
+    assert C.sizeof(hg.rd_options) == 48
+    assert C.sizeof(hg.rd_mlp) == 4 * 6337
 
 
 def test_no_device_fails_loudly():

@@ -227,3 +227,85 @@ def batched(seed=2002, n_models=256, pairs_per_model=16, max_grid=1024,
                             name="batched%d" % mi))
     return Workload(models, pairs, name="batched",
                     meta={"seed": seed, "scale": scale})
+
+
+# ---------------------------------------------------------------------------
+# race-free throughput stress: 128 pairs, 2^30 points per access, int64
+
+def stress(seed=3003, n_pairs=128, grid=1 << 16, block=256, iters=64):
+    """128 write/write or write/read pairs on 64-bit global arrays, each
+    access with grid * block * iters points (2^16 * 256 * 64 = 2^30 by
+    default), race-free by construction, no early exit possible:
+
+      * strided-disjoint: A_i = base + 2 f, A_j = base + 2 f + 1 with
+        f = (global thread id) * iters + i injective: one side even, the
+        other odd, every address one away from an address of the other side;
+      * blocked-disjoint: with K = block * iters, A_i covers
+        [base + 2Kb, base + 2Kb + K) and A_j [base + 2Kb + K, base + 2K(b+1))
+        for block b: adjacent ranges, edges one element apart.
+
+    Bases are >= 2^40.  Every pair's verdict is 0 and count 0 by
+    construction.
+    """
+    rng = _rng(seed)
+    B, I = block, iters
+    K = B * I
+    g = bid(0) * bdim(0) + tid(0)
+    f = g * I + loop(0)
+    accs, pairs = [], []
+    for p in range(n_pairs):
+        base = (1 << 40) + int(rng.integers(0, 1 << 20)) * (1 << 24)
+        kind_b = WRITE if rng.random() < 0.5 else READ
+        if p % 2 == 0:
+            ea = c(base) + f * 2
+            eb = c(base) + f * 2 + 1
+        else:
+            ea = c(base) + bid(0) * (2 * K) + tid(0) * I + loop(0)
+            eb = c(base) + bid(0) * (2 * K) + K + tid(0) * I + loop(0)
+        accs.append(Access(0, WRITE, ea, None, [0], name="stress a%d" % p))
+        accs.append(Access(0, kind_b, eb, None, [0], name="stress b%d" % p))
+        pairs.append((0, 2 * p, 2 * p + 1, ALL_CLASSES))
+    m = Model(0, [Array(GLOBAL, 64)], accs, Launch((grid, 1, 1), (B, 1, 1), 32),
+              [[]], loops=[Loop(0, "lt", I, "add", 1)], name="stress")
+    return Workload([m], pairs, name="stress",
+                    meta={"seed": seed, "race_free": True,
+                          "points_per_access": grid * B * I})
+
+
+# ---------------------------------------------------------------------------
+# sparse witnesses: one conflicting block pair out of G*G
+
+def sparse(seed=4004, n_queries=16384, G=256, B=256, racy_frac=0.5,
+           queries_per_model=64):
+    """Queries whose only conflicts sit in a single (block of a, block of b)
+    pair out of G * G: access a writes base + g, access b writes
+    base + g + D + K * (bid != c_b) with g the global thread id; K moves
+    every block of b except block c_b far away, and D shifts block c_b so
+    that it lands on block c_a of a (D = B * (c_a - c_b)).  Race-free
+    queries use D = G * B (a near miss: one past a's range), so no block
+    pair meets.  Global int32 arrays, one tuple, no loops.
+    """
+    rng = _rng(seed)
+    models, pairs = [], []
+    for q0 in range(0, n_queries, queries_per_model):
+        accs = []
+        nq = min(queries_per_model, n_queries - q0)
+        for k in range(nq):
+            racy = rng.random() < racy_frac
+            ca = int(rng.integers(0, G))
+            cb = int(rng.integers(0, G))
+            if cb == ca:  # same block, same thread: would not conflict
+                cb = (ca + 1) % G
+            base = int(rng.integers(0, 1 << 20)) * 4
+            Kf = 4 * G * B
+            g = bid(0) * bdim(0) + tid(0)
+            D = B * (ca - cb) if racy else G * B
+            ea = c(base) + g
+            eb = c(base) + g + D + c(Kf) * ne(bid(0), cb)
+            accs.append(Access(0, WRITE, ea, name="sparse a"))
+            accs.append(Access(0, WRITE, eb, name="sparse b"))
+            pairs.append((len(models), 2 * k, 2 * k + 1, ALL_CLASSES))
+        models.append(Model(0, [Array(GLOBAL, 32)], accs,
+                            Launch((G, 1, 1), (B, 1, 1), 32), [[]],
+                            name="sparse%d" % len(models)))
+    return Workload(models, pairs, name="sparse", meta={"seed": seed, "G": G})
