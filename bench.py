@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB three times "
+                         "(the reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported "
@@ -69,6 +72,15 @@ def main():
               "notes)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.int32, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 3 x %d bytes" % (src.numel() * 4))
+        return
     import paper_2604_02106_amd as hg
     from workloads import configs
     assert torch.cuda.is_available()

@@ -174,14 +174,18 @@ typedef struct {
   uint32_t order;      /* VERDICT tile order: RD_ORDER_LEX or RD_ORDER_MLP */
   uint32_t batched;    /* reserved; 0 */
   uint32_t log_level;  /* 0 silent, 1 summary, 2 per-launch (stderr) */
-  uint32_t lds_cap;    /* records per LDS join tile; 0 = autotuned */
+  uint32_t lds_cap;    /* records per LDS join tile (1024, 1536 or 3072);
+                          0 = the context's default (1536 until
+                          rd_autotune picks one) */
   uint32_t tile_budget;/* VERDICT: tiles searched per (pair, tuple) before
                           the exact path; 0 = 256 */
   const rd_mlp* mlp;   /* weights for RD_ORDER_MLP (copied at prepare) */
   uint64_t max_device_bytes; /* HBM bucket bytes per partition wave;
-                                0 = library default (96 MiB, sized to stay
-                                in the last-level cache) */
-  void* stream;        /* hipStream_t; NULL = null stream */
+                                0 = the context's default (96 MiB, sized
+                                to stay in the last-level cache, until
+                                rd_autotune picks one) */
+  void* stream;        /* hipStream_t every launch goes to; NULL = a
+                          stream the context owns */
 } rd_options;
 
 /* ---- results ----------------------------------------------------------
@@ -238,6 +242,27 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
                rd_plan** plan);
 int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out);
 void rd_plan_destroy(rd_plan* plan);
+
+/* The first phase of rd_execute (accumulator set-up, the VERDICT tile
+ * search, the LDS joins of small items and the HBM partition waves) has no
+ * host round trip; the first rd_execute of a plan captures it in a HIP
+ * graph and later calls replay that graph (log_level 2 or the environment
+ * variable HGRD_TIMING run it eagerly with per-kernel timing).  Calls on one
+ * plan must not overlap. */
+
+/* Batch autotuning: for the batch given (as rd_prepare), times rd_execute
+ * for every LDS tile shape (1024, 1536, 3072 records) and partition-wave
+ * size (48, 96, 192 MiB): one warm-up and `reps` timed runs each (1..16),
+ * median wall time.  The fastest pair becomes the context's default for
+ * plans whose options leave lds_cap and max_device_bytes at 0.  *best is a
+ * copy of opt (or of zeroed options) with those two fields set; *best_ms
+ * its median time (may be NULL).  Returns RD_EINVAL for a NULL ctx or
+ * best, else the first non-OK status of rd_prepare or rd_execute. */
+int rd_autotune(rd_context* ctx, const rd_kernel_model* models,
+                uint32_t n_models, const rd_access_pair* pairs,
+                uint32_t n_pairs, const rd_launch_domain* launch,
+                const rd_param_sets* params, const rd_options* opt,
+                uint32_t reps, rd_options* best, double* best_ms);
 
 /* Timing and size figures of the last rd_execute (or rd_check_pairs). */
 typedef struct {
@@ -310,6 +335,19 @@ const char* rd_strerror(int status);
 /* Host-side self-checks of the library's integer helpers (no device work).
  * Returns 0 when they pass. */
 int rd_selftest(void);
+
+/* Host-side check of the term-table lowering of one access under one
+ * parameter tuple (no device work): builds the tables as the device would,
+ * then compares guard, address and interval ids at every point of the
+ * launch box (or at max_points points spread over it when max_points is
+ * nonzero and smaller) with the interpreter on the original expressions.
+ * Returns 0 when they agree (*n_checked = points compared), 1 when the
+ * access does not qualify for tables, 2 when it has an error or no points,
+ * a negative value on a disagreement, RD_EINVAL on bad indices. */
+int rd_table_selftest(const rd_kernel_model* models, uint32_t n_models,
+                      const rd_launch_domain* launch, const rd_param_sets* params,
+                      uint32_t model, uint32_t access, uint32_t set,
+                      uint64_t max_points, uint64_t* n_checked);
 
 #ifdef __cplusplus
 }

@@ -122,7 +122,7 @@ assert C.sizeof(rd_pair_result) == 88
 EXPORTS = ("rd_context_create", "rd_context_destroy", "rd_check_pairs",
            "rd_prepare", "rd_execute", "rd_plan_destroy", "rd_get_stats",
            "rd_strerror", "rd_selftest", "rd_tile_data", "rd_mlp_forward",
-           "rd_mlp_grad", "rd_mlp_train")
+           "rd_mlp_grad", "rd_mlp_train", "rd_autotune", "rd_table_selftest")
 
 _lib = None
 
@@ -151,6 +151,12 @@ def lib():
             C.POINTER(rd_access_pair), C.c_uint32, C.POINTER(rd_launch_domain),
             C.POINTER(rd_param_sets), C.POINTER(rd_options),
             C.POINTER(C.c_void_p)]
+        L.rd_autotune.restype = C.c_int
+        L.rd_autotune.argtypes = [
+            C.c_void_p, C.POINTER(rd_kernel_model), C.c_uint32,
+            C.POINTER(rd_access_pair), C.c_uint32, C.POINTER(rd_launch_domain),
+            C.POINTER(rd_param_sets), C.POINTER(rd_options), C.c_uint32,
+            C.POINTER(rd_options), C.POINTER(C.c_double)]
         L.rd_execute.restype = C.c_int
         L.rd_execute.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(rd_pair_result)]
         L.rd_plan_destroy.restype = None
@@ -171,6 +177,11 @@ def lib():
         L.rd_mlp_train.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_uint64, C.c_uint32, C.c_uint32, C.c_float,
                                    C.c_uint64, C.c_void_p, C.c_void_p]
+        L.rd_table_selftest.restype = C.c_int
+        L.rd_table_selftest.argtypes = [
+            C.POINTER(rd_kernel_model), C.c_uint32, C.POINTER(rd_launch_domain),
+            C.POINTER(rd_param_sets), C.c_uint32, C.c_uint32, C.c_uint32,
+            C.c_uint64, C.POINTER(C.c_uint64)]
         L.rd_selftest.restype = C.c_int
         L.rd_selftest.argtypes = []
         L.rd_get_stats.restype = C.c_int
@@ -369,6 +380,33 @@ def rd_check_pairs(ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
     if st != RD_OK:
         raise RuntimeError("rd_check_pairs failed: %s" % rd_strerror(st))
     return [result_dict(out[k]) for k in range(n)]
+
+
+def rd_autotune(ctx, workload, reps=3, mode=MODE_EXACT, order=ORDER_LEX,
+                stream=None, mlp=None, tile_budget=0):
+    """Times the batch for every tile shape and wave size and makes the
+    fastest the context's default.  Returns (lds_cap, max_device_bytes,
+    median ms)."""
+    pk = Packed(workload)
+    pairs = _pairs(workload)
+    opt, keep = _options(mode, order, 0, 0, 0, stream, mlp, tile_budget)
+    best = rd_options()
+    ms = C.c_double()
+    st = lib().rd_autotune(ctx.h, pk.models, pk.n_models, pairs, len(workload.pairs),
+                           pk.launch, pk.params, C.byref(opt), reps,
+                           C.byref(best), C.byref(ms))
+    if st != RD_OK:
+        raise RuntimeError("rd_autotune failed: %s" % rd_strerror(st))
+    return best.lds_cap, best.max_device_bytes, ms.value
+
+
+def table_selftest(workload, model, access, tuple_index, max_points=0, packed=None):
+    """rd_table_selftest: (status, points compared).  Host only."""
+    pk = packed or Packed(workload)
+    n = C.c_uint64()
+    st = lib().rd_table_selftest(pk.models, pk.n_models, pk.launch, pk.params,
+                                 model, access, tuple_index, max_points, C.byref(n))
+    return st, n.value
 
 
 def result_dict(r):

@@ -51,14 +51,21 @@ __device__ __forceinline__ int64_t alu(uint8_t op, int64_t a, int64_t b,
       if (__builtin_sub_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
       return r;
     case D_MUL:
+      // both operands in int32: the product fits int64 (one 32x32 multiply)
+      if ((uint64_t)a + 0x80000000ull < 0x100000000ull &&
+          (uint64_t)b + 0x80000000ull < 0x100000000ull)
+        return (int64_t)(int32_t)a * (int64_t)(int32_t)b;
       if (__builtin_mul_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
       return r;
     case D_DIV:
       if (b == 0) { err |= ERR_DIVZERO; return 0; }
+      // both operands in [0, 2^31): a 32-bit unsigned division
+      if (((uint64_t)(a | b) >> 31) == 0) return (int64_t)((uint32_t)a / (uint32_t)b);
       if (a == INT64_MIN && b == -1) { err |= ERR_RANGE; return 0; }
       return a / b;
     case D_MOD:
       if (b == 0) { err |= ERR_DIVZERO; return 0; }
+      if (((uint64_t)(a | b) >> 31) == 0) return (int64_t)((uint32_t)a % (uint32_t)b);
       if (a == INT64_MIN && b == -1) { err |= ERR_RANGE; return 0; }
       return a % b;
     case D_SHL: {
@@ -117,6 +124,11 @@ struct DevInst {
   AccInst a;
   FastDiv f_nthr, f_niota, f_gx, f_gxy, f_bx, f_bxy;
   FastDiv f_loop[4];
+  // term tables (tab != 0), see TabHost
+  const int64_t* tpool;
+  int64_t tu;
+  uint32_t toff[3];
+  uint32_t iv_off, iv_const, tnever, tab, tpad;
 };
 
 // Runs one compiled expression.  `code`, `p`, `params` and `dims` are
@@ -219,6 +231,68 @@ __device__ __forceinline__ bool eval_point(const DevInst& I,
   pt.bint = (uint32_t)bi & 0xFFFF;
   pt.wint = (uint32_t)wi & 0xFFFF;
   return e == 0;
+}
+
+// Guard, address and interval ids of one point: table lookups when the
+// instance has term tables, else the interpreter.
+__device__ __forceinline__ bool point_eval(const DevInst& I, const PointIds& id,
+                                           const DInsn* __restrict__ code,
+                                           const int64_t* __restrict__ params,
+                                           const int64_t* __restrict__ loopvals,
+                                           Point& pt, uint32_t& err) {
+  if (I.tab) {
+    if (I.tnever) return false;
+    int64_t a = I.tu;
+    if (I.toff[0] != kNoTab) {
+      const int64_t v = I.tpool[I.toff[0] + id.blin];
+      if (v == INT64_MIN) return false;
+      a += v;
+    }
+    if (I.toff[1] != kNoTab) {
+      const int64_t v = I.tpool[I.toff[1] + id.tlin];
+      if (v == INT64_MIN) return false;
+      a += v;
+    }
+    if (I.toff[2] != kNoTab) {
+      const int64_t v = I.tpool[I.toff[2] + id.ilin];
+      if (v == INT64_MIN) return false;
+      a += v;
+    }
+    const uint32_t iv =
+        I.iv_off != kNoTab ? (uint32_t)I.tpool[I.iv_off + id.ilin] : I.iv_const;
+    pt.addr = a;
+    pt.bint = iv & 0xFFFF;
+    pt.wint = iv >> 16;
+    return true;
+  }
+  Regs R;
+  set_coords(I, id, loopvals, R);
+  return eval_point(I, code, params, R, pt, err);
+}
+
+// Interval ids of a point already known to be present.
+__device__ __forceinline__ void point_iv(const DevInst& I, const PointIds& id,
+                                         const DInsn* __restrict__ code,
+                                         const int64_t* __restrict__ params,
+                                         const int64_t* __restrict__ loopvals,
+                                         uint32_t& bi, uint32_t& wi) {
+  if (I.tab) {
+    const uint32_t iv =
+        I.iv_off != kNoTab ? (uint32_t)I.tpool[I.iv_off + id.ilin] : I.iv_const;
+    bi = iv & 0xFFFF;
+    wi = iv >> 16;
+    return;
+  }
+  if (I.a.bint.absent && I.a.wint.absent) {
+    bi = wi = 0;
+    return;
+  }
+  Regs R;
+  set_coords(I, id, loopvals, R);
+  const int64_t* pr = params + I.a.params_off;
+  uint32_t e = 0;
+  bi = (uint32_t)run_prog(code, I.a.bint, R, pr, 0, e) & 0xFFFF;
+  wi = (uint32_t)run_prog(code, I.a.wint, R, pr, 0, e) & 0xFFFF;
 }
 
 __device__ __forceinline__ void load_inst(DevInst& D,

@@ -41,9 +41,11 @@ constexpr uint32_t kMaxSets = 4096;
 constexpr int64_t kMaxBlock = 1024;
 constexpr int64_t kMaxGrid = 1ll << 26;
 constexpr int64_t kMaxPoints = 1ll << 31;
-constexpr uint32_t kChunkPts = 8192;
+constexpr uint32_t kChunkPts = 1024;
 constexpr uint64_t kWaveBytes = 96ull << 20;
 constexpr uint64_t kFallbackRecords = 256ull << 20;
+constexpr uint64_t kMaxTabInst = 1ull << 24;  // table entries per instance
+constexpr uint64_t kMaxTabPool = 1ull << 28;  // table entries per plan
 
 // ---------------------------------------------------------------------------
 // checked int64 arithmetic on the host (errors yield 0, evaluation goes on)
@@ -320,6 +322,9 @@ struct rd_context {
   std::map<std::string, DevBuf> bufs;
   rd_stats stats;
   int cfg = 1;
+  uint32_t n_cu = 256;
+  uint64_t wave_bytes = kWaveBytes;  // default partition wave size
+  hipStream_t stream = nullptr;  // used when the caller passes no stream
   hipEvent_t ev[16];
   void* ensure(const char* name, size_t bytes, int* err) {
     DevBuf& b = bufs[name];
@@ -346,6 +351,341 @@ struct rd_context {
 namespace {
 
 // Per (model, tuple): launch extents.
+// ---------------------------------------------------------------------------
+// Term tables (lowering of one access under one tuple).
+//
+// An expression qualifies when interval bounds over the launch box prove
+// that no operation in it can fail (overflow, zero divisor, shift count,
+// INT64_MIN / -1), so the interpreter would never flag an error for it.
+// It is then rewritten, in exact integer arithmetic, as a uniform constant
+// plus a sum of terms that each depend on one coordinate group only (block
+// ids, thread ids or loop values): sums and differences split, products
+// and left shifts by uniform values distribute, and a truncating division
+// or remainder by a positive uniform d splits when every term but those of
+// one group is a multiple of d and both parts are non-negative.  Each
+// group's terms are tabulated over the group's linear index.
+
+using i128 = __int128;
+constexpr i128 kI64Lo = INT64_MIN, kI64Hi = INT64_MAX;
+
+struct TNode {
+  uint16_t op = 0, arg = 0;
+  int64_t imm = 0;
+  int kid[2] = {-1, -1};
+  uint32_t start = 0;   // first postfix index of the subtree
+  uint8_t groups = 0;   // bit 0 blocks, bit 1 threads, bit 2 loop values
+  int64_t val = 0;      // value of a uniform node
+  i128 lo = 0, hi = 0;  // value range over the box
+};
+
+inline bool fits64(i128 v) { return v >= kI64Lo && v <= kI64Hi; }
+inline i128 i128abs(i128 v) { return v < 0 ? -v : v; }
+
+// Range of `op` over operand ranges; false if the operation may fail.
+bool range_op(uint16_t op, i128 al, i128 ah, i128 bl, i128 bh, i128& lo, i128& hi) {
+  auto corners = [&](i128 c0, i128 c1, i128 c2, i128 c3) {
+    lo = std::min(std::min(c0, c1), std::min(c2, c3));
+    hi = std::max(std::max(c0, c1), std::max(c2, c3));
+  };
+  switch (op) {
+    case RD_OP_ADD: lo = al + bl; hi = ah + bh; return fits64(lo) && fits64(hi);
+    case RD_OP_SUB: lo = al - bh; hi = ah - bl; return fits64(lo) && fits64(hi);
+    case RD_OP_MUL:
+      corners(al * bl, al * bh, ah * bl, ah * bh);
+      return fits64(lo) && fits64(hi);
+    case RD_OP_DIV:
+      if (bl <= 0 && bh >= 0) return false;
+      if (al == kI64Lo && bl <= -1 && bh >= -1) return false;
+      corners(al / bl, al / bh, ah / bl, ah / bh);
+      return true;
+    case RD_OP_MOD: {
+      if (bl <= 0 && bh >= 0) return false;
+      if (al == kI64Lo && bl <= -1 && bh >= -1) return false;
+      const i128 m = std::max(i128abs(bl), i128abs(bh)) - 1;
+      lo = al >= 0 ? 0 : std::max(al, -m);
+      hi = ah <= 0 ? 0 : std::min(ah, m);
+      return true;
+    }
+    case RD_OP_SHL:
+      if (bl < 0 || bh > 63) return false;
+      corners(al * ((i128)1 << (int)bl), al * ((i128)1 << (int)bh),
+              ah * ((i128)1 << (int)bl), ah * ((i128)1 << (int)bh));
+      return fits64(lo) && fits64(hi);
+    case RD_OP_SHR:
+      if (bl < 0 || bh > 63) return false;
+      corners(al >> (int)bl, al >> (int)bh, ah >> (int)bl, ah >> (int)bh);
+      return true;
+    case RD_OP_AND:
+    case RD_OP_OR:
+    case RD_OP_XOR:
+      if (al >= 0 && bl >= 0) {
+        i128 m = std::max(ah, bh), p = 1;
+        while (p <= m) p <<= 1;
+        lo = 0;
+        hi = op == RD_OP_AND ? std::min(ah, bh) : p - 1;
+      } else {
+        lo = kI64Lo;
+        hi = kI64Hi;
+      }
+      return true;
+    case RD_OP_MIN: lo = std::min(al, bl); hi = std::min(ah, bh); return true;
+    case RD_OP_MAX: lo = std::max(al, bl); hi = std::max(ah, bh); return true;
+    default: lo = 0; hi = 1; return true;  // comparisons and logic
+  }
+}
+
+// One term: value of `code` (in [lo, hi]) times `mult`, of group `group`.
+struct STerm {
+  std::vector<rd_insn> code;
+  int64_t mult = 1;
+  i128 lo = 0, hi = 0;
+  int group = 0;
+};
+
+struct Lin {
+  i128 u = 0;
+  std::vector<STerm> terms;
+};
+
+inline i128 contrib_lo(const STerm& t) { return std::min(t.lo * t.mult, t.hi * t.mult); }
+inline i128 contrib_hi(const STerm& t) { return std::max(t.lo * t.mult, t.hi * t.mult); }
+inline i128 contrib_abs(const STerm& t) {
+  return std::max(i128abs(t.lo), i128abs(t.hi)) * i128abs((i128)t.mult);
+}
+
+inline rd_insn mk_insn(uint16_t op, int64_t imm = 0, uint16_t arg = 0) {
+  rd_insn t;
+  memset(&t, 0, sizeof t);
+  t.op = op;
+  t.arg = arg;
+  t.imm = imm;
+  return t;
+}
+
+struct TermBuilder {
+  const rd_kernel_model& M;
+  const rd_access& A;
+  const int64_t* pv;
+  const int64_t* dims;
+  const int64_t* lmin;
+  const int64_t* lmax;
+  std::vector<TNode> nodes;
+  const rd_insn* ins = nullptr;
+
+  // Builds the tree of `e` with groups, uniform values and ranges; false if
+  // some operation may fail anywhere in the box.
+  bool build(rd_expr e) {
+    nodes.clear();
+    ins = M.insns + e.first;
+    std::vector<int> st;
+    for (uint32_t k = 0; k < e.count; ++k) {
+      const rd_insn& t = ins[k];
+      TNode n;
+      n.op = t.op;
+      n.arg = t.arg;
+      n.imm = t.imm;
+      n.start = k;
+      if (is_leaf(t.op)) {
+        switch (t.op) {
+          case RD_OP_CONST: n.val = t.imm; break;
+          case RD_OP_PARAM: n.val = pv[t.arg]; break;
+          case RD_OP_GDIM: n.val = dims[t.arg]; break;
+          case RD_OP_BDIM: n.val = dims[3 + t.arg]; break;
+          case RD_OP_TID: n.groups = 2; n.lo = 0; n.hi = dims[3 + t.arg] - 1; break;
+          case RD_OP_BID: n.groups = 1; n.lo = 0; n.hi = dims[t.arg] - 1; break;
+          case RD_OP_LOOP: {
+            const int p = loop_pos(&A, t.arg);
+            n.groups = 4;
+            n.lo = lmin[p];
+            n.hi = lmax[p];
+            break;
+          }
+        }
+        if (n.groups == 0) n.lo = n.hi = n.val;
+      } else if (is_unary(t.op)) {
+        const TNode& c = nodes[st.back()];
+        n.kid[0] = st.back();
+        st.pop_back();
+        n.start = c.start;
+        n.groups = c.groups;
+        if (t.op == RD_OP_NEG) {
+          if (c.lo == kI64Lo) return false;
+          n.lo = -c.hi;
+          n.hi = -c.lo;
+        } else {
+          n.lo = 0;
+          n.hi = 1;
+        }
+        if (!n.groups) {
+          n.val = t.op == RD_OP_NEG ? -c.val : (c.val == 0);
+          n.lo = n.hi = n.val;
+        }
+      } else {
+        n.kid[1] = st.back();
+        st.pop_back();
+        n.kid[0] = st.back();
+        st.pop_back();
+        const TNode& a = nodes[n.kid[0]];
+        const TNode& b = nodes[n.kid[1]];
+        n.start = a.start;
+        n.groups = a.groups | b.groups;
+        if (!n.groups) {
+          uint32_t err = 0;
+          n.val = hop(t.op, a.val, b.val, err);
+          if (err) return false;
+          n.lo = n.hi = n.val;
+        } else if (!range_op(t.op, a.lo, a.hi, b.lo, b.hi, n.lo, n.hi)) {
+          return false;
+        }
+      }
+      st.push_back((int)nodes.size());
+      nodes.push_back(n);
+    }
+    return true;
+  }
+
+  void subtree(int i, std::vector<rd_insn>& out) const {
+    const TNode& n = nodes[i];
+    uint32_t end = (uint32_t)i;  // node index == its postfix position
+    for (uint32_t k = n.start; k <= end; ++k) out.push_back(ins[k]);
+  }
+
+  static bool single(uint8_t g) { return g == 1 || g == 2 || g == 4; }
+  static int gidx(uint8_t g) { return g == 1 ? 0 : g == 2 ? 1 : 2; }
+
+  bool add_term(Lin& L, std::vector<rd_insn>&& code, i128 lo, i128 hi, int group, i128 mu) {
+    if (!fits64(mu)) return false;
+    if (mu == 0) return true;
+    STerm t;
+    t.code = std::move(code);
+    t.mult = (int64_t)mu;
+    t.lo = lo;
+    t.hi = hi;
+    t.group = group;
+    if (!fits64(contrib_abs(t))) return false;
+    L.terms.push_back(std::move(t));
+    return true;
+  }
+
+  // Postfix of sum(term * mult) + u over `ts` (at least one term or u).
+  static void emit_sum(const std::vector<const STerm*>& ts, i128 u, std::vector<rd_insn>& out) {
+    bool first = true;
+    for (const STerm* t : ts) {
+      out.insert(out.end(), t->code.begin(), t->code.end());
+      if (t->mult != 1) {
+        out.push_back(mk_insn(RD_OP_CONST, t->mult));
+        out.push_back(mk_insn(RD_OP_MUL));
+      }
+      if (!first) out.push_back(mk_insn(RD_OP_ADD));
+      first = false;
+    }
+    if (u != 0 || first) {
+      out.push_back(mk_insn(RD_OP_CONST, (int64_t)u));
+      if (!first) out.push_back(mk_insn(RD_OP_ADD));
+    }
+  }
+
+  bool decompose(int i, Lin& L, i128 mu) {
+    const TNode& n = nodes[i];
+    if (!n.groups) {
+      L.u += mu * (i128)n.val;
+      return fits64(L.u);
+    }
+    if (single(n.groups)) {
+      std::vector<rd_insn> code;
+      subtree(i, code);
+      return add_term(L, std::move(code), n.lo, n.hi, gidx(n.groups), mu);
+    }
+    const TNode* a = n.kid[0] >= 0 ? &nodes[n.kid[0]] : nullptr;
+    const TNode* b = n.kid[1] >= 0 ? &nodes[n.kid[1]] : nullptr;
+    switch (n.op) {
+      case RD_OP_ADD: return decompose(n.kid[0], L, mu) && decompose(n.kid[1], L, mu);
+      case RD_OP_SUB: return decompose(n.kid[0], L, mu) && decompose(n.kid[1], L, -mu);
+      case RD_OP_NEG: return decompose(n.kid[0], L, -mu);
+      case RD_OP_MUL:
+        if (!a->groups) return fits64(mu * a->val) && decompose(n.kid[1], L, mu * a->val);
+        if (!b->groups) return fits64(mu * b->val) && decompose(n.kid[0], L, mu * b->val);
+        return false;
+      case RD_OP_SHL:
+        if (b->groups || b->val < 0 || b->val > 62) return false;
+        return fits64(mu << (int)b->val) && decompose(n.kid[0], L, mu << (int)b->val);
+      case RD_OP_DIV:
+      case RD_OP_MOD: {
+        if (b->groups || b->val <= 0) return false;
+        const int64_t d = b->val;
+        Lin in;
+        if (!decompose(n.kid[0], in, 1)) return false;
+        std::vector<const STerm*> xs, ys;
+        i128 xlo = 0, ylo = in.u, yhi = in.u;
+        int yg = -1;
+        for (const STerm& t : in.terms) {
+          if (t.mult % d == 0) {
+            xs.push_back(&t);
+            xlo += contrib_lo(t);
+          } else {
+            if (yg >= 0 && yg != t.group) return false;
+            yg = t.group;
+            ys.push_back(&t);
+            ylo += contrib_lo(t);
+            yhi += contrib_hi(t);
+          }
+        }
+        if (xlo < 0 || ylo < 0) return false;
+        i128 yabs = i128abs(in.u);
+        for (const STerm* t : ys) yabs += contrib_abs(*t);
+        if (yabs > kI64Hi) return false;
+        if (n.op == RD_OP_DIV)
+          for (const STerm* t : xs) {
+            std::vector<rd_insn> code = t->code;
+            if (!add_term(L, std::move(code), t->lo, t->hi, t->group, mu * (i128)(t->mult / d)))
+              return false;
+          }
+        if (ys.empty()) {  // uniform remainder part
+          L.u += mu * (n.op == RD_OP_DIV ? in.u / d : in.u % d);
+          return fits64(L.u);
+        }
+        std::vector<rd_insn> code;
+        emit_sum(ys, in.u, code);
+        code.push_back(mk_insn(RD_OP_CONST, d));
+        code.push_back(mk_insn(n.op));
+        const i128 lo = n.op == RD_OP_DIV ? ylo / d : 0;
+        const i128 hi = n.op == RD_OP_DIV ? yhi / d : std::min(yhi, (i128)d - 1);
+        return add_term(L, std::move(code), lo, hi, yg, mu);
+      }
+      default:
+        return false;
+    }
+  }
+
+  // Guard as a conjunction of single-group (or uniform) conjuncts.
+  bool conjuncts(int i, std::vector<rd_insn> (&c)[3], bool& never) {
+    const TNode& n = nodes[i];
+    if (n.op == RD_OP_LAND && n.groups && !single(n.groups))
+      return conjuncts(n.kid[0], c, never) && conjuncts(n.kid[1], c, never);
+    if (!n.groups) {
+      if (n.val == 0) never = true;
+      return true;
+    }
+    if (!single(n.groups)) return false;
+    std::vector<rd_insn>& out = c[gidx(n.groups)];
+    const bool first = out.empty();
+    subtree(i, out);
+    if (!first) out.push_back(mk_insn(RD_OP_LAND));
+    return true;
+  }
+};
+
+// Largest stack depth of a postfix sequence.
+uint32_t postfix_depth(const std::vector<rd_insn>& code) {
+  uint32_t d = 0, m = 0;
+  for (const rd_insn& t : code) {
+    if (is_leaf(t.op)) ++d;
+    else if (is_binary(t.op)) --d;
+    m = std::max(m, d);
+  }
+  return m;
+}
+
 struct DimInfo {
   bool done = false;
   uint32_t err = 0;
@@ -381,6 +721,123 @@ struct Planner {
   std::vector<int64_t> pool_params;
   std::vector<int64_t> pool_loops;
   std::vector<AccInst> dev_insts;
+  std::vector<TabHost> tabs;  // per device instance
+  std::vector<TabJob> tjobs;
+  uint64_t tpool = 0;         // table entries
+  bool use_tables = true;
+
+  // Term tables of instance I (access a of model m); T.on = 0 when some
+  // expression does not qualify.
+  void tables_for(uint32_t m, uint32_t a, const AccInst& I, uint32_t inst, TabHost& T) {
+    memset(&T, 0, sizeof T);
+    for (int g = 0; g < 3; ++g) T.off[g] = kNoTab;
+    T.iv_off = kNoTab;
+    if (!use_tables) return;
+    const rd_kernel_model& M = models[m];
+    const rd_access& A = M.acc[a];
+    const int64_t* pv = pool_params.data() + I.params_off;
+    int64_t dims[6], lmin[4] = {0, 0, 0, 0}, lmax[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 6; ++k) dims[k] = I.dims[k];
+    for (uint32_t k = 0; k < I.n_loops; ++k) {
+      const int64_t* v = pool_loops.data() + I.loop_off[k];
+      lmin[k] = *std::min_element(v, v + I.loop_n[k]);
+      lmax[k] = *std::max_element(v, v + I.loop_n[k]);
+    }
+    TermBuilder tb{M, A, pv, dims, lmin, lmax};
+    // address
+    if (!tb.build(A.addr)) return;
+    const i128 root_lo = tb.nodes.back().lo, root_hi = tb.nodes.back().hi;
+    Lin L;
+    if (!tb.decompose((int)tb.nodes.size() - 1, L, 1)) return;
+    i128 tot = i128abs(L.u), lo = L.u, hi = L.u;
+    for (const STerm& t : L.terms) {
+      tot += contrib_abs(t);
+      lo += contrib_lo(t);
+      hi += contrib_hi(t);
+    }
+    if (tot > kI64Hi) return;
+    if (I.is32 && !(root_lo >= INT32_MIN && root_hi <= INT32_MAX) &&
+        !(lo >= INT32_MIN && hi <= INT32_MAX))
+      return;
+    // guard
+    std::vector<rd_insn> conj[3];
+    bool never = false;
+    if (A.guard.count) {
+      if (!tb.build(A.guard)) return;
+      if (!tb.conjuncts((int)tb.nodes.size() - 1, conj, never)) return;
+    }
+    // interval ids
+    int64_t ivc[2] = {0, 0};
+    bool ivtab = false;
+    const rd_expr ive[2] = {A.bint, A.wint};
+    for (int w = 0; w < 2; ++w) {
+      if (!ive[w].count) continue;
+      if (!tb.build(ive[w])) return;
+      const TNode& r = tb.nodes.back();
+      if (r.lo < 0 || r.hi > 65535) return;
+      if (r.groups) ivtab = true;
+      else ivc[w] = r.val;
+    }
+    // programs and table jobs
+    const uint32_t gsize[3] = {I.nblk, I.nthr, I.niota};
+    std::vector<TabJob> jobs;
+    uint64_t entries = 0;
+    if (!never) {
+      rd_kernel_model tm = M;
+      for (int g = 0; g < 3; ++g) {
+        std::vector<const STerm*> ts;
+        for (const STerm& t : L.terms)
+          if (t.group == g) ts.push_back(&t);
+        if (ts.empty() && conj[g].empty()) continue;
+        TabJob J;
+        memset(&J, 0, sizeof J);
+        J.inst = inst;
+        J.group = (uint32_t)g;
+        J.n = gsize[g];
+        J.val.absent = 1;
+        J.guard.absent = 1;
+        if (!ts.empty()) {
+          std::vector<rd_insn> code;
+          TermBuilder::emit_sum(ts, 0, code);
+          if (postfix_depth(code) > (uint32_t)kMaxStack) return;
+          tm.insns = code.data();
+          tm.n_insns = (uint32_t)code.size();
+          J.val = compile(tm, rd_expr{0, (uint32_t)code.size()}, A, this->code);
+        }
+        if (!conj[g].empty()) {
+          if (postfix_depth(conj[g]) > (uint32_t)kMaxStack) return;
+          tm.insns = conj[g].data();
+          tm.n_insns = (uint32_t)conj[g].size();
+          J.guard = compile(tm, rd_expr{0, (uint32_t)conj[g].size()}, A, this->code);
+        }
+        jobs.push_back(J);
+        entries += J.n;
+      }
+      if (ivtab) {
+        TabJob J;
+        memset(&J, 0, sizeof J);
+        J.inst = inst;
+        J.group = 3;
+        J.n = I.niota;
+        J.val.absent = 1;
+        J.guard.absent = 1;
+        jobs.push_back(J);
+        entries += J.n;
+      }
+    }
+    if (entries > kMaxTabInst || tpool + entries > kMaxTabPool) return;
+    for (TabJob& J : jobs) {
+      J.out_off = (uint32_t)tpool;
+      if (J.group < 3) T.off[J.group] = J.out_off;
+      else T.iv_off = J.out_off;
+      tpool += J.n;
+      tjobs.push_back(J);
+    }
+    T.u = (int64_t)L.u;
+    T.iv_const = (uint32_t)ivc[0] | ((uint32_t)ivc[1] << 16);
+    T.never = never;
+    T.on = 1;
+  }
 
   DimInfo& dim(uint32_t m, uint32_t s) {
     DimInfo& d = dims[m][s];
@@ -519,6 +976,9 @@ struct Planner {
     ii.idx = (int32_t)dev_insts.size();
     ii.npts = (uint32_t)box;
     dev_insts.push_back(I);
+    TabHost T;
+    tables_for(m, a, I, (uint32_t)ii.idx, T);
+    tabs.push_back(T);
     return ii;
   }
 };
@@ -588,6 +1048,13 @@ int rd_context_create(rd_context** ctx, int hip_device) {
     }
   const char* cfg = getenv("HGRD_LDS_CFG");
   if (cfg) c->cfg = atoi(cfg) % 3;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess)
+    c->n_cu = (uint32_t)prop.multiProcessorCount;
+  if (hipStreamCreate(&c->stream) != hipSuccess || init_kernel_attributes() != 0) {
+    delete c;
+    return RD_EDEVICE;
+  }
   *ctx = c;
   return RD_OK;
 }
@@ -598,6 +1065,7 @@ void rd_context_destroy(rd_context* ctx) {
   for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 
@@ -618,6 +1086,9 @@ struct rd_plan_impl {
   std::vector<uint32_t> npts;  // per device instance
   uint64_t evals = 0;
   uint32_t n_sitems = 0;
+  uint32_t persist_grid = 0;  // workgroups of the persistent small join
+  uint32_t n_tabchunks = 0;   // term-table fill chunks
+  uint32_t n_insts = 0, tab_insts = 0;
   struct Wave {
     uint32_t first_item, n_items, n_chunks, n_buckets;
     uint64_t key_bytes, pid_elems;
@@ -655,7 +1126,12 @@ struct rd_plan_impl {
     }
     return b.p;
   }
+  // the first phase of rd_execute (everything before the first host round
+  // trip), captured once and replayed
+  hipGraphExec_t graph = nullptr;
+  bool graph_failed = false;
   ~rd_plan_impl() {
+    if (graph) (void)hipGraphExecDestroy(graph);
     for (auto& kv : dev)
       if (kv.second.p) (void)hipFree(kv.second.p);
   }
@@ -680,19 +1156,26 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   rd_plan* plan = new rd_plan();
   std::unique_ptr<rd_plan> guard(plan);
   plan->n_pairs = n_pairs;
-  plan->st = (hipStream_t)o.stream;
+  plan->st = o.stream ? (hipStream_t)o.stream : ctx->stream;
   plan->log_level = o.log_level;
   int cfg = ctx->cfg;
   if (o.lds_cap) cfg = o.lds_cap <= 1024 ? 0 : o.lds_cap <= 1536 ? 1 : 2;
   plan->cfg = cfg;
   const uint32_t cap = (uint32_t)join_cap(cfg);
   plan->cap = cap;
+  {
+    // as many join workgroups as the CUs' LDS holds at once (160 KiB each)
+    uint32_t per_cu = (160u * 1024u) / (uint32_t)join_lds_bytes(cfg);
+    per_cu = std::max(1u, std::min(per_cu, 8u));
+    plan->persist_grid = per_cu * ctx->n_cu;
+  }
 
   Planner P;
   P.models = models;
   P.launch = launch;
   P.params = params;
   P.dims.resize(n_models);
+  P.use_tables = getenv("HGRD_INTERP") == nullptr;
   std::vector<uint32_t> model_err(n_models, 0);
   for (uint32_t m = 0; m < n_models; ++m) {
     const rd_kernel_model& M = models[m];
@@ -831,6 +1314,15 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       }
     }
   }
+  // longest first: the persistent join pops items in this order
+  std::stable_sort(sitems.begin(), sitems.end(), [&](const SItem& x, const SItem& y) {
+    auto size = [&](const SItem& it) {
+      uint64_t a = (uint64_t)(it.b1 - it.b0) * P.dev_insts[it.inst_i].tpb;
+      if (!Q[it.q].qd.self) a += (uint64_t)(it.b1 - it.b0) * P.dev_insts[it.inst_j].tpb;
+      return a;
+    };
+    return size(x) > size(y);
+  });
   plan->n_sitems = (uint32_t)sitems.size();
 
   // ---- VERDICT mode: search units, their blocks, tiles and rounds ----------
@@ -918,7 +1410,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   // ---- waves of HBM items, bounded by the device budget --------------------
   // A wave's buckets are small enough to stay in the last-level cache while
   // they are filled and joined, so HBM sees whole lines.
-  const uint64_t budget = o.max_device_bytes ? o.max_device_bytes : kWaveBytes;
+  const uint64_t budget = o.max_device_bytes ? o.max_device_bytes : ctx->wave_bytes;
   plan->wave_budget = budget;
   std::vector<Chunk> all_chunks;
   std::vector<uint32_t> all_bitem;
@@ -979,9 +1471,19 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   // ---- upload descriptors -----------------------------------------------------
   int merr = 0;
   const size_t isz = devinst_size();
+  const int64_t* d_tpool = (const int64_t*)plan->buf("tpool", std::max<uint64_t>(1, P.tpool) * 8, &merr);
   std::vector<unsigned char> dinst(isz * std::max<size_t>(1, P.dev_insts.size()));
-  for (size_t i = 0; i < P.dev_insts.size(); ++i)
+  for (size_t i = 0; i < P.dev_insts.size(); ++i) {
     fill_devinst(dinst.data() + i * isz, P.dev_insts[i]);
+    set_devinst_tab(dinst.data() + i * isz, P.tabs[i], d_tpool);
+    plan->tab_insts += P.tabs[i].on;
+  }
+  std::vector<Chunk> tabchunks;
+  for (uint32_t j = 0; j < P.tjobs.size(); ++j)
+    for (uint32_t e = 0; e < P.tjobs[j].n; e += 1024)
+      tabchunks.push_back(Chunk{j, 0, e, std::min<uint32_t>(P.tjobs[j].n, e + 1024)});
+  plan->n_tabchunks = (uint32_t)tabchunks.size();
+  plan->n_insts = (uint32_t)P.dev_insts.size();
   plan->npts.resize(P.dev_insts.size());
   for (size_t i = 0; i < P.dev_insts.size(); ++i) plan->npts[i] = P.dev_insts[i].npts;
   std::vector<QDesc> qd(n_pairs);
@@ -1008,6 +1510,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   up("params", P.pool_params.data(), P.pool_params.size() * 8);
   up("loops", P.pool_loops.data(), P.pool_loops.size() * 8);
   up("insts", dinst.data(), dinst.size());
+  up("tabjobs", P.tjobs.data(), P.tjobs.size() * sizeof(TabJob));
+  up("tabchunks", tabchunks.data(), tabchunks.size() * sizeof(Chunk));
   up("qdesc", qd.data(), n_pairs * sizeof(QDesc));
   up("herr", herr.data(), n_pairs * 4);
   up("triv", triv.data(), n_pairs);
@@ -1031,6 +1535,14 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     plan->buf("claim", std::max<size_t>(1, n_pairs) * 8, &merr);
   }
   plan->buf("qacc", std::max<size_t>(1, n_pairs) * sizeof(QAcc), &merr);
+  // scratch of the first phase belongs to the plan (a captured graph keeps
+  // these addresses)
+  plan->buf("keys", plan->max_key_bytes, &merr);
+  plan->buf("pids", plan->max_pid_elems * 4, &merr);
+  plan->buf("cursor", plan->max_buckets * 4, &merr);
+  plan->buf("ovf", std::max<size_t>(1, plan->hitems.size()) * 4, &merr);
+  plan->buf("done", std::max<size_t>(1, n_pairs) * 4, &merr);
+  plan->buf("pcursor", 4, &merr);
   plan->buf("out", std::max<size_t>(1, n_pairs) * sizeof(rd_pair_result), &merr);
   if (merr) return merr;
   *plan_out = guard.release();
@@ -1068,97 +1580,44 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   const HItem* d_hitems_all = (const HItem*)D("hitems");
   const Chunk* d_chunks_all = (const Chunk*)D("chunks");
   const uint32_t* d_bitem_all = (const uint32_t*)D("bitem");
-  // scratch shared by all plans of the context
-  unsigned char* d_keys = (unsigned char*)ctx->ensure("keys", plan->max_key_bytes, &merr);
-  uint32_t* d_pids = (uint32_t*)ctx->ensure("pids", plan->max_pid_elems * 4, &merr);
-  uint32_t* d_cursor = (uint32_t*)ctx->ensure("cursor", plan->max_buckets * 4, &merr);
-  uint32_t* d_ovf = (uint32_t*)ctx->ensure("ovf", plan->max_items * 4, &merr);
-  if (merr) return merr;
-
-  uint32_t* d_done = (uint32_t*)ctx->ensure("done", std::max<size_t>(1, n_pairs) * 4, &merr);
-  if (merr) return merr;
-  hipEvent_t* ev = ctx->ev;
-  TRY_HIP(hipEventRecord(ev[0], st));
-  if (launch_init_acc(st, n_pairs, d_acc)) return RD_EDEVICE;
-  if (launch_fill_u32(st, d_done, n_pairs, 0)) return RD_EDEVICE;
-  double verdict_ms = 0;
-  if (plan->verdict && plan->n_vq) {
-    VQuery* d_vq = (VQuery*)D("vq");
-    BBound* d_bb = (BBound*)D("bbounds");
-    float* d_sc = (float*)D("scores");
-    uint32_t* d_order = plan->use_mlp ? (uint32_t*)D("order") : nullptr;
-    TOut* d_tout = (TOut*)D("tout");
-    u64* d_claim = (u64*)D("claim");
-    TRY_HIP(hipEventRecord(ev[15], st));
-    if (launch_fill_u64(st, d_claim, n_pairs, kNoKey) ||
-        launch_block_bounds(st, (const BItem*)D("bitems"), plan->n_bitems, d_insts,
-                            d_code, d_params, d_loops, d_acc, d_bb) ||
-        launch_vq_span(st, d_vq, plan->n_vq, d_bb))
-      return RD_EDEVICE;
-    if (plan->use_mlp) {
-      if (launch_tile_scores(st, (const TChunk*)D("tchunks"), plan->n_tchunks, d_vq,
-                             d_bb, (const float*)D("mlp_w"), 1, d_sc) ||
-          launch_topk(st, d_vq, plan->n_vq, d_sc, plan->K, plan->max_tiles, d_order))
-        return RD_EDEVICE;
-    }
-    for (auto& rr : plan->rounds) {
-      if (launch_tile_join(cfg, st, (const TItem*)D("titems"), rr.first,
-                           rr.second - rr.first, d_vq, d_order, plan->K, d_insts,
-                           d_code, d_params, d_loops, d_qd, d_done, d_tout, d_claim) ||
-          launch_verdict_commit(st, n_pairs, d_claim, d_tout, d_acc, d_done))
-        return RD_EDEVICE;
-    }
-    TRY_HIP(hipEventRecord(ev[1], st));
-    TRY_HIP(hipEventSynchronize(ev[1]));
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, ev[15], ev[1]);
-    verdict_ms = ms;
-  }
-  double small_ms = 0, scatter_ms = 0, bucket_ms = 0, fallback_ms = 0, retry_ms = 0;
-  double split_ms = 0;
-  std::vector<uint32_t> skip;  // kept alive until the stream is synchronised
-  if (plan->n_sitems) {
-    TRY_HIP(hipEventRecord(ev[2], st));
-    if (launch_small(cfg, st, d_sitems, plan->n_sitems, d_insts, d_code,
-                     d_params, d_loops, d_qd, d_acc, d_done))
-      return RD_EDEVICE;
-    TRY_HIP(hipEventRecord(ev[3], st));
-    S.join_launches += 1;
-  }
-  if (plan->n_sitems) {
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, ev[2], ev[3]);
-    small_ms = ms;
-  }
-
-  // ---- HBM waves: no host round trip between waves; the scratch buckets
-  // are reused by the next wave in stream order.
-  const bool timing = plan->log_level >= 2 || getenv("HGRD_TIMING") != nullptr;
+  // first-phase scratch owned by the plan (fixed addresses, so a captured
+  // graph stays valid); later phases reuse the context's arena
+  unsigned char* d_keys = (unsigned char*)D("keys");
+  uint32_t* d_pids = (uint32_t*)D("pids");
+  uint32_t* d_cursor = (uint32_t*)D("cursor");
+  uint32_t* d_done = (uint32_t*)D("done");
+  uint32_t* d_pcursor = (uint32_t*)D("pcursor");
   const uint32_t nh = (uint32_t)plan->hitems.size();
-  uint32_t* d_ovf_all = (uint32_t*)ctx->ensure("ovf", std::max<size_t>(1, nh) * 4, &merr);
-  if (merr) return merr;
+  uint32_t* d_ovf_all = (uint32_t*)D("ovf");
+  hipEvent_t* ev = ctx->ev;
+  // timing mode runs the first phase eagerly with events between kernels
+  const bool timing = plan->log_level >= 2 || getenv("HGRD_TIMING") != nullptr;
+  double verdict_ms = 0, small_ms = 0, scatter_ms = 0, bucket_ms = 0;
+  double fallback_ms = 0, retry_ms = 0, split_ms = 0, waves_ms = 0;
+  std::vector<uint32_t> skip;  // kept alive until the stream is synchronised
+
   auto run_waves = [&](const std::vector<rd_plan_impl::Wave>& waves,
                        const HItem* d_hit, const Chunk* d_chk,
                        const uint32_t* d_bit, uint32_t* d_ovf, int wcfg,
-                       const u64* l0k, const u64* l0c) -> int {
+                       const u64* l0k, const u64* l0c, bool events) -> int {
     const uint32_t wcap = (uint32_t)join_cap(wcfg);
     for (const auto& W : waves) {
       if (launch_fill_u32(st, d_cursor, W.n_buckets, 0)) return RD_EDEVICE;
-      TRY_HIP(hipEventRecord(ev[4], st));
+      if (events) TRY_HIP(hipEventRecord(ev[4], st));
       if (launch_scatter(st, d_chk + W.chunk_off, W.n_chunks, d_hit, d_insts,
                          d_code, d_params, d_loops, d_acc, d_keys, d_pids,
                          d_cursor, d_ovf, wcap, d_done))
         return RD_EDEVICE;
-      TRY_HIP(hipEventRecord(ev[5], st));
+      if (events) TRY_HIP(hipEventRecord(ev[5], st));
       if (W.n_buckets &&
           launch_bucket(wcfg, st, W.n_buckets, 0, d_bit + W.bitem_off, d_hit,
                         d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_keys,
                         d_pids, d_cursor, d_ovf, d_done, l0k, l0c))
         return RD_EDEVICE;
-      TRY_HIP(hipEventRecord(ev[6], st));
       if (W.n_buckets) S.join_launches += 1;
       S.buckets += W.n_buckets;
-      if (timing) {
+      if (events && timing) {
+        TRY_HIP(hipEventRecord(ev[6], st));
         TRY_HIP(hipEventSynchronize(ev[6]));
         float ms = 0;
         (void)hipEventElapsedTime(&ms, ev[4], ev[5]);
@@ -1169,25 +1628,125 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     }
     return RD_OK;
   };
-  if (nh) {
-    if (launch_fill_u32(st, d_ovf_all, nh, 0)) return RD_EDEVICE;
-    TRY_HIP(hipEventRecord(ev[11], st));
-    int rc = run_waves(plan->waves, d_hitems_all, d_chunks_all, d_bitem_all, d_ovf_all,
-                       cfg, nullptr, nullptr);
-    if (rc) return rc;
-    TRY_HIP(hipEventRecord(ev[12], st));
+
+  // ---- first phase: accumulator init, VERDICT tile search, LDS joins of
+  // small items, HBM waves.  No host round trip inside; replayed from a
+  // captured graph unless timing.
+  auto phase1 = [&](bool events) -> int {
+    if (plan->n_tabchunks &&
+        launch_tabulate(st, (const Chunk*)D("tabchunks"), plan->n_tabchunks,
+                        (const TabJob*)D("tabjobs"), d_insts, d_code, d_params,
+                        d_loops, (int64_t*)D("tpool")))
+      return RD_EDEVICE;
+    if (launch_init_acc(st, n_pairs, d_acc)) return RD_EDEVICE;
+    if (launch_fill_u32(st, d_done, n_pairs, 0)) return RD_EDEVICE;
+    if (plan->verdict && plan->n_vq) {
+      VQuery* d_vq = (VQuery*)D("vq");
+      BBound* d_bb = (BBound*)D("bbounds");
+      float* d_sc = (float*)D("scores");
+      uint32_t* d_order = plan->use_mlp ? (uint32_t*)D("order") : nullptr;
+      TOut* d_tout = (TOut*)D("tout");
+      u64* d_claim = (u64*)D("claim");
+      if (events) TRY_HIP(hipEventRecord(ev[15], st));
+      if (launch_fill_u64(st, d_claim, n_pairs, kNoKey) ||
+          launch_block_bounds(st, (const BItem*)D("bitems"), plan->n_bitems, d_insts,
+                              d_code, d_params, d_loops, d_acc, d_bb) ||
+          launch_vq_span(st, d_vq, plan->n_vq, d_bb))
+        return RD_EDEVICE;
+      if (plan->use_mlp) {
+        if (launch_tile_scores(st, (const TChunk*)D("tchunks"), plan->n_tchunks, d_vq,
+                               d_bb, (const float*)D("mlp_w"), 1, d_sc) ||
+            launch_topk(st, d_vq, plan->n_vq, d_sc, plan->K, plan->max_tiles, d_order))
+          return RD_EDEVICE;
+      }
+      for (auto& rr : plan->rounds) {
+        if (launch_tile_join(cfg, st, (const TItem*)D("titems"), rr.first,
+                             rr.second - rr.first, d_vq, d_order, plan->K, d_insts,
+                             d_code, d_params, d_loops, d_qd, d_done, d_tout, d_claim) ||
+            launch_verdict_commit(st, n_pairs, d_claim, d_tout, d_acc, d_done))
+          return RD_EDEVICE;
+      }
+      if (events) TRY_HIP(hipEventRecord(ev[1], st));
+    }
+    if (plan->n_sitems) {
+      if (events) TRY_HIP(hipEventRecord(ev[2], st));
+      if (launch_small(cfg, st, d_sitems, plan->n_sitems, d_insts, d_code, d_params,
+                       d_loops, d_qd, d_acc, d_done, d_pcursor, plan->persist_grid))
+        return RD_EDEVICE;
+      if (events) TRY_HIP(hipEventRecord(ev[3], st));
+      S.join_launches += 1;
+    }
+    // HBM waves: the scratch buckets are reused by the next wave in stream
+    // order
+    if (nh) {
+      if (launch_fill_u32(st, d_ovf_all, nh, 0)) return RD_EDEVICE;
+      if (events) TRY_HIP(hipEventRecord(ev[11], st));
+      int rc = run_waves(plan->waves, d_hitems_all, d_chunks_all, d_bitem_all,
+                         d_ovf_all, cfg, nullptr, nullptr, events);
+      if (rc) return rc;
+      if (events) TRY_HIP(hipEventRecord(ev[12], st));
+    }
+    return RD_OK;
+  };
+
+  TRY_HIP(hipEventRecord(ev[0], st));
+  bool replayed = false;
+  if (!timing && !plan->graph_failed && !plan->graph) {
+    // capture once; any failure falls back to eager launches for this plan
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      int rc = phase1(false);
+      ok = hipStreamEndCapture(st, &g) == hipSuccess && rc == RD_OK && g;
+      if (ok) ok = hipGraphInstantiate(&plan->graph, g, nullptr, nullptr, 0) == hipSuccess;
+      if (g) (void)hipGraphDestroy(g);
+    }
+    if (!ok) {
+      (void)hipGetLastError();
+      plan->graph = nullptr;
+      plan->graph_failed = true;
+    }
+    S.join_launches = 0;
+    S.buckets = 0;
   }
+  if (!timing && plan->graph) {
+    TRY_HIP(hipGraphLaunch(plan->graph, st));
+    replayed = true;
+    S.join_launches = (plan->n_sitems ? 1 : 0);
+    for (const auto& W : plan->waves) {
+      S.join_launches += W.n_buckets ? 1 : 0;
+      S.buckets += W.n_buckets;
+    }
+  } else {
+    int rc = phase1(true);
+    if (rc) return rc;
+  }
+  TRY_HIP(hipEventRecord(ev[13], st));
   S.hbm_items = nh;
   for (uint32_t i = 0; i < nh; ++i)
     if (plan->hitems[i].shared != 2) S.records += plan->hR[i];
   std::vector<uint32_t> ovf(nh);
   if (nh) TRY_HIP(hipMemcpyAsync(ovf.data(), d_ovf_all, nh * 4, hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
-  double waves_ms = 0;
-  if (nh) {
+  {
     float ms = 0;
-    (void)hipEventElapsedTime(&ms, ev[11], ev[12]);
-    waves_ms = ms;  // scatter and bucket joins together
+    if (replayed) {
+      (void)hipEventElapsedTime(&ms, ev[0], ev[13]);
+      waves_ms = ms;  // the whole first phase
+    } else {
+      if (plan->verdict && plan->n_vq) {
+        (void)hipEventElapsedTime(&ms, ev[15], ev[1]);
+        verdict_ms = ms;
+      }
+      if (plan->n_sitems) {
+        (void)hipEventElapsedTime(&ms, ev[2], ev[3]);
+        small_ms = ms;
+      }
+      if (nh) {
+        (void)hipEventElapsedTime(&ms, ev[11], ev[12]);
+        waves_ms = ms;  // scatter and bucket joins together
+      }
+    }
   }
 
   // ---- re-partition overflowed items ---------------------------------------
@@ -1261,7 +1820,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     TRY_HIP(hipMemcpyAsync(d_rb, bitem.data(), bitem.size() * 4, hipMemcpyHostToDevice, st));
     if (launch_fill_u32(st, d_rovf, nr, 0)) return RD_EDEVICE;
     TRY_HIP(hipEventRecord(ev[13], st));
-    int rc = run_waves(waves, d_rh, d_rc, d_rb, d_rovf, wcfg, l0k, l0c);
+    int rc = run_waves(waves, d_rh, d_rc, d_rb, d_rovf, wcfg, l0k, l0c, true);
     if (rc) return rc;
     TRY_HIP(hipEventRecord(ev[14], st));
     ovf_out.assign(nr, 0);
@@ -1526,6 +2085,52 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
   return rc;
 }
 
+int rd_autotune(rd_context* ctx, const rd_kernel_model* models,
+                uint32_t n_models, const rd_access_pair* pairs,
+                uint32_t n_pairs, const rd_launch_domain* launch,
+                const rd_param_sets* params, const rd_options* opt,
+                uint32_t reps, rd_options* best, double* best_ms) {
+  if (!ctx || !best) return RD_EINVAL;
+  rd_options base;
+  memset(&base, 0, sizeof base);
+  if (opt) base = *opt;
+  reps = std::max(1u, std::min(reps, 16u));
+  std::vector<rd_pair_result> out(std::max<uint32_t>(1, n_pairs));
+  static const uint64_t kWaves[3] = {kWaveBytes / 2, kWaveBytes, kWaveBytes * 2};
+  double t_best = 1e300;
+  rd_options o_best = base;
+  for (int cfg = 0; cfg < 3; ++cfg) {
+    for (uint64_t wb : kWaves) {
+      rd_options o = base;
+      o.lds_cap = (uint32_t)join_cap(cfg);
+      o.max_device_bytes = wb;
+      rd_plan* plan = nullptr;
+      int rc = rd_prepare(ctx, models, n_models, pairs, n_pairs, launch, params, &o, &plan);
+      if (rc != RD_OK) return rc;
+      rc = rd_execute(ctx, plan, out.data());  // warm-up (and graph capture)
+      std::vector<double> ts;
+      for (uint32_t r = 0; rc == RD_OK && r < reps; ++r) {
+        const double t0 = now_ms();
+        rc = rd_execute(ctx, plan, out.data());
+        ts.push_back(now_ms() - t0);
+      }
+      rd_plan_destroy(plan);
+      if (rc != RD_OK) return rc;
+      std::sort(ts.begin(), ts.end());
+      const double t = ts[ts.size() / 2];
+      if (t < t_best) {
+        t_best = t;
+        o_best = o;
+      }
+    }
+  }
+  ctx->cfg = o_best.lds_cap <= 1024 ? 0 : o_best.lds_cap <= 1536 ? 1 : 2;
+  ctx->wave_bytes = o_best.max_device_bytes;
+  *best = o_best;
+  if (best_ms) *best_ms = t_best;
+  return RD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Tile data and the tile-scoring network.
 
@@ -1559,7 +2164,12 @@ int rd_tile_data(rd_context* ctx, const rd_kernel_model* models,
   BBound* d_bb = (BBound*)D("bbounds");
   TOut* d_tout = (TOut*)D("tout");
   QAcc* d_acc = (QAcc*)D("qacc");
-  if (launch_init_acc(st, n_pairs, d_acc) || launch_fill_u32(st, d_done, n_pairs, 0) ||
+  if ((plan->n_tabchunks &&
+       launch_tabulate(st, (const Chunk*)D("tabchunks"), plan->n_tabchunks,
+                       (const TabJob*)D("tabjobs"), D("insts"), (const DInsn*)D("code"),
+                       (const int64_t*)D("params"), (const int64_t*)D("loops"),
+                       (int64_t*)D("tpool"))) ||
+      launch_init_acc(st, n_pairs, d_acc) || launch_fill_u32(st, d_done, n_pairs, 0) ||
       launch_fill_u64(st, (u64*)D("claim"), n_pairs, kNoKey) ||
       launch_fill_u64(st, (u64*)d_tout, (u64)plan->n_titems * (sizeof(TOut) / 8), kNoKey) ||
       launch_block_bounds(st, (const BItem*)D("bitems"), plan->n_bitems, D("insts"),
@@ -1719,6 +2329,129 @@ int rd_mlp_train(rd_context* ctx, rd_mlp* w, const float* X, const float* Y,
   TRY_HIP(hipMemcpyAsync(w, d.w, nw, hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
   return RD_OK;
+}
+
+// Host interpreter of compiled programs (same semantics as the device's).
+static int64_t host_prog(const std::vector<DInsn>& code, const Prog& p,
+                         const int64_t* coords, const int64_t* params,
+                         int64_t dflt, uint32_t& err) {
+  static const uint16_t kOp[] = {0, RD_OP_ADD, RD_OP_SUB, RD_OP_MUL, RD_OP_DIV,
+                                 RD_OP_MOD, RD_OP_SHL, RD_OP_SHR, RD_OP_AND,
+                                 RD_OP_OR, RD_OP_XOR, RD_OP_MIN, RD_OP_MAX,
+                                 RD_OP_LT, RD_OP_LE, RD_OP_EQ, RD_OP_NE,
+                                 RD_OP_GE, RD_OP_GT, RD_OP_LAND, RD_OP_LOR};
+  if (p.absent) return dflt;
+  int64_t st[kMaxStack];
+  for (uint32_t k = 0; k < p.n; ++k) {
+    const DInsn& in = code[p.off + k];
+    auto opnd = [&](uint8_t mode, uint16_t i) -> int64_t {
+      return mode == M_REG ? st[i] : mode == M_IMM ? in.imm
+             : mode == M_PARAM ? params[i] : coords[i];
+    };
+    const int64_t a = opnd(in.ma, in.a), b = opnd(in.mb, in.b);
+    int64_t r;
+    if (in.op == D_MOV) r = a;
+    else if (in.op == D_NEG) r = hop(RD_OP_SUB, 0, a, err);
+    else if (in.op == D_LNOT) r = a == 0;
+    else r = hop(kOp[in.op], a, b, err);
+    st[in.dst] = r;
+  }
+  return st[p.res];
+}
+
+static void host_coords(const AccInst& I, const std::vector<int64_t>& loops,
+                        uint32_t blin, uint32_t tlin, uint32_t ilin, int64_t* c) {
+  c[0] = tlin % I.dims[3];
+  c[1] = (tlin / I.dims[3]) % I.dims[4];
+  c[2] = tlin / (I.dims[3] * I.dims[4]);
+  c[3] = blin % I.dims[0];
+  c[4] = (blin / I.dims[0]) % I.dims[1];
+  c[5] = blin / (I.dims[0] * I.dims[1]);
+  c[6] = c[7] = c[8] = c[9] = 0;
+  uint32_t rem = ilin;
+  for (int k = (int)I.n_loops - 1; k >= 0; --k) {
+    c[6 + k] = loops[I.loop_off[k] + rem % I.loop_n[k]];
+    rem /= I.loop_n[k];
+  }
+}
+
+int rd_table_selftest(const rd_kernel_model* models, uint32_t n_models,
+                      const rd_launch_domain* launch, const rd_param_sets* params,
+                      uint32_t model, uint32_t access, uint32_t set,
+                      uint64_t max_points, uint64_t* n_checked) {
+  if (!models || !launch || !params || model >= n_models) return RD_EINVAL;
+  if (access >= models[model].n_acc || set >= params[model].n_sets) return RD_EINVAL;
+  if (check_access(models[model], models[model].acc[access])) return 2;
+  Planner P;
+  P.models = models;
+  P.launch = launch;
+  P.params = params;
+  P.dims.resize(n_models);
+  P.dims[model].resize(params[model].n_sets);
+  InstInfo& ii = P.inst(model, access, set);
+  if (ii.err || ii.idx < 0) return 2;
+  const AccInst& I = P.dev_insts[ii.idx];
+  const TabHost& T = P.tabs[ii.idx];
+  if (!T.on) return 1;
+  // fill the tables as the device does
+  std::vector<int64_t> pool(P.tpool + 1);
+  const int64_t* pr = P.pool_params.data() + I.params_off;
+  int64_t c[10];
+  for (const TabJob& J : P.tjobs) {
+    for (uint32_t e = 0; e < J.n; ++e) {
+      host_coords(I, P.pool_loops, J.group == 0 ? e : 0, J.group == 1 ? e : 0,
+                  J.group >= 2 ? e : 0, c);
+      uint32_t err = 0;
+      int64_t v;
+      if (J.group == 3) {
+        v = host_prog(P.code, I.bint, c, pr, 0, err) |
+            (host_prog(P.code, I.wint, c, pr, 0, err) << 16);
+      } else {
+        bool g = J.guard.absent || host_prog(P.code, J.guard, c, pr, 1, err) != 0;
+        v = g ? host_prog(P.code, J.val, c, pr, 0, err) : INT64_MIN;
+      }
+      if (err) return -2;  // a table program failed: the proof was wrong
+      pool[J.out_off + e] = v;
+    }
+  }
+  // every box point: tables against the interpreter on the original programs
+  const uint64_t npts = std::min<uint64_t>(I.npts, max_points ? max_points : I.npts);
+  for (uint64_t k = 0; k < npts; ++k) {
+    const uint64_t pidx = I.npts <= max_points || !max_points
+                              ? k : (k * 2654435761ull) % I.npts;
+    const uint32_t tlin = (uint32_t)(pidx % I.nthr);
+    const uint32_t rest = (uint32_t)(pidx / I.nthr);
+    const uint32_t ilin = rest % I.niota, blin = rest / I.niota;
+    host_coords(I, P.pool_loops, blin, tlin, ilin, c);
+    uint32_t err = 0;
+    const bool g0 = host_prog(P.code, I.guard, c, pr, 1, err) != 0;
+    int64_t a0 = 0, b0 = 0, w0 = 0;
+    if (g0) {
+      a0 = host_prog(P.code, I.addr, c, pr, 0, err);
+      b0 = host_prog(P.code, I.bint, c, pr, 0, err);
+      w0 = host_prog(P.code, I.wint, c, pr, 0, err);
+      if (I.is32 && (a0 < INT32_MIN || a0 > INT32_MAX)) err |= ERR_RANGE;
+      if (b0 < 0 || b0 > 65535 || w0 < 0 || w0 > 65535) err |= ERR_UNSUP;
+    }
+    if (err) return -3;  // the interpreter fails where tables were allowed
+    bool g1 = !T.never;
+    int64_t a1 = T.u;
+    const uint32_t gi[3] = {blin, tlin, ilin};
+    for (int g = 0; g < 3 && g1; ++g) {
+      if (T.off[g] == kNoTab) continue;
+      const int64_t v = pool[T.off[g] + gi[g]];
+      if (v == INT64_MIN) g1 = false;
+      else a1 += v;
+    }
+    if (g0 != g1) return -4;
+    if (g0) {
+      const uint32_t iv = T.iv_off != kNoTab ? (uint32_t)pool[T.iv_off + ilin] : T.iv_const;
+      if (a0 != a1) return -5;
+      if ((uint32_t)b0 != (iv & 0xFFFF) || (uint32_t)w0 != (iv >> 16)) return -6;
+    }
+  }
+  if (n_checked) *n_checked = npts;
+  return 0;
 }
 
 int rd_selftest(void) {

@@ -63,6 +63,31 @@ struct alignas(16) AccInst {
   uint32_t tpb;                  // nthr * niota (points per block)
 };
 
+// Term tables of one instance.  When an expression is proven free of
+// errors over the whole launch box it is split into a uniform part and one
+// term per coordinate group (blocks, threads, loop iterations), each
+// tabulated over its group's linear index:
+//   addr = u + T_B[blin] + T_T[tlin] + T_L[ilin]
+// A table entry of INT64_MIN marks a group index at which a conjunct of
+// the guard is false.  iv: (bint | wint << 16) per iteration, or constant.
+constexpr uint32_t kNoTab = 0xFFFFFFFFu;
+struct TabHost {
+  int64_t u;
+  uint32_t off[3];    // entry offsets in the table pool per group, kNoTab = none
+  uint32_t iv_off;    // kNoTab: iv_const for every iteration
+  uint32_t iv_const;
+  uint32_t never;     // a uniform guard conjunct is false
+  uint32_t on;        // tables in use for this instance
+};
+
+// One table to fill: entries [0, n) of group `group` (0 blocks, 1 threads,
+// 2 iterations, 3 packed interval ids over iterations) of instance `inst`.
+struct TabJob {
+  uint32_t inst, group, out_off, n;
+  Prog val, guard;  // value and guard-conjunct programs of the group
+};
+static_assert(sizeof(TabJob) == 32, "TabJob layout");
+
 // Per-query description and accumulators.
 struct QDesc {
   uint32_t mask;     // classes to check (bit 0 inter, 1 block, 2 warp)

@@ -36,17 +36,17 @@ namespace hgrd {
 using u64 = unsigned long long;
 
 // ---------------------------------------------------------------------------
-// Kernel: generate both sides of a small item straight into LDS and join.
+// Small items: generate both sides straight into LDS and join.
 
 template <int CAP, int TBL>
-__global__ void __launch_bounds__(256)
-k_small_join(const SItem* __restrict__ items, const DevInst* __restrict__ insts,
-             const DInsn* __restrict__ code, const int64_t* __restrict__ params,
-             const int64_t* __restrict__ loopvals, const QDesc* __restrict__ qd,
-             QAcc* __restrict__ acc, const uint32_t* __restrict__ done) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
-  const SItem it = items[blockIdx.x];
+__device__ __forceinline__ void small_item(JoinLds<CAP, TBL>& S, const SItem& it,
+                                           const DevInst* __restrict__ insts,
+                                           const DInsn* __restrict__ code,
+                                           const int64_t* __restrict__ params,
+                                           const int64_t* __restrict__ loopvals,
+                                           const QDesc* __restrict__ qd,
+                                           QAcc* __restrict__ acc,
+                                           const uint32_t* __restrict__ done) {
   if (done[it.q]) return;
   const QDesc q = qd[it.q];
   if (threadIdx.x == 0) {
@@ -68,9 +68,7 @@ k_small_join(const SItem* __restrict__ items, const DevInst* __restrict__ insts,
       PointIds id;
       if (pidx < p1) {
         id = decode(I, pidx);
-        Regs R;
-        set_coords(I, id, loopvals, R);
-        valid = eval_point(I, code, params, R, pt, err);
+        valid = point_eval(I, id, code, params, loopvals, pt, err);
       }
       uint32_t w = valid ? id.tlin / q.warp : 0;
       lds_append(S, valid, pt, id, (uint32_t)side, w);
@@ -85,6 +83,77 @@ k_small_join(const SItem* __restrict__ items, const DevInst* __restrict__ insts,
   }
   lds_join(S, q, it.sigma);
   commit_join(S, &acc[it.q]);
+}
+
+// One workgroup per item.
+template <int CAP, int TBL>
+__global__ void __launch_bounds__(256)
+k_small_join(const SItem* __restrict__ items, const DevInst* __restrict__ insts,
+             const DInsn* __restrict__ code, const int64_t* __restrict__ params,
+             const int64_t* __restrict__ loopvals, const QDesc* __restrict__ qd,
+             QAcc* __restrict__ acc, const uint32_t* __restrict__ done) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
+  small_item(S, items[blockIdx.x], insts, code, params, loopvals, qd, acc, done);
+}
+
+// Persistent form: a grid sized to the machine pops items (largest first,
+// as the host orders them) from a work counter until none is left.
+template <int CAP, int TBL>
+__global__ void __launch_bounds__(256)
+k_small_persist(const SItem* __restrict__ items, uint32_t n,
+                uint32_t* __restrict__ cursor, const DevInst* __restrict__ insts,
+                const DInsn* __restrict__ code, const int64_t* __restrict__ params,
+                const int64_t* __restrict__ loopvals, const QDesc* __restrict__ qd,
+                QAcc* __restrict__ acc, const uint32_t* __restrict__ done) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
+  __shared__ uint32_t cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(cursor, 1u);
+    __syncthreads();
+    const uint32_t k = cur;
+    __syncthreads();
+    if (k >= n) break;
+    small_item(S, items[k], insts, code, params, loopvals, qd, acc, done);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel: fill term tables.  One workgroup per chunk of one table; every
+// entry evaluates the group's programs at that group index (the other
+// coordinates are zero and unused).  The host proved these programs free of
+// errors over the whole box.
+__global__ void __launch_bounds__(256)
+k_tabulate(const Chunk* __restrict__ chunks, const TabJob* __restrict__ jobs,
+           const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
+           const int64_t* __restrict__ params,
+           const int64_t* __restrict__ loopvals, int64_t* __restrict__ pool) {
+  const Chunk ch = chunks[blockIdx.x];
+  const TabJob J = jobs[ch.item];
+  DevInst I;
+  load_inst(I, insts, J.inst);
+  const int64_t* pr = params + I.a.params_off;
+  for (uint32_t e = ch.p0 + threadIdx.x; e < ch.p1; e += blockDim.x) {
+    PointIds id;
+    id.blin = J.group == 0 ? e : 0;
+    id.tlin = J.group == 1 ? e : 0;
+    id.ilin = J.group >= 2 ? e : 0;
+    Regs R;
+    set_coords(I, id, loopvals, R);
+    uint32_t err = 0;
+    int64_t v;
+    if (J.group == 3) {
+      const int64_t b = run_prog(code, I.a.bint, R, pr, 0, err);
+      const int64_t w = run_prog(code, I.a.wint, R, pr, 0, err);
+      v = b | (w << 16);
+    } else {
+      const bool g = J.guard.absent || run_prog(code, J.guard, R, pr, 1, err) != 0;
+      v = g ? run_prog(code, J.val, R, pr, 0, err) : INT64_MIN;
+    }
+    pool[J.out_off + e] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -120,10 +189,8 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
     uint32_t pidx = base + threadIdx.x;
     if (pidx >= ch.p1) break;
     PointIds id = decode(I, pidx);
-    Regs R;
-    set_coords(I, id, loopvals, R);
     Point pt;
-    if (!eval_point(I, code, params, R, pt, err)) continue;
+    if (!point_eval(I, id, code, params, loopvals, pt, err)) continue;
     if (h.nbuckets == 0) continue;  // error scan only
     u64 hk = (u64)pt.addr;
     if (h.shared == 1 || h.shared == 3) hk ^= (u64)(id.blin + 1) * 0x9E3779B97F4A7C15ull;
@@ -208,10 +275,8 @@ k_level0(const Chunk* __restrict__ chunks, const L0Item* __restrict__ items,
       uint32_t pidx = t0 + j * 256 + threadIdx.x;
       if (pidx >= ch.p1) break;
       PointIds id = decode(I, pidx);
-      Regs R;
-      set_coords(I, id, loopvals, R);
       Point pt;
-      if (!eval_point(I, code, params, R, pt, err)) continue;
+      if (!point_eval(I, id, code, params, loopvals, pt, err)) continue;
       uint32_t h;
       if ((u64)pt.addr == kL0Empty) {
         h = kT;
@@ -300,7 +365,6 @@ k_bucket_join(const uint32_t* __restrict__ bucket_item,
   for (int side = 0; side < 2; ++side) {
     DevInst I;
     load_inst(I, insts, side ? h.inst_j : h.inst_i);
-    const bool need_iv = !(I.a.bint.absent && I.a.wint.absent);
     for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
       uint32_t pid = pids[h.pid_off + slot0 + r];
       if ((pid >> 31) != (uint32_t)side) continue;
@@ -310,15 +374,8 @@ k_bucket_join(const uint32_t* __restrict__ bucket_item,
         a = reinterpret_cast<const int32_t*>(keys + h.key_off)[slot0 + r];
       else
         a = reinterpret_cast<const int64_t*>(keys + h.key_off)[slot0 + r];
-      uint32_t bi = 0, wi = 0;
-      if (need_iv) {
-        Regs R;
-        set_coords(I, id, loopvals, R);
-        const int64_t* pr = params + I.a.params_off;
-        uint32_t e = 0;
-        bi = (uint32_t)run_prog(code, I.a.bint, R, pr, 0, e) & 0xFFFF;
-        wi = (uint32_t)run_prog(code, I.a.wint, R, pr, 0, e) & 0xFFFF;
-      }
+      uint32_t bi, wi;
+      point_iv(I, id, code, params, loopvals, bi, wi);
       S.addr[r] = (u64)a;
       S.blin[r] = id.blin;
       S.tli[r] = (id.ilin << 16) | ((uint32_t)side << 15) | id.tlin;
@@ -383,9 +440,7 @@ k_gen_linear(const Chunk* __restrict__ chunks, const FItem* __restrict__ fitems,
     PointIds id;
     if (pidx < ch.p1) {
       id = decode(I, pidx);
-      Regs R;
-      set_coords(I, id, loopvals, R);
-      valid = eval_point(I, code, params, R, pt, err);
+      valid = point_eval(I, id, code, params, loopvals, pt, err);
     }
     u64 bal = __ballot(valid);
     if (bal == 0) continue;
@@ -603,9 +658,7 @@ k_witness2(const W2Item* __restrict__ items, const DevInst* __restrict__ insts,
     id.blin = pb;
     id.tlin = pt_;
     id.ilin = pi;
-    Regs R;
-    set_coords(I, id, loopvals, R);
-    eval_point(I, code, params, R, P, e);
+    point_eval(I, id, code, params, loopvals, P, e);
   }
   const uint32_t pw = pt_ / q.warp;
   if (it.p0 == 0 && threadIdx.x == 0) acc[it.q].waddr = P.addr;
@@ -617,10 +670,8 @@ k_witness2(const W2Item* __restrict__ items, const DevInst* __restrict__ insts,
     uint32_t pidx = base + threadIdx.x;
     if (pidx >= it.p1) break;
     PointIds id = decode(J, pidx);
-    Regs R;
-    set_coords(J, id, loopvals, R);
     Point Q;
-    if (!eval_point(J, code, params, R, Q, err)) continue;
+    if (!point_eval(J, id, code, params, loopvals, Q, err)) continue;
     if (Q.addr != P.addr) continue;
     if (id.blin == pb && id.tlin == pt_) continue;
     uint32_t cls;
@@ -728,14 +779,16 @@ template <int CAP, int TBL>
 static int launch_small_t(hipStream_t st, const SItem* items, uint32_t n,
                           const DevInst* insts, const DInsn* code,
                           const int64_t* params, const int64_t* loopvals,
-                          const QDesc* qd, QAcc* acc, const uint32_t* done) {
+                          const QDesc* qd, QAcc* acc, const uint32_t* done,
+                          uint32_t* cursor, uint32_t persist_grid) {
   size_t lds = sizeof(JoinLds<CAP, TBL>);
-  static bool attr = false;
-  if (!attr) {
-    HGRD_CHECK(hipFuncSetAttribute((const void*)k_small_join<CAP, TBL>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-    attr = true;
+  if (cursor) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, cursor, 1u, 0u);
+    hipLaunchKernelGGL((k_small_persist<CAP, TBL>), dim3(persist_grid), dim3(256),
+                       lds, st, items, n, cursor, insts, code, params, loopvals,
+                       qd, acc, done);
+    HGRD_CHECK(hipGetLastError());
+    return 0;
   }
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
@@ -743,6 +796,18 @@ static int launch_small_t(hipStream_t st, const SItem* items, uint32_t n,
                        items + off, insts, code, params, loopvals, qd, acc, done);
     HGRD_CHECK(hipGetLastError());
   }
+  return 0;
+}
+
+template <int CAP, int TBL>
+static int set_lds_attrs() {
+  const int lds = (int)sizeof(JoinLds<CAP, TBL>);
+  HGRD_CHECK(hipFuncSetAttribute((const void*)k_small_join<CAP, TBL>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  HGRD_CHECK(hipFuncSetAttribute((const void*)k_small_persist<CAP, TBL>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  HGRD_CHECK(hipFuncSetAttribute((const void*)k_bucket_join<CAP, TBL>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   return 0;
 }
 
@@ -757,13 +822,6 @@ static int launch_bucket_t(hipStream_t st, uint32_t nb, uint32_t base,
                            const uint32_t* done, const u64* l0keys,
                            const u64* l0cnt) {
   size_t lds = sizeof(JoinLds<CAP, TBL>);
-  static bool attr = false;
-  if (!attr) {
-    HGRD_CHECK(hipFuncSetAttribute((const void*)k_bucket_join<CAP, TBL>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-    attr = true;
-  }
   hipLaunchKernelGGL((k_bucket_join<CAP, TBL>), dim3(nb), dim3(256), lds, st,
                      bucket_item, hitems, insts, code, params, loopvals, qd,
                      acc, keys, pids, cursor, ovf, base, done, l0keys, l0cnt);
@@ -777,6 +835,19 @@ static int launch_bucket_t(hipStream_t st, uint32_t nb, uint32_t base,
 namespace hgrd {
 
 size_t devinst_size() { return sizeof(DevInst); }
+
+void set_devinst_tab(void* dst, const TabHost& t, const int64_t* pool) {
+  DevInst d;
+  memcpy(&d, dst, sizeof d);
+  d.tpool = pool;
+  d.tu = t.u;
+  for (int g = 0; g < 3; ++g) d.toff[g] = t.off[g];
+  d.iv_off = t.iv_off;
+  d.iv_const = t.iv_const;
+  d.tnever = t.never;
+  d.tab = t.on;
+  memcpy(dst, &d, sizeof d);
+}
 
 void fill_devinst(void* dst, const AccInst& a) {
   DevInst d;
@@ -813,13 +884,34 @@ int join_cap(int cfg) { return cfg == 0 ? 1024 : cfg == 1 ? 1536 : 3072; }
 int launch_small(int cfg, hipStream_t st, const SItem* items, uint32_t n,
                  const void* insts, const DInsn* code, const int64_t* params,
                  const int64_t* loopvals, const QDesc* qd, QAcc* acc,
-                 const uint32_t* done) {
+                 const uint32_t* done, uint32_t* cursor, uint32_t persist_grid) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_small_t<1024, 2048>(st, items, n, I, code, params, loopvals, qd, acc, done);
-    case 1: return launch_small_t<1536, 4096>(st, items, n, I, code, params, loopvals, qd, acc, done);
-    default: return launch_small_t<3072, 8192>(st, items, n, I, code, params, loopvals, qd, acc, done);
+    case 0: return launch_small_t<1024, 2048>(st, items, n, I, code, params, loopvals, qd, acc, done, cursor, persist_grid);
+    case 1: return launch_small_t<1536, 4096>(st, items, n, I, code, params, loopvals, qd, acc, done, cursor, persist_grid);
+    default: return launch_small_t<3072, 8192>(st, items, n, I, code, params, loopvals, qd, acc, done, cursor, persist_grid);
   }
+}
+
+// Raises the LDS limit of every join kernel (once per device, before any
+// launch or graph capture).
+int init_kernel_attributes() {
+  if (set_lds_attrs<1024, 2048>() || set_lds_attrs<1536, 4096>() ||
+      set_lds_attrs<3072, 8192>())
+    return -1;
+  return init_verdict_attributes();
+}
+
+int launch_tabulate(hipStream_t st, const Chunk* chunks, uint32_t n,
+                    const TabJob* jobs, const void* insts, const DInsn* code,
+                    const int64_t* params, const int64_t* loopvals, int64_t* pool) {
+  for (uint32_t off = 0; off < n; off += 1u << 20) {
+    uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
+    hipLaunchKernelGGL(k_tabulate, dim3(m), dim3(256), 0, st, chunks + off, jobs,
+                       (const DevInst*)insts, code, params, loopvals, pool);
+    HGRD_CHECK(hipGetLastError());
+  }
+  return 0;
 }
 
 int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n,

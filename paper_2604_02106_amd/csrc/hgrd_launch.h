@@ -21,6 +21,10 @@ struct GRecPtrs {
 
 size_t devinst_size();
 void fill_devinst(void* dst, const AccInst& a);
+void set_devinst_tab(void* dst, const TabHost& t, const int64_t* pool);
+int launch_tabulate(hipStream_t st, const Chunk* chunks, uint32_t n,
+                    const TabJob* jobs, const void* insts, const DInsn* code,
+                    const int64_t* params, const int64_t* loopvals, int64_t* pool);
 int fastdiv_check(uint32_t n, uint32_t d);
 int join_lds_bytes(int cfg);
 int join_cap(int cfg);
@@ -29,7 +33,9 @@ size_t w2item_size();
 int launch_small(int cfg, hipStream_t st, const SItem* items, uint32_t n,
                  const void* insts, const DInsn* code, const int64_t* params,
                  const int64_t* loopvals, const QDesc* qd, QAcc* acc,
-                 const uint32_t* done);
+                 const uint32_t* done, uint32_t* cursor, uint32_t persist_grid);
+int init_kernel_attributes();
+int init_verdict_attributes();
 int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n,
                    const HItem* hitems, const void* insts, const DInsn* code,
                    const int64_t* params, const int64_t* loopvals, QAcc* acc,

@@ -43,10 +43,8 @@ k_block_bounds(const BItem* __restrict__ items, const DevInst* __restrict__ inst
     uint32_t pidx = base + threadIdx.x;
     if (pidx >= p1) break;
     PointIds id = decode(I, pidx);
-    Regs R;
-    set_coords(I, id, loopvals, R);
     Point pt;
-    if (!eval_point(I, code, params, R, pt, err)) continue;
+    if (!point_eval(I, id, code, params, loopvals, pt, err)) continue;
     mn = pt.addr < mn ? pt.addr : mn;
     mx = pt.addr > mx ? pt.addr : mx;
     ++cnt;
@@ -416,9 +414,7 @@ k_tile_join(const TItem* __restrict__ items, const VQuery* __restrict__ vq,
       PointIds id;
       if (pidx < p1) {
         id = decode(I, pidx);
-        Regs R;
-        set_coords(I, id, loopvals, R);
-        valid = eval_point(I, code, params, R, pt, err);
+        valid = point_eval(I, id, code, params, loopvals, pt, err);
       }
       uint32_t w = valid ? id.tlin / q.warp : 0;
       lds_append(S, valid, pt, id, sd, w);
@@ -553,13 +549,6 @@ int launch_topk(hipStream_t st, const VQuery* vq, uint32_t nvq,
                 uint32_t* order) {
   if (!nvq) return 0;
   size_t lds = ((max_tiles + 31) / 32) * 4;
-  static size_t attr = 0;
-  if (lds > attr && lds > 48 * 1024) {
-    HGRD_CHECK(hipFuncSetAttribute((const void*)k_topk,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-    attr = lds;
-  }
   hipLaunchKernelGGL(k_topk, dim3(nvq), dim3(256), lds, st, vq, scores, K, order);
   HGRD_CHECK(hipGetLastError());
   return 0;
@@ -573,13 +562,6 @@ static int launch_tile_join_t(hipStream_t st, const TItem* items, uint32_t item0
                               const QDesc* qd, uint32_t* done, TOut* tout,
                               u64* claim) {
   size_t lds = sizeof(JoinLds<CAP, TBL>);
-  static bool attr = false;
-  if (!attr) {
-    HGRD_CHECK(hipFuncSetAttribute((const void*)k_tile_join<CAP, TBL>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-    attr = true;
-  }
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
     hipLaunchKernelGGL((k_tile_join<CAP, TBL>), dim3(m), dim3(256), lds, st,
@@ -646,5 +628,21 @@ int launch_adam(hipStream_t st, float* w, float* g, float* m, float* v, float lr
 }
 
 int mlp_num_weights() { return kNW; }
+
+int init_verdict_attributes() {
+  HGRD_CHECK(hipFuncSetAttribute((const void*)k_topk,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (1 << 20) / 8));
+  HGRD_CHECK(hipFuncSetAttribute((const void*)k_tile_join<1024, 2048>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sizeof(JoinLds<1024, 2048>)));
+  HGRD_CHECK(hipFuncSetAttribute((const void*)k_tile_join<1536, 4096>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sizeof(JoinLds<1536, 4096>)));
+  HGRD_CHECK(hipFuncSetAttribute((const void*)k_tile_join<3072, 8192>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sizeof(JoinLds<3072, 8192>)));
+  return 0;
+}
 
 }  // namespace hgrd

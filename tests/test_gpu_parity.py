@@ -189,3 +189,46 @@ def test_invariance_tile_shapes(hg):
         compare(hg.check_pairs(wl, lds_cap=cap), base, "lds_cap=%d" % cap)
     # a tiny device budget forces many HBM waves
     compare(hg.check_pairs(wl, max_device_bytes=1 << 22), base, "waves")
+
+
+def test_graph_replay_matches_eager(hg):
+    """The first phase is captured once and replayed: every replay, with
+    eager work and synchronisations between replays, equals the eager run
+    (log_level 2 runs the first phase eagerly) and the oracle."""
+    ctx = hg.default_context()
+    wl = configs.batched(seed=91, n_models=12, scale=0.05, max_iters=8)
+    say("graph replay")
+    want, _ = oracle.check_pairs(wl, "B", threads=8)
+    eager = hg.Plan(ctx, wl, log_level=2)
+    graph = hg.Plan(ctx, wl)
+    base = eager.execute()
+    compare(base, want, "eager")
+    for rep in range(4):
+        compare(graph.execute(), base, "replay %d" % rep)
+        compare(eager.execute(), base, "eager %d" % rep)
+        compare(hg.check_pairs(configs.tiny()), oracle.check_pairs(configs.tiny(), "B")[0],
+                "tiny between replays")
+    eager.close()
+    graph.close()
+
+
+def test_autotune_picks_a_shape_and_keeps_results(hg):
+    ctx = hg.Context(0)
+    wl = configs.batched(seed=92, n_models=8, scale=0.05, max_iters=8)
+    say("autotune")
+    cap, wave, ms = hg.rd_autotune(ctx, wl, reps=1)
+    say("autotune picked", cap, wave, ms)
+    assert cap in (1024, 1536, 3072) and wave in (48 << 20, 96 << 20, 192 << 20)
+    assert ms > 0
+    want, _ = oracle.check_pairs(wl, "B", threads=8)
+    compare(hg.rd_check_pairs(ctx, wl), want, "after autotune")
+
+
+@pytest.mark.parametrize("seed", range(0, 60, 6))
+def test_random_models_interpreter_only(hg, seed, monkeypatch):
+    """Term tables switched off (HGRD_INTERP): every point goes through the
+    expression interpreter; results stay identical to the oracle."""
+    monkeypatch.setenv("HGRD_INTERP", "1")
+    run_both(hg, rand_workload(seed), "rand interp seed=%d" % seed)
+    run_both(hg, configs.batched(seed=93, n_models=6, scale=0.05, max_iters=8),
+             "batched interp")
