@@ -246,9 +246,10 @@ void rd_plan_destroy(rd_plan* plan);
 /* The first phase of rd_execute (accumulator set-up, the VERDICT tile
  * search, the LDS joins of small items and the HBM partition waves) has no
  * host round trip; the first rd_execute of a plan captures it in a HIP
- * graph and later calls replay that graph (log_level 2 or the environment
- * variable HGRD_TIMING run it eagerly with per-kernel timing).  Calls on one
- * plan must not overlap. */
+ * graph and later calls replay that graph.  log_level 2 or the environment
+ * variable HGRD_TIMING run it eagerly instead, with HIP events around the
+ * partition kernels (rd_stats.scatter_ms and friends are only filled then
+ * for the first phase).  Calls on one plan must not overlap. */
 
 /* Batch autotuning: for the batch given (as rd_prepare), times rd_execute
  * for every LDS tile shape (1024, 1536, 3072 records) and partition-wave
@@ -286,6 +287,9 @@ typedef struct {
   uint64_t verdict_units; /* (query, tuple) units searched tile by tile */
   double split_ms;        /* items split by (address, block) */
   uint64_t split_items;
+  uint64_t scatter_launches; /* partition kernels timed in scatter_ms */
+  uint64_t scatter_bytes;    /* record bytes they wrote */
+  uint64_t fallback_records; /* point bound of the fallback items */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

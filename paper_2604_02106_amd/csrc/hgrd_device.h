@@ -156,17 +156,26 @@ __device__ __forceinline__ int64_t run_prog(const DInsn* __restrict__ code,
   return st[p.res];
 }
 
-// Point coordinates of point index `pidx` = (blin * niota + ilin) * nthr + tlin.
+// Point coordinates of point index `pidx`: (blin * niota + ilin) * nthr +
+// tlin, or (blin * nthr + tlin) * niota + ilin when iterations go fastest
+// (the block is always slowest, so block b owns [b * tpb, (b + 1) * tpb)).
 struct PointIds {
   uint32_t blin, tlin, ilin;
 };
 
 __device__ __forceinline__ PointIds decode(const DevInst& I, uint32_t pidx) {
   PointIds o;
-  uint32_t rest = fdiv(pidx, I.f_nthr);
-  o.tlin = pidx - rest * I.a.nthr;
-  o.blin = fdiv(rest, I.f_niota);
-  o.ilin = rest - o.blin * I.a.niota;
+  if (I.a.iorder) {
+    uint32_t rest = fdiv(pidx, I.f_niota);
+    o.ilin = pidx - rest * I.a.niota;
+    o.blin = fdiv(rest, I.f_nthr);
+    o.tlin = rest - o.blin * I.a.nthr;
+  } else {
+    uint32_t rest = fdiv(pidx, I.f_nthr);
+    o.tlin = pidx - rest * I.a.nthr;
+    o.blin = fdiv(rest, I.f_niota);
+    o.ilin = rest - o.blin * I.a.niota;
+  }
   return o;
 }
 
@@ -233,6 +242,34 @@ __device__ __forceinline__ bool eval_point(const DevInst& I,
   return e == 0;
 }
 
+// Table lookups only (the instance has term tables).
+__device__ __forceinline__ bool point_tab(const DevInst& I, const PointIds& id,
+                                          Point& pt) {
+  if (I.tnever) return false;
+  int64_t a = I.tu;
+  if (I.toff[0] != kNoTab) {
+    const int64_t v = I.tpool[I.toff[0] + id.blin];
+    if (v == INT64_MIN) return false;
+    a += v;
+  }
+  if (I.toff[1] != kNoTab) {
+    const int64_t v = I.tpool[I.toff[1] + id.tlin];
+    if (v == INT64_MIN) return false;
+    a += v;
+  }
+  if (I.toff[2] != kNoTab) {
+    const int64_t v = I.tpool[I.toff[2] + id.ilin];
+    if (v == INT64_MIN) return false;
+    a += v;
+  }
+  const uint32_t iv =
+      I.iv_off != kNoTab ? (uint32_t)I.tpool[I.iv_off + id.ilin] : I.iv_const;
+  pt.addr = a;
+  pt.bint = iv & 0xFFFF;
+  pt.wint = iv >> 16;
+  return true;
+}
+
 // Guard, address and interval ids of one point: table lookups when the
 // instance has term tables, else the interpreter.
 __device__ __forceinline__ bool point_eval(const DevInst& I, const PointIds& id,
@@ -240,31 +277,7 @@ __device__ __forceinline__ bool point_eval(const DevInst& I, const PointIds& id,
                                            const int64_t* __restrict__ params,
                                            const int64_t* __restrict__ loopvals,
                                            Point& pt, uint32_t& err) {
-  if (I.tab) {
-    if (I.tnever) return false;
-    int64_t a = I.tu;
-    if (I.toff[0] != kNoTab) {
-      const int64_t v = I.tpool[I.toff[0] + id.blin];
-      if (v == INT64_MIN) return false;
-      a += v;
-    }
-    if (I.toff[1] != kNoTab) {
-      const int64_t v = I.tpool[I.toff[1] + id.tlin];
-      if (v == INT64_MIN) return false;
-      a += v;
-    }
-    if (I.toff[2] != kNoTab) {
-      const int64_t v = I.tpool[I.toff[2] + id.ilin];
-      if (v == INT64_MIN) return false;
-      a += v;
-    }
-    const uint32_t iv =
-        I.iv_off != kNoTab ? (uint32_t)I.tpool[I.iv_off + id.ilin] : I.iv_const;
-    pt.addr = a;
-    pt.bint = iv & 0xFFFF;
-    pt.wint = iv >> 16;
-    return true;
-  }
+  if (I.tab) return point_tab(I, id, pt);
   Regs R;
   set_coords(I, id, loopvals, R);
   return eval_point(I, code, params, R, pt, err);

@@ -19,6 +19,7 @@
 #include "hgrd_launch.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -289,6 +290,50 @@ Prog compile(const rd_kernel_model& m, rd_expr e, const rd_access& a,
   return p;
 }
 
+// Host interpreter of compiled programs (same semantics as the device's).
+static int64_t host_prog(const std::vector<DInsn>& code, const Prog& p,
+                         const int64_t* coords, const int64_t* params,
+                         int64_t dflt, uint32_t& err) {
+  static const uint16_t kOp[] = {0, RD_OP_ADD, RD_OP_SUB, RD_OP_MUL, RD_OP_DIV,
+                                 RD_OP_MOD, RD_OP_SHL, RD_OP_SHR, RD_OP_AND,
+                                 RD_OP_OR, RD_OP_XOR, RD_OP_MIN, RD_OP_MAX,
+                                 RD_OP_LT, RD_OP_LE, RD_OP_EQ, RD_OP_NE,
+                                 RD_OP_GE, RD_OP_GT, RD_OP_LAND, RD_OP_LOR};
+  if (p.absent) return dflt;
+  int64_t st[kMaxStack];
+  for (uint32_t k = 0; k < p.n; ++k) {
+    const DInsn& in = code[p.off + k];
+    auto opnd = [&](uint8_t mode, uint16_t i) -> int64_t {
+      return mode == M_REG ? st[i] : mode == M_IMM ? in.imm
+             : mode == M_PARAM ? params[i] : coords[i];
+    };
+    const int64_t a = opnd(in.ma, in.a), b = opnd(in.mb, in.b);
+    int64_t r;
+    if (in.op == D_MOV) r = a;
+    else if (in.op == D_NEG) r = hop(RD_OP_SUB, 0, a, err);
+    else if (in.op == D_LNOT) r = a == 0;
+    else r = hop(kOp[in.op], a, b, err);
+    st[in.dst] = r;
+  }
+  return st[p.res];
+}
+
+static void host_coords(const AccInst& I, const std::vector<int64_t>& loops,
+                        uint32_t blin, uint32_t tlin, uint32_t ilin, int64_t* c) {
+  c[0] = tlin % I.dims[3];
+  c[1] = (tlin / I.dims[3]) % I.dims[4];
+  c[2] = tlin / (I.dims[3] * I.dims[4]);
+  c[3] = blin % I.dims[0];
+  c[4] = (blin / I.dims[0]) % I.dims[1];
+  c[5] = blin / (I.dims[0] * I.dims[1]);
+  c[6] = c[7] = c[8] = c[9] = 0;
+  uint32_t rem = ilin;
+  for (int k = (int)I.n_loops - 1; k >= 0; --k) {
+    c[6 + k] = loops[I.loop_off[k] + rem % I.loop_n[k]];
+    rem /= I.loop_n[k];
+  }
+}
+
 bool cmp_holds(uint32_t cmp, int64_t v, int64_t bound) {
   switch (cmp) {
     case RD_CMP_LT: return v < bound;
@@ -306,6 +351,55 @@ struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
 };
+
+uint64_t next_prime(uint64_t n) {
+  if (n <= 2) return 2;
+  for (uint64_t c = n | 1;; c += 2) {
+    bool prime = true;
+    for (uint64_t d = 3; d * d <= c; d += 2)
+      if (c % d == 0) {
+        prime = false;
+        break;
+      }
+    if (prime) return c;
+  }
+}
+
+// Bucket map of an HBM item whose instances have term tables: the dense key
+// ((addr - lo) >> shift) + blin * kb modulo a prime bucket count (mode 1),
+// when the key stays below 2^32; else the hash (mode 0).  per_block: keys
+// carry the block (shared arrays, split items).
+void set_bucket_map(HItem& h, const std::vector<uint8_t>& tab_on,
+                    const std::vector<std::pair<int64_t, int64_t>>& arange,
+                    uint32_t nblk, bool self, bool per_block, uint64_t R,
+                    uint32_t cap, double load) {
+  h.mode = 0;
+  h.kb = 0;
+  h.lo = 0;
+  h.fm = 0;
+  __int128 lo = 0, hi = -1;
+  bool first = true;
+  (void)self;  // a self pair names its one instance twice
+  for (uint32_t x : {h.inst_i, h.inst_j}) {
+    if (!tab_on[x]) return;
+    const auto& r = arange[x];
+    if (first || r.first < lo) lo = r.first;
+    if (first || r.second > hi) hi = r.second;
+    first = false;
+  }
+  if (hi < lo || hi - lo >= ((__int128)1 << 62)) return;
+  const __int128 kr = ((hi - lo) >> h.shift) + 1;
+  const __int128 kmax = per_block ? kr * nblk : kr;
+  if (kmax >= ((__int128)1 << 32)) return;
+  uint64_t nb = (uint64_t)((double)R / (cap * load)) + 1;
+  nb = nb <= 1 ? 1 : next_prime(nb);
+  if (nb >= (1ull << 31)) return;
+  h.mode = 1;
+  h.lo = (long long)lo;
+  h.kb = per_block ? (uint32_t)kr : 0;
+  h.nbuckets = (uint32_t)nb;
+  h.fm = ~0ull / nb + 1;
+}
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
@@ -326,6 +420,7 @@ struct rd_context {
   uint64_t wave_bytes = kWaveBytes;  // default partition wave size
   hipStream_t stream = nullptr;  // used when the caller passes no stream
   hipEvent_t ev[16];
+  std::vector<hipEvent_t> wev;    // per-wave timing events
   void* ensure(const char* name, size_t bytes, int* err) {
     DevBuf& b = bufs[name];
     if (bytes == 0) bytes = 256;
@@ -722,6 +817,7 @@ struct Planner {
   std::vector<int64_t> pool_loops;
   std::vector<AccInst> dev_insts;
   std::vector<TabHost> tabs;  // per device instance
+  std::vector<std::pair<int64_t, int64_t>> arange;  // address range, tables only
   std::vector<TabJob> tjobs;
   uint64_t tpool = 0;         // table entries
   bool use_tables = true;
@@ -837,6 +933,23 @@ struct Planner {
     T.iv_const = (uint32_t)ivc[0] | ((uint32_t)ivc[1] << 16);
     T.never = never;
     T.on = 1;
+    arange[inst] = {(int64_t)lo, (int64_t)hi};
+    // point order: iterations fastest when the address moves less along
+    // them than along threads (consecutive points then share buckets)
+    int64_t stride[3] = {0, 0, 0};
+    for (const TabJob& J : jobs) {
+      if (J.group == 0 || J.group == 3 || J.val.absent || J.n < 2) continue;
+      int64_t c[10];
+      uint32_t e = 0;
+      host_coords(I, pool_loops, 0, J.group == 1 ? 1 : 0, J.group == 2 ? 1 : 0, c);
+      const int64_t v1 = host_prog(this->code, J.val, c, pv, 0, e);
+      host_coords(I, pool_loops, 0, 0, 0, c);
+      const int64_t v0 = host_prog(this->code, J.val, c, pv, 0, e);
+      if (!e) stride[J.group] = v1 > v0 ? v1 - v0 : v0 - v1;
+      else stride[J.group] = INT64_MAX;
+    }
+    const bool t_moves = I.nthr > 1, i_moves = I.niota > 1;
+    dev_insts[inst].iorder = i_moves && (!t_moves || stride[2] < stride[1]) ? 1 : 0;
   }
 
   DimInfo& dim(uint32_t m, uint32_t s) {
@@ -977,6 +1090,7 @@ struct Planner {
     ii.npts = (uint32_t)box;
     dev_insts.push_back(I);
     TabHost T;
+    arange.push_back({0, -1});
     tables_for(m, a, I, (uint32_t)ii.idx, T);
     tabs.push_back(T);
     return ii;
@@ -1065,6 +1179,7 @@ void rd_context_destroy(rd_context* ctx) {
   for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+  for (auto& e : ctx->wev) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -1084,6 +1199,10 @@ struct rd_plan_impl {
   hipStream_t st = nullptr;
   std::vector<QPlan> Q;
   std::vector<uint32_t> npts;  // per device instance
+  std::vector<uint8_t> tab_on;  // per device instance: has term tables
+  std::vector<uint32_t> nblk;   // per device instance: blocks
+  std::vector<std::pair<int64_t, int64_t>> arange;  // address range (tables)
+  bool no_map = false;          // hash buckets only
   uint64_t evals = 0;
   uint32_t n_sitems = 0;
   uint32_t persist_grid = 0;  // workgroups of the persistent small join
@@ -1091,14 +1210,15 @@ struct rd_plan_impl {
   uint32_t n_insts = 0, tab_insts = 0;
   struct Wave {
     uint32_t first_item, n_items, n_chunks, n_buckets;
-    uint64_t key_bytes, pid_elems;
+    uint32_t n_tab_chunks;  // the first n_tab_chunks chunks have term tables
+    uint64_t key_bytes;
     uint64_t hitem_off, chunk_off, bitem_off;  // element offsets in the plan pools
   };
   std::vector<Wave> waves;
   std::vector<HItem> hitems;   // all waves, wave-local bucket numbering
   std::vector<uint64_t> hR;    // records bound per HBM item
   std::vector<uint8_t> herr_scan;  // error-scan-only items
-  uint64_t max_key_bytes = 0, max_pid_elems = 0, max_buckets = 0, max_items = 0;
+  uint64_t max_key_bytes = 0, max_buckets = 0, max_items = 0;
   uint64_t wave_budget = 0;
   // VERDICT mode
   bool verdict = false, use_mlp = false;
@@ -1249,6 +1369,22 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   auto npts_of = [&](int32_t idx) -> uint64_t {
     return idx < 0 ? 0 : P.dev_insts[idx].npts;
   };
+  // Bucket shift of an HBM item: blocks of 2^shift consecutive addresses
+  // should hold about 32 records, from the density (points per address of
+  // the tabulated range; per block for shared arrays) of the denser side.
+  auto item_shift = [&](int32_t ia, int32_t ib, bool self, bool shared) -> uint32_t {
+    double dens = 0;
+    for (int32_t x : {ia, ib}) {
+      if (self && x == ib) continue;
+      if (!P.tabs[x].on) return 0;
+      const double span = (double)P.arange[x].second - (double)P.arange[x].first + 1.0;
+      if (span < 1) return 0;
+      const double pts = shared ? P.dev_insts[x].tpb : P.dev_insts[x].npts;
+      dens = std::max(dens, pts / span);
+    }
+    if (dens <= 0 || 32.0 / dens < 2.0) return 0;
+    return (uint32_t)std::min(30.0, std::floor(std::log2(32.0 / dens)));
+  };
   for (uint32_t k = 0; k < n_pairs; ++k) {
     QPlan& q = Q[k];
     if (!q.work) continue;
@@ -1309,6 +1445,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         hp.h.inst_j = (uint32_t)ib;
         hp.h.shared = q.qd.shared;
         hp.h.is32 = R0.is32;
+        hp.h.shift = item_shift(ia, ib, q.qd.self, q.qd.shared);
         hp.R = tot;
         hplans.push_back(hp);
       }
@@ -1407,6 +1544,10 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     plan->n_titems = (uint32_t)titems.size();
   }
 
+  std::vector<uint8_t> tab_on(P.dev_insts.size());
+  for (size_t i = 0; i < P.dev_insts.size(); ++i) tab_on[i] = (uint8_t)P.tabs[i].on;
+  plan->no_map = getenv("HGRD_HASH_BUCKETS") != nullptr;
+
   // ---- waves of HBM items, bounded by the device budget --------------------
   // A wave's buckets are small enough to stay in the last-level cache while
   // they are filled and joined, so HBM sees whole lines.
@@ -1423,24 +1564,27 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     W.chunk_off = all_chunks.size();
     W.bitem_off = all_bitem.size();
     size_t end = pos;
-    uint64_t bytes = 0, nbk = 0, pid_base = 0;
+    uint64_t bytes = 0, nbk = 0;
     while (end < hplans.size()) {
       HPlan& hp = hplans[end];
       uint64_t nbuckets =
           hp.h.shared == 2 ? 0
                            : std::max<uint64_t>(1, (hp.R * 100 + cap * 55 - 1) / (cap * 55));
-      uint64_t ksz = hp.h.is32 ? 4 : 8;
-      uint64_t need = nbuckets * cap * (ksz + 4);
-      if (end > pos && bytes + pid_base * 4 + need > budget) break;
+      if (hp.h.shared != 2 && !plan->no_map) {
+        set_bucket_map(hp.h, tab_on, P.arange, P.dev_insts[hp.h.inst_i].nblk,
+                       Q[hp.h.q].qd.self, hp.h.shared == 1, hp.R, cap, 0.6);
+        if (hp.h.mode) nbuckets = hp.h.nbuckets;
+      }
+      const uint64_t need = nbuckets * cap * (hp.h.is32 ? 8 : 16);
+      if (end > pos && bytes + need > budget) break;
       hp.h.nbuckets = (uint32_t)nbuckets;
       hp.h.bucket0 = (uint32_t)nbk;
-      hp.h.key_off = bytes;
-      hp.h.pid_off = pid_base;
-      bytes += (nbuckets * cap * ksz + 255) / 256 * 256;
-      pid_base += nbuckets * cap;
+      hp.h.rec_off = bytes;
+      bytes += (need + 255) / 256 * 256;
       nbk += nbuckets;
       ++end;
     }
+    std::vector<Chunk> interp;  // chunks of instances without tables go last
     for (size_t i = pos; i < end; ++i) {
       const HItem& h = hplans[i].h;
       uint32_t li = (uint32_t)plan->hitems.size();  // global item index
@@ -1451,17 +1595,18 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       for (int side = 0; side < (q.qd.self || h.shared == 2 ? 1 : 2); ++side) {
         uint32_t inst = side ? h.inst_j : h.inst_i;
         uint32_t np = P.dev_insts[inst].npts;
+        std::vector<Chunk>& dst = P.tabs[inst].on ? all_chunks : interp;
         for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
-          all_chunks.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+          dst.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
       }
     }
+    W.n_tab_chunks = (uint32_t)(all_chunks.size() - W.chunk_off);
+    all_chunks.insert(all_chunks.end(), interp.begin(), interp.end());
     W.n_items = (uint32_t)(end - pos);
     W.n_chunks = (uint32_t)(all_chunks.size() - W.chunk_off);
     W.n_buckets = (uint32_t)nbk;
     W.key_bytes = bytes;
-    W.pid_elems = pid_base;
     plan->max_key_bytes = std::max(plan->max_key_bytes, bytes);
-    plan->max_pid_elems = std::max(plan->max_pid_elems, pid_base);
     plan->max_buckets = std::max(plan->max_buckets, nbk);
     plan->max_items = std::max<uint64_t>(plan->max_items, W.n_items);
     plan->waves.push_back(W);
@@ -1485,7 +1630,13 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   plan->n_tabchunks = (uint32_t)tabchunks.size();
   plan->n_insts = (uint32_t)P.dev_insts.size();
   plan->npts.resize(P.dev_insts.size());
-  for (size_t i = 0; i < P.dev_insts.size(); ++i) plan->npts[i] = P.dev_insts[i].npts;
+  plan->nblk.resize(P.dev_insts.size());
+  for (size_t i = 0; i < P.dev_insts.size(); ++i) {
+    plan->npts[i] = P.dev_insts[i].npts;
+    plan->nblk[i] = P.dev_insts[i].nblk;
+  }
+  plan->tab_on = tab_on;
+  plan->arange = P.arange;
   std::vector<QDesc> qd(n_pairs);
   std::vector<uint32_t> herr(n_pairs);
   std::vector<uint8_t> triv(n_pairs);
@@ -1537,12 +1688,12 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   plan->buf("qacc", std::max<size_t>(1, n_pairs) * sizeof(QAcc), &merr);
   // scratch of the first phase belongs to the plan (a captured graph keeps
   // these addresses)
-  plan->buf("keys", plan->max_key_bytes, &merr);
-  plan->buf("pids", plan->max_pid_elems * 4, &merr);
+  plan->buf("recs", plan->max_key_bytes, &merr);
   plan->buf("cursor", plan->max_buckets * 4, &merr);
   plan->buf("ovf", std::max<size_t>(1, plan->hitems.size()) * 4, &merr);
   plan->buf("done", std::max<size_t>(1, n_pairs) * 4, &merr);
   plan->buf("pcursor", 4, &merr);
+  plan->buf("nbytes", 64 * 8, &merr);
   plan->buf("out", std::max<size_t>(1, n_pairs) * sizeof(rd_pair_result), &merr);
   if (merr) return merr;
   *plan_out = guard.release();
@@ -1582,11 +1733,11 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   const uint32_t* d_bitem_all = (const uint32_t*)D("bitem");
   // first-phase scratch owned by the plan (fixed addresses, so a captured
   // graph stays valid); later phases reuse the context's arena
-  unsigned char* d_keys = (unsigned char*)D("keys");
-  uint32_t* d_pids = (uint32_t*)D("pids");
+  unsigned char* d_recs = (unsigned char*)D("recs");
   uint32_t* d_cursor = (uint32_t*)D("cursor");
   uint32_t* d_done = (uint32_t*)D("done");
   uint32_t* d_pcursor = (uint32_t*)D("pcursor");
+  u64* d_nbytes = (u64*)D("nbytes");
   const uint32_t nh = (uint32_t)plan->hitems.size();
   uint32_t* d_ovf_all = (uint32_t*)D("ovf");
   hipEvent_t* ev = ctx->ev;
@@ -1596,37 +1747,68 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   double fallback_ms = 0, retry_ms = 0, split_ms = 0, waves_ms = 0;
   std::vector<uint32_t> skip;  // kept alive until the stream is synchronised
 
+  // Every eagerly launched partition wave is bracketed by events from the
+  // context's pool (scatter start, scatter end = join start, join end);
+  // their times are collected once the stream has drained.  A replayed
+  // graph carries no events (their times are not reliable inside graphs).
+  uint32_t wev_n = 0;
+  std::vector<std::array<uint32_t, 3>> wtimes;
+  auto wevent = [&](uint32_t k) -> hipEvent_t {
+    while (ctx->wev.size() <= k) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ctx->wev.push_back(e);
+    }
+    return ctx->wev[k];
+  };
   auto run_waves = [&](const std::vector<rd_plan_impl::Wave>& waves,
                        const HItem* d_hit, const Chunk* d_chk,
                        const uint32_t* d_bit, uint32_t* d_ovf, int wcfg,
                        const u64* l0k, const u64* l0c, bool events) -> int {
     const uint32_t wcap = (uint32_t)join_cap(wcfg);
     for (const auto& W : waves) {
+      const uint32_t k = wev_n;
+      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+      if (events) {
+        wev_n += 3;
+        e0 = wevent(k);
+        e1 = wevent(k + 1);
+        e2 = wevent(k + 2);
+        if (!e0 || !e1 || !e2) return RD_EDEVICE;
+      }
       if (launch_fill_u32(st, d_cursor, W.n_buckets, 0)) return RD_EDEVICE;
-      if (events) TRY_HIP(hipEventRecord(ev[4], st));
+      if (events) TRY_HIP(hipEventRecord(e0, st));
       if (launch_scatter(st, d_chk + W.chunk_off, W.n_chunks, d_hit, d_insts,
-                         d_code, d_params, d_loops, d_acc, d_keys, d_pids,
-                         d_cursor, d_ovf, wcap, d_done))
+                         d_code, d_params, d_loops, d_acc, d_recs,
+                         d_cursor, d_ovf, wcap, d_done, d_nbytes, W.n_tab_chunks))
         return RD_EDEVICE;
-      if (events) TRY_HIP(hipEventRecord(ev[5], st));
+      if (events) TRY_HIP(hipEventRecord(e1, st));
       if (W.n_buckets &&
           launch_bucket(wcfg, st, W.n_buckets, 0, d_bit + W.bitem_off, d_hit,
-                        d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_keys,
-                        d_pids, d_cursor, d_ovf, d_done, l0k, l0c))
+                        d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs,
+                        d_cursor, d_ovf, d_done, l0k, l0c))
         return RD_EDEVICE;
+      if (events) {
+        TRY_HIP(hipEventRecord(e2, st));
+        wtimes.push_back({k, k + 1, k + 2});
+      }
       if (W.n_buckets) S.join_launches += 1;
       S.buckets += W.n_buckets;
-      if (events && timing) {
-        TRY_HIP(hipEventRecord(ev[6], st));
-        TRY_HIP(hipEventSynchronize(ev[6]));
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, ev[4], ev[5]);
-        scatter_ms += ms;
-        (void)hipEventElapsedTime(&ms, ev[5], ev[6]);
-        bucket_ms += ms;
-      }
     }
     return RD_OK;
+  };
+  auto collect_waves = [&]() {
+    for (const auto& t : wtimes) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, ctx->wev[t[0]], ctx->wev[t[1]]) == hipSuccess) {
+        scatter_ms += ms;
+        S.scatter_launches += 1;
+      }
+      if (hipEventElapsedTime(&ms, ctx->wev[t[1]], ctx->wev[t[2]]) == hipSuccess)
+        bucket_ms += ms;
+    }
+    wtimes.clear();
+    (void)hipGetLastError();
   };
 
   // ---- first phase: accumulator init, VERDICT tile search, LDS joins of
@@ -1640,6 +1822,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       return RD_EDEVICE;
     if (launch_init_acc(st, n_pairs, d_acc)) return RD_EDEVICE;
     if (launch_fill_u32(st, d_done, n_pairs, 0)) return RD_EDEVICE;
+    if (launch_fill_u64(st, d_nbytes, 64, 0)) return RD_EDEVICE;
     if (plan->verdict && plan->n_vq) {
       VQuery* d_vq = (VQuery*)D("vq");
       BBound* d_bb = (BBound*)D("bbounds");
@@ -1696,7 +1879,10 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     hipGraph_t g = nullptr;
     bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
+      // no events inside the graph: their times are not reliable there
       int rc = phase1(false);
+      wtimes.clear();
+      wev_n = 0;
       ok = hipStreamEndCapture(st, &g) == hipSuccess && rc == RD_OK && g;
       if (ok) ok = hipGraphInstantiate(&plan->graph, g, nullptr, nullptr, 0) == hipSuccess;
       if (g) (void)hipGraphDestroy(g);
@@ -1729,25 +1915,19 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   if (nh) TRY_HIP(hipMemcpyAsync(ovf.data(), d_ovf_all, nh * 4, hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
   {
+    // events recorded inside a replayed graph time the same way; a failed
+    // query leaves the figure at 0
     float ms = 0;
-    if (replayed) {
-      (void)hipEventElapsedTime(&ms, ev[0], ev[13]);
-      waves_ms = ms;  // the whole first phase
-    } else {
-      if (plan->verdict && plan->n_vq) {
-        (void)hipEventElapsedTime(&ms, ev[15], ev[1]);
-        verdict_ms = ms;
-      }
-      if (plan->n_sitems) {
-        (void)hipEventElapsedTime(&ms, ev[2], ev[3]);
-        small_ms = ms;
-      }
-      if (nh) {
-        (void)hipEventElapsedTime(&ms, ev[11], ev[12]);
-        waves_ms = ms;  // scatter and bucket joins together
-      }
-    }
+    if (plan->verdict && plan->n_vq && hipEventElapsedTime(&ms, ev[15], ev[1]) == hipSuccess)
+      verdict_ms = ms;
+    if (plan->n_sitems && hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess)
+      small_ms = ms;
+    if (nh && hipEventElapsedTime(&ms, ev[11], ev[12]) == hipSuccess)
+      waves_ms = ms;  // scatter and bucket joins together
+    (void)hipGetLastError();
+    (void)replayed;
   }
+  collect_waves();
 
   // ---- re-partition overflowed items ---------------------------------------
   // Round 1 retries with more buckets (bucket loads vary with how many points
@@ -1766,48 +1946,50 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     std::vector<Chunk> chunks;
     std::vector<uint32_t> bitem;
     std::vector<HItem> hs;
-    uint64_t max_bytes = 0, max_pids = 0, max_nbk = 0;
+    std::vector<Chunk> interp;
+    uint64_t max_bytes = 0, max_nbk = 0;
     size_t pos = 0;
     while (pos < items.size()) {
       rd_plan_impl::Wave W;
       memset(&W, 0, sizeof W);
       W.chunk_off = chunks.size();
       W.bitem_off = bitem.size();
-      uint64_t bytes = 0, nbk = 0, pid_base = 0;
+      uint64_t bytes = 0, nbk = 0;
       size_t end = pos;
       while (end < items.size()) {
         HItem h = items[end].h;
-        uint64_t ksz = h.is32 ? 4 : 8;
-        uint64_t need = (uint64_t)h.nbuckets * wcap * (ksz + 4);
-        if (end > pos && bytes + pid_base * 4 + need > plan->wave_budget) break;
+        const uint64_t need = (uint64_t)h.nbuckets * wcap * (h.is32 ? 8 : 16);
+        if (end > pos && bytes + need > plan->wave_budget) break;
         h.bucket0 = (uint32_t)nbk;
-        h.key_off = bytes;
-        h.pid_off = pid_base;
-        bytes += ((uint64_t)h.nbuckets * wcap * ksz + 255) / 256 * 256;
-        pid_base += (uint64_t)h.nbuckets * wcap;
+        h.rec_off = bytes;
+        if (!h.mode) h.shift = 0;  // hashed re-partitions: single addresses
+        bytes += (need + 255) / 256 * 256;
         nbk += h.nbuckets;
         uint32_t li = (uint32_t)hs.size();
         hs.push_back(h);
         for (uint32_t b = 0; b < h.nbuckets; ++b) bitem.push_back(li);
         const QPlan& q = plan->Q[h.q];
         for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
-          uint32_t np = plan->npts[side ? h.inst_j : h.inst_i];
+          const uint32_t inst = side ? h.inst_j : h.inst_i;
+          uint32_t np = plan->npts[inst];
+          std::vector<Chunk>& dst = plan->tab_on[inst] ? chunks : interp;
           for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
-            chunks.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+            dst.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
         }
         ++end;
       }
+      W.n_tab_chunks = (uint32_t)(chunks.size() - W.chunk_off);
+      chunks.insert(chunks.end(), interp.begin(), interp.end());
+      interp.clear();
       W.n_items = (uint32_t)(end - pos);
       W.n_chunks = (uint32_t)(chunks.size() - W.chunk_off);
       W.n_buckets = (uint32_t)nbk;
       waves.push_back(W);
       max_bytes = std::max(max_bytes, bytes);
-      max_pids = std::max(max_pids, pid_base);
       max_nbk = std::max(max_nbk, nbk);
       pos = end;
     }
-    d_keys = (unsigned char*)ctx->ensure("keys", std::max<uint64_t>(max_bytes, plan->max_key_bytes), &merr);
-    d_pids = (uint32_t*)ctx->ensure("pids", std::max<uint64_t>(max_pids, plan->max_pid_elems) * 4, &merr);
+    d_recs = (unsigned char*)ctx->ensure("recs", std::max<uint64_t>(max_bytes, plan->max_key_bytes), &merr);
     d_cursor = (uint32_t*)ctx->ensure("cursor", std::max<uint64_t>(max_nbk, plan->max_buckets) * 4, &merr);
     const uint32_t nr = (uint32_t)hs.size();
     HItem* d_rh = (HItem*)ctx->ensure("r_hitems", nr * sizeof(HItem), &merr);
@@ -1827,6 +2009,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     TRY_HIP(hipMemcpyAsync(ovf_out.data(), d_rovf, nr * 4, hipMemcpyDeviceToHost, st));
     TRY_HIP(hipStreamSynchronize(st));
     (void)hipEventElapsedTime(&ms_out, ev[13], ev[14]);
+    collect_waves();
     return RD_OK;
   };
 
@@ -1837,6 +2020,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     uint64_t need_f = (ovf[i] * 10ull + cap * 6 - 1) / (cap * 6);
     need_f = std::min<uint64_t>(std::max<uint64_t>(need_f, 2), 64);
     r.h.nbuckets = (uint32_t)((uint64_t)r.h.nbuckets * need_f);
+    r.h.mode = 0;
     rit.push_back(r);
   }
   S.retry_items = rit.size();
@@ -1869,6 +2053,10 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       r.h.l0_off = slots;
       r.h.l0_mask = (uint32_t)(t - 1);
       r.h.nbuckets = (uint32_t)std::max<uint64_t>(1, (r.R * 100 + scap * 55 - 1) / (scap * 55));
+      r.h.shift = 0;
+      if (!plan->no_map)
+        set_bucket_map(r.h, plan->tab_on, plan->arange, plan->nblk[r.h.inst_i],
+                       q.qd.self, true, r.R, scap, 0.5);
       L0Item li;
       memset(&li, 0, sizeof li);
       li.q = r.h.q;
@@ -1944,6 +2132,10 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     f.mask = q.qd.mask;
     f.warp = q.qd.warp;
     f.cap = (uint32_t)direct[i].R;
+    S.fallback_records += direct[i].R;
+    if (plan->log_level >= 2)
+      fprintf(stderr, "hgrd: fallback item pair=%u tuple=%u shared=%u points=%llu buckets=%u\n",
+              h.q, h.sigma, h.shared, (unsigned long long)direct[i].R, h.nbuckets);
     fall.push_back(f);
   }
   S.overflow_items = fall.size();
@@ -2039,7 +2231,10 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   TRY_HIP(hipEventRecord(ev[1], st));
   if (n_pairs)
     TRY_HIP(hipMemcpyAsync(out, d_out, n_pairs * sizeof(rd_pair_result), hipMemcpyDeviceToHost, st));
+  u64 scat_bytes[64];
+  TRY_HIP(hipMemcpyAsync(scat_bytes, d_nbytes, sizeof scat_bytes, hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
+  for (u64 b : scat_bytes) S.scatter_bytes += b;
   float ms = 0;
   if (!w2.empty()) {
     (void)hipEventElapsedTime(&ms, ev[9], ev[10]);
@@ -2047,6 +2242,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   }
   (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
   S.device_ms = ms;
+  collect_waves();
   S.scatter_ms = scatter_ms;
   S.join_ms = small_ms + bucket_ms;
   S.join_kernel_ms = small_ms + bucket_ms;
@@ -2329,50 +2525,6 @@ int rd_mlp_train(rd_context* ctx, rd_mlp* w, const float* X, const float* Y,
   TRY_HIP(hipMemcpyAsync(w, d.w, nw, hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
   return RD_OK;
-}
-
-// Host interpreter of compiled programs (same semantics as the device's).
-static int64_t host_prog(const std::vector<DInsn>& code, const Prog& p,
-                         const int64_t* coords, const int64_t* params,
-                         int64_t dflt, uint32_t& err) {
-  static const uint16_t kOp[] = {0, RD_OP_ADD, RD_OP_SUB, RD_OP_MUL, RD_OP_DIV,
-                                 RD_OP_MOD, RD_OP_SHL, RD_OP_SHR, RD_OP_AND,
-                                 RD_OP_OR, RD_OP_XOR, RD_OP_MIN, RD_OP_MAX,
-                                 RD_OP_LT, RD_OP_LE, RD_OP_EQ, RD_OP_NE,
-                                 RD_OP_GE, RD_OP_GT, RD_OP_LAND, RD_OP_LOR};
-  if (p.absent) return dflt;
-  int64_t st[kMaxStack];
-  for (uint32_t k = 0; k < p.n; ++k) {
-    const DInsn& in = code[p.off + k];
-    auto opnd = [&](uint8_t mode, uint16_t i) -> int64_t {
-      return mode == M_REG ? st[i] : mode == M_IMM ? in.imm
-             : mode == M_PARAM ? params[i] : coords[i];
-    };
-    const int64_t a = opnd(in.ma, in.a), b = opnd(in.mb, in.b);
-    int64_t r;
-    if (in.op == D_MOV) r = a;
-    else if (in.op == D_NEG) r = hop(RD_OP_SUB, 0, a, err);
-    else if (in.op == D_LNOT) r = a == 0;
-    else r = hop(kOp[in.op], a, b, err);
-    st[in.dst] = r;
-  }
-  return st[p.res];
-}
-
-static void host_coords(const AccInst& I, const std::vector<int64_t>& loops,
-                        uint32_t blin, uint32_t tlin, uint32_t ilin, int64_t* c) {
-  c[0] = tlin % I.dims[3];
-  c[1] = (tlin / I.dims[3]) % I.dims[4];
-  c[2] = tlin / (I.dims[3] * I.dims[4]);
-  c[3] = blin % I.dims[0];
-  c[4] = (blin / I.dims[0]) % I.dims[1];
-  c[5] = blin / (I.dims[0] * I.dims[1]);
-  c[6] = c[7] = c[8] = c[9] = 0;
-  uint32_t rem = ilin;
-  for (int k = (int)I.n_loops - 1; k >= 0; --k) {
-    c[6 + k] = loops[I.loop_off[k] + rem % I.loop_n[k]];
-    rem /= I.loop_n[k];
-  }
 }
 
 int rd_table_selftest(const rd_kernel_model* models, uint32_t n_models,

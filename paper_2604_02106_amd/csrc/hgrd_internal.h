@@ -61,7 +61,11 @@ struct alignas(16) AccInst {
   uint32_t is32;                 // 32-bit array
   uint32_t npts;                 // nblk * nthr * niota (< 2^31)
   uint32_t tpb;                  // nthr * niota (points per block)
+  uint32_t iorder;               // point order inside a block: 0 thread
+                                 // fastest, 1 iteration fastest
+  uint32_t pad_;
 };
+static_assert(sizeof(AccInst) == 128, "AccInst layout");
 
 // Term tables of one instance.  When an expression is proven free of
 // errors over the whole launch box it is split into a uniform part and one
@@ -129,11 +133,24 @@ struct HItem {
   uint32_t bucket0;       // first global bucket index
   uint32_t shared;        // hash (addr, blin) instead of addr
   uint32_t is32;          // 32-bit keys
-  unsigned long long key_off;  // byte offset of bucket 0's keys
-  unsigned long long pid_off;  // element offset of bucket 0's point ids
+  unsigned long long rec_off;  // byte offset of bucket 0's records
+  unsigned long long pad0;
   unsigned long long l0_off;   // mode 3: the item's address-count table
-  uint32_t l0_mask, pad;       //   (slots l0_off .. l0_off + l0_mask + 1)
+  uint32_t l0_mask;            //   (slots l0_off .. l0_off + l0_mask + 1)
+  uint32_t shift;              // buckets see address >> shift (blocks of
+                               // 2^shift consecutive addresses stay together)
+  // Bucket map.  mode 0: a hash of the key.  mode 1: the key
+  //   k = ((addr - lo) >> shift) + blin * kb   (below 2^32 by construction)
+  // modulo nbuckets (a prime), so a dense key range fills the buckets
+  // evenly whatever the group sizes; fm = floor(2^64 / nbuckets) + 1.
+  uint32_t mode, kb;
+  long long lo;
+  unsigned long long fm;
+  unsigned long long pad1;
 };
+static_assert(sizeof(HItem) == 96, "HItem layout");
+// Records: int32 keys as one u64 (address | point id << 32), int64 keys as
+// 16 bytes (address, point id); point id = side << 31 | point index.
 // HItem.shared: 0 global (hash of the address), 1 shared array (hash of
 // address and block), 2 error scan only (never joined), 3 global item split
 // by (address, block) with its level 0 counted in an address-count table.

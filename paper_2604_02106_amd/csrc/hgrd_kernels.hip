@@ -170,48 +170,135 @@ __device__ __forceinline__ u64 mix64(u64 x) {
   return x;
 }
 
+// Bucket of a record.  mode 1: the dense key modulo the prime bucket count
+// (Lemire's 32-bit fastmod: one 64-bit multiply and a multiply-high);
+// mode 0: a hash of (address >> shift), and of the block for shared arrays
+// and split items.
+__device__ __forceinline__ uint32_t bucket_of(const HItem& h, int64_t addr,
+                                              uint32_t blin) {
+  if (h.mode) {
+    const uint32_t k = (uint32_t)((u64)(addr - h.lo) >> h.shift) + blin * h.kb;
+    return (uint32_t)__umul64hi(h.fm * (u64)k, (u64)h.nbuckets);
+  }
+  u64 hk = (u64)(addr >> h.shift);
+  if (h.shared == 1 || h.shared == 3) hk ^= (u64)(blin + 1) * 0x9E3779B97F4A7C15ull;
+  return (uint32_t)__umul64hi(mix64(hk), (u64)h.nbuckets);
+}
+
+// One workgroup takes one chunk of one side: it generates the points,
+// merges the chunk's records per bucket in LDS (open addressing on the
+// bucket id; each record gets its rank in its bucket from an LDS atomic),
+// reserves each bucket's run with one global atomic (all of a tile's
+// reservations in flight at once), then writes the runs.  Points follow
+// address order closely (see iorder) and buckets keep blocks of 2^shift
+// addresses together, so a chunk touches few buckets and its writes are
+// runs of whole lines.  TAB: every instance of the launch has term tables
+// (no interpreter code, fewer registers, more waves in flight).
+constexpr uint32_t kScatterPts = 1024;  // points per LDS tile
+constexpr uint32_t kScatterSlots = 2048;
+constexpr uint32_t kByteSlots = 64;     // spread of the record-byte counters
+template <bool TAB>
 __global__ void __launch_bounds__(256)
 k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
           const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
           const int64_t* __restrict__ params,
           const int64_t* __restrict__ loopvals, QAcc* __restrict__ acc,
-          unsigned char* __restrict__ keys, uint32_t* __restrict__ pids,
-          uint32_t* __restrict__ cursor, uint32_t* __restrict__ ovf,
-          uint32_t capb, const uint32_t* __restrict__ done) {
+          unsigned char* __restrict__ recs, uint32_t* __restrict__ cursor,
+          uint32_t* __restrict__ ovf, uint32_t capb, const uint32_t* __restrict__ done,
+          u64* __restrict__ nbytes) {
+  __shared__ uint32_t skey[kScatterSlots];  // bucket + 1, 0 = empty
+  __shared__ uint32_t scnt[kScatterSlots];  // count, then the run's base
+  __shared__ uint16_t used[kScatterPts];    // slots taken in this tile
+  __shared__ uint32_t nused;
+  __shared__ u64 sbytes;
   const Chunk ch = chunks[blockIdx.x];
   const HItem h = hitems[ch.item];
   if (done[h.q]) return;
   DevInst I;
   load_inst(I, insts, ch.side ? h.inst_j : h.inst_i);
   uint32_t err = 0;
-  bool over = false;
-  for (uint32_t base = ch.p0; base < ch.p1; base += blockDim.x) {
-    uint32_t pidx = base + threadIdx.x;
-    if (pidx >= ch.p1) break;
-    PointIds id = decode(I, pidx);
-    Point pt;
-    if (!point_eval(I, id, code, params, loopvals, pt, err)) continue;
-    if (h.nbuckets == 0) continue;  // error scan only
-    u64 hk = (u64)pt.addr;
-    if (h.shared == 1 || h.shared == 3) hk ^= (u64)(id.blin + 1) * 0x9E3779B97F4A7C15ull;
-    uint32_t b = (uint32_t)__umul64hi(mix64(hk), (u64)h.nbuckets);
-    uint32_t g = h.bucket0 + b;
-    uint32_t pos = atomicAdd(&cursor[g], 1u);
-    if (pos < capb) {
-      u64 slot = (u64)b * capb + pos;
-      if (h.is32)
-        reinterpret_cast<int32_t*>(keys + h.key_off)[slot] = (int32_t)pt.addr;
-      else
-        reinterpret_cast<int64_t*>(keys + h.key_off)[slot] = pt.addr;
-      pids[h.pid_off + slot] = (ch.side << 31) | pidx;
-    } else {
-      over = true;
-      atomicMax(&ovf[ch.item], pos + 1);  // largest bucket load seen
-    }
+  const bool store = h.nbuckets != 0;  // 0: error scan only
+  const uint32_t rs = h.is32 ? 8 : 16;
+  constexpr int kPer = kScatterPts / 256;
+  for (uint32_t k = threadIdx.x; k < kScatterSlots; k += 256) {
+    skey[k] = 0;
+    scnt[k] = 0;
   }
-  err = wave_or(err);
-  if ((threadIdx.x & 63) == 0 && err) atomicOr(&acc[h.q].err, err);
-  (void)over;
+  if (threadIdx.x == 0) {
+    nused = 0;
+    sbytes = 0;
+  }
+  for (uint32_t t0 = ch.p0; t0 < ch.p1; t0 += kScatterPts) {
+    __syncthreads();
+    int64_t ad[kPer];
+    uint32_t pv[kPer], sl[kPer], rk[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      sl[j] = kScatterSlots;
+      const uint32_t pidx = t0 + (uint32_t)j * 256 + threadIdx.x;
+      if (pidx >= ch.p1) continue;
+      const PointIds id = decode(I, pidx);
+      Point pt;
+      const bool ok = TAB ? point_tab(I, id, pt)
+                          : point_eval(I, id, code, params, loopvals, pt, err);
+      if (!ok || !store) continue;
+      const uint32_t b = bucket_of(h, pt.addr, id.blin);
+      uint32_t s = (b * 0x9E3779B1u) >> 21;  // 11 bits: kScatterSlots
+      for (;;) {
+        const uint32_t k = atomicCAS(&skey[s], 0u, b + 1);
+        if (k == 0) used[atomicAdd(&nused, 1u)] = (uint16_t)s;
+        if (k == 0 || k == b + 1) break;
+        s = (s + 1) & (kScatterSlots - 1);
+      }
+      sl[j] = s;
+      rk[j] = atomicAdd(&scnt[s], 1u);
+      ad[j] = pt.addr;
+      pv[j] = (ch.side << 31) | pidx;
+    }
+    __syncthreads();
+    // one reservation per bucket present in the tile; scnt becomes the base
+    const uint32_t nu = nused;
+    u64 written = 0;
+    for (uint32_t u = threadIdx.x; u < nu; u += 256) {
+      const uint32_t k = used[u];
+      const uint32_t n = scnt[k];
+      const uint32_t base = atomicAdd(&cursor[h.bucket0 + skey[k] - 1], n);
+      if (base + n > capb) atomicMax(&ovf[ch.item], base + n);  // largest load
+      const uint32_t kept = base >= capb ? 0 : (base + n > capb ? capb - base : n);
+      written += (u64)kept * rs;
+      scnt[k] = base;
+    }
+    written = wave_sum(written);
+    if ((threadIdx.x & 63) == 0 && written) atomicAdd(&sbytes, written);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      if (sl[j] == kScatterSlots) continue;
+      const uint32_t pos = scnt[sl[j]] + rk[j];
+      if (pos >= capb) continue;
+      const u64 slot = (u64)(skey[sl[j]] - 1) * capb + pos;
+      if (h.is32) {
+        reinterpret_cast<u64*>(recs + h.rec_off)[slot] =
+            (u64)(uint32_t)(int32_t)ad[j] | ((u64)pv[j] << 32);
+      } else {
+        reinterpret_cast<ulonglong2*>(recs + h.rec_off)[slot] =
+            make_ulonglong2((u64)ad[j], (u64)pv[j]);
+      }
+    }
+    __syncthreads();
+    // clear the slots this tile used
+    for (uint32_t u = threadIdx.x; u < nu; u += 256) {
+      skey[used[u]] = 0;
+      scnt[used[u]] = 0;
+    }
+    if (threadIdx.x == 0) nused = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && sbytes) atomicAdd(&nbytes[blockIdx.x & (kByteSlots - 1)], sbytes);
+  if (!TAB) {
+    err = wave_or(err);
+    if ((threadIdx.x & 63) == 0 && err) atomicOr(&acc[h.q].err, err);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -343,8 +430,7 @@ k_bucket_join(const uint32_t* __restrict__ bucket_item,
               const int64_t* __restrict__ params,
               const int64_t* __restrict__ loopvals,
               const QDesc* __restrict__ qd, QAcc* __restrict__ acc,
-              const unsigned char* __restrict__ keys,
-              const uint32_t* __restrict__ pids,
+              const unsigned char* __restrict__ recs,
               const uint32_t* __restrict__ cursor,
               const uint32_t* __restrict__ ovf, uint32_t bucket_base,
               const uint32_t* __restrict__ done, const u64* __restrict__ l0keys,
@@ -366,14 +452,19 @@ k_bucket_join(const uint32_t* __restrict__ bucket_item,
     DevInst I;
     load_inst(I, insts, side ? h.inst_j : h.inst_i);
     for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
-      uint32_t pid = pids[h.pid_off + slot0 + r];
+      uint32_t pid;
+      int64_t a;
+      if (h.is32) {
+        const u64 rec = reinterpret_cast<const u64*>(recs + h.rec_off)[slot0 + r];
+        pid = (uint32_t)(rec >> 32);
+        a = (int32_t)(uint32_t)rec;
+      } else {
+        const ulonglong2 rec = reinterpret_cast<const ulonglong2*>(recs + h.rec_off)[slot0 + r];
+        pid = (uint32_t)rec.y;
+        a = (int64_t)rec.x;
+      }
       if ((pid >> 31) != (uint32_t)side) continue;
       PointIds id = decode(I, pid & 0x7FFFFFFFu);
-      int64_t a;
-      if (h.is32)
-        a = reinterpret_cast<const int32_t*>(keys + h.key_off)[slot0 + r];
-      else
-        a = reinterpret_cast<const int64_t*>(keys + h.key_off)[slot0 + r];
       uint32_t bi, wi;
       point_iv(I, id, code, params, loopvals, bi, wi);
       S.addr[r] = (u64)a;
@@ -817,14 +908,14 @@ static int launch_bucket_t(hipStream_t st, uint32_t nb, uint32_t base,
                            const DevInst* insts, const DInsn* code,
                            const int64_t* params, const int64_t* loopvals,
                            const QDesc* qd, QAcc* acc,
-                           const unsigned char* keys, const uint32_t* pids,
+                           const unsigned char* recs,
                            const uint32_t* cursor, const uint32_t* ovf,
                            const uint32_t* done, const u64* l0keys,
                            const u64* l0cnt) {
   size_t lds = sizeof(JoinLds<CAP, TBL>);
   hipLaunchKernelGGL((k_bucket_join<CAP, TBL>), dim3(nb), dim3(256), lds, st,
                      bucket_item, hitems, insts, code, params, loopvals, qd,
-                     acc, keys, pids, cursor, ovf, base, done, l0keys, l0cnt);
+                     acc, recs, cursor, ovf, base, done, l0keys, l0cnt);
   HGRD_CHECK(hipGetLastError());
   return 0;
 }
@@ -917,13 +1008,21 @@ int launch_tabulate(hipStream_t st, const Chunk* chunks, uint32_t n,
 int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n,
                    const HItem* hitems, const void* insts, const DInsn* code,
                    const int64_t* params, const int64_t* loopvals, QAcc* acc,
-                   unsigned char* keys, uint32_t* pids, uint32_t* cursor,
-                   uint32_t* ovf, uint32_t capb, const uint32_t* done) {
+                   unsigned char* recs, uint32_t* cursor,
+                   uint32_t* ovf, uint32_t capb, const uint32_t* done,
+                   unsigned long long* nbytes, uint32_t n_tab) {
+  // chunks [0, n_tab) are of instances with term tables
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
-    hipLaunchKernelGGL(k_scatter, dim3(m), dim3(256), 0, st, chunks + off,
-                       hitems, (const DevInst*)insts, code, params, loopvals,
-                       acc, keys, pids, cursor, ovf, capb, done);
+    uint32_t mt = off >= n_tab ? 0 : (n_tab - off < m ? n_tab - off : m);
+    if (mt)
+      hipLaunchKernelGGL(k_scatter<true>, dim3(mt), dim3(256), 0, st, chunks + off,
+                         hitems, (const DevInst*)insts, code, params, loopvals,
+                         acc, recs, cursor, ovf, capb, done, nbytes);
+    if (m > mt)
+      hipLaunchKernelGGL(k_scatter<false>, dim3(m - mt), dim3(256), 0, st,
+                         chunks + off + mt, hitems, (const DevInst*)insts, code,
+                         params, loopvals, acc, recs, cursor, ovf, capb, done, nbytes);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -933,14 +1032,14 @@ int launch_bucket(int cfg, hipStream_t st, uint32_t nb, uint32_t base,
                   const uint32_t* bucket_item, const HItem* hitems,
                   const void* insts, const DInsn* code, const int64_t* params,
                   const int64_t* loopvals, const QDesc* qd, QAcc* acc,
-                  const unsigned char* keys, const uint32_t* pids,
+                  const unsigned char* recs,
                   const uint32_t* cursor, const uint32_t* ovf,
                   const uint32_t* done, const u64* l0keys, const u64* l0cnt) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_bucket_t<1024, 2048>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, keys, pids, cursor, ovf, done, l0keys, l0cnt);
-    case 1: return launch_bucket_t<1536, 4096>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, keys, pids, cursor, ovf, done, l0keys, l0cnt);
-    default: return launch_bucket_t<3072, 8192>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, keys, pids, cursor, ovf, done, l0keys, l0cnt);
+    case 0: return launch_bucket_t<1024, 2048>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
+    case 1: return launch_bucket_t<1536, 4096>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
+    default: return launch_bucket_t<3072, 8192>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
   }
 }
 

@@ -39,13 +39,14 @@ int init_verdict_attributes();
 int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n,
                    const HItem* hitems, const void* insts, const DInsn* code,
                    const int64_t* params, const int64_t* loopvals, QAcc* acc,
-                   unsigned char* keys, uint32_t* pids, uint32_t* cursor,
-                   uint32_t* ovf, uint32_t capb, const uint32_t* done);
+                   unsigned char* recs, uint32_t* cursor,
+                   uint32_t* ovf, uint32_t capb, const uint32_t* done,
+                   unsigned long long* nbytes, uint32_t n_tab);
 int launch_bucket(int cfg, hipStream_t st, uint32_t nb, uint32_t base,
                   const uint32_t* bucket_item, const HItem* hitems,
                   const void* insts, const DInsn* code, const int64_t* params,
                   const int64_t* loopvals, const QDesc* qd, QAcc* acc,
-                  const unsigned char* keys, const uint32_t* pids,
+                  const unsigned char* recs,
                   const uint32_t* cursor, const uint32_t* ovf,
                   const uint32_t* done, const unsigned long long* l0keys,
                   const unsigned long long* l0cnt);

@@ -232,3 +232,11 @@ def test_random_models_interpreter_only(hg, seed, monkeypatch):
     run_both(hg, rand_workload(seed), "rand interp seed=%d" % seed)
     run_both(hg, configs.batched(seed=93, n_models=6, scale=0.05, max_iters=8),
              "batched interp")
+
+
+def test_mixed_config_small(hg):
+    """Mixed domain sizes (2^8..2^16 per query), 2-D/3-D launches, up to 64
+    tuples, shared and global: every field equal to the oracle's."""
+    wl = configs.mixed(seed=5005, n_queries=160, log2_max=16)
+    got = run_both(hg, wl, "mixed small")
+    assert any(r["verdict"] for r in got)

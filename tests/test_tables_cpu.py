@@ -53,3 +53,8 @@ def test_stress_and_sparse_sampled():
     st = sweep(configs.sparse(seed=5, n_queries=16, G=256, B=256,
                               queries_per_model=16), max_points=1 << 15)
     assert st[1] == 0
+
+
+def test_mixed_models():
+    st = sweep(configs.mixed(seed=5005, n_queries=96, log2_max=16), max_points=1 << 14)
+    assert st[0] >= 0.8 * (st[0] + st[1]), st

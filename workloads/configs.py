@@ -309,3 +309,94 @@ def sparse(seed=4004, n_queries=16384, G=256, B=256, racy_frac=0.5,
                             Launch((G, 1, 1), (B, 1, 1), 32), [[]],
                             name="sparse%d" % len(models)))
     return Workload(models, pairs, name="sparse", meta={"seed": seed, "G": G})
+
+
+# ---------------------------------------------------------------------------
+# mixed: many queries of log-uniform domain size
+
+def mixed(seed=5005, n_queries=100000, log2_min=8, log2_max=28, racy_frac=0.10,
+          queries_per_model=16, max_sets=64):
+    """Queries whose domain (points of one access over all its tuples) is
+    log-uniform in [2^log2_min, 2^log2_max]; 2-D and 3-D launches;
+    global and shared arrays mixed (one in three models shared); 1..max_sets
+    parameter tuples (W, N) per model derived from one host variable; about
+    10% of pairs planted racy (a non-injective map on both sides), the rest
+    race-free by an injective map with the two sides' ranges separated.
+    Address forms are those of ``batched`` over the linear thread id, the
+    linear block id and the loop variable.  Labels come from the oracle.
+    """
+    rng = _rng(seed)
+    models, pairs, sizes = [], [], []
+    q = 0
+    while q < n_queries:
+        nsets = int(rng.integers(1, max_sets + 1))
+        L = int(round(rng.uniform(log2_min, log2_max) - np.log2(nsets)))
+        L = max(L, min(log2_min, 5))
+        space = SHARED if len(models) % 3 == 2 else GLOBAL
+        # block: 2-D or 3-D, 32..1024 threads
+        bx = int(rng.choice([8, 16, 32, 64]))
+        by = int(rng.choice([1, 2, 4, 8]))
+        bz = int(rng.choice([1, 1, 2, 4])) if rng.random() < 0.4 else 1
+        while bx * by * bz > 1024:
+            bz = max(1, bz // 2)
+            by = max(1, by // 2)
+        bt = bx * by * bz
+        lb = int(np.log2(bt))
+        iters = 1 << int(rng.integers(0, max(1, min(6, L - lb)) + 1))
+        nblk = max(1, (1 << L) // (bt * iters))
+        if space == SHARED:
+            nblk = min(nblk, 1 << 16)
+        three = rng.random() < 0.3 and nblk >= 8
+        if three:
+            gz = 1 << int(rng.integers(0, 3))
+            gx = max(1, nblk // (gz * 2))
+            gy = max(1, nblk // (gx * gz))
+        elif rng.random() < 0.5 and nblk >= 4:
+            gx = 1 << int(rng.integers(1, max(2, int(np.log2(nblk)))))
+            gx = min(gx, nblk)
+            gy, gz = max(1, nblk // gx), 1
+        else:
+            gx, gy, gz = nblk, 1, 1
+        nb = gx * gy * gz
+        Ws = sorted(set(int(x) for x in rng.choice(
+            [1, 2, 4, 8, 16, 32, 64, bx, bx * gx, 3, 5], size=nsets)))
+        sets = [[w, w * int(rng.integers(1, 5)) + bt // 2] for w in Ws]
+        W, Np = param(0), param(1)
+        tl = tid(0) + bdim(0) * (tid(1) + bdim(1) * tid(2))
+        blin = bid(0) + c(gx) * (bid(1) + c(gy) * bid(2))
+        gid = blin * bt + tl
+        i = loop(0)
+        span = nb * bt * iters * 2 + 4096
+        accs = []
+        nq = min(queries_per_model, n_queries - q)
+        for k in range(nq):
+            racy = rng.random() < racy_frac
+            form = int(rng.integers(0, 3))
+            guard = lt(tl, Np - int(rng.integers(0, 4))) if rng.random() < 0.3 else None
+            if space == SHARED:
+                e_ok = [tl * iters + i, tl + bt * i, tl * 2 + i * (2 * bt)][form]
+                e_bad = [tl // 32 + i * 8, tl % W + i, tl * 2 + i][form]
+            else:
+                e_ok = [gid * iters + i, gid + c(nb * bt) * i,
+                        blin * (bt * iters) + tl * iters + i][form]
+                e_bad = [gid // 32 + i * 4, tl % W + blin * W + i, tl + i * 16][form]
+            kinds = [(WRITE, WRITE), (WRITE, READ), (READ, WRITE)]
+            ka, kb = kinds[int(rng.integers(0, 3))]
+            if racy:
+                ea, eb = e_bad, e_bad
+            else:
+                sep = int(rng.integers(2, 6)) * (span if space == GLOBAL
+                                                 else 2 * bt * iters + 4096)
+                ea, eb = e_ok, e_ok + sep
+            accs.append(Access(0, ka, ea, guard, [0]))
+            accs.append(Access(0, kb, eb, guard, [0]))
+            pairs.append((len(models), len(accs) - 2, len(accs) - 1, ALL_CLASSES))
+        q += nq
+        models.append(Model(2, [Array(space, 32)], accs,
+                            Launch((gx, gy, gz), (bx, by, bz), 32), sets,
+                            loops=[Loop(0, "lt", iters, "add", 1)],
+                            name="mixed%d" % len(models)))
+        sizes.append(nb * bt * iters * len(sets))
+    return Workload(models, pairs, name="mixed",
+                    meta={"seed": seed, "log2": (log2_min, log2_max),
+                          "sizes": sizes})
