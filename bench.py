@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--wave-mib", type=int, default=0,
+                    help="partition wave size in MiB (0: the library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB three times "
                          "(the reference for the HBM byte counters)")
@@ -89,10 +91,10 @@ def main():
     log("workload: %d models, %d pairs" % (len(wl.models), len(wl.pairs)))
     ctx = hg.Context(0)
     t0 = time.perf_counter()
-    e2e = hg.rd_check_pairs(ctx, wl)
+    e2e = hg.rd_check_pairs(ctx, wl, max_device_bytes=args.wave_mib << 20)
     e2e_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plan = hg.Plan(ctx, wl)
+    plan = hg.Plan(ctx, wl, max_device_bytes=args.wave_mib << 20)
     prep_s = time.perf_counter() - t0
     log("prepared in %.3f s (end-to-end call %.3f s)" % (prep_s, e2e_s))
     for i in range(max(1, args.warmup)):
@@ -145,7 +147,7 @@ def main():
                                "x 256 threads, loops up to 64 iterations, "
                                "1-16 parameter tuples",
                    "queries": n, "evals_per_step": evals, "racy": racy,
-                   "scale": args.scale},
+                   "scale": args.scale, "wave_mib": args.wave_mib or 1536},
         "evals_per_s_G": evals * args.steps / dt / 1e9,
         "end_to_end_queries_per_s": n / e2e_s,
         "graph_replay_queries_per_s": n * args.steps / dt_graph,

@@ -494,6 +494,44 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
   __syncthreads();
 }
 
+// Address-level pre-filter of S.n records holding only S.addr and the side
+// bit in S.tli: marks inactive every record whose address no record of the
+// other side (for a self pair: no other record) shares, since a conflict
+// needs equal addresses whatever the classes.  Hash table sized to the
+// records (a power of two >= 2n, at most TBL).  Returns, uniformly over
+// the block, whether any record is left.
+template <int CAP, int TBL>
+__device__ bool addr_prefilter(JoinLds<CAP, TBL>& S, uint32_t n, bool self) {
+  uint32_t lg = 6;
+  while ((1u << lg) < 2 * n) ++lg;
+  const uint32_t tsz = 1u << lg, tm = tsz - 1;
+  for (uint32_t k = threadIdx.x; k < tsz; k += blockDim.x) {
+    S.owner[k] = kEmpty;
+    S.cnt[k] = 0;
+  }
+  __syncthreads();
+  for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
+    const u64 a = S.addr[r];
+    uint32_t h = (((uint32_t)a ^ (uint32_t)(a >> 32)) * 0x9E3779B1u) >> (32 - lg);
+    for (;;) {
+      const uint32_t o = atomicCAS(&S.owner[h], kEmpty, r);
+      if (o == kEmpty || S.addr[o] == a) break;
+      h = (h + 1) & tm;
+    }
+    atomicAdd(&S.cnt[h], (self || !(S.tli[r] & kSide)) ? 1u : 0x10000u);
+    S.slot[r] = (uint16_t)h;
+  }
+  __syncthreads();
+  bool any = false;
+  for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
+    const uint32_t c = S.cnt[S.slot[r]];
+    const bool cand = self ? ((c & 0xFFFF) >= 2) : ((c & 0xFFFF) && (c >> 16));
+    if (cand) any = true;
+    else S.tli[r] |= kInactive;
+  }
+  return __syncthreads_or(any);
+}
+
 // Adds a join's results (S.red) to a query's accumulators (thread 0).
 template <int CAP, int TBL>
 __device__ __forceinline__ void commit_join(const JoinLds<CAP, TBL>& S,

@@ -43,7 +43,8 @@ constexpr int64_t kMaxBlock = 1024;
 constexpr int64_t kMaxGrid = 1ll << 26;
 constexpr int64_t kMaxPoints = 1ll << 31;
 constexpr uint32_t kChunkPts = 1024;
-constexpr uint64_t kWaveBytes = 96ull << 20;
+constexpr uint32_t kRunBuckets = 4;  // buckets joined by one workgroup
+constexpr uint64_t kWaveBytes = 1536ull << 20;  // bucket bytes per partition wave
 constexpr uint64_t kFallbackRecords = 256ull << 20;
 constexpr uint64_t kMaxTabInst = 1ull << 24;  // table entries per instance
 constexpr uint64_t kMaxTabPool = 1ull << 28;  // table entries per plan
@@ -1211,6 +1212,7 @@ struct rd_plan_impl {
   struct Wave {
     uint32_t first_item, n_items, n_chunks, n_buckets;
     uint32_t n_tab_chunks;  // the first n_tab_chunks chunks have term tables
+    uint32_t n_runs;        // bucket runs (one join workgroup each)
     uint64_t key_bytes;
     uint64_t hitem_off, chunk_off, bitem_off;  // element offsets in the plan pools
   };
@@ -1549,12 +1551,12 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   plan->no_map = getenv("HGRD_HASH_BUCKETS") != nullptr;
 
   // ---- waves of HBM items, bounded by the device budget --------------------
-  // A wave's buckets are small enough to stay in the last-level cache while
-  // they are filled and joined, so HBM sees whole lines.
+  // Large waves keep the partition and join launches few (each launch has a
+  // tail); records cost 16 bytes of HBM traffic per point either way.
   const uint64_t budget = o.max_device_bytes ? o.max_device_bytes : ctx->wave_bytes;
   plan->wave_budget = budget;
   std::vector<Chunk> all_chunks;
-  std::vector<uint32_t> all_bitem;
+  std::vector<BRun> all_runs;
   size_t pos = 0;
   while (pos < hplans.size()) {
     rd_plan_impl::Wave W;
@@ -1562,7 +1564,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     W.first_item = (uint32_t)plan->hitems.size();
     W.hitem_off = plan->hitems.size();
     W.chunk_off = all_chunks.size();
-    W.bitem_off = all_bitem.size();
+    W.bitem_off = all_runs.size();
     size_t end = pos;
     uint64_t bytes = 0, nbk = 0;
     while (end < hplans.size()) {
@@ -1590,7 +1592,9 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       uint32_t li = (uint32_t)plan->hitems.size();  // global item index
       plan->hitems.push_back(h);
       plan->hR.push_back(hplans[i].R);
-      for (uint32_t b = 0; b < h.nbuckets; ++b) all_bitem.push_back(li);
+      for (uint32_t b = 0; b < h.nbuckets; b += kRunBuckets)
+        all_runs.push_back({li, b,
+                            std::min(h.nbuckets, b + kRunBuckets), 0});
       const QPlan& q = Q[h.q];
       for (int side = 0; side < (q.qd.self || h.shared == 2 ? 1 : 2); ++side) {
         uint32_t inst = side ? h.inst_j : h.inst_i;
@@ -1603,6 +1607,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     W.n_tab_chunks = (uint32_t)(all_chunks.size() - W.chunk_off);
     all_chunks.insert(all_chunks.end(), interp.begin(), interp.end());
     W.n_items = (uint32_t)(end - pos);
+    W.n_runs = (uint32_t)(all_runs.size() - W.bitem_off);
     W.n_chunks = (uint32_t)(all_chunks.size() - W.chunk_off);
     W.n_buckets = (uint32_t)nbk;
     W.key_bytes = bytes;
@@ -1670,7 +1675,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   up("sitems", sitems.data(), sitems.size() * sizeof(SItem));
   up("hitems", plan->hitems.data(), plan->hitems.size() * sizeof(HItem));
   up("chunks", all_chunks.data(), all_chunks.size() * sizeof(Chunk));
-  up("bitem", all_bitem.data(), all_bitem.size() * 4);
+  up("runs", all_runs.data(), all_runs.size() * sizeof(BRun));
   if (plan->verdict) {
     up("vq", vqs.data(), vqs.size() * sizeof(VQuery));
     up("bitems", bitems.data(), bitems.size() * sizeof(BItem));
@@ -1730,7 +1735,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   const SItem* d_sitems = (const SItem*)D("sitems");
   const HItem* d_hitems_all = (const HItem*)D("hitems");
   const Chunk* d_chunks_all = (const Chunk*)D("chunks");
-  const uint32_t* d_bitem_all = (const uint32_t*)D("bitem");
+  const BRun* d_runs_all = (const BRun*)D("runs");
   // first-phase scratch owned by the plan (fixed addresses, so a captured
   // graph stays valid); later phases reuse the context's arena
   unsigned char* d_recs = (unsigned char*)D("recs");
@@ -1763,7 +1768,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   };
   auto run_waves = [&](const std::vector<rd_plan_impl::Wave>& waves,
                        const HItem* d_hit, const Chunk* d_chk,
-                       const uint32_t* d_bit, uint32_t* d_ovf, int wcfg,
+                       const BRun* d_bit, uint32_t* d_ovf, int wcfg,
                        const u64* l0k, const u64* l0c, bool events) -> int {
     const uint32_t wcap = (uint32_t)join_cap(wcfg);
     for (const auto& W : waves) {
@@ -1783,8 +1788,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
                          d_cursor, d_ovf, wcap, d_done, d_nbytes, W.n_tab_chunks))
         return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(e1, st));
-      if (W.n_buckets &&
-          launch_bucket(wcfg, st, W.n_buckets, 0, d_bit + W.bitem_off, d_hit,
+      if (W.n_runs &&
+          launch_bucket(wcfg, st, W.n_runs, d_bit + W.bitem_off, d_hit,
                         d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs,
                         d_cursor, d_ovf, d_done, l0k, l0c))
         return RD_EDEVICE;
@@ -1864,7 +1869,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     if (nh) {
       if (launch_fill_u32(st, d_ovf_all, nh, 0)) return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(ev[11], st));
-      int rc = run_waves(plan->waves, d_hitems_all, d_chunks_all, d_bitem_all,
+      int rc = run_waves(plan->waves, d_hitems_all, d_chunks_all, d_runs_all,
                          d_ovf_all, cfg, nullptr, nullptr, events);
       if (rc) return rc;
       if (events) TRY_HIP(hipEventRecord(ev[12], st));
@@ -1944,7 +1949,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     const uint32_t wcap = (uint32_t)join_cap(wcfg);
     std::vector<rd_plan_impl::Wave> waves;
     std::vector<Chunk> chunks;
-    std::vector<uint32_t> bitem;
+    std::vector<BRun> bitem;
     std::vector<HItem> hs;
     std::vector<Chunk> interp;
     uint64_t max_bytes = 0, max_nbk = 0;
@@ -1967,7 +1972,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
         nbk += h.nbuckets;
         uint32_t li = (uint32_t)hs.size();
         hs.push_back(h);
-        for (uint32_t b = 0; b < h.nbuckets; ++b) bitem.push_back(li);
+        for (uint32_t b = 0; b < h.nbuckets; b += kRunBuckets)
+          bitem.push_back({li, b, std::min(h.nbuckets, b + kRunBuckets), 0});
         const QPlan& q = plan->Q[h.q];
         for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
           const uint32_t inst = side ? h.inst_j : h.inst_i;
@@ -1982,6 +1988,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       chunks.insert(chunks.end(), interp.begin(), interp.end());
       interp.clear();
       W.n_items = (uint32_t)(end - pos);
+      W.n_runs = (uint32_t)(bitem.size() - W.bitem_off);
       W.n_chunks = (uint32_t)(chunks.size() - W.chunk_off);
       W.n_buckets = (uint32_t)nbk;
       waves.push_back(W);
@@ -1994,12 +2001,12 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     const uint32_t nr = (uint32_t)hs.size();
     HItem* d_rh = (HItem*)ctx->ensure("r_hitems", nr * sizeof(HItem), &merr);
     Chunk* d_rc = (Chunk*)ctx->ensure("r_chunks", chunks.size() * sizeof(Chunk), &merr);
-    uint32_t* d_rb = (uint32_t*)ctx->ensure("r_bitem", bitem.size() * 4, &merr);
+    BRun* d_rb = (BRun*)ctx->ensure("r_runs", bitem.size() * sizeof(BRun), &merr);
     uint32_t* d_rovf = (uint32_t*)ctx->ensure("r_ovf", nr * 4, &merr);
     if (merr) return merr;
     TRY_HIP(hipMemcpyAsync(d_rh, hs.data(), nr * sizeof(HItem), hipMemcpyHostToDevice, st));
     TRY_HIP(hipMemcpyAsync(d_rc, chunks.data(), chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
-    TRY_HIP(hipMemcpyAsync(d_rb, bitem.data(), bitem.size() * 4, hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemcpyAsync(d_rb, bitem.data(), bitem.size() * sizeof(BRun), hipMemcpyHostToDevice, st));
     if (launch_fill_u32(st, d_rovf, nr, 0)) return RD_EDEVICE;
     TRY_HIP(hipEventRecord(ev[13], st));
     int rc = run_waves(waves, d_rh, d_rc, d_rb, d_rovf, wcfg, l0k, l0c, true);
@@ -2014,9 +2021,16 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   };
 
   std::vector<RItem> rit;
+  std::vector<RItem> still;
   for (uint32_t i = 0; i < nh; ++i) {
     if (!ovf[i] || plan->hitems[i].shared == 2) continue;
     RItem r{plan->hitems[i], plan->hR[i]};
+    if (r.h.mode && r.h.shared == 0) {
+      // a dense-map global item overflows only on heavy address groups,
+      // which more buckets do not spread: split it right away
+      still.push_back(r);
+      continue;
+    }
     uint64_t need_f = (ovf[i] * 10ull + cap * 6 - 1) / (cap * 6);
     need_f = std::min<uint64_t>(std::max<uint64_t>(need_f, 2), 64);
     r.h.nbuckets = (uint32_t)((uint64_t)r.h.nbuckets * need_f);
@@ -2025,7 +2039,6 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   }
   S.retry_items = rit.size();
   std::vector<uint32_t> rovf;
-  std::vector<RItem> still;
   if (!rit.empty()) {
     float ms = 0;
     int rc = repartition(rit, cfg, nullptr, nullptr, rovf, ms);
@@ -2040,7 +2053,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   for (auto& r : still) (r.h.shared == 0 ? split : direct).push_back(r);
   S.split_items = split.size();
   if (!split.empty()) {
-    const int scfg = 2;
+    const int scfg = 1;  // first pass; its overflows get join_cap(2) tiles
     const uint32_t scap = (uint32_t)join_cap(scfg);
     std::vector<L0Item> l0;
     uint64_t slots = 0;
@@ -2096,12 +2109,33 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
         return RD_EDEVICE;
     }
     TRY_HIP(hipEventRecord(ev[8], st));
+    float ms0 = 0;
+    (void)hipEventElapsedTime(&ms0, ev[7], ev[8]);
     float ms = 0;
     int rc = repartition(split, scfg, d_l0k, d_l0c, rovf, ms);
     if (rc) return rc;
-    float ms0 = 0;
-    (void)hipEventElapsedTime(&ms0, ev[7], ev[8]);
     split_ms = ms0 + ms;
+    // second pass: the overflowed split items with the biggest tiles and a
+    // hashed map at a lower load
+    std::vector<RItem> split2;
+    std::vector<size_t> at2;
+    const uint32_t scap2 = (uint32_t)join_cap(2);
+    for (size_t i = 0; i < split.size(); ++i) {
+      if (!rovf[i]) continue;
+      RItem r = split[i];
+      r.h.mode = 0;
+      r.h.shift = 0;
+      r.h.nbuckets = (uint32_t)std::max<uint64_t>(1, (r.R * 100 + scap2 * 40 - 1) / (scap2 * 40));
+      split2.push_back(r);
+      at2.push_back(i);
+    }
+    if (!split2.empty()) {
+      std::vector<uint32_t> rovf2;
+      rc = repartition(split2, 2, d_l0k, d_l0c, rovf2, ms);
+      if (rc) return rc;
+      split_ms += ms;
+      for (size_t k = 0; k < at2.size(); ++k) rovf[at2[k]] = rovf2[k];
+    }
     // an overflowed split item joined none of its buckets; its S_0 is not
     // applied and the fallback counts the whole item
     for (size_t i = 0; i < split.size(); ++i) {
@@ -2292,7 +2326,7 @@ int rd_autotune(rd_context* ctx, const rd_kernel_model* models,
   if (opt) base = *opt;
   reps = std::max(1u, std::min(reps, 16u));
   std::vector<rd_pair_result> out(std::max<uint32_t>(1, n_pairs));
-  static const uint64_t kWaves[3] = {kWaveBytes / 2, kWaveBytes, kWaveBytes * 2};
+  static const uint64_t kWaves[3] = {kWaveBytes / 4, kWaveBytes, kWaveBytes * 4};
   double t_best = 1e300;
   rd_options o_best = base;
   for (int cfg = 0; cfg < 3; ++cfg) {

@@ -149,6 +149,11 @@ struct HItem {
   unsigned long long pad1;
 };
 static_assert(sizeof(HItem) == 96, "HItem layout");
+// A run of buckets [b0, b1) of one HBM item, joined by one workgroup.
+struct BRun {
+  uint32_t item, b0, b1, pad;
+};
+
 // Records: int32 keys as one u64 (address | point id << 32), int64 keys as
 // 16 bytes (address, point id); point id = side << 31 | point index.
 // HItem.shared: 0 global (hash of the address), 1 shared array (hash of

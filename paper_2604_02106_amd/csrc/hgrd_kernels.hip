@@ -422,75 +422,131 @@ __global__ void k_apply_s0(uint32_t n, const L0Item* __restrict__ items,
 // ---------------------------------------------------------------------------
 // Kernel: one workgroup per HBM bucket; load its records into LDS and join.
 
+constexpr uint32_t kJoinThreads = 512;  // bucket-join workgroup size
+
+// One workgroup joins a run of buckets of one item.  The item's header,
+// query and both access instances are loaded once per run (the instances
+// into LDS); the next bucket's records are loaded into registers while the
+// current one is joined, and the counts are committed once per run.
 template <int CAP, int TBL>
-__global__ void __launch_bounds__(256)
-k_bucket_join(const uint32_t* __restrict__ bucket_item,
-              const HItem* __restrict__ hitems,
+__global__ void __launch_bounds__(kJoinThreads)
+k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
               const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
               const int64_t* __restrict__ params,
               const int64_t* __restrict__ loopvals,
               const QDesc* __restrict__ qd, QAcc* __restrict__ acc,
               const unsigned char* __restrict__ recs,
               const uint32_t* __restrict__ cursor,
-              const uint32_t* __restrict__ ovf, uint32_t bucket_base,
+              const uint32_t* __restrict__ ovf,
               const uint32_t* __restrict__ done, const u64* __restrict__ l0keys,
               const u64* __restrict__ l0cnt) {
   extern __shared__ __align__(16) unsigned char smem[];
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
-  const uint32_t g = bucket_base + blockIdx.x;
-  const uint32_t hi = bucket_item[g];
-  const HItem h = hitems[hi];
-  if (ovf[hi] || done[h.q]) return;
-  uint32_t n = cursor[g];
-  if (n == 0) return;
-  if (n > CAP) n = CAP;  // cannot happen without the overflow flag
+  const BRun R = runs[blockIdx.x];
+  const HItem h = hitems[R.item];
+  if (ovf[R.item] || done[h.q]) return;
   const QDesc q = qd[h.q];
-  const uint32_t b = g - h.bucket0;
-  const u64 slot0 = (u64)b * CAP;
-  uint32_t err = 0;
-  for (int side = 0; side < 2; ++side) {
-    DevInst I;
-    load_inst(I, insts, side ? h.inst_j : h.inst_i);
-    for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
-      uint32_t pid;
-      int64_t a;
-      if (h.is32) {
-        const u64 rec = reinterpret_cast<const u64*>(recs + h.rec_off)[slot0 + r];
-        pid = (uint32_t)(rec >> 32);
-        a = (int32_t)(uint32_t)rec;
-      } else {
-        const ulonglong2 rec = reinterpret_cast<const ulonglong2*>(recs + h.rec_off)[slot0 + r];
-        pid = (uint32_t)rec.y;
-        a = (int64_t)rec.x;
-      }
-      if ((pid >> 31) != (uint32_t)side) continue;
-      PointIds id = decode(I, pid & 0x7FFFFFFFu);
-      uint32_t bi, wi;
-      point_iv(I, id, code, params, loopvals, bi, wi);
-      S.addr[r] = (u64)a;
-      S.blin[r] = id.blin;
-      S.tli[r] = (id.ilin << 16) | ((uint32_t)side << 15) | id.tlin;
-      S.bw[r] = (bi << 16) | wi;
-      S.w[r] = (uint16_t)(id.tlin / q.warp);
-    }
-  }
-  (void)err;
-  const bool l0ext = h.shared == 3;
-  if (l0ext) {
-    // level-0 partners of each side-a record: the other side's count at its
-    // address in the item's address-count table
-    for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
-      int32_t nj = 0;
-      if ((q.mask & 1) && (q.self || !(S.tli[r] & kSide)))
-        nj = (int32_t)l0_lookup(l0keys, l0cnt, h.l0_off, h.l0_mask,
-                                (long long)S.addr[r], q.self != 0);
-      S.part[r] = nj;
-    }
-  }
-  if (threadIdx.x == 0) S.n = n;
   init_red(S);
-  __syncthreads();
-  lds_join(S, q, h.sigma, l0ext);
+  const bool l0ext = h.shared == 3;
+  const bool is32 = h.is32 != 0;
+  constexpr int RPT = (CAP + kJoinThreads - 1) / kJoinThreads;
+  u64 rx[RPT], ry[RPT];
+  const u64* r8 = reinterpret_cast<const u64*>(recs + h.rec_off);
+  const ulonglong2* r16 = reinterpret_cast<const ulonglong2*>(recs + h.rec_off);
+#define HGRD_FETCH(B, N)                                            \
+  {                                                                 \
+    const u64 slot0 = (u64)(B) * CAP;                               \
+    _Pragma("unroll") for (int j = 0; j < RPT; ++j) {               \
+      const uint32_t r = threadIdx.x + (uint32_t)j * kJoinThreads;  \
+      rx[j] = 0;                                                    \
+      ry[j] = 0;                                                    \
+      if (r < (N)) {                                                \
+        if (is32) {                                                 \
+          rx[j] = r8[slot0 + r];                                    \
+        } else {                                                    \
+          const ulonglong2 v = r16[slot0 + r];                      \
+          rx[j] = v.x;                                              \
+          ry[j] = v.y;                                              \
+        }                                                           \
+      }                                                             \
+    }                                                               \
+  }
+  uint32_t n = R.b0 < R.b1 ? min(cursor[h.bucket0 + R.b0], (uint32_t)CAP) : 0;
+  uint32_t n1 = R.b0 + 1 < R.b1 ? min(cursor[h.bucket0 + R.b0 + 1], (uint32_t)CAP) : 0;
+  HGRD_FETCH(R.b0, n)
+  __syncthreads();  // S.red ready
+  for (uint32_t b = R.b0; b < R.b1; ++b) {
+    bool go = n != 0;
+    if (!l0ext) {
+      // address and side only; the point id waits in S.blin until the
+      // records that share an address with the other side are known
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const uint32_t r = threadIdx.x + (uint32_t)j * kJoinThreads;
+        if (r >= n) continue;
+        const uint32_t pid = is32 ? (uint32_t)(rx[j] >> 32) : (uint32_t)ry[j];
+        S.addr[r] = is32 ? (u64)(int64_t)(int32_t)(uint32_t)rx[j] : rx[j];
+        S.tli[r] = (pid >> 31) << 15;
+        S.blin[r] = pid;
+      }
+    }
+    // the next bucket's records load while this one is joined
+    const uint32_t n2 = b + 2 < R.b1 ? min(cursor[h.bucket0 + b + 2], (uint32_t)CAP) : 0;
+    if (!l0ext) {
+      if (b + 1 < R.b1) HGRD_FETCH(b + 1, n1)
+      __syncthreads();
+      if (go) go = addr_prefilter(S, n, q.self != 0);
+    }
+    if (go) {
+      // full records of the candidates, one side at a time (the instance
+      // stays uniform: scalar loads, no divergent interpreter)
+      for (uint32_t side = 0; side < 2; ++side) {
+        DevInst I;
+        load_inst(I, insts, side ? h.inst_j : h.inst_i);
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const uint32_t r = threadIdx.x + (uint32_t)j * kJoinThreads;
+          if (r >= n) continue;
+          uint32_t pid;
+          int64_t a;
+          if (l0ext) {
+            pid = is32 ? (uint32_t)(rx[j] >> 32) : (uint32_t)ry[j];
+            a = is32 ? (int64_t)(int32_t)(uint32_t)rx[j] : (int64_t)rx[j];
+          } else {
+            if (S.tli[r] & kInactive) continue;
+            pid = S.blin[r];
+            a = (int64_t)S.addr[r];
+          }
+          if ((pid >> 31) != side) continue;
+          const PointIds id = decode(I, pid & 0x7FFFFFFFu);
+          uint32_t bi, wi;
+          point_iv(I, id, code, params, loopvals, bi, wi);
+          S.addr[r] = (u64)a;
+          S.blin[r] = id.blin;
+          S.tli[r] = (id.ilin << 16) | (side << 15) | id.tlin;
+          S.bw[r] = (bi << 16) | wi;
+          S.w[r] = (uint16_t)(id.tlin / q.warp);
+          if (l0ext) {
+            // level-0 partners of a side-a record: the other side's count
+            // at its address in the item's address-count table
+            int32_t nj = 0;
+            if ((q.mask & 1) && (q.self || !side))
+              nj = (int32_t)l0_lookup(l0keys, l0cnt, h.l0_off, h.l0_mask, (long long)a,
+                                      q.self != 0);
+            S.part[r] = nj;
+          }
+        }
+      }
+    }
+    if (l0ext && b + 1 < R.b1) HGRD_FETCH(b + 1, n1)
+#undef HGRD_FETCH
+    if (threadIdx.x == 0) S.n = n;
+    __syncthreads();
+    if (go) lds_join(S, q, h.sigma, l0ext);
+    __syncthreads();
+    n = n1;
+    n1 = n2;
+  }
   commit_join(S, &acc[h.q]);
 }
 
@@ -903,20 +959,21 @@ static int set_lds_attrs() {
 }
 
 template <int CAP, int TBL>
-static int launch_bucket_t(hipStream_t st, uint32_t nb, uint32_t base,
-                           const uint32_t* bucket_item, const HItem* hitems,
-                           const DevInst* insts, const DInsn* code,
-                           const int64_t* params, const int64_t* loopvals,
-                           const QDesc* qd, QAcc* acc,
-                           const unsigned char* recs,
-                           const uint32_t* cursor, const uint32_t* ovf,
-                           const uint32_t* done, const u64* l0keys,
-                           const u64* l0cnt) {
+static int launch_bucket_t(hipStream_t st, uint32_t nruns, const BRun* runs,
+                           const HItem* hitems, const DevInst* insts,
+                           const DInsn* code, const int64_t* params,
+                           const int64_t* loopvals, const QDesc* qd, QAcc* acc,
+                           const unsigned char* recs, const uint32_t* cursor,
+                           const uint32_t* ovf, const uint32_t* done,
+                           const u64* l0keys, const u64* l0cnt) {
   size_t lds = sizeof(JoinLds<CAP, TBL>);
-  hipLaunchKernelGGL((k_bucket_join<CAP, TBL>), dim3(nb), dim3(256), lds, st,
-                     bucket_item, hitems, insts, code, params, loopvals, qd,
-                     acc, recs, cursor, ovf, base, done, l0keys, l0cnt);
-  HGRD_CHECK(hipGetLastError());
+  for (uint32_t off = 0; off < nruns; off += 1u << 20) {
+    uint32_t m = nruns - off < (1u << 20) ? nruns - off : (1u << 20);
+    hipLaunchKernelGGL((k_bucket_join<CAP, TBL>), dim3(m), dim3(kJoinThreads), lds, st,
+                       runs + off, hitems, insts, code, params, loopvals, qd, acc,
+                       recs, cursor, ovf, done, l0keys, l0cnt);
+    HGRD_CHECK(hipGetLastError());
+  }
   return 0;
 }
 
@@ -1028,18 +1085,17 @@ int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n,
   return 0;
 }
 
-int launch_bucket(int cfg, hipStream_t st, uint32_t nb, uint32_t base,
-                  const uint32_t* bucket_item, const HItem* hitems,
-                  const void* insts, const DInsn* code, const int64_t* params,
-                  const int64_t* loopvals, const QDesc* qd, QAcc* acc,
-                  const unsigned char* recs,
-                  const uint32_t* cursor, const uint32_t* ovf,
-                  const uint32_t* done, const u64* l0keys, const u64* l0cnt) {
+int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
+                  const HItem* hitems, const void* insts, const DInsn* code,
+                  const int64_t* params, const int64_t* loopvals, const QDesc* qd,
+                  QAcc* acc, const unsigned char* recs, const uint32_t* cursor,
+                  const uint32_t* ovf, const uint32_t* done, const u64* l0keys,
+                  const u64* l0cnt) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_bucket_t<1024, 2048>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
-    case 1: return launch_bucket_t<1536, 4096>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
-    default: return launch_bucket_t<3072, 8192>(st, nb, base, bucket_item, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
+    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
+    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
+    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
   }
 }
 
