@@ -62,6 +62,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--config", default="batched",
+                    choices=("batched", "stress", "mixed"),
+                    help="workload: batched uneven queries (the headline), "
+                         "race-free stress (128 pairs, 2^30 points per "
+                         "access), or mixed domain sizes")
     ap.add_argument("--wave-mib", type=int, default=0,
                     help="partition wave size in MiB (0: the library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -87,7 +92,20 @@ def main():
     from workloads import configs
     assert torch.cuda.is_available()
     torch.cuda.set_device(0)
-    wl = configs.batched(seed=2002, scale=args.scale)
+    if args.config == "stress":
+        wl = configs.stress()
+        desc = ("race-free stress: 128 access pairs, 2^30 points per access "
+                "(grid 65536 x block 256 x 64 iterations), int64 addresses, "
+                "strided and blocked near misses, seed 3003")
+    elif args.config == "mixed":
+        wl = configs.mixed(n_queries=int(100000 * args.scale))
+        desc = ("mixed: %d queries, per-query domain log-uniform 2^8..2^28 "
+                "points, 2-D/3-D launches, 1-64 tuples, seed 5005" % len(wl.pairs))
+    else:
+        wl = configs.batched(seed=2002, scale=args.scale)
+        desc = ("batched uneven queries: 256 kernel models x 16 access pairs, "
+                "seed 2002, grids up to 1024 blocks x 256 threads, loops up to "
+                "64 iterations, 1-16 parameter tuples")
     log("workload: %d models, %d pairs" % (len(wl.models), len(wl.pairs)))
     ctx = hg.Context(0)
     t0 = time.perf_counter()
@@ -142,10 +160,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "batched uneven queries: 256 kernel models x 16 "
-                               "access pairs, seed 2002, grids up to 1024 blocks "
-                               "x 256 threads, loops up to 64 iterations, "
-                               "1-16 parameter tuples",
+        "config": {"workload": desc,
                    "queries": n, "evals_per_step": evals, "racy": racy,
                    "scale": args.scale, "wave_mib": args.wave_mib or 1536},
         "evals_per_s_G": evals * args.steps / dt / 1e9,
@@ -178,7 +193,7 @@ def main():
                             "bytes_per_launch": per_launch,
                             "avg_launch_ms": avg_ms,
                             "launches_per_step": launches / len(stats)}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.config == "batched":
         line["cpu_baseline"] = cpu_baseline(wl, res)
     print(json.dumps(line), flush=True)
 

@@ -43,7 +43,6 @@ constexpr int64_t kMaxBlock = 1024;
 constexpr int64_t kMaxGrid = 1ll << 26;
 constexpr int64_t kMaxPoints = 1ll << 31;
 constexpr uint32_t kChunkPts = 1024;
-constexpr uint32_t kRunBuckets = 4;  // buckets joined by one workgroup
 constexpr uint64_t kWaveBytes = 1536ull << 20;  // bucket bytes per partition wave
 constexpr uint64_t kFallbackRecords = 256ull << 20;
 constexpr uint64_t kMaxTabInst = 1ull << 24;  // table entries per instance
@@ -1207,6 +1206,8 @@ struct rd_plan_impl {
   uint64_t evals = 0;
   uint32_t n_sitems = 0;
   uint32_t persist_grid = 0;  // workgroups of the persistent small join
+  uint32_t chunk_pts = 4096;  // points per partition workgroup
+  uint32_t run_buckets = 4;   // buckets per join workgroup
   uint32_t n_tabchunks = 0;   // term-table fill chunks
   uint32_t n_insts = 0, tab_insts = 0;
   struct Wave {
@@ -1372,8 +1373,11 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     return idx < 0 ? 0 : P.dev_insts[idx].npts;
   };
   // Bucket shift of an HBM item: blocks of 2^shift consecutive addresses
-  // should hold about 32 records, from the density (points per address of
-  // the tabulated range; per block for shared arrays) of the denser side.
+  // should hold about block_recs records, from the density (points per
+  // address of the tabulated range; per block for shared arrays) of the
+  // denser side.
+  double block_recs = 32;
+  if (const char* e = getenv("HGRD_BLOCK_RECS")) block_recs = std::max(1, atoi(e));
   auto item_shift = [&](int32_t ia, int32_t ib, bool self, bool shared) -> uint32_t {
     double dens = 0;
     for (int32_t x : {ia, ib}) {
@@ -1384,8 +1388,9 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       const double pts = shared ? P.dev_insts[x].tpb : P.dev_insts[x].npts;
       dens = std::max(dens, pts / span);
     }
-    if (dens <= 0 || 32.0 / dens < 2.0) return 0;
-    return (uint32_t)std::min(30.0, std::floor(std::log2(32.0 / dens)));
+    const double target = block_recs;
+    if (dens <= 0 || target / dens < 2.0) return 0;
+    return (uint32_t)std::min(30.0, std::floor(std::log2(target / dens)));
   };
   for (uint32_t k = 0; k < n_pairs; ++k) {
     QPlan& q = Q[k];
@@ -1549,6 +1554,10 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   std::vector<uint8_t> tab_on(P.dev_insts.size());
   for (size_t i = 0; i < P.dev_insts.size(); ++i) tab_on[i] = (uint8_t)P.tabs[i].on;
   plan->no_map = getenv("HGRD_HASH_BUCKETS") != nullptr;
+  if (const char* e = getenv("HGRD_CHUNK_PTS"))
+    plan->chunk_pts = std::max(256u, std::min(1u << 20, (uint32_t)atoi(e)));
+  if (const char* e = getenv("HGRD_RUN_BUCKETS"))
+    plan->run_buckets = std::max(1u, std::min(256u, (uint32_t)atoi(e)));
 
   // ---- waves of HBM items, bounded by the device budget --------------------
   // Large waves keep the partition and join launches few (each launch has a
@@ -1592,16 +1601,16 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       uint32_t li = (uint32_t)plan->hitems.size();  // global item index
       plan->hitems.push_back(h);
       plan->hR.push_back(hplans[i].R);
-      for (uint32_t b = 0; b < h.nbuckets; b += kRunBuckets)
+      for (uint32_t b = 0; b < h.nbuckets; b += plan->run_buckets)
         all_runs.push_back({li, b,
-                            std::min(h.nbuckets, b + kRunBuckets), 0});
+                            std::min(h.nbuckets, b + plan->run_buckets), 0});
       const QPlan& q = Q[h.q];
       for (int side = 0; side < (q.qd.self || h.shared == 2 ? 1 : 2); ++side) {
         uint32_t inst = side ? h.inst_j : h.inst_i;
         uint32_t np = P.dev_insts[inst].npts;
         std::vector<Chunk>& dst = P.tabs[inst].on ? all_chunks : interp;
-        for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
-          dst.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+        for (uint32_t p0 = 0; p0 < np; p0 += plan->chunk_pts)
+          dst.push_back({li, (uint32_t)side, p0, std::min(np, p0 + plan->chunk_pts)});
       }
     }
     W.n_tab_chunks = (uint32_t)(all_chunks.size() - W.chunk_off);
@@ -1972,15 +1981,15 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
         nbk += h.nbuckets;
         uint32_t li = (uint32_t)hs.size();
         hs.push_back(h);
-        for (uint32_t b = 0; b < h.nbuckets; b += kRunBuckets)
-          bitem.push_back({li, b, std::min(h.nbuckets, b + kRunBuckets), 0});
+        for (uint32_t b = 0; b < h.nbuckets; b += plan->run_buckets)
+          bitem.push_back({li, b, std::min(h.nbuckets, b + plan->run_buckets), 0});
         const QPlan& q = plan->Q[h.q];
         for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
           const uint32_t inst = side ? h.inst_j : h.inst_i;
           uint32_t np = plan->npts[inst];
           std::vector<Chunk>& dst = plan->tab_on[inst] ? chunks : interp;
-          for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
-            dst.push_back({li, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+          for (uint32_t p0 = 0; p0 < np; p0 += plan->chunk_pts)
+            dst.push_back({li, (uint32_t)side, p0, std::min(np, p0 + plan->chunk_pts)});
         }
         ++end;
       }

@@ -231,10 +231,11 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
   for (uint32_t t0 = ch.p0; t0 < ch.p1; t0 += kScatterPts) {
     __syncthreads();
     int64_t ad[kPer];
-    uint32_t pv[kPer], sl[kPer], rk[kPer];
+    uint32_t pv[kPer], sl[kPer], rk[kPer], bk[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       sl[j] = kScatterSlots;
+      bk[j] = 0xFFFFFFFFu;  // no record
       const uint32_t pidx = t0 + (uint32_t)j * 256 + threadIdx.x;
       if (pidx >= ch.p1) continue;
       const PointIds id = decode(I, pidx);
@@ -243,17 +244,56 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
                           : point_eval(I, id, code, params, loopvals, pt, err);
       if (!ok || !store) continue;
       const uint32_t b = bucket_of(h, pt.addr, id.blin);
-      uint32_t s = (b * 0x9E3779B1u) >> 21;  // 11 bits: kScatterSlots
-      for (;;) {
-        const uint32_t k = atomicCAS(&skey[s], 0u, b + 1);
-        if (k == 0) used[atomicAdd(&nused, 1u)] = (uint16_t)s;
-        if (k == 0 || k == b + 1) break;
-        s = (s + 1) & (kScatterSlots - 1);
-      }
-      sl[j] = s;
-      rk[j] = atomicAdd(&scnt[s], 1u);
       ad[j] = pt.addr;
       pv[j] = (ch.side << 31) | pidx;
+      bk[j] = b;
+    }
+    // claim LDS slots and ranks.  Dense-map items: the lanes of a wave that
+    // share a bucket (consecutive points) are grouped with ballots and one
+    // lane claims for the group; hashed items: one claim per lane.
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const bool v = bk[j] != 0xFFFFFFFFu;
+      const uint32_t b = bk[j];
+      u64 act = __ballot(v);
+      if (h.mode) {
+        // at most 8 groups per wave this way; any rest claims per lane
+        for (int it = 0; act && it < 8; ++it) {
+          const uint32_t leader = (uint32_t)__ffsll((long long)act) - 1;
+          const uint32_t bl = __shfl(b, leader, 64);
+          const u64 grp = __ballot(v && b == bl) & act;
+          uint32_t s = 0, base = 0;
+          if (lane == leader) {
+            s = (bl * 0x9E3779B1u) >> 21;  // 11 bits: kScatterSlots
+            for (;;) {
+              const uint32_t k = atomicCAS(&skey[s], 0u, bl + 1);
+              if (k == 0) used[atomicAdd(&nused, 1u)] = (uint16_t)s;
+              if (k == 0 || k == bl + 1) break;
+              s = (s + 1) & (kScatterSlots - 1);
+            }
+            base = atomicAdd(&scnt[s], (uint32_t)__popcll(grp));
+          }
+          s = __shfl(s, leader, 64);
+          base = __shfl(base, leader, 64);
+          if ((grp >> lane) & 1) {
+            sl[j] = s;
+            rk[j] = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1));
+          }
+          act &= ~grp;
+        }
+      }
+      if ((act >> lane) & 1) {
+        uint32_t s = (b * 0x9E3779B1u) >> 21;
+        for (;;) {
+          const uint32_t k = atomicCAS(&skey[s], 0u, b + 1);
+          if (k == 0) used[atomicAdd(&nused, 1u)] = (uint16_t)s;
+          if (k == 0 || k == b + 1) break;
+          s = (s + 1) & (kScatterSlots - 1);
+        }
+        sl[j] = s;
+        rk[j] = atomicAdd(&scnt[s], 1u);
+      }
     }
     __syncthreads();
     // one reservation per bucket present in the tile; scnt becomes the base
