@@ -286,9 +286,12 @@ typedef struct {
   uint64_t verdict_units; /* (query, tuple) units searched tile by tile */
   double split_ms;        /* items split by (address, block) */
   uint64_t split_items;
-  uint64_t scatter_launches; /* partition kernels timed in scatter_ms */
-  uint64_t scatter_bytes;    /* record bytes they wrote */
+  uint64_t scatter_launches; /* table-path partition launches (k_scatter
+                                with term tables), timed in scatter_tab_ms */
+  uint64_t scatter_bytes;    /* record bytes all partition kernels wrote */
   uint64_t fallback_records; /* point bound of the fallback items */
+  double scatter_tab_ms;     /* table-path partition kernels */
+  uint64_t scatter_tab_bytes; /* record bytes they wrote */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

@@ -115,7 +115,8 @@ class rd_stats(C.Structure):
                 ("waves_ms", C.c_double), ("verdict_ms", C.c_double),
                 ("verdict_units", C.c_uint64), ("split_ms", C.c_double),
                 ("split_items", C.c_uint64), ("scatter_launches", C.c_uint64),
-                ("scatter_bytes", C.c_uint64), ("fallback_records", C.c_uint64)]
+                ("scatter_bytes", C.c_uint64), ("fallback_records", C.c_uint64),
+                ("scatter_tab_ms", C.c_double), ("scatter_tab_bytes", C.c_uint64)]
 
 
 assert C.sizeof(rd_pair_result) == 88

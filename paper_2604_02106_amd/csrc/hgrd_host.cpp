@@ -1707,7 +1707,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   plan->buf("ovf", std::max<size_t>(1, plan->hitems.size()) * 4, &merr);
   plan->buf("done", std::max<size_t>(1, n_pairs) * 4, &merr);
   plan->buf("pcursor", 4, &merr);
-  plan->buf("nbytes", 64 * 8, &merr);
+  plan->buf("nbytes", 128 * 8, &merr);
   plan->buf("out", std::max<size_t>(1, n_pairs) * sizeof(rd_pair_result), &merr);
   if (merr) return merr;
   *plan_out = guard.release();
@@ -1766,7 +1766,9 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   // their times are collected once the stream has drained.  A replayed
   // graph carries no events (their times are not reliable inside graphs).
   uint32_t wev_n = 0;
-  std::vector<std::array<uint32_t, 3>> wtimes;
+  // per wave: events before and after the table partition, after the
+  // interpreted partition and after the join; whether tables ran
+  std::vector<std::array<uint32_t, 5>> wtimes;
   auto wevent = [&](uint32_t k) -> hipEvent_t {
     while (ctx->wev.size() <= k) {
       hipEvent_t e = nullptr;
@@ -1782,29 +1784,40 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     const uint32_t wcap = (uint32_t)join_cap(wcfg);
     for (const auto& W : waves) {
       const uint32_t k = wev_n;
-      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
       if (events) {
-        wev_n += 3;
+        wev_n += 4;
         e0 = wevent(k);
         e1 = wevent(k + 1);
         e2 = wevent(k + 2);
-        if (!e0 || !e1 || !e2) return RD_EDEVICE;
+        e3 = wevent(k + 3);
+        if (!e0 || !e1 || !e2 || !e3) return RD_EDEVICE;
       }
       if (launch_fill_u32(st, d_cursor, W.n_buckets, 0)) return RD_EDEVICE;
+      // partition: instances with term tables, then the interpreted ones
+      // (record bytes counted in slots 0..63 and 64..127)
       if (events) TRY_HIP(hipEventRecord(e0, st));
-      if (launch_scatter(st, d_chk + W.chunk_off, W.n_chunks, d_hit, d_insts,
+      if (W.n_tab_chunks &&
+          launch_scatter(st, d_chk + W.chunk_off, W.n_tab_chunks, true, d_hit, d_insts,
                          d_code, d_params, d_loops, d_acc, d_recs,
-                         d_cursor, d_ovf, wcap, d_done, d_nbytes, W.n_tab_chunks))
+                         d_cursor, d_ovf, wcap, d_done, d_nbytes))
         return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(e1, st));
+      if (W.n_chunks > W.n_tab_chunks &&
+          launch_scatter(st, d_chk + W.chunk_off + W.n_tab_chunks,
+                         W.n_chunks - W.n_tab_chunks, false, d_hit, d_insts,
+                         d_code, d_params, d_loops, d_acc, d_recs,
+                         d_cursor, d_ovf, wcap, d_done, d_nbytes + 64))
+        return RD_EDEVICE;
+      if (events) TRY_HIP(hipEventRecord(e2, st));
       if (W.n_runs &&
           launch_bucket(wcfg, st, W.n_runs, d_bit + W.bitem_off, d_hit,
                         d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs,
                         d_cursor, d_ovf, d_done, l0k, l0c))
         return RD_EDEVICE;
       if (events) {
-        TRY_HIP(hipEventRecord(e2, st));
-        wtimes.push_back({k, k + 1, k + 2});
+        TRY_HIP(hipEventRecord(e3, st));
+        wtimes.push_back({k, k + 1, k + 2, k + 3, W.n_tab_chunks ? 1u : 0u});
       }
       if (W.n_buckets) S.join_launches += 1;
       S.buckets += W.n_buckets;
@@ -1816,9 +1829,14 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       float ms = 0;
       if (hipEventElapsedTime(&ms, ctx->wev[t[0]], ctx->wev[t[1]]) == hipSuccess) {
         scatter_ms += ms;
-        S.scatter_launches += 1;
+        if (t[4]) {
+          S.scatter_tab_ms += ms;
+          S.scatter_launches += 1;
+        }
       }
       if (hipEventElapsedTime(&ms, ctx->wev[t[1]], ctx->wev[t[2]]) == hipSuccess)
+        scatter_ms += ms;
+      if (hipEventElapsedTime(&ms, ctx->wev[t[2]], ctx->wev[t[3]]) == hipSuccess)
         bucket_ms += ms;
     }
     wtimes.clear();
@@ -1836,7 +1854,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       return RD_EDEVICE;
     if (launch_init_acc(st, n_pairs, d_acc)) return RD_EDEVICE;
     if (launch_fill_u32(st, d_done, n_pairs, 0)) return RD_EDEVICE;
-    if (launch_fill_u64(st, d_nbytes, 64, 0)) return RD_EDEVICE;
+    if (launch_fill_u64(st, d_nbytes, 128, 0)) return RD_EDEVICE;
     if (plan->verdict && plan->n_vq) {
       VQuery* d_vq = (VQuery*)D("vq");
       BBound* d_bb = (BBound*)D("bbounds");
@@ -2274,10 +2292,13 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   TRY_HIP(hipEventRecord(ev[1], st));
   if (n_pairs)
     TRY_HIP(hipMemcpyAsync(out, d_out, n_pairs * sizeof(rd_pair_result), hipMemcpyDeviceToHost, st));
-  u64 scat_bytes[64];
+  u64 scat_bytes[128];
   TRY_HIP(hipMemcpyAsync(scat_bytes, d_nbytes, sizeof scat_bytes, hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
-  for (u64 b : scat_bytes) S.scatter_bytes += b;
+  for (int k = 0; k < 128; ++k) {
+    S.scatter_bytes += scat_bytes[k];
+    if (k < 64) S.scatter_tab_bytes += scat_bytes[k];
+  }
   float ms = 0;
   if (!w2.empty()) {
     (void)hipEventElapsedTime(&ms, ev[9], ev[10]);

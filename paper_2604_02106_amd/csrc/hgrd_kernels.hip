@@ -1102,24 +1102,23 @@ int launch_tabulate(hipStream_t st, const Chunk* chunks, uint32_t n,
   return 0;
 }
 
-int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n,
+int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n, bool tab,
                    const HItem* hitems, const void* insts, const DInsn* code,
                    const int64_t* params, const int64_t* loopvals, QAcc* acc,
                    unsigned char* recs, uint32_t* cursor,
                    uint32_t* ovf, uint32_t capb, const uint32_t* done,
-                   unsigned long long* nbytes, uint32_t n_tab) {
-  // chunks [0, n_tab) are of instances with term tables
+                   unsigned long long* nbytes) {
+  // tab: every chunk's instance has term tables
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
-    uint32_t mt = off >= n_tab ? 0 : (n_tab - off < m ? n_tab - off : m);
-    if (mt)
-      hipLaunchKernelGGL(k_scatter<true>, dim3(mt), dim3(256), 0, st, chunks + off,
+    if (tab)
+      hipLaunchKernelGGL(k_scatter<true>, dim3(m), dim3(256), 0, st, chunks + off,
                          hitems, (const DevInst*)insts, code, params, loopvals,
                          acc, recs, cursor, ovf, capb, done, nbytes);
-    if (m > mt)
-      hipLaunchKernelGGL(k_scatter<false>, dim3(m - mt), dim3(256), 0, st,
-                         chunks + off + mt, hitems, (const DevInst*)insts, code,
-                         params, loopvals, acc, recs, cursor, ovf, capb, done, nbytes);
+    else
+      hipLaunchKernelGGL(k_scatter<false>, dim3(m), dim3(256), 0, st, chunks + off,
+                         hitems, (const DevInst*)insts, code, params, loopvals,
+                         acc, recs, cursor, ovf, capb, done, nbytes);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;

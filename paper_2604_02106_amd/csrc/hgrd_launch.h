@@ -36,12 +36,12 @@ int launch_small(int cfg, hipStream_t st, const SItem* items, uint32_t n,
                  const uint32_t* done, uint32_t* cursor, uint32_t persist_grid);
 int init_kernel_attributes();
 int init_verdict_attributes();
-int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n,
+int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n, bool tab,
                    const HItem* hitems, const void* insts, const DInsn* code,
                    const int64_t* params, const int64_t* loopvals, QAcc* acc,
                    unsigned char* recs, uint32_t* cursor,
                    uint32_t* ovf, uint32_t capb, const uint32_t* done,
-                   unsigned long long* nbytes, uint32_t n_tab);
+                   unsigned long long* nbytes);
 int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
                   const HItem* hitems, const void* insts, const DInsn* code,
                   const int64_t* params, const int64_t* loopvals, const QDesc* qd,
