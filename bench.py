@@ -87,6 +87,72 @@ def cpu_baseline(wl, gpu_res, budget_s=20.0, seed=7):
             "agreement": "%d/%d sampled pairs identical to the GPU" % (agree, done)}
 
 
+def run_learned(args):
+    """Learned tile order on sparse witnesses (16384 queries, G = 256 blocks
+    per side, one conflicting block pair in 2^16 for the racy half): EXACT,
+    VERDICT with LEX order and VERDICT with the trained MLP order, each timed
+    over the same steps; tiles examined before the first witness."""
+    import numpy as np
+    import torch
+    import paper_2604_02106_amd as hg
+    from paper_2604_02106_amd import tile_mlp
+    from workloads import configs
+    wl = configs.sparse(seed=4004, n_queries=int(16384 * args.scale))
+    try:
+        w, meta = tile_mlp.load()
+        wsrc = "committed weights (%s)" % os.path.relpath(tile_mlp.DEFAULT, ROOT)
+    except OSError:
+        log("no committed weights: training")
+        w, _, _ = tile_mlp.train(hg.Context(0))
+        wsrc = "trained in this run"
+    ctx = hg.Context(0)
+    n = len(wl.pairs)
+    out = {}
+    for name, mode, order in (("exact", hg.MODE_EXACT, 0),
+                              ("verdict_lex", hg.MODE_VERDICT, hg.ORDER_LEX),
+                              ("verdict_mlp", hg.MODE_VERDICT, hg.ORDER_MLP)):
+        plan = hg.Plan(ctx, wl, mode=mode, order=order,
+                       mlp=w if order == hg.ORDER_MLP else None)
+        for _ in range(max(1, args.warmup)):
+            res = plan.execute()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.execute(raw=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        out[name] = (res, plan.tiles(), dt)
+        log("%s: %.3f s per step" % (name, dt))
+        plan.close()
+    verdicts = [r["verdict"] for r in out["exact"][0]]
+    agree = all([r["verdict"] for r in out[k][0]] == verdicts for k in out)
+    racy = [k for k, v in enumerate(verdicts) if v]
+
+    def tile_stats(tiles):
+        t = np.array([tiles[k] if tiles[k] else 10 ** 9 for k in racy], dtype=float)
+        found = t < 10 ** 9
+        return {"median": float(np.median(t[found])) if found.any() else None,
+                "p90": float(np.percentile(t[found], 90)) if found.any() else None,
+                "stopped": int(found.sum()), "racy": len(racy)}
+    line = {
+        "metric": "race queries/sec, VERDICT mode with learned tile order",
+        "value": n / out["verdict_mlp"][2], "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": out["verdict_mlp"][2] * 1000, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "sparse witnesses: %d queries, 256 blocks x 256 "
+                               "threads per side, one conflicting block pair "
+                               "in 2^16 for the racy half, seed 4004" % n,
+                   "weights": wsrc},
+        "queries_per_s": {k: n / v[2] for k, v in out.items()},
+        "tiles_to_witness": {"lex": tile_stats(out["verdict_lex"][1]),
+                             "mlp": tile_stats(out["verdict_mlp"][1])},
+        "verdicts_agree": agree,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,7 +161,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--config", default="batched",
-                    choices=("batched", "stress", "mixed"),
+                    choices=("batched", "stress", "mixed", "learned"),
                     help="workload: batched uneven queries (the headline), "
                          "race-free stress (128 pairs, 2^30 points per "
                          "access), or mixed domain sizes")
@@ -110,6 +176,8 @@ def main():
               "(queries shard across GPUs without exchange, see the design "
               "notes)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.config == "learned":
+        return run_learned(args)
     import torch
     if args.calibrate_copy:
         # 8 GiB: far beyond the 256 MiB last-level cache, so the counters see

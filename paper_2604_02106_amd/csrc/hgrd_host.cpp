@@ -1877,7 +1877,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       for (auto& rr : plan->rounds) {
         if (launch_tile_join(cfg, st, (const TItem*)D("titems"), rr.first,
                              rr.second - rr.first, d_vq, d_order, plan->K, d_insts,
-                             d_code, d_params, d_loops, d_qd, d_done, d_tout, d_claim) ||
+                             d_code, d_params, d_loops, d_qd, d_done, d_tout, d_claim, d_bb) ||
             launch_verdict_commit(st, n_pairs, d_claim, d_tout, d_acc, d_done))
           return RD_EDEVICE;
       }
@@ -2444,7 +2444,7 @@ int rd_tile_data(rd_context* ctx, const rd_kernel_model* models,
                          rr.second - rr.first, d_vq, nullptr, plan->K, D("insts"),
                          (const DInsn*)D("code"), (const int64_t*)D("params"),
                          (const int64_t*)D("loops"), (const QDesc*)D("qdesc"), d_done,
-                         d_tout, (u64*)D("claim")))
+                         d_tout, (u64*)D("claim"), d_bb))
       return RD_EDEVICE;
   std::vector<TOut> tout(plan->n_titems);
   std::vector<QAcc> acc(n_pairs);

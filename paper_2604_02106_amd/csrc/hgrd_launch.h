@@ -94,7 +94,7 @@ int launch_tile_join(int cfg, hipStream_t st, const TItem* items, uint32_t item0
                      uint32_t K, const void* insts, const DInsn* code,
                      const int64_t* params, const int64_t* loopvals,
                      const QDesc* qd, uint32_t* done, TOut* tout,
-                     unsigned long long* claim);
+                     unsigned long long* claim, const BBound* bb);
 int launch_verdict_commit(hipStream_t st, uint32_t n,
                           const unsigned long long* claim, const TOut* tout,
                           QAcc* acc, uint32_t* done);

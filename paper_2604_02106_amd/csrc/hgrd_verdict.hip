@@ -197,9 +197,15 @@ k_tile_scores(const TChunk* __restrict__ chunks, const VQuery* __restrict__ vq,
     float s;
     if (use_mlp) {
       uint32_t b1 = t / v.G, b2 = t - b1 * v.G;
-      float f[kIn];
-      tile_features(v, b1, b2, bb[v.bb_i + b1], bb[v.bb_j + b2], f);
-      s = mlp_logit(sw, f);
+      const BBound x = bb[v.bb_i + b1], y = bb[v.bb_j + b2];
+      if (!x.cnt || !y.cnt || x.mx < y.mn || y.mx < x.mn) {
+        // disjoint address ranges: no conflict in this tile, last in order
+        s = -INFINITY;
+      } else {
+        float f[kIn];
+        tile_features(v, b1, b2, x, y, f);
+        s = mlp_logit(sw, f);
+      }
     } else {
       s = -(float)t;
     }
@@ -356,10 +362,23 @@ k_topk(const VQuery* __restrict__ vq, const float* __restrict__ scores,
     if (threadIdx.x == 0) {
       for (uint32_t k = 1; k < (blockDim.x >> 6); ++k)
         if (bs[k] > best || (bs[k] == best && bi[k] < bidx)) { best = bs[k]; bidx = bi[k]; }
-      if (bidx == 0xFFFFFFFFu) bidx = 0;
-      order[(u64)blockIdx.x * K + r] = bidx;
-      sel[bidx >> 5] |= 1u << (bidx & 31);
+      if (best == -INFINITY) {
+        // every tile left scores -inf: the rest of the order is index order
+        uint32_t t = 0;
+        for (uint32_t r2 = r; r2 < kk; ++r2, ++t) {
+          while ((sel[t >> 5] >> (t & 31)) & 1) ++t;
+          order[(u64)blockIdx.x * K + r2] = t;
+        }
+        bs[0] = -INFINITY;
+      } else {
+        if (bidx == 0xFFFFFFFFu) bidx = 0;
+        order[(u64)blockIdx.x * K + r] = bidx;
+        sel[bidx >> 5] |= 1u << (bidx & 31);
+        bs[0] = best;
+      }
     }
+    __syncthreads();
+    if (bs[0] == -INFINITY) break;
     __syncthreads();
   }
 }
@@ -378,7 +397,7 @@ k_tile_join(const TItem* __restrict__ items, const VQuery* __restrict__ vq,
             const int64_t* __restrict__ params,
             const int64_t* __restrict__ loopvals, const QDesc* __restrict__ qd,
             uint32_t* __restrict__ done, TOut* __restrict__ tout,
-            u64* __restrict__ claim, uint32_t item0) {
+            u64* __restrict__ claim, uint32_t item0, const BBound* __restrict__ bb) {
   extern __shared__ __align__(16) unsigned char smem[];
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
   __shared__ uint32_t pidx_star;
@@ -389,6 +408,11 @@ k_tile_join(const TItem* __restrict__ items, const VQuery* __restrict__ vq,
   const QDesc q = qd[v.q];
   const uint32_t tile = order ? order[(u64)it.vq * K + it.rank] : it.rank;
   const uint32_t b1 = tile / v.G, b2 = tile - (tile / v.G) * v.G;
+  {
+    // a tile whose blocks' address ranges are disjoint holds no conflict
+    const BBound x = bb[v.bb_i + b1], y = bb[v.bb_j + b2];
+    if (!x.cnt || !y.cnt || x.mx < y.mn || y.mx < x.mn) return;
+  }
   if (threadIdx.x == 0) {
     S.n = 0;
     S.err = 0;
@@ -560,13 +584,13 @@ static int launch_tile_join_t(hipStream_t st, const TItem* items, uint32_t item0
                               uint32_t K, const void* insts, const DInsn* code,
                               const int64_t* params, const int64_t* loopvals,
                               const QDesc* qd, uint32_t* done, TOut* tout,
-                              u64* claim) {
+                              u64* claim, const BBound* bb) {
   size_t lds = sizeof(JoinLds<CAP, TBL>);
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
     hipLaunchKernelGGL((k_tile_join<CAP, TBL>), dim3(m), dim3(256), lds, st,
                        items, vq, order, K, (const DevInst*)insts, code, params,
-                       loopvals, qd, done, tout, claim, item0 + off);
+                       loopvals, qd, done, tout, claim, item0 + off, bb);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -577,11 +601,11 @@ int launch_tile_join(int cfg, hipStream_t st, const TItem* items, uint32_t item0
                      uint32_t K, const void* insts, const DInsn* code,
                      const int64_t* params, const int64_t* loopvals,
                      const QDesc* qd, uint32_t* done, TOut* tout,
-                     unsigned long long* claim) {
+                     unsigned long long* claim, const BBound* bb) {
   switch (cfg) {
-    case 0: return launch_tile_join_t<1024, 2048>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim);
-    case 1: return launch_tile_join_t<1536, 4096>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim);
-    default: return launch_tile_join_t<3072, 8192>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim);
+    case 0: return launch_tile_join_t<1024, 2048>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim, bb);
+    case 1: return launch_tile_join_t<1536, 4096>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim, bb);
+    default: return launch_tile_join_t<3072, 8192>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim, bb);
   }
 }
 
