@@ -471,7 +471,23 @@ struct TNode {
   uint8_t groups = 0;   // bit 0 blocks, bit 1 threads, bit 2 loop values
   int64_t val = 0;      // value of a uniform node
   i128 lo = 0, hi = 0;  // value range over the box
+  uint64_t g = 1;       // every value of the node is a multiple of g (0: always 0)
 };
+
+inline uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) {
+    const uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+inline uint64_t uabs64(int64_t v) { return v < 0 ? 0 - (uint64_t)v : (uint64_t)v; }
+// product of two divisors, 1 (always a divisor) when it does not fit
+inline uint64_t gmul(uint64_t a, uint64_t b) {
+  const unsigned __int128 p = (unsigned __int128)a * b;
+  return p >> 62 ? 1 : (uint64_t)p;
+}
 
 inline bool fits64(i128 v) { return v >= kI64Lo && v <= kI64Hi; }
 inline i128 i128abs(i128 v) { return v < 0 ? -v : v; }
@@ -535,6 +551,7 @@ struct STerm {
   int64_t mult = 1;
   i128 lo = 0, hi = 0;
   int group = 0;
+  uint64_t g = 1;  // every value of `code` is a multiple of g
 };
 
 struct Lin {
@@ -564,6 +581,7 @@ struct TermBuilder {
   const int64_t* dims;
   const int64_t* lmin;
   const int64_t* lmax;
+  const uint64_t* lgcd;  // per loop position: gcd of its values
   std::vector<TNode> nodes;
   const rd_insn* ins = nullptr;
 
@@ -593,10 +611,14 @@ struct TermBuilder {
             n.groups = 4;
             n.lo = lmin[p];
             n.hi = lmax[p];
+            n.g = lgcd[p];
             break;
           }
         }
-        if (n.groups == 0) n.lo = n.hi = n.val;
+        if (n.groups == 0) {
+          n.lo = n.hi = n.val;
+          n.g = uabs64(n.val);
+        }
       } else if (is_unary(t.op)) {
         const TNode& c = nodes[st.back()];
         n.kid[0] = st.back();
@@ -611,9 +633,11 @@ struct TermBuilder {
           n.lo = 0;
           n.hi = 1;
         }
+        n.g = t.op == RD_OP_NEG ? c.g : 1;
         if (!n.groups) {
           n.val = t.op == RD_OP_NEG ? -c.val : (c.val == 0);
           n.lo = n.hi = n.val;
+          n.g = uabs64(n.val);
         }
       } else {
         n.kid[1] = st.back();
@@ -629,8 +653,20 @@ struct TermBuilder {
           n.val = hop(t.op, a.val, b.val, err);
           if (err) return false;
           n.lo = n.hi = n.val;
-        } else if (!range_op(t.op, a.lo, a.hi, b.lo, b.hi, n.lo, n.hi)) {
-          return false;
+          n.g = uabs64(n.val);
+        } else {
+          if (!range_op(t.op, a.lo, a.hi, b.lo, b.hi, n.lo, n.hi)) return false;
+          switch (t.op) {
+            case RD_OP_ADD:
+            case RD_OP_SUB:
+            case RD_OP_MIN:
+            case RD_OP_MAX: n.g = gcd64(a.g, b.g); break;
+            case RD_OP_MUL: n.g = gmul(a.g, b.g); break;
+            case RD_OP_SHL:
+              n.g = b.groups ? 1 : gmul(a.g, 1ull << (b.val & 63));
+              break;
+            default: n.g = 1;
+          }
         }
       }
       st.push_back((int)nodes.size());
@@ -648,7 +684,8 @@ struct TermBuilder {
   static bool single(uint8_t g) { return g == 1 || g == 2 || g == 4; }
   static int gidx(uint8_t g) { return g == 1 ? 0 : g == 2 ? 1 : 2; }
 
-  bool add_term(Lin& L, std::vector<rd_insn>&& code, i128 lo, i128 hi, int group, i128 mu) {
+  bool add_term(Lin& L, std::vector<rd_insn>&& code, i128 lo, i128 hi, int group, i128 mu,
+                uint64_t g = 1) {
     if (!fits64(mu)) return false;
     if (mu == 0) return true;
     STerm t;
@@ -657,6 +694,7 @@ struct TermBuilder {
     t.lo = lo;
     t.hi = hi;
     t.group = group;
+    t.g = g;
     if (!fits64(contrib_abs(t))) return false;
     L.terms.push_back(std::move(t));
     return true;
@@ -689,7 +727,7 @@ struct TermBuilder {
     if (single(n.groups)) {
       std::vector<rd_insn> code;
       subtree(i, code);
-      return add_term(L, std::move(code), n.lo, n.hi, gidx(n.groups), mu);
+      return add_term(L, std::move(code), n.lo, n.hi, gidx(n.groups), mu, n.g);
     }
     const TNode* a = n.kid[0] >= 0 ? &nodes[n.kid[0]] : nullptr;
     const TNode* b = n.kid[1] >= 0 ? &nodes[n.kid[1]] : nullptr;
@@ -714,7 +752,9 @@ struct TermBuilder {
         i128 xlo = 0, ylo = in.u, yhi = in.u;
         int yg = -1;
         for (const STerm& t : in.terms) {
-          if (t.mult % d == 0) {
+          // divisible when (multiple of g) * mult is always a multiple of d
+          if (gmul(t.g, uabs64(t.mult)) % (uint64_t)d == 0 && t.g != 1 ? true
+              : t.mult % d == 0) {
             xs.push_back(&t);
             xlo += contrib_lo(t);
           } else {
@@ -731,8 +771,22 @@ struct TermBuilder {
         if (yabs > kI64Hi) return false;
         if (n.op == RD_OP_DIV)
           for (const STerm* t : xs) {
+            // t = v * mult with d | g * mult: t / d = (v / d1) * (mult / gm),
+            // gm = gcd(d, |mult|), d1 = d / gm dividing every v
+            const uint64_t gm = gcd64((uint64_t)d, uabs64(t->mult));
+            const int64_t d1 = (int64_t)((uint64_t)d / gm);
             std::vector<rd_insn> code = t->code;
-            if (!add_term(L, std::move(code), t->lo, t->hi, t->group, mu * (i128)(t->mult / d)))
+            i128 lo = t->lo, hi = t->hi;
+            uint64_t g = t->g;
+            if (d1 != 1) {
+              code.push_back(mk_insn(RD_OP_CONST, d1));
+              code.push_back(mk_insn(RD_OP_DIV));
+              lo /= d1;
+              hi /= d1;
+              g = g / (uint64_t)d1;
+            }
+            if (!add_term(L, std::move(code), lo, hi, t->group,
+                          mu * (i128)(t->mult / (int64_t)gm), g))
               return false;
           }
         if (ys.empty()) {  // uniform remainder part
@@ -833,13 +887,17 @@ struct Planner {
     const rd_access& A = M.acc[a];
     const int64_t* pv = pool_params.data() + I.params_off;
     int64_t dims[6], lmin[4] = {0, 0, 0, 0}, lmax[4] = {0, 0, 0, 0};
+    uint64_t lgcd[4] = {1, 1, 1, 1};
     for (int k = 0; k < 6; ++k) dims[k] = I.dims[k];
     for (uint32_t k = 0; k < I.n_loops; ++k) {
       const int64_t* v = pool_loops.data() + I.loop_off[k];
       lmin[k] = *std::min_element(v, v + I.loop_n[k]);
       lmax[k] = *std::max_element(v, v + I.loop_n[k]);
+      uint64_t g = 0;
+      for (uint32_t e = 0; e < I.loop_n[k]; ++e) g = gcd64(g, uabs64(v[e]));
+      lgcd[k] = g;
     }
-    TermBuilder tb{M, A, pv, dims, lmin, lmax};
+    TermBuilder tb{M, A, pv, dims, lmin, lmax, lgcd};
     // address
     if (!tb.build(A.addr)) return;
     const i128 root_lo = tb.nodes.back().lo, root_hi = tb.nodes.back().hi;

@@ -194,11 +194,12 @@ __device__ __forceinline__ uint32_t bucket_of(const HItem& h, int64_t addr,
 // addresses together, so a chunk touches few buckets and its writes are
 // runs of whole lines.  TAB: every instance of the launch has term tables
 // (no interpreter code, fewer registers, more waves in flight).
-constexpr uint32_t kScatterPts = 1024;  // points per LDS tile
-constexpr uint32_t kScatterSlots = 2048;
+constexpr uint32_t kScatterThreads = 512;  // partition workgroup size
+constexpr uint32_t kScatterPts = 2048;     // points per LDS tile
+constexpr uint32_t kScatterSlots = 4096;
 constexpr uint32_t kByteSlots = 64;     // spread of the record-byte counters
 template <bool TAB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kScatterThreads)
 k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
           const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
           const int64_t* __restrict__ params,
@@ -219,8 +220,8 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
   uint32_t err = 0;
   const bool store = h.nbuckets != 0;  // 0: error scan only
   const uint32_t rs = h.is32 ? 8 : 16;
-  constexpr int kPer = kScatterPts / 256;
-  for (uint32_t k = threadIdx.x; k < kScatterSlots; k += 256) {
+  constexpr int kPer = kScatterPts / kScatterThreads;
+  for (uint32_t k = threadIdx.x; k < kScatterSlots; k += kScatterThreads) {
     skey[k] = 0;
     scnt[k] = 0;
   }
@@ -236,7 +237,7 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
     for (int j = 0; j < kPer; ++j) {
       sl[j] = kScatterSlots;
       bk[j] = 0xFFFFFFFFu;  // no record
-      const uint32_t pidx = t0 + (uint32_t)j * 256 + threadIdx.x;
+      const uint32_t pidx = t0 + (uint32_t)j * kScatterThreads + threadIdx.x;
       if (pidx >= ch.p1) continue;
       const PointIds id = decode(I, pidx);
       Point pt;
@@ -265,7 +266,7 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
           const u64 grp = __ballot(v && b == bl) & act;
           uint32_t s = 0, base = 0;
           if (lane == leader) {
-            s = (bl * 0x9E3779B1u) >> 21;  // 11 bits: kScatterSlots
+            s = (bl * 0x9E3779B1u) >> 20;  // 12 bits: kScatterSlots
             for (;;) {
               const uint32_t k = atomicCAS(&skey[s], 0u, bl + 1);
               if (k == 0) used[atomicAdd(&nused, 1u)] = (uint16_t)s;
@@ -284,7 +285,7 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
         }
       }
       if ((act >> lane) & 1) {
-        uint32_t s = (b * 0x9E3779B1u) >> 21;
+        uint32_t s = (b * 0x9E3779B1u) >> 20;
         for (;;) {
           const uint32_t k = atomicCAS(&skey[s], 0u, b + 1);
           if (k == 0) used[atomicAdd(&nused, 1u)] = (uint16_t)s;
@@ -299,7 +300,7 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
     // one reservation per bucket present in the tile; scnt becomes the base
     const uint32_t nu = nused;
     u64 written = 0;
-    for (uint32_t u = threadIdx.x; u < nu; u += 256) {
+    for (uint32_t u = threadIdx.x; u < nu; u += kScatterThreads) {
       const uint32_t k = used[u];
       const uint32_t n = scnt[k];
       const uint32_t base = atomicAdd(&cursor[h.bucket0 + skey[k] - 1], n);
@@ -327,7 +328,7 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
     }
     __syncthreads();
     // clear the slots this tile used
-    for (uint32_t u = threadIdx.x; u < nu; u += 256) {
+    for (uint32_t u = threadIdx.x; u < nu; u += kScatterThreads) {
       skey[used[u]] = 0;
       scnt[used[u]] = 0;
     }
@@ -1112,11 +1113,11 @@ int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n, bool tab,
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
     if (tab)
-      hipLaunchKernelGGL(k_scatter<true>, dim3(m), dim3(256), 0, st, chunks + off,
+      hipLaunchKernelGGL(k_scatter<true>, dim3(m), dim3(kScatterThreads), 0, st, chunks + off,
                          hitems, (const DevInst*)insts, code, params, loopvals,
                          acc, recs, cursor, ovf, capb, done, nbytes);
     else
-      hipLaunchKernelGGL(k_scatter<false>, dim3(m), dim3(256), 0, st, chunks + off,
+      hipLaunchKernelGGL(k_scatter<false>, dim3(m), dim3(kScatterThreads), 0, st, chunks + off,
                          hitems, (const DevInst*)insts, code, params, loopvals,
                          acc, recs, cursor, ovf, capb, done, nbytes);
     HGRD_CHECK(hipGetLastError());
