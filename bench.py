@@ -238,6 +238,18 @@ def main():
     res = [hg.result_dict(plan.out[k]) for k in range(len(wl.pairs))]
     assert res == e2e
     tstat = stats[-1]
+    # with the exact interval pre-filter (beside the headline)
+    pplan = hg.Plan(ctx, wl, max_device_bytes=args.wave_mib << 20, prefilter=1)
+    pres = pplan.execute()
+    assert pres == res
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        pplan.execute(raw=True)
+    torch.cuda.synchronize()
+    dt_pre = time.perf_counter() - t0
+    pre_units = ctx.stats()["prefiltered"]
+    pplan.close()
     # the same plan replaying its captured graph (beside the headline)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -268,6 +280,8 @@ def main():
         "evals_per_s_G": evals * args.steps / dt / 1e9,
         "end_to_end_queries_per_s": n / e2e_s,
         "graph_replay_queries_per_s": n * args.steps / dt_graph,
+        "prefilter_queries_per_s": n * args.steps / dt_pre,
+        "prefilter_units": pre_units,
         "prepare_s": prep_s,
         "kernel_ms": {k: sum(s[k] for s in stats) / len(stats)
                       for k in ("device_ms", "total_ms")},

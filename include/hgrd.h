@@ -172,7 +172,9 @@ typedef struct {
 typedef struct {
   uint32_t mode;       /* RD_MODE_EXACT (default) or RD_MODE_VERDICT */
   uint32_t order;      /* VERDICT tile order: RD_ORDER_LEX or RD_ORDER_MLP */
-  uint32_t batched;    /* reserved; 0 */
+  uint32_t prefilter;  /* 1: decide (pair, tuple) units whose two address
+                          ranges (bounds proven for the term tables) do not
+                          meet without enumerating them (exact); 0: off */
   uint32_t log_level;  /* 0 silent, 1 summary, 2 per-launch (stderr) */
   uint32_t lds_cap;    /* records per LDS join tile (1024, 1536 or 3072);
                           0 = the context's default (1536 until
@@ -292,6 +294,7 @@ typedef struct {
   uint64_t fallback_records; /* point bound of the fallback items */
   double scatter_tab_ms;     /* table-path partition kernels */
   uint64_t scatter_tab_bytes; /* record bytes they wrote */
+  uint64_t prefiltered;      /* (pair, tuple) units the pre-filter decided */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

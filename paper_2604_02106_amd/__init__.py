@@ -84,7 +84,7 @@ rd_mlp = C.c_float * N_MLP  # w1, b1, w2, b2, w3, b3 (include/hgrd.h)
 
 class rd_options(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("order", C.c_uint32),
-                ("batched", C.c_uint32), ("log_level", C.c_uint32),
+                ("prefilter", C.c_uint32), ("log_level", C.c_uint32),
                 ("lds_cap", C.c_uint32), ("tile_budget", C.c_uint32),
                 ("mlp", C.c_void_p),
                 ("max_device_bytes", C.c_uint64), ("stream", C.c_void_p)]
@@ -116,7 +116,8 @@ class rd_stats(C.Structure):
                 ("verdict_units", C.c_uint64), ("split_ms", C.c_double),
                 ("split_items", C.c_uint64), ("scatter_launches", C.c_uint64),
                 ("scatter_bytes", C.c_uint64), ("fallback_records", C.c_uint64),
-                ("scatter_tab_ms", C.c_double), ("scatter_tab_bytes", C.c_uint64)]
+                ("scatter_tab_ms", C.c_double), ("scatter_tab_bytes", C.c_uint64),
+                ("prefiltered", C.c_uint64)]
 
 
 assert C.sizeof(rd_pair_result) == 88
@@ -304,8 +305,8 @@ def _as_f32(a, n=None):
 
 
 def _options(mode, order, lds_cap, max_device_bytes, log_level, stream,
-             mlp=None, tile_budget=0):
-    o = rd_options(mode, order, 0, log_level, lds_cap, tile_budget, None,
+             mlp=None, tile_budget=0, prefilter=0):
+    o = rd_options(mode, order, prefilter, log_level, lds_cap, tile_budget, None,
                    max_device_bytes, _stream_handle(stream))
     keep = None
     if mlp is not None:
@@ -325,13 +326,13 @@ class Plan:
 
     def __init__(self, ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
                  lds_cap=0, max_device_bytes=0, log_level=0, stream=None,
-                 mlp=None, tile_budget=0):
+                 mlp=None, tile_budget=0, prefilter=0):
         self.ctx = ctx
         self.n = len(workload.pairs)
         pk = Packed(workload)
         pairs = _pairs(workload)
         opt, keep = _options(mode, order, lds_cap, max_device_bytes, log_level,
-                             stream, mlp, tile_budget)
+                             stream, mlp, tile_budget, prefilter)
         self.h = C.c_void_p()
         st = lib().rd_prepare(ctx.h, pk.models, pk.n_models, pairs, self.n,
                               pk.launch, pk.params, C.byref(opt), C.byref(self.h))
@@ -366,7 +367,7 @@ class Plan:
 
 def rd_check_pairs(ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
                    lds_cap=0, max_device_bytes=0, log_level=0, stream=None,
-                   packed=None, mlp=None, tile_budget=0):
+                   packed=None, mlp=None, tile_budget=0, prefilter=0):
     """Decides every pair of ``workload`` on the GPU.
 
     Returns a list of result dicts (same fields as rd_pair_result).
@@ -376,7 +377,7 @@ def rd_check_pairs(ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
     pairs = _pairs(workload)
     out = (rd_pair_result * max(1, n))()
     opt, keep = _options(mode, order, lds_cap, max_device_bytes, log_level,
-                         stream, mlp, tile_budget)
+                         stream, mlp, tile_budget, prefilter)
     st = lib().rd_check_pairs(ctx.h, pk.models, pk.n_models, pairs, n,
                               pk.launch, pk.params, C.byref(opt), out)
     if st != RD_OK:

@@ -1267,6 +1267,7 @@ struct rd_plan_impl {
   uint32_t chunk_pts = 4096;  // points per partition workgroup
   uint32_t run_buckets = 4;   // buckets per join workgroup
   uint32_t n_tabchunks = 0;   // term-table fill chunks
+  uint64_t prefiltered = 0;   // (pair, tuple) units decided by the pre-filter
   uint32_t n_insts = 0, tab_insts = 0;
   struct Wave {
     uint32_t first_item, n_items, n_chunks, n_buckets;
@@ -1472,6 +1473,16 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         hp.h.shared = 2;  // error scan only
         hplans.push_back(hp);
         continue;
+      }
+      if (o.prefilter && ia != ib && P.tabs[ia].on && P.tabs[ib].on) {
+        // exact pre-filter: the two accesses' address ranges over the whole
+        // launch box (term-table bounds) do not meet, so no pair conflicts
+        const auto& ra = P.arange[ia];
+        const auto& rb = P.arange[ib];
+        if (ra.second < rb.first || rb.second < ra.first) {
+          ++plan->prefiltered;
+          continue;
+        }
       }
       const AccInst& R0 = P.dev_insts[ia];
       const uint64_t na = npts_of(ia), nb = q.qd.self ? 0 : npts_of(ib);
@@ -1786,6 +1797,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   rd_stats& S = ctx->stats;
   memset(&S, 0, sizeof S);
   S.evals = plan->evals;
+  S.prefiltered = plan->prefiltered;
   S.small_items = plan->n_sitems;
   int merr = 0;
   auto D = [&](const char* name) { return plan->dev[name].p; };

@@ -240,3 +240,15 @@ def test_mixed_config_small(hg):
     wl = configs.mixed(seed=5005, n_queries=160, log2_max=16)
     got = run_both(hg, wl, "mixed small")
     assert any(r["verdict"] for r in got)
+
+
+def test_prefilter_is_exact(hg):
+    """The interval pre-filter decides (pair, tuple) units whose address
+    ranges cannot meet; every field stays equal to the oracle's."""
+    for name, wl in (("batched pre", configs.batched(seed=94, n_models=16, scale=0.05,
+                                                      max_iters=8)),
+                     ("mixed pre", configs.mixed(seed=95, n_queries=96, log2_max=15)),
+                     ("rand pre", rand_workload(7))):
+        run_both(hg, wl, name, prefilter=1)
+    st = hg.default_context().stats()
+    say("prefiltered", st["prefiltered"])
