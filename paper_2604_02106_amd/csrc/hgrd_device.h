@@ -407,12 +407,22 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
   if (mask & 4) used |= 0x30;
   if (used == 0 || n == 0) return;
   const int f = l0ext ? 99 : __ffs(used) - 1;  // filter level (none: 99)
+  // a level whose groups equal the previous level's (constant, equal
+  // interval ids) is not recomputed: its sums and counts are the previous
+  // level's
+  const bool same2 = (qd.flags & 1) && ((used >> 1) & 1) && ((used >> 2) & 1);
+  const bool same4 = (qd.flags & 2) && ((used >> 3) & 1) && ((used >> 4) & 1);
   u64 Sl[6] = {0, 0, 0, 0, 0, 0};
   if (!l0ext)
     for (uint32_t r = tid; r < n; r += nt) S.part[r] = 0;
   bool any = true;
   for (int L = 0; L < 6; ++L) {
     if (!((used >> L) & 1)) continue;
+    if ((L == 2 && same2) || (L == 4 && same4)) {
+      Sl[L] = Sl[L - 1];
+      continue;
+    }
+    const bool twin = (L == 1 && same2) || (L == 3 && same4);
     for (uint32_t k = tid; k < TBL; k += nt) {
       S.owner[k] = kEmpty;
       S.cnt[k] = 0;
@@ -453,10 +463,9 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
         any_local = true;
       }
       if (!self && (tl & kSide)) continue;
-      if (cls & mask) {
-        int32_t nj = (int32_t)(self ? (c & 0xFFFF) : (c >> 16));
-        S.part[r] += sign * nj;
-      }
+      const int32_t nj = (int32_t)(self ? (c & 0xFFFF) : (c >> 16));
+      if (cls & mask) S.part[r] += sign * nj;
+      if (twin && ((cls << 1) & mask)) S.part[r] -= sign * nj;  // level L + 1
     }
     Sl[L] = s;
     if (L == f) {

@@ -1419,6 +1419,30 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       q.inst[s] = {ia.idx, ib_idx};
     }
     q.work = !(q.host_err & (ERR_INVAL | ERR_UNSUP));
+    // interval ids constant and equal on both sides in every tuple
+    {
+      // component c (0 bint, 1 wint) of instance x is a known constant
+      auto iv_const = [&](int32_t x, int c, uint32_t& v) -> bool {
+        const TabHost& T = P.tabs[x];
+        if (T.on && T.iv_off == kNoTab) {
+          v = c ? (T.iv_const >> 16) : (T.iv_const & 0xFFFF);
+          return true;
+        }
+        const Prog& pg = c ? P.dev_insts[x].wint : P.dev_insts[x].bint;
+        v = 0;
+        return pg.absent != 0;
+      };
+      uint32_t fl = 3;
+      for (const auto& pr2 : q.inst) {
+        if (pr2.first < 0 || pr2.second < 0) continue;
+        for (int c = 0; c < 2; ++c) {
+          uint32_t va = 0, vb = 0;
+          if (!iv_const(pr2.first, c, va) || !iv_const(pr2.second, c, vb) || va != vb)
+            fl &= ~(1u << c);
+        }
+      }
+      q.qd.flags = fl;
+    }
   }
 
   // ---- items ----------------------------------------------------------------

@@ -98,6 +98,10 @@ struct QDesc {
   uint32_t self;     // access a == access b
   uint32_t warp;     // warp size of the analysed program
   uint32_t shared;   // shared-memory array
+  uint32_t flags;    // bit 0: both accesses have one and the same block-
+                     // barrier interval id in every tuple (the block level
+                     // groups equal the (address, block) groups); bit 1: the
+                     // same for the warp-barrier id
 };
 
 struct QAcc {
