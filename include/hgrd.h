@@ -177,7 +177,7 @@ typedef struct {
                           meet without enumerating them (exact); 0: off */
   uint32_t log_level;  /* 0 silent, 1 summary, 2 per-launch (stderr) */
   uint32_t lds_cap;    /* records per LDS join tile (1024, 1536 or 3072);
-                          0 = the context's default (1536 until
+                          0 = the context's default (1024 until
                           rd_autotune picks one) */
   uint32_t tile_budget;/* VERDICT: tiles searched per (pair, tuple) before
                           the exact path; 0 = 256 */

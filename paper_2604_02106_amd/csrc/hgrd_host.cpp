@@ -415,7 +415,7 @@ struct rd_context {
   int device = 0;
   std::map<std::string, DevBuf> bufs;
   rd_stats stats;
-  int cfg = 1;
+  int cfg = 0;  // LDS tile shape: 1024 records, 2048 slots (rd_autotune may change it)
   uint32_t n_cu = 256;
   uint64_t wave_bytes = kWaveBytes;  // default partition wave size
   hipStream_t stream = nullptr;  // used when the caller passes no stream
@@ -1273,6 +1273,7 @@ struct rd_plan_impl {
     uint32_t first_item, n_items, n_chunks, n_buckets;
     uint32_t n_tab_chunks;  // the first n_tab_chunks chunks have term tables
     uint32_t n_runs;        // bucket runs (one join workgroup each)
+    uint32_t n_tab_runs;    // the first n_tab_runs runs are of items with tables
     uint64_t key_bytes;
     uint64_t hitem_off, chunk_off, bitem_off;  // element offsets in the plan pools
   };
@@ -1689,14 +1690,16 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       ++end;
     }
     std::vector<Chunk> interp;  // chunks of instances without tables go last
+    std::vector<BRun> interp_runs;  // so do runs of items without tables
     for (size_t i = pos; i < end; ++i) {
       const HItem& h = hplans[i].h;
       uint32_t li = (uint32_t)plan->hitems.size();  // global item index
       plan->hitems.push_back(h);
       plan->hR.push_back(hplans[i].R);
+      std::vector<BRun>& rdst =
+          P.tabs[h.inst_i].on && P.tabs[h.inst_j].on ? all_runs : interp_runs;
       for (uint32_t b = 0; b < h.nbuckets; b += plan->run_buckets)
-        all_runs.push_back({li, b,
-                            std::min(h.nbuckets, b + plan->run_buckets), 0});
+        rdst.push_back({li, b, std::min(h.nbuckets, b + plan->run_buckets), 0});
       const QPlan& q = Q[h.q];
       for (int side = 0; side < (q.qd.self || h.shared == 2 ? 1 : 2); ++side) {
         uint32_t inst = side ? h.inst_j : h.inst_i;
@@ -1708,6 +1711,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     }
     W.n_tab_chunks = (uint32_t)(all_chunks.size() - W.chunk_off);
     all_chunks.insert(all_chunks.end(), interp.begin(), interp.end());
+    W.n_tab_runs = (uint32_t)(all_runs.size() - W.bitem_off);
+    all_runs.insert(all_runs.end(), interp_runs.begin(), interp_runs.end());
     W.n_items = (uint32_t)(end - pos);
     W.n_runs = (uint32_t)(all_runs.size() - W.bitem_off);
     W.n_chunks = (uint32_t)(all_chunks.size() - W.chunk_off);
@@ -1905,7 +1910,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
         return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(e2, st));
       if (W.n_runs &&
-          launch_bucket(wcfg, st, W.n_runs, d_bit + W.bitem_off, d_hit,
+          launch_bucket(wcfg, st, W.n_runs, d_bit + W.bitem_off, W.n_tab_runs, d_hit,
                         d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs,
                         d_cursor, d_ovf, d_done, l0k, l0c))
         return RD_EDEVICE;
@@ -2073,6 +2078,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     std::vector<BRun> bitem;
     std::vector<HItem> hs;
     std::vector<Chunk> interp;
+    std::vector<BRun> interp_runs;
     uint64_t max_bytes = 0, max_nbk = 0;
     size_t pos = 0;
     while (pos < items.size()) {
@@ -2093,8 +2099,10 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
         nbk += h.nbuckets;
         uint32_t li = (uint32_t)hs.size();
         hs.push_back(h);
+        std::vector<BRun>& rdst =
+            plan->tab_on[h.inst_i] && plan->tab_on[h.inst_j] ? bitem : interp_runs;
         for (uint32_t b = 0; b < h.nbuckets; b += plan->run_buckets)
-          bitem.push_back({li, b, std::min(h.nbuckets, b + plan->run_buckets), 0});
+          rdst.push_back({li, b, std::min(h.nbuckets, b + plan->run_buckets), 0});
         const QPlan& q = plan->Q[h.q];
         for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
           const uint32_t inst = side ? h.inst_j : h.inst_i;
@@ -2108,6 +2116,9 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       W.n_tab_chunks = (uint32_t)(chunks.size() - W.chunk_off);
       chunks.insert(chunks.end(), interp.begin(), interp.end());
       interp.clear();
+      W.n_tab_runs = (uint32_t)(bitem.size() - W.bitem_off);
+      bitem.insert(bitem.end(), interp_runs.begin(), interp_runs.end());
+      interp_runs.clear();
       W.n_items = (uint32_t)(end - pos);
       W.n_runs = (uint32_t)(bitem.size() - W.bitem_off);
       W.n_chunks = (uint32_t)(chunks.size() - W.chunk_off);

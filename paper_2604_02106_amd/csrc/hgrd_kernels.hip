@@ -465,11 +465,12 @@ __global__ void k_apply_s0(uint32_t n, const L0Item* __restrict__ items,
 
 constexpr uint32_t kJoinThreads = 512;  // bucket-join workgroup size
 
-// One workgroup joins a run of buckets of one item.  The item's header,
-// query and both access instances are loaded once per run (the instances
-// into LDS); the next bucket's records are loaded into registers while the
-// current one is joined, and the counts are committed once per run.
-template <int CAP, int TBL>
+// One workgroup joins a run of buckets of one item.  The item's header
+// and query are loaded once per run; the next bucket's records are loaded
+// into registers while the current one is joined, and the counts are
+// committed once per run.  TAB: both instances of every item of the launch
+// have term tables (interval ids by lookup, no interpreter code).
+template <int CAP, int TBL, bool TAB>
 __global__ void __launch_bounds__(kJoinThreads)
 k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
               const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
@@ -561,7 +562,14 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
           if ((pid >> 31) != side) continue;
           const PointIds id = decode(I, pid & 0x7FFFFFFFu);
           uint32_t bi, wi;
-          point_iv(I, id, code, params, loopvals, bi, wi);
+          if (TAB) {
+            const uint32_t iv = I.iv_off != kNoTab ? (uint32_t)I.tpool[I.iv_off + id.ilin]
+                                                   : I.iv_const;
+            bi = iv & 0xFFFF;
+            wi = iv >> 16;
+          } else {
+            point_iv(I, id, code, params, loopvals, bi, wi);
+          }
           S.addr[r] = (u64)a;
           S.blin[r] = id.blin;
           S.tli[r] = (id.ilin << 16) | (side << 15) | id.tlin;
@@ -994,25 +1002,34 @@ static int set_lds_attrs() {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   HGRD_CHECK(hipFuncSetAttribute((const void*)k_small_persist<CAP, TBL>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-  HGRD_CHECK(hipFuncSetAttribute((const void*)k_bucket_join<CAP, TBL>,
+  HGRD_CHECK(hipFuncSetAttribute((const void*)k_bucket_join<CAP, TBL, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  HGRD_CHECK(hipFuncSetAttribute((const void*)k_bucket_join<CAP, TBL, false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   return 0;
 }
 
 template <int CAP, int TBL>
 static int launch_bucket_t(hipStream_t st, uint32_t nruns, const BRun* runs,
-                           const HItem* hitems, const DevInst* insts,
+                           uint32_t n_tab, const HItem* hitems, const DevInst* insts,
                            const DInsn* code, const int64_t* params,
                            const int64_t* loopvals, const QDesc* qd, QAcc* acc,
                            const unsigned char* recs, const uint32_t* cursor,
                            const uint32_t* ovf, const uint32_t* done,
                            const u64* l0keys, const u64* l0cnt) {
+  // runs [0, n_tab) are of items whose instances have term tables
   size_t lds = sizeof(JoinLds<CAP, TBL>);
   for (uint32_t off = 0; off < nruns; off += 1u << 20) {
     uint32_t m = nruns - off < (1u << 20) ? nruns - off : (1u << 20);
-    hipLaunchKernelGGL((k_bucket_join<CAP, TBL>), dim3(m), dim3(kJoinThreads), lds, st,
-                       runs + off, hitems, insts, code, params, loopvals, qd, acc,
-                       recs, cursor, ovf, done, l0keys, l0cnt);
+    uint32_t mt = off >= n_tab ? 0 : (n_tab - off < m ? n_tab - off : m);
+    if (mt)
+      hipLaunchKernelGGL((k_bucket_join<CAP, TBL, true>), dim3(mt), dim3(kJoinThreads), lds,
+                         st, runs + off, hitems, insts, code, params, loopvals, qd, acc,
+                         recs, cursor, ovf, done, l0keys, l0cnt);
+    if (m > mt)
+      hipLaunchKernelGGL((k_bucket_join<CAP, TBL, false>), dim3(m - mt), dim3(kJoinThreads),
+                         lds, st, runs + off + mt, hitems, insts, code, params, loopvals,
+                         qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -1126,16 +1143,16 @@ int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n, bool tab,
 }
 
 int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
-                  const HItem* hitems, const void* insts, const DInsn* code,
-                  const int64_t* params, const int64_t* loopvals, const QDesc* qd,
-                  QAcc* acc, const unsigned char* recs, const uint32_t* cursor,
-                  const uint32_t* ovf, const uint32_t* done, const u64* l0keys,
-                  const u64* l0cnt) {
+                  uint32_t n_tab, const HItem* hitems, const void* insts,
+                  const DInsn* code, const int64_t* params, const int64_t* loopvals,
+                  const QDesc* qd, QAcc* acc, const unsigned char* recs,
+                  const uint32_t* cursor, const uint32_t* ovf, const uint32_t* done,
+                  const u64* l0keys, const u64* l0cnt) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
-    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
-    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
+    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
+    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
+    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
   }
 }
 

@@ -43,10 +43,10 @@ int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n, bool tab,
                    uint32_t* ovf, uint32_t capb, const uint32_t* done,
                    unsigned long long* nbytes);
 int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
-                  const HItem* hitems, const void* insts, const DInsn* code,
-                  const int64_t* params, const int64_t* loopvals, const QDesc* qd,
-                  QAcc* acc, const unsigned char* recs, const uint32_t* cursor,
-                  const uint32_t* ovf, const uint32_t* done,
+                  uint32_t n_tab, const HItem* hitems, const void* insts,
+                  const DInsn* code, const int64_t* params, const int64_t* loopvals,
+                  const QDesc* qd, QAcc* acc, const unsigned char* recs,
+                  const uint32_t* cursor, const uint32_t* ovf, const uint32_t* done,
                   const unsigned long long* l0keys, const unsigned long long* l0cnt);
 int launch_level0(hipStream_t st, const Chunk* chunks, uint32_t n,
                   const L0Item* items, const void* insts, const DInsn* code,
