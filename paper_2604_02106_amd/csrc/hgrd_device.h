@@ -569,7 +569,7 @@ __device__ __forceinline__ void lds_append(JoinLds<CAP, TBL>& S, bool valid,
   uint32_t leader = __ffsll((long long)bal) - 1;
   uint32_t base = 0;
   if (lane == leader) base = atomicAdd(&S.n, (uint32_t)__popcll(bal));
-  base = __shfl(base, leader, 64);
+  base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
   if (valid) {
     uint32_t r = base + __popcll(bal & ((1ull << lane) - 1));
     if (r >= CAP) {  // the planner never lets this happen; never write past

@@ -262,7 +262,7 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
         // at most 8 groups per wave this way; any rest claims per lane
         for (int it = 0; act && it < 8; ++it) {
           const uint32_t leader = (uint32_t)__ffsll((long long)act) - 1;
-          const uint32_t bl = __shfl(b, leader, 64);
+          const uint32_t bl = (uint32_t)__builtin_amdgcn_readlane((int)b, (int)leader);
           const u64 grp = __ballot(v && b == bl) & act;
           uint32_t s = 0, base = 0;
           if (lane == leader) {
@@ -275,8 +275,8 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
             }
             base = atomicAdd(&scnt[s], (uint32_t)__popcll(grp));
           }
-          s = __shfl(s, leader, 64);
-          base = __shfl(base, leader, 64);
+          s = (uint32_t)__builtin_amdgcn_readlane((int)s, (int)leader);
+          base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
           if ((grp >> lane) & 1) {
             sl[j] = s;
             rk[j] = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1));
@@ -644,7 +644,7 @@ k_gen_linear(const Chunk* __restrict__ chunks, const FItem* __restrict__ fitems,
     uint32_t leader = __ffsll((long long)bal) - 1;
     uint32_t b0 = 0;
     if (lane == leader) b0 = atomicAdd(&count[ch.item], (uint32_t)__popcll(bal));
-    b0 = __shfl(b0, leader, 64);
+    b0 = (uint32_t)__builtin_amdgcn_readlane((int)b0, (int)leader);
     if (valid) {
       uint32_t k = b0 + __popcll(bal & ((1ull << lane) - 1));
       if (k < f.cap) {
