@@ -245,26 +245,14 @@ __device__ __forceinline__ bool eval_point(const DevInst& I,
 // Table lookups only (the instance has term tables).
 __device__ __forceinline__ bool point_tab(const DevInst& I, const PointIds& id,
                                           Point& pt) {
-  if (I.tnever) return false;
-  int64_t a = I.tu;
-  if (I.toff[0] != kNoTab) {
-    const int64_t v = I.tpool[I.toff[0] + id.blin];
-    if (v == INT64_MIN) return false;
-    a += v;
-  }
-  if (I.toff[1] != kNoTab) {
-    const int64_t v = I.tpool[I.toff[1] + id.tlin];
-    if (v == INT64_MIN) return false;
-    a += v;
-  }
-  if (I.toff[2] != kNoTab) {
-    const int64_t v = I.tpool[I.toff[2] + id.ilin];
-    if (v == INT64_MIN) return false;
-    a += v;
-  }
+  // all lookups issued before any is tested: one memory round trip
+  const int64_t v0 = I.toff[0] != kNoTab ? I.tpool[I.toff[0] + id.blin] : 0;
+  const int64_t v1 = I.toff[1] != kNoTab ? I.tpool[I.toff[1] + id.tlin] : 0;
+  const int64_t v2 = I.toff[2] != kNoTab ? I.tpool[I.toff[2] + id.ilin] : 0;
   const uint32_t iv =
       I.iv_off != kNoTab ? (uint32_t)I.tpool[I.iv_off + id.ilin] : I.iv_const;
-  pt.addr = a;
+  if (I.tnever || v0 == INT64_MIN || v1 == INT64_MIN || v2 == INT64_MIN) return false;
+  pt.addr = I.tu + v0 + v1 + v2;
   pt.bint = iv & 0xFFFF;
   pt.wint = iv >> 16;
   return true;
