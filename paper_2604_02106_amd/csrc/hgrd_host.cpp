@@ -46,7 +46,7 @@ constexpr uint32_t kChunkPts = 1024;
 constexpr uint64_t kWaveBytes = 1536ull << 20;  // bucket bytes per partition wave
 constexpr uint64_t kFallbackRecords = 256ull << 20;
 constexpr uint64_t kMaxTabInst = 1ull << 24;  // table entries per instance
-constexpr uint64_t kMaxTabPool = 1ull << 28;  // table entries per plan
+constexpr uint64_t kMaxTabPool = 1ull << 31;  // table entries per plan (16 GiB)
 
 // ---------------------------------------------------------------------------
 // checked int64 arithmetic on the host (errors yield 0, evaluation goes on)
@@ -758,14 +758,14 @@ struct TermBuilder {
             xs.push_back(&t);
             xlo += contrib_lo(t);
           } else {
-            if (yg >= 0 && yg != t.group) return false;
+            if (yg >= 0 && yg != t.group) return split_small_rest(n, in, L, mu, d);
             yg = t.group;
             ys.push_back(&t);
             ylo += contrib_lo(t);
             yhi += contrib_hi(t);
           }
         }
-        if (xlo < 0 || ylo < 0) return false;
+        if (xlo < 0 || ylo < 0) return split_small_rest(n, in, L, mu, d);
         i128 yabs = i128abs(in.u);
         for (const STerm* t : ys) yabs += contrib_abs(*t);
         if (yabs > kI64Hi) return false;
@@ -804,6 +804,53 @@ struct TermBuilder {
       default:
         return false;
     }
+  }
+
+  // Second way to split X + Y by a positive d: X (the uniform part and the
+  // terms of one group) is a multiple of some g with g | d and X >= 0, and
+  // Y (the terms of one other group) lies in [0, g).  Then no multiple of d
+  // falls inside (X, X + Y], so (X + Y) / d = X / d and (X + Y) % d =
+  // X % d + Y.
+  bool split_small_rest(const TNode& n, const Lin& in, Lin& L, i128 mu, int64_t d) {
+    for (int gy = 0; gy < 3; ++gy) {
+      std::vector<const STerm*> xs, ys;
+      int gx = -1;
+      bool ok = true;
+      i128 xlo = in.u, ylo = 0, yhi = 0, xabs = i128abs(in.u);
+      uint64_t g = uabs64((int64_t)in.u);
+      for (const STerm& t : in.terms) {
+        if (t.group == gy) {
+          ys.push_back(&t);
+          ylo += contrib_lo(t);
+          yhi += contrib_hi(t);
+        } else {
+          if (gx >= 0 && gx != t.group) { ok = false; break; }
+          gx = t.group;
+          xs.push_back(&t);
+          xlo += contrib_lo(t);
+          xabs += contrib_abs(t);
+          g = gcd64(g, gmul(t.g, uabs64(t.mult)));
+        }
+      }
+      if (!ok || ys.empty() || xs.empty() || xabs > kI64Hi) continue;
+      if (g == 0 || (uint64_t)d % g != 0 || xlo < 0 || ylo < 0 || yhi >= (i128)g) continue;
+      // X / d or X % d as one term of group gx
+      std::vector<rd_insn> code;
+      emit_sum(xs, in.u, code);
+      code.push_back(mk_insn(RD_OP_CONST, d));
+      code.push_back(mk_insn(n.op));
+      i128 xhi = in.u;
+      for (const STerm* t : xs) xhi += contrib_hi(*t);
+      if (n.op == RD_OP_DIV) return add_term(L, std::move(code), xlo / d, xhi / d, gx, mu);
+      if (!add_term(L, std::move(code), 0, std::min(xhi, (i128)d - 1), gx, mu)) return false;
+      for (const STerm* t : ys) {
+        std::vector<rd_insn> c2 = t->code;
+        if (!add_term(L, std::move(c2), t->lo, t->hi, t->group, mu * (i128)t->mult, t->g))
+          return false;
+      }
+      return true;
+    }
+    return false;
   }
 
   // Guard as a conjunction of single-group (or uniform) conjuncts.

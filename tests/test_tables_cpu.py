@@ -58,3 +58,30 @@ def test_stress_and_sparse_sampled():
 def test_mixed_models():
     st = sweep(configs.mixed(seed=5005, n_queries=96, log2_max=16), max_points=1 << 14)
     assert st[0] >= 0.8 * (st[0] + st[1]), st
+
+
+def test_division_splits():
+    """Truncating divisions and remainders of sums that mix groups: every
+    form below must qualify for tables (status 0) and agree with the
+    interpreter at every box point."""
+    from workloads import (Access, Array, Launch, Loop, Model, Workload, GLOBAL,
+                           WRITE, tid, bid, loop, c, param)
+    gid8 = bid(0) * 8 + tid(0)          # block of 8: 8 * bid is a multiple of 8
+    gid96 = (bid(0) + bid(1) * 3) * 96 + tid(0)
+    exprs = [gid8 // 32, gid8 % 32, gid8 // 4, gid8 % 8,       # small-rest rule
+             gid96 // 32, gid96 % 32,                            # divisor rule
+             (bid(0) * 64 + tid(0) * 8 + loop(0)) // 8,          # two groups, rest
+             (loop(0) * 16 + tid(0)) // 16 + param(0),
+             (bid(0) * 64 + tid(0) * 2 + loop(0)) // 8]          # rest of two groups
+    accs = [Access(0, WRITE, e, None, [0]) for e in exprs]
+    m = Model(1, [Array(GLOBAL, 32)], accs, Launch((6, 2, 1), (8, 1, 1), 32),
+              [[3], [7]], loops=[Loop(0, "lt", 4)])
+    wl = Workload([m], [(0, k, k, 7) for k in range(len(accs))])
+    pk = hg.Packed(wl)
+    for a in range(len(accs)):
+        for s in range(2):
+            st, n = hg.table_selftest(wl, 0, a, s, packed=pk)
+            if a == len(accs) - 1:
+                assert st == 1  # no split: the interpreter keeps it
+                continue
+            assert st == 0 and n == 6 * 2 * 8 * 4, (a, s, st, n)
