@@ -226,6 +226,7 @@ def main():
     os.environ["HGRD_TIMING"] = "1"
     plan.execute(raw=True)  # untimed: first eager pass
     torch.cuda.synchronize()
+    log("eager pass done")
     stats = []
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -243,9 +244,11 @@ def main():
     pres = pplan.execute()
     assert pres == res
     torch.cuda.synchronize()
+    log("pre-filtered plan checked")
     t0 = time.perf_counter()
     for i in range(args.steps):
         pplan.execute(raw=True)
+        log("pre-filtered step %d done" % i)
     torch.cuda.synchronize()
     dt_pre = time.perf_counter() - t0
     pre_units = ctx.stats()["prefiltered"]
@@ -255,6 +258,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         plan.execute(raw=True)
+        log("graph step %d done" % i)
     torch.cuda.synchronize()
     dt_graph = time.perf_counter() - t0
     log("timed %d steps in %.3f s (graph replay %.3f s)" % (args.steps, dt, dt_graph))

@@ -46,7 +46,9 @@ constexpr uint32_t kChunkPts = 1024;
 constexpr uint64_t kWaveBytes = 1536ull << 20;  // bucket bytes per partition wave
 constexpr uint64_t kFallbackRecords = 256ull << 20;
 constexpr uint64_t kMaxTabInst = 1ull << 24;  // table entries per instance
-constexpr uint64_t kMaxTabPool = 1ull << 31;  // table entries per plan (16 GiB)
+constexpr uint64_t kMaxTabPool = 1ull << 33;  // table entries per plan (64 GiB)
+constexpr uint64_t kL0Slots = 1ull << 29;     // address-count slots per split batch
+constexpr uint64_t kRetryBytes = 16ull << 30;  // bucket bytes of one retried item
 
 // ---------------------------------------------------------------------------
 // checked int64 arithmetic on the host (errors yield 0, evaluation goes on)
@@ -431,6 +433,9 @@ struct rd_context {
       if (hipMalloc(&b.p, want) != hipSuccess) {
         b.cap = 0;
         if (hipMalloc(&b.p, bytes) != hipSuccess) {
+          (void)hipGetLastError();
+          fprintf(stderr, "hgrd: device allocation of %zu bytes for '%s' failed\n", bytes,
+                  name);
           b.p = nullptr;
           *err = RD_ENOMEM;
           return nullptr;
@@ -1027,10 +1032,12 @@ struct Planner {
       }
     }
     if (entries > kMaxTabInst || tpool + entries > kMaxTabPool) return;
+    T.base = tpool;
     for (TabJob& J : jobs) {
-      J.out_off = (uint32_t)tpool;
-      if (J.group < 3) T.off[J.group] = J.out_off;
-      else T.iv_off = J.out_off;
+      J.out_off = tpool;
+      const uint32_t rel = (uint32_t)(tpool - T.base);
+      if (J.group < 3) T.off[J.group] = rel;
+      else T.iv_off = rel;
       tpool += J.n;
       tjobs.push_back(J);
     }
@@ -1348,6 +1355,8 @@ struct rd_plan_impl {
       b.p = nullptr;
       b.cap = 0;
       if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        fprintf(stderr, "hgrd: device allocation of %zu bytes for '%s' failed\n", bytes, name);
         b.p = nullptr;
         *err = RD_ENOMEM;
         return nullptr;
@@ -2212,6 +2221,14 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     }
     uint64_t need_f = (ovf[i] * 10ull + cap * 6 - 1) / (cap * 6);
     need_f = std::min<uint64_t>(std::max<uint64_t>(need_f, 2), 64);
+    // at most kRetryBytes of buckets per retried item; else split it
+    const uint64_t rs = r.h.is32 ? 8 : 16;
+    while (need_f > 2 && (uint64_t)r.h.nbuckets * need_f * cap * rs > kRetryBytes) need_f /= 2;
+    if ((uint64_t)r.h.nbuckets * need_f * cap * rs > kRetryBytes ||
+        (uint64_t)r.h.nbuckets * need_f >= (1ull << 31)) {
+      still.push_back(r);
+      continue;
+    }
     r.h.nbuckets = (uint32_t)((uint64_t)r.h.nbuckets * need_f);
     r.h.mode = 0;
     rit.push_back(r);
@@ -2227,11 +2244,21 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       if (rovf[i]) still.push_back(rit[i]);
   }
 
-  // round 2: split global items by (address, block); level 0 in tables
-  std::vector<RItem> split, direct;
-  for (auto& r : still) (r.h.shared == 0 ? split : direct).push_back(r);
-  S.split_items = split.size();
-  if (!split.empty()) {
+  // round 2: split global items by (address, block); level 0 in tables,
+  // in batches whose address-count tables stay within kL0Slots
+  std::vector<RItem> split_all, direct;
+  for (auto& r : still) (r.h.shared == 0 ? split_all : direct).push_back(r);
+  S.split_items = split_all.size();
+  for (size_t sp0 = 0; sp0 < split_all.size();) {
+    std::vector<RItem> split;
+    uint64_t bslots = 0;
+    while (sp0 < split_all.size()) {
+      uint64_t t = 1;
+      while (t < 2 * split_all[sp0].R) t <<= 1;
+      if (!split.empty() && bslots + t + 1 > kL0Slots) break;
+      bslots += t + 1;
+      split.push_back(split_all[sp0++]);
+    }
     const int scfg = 1;  // first pass; its overflows get join_cap(2) tiles
     const uint32_t scap = (uint32_t)join_cap(scfg);
     std::vector<L0Item> l0;
@@ -2316,7 +2343,9 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       for (size_t k = 0; k < at2.size(); ++k) rovf[at2[k]] = rovf2[k];
     }
     // an overflowed split item joined none of its buckets; its S_0 is not
-    // applied and the fallback counts the whole item
+    // applied and the fallback counts the whole item (the stream has
+    // drained, so the previous batch's copy of `skip` is done)
+    skip.clear();
     for (size_t i = 0; i < split.size(); ++i) {
       if (plan->Q[split[i].h.q].qd.mask & 1) skip.push_back(rovf[i] ? 1u : 0u);
       if (!rovf[i]) continue;
@@ -2807,13 +2836,13 @@ int rd_table_selftest(const rd_kernel_model* models, uint32_t n_models,
     const uint32_t gi[3] = {blin, tlin, ilin};
     for (int g = 0; g < 3 && g1; ++g) {
       if (T.off[g] == kNoTab) continue;
-      const int64_t v = pool[T.off[g] + gi[g]];
+      const int64_t v = pool[T.base + T.off[g] + gi[g]];
       if (v == INT64_MIN) g1 = false;
       else a1 += v;
     }
     if (g0 != g1) return -4;
     if (g0) {
-      const uint32_t iv = T.iv_off != kNoTab ? (uint32_t)pool[T.iv_off + ilin] : T.iv_const;
+      const uint32_t iv = T.iv_off != kNoTab ? (uint32_t)pool[T.base + T.iv_off + ilin] : T.iv_const;
       if (a0 != a1) return -5;
       if ((uint32_t)b0 != (iv & 0xFFFF) || (uint32_t)w0 != (iv >> 16)) return -6;
     }

@@ -77,7 +77,8 @@ static_assert(sizeof(AccInst) == 128, "AccInst layout");
 constexpr uint32_t kNoTab = 0xFFFFFFFFu;
 struct TabHost {
   int64_t u;
-  uint32_t off[3];    // entry offsets in the table pool per group, kNoTab = none
+  unsigned long long base;  // first pool entry of this instance's tables
+  uint32_t off[3];    // entry offsets from base per group, kNoTab = none
   uint32_t iv_off;    // kNoTab: iv_const for every iteration
   uint32_t iv_const;
   uint32_t never;     // a uniform guard conjunct is false
@@ -87,10 +88,11 @@ struct TabHost {
 // One table to fill: entries [0, n) of group `group` (0 blocks, 1 threads,
 // 2 iterations, 3 packed interval ids over iterations) of instance `inst`.
 struct TabJob {
-  uint32_t inst, group, out_off, n;
+  uint32_t inst, group, n, pad;
+  unsigned long long out_off;  // first pool entry written
   Prog val, guard;  // value and guard-conjunct programs of the group
 };
-static_assert(sizeof(TabJob) == 32, "TabJob layout");
+static_assert(sizeof(TabJob) == 40, "TabJob layout");
 
 // Per-query description and accumulators.
 struct QDesc {

@@ -1045,7 +1045,7 @@ size_t devinst_size() { return sizeof(DevInst); }
 void set_devinst_tab(void* dst, const TabHost& t, const int64_t* pool) {
   DevInst d;
   memcpy(&d, dst, sizeof d);
-  d.tpool = pool;
+  d.tpool = pool + t.base;
   d.tu = t.u;
   for (int g = 0; g < 3; ++g) d.toff[g] = t.off[g];
   d.iv_off = t.iv_off;
