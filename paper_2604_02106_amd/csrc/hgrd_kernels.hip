@@ -233,67 +233,82 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
     __syncthreads();
     int64_t ad[kPer];
     uint32_t pv[kPer], sl[kPer], rk[kPer], bk[kPer];
+    if constexpr (TAB) {
+      // every table lookup of the tile's points in flight before any is
+      // used: one memory round trip per tile instead of one per point
+      int64_t v0[kPer], v1[kPer], v2[kPer];
+      uint32_t bl[kPer];
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      sl[j] = kScatterSlots;
-      bk[j] = 0xFFFFFFFFu;  // no record
-      const uint32_t pidx = t0 + (uint32_t)j * kScatterThreads + threadIdx.x;
-      if (pidx >= ch.p1) continue;
-      const PointIds id = decode(I, pidx);
-      Point pt;
-      const bool ok = TAB ? point_tab(I, id, pt)
-                          : point_eval(I, id, code, params, loopvals, pt, err);
-      if (!ok || !store) continue;
-      const uint32_t b = bucket_of(h, pt.addr, id.blin);
-      ad[j] = pt.addr;
-      pv[j] = (ch.side << 31) | pidx;
-      bk[j] = b;
+      for (int j = 0; j < kPer; ++j) {
+        const uint32_t pidx = t0 + (uint32_t)j * kScatterThreads + threadIdx.x;
+        const PointIds id = decode(I, pidx < ch.p1 ? pidx : ch.p0);
+        bl[j] = id.blin;
+        v0[j] = I.toff[0] != kNoTab ? I.tpool[I.toff[0] + id.blin] : 0;
+        v1[j] = I.toff[1] != kNoTab ? I.tpool[I.toff[1] + id.tlin] : 0;
+        v2[j] = I.toff[2] != kNoTab ? I.tpool[I.toff[2] + id.ilin] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const uint32_t pidx = t0 + (uint32_t)j * kScatterThreads + threadIdx.x;
+        sl[j] = kScatterSlots;
+        bk[j] = 0xFFFFFFFFu;
+        const bool ok = store && pidx < ch.p1 && !I.tnever && v0[j] != INT64_MIN &&
+                        v1[j] != INT64_MIN && v2[j] != INT64_MIN;
+        ad[j] = I.tu + v0[j] + v1[j] + v2[j];
+        pv[j] = (ch.side << 31) | pidx;
+        if (ok) bk[j] = bucket_of(h, ad[j], bl[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        sl[j] = kScatterSlots;
+        bk[j] = 0xFFFFFFFFu;  // no record
+        const uint32_t pidx = t0 + (uint32_t)j * kScatterThreads + threadIdx.x;
+        if (pidx >= ch.p1) continue;
+        const PointIds id = decode(I, pidx);
+        Point pt;
+        const bool ok = point_eval(I, id, code, params, loopvals, pt, err);
+        if (!ok || !store) continue;
+        ad[j] = pt.addr;
+        pv[j] = (ch.side << 31) | pidx;
+        bk[j] = bucket_of(h, pt.addr, id.blin);
+      }
     }
-    // claim LDS slots and ranks.  Dense-map items: the lanes of a wave that
-    // share a bucket (consecutive points) are grouped with ballots and one
-    // lane claims for the group; hashed items: one claim per lane.
+    // claim LDS slots and ranks by runs: the lanes of a wave that hold one
+    // bucket in a row (consecutive points of a dense-map item) form a run;
+    // the run's first lane claims the slot and the run's length at once,
+    // the others take slot and base from it and add their offset in the run
     const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-      const bool v = bk[j] != 0xFFFFFFFFu;
       const uint32_t b = bk[j];
-      u64 act = __ballot(v);
-      if (h.mode) {
-        // at most 8 groups per wave this way; any rest claims per lane
-        for (int it = 0; act && it < 8; ++it) {
-          const uint32_t leader = (uint32_t)__ffsll((long long)act) - 1;
-          const uint32_t bl = (uint32_t)__builtin_amdgcn_readlane((int)b, (int)leader);
-          const u64 grp = __ballot(v && b == bl) & act;
-          uint32_t s = 0, base = 0;
-          if (lane == leader) {
-            s = (bl * 0x9E3779B1u) >> 20;  // 12 bits: kScatterSlots
-            for (;;) {
-              const uint32_t k = atomicCAS(&skey[s], 0u, bl + 1);
-              if (k == 0) used[atomicAdd(&nused, 1u)] = (uint16_t)s;
-              if (k == 0 || k == bl + 1) break;
-              s = (s + 1) & (kScatterSlots - 1);
-            }
-            base = atomicAdd(&scnt[s], (uint32_t)__popcll(grp));
-          }
-          s = (uint32_t)__builtin_amdgcn_readlane((int)s, (int)leader);
-          base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
-          if ((grp >> lane) & 1) {
-            sl[j] = s;
-            rk[j] = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1));
-          }
-          act &= ~grp;
-        }
-      }
-      if ((act >> lane) & 1) {
-        uint32_t s = (b * 0x9E3779B1u) >> 20;
+      const bool v = b != 0xFFFFFFFFu;
+      const uint32_t bp = __shfl_up(b, 1, 64);
+      const bool head = v && (lane == 0 || bp != b);
+      const u64 H = __ballot(head);
+      const u64 V = __ballot(v);
+      if (!V) continue;
+      uint32_t s = 0, base = 0;
+      if (head) {
+        const u64 above = lane == 63 ? 0ull : (~0ull << (lane + 1));
+        const u64 stop = (H | ~V) & above;
+        const uint32_t end = stop ? (uint32_t)__ffsll((long long)stop) - 1 : 64u;
+        s = (b * 0x9E3779B1u) >> 20;  // 12 bits: kScatterSlots
         for (;;) {
           const uint32_t k = atomicCAS(&skey[s], 0u, b + 1);
           if (k == 0) used[atomicAdd(&nused, 1u)] = (uint16_t)s;
           if (k == 0 || k == b + 1) break;
           s = (s + 1) & (kScatterSlots - 1);
         }
-        sl[j] = s;
-        rk[j] = atomicAdd(&scnt[s], 1u);
+        base = atomicAdd(&scnt[s], end - lane);
+      }
+      const u64 upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+      const uint32_t hl = 63u - (uint32_t)__clzll((long long)(H & upto));
+      const uint32_t hs = (uint32_t)__shfl((int)s, (int)hl, 64);
+      const uint32_t hb = (uint32_t)__shfl((int)base, (int)hl, 64);
+      if (v) {
+        sl[j] = hs;
+        rk[j] = hb + lane - hl;
       }
     }
     __syncthreads();
