@@ -491,42 +491,53 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
   __syncthreads();
 }
 
-// Address-level pre-filter of S.n records holding only S.addr and the side
-// bit in S.tli: marks inactive every record whose address no record of the
-// other side (for a self pair: no other record) shares, since a conflict
-// needs equal addresses whatever the classes.  Hash table sized to the
-// records (a power of two >= 2n, at most TBL).  Returns, uniformly over
-// the block, whether any record is left.
+// Address-level pre-filter by signatures: a conflict needs equal addresses
+// whatever the classes, so a record whose address no record of the other
+// side (for a self pair: no other record) holds can take no part in the
+// join.  Each side sets two bits per record, chosen by two hashes of the
+// address, in a bitmap of 32 * TBL bits (S.owner for side a, S.cnt for
+// side b; for a self pair S.owner marks addresses seen once and S.cnt
+// seen twice).  A record stays active when the other bitmap has both its
+// bits: no record with a partner is ever dropped, and the few kept by
+// colliding hashes are dropped exactly at the join's first level.
+template <int TBL>
+__device__ __forceinline__ void sig_index(u64 a, uint32_t& i1, uint32_t& i2) {
+  constexpr uint32_t lgb = 5 + (TBL >= 8192 ? 13 : TBL >= 4096 ? 12 : 11);
+  static_assert(TBL == 2048 || TBL == 4096 || TBL == 8192, "signature bitmap size");
+  const uint32_t x = (uint32_t)a ^ ((uint32_t)(a >> 32) * 0x85EBCA6Bu);
+  i1 = (x * 0x9E3779B1u) >> (32 - lgb);
+  i2 = ((x ^ (x >> 15)) * 0xC2B2AE35u) >> (32 - lgb);
+}
+
 template <int CAP, int TBL>
-__device__ bool addr_prefilter(JoinLds<CAP, TBL>& S, uint32_t n, bool self) {
-  uint32_t lg = 6;
-  while ((1u << lg) < 2 * n) ++lg;
-  const uint32_t tsz = 1u << lg, tm = tsz - 1;
-  for (uint32_t k = threadIdx.x; k < tsz; k += blockDim.x) {
-    S.owner[k] = kEmpty;
-    S.cnt[k] = 0;
+__device__ __forceinline__ void sig_clear(JoinLds<CAP, TBL>& S) {
+  uint4* o = reinterpret_cast<uint4*>(S.owner);
+  uint4* c = reinterpret_cast<uint4*>(S.cnt);
+  for (uint32_t k = threadIdx.x; k < TBL / 4; k += blockDim.x) {
+    o[k] = make_uint4(0, 0, 0, 0);
+    c[k] = make_uint4(0, 0, 0, 0);
   }
-  __syncthreads();
-  for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
-    const u64 a = S.addr[r];
-    uint32_t h = (((uint32_t)a ^ (uint32_t)(a >> 32)) * 0x9E3779B1u) >> (32 - lg);
-    for (;;) {
-      const uint32_t o = atomicCAS(&S.owner[h], kEmpty, r);
-      if (o == kEmpty || S.addr[o] == a) break;
-      h = (h + 1) & tm;
-    }
-    atomicAdd(&S.cnt[h], (self || !(S.tli[r] & kSide)) ? 1u : 0x10000u);
-    S.slot[r] = (uint16_t)h;
+}
+
+template <int CAP, int TBL>
+__device__ __forceinline__ void sig_insert(JoinLds<CAP, TBL>& S, uint32_t i1,
+                                           uint32_t i2, bool side, bool self) {
+  const uint32_t m1 = 1u << (i1 & 31), m2 = 1u << (i2 & 31);
+  if (self) {
+    if (atomicOr(&S.owner[i1 >> 5], m1) & m1) atomicOr(&S.cnt[i1 >> 5], m1);
+    if (atomicOr(&S.owner[i2 >> 5], m2) & m2) atomicOr(&S.cnt[i2 >> 5], m2);
+  } else {
+    uint32_t* t = side ? S.cnt : S.owner;
+    atomicOr(&t[i1 >> 5], m1);
+    atomicOr(&t[i2 >> 5], m2);
   }
-  __syncthreads();
-  bool any = false;
-  for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
-    const uint32_t c = S.cnt[S.slot[r]];
-    const bool cand = self ? ((c & 0xFFFF) >= 2) : ((c & 0xFFFF) && (c >> 16));
-    if (cand) any = true;
-    else S.tli[r] |= kInactive;
-  }
-  return __syncthreads_or(any);
+}
+
+template <int CAP, int TBL>
+__device__ __forceinline__ bool sig_test(const JoinLds<CAP, TBL>& S, uint32_t i1,
+                                         uint32_t i2, bool side, bool self) {
+  const uint32_t* t = (self || !side) ? S.cnt : S.owner;
+  return ((t[i1 >> 5] >> (i1 & 31)) & (t[i2 >> 5] >> (i2 & 31)) & 1u) != 0;
 }
 
 // Adds a join's results (S.red) to a query's accumulators (thread 0).

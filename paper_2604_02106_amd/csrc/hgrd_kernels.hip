@@ -532,18 +532,25 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
   uint32_t n1 = R.b0 + 1 < R.b1 ? min(cursor[h.bucket0 + R.b0 + 1], (uint32_t)CAP) : 0;
   HGRD_FETCH(R.b0, n)
   __syncthreads();  // S.red ready
+  const bool self = q.self != 0;
   for (uint32_t b = R.b0; b < R.b1; ++b) {
     bool go = n != 0;
+    uint32_t i1[RPT], i2[RPT];
+    bool sd[RPT];
     if (!l0ext) {
-      // address and side only; the point id waits in S.blin until the
-      // records that share an address with the other side are known
+      // address and point id only (the point id waits in S.blin until the
+      // records that may share an address with the other side are known);
+      // the signature bitmap is cleared for this bucket
+      sig_clear(S);
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const uint32_t r = threadIdx.x + (uint32_t)j * kJoinThreads;
-        if (r >= n) continue;
         const uint32_t pid = is32 ? (uint32_t)(rx[j] >> 32) : (uint32_t)ry[j];
-        S.addr[r] = is32 ? (u64)(int64_t)(int32_t)(uint32_t)rx[j] : rx[j];
-        S.tli[r] = (pid >> 31) << 15;
+        const u64 a = is32 ? (u64)(int64_t)(int32_t)(uint32_t)rx[j] : rx[j];
+        sig_index<TBL>(a, i1[j], i2[j]);
+        sd[j] = (pid >> 31) != 0;
+        if (r >= n) continue;
+        S.addr[r] = a;
         S.blin[r] = pid;
       }
     }
@@ -552,7 +559,22 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
     if (!l0ext) {
       if (b + 1 < R.b1) HGRD_FETCH(b + 1, n1)
       __syncthreads();
-      if (go) go = addr_prefilter(S, n, q.self != 0);
+      if (go) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+          if (threadIdx.x + (uint32_t)j * kJoinThreads < n) sig_insert(S, i1[j], i2[j], sd[j], self);
+        __syncthreads();
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const uint32_t r = threadIdx.x + (uint32_t)j * kJoinThreads;
+          if (r >= n) continue;
+          const bool cand = sig_test(S, i1[j], i2[j], sd[j], self);
+          any |= cand;
+          S.tli[r] = (sd[j] ? kSide : 0u) | (cand ? 0u : kInactive);
+        }
+        go = __syncthreads_or(any);
+      }
     }
     if (go) {
       // full records of the candidates, one side at a time (the instance
