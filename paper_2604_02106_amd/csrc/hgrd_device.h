@@ -343,7 +343,20 @@ struct JoinLds {
   u64 red[8];
   uint32_t n;
   uint32_t err;
+  uint32_t vote[3];          // block-wide votes (see block_vote)
+  uint32_t bn[kMaxRunBuckets];  // record counts of a bucket run
 };
+
+// Block-wide OR with one barrier (the library's __syncthreads_or costs
+// three): waves holding a true lane store `tag` into an LDS word, then all
+// compare it after the barrier.  The caller keeps every earlier vote on
+// the same word behind a barrier and never repeats a tag while the word
+// still holds it.
+__device__ __forceinline__ bool block_vote(bool v, uint32_t* word, uint32_t tag) {
+  if (__ballot(v) != 0 && (threadIdx.x & 63) == 0) *word = tag;
+  __syncthreads();
+  return *reinterpret_cast<volatile uint32_t*>(word) == tag;
+}
 
 __device__ __forceinline__ uint32_t level_hash(int L, u64 addr, uint32_t blin,
                                                uint32_t bw, uint32_t w,
@@ -403,6 +416,7 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
   u64 Sl[6] = {0, 0, 0, 0, 0, 0};
   if (!l0ext)
     for (uint32_t r = tid; r < n; r += nt) S.part[r] = 0;
+  if (tid == 0) S.vote[2] = 0;  // the filter level's vote (after a barrier)
   bool any = true;
   for (int L = 0; L < 6; ++L) {
     if (!((used >> L) & 1)) continue;
@@ -457,7 +471,7 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
     }
     Sl[L] = s;
     if (L == f) {
-      any = __syncthreads_or(any_local);
+      any = block_vote(any_local, &S.vote[2], 1u);
       if (!any) break;
     } else {
       __syncthreads();
@@ -509,11 +523,12 @@ __device__ __forceinline__ void sig_index(u64 a, uint32_t& i1, uint32_t& i2) {
   i2 = ((x ^ (x >> 15)) * 0xC2B2AE35u) >> (32 - lgb);
 }
 
-template <int CAP, int TBL>
+template <uint32_t NT, int CAP, int TBL>
 __device__ __forceinline__ void sig_clear(JoinLds<CAP, TBL>& S) {
   uint4* o = reinterpret_cast<uint4*>(S.owner);
   uint4* c = reinterpret_cast<uint4*>(S.cnt);
-  for (uint32_t k = threadIdx.x; k < TBL / 4; k += blockDim.x) {
+#pragma unroll
+  for (uint32_t k = threadIdx.x; k < TBL / 4; k += NT) {
     o[k] = make_uint4(0, 0, 0, 0);
     c[k] = make_uint4(0, 0, 0, 0);
   }
@@ -555,6 +570,7 @@ __device__ __forceinline__ void commit_join(const JoinLds<CAP, TBL>& S,
 template <int CAP, int TBL>
 __device__ __forceinline__ void init_red(JoinLds<CAP, TBL>& S) {
   if (threadIdx.x < 8) S.red[threadIdx.x] = (threadIdx.x == 3 || threadIdx.x == 4) ? kNoKey : 0;
+  if (threadIdx.x < 3) S.vote[threadIdx.x] = 0;
 }
 
 // Appends a record to the LDS arrays (wavefront-aggregated slot claim).

@@ -1707,7 +1707,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   if (const char* e = getenv("HGRD_CHUNK_PTS"))
     plan->chunk_pts = std::max(256u, std::min(1u << 20, (uint32_t)atoi(e)));
   if (const char* e = getenv("HGRD_RUN_BUCKETS"))
-    plan->run_buckets = std::max(1u, std::min(256u, (uint32_t)atoi(e)));
+    plan->run_buckets = std::max(1u, std::min(kMaxRunBuckets, (uint32_t)atoi(e)));
 
   // ---- waves of HBM items, bounded by the device budget --------------------
   // Large waves keep the partition and join launches few (each launch has a

@@ -156,6 +156,7 @@ struct HItem {
 };
 static_assert(sizeof(HItem) == 96, "HItem layout");
 // A run of buckets [b0, b1) of one HBM item, joined by one workgroup.
+constexpr uint32_t kMaxRunBuckets = 64;  // buckets per join workgroup at most
 struct BRun {
   uint32_t item, b0, b1, pad;
 };

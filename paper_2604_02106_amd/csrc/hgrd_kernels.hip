@@ -528,10 +528,12 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
       }                                                             \
     }                                                               \
   }
+  // record counts of the run's buckets, read once
+  for (uint32_t k = threadIdx.x; k < R.b1 - R.b0; k += kJoinThreads)
+    S.bn[k] = min(cursor[h.bucket0 + R.b0 + k], (uint32_t)CAP);
   uint32_t n = R.b0 < R.b1 ? min(cursor[h.bucket0 + R.b0], (uint32_t)CAP) : 0;
-  uint32_t n1 = R.b0 + 1 < R.b1 ? min(cursor[h.bucket0 + R.b0 + 1], (uint32_t)CAP) : 0;
   HGRD_FETCH(R.b0, n)
-  __syncthreads();  // S.red ready
+  __syncthreads();  // S.red, S.vote and S.bn ready
   const bool self = q.self != 0;
   for (uint32_t b = R.b0; b < R.b1; ++b) {
     bool go = n != 0;
@@ -541,7 +543,7 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
       // address and point id only (the point id waits in S.blin until the
       // records that may share an address with the other side are known);
       // the signature bitmap is cleared for this bucket
-      sig_clear(S);
+      sig_clear<kJoinThreads>(S);
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const uint32_t r = threadIdx.x + (uint32_t)j * kJoinThreads;
@@ -555,7 +557,7 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
       }
     }
     // the next bucket's records load while this one is joined
-    const uint32_t n2 = b + 2 < R.b1 ? min(cursor[h.bucket0 + b + 2], (uint32_t)CAP) : 0;
+    const uint32_t n1 = b + 1 < R.b1 ? S.bn[b + 1 - R.b0] : 0;
     if (!l0ext) {
       if (b + 1 < R.b1) HGRD_FETCH(b + 1, n1)
       __syncthreads();
@@ -573,7 +575,9 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
           any |= cand;
           S.tli[r] = (sd[j] ? kSide : 0u) | (cand ? 0u : kInactive);
         }
-        go = __syncthreads_or(any);
+        // tag b + 1 on the word of b's parity: the same word's previous
+        // vote (bucket b - 2) was read before this bucket's first barrier
+        go = block_vote(any, &S.vote[b & 1], b + 1);
       }
     }
     if (go) {
@@ -631,7 +635,6 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
     if (go) lds_join(S, q, h.sigma, l0ext);
     __syncthreads();
     n = n1;
-    n1 = n2;
   }
   commit_join(S, &acc[h.q]);
 }
