@@ -515,10 +515,12 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
 // bits: no record with a partner is ever dropped, and the few kept by
 // colliding hashes are dropped exactly at the join's first level.
 template <int TBL>
-__device__ __forceinline__ void sig_index(u64 a, uint32_t& i1, uint32_t& i2) {
+__device__ __forceinline__ void sig_index(u64 a, uint32_t salt, uint32_t& i1,
+                                          uint32_t& i2) {
   constexpr uint32_t lgb = 5 + (TBL >= 8192 ? 13 : TBL >= 4096 ? 12 : 11);
   static_assert(TBL == 2048 || TBL == 4096 || TBL == 8192, "signature bitmap size");
-  const uint32_t x = (uint32_t)a ^ ((uint32_t)(a >> 32) * 0x85EBCA6Bu);
+  const uint32_t x = (uint32_t)a ^ ((uint32_t)(a >> 32) * 0x85EBCA6Bu) ^
+                     (salt * 0x27D4EB2Fu);
   i1 = (x * 0x9E3779B1u) >> (32 - lgb);
   i2 = ((x ^ (x >> 15)) * 0xC2B2AE35u) >> (32 - lgb);
 }

@@ -1603,6 +1603,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         hp.h.shared = q.qd.shared;
         hp.h.is32 = R0.is32;
         hp.h.shift = item_shift(ia, ib, q.qd.self, q.qd.shared);
+        fastdiv_consts(P.dev_insts[ia].tpb, &hp.h.tpb_m[0], &hp.h.tpb_s[0]);
+        fastdiv_consts(P.dev_insts[ib].tpb, &hp.h.tpb_m[1], &hp.h.tpb_s[1]);
         hp.R = tot;
         hplans.push_back(hp);
       }

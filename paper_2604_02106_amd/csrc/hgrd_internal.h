@@ -140,7 +140,8 @@ struct HItem {
   uint32_t shared;        // hash (addr, blin) instead of addr
   uint32_t is32;          // 32-bit keys
   unsigned long long rec_off;  // byte offset of bucket 0's records
-  unsigned long long pad0;
+  uint32_t tpb_m[2];           // points per block of side a, b as fast-division
+                               // multipliers (block of a point = pidx / tpb)
   unsigned long long l0_off;   // mode 3: the item's address-count table
   uint32_t l0_mask;            //   (slots l0_off .. l0_off + l0_mask + 1)
   uint32_t shift;              // buckets see address >> shift (blocks of
@@ -152,7 +153,7 @@ struct HItem {
   uint32_t mode, kb;
   long long lo;
   unsigned long long fm;
-  unsigned long long pad1;
+  uint32_t tpb_s[2];           // and shifts
 };
 static_assert(sizeof(HItem) == 96, "HItem layout");
 // A run of buckets [b0, b1) of one HBM item, joined by one workgroup.

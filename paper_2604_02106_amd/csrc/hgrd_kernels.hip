@@ -549,8 +549,16 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
         const uint32_t r = threadIdx.x + (uint32_t)j * kJoinThreads;
         const uint32_t pid = is32 ? (uint32_t)(rx[j] >> 32) : (uint32_t)ry[j];
         const u64 a = is32 ? (u64)(int64_t)(int32_t)(uint32_t)rx[j] : rx[j];
-        sig_index<TBL>(a, i1[j], i2[j]);
         sd[j] = (pid >> 31) != 0;
+        // shared arrays: memory is per block, so the block joins the address
+        uint32_t salt = 0;
+        if (h.shared == 1) {
+          const uint32_t p = pid & 0x7FFFFFFFu;
+          const uint32_t m = sd[j] ? h.tpb_m[1] : h.tpb_m[0];
+          const uint32_t sh = sd[j] ? h.tpb_s[1] : h.tpb_s[0];
+          salt = ((__umulhi(m, p) + p) >> sh) + 1;
+        }
+        sig_index<TBL>(a, salt, i1[j], i2[j]);
         if (r >= n) continue;
         S.addr[r] = a;
         S.blin[r] = pid;
@@ -580,6 +588,7 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
         go = block_vote(any, &S.vote[b & 1], b + 1);
       }
     }
+    const uint32_t wsh = (q.warp & (q.warp - 1)) == 0 ? (uint32_t)__ffs((int)q.warp) - 1 : 32u;
     if (go) {
       // full records of the candidates, one side at a time (the instance
       // stays uniform: scalar loads, no divergent interpreter)
@@ -615,7 +624,7 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
           S.blin[r] = id.blin;
           S.tli[r] = (id.ilin << 16) | (side << 15) | id.tlin;
           S.bw[r] = (bi << 16) | wi;
-          S.w[r] = (uint16_t)(id.tlin / q.warp);
+          S.w[r] = (uint16_t)(wsh < 32 ? id.tlin >> wsh : id.tlin / q.warp);
           if (l0ext) {
             // level-0 partners of a side-a record: the other side's count
             // at its address in the item's address-count table
@@ -1110,6 +1119,12 @@ void fill_devinst(void* dst, const AccInst& a) {
 }
 
 // Host check of the division helper (exported for the CPU tests).
+void fastdiv_consts(uint32_t d, uint32_t* m, uint32_t* s) {
+  const FastDiv f = make_fastdiv(d);
+  *m = f.m;
+  *s = f.s;
+}
+
 int fastdiv_check(uint32_t n, uint32_t d) {
   FastDiv f = make_fastdiv(d);
   uint32_t t = (uint32_t)(((u64)f.m * n) >> 32);

@@ -26,6 +26,7 @@ int launch_tabulate(hipStream_t st, const Chunk* chunks, uint32_t n,
                     const TabJob* jobs, const void* insts, const DInsn* code,
                     const int64_t* params, const int64_t* loopvals, int64_t* pool);
 int fastdiv_check(uint32_t n, uint32_t d);
+void fastdiv_consts(uint32_t d, uint32_t* m, uint32_t* s);
 int join_lds_bytes(int cfg);
 int join_cap(int cfg);
 size_t w2item_size();
