@@ -336,7 +336,7 @@ struct JoinLds {
   uint32_t tli[CAP];  // ilin << 16 | side << 15 | inactive << 14 | tlin
   uint32_t bw[CAP];   // bint << 16 | wint
   uint16_t w[CAP];    // warp of the analysed program
-  uint16_t slot[CAP];
+  uint32_t key[CAP];  // a record's group key at the level being joined
   int32_t part[CAP];
   uint32_t owner[TBL];
   uint32_t cnt[TBL];
@@ -387,18 +387,34 @@ __device__ __forceinline__ bool level_eq(const JoinLds<CAP, TBL>& S, int L,
 
 // Joins the S.n records in LDS.  Leaves the class counts in S.red[0..2] and
 // the smallest p key with a partner in S.red[3] (kNoKey: none); the caller
-// sets S.red to (0, 0, 0, kNoKey) and synchronises before the call.  All
+// sets S.red to (0, 0, 0, kNoKey) and synchronises before the call.  All NT
 // threads of the block must call it; it ends with a barrier.
+//
+// Level L groups refine level L - 1 groups, so after the first level a
+// record's group at L is (its group at the previous level, the one field
+// that L adds): the previous group's table slot and that field make a
+// 32-bit key (the block, 32 bits itself, is compared beside the key).  Each
+// insert then costs one compare-and-swap and one read; the first level
+// compares the fields themselves.
 //
 // l0ext: the records hold whole (address, block) groups but not whole
 // address groups; level 0 (S_0, the address-only sums) is counted elsewhere
 // and the caller has put each side-a record's level-0 partner count in
 // S.part.  Then S.red[0] gets -S_1 (inter = S_0 - S_1 modulo 2^64) and no
 // record is filtered out.
-template <int CAP, int TBL>
+__device__ __forceinline__ uint32_t key_slot(uint32_t k, uint32_t b, uint32_t tbl) {
+  uint32_t x = k * 0x9E3779B1u ^ b * 0x85EBCA77u;
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  return x & (tbl - 1);
+}
+
+template <uint32_t NT, int CAP, int TBL>
 __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
                          bool l0ext = false) {
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  constexpr int RPT = (CAP + NT - 1) / NT;
+  const uint32_t tid = threadIdx.x;
   const uint32_t n = S.n;
   const uint32_t mask = qd.mask;
   const bool self = qd.self != 0;
@@ -414,10 +430,19 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
   const bool same2 = (qd.flags & 1) && ((used >> 1) & 1) && ((used >> 2) & 1);
   const bool same4 = (qd.flags & 2) && ((used >> 3) & 1) && ((used >> 4) & 1);
   u64 Sl[6] = {0, 0, 0, 0, 0, 0};
-  if (!l0ext)
-    for (uint32_t r = tid; r < n; r += nt) S.part[r] = 0;
+  // per record of this thread: tli (kInactive also past the end) and the
+  // table slot of its group at the last computed level
+  uint32_t tl[RPT], gid[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const uint32_t r = tid + (uint32_t)j * NT;
+    tl[j] = r < n ? S.tli[r] : kInactive;
+    gid[j] = 0;
+    if (!l0ext && r < n) S.part[r] = 0;
+  }
   if (tid == 0) S.vote[2] = 0;  // the filter level's vote (after a barrier)
   bool any = true;
+  int P = -1;  // last computed level
   for (int L = 0; L < 6; ++L) {
     if (!((used >> L) & 1)) continue;
     if ((L == 2 && same2) || (L == 4 && same4)) {
@@ -425,51 +450,86 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
       continue;
     }
     const bool twin = (L == 1 && same2) || (L == 3 && same4);
-    for (uint32_t k = tid; k < TBL; k += nt) {
+    // incremental key: L adds one field to P (a skipped level between adds
+    // a field that is one constant for every record)
+    const bool inc = P >= 0 && (L == P + 1 || (L == 3 && P == 1 && same2) ||
+                                (L == 5 && P == 3 && same4));
+    for (uint32_t k = tid; k < TBL; k += NT) {
       S.owner[k] = kEmpty;
       S.cnt[k] = 0;
     }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const uint32_t r = tid + (uint32_t)j * NT;
+      if ((tl[j] & kInactive) || !inc) continue;
+      uint32_t fld;
+      if (L == 1) {
+        fld = 0;
+      } else if (L == 2) {
+        fld = S.bw[r] >> 16;
+      } else if (L == 3) {
+        fld = S.w[r];
+      } else if (L == 4) {
+        fld = S.bw[r] & 0xFFFF;
+      } else {
+        fld = tl[j] & 0x3FF;
+      }
+      S.key[r] = (gid[j] << 16) | fld;
+    }
     __syncthreads();
-    u64 s = 0;
-    for (uint32_t r = tid; r < n; r += nt) {
-      uint32_t tl = S.tli[r];
-      if (tl & kInactive) continue;
-      uint32_t h = level_hash(L, S.addr[r], S.blin[r], S.bw[r], S.w[r],
-                              tl & 0x3FF) & (TBL - 1);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const uint32_t r = tid + (uint32_t)j * NT;
+      if (tl[j] & kInactive) continue;
+      const uint32_t kr = inc ? S.key[r] : 0u;
+      const uint32_t kb = inc && L == 1 ? S.blin[r] : 0u;
+      uint32_t h = inc ? key_slot(kr, kb, TBL)
+                       : level_hash(L, S.addr[r], S.blin[r], S.bw[r], S.w[r],
+                                    tl[j] & 0x3FF) & (TBL - 1);
       for (;;) {
-        uint32_t o = atomicCAS(&S.owner[h], kEmpty, r);
-        if (o == kEmpty || level_eq(S, L, o, r)) break;
+        const uint32_t o = atomicCAS(&S.owner[h], kEmpty, r);
+        if (o == kEmpty) break;
+        if (inc ? (S.key[o] == kr && (L != 1 || S.blin[o] == kb))
+                : level_eq(S, L, o, r))
+          break;
         h = (h + 1) & (TBL - 1);
       }
-      uint32_t side = (tl & kSide) ? 1u : 0u;
-      uint32_t old = atomicAdd(&S.cnt[h], (self || !side) ? 1u : 0x10000u);
-      if (self) s += 2ull * (old & 0xFFFF) + 1;
-      else s += side ? (old & 0xFFFF) : (old >> 16);
-      S.slot[r] = (uint16_t)h;
+      atomicAdd(&S.cnt[h], (self || !(tl[j] & kSide)) ? 1u : 0x10000u);
+      gid[j] = h;
     }
     __syncthreads();
     const int sign = (L & 1) ? -1 : 1;
     const uint32_t cls = L < 2 ? 1u : (L < 4 ? 2u : 4u);
     bool any_local = false;
-    for (uint32_t r = tid; r < n; r += nt) {
-      uint32_t tl = S.tli[r];
-      if (tl & kInactive) continue;
-      uint32_t c = S.cnt[S.slot[r]];
+    u64 s = 0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const uint32_t r = tid + (uint32_t)j * NT;
+      if (tl[j] & kInactive) continue;
+      const uint32_t c = S.cnt[gid[j]];
+      const bool sb = (tl[j] & kSide) != 0;
+      // ordered pairs of the group: a self pair counts every record with
+      // each of its group (itself included), a pair of two accesses each
+      // side-a record with the group's side-b records
+      if (self) s += c & 0xFFFF;
+      else if (!sb) s += c >> 16;
       if (L == f) {
-        bool cand = self ? ((c & 0xFFFF) >= 2) : ((c & 0xFFFF) && (c >> 16));
+        const bool cand = self ? ((c & 0xFFFF) >= 2) : ((c & 0xFFFF) && (c >> 16));
         if (!cand) {
-          S.tli[r] = tl | kInactive;
+          tl[j] |= kInactive;
+          S.tli[r] = tl[j];
           if (self) s -= 1;  // a lone record pairs only with itself
           continue;
         }
         any_local = true;
       }
-      if (!self && (tl & kSide)) continue;
+      if (!self && sb) continue;
       const int32_t nj = (int32_t)(self ? (c & 0xFFFF) : (c >> 16));
       if (cls & mask) S.part[r] += sign * nj;
       if (twin && ((cls << 1) & mask)) S.part[r] -= sign * nj;  // level L + 1
     }
     Sl[L] = s;
+    P = L;
     if (L == f) {
       any = block_vote(any_local, &S.vote[2], 1u);
       if (!any) break;
@@ -483,11 +543,12 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
   u64 c1 = (mask & 2) ? Sl[2] - Sl[3] : 0;
   u64 c2 = (mask & 4) ? Sl[4] - Sl[5] : 0;
   u64 best = kNoKey;
-  for (uint32_t r = tid; r < n; r += nt) {
-    uint32_t tl = S.tli[r];
-    if ((tl & kInactive) || (!self && (tl & kSide))) continue;
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const uint32_t r = tid + (uint32_t)j * NT;
+    if ((tl[j] & kInactive) || (!self && (tl[j] & kSide))) continue;
     if (S.part[r] > 0) {
-      u64 k = pkey(sigma, S.blin[r], tl & 0x3FF, tl >> 16);
+      u64 k = pkey(sigma, S.blin[r], tl[j] & 0x3FF, tl[j] >> 16);
       best = k < best ? k : best;
     }
   }

@@ -81,7 +81,7 @@ __device__ __forceinline__ void small_item(JoinLds<CAP, TBL>& S, const SItem& it
     if (threadIdx.x == 0) atomicOr(&acc[it.q].err, S.err);
     return;
   }
-  lds_join(S, q, it.sigma);
+  lds_join<256>(S, q, it.sigma);
   commit_join(S, &acc[it.q]);
 }
 
@@ -485,8 +485,17 @@ constexpr uint32_t kJoinThreads = 512;  // bucket-join workgroup size
 // into registers while the current one is joined, and the counts are
 // committed once per run.  TAB: both instances of every item of the launch
 // have term tables (interval ids by lookup, no interpreter code).
+// Workgroups of the bucket join that the LDS of one CU holds (160 KiB):
+// the register budget of the table-path join is set so that as many fit by
+// registers too (the interpreter path keeps its registers: no spills).
+template <int CAP, int TBL>
+constexpr uint32_t join_waves_per_simd() {
+  return 2u * (uint32_t)(163840 / sizeof(JoinLds<CAP, TBL>));
+}
+
 template <int CAP, int TBL, bool TAB>
 __global__ void __launch_bounds__(kJoinThreads)
+__attribute__((amdgpu_waves_per_eu(TAB ? join_waves_per_simd<CAP, TBL>() : 1u)))
 k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
               const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
               const int64_t* __restrict__ params,
@@ -641,7 +650,7 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
 #undef HGRD_FETCH
     if (threadIdx.x == 0) S.n = n;
     __syncthreads();
-    if (go) lds_join(S, q, h.sigma, l0ext);
+    if (go) lds_join<kJoinThreads>(S, q, h.sigma, l0ext);
     __syncthreads();
     n = n1;
   }

@@ -447,7 +447,7 @@ k_tile_join(const TItem* __restrict__ items, const VQuery* __restrict__ vq,
   }
   __syncthreads();
   if (S.err) return;  // errors are reported by the bounds pass
-  lds_join(S, q, v.sigma);
+  lds_join<256>(S, q, v.sigma);
   const u64 pk = S.red[3];
   if (pk == kNoKey) return;
   // p*: the record with key pk on side 0; then the smallest partner q
