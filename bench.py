@@ -20,6 +20,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_scatter_batched_hbm.md")
+JOIN_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bucket_join_batched_hbm.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_02106_amd", "csrc", f)
                   for f in ("hgrd_kernels.hip", "hgrd_device.h", "hgrd_internal.h")]
 
@@ -33,11 +34,11 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per k_scatter<true> launch from the committed counter
-    summary, if it was taken on the current kernel sources (else None)."""
+def measured_traffic(path):
+    """HBM bytes per launch of a kernel from its committed counter summary,
+    if it was taken on the current kernel sources (else None)."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     fields = {}
@@ -297,22 +298,33 @@ def main():
                                             "overflow_items", "fallback_records",
                                             "buckets", "records", "scatter_bytes")},
     }
-    # dominant kernel: the partition kernel k_scatter, timed with HIP events
-    # on the library's stream around every launch of the timed steps
-    launches = sum(s["scatter_launches"] for s in stats)
-    sms = sum(s["scatter_tab_ms"] for s in stats)
-    sbytes = sum(s["scatter_tab_bytes"] for s in stats)
-    if launches and sms > 0:
+    # dominant kernel: the table-path bucket join (records read back from
+    # HBM and joined in LDS); beside it the table-path partition kernel
+    # (records generated and written).  Both are timed with HIP events on
+    # the library's stream around every launch of the timed steps.
+    # (the context's default LDS tile: 1024 records, 2048 table slots)
+    for key, name, lk, mk, bk, tfile in (
+            ("roofline", "k_bucket_join<1024, 2048, true>", "join_tab_launches", "join_tab_ms",
+             "join_tab_bytes", JOIN_TRAFFIC_FILE),
+            ("roofline_partition", "k_scatter<true>", "scatter_launches",
+             "scatter_tab_ms", "scatter_tab_bytes", TRAFFIC_FILE)):
+        launches = sum(s[lk] for s in stats)
+        sms = sum(s[mk] for s in stats)
+        sbytes = sum(s[bk] for s in stats)
+        if not launches or sms <= 0:
+            continue
         avg_ms = sms / launches
         per_launch = sbytes / launches
         achieved = per_launch / (avg_ms / 1e3) / 1e9
-        line["roofline"] = {"bound": "hbm", "kernel": "k_scatter<true>",
-                            "achieved": achieved, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                            "traffic": measured_traffic(),
-                            "bytes_per_launch": per_launch,
-                            "avg_launch_ms": avg_ms,
-                            "launches_per_step": launches / len(stats)}
+        line[key] = {"bound": "hbm", "kernel": name,
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     # counters were taken on the batched workload only
+                     "traffic": (measured_traffic(tfile)
+                                 if args.config == "batched" else None),
+                     "bytes_per_launch": per_launch,
+                     "avg_launch_ms": avg_ms,
+                     "launches_per_step": launches / len(stats)}
     if not args.no_cpu_baseline and args.config == "batched":
         line["cpu_baseline"] = cpu_baseline(wl, res)
     print(json.dumps(line), flush=True)

@@ -295,6 +295,10 @@ typedef struct {
   double scatter_tab_ms;     /* table-path partition kernels */
   uint64_t scatter_tab_bytes; /* record bytes they wrote */
   uint64_t prefiltered;      /* (pair, tuple) units the pre-filter decided */
+  uint64_t join_tab_launches; /* table-path bucket join launches
+                                 (k_bucket_join with term tables) */
+  double join_tab_ms;        /* their summed duration */
+  uint64_t join_tab_bytes;   /* record bytes they read */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

@@ -1863,7 +1863,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   plan->buf("ovf", std::max<size_t>(1, plan->hitems.size()) * 4, &merr);
   plan->buf("done", std::max<size_t>(1, n_pairs) * 4, &merr);
   plan->buf("pcursor", 4, &merr);
-  plan->buf("nbytes", 128 * 8, &merr);
+  plan->buf("nbytes", 256 * 8, &merr);
   plan->buf("out", std::max<size_t>(1, n_pairs) * sizeof(rd_pair_result), &merr);
   if (merr) return merr;
   *plan_out = guard.release();
@@ -1924,8 +1924,9 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   // graph carries no events (their times are not reliable inside graphs).
   uint32_t wev_n = 0;
   // per wave: events before and after the table partition, after the
-  // interpreted partition and after the join; whether tables ran
-  std::vector<std::array<uint32_t, 5>> wtimes;
+  // interpreted partition, after the table-path join and after the
+  // interpreted join; whether table partition and table join ran
+  std::vector<std::array<uint32_t, 7>> wtimes;
   auto wevent = [&](uint32_t k) -> hipEvent_t {
     while (ctx->wev.size() <= k) {
       hipEvent_t e = nullptr;
@@ -1941,14 +1942,15 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     const uint32_t wcap = (uint32_t)join_cap(wcfg);
     for (const auto& W : waves) {
       const uint32_t k = wev_n;
-      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr;
       if (events) {
-        wev_n += 4;
+        wev_n += 5;
         e0 = wevent(k);
         e1 = wevent(k + 1);
         e2 = wevent(k + 2);
         e3 = wevent(k + 3);
-        if (!e0 || !e1 || !e2 || !e3) return RD_EDEVICE;
+        e4 = wevent(k + 4);
+        if (!e0 || !e1 || !e2 || !e3 || !e4) return RD_EDEVICE;
       }
       if (launch_fill_u32(st, d_cursor, W.n_buckets, 0)) return RD_EDEVICE;
       // partition: instances with term tables, then the interpreted ones
@@ -1967,14 +1969,23 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
                          d_cursor, d_ovf, wcap, d_done, d_nbytes + 64))
         return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(e2, st));
-      if (W.n_runs &&
-          launch_bucket(wcfg, st, W.n_runs, d_bit + W.bitem_off, W.n_tab_runs, d_hit,
+      // join: runs of items with term tables, then the interpreted ones
+      // (record bytes read counted in slots 128..191 and 192..255)
+      if (W.n_tab_runs &&
+          launch_bucket(wcfg, st, W.n_tab_runs, d_bit + W.bitem_off, W.n_tab_runs, d_hit,
                         d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs,
-                        d_cursor, d_ovf, d_done, l0k, l0c))
+                        d_cursor, d_ovf, d_done, l0k, l0c, d_nbytes + 128))
+        return RD_EDEVICE;
+      if (events) TRY_HIP(hipEventRecord(e3, st));
+      if (W.n_runs > W.n_tab_runs &&
+          launch_bucket(wcfg, st, W.n_runs - W.n_tab_runs, d_bit + W.bitem_off + W.n_tab_runs,
+                        0, d_hit, d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs,
+                        d_cursor, d_ovf, d_done, l0k, l0c, d_nbytes + 128))
         return RD_EDEVICE;
       if (events) {
-        TRY_HIP(hipEventRecord(e3, st));
-        wtimes.push_back({k, k + 1, k + 2, k + 3, W.n_tab_chunks ? 1u : 0u});
+        TRY_HIP(hipEventRecord(e4, st));
+        wtimes.push_back({k, k + 1, k + 2, k + 3, k + 4, W.n_tab_chunks ? 1u : 0u,
+                          W.n_tab_runs ? 1u : 0u});
       }
       if (W.n_buckets) S.join_launches += 1;
       S.buckets += W.n_buckets;
@@ -1986,14 +1997,21 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       float ms = 0;
       if (hipEventElapsedTime(&ms, ctx->wev[t[0]], ctx->wev[t[1]]) == hipSuccess) {
         scatter_ms += ms;
-        if (t[4]) {
+        if (t[5]) {
           S.scatter_tab_ms += ms;
           S.scatter_launches += 1;
         }
       }
       if (hipEventElapsedTime(&ms, ctx->wev[t[1]], ctx->wev[t[2]]) == hipSuccess)
         scatter_ms += ms;
-      if (hipEventElapsedTime(&ms, ctx->wev[t[2]], ctx->wev[t[3]]) == hipSuccess)
+      if (hipEventElapsedTime(&ms, ctx->wev[t[2]], ctx->wev[t[3]]) == hipSuccess) {
+        bucket_ms += ms;
+        if (t[6]) {
+          S.join_tab_ms += ms;
+          S.join_tab_launches += 1;
+        }
+      }
+      if (hipEventElapsedTime(&ms, ctx->wev[t[3]], ctx->wev[t[4]]) == hipSuccess)
         bucket_ms += ms;
     }
     wtimes.clear();
@@ -2011,7 +2029,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       return RD_EDEVICE;
     if (launch_init_acc(st, n_pairs, d_acc)) return RD_EDEVICE;
     if (launch_fill_u32(st, d_done, n_pairs, 0)) return RD_EDEVICE;
-    if (launch_fill_u64(st, d_nbytes, 128, 0)) return RD_EDEVICE;
+    if (launch_fill_u64(st, d_nbytes, 256, 0)) return RD_EDEVICE;
     if (plan->verdict && plan->n_vq) {
       VQuery* d_vq = (VQuery*)D("vq");
       BBound* d_bb = (BBound*)D("bbounds");
@@ -2475,12 +2493,13 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   TRY_HIP(hipEventRecord(ev[1], st));
   if (n_pairs)
     TRY_HIP(hipMemcpyAsync(out, d_out, n_pairs * sizeof(rd_pair_result), hipMemcpyDeviceToHost, st));
-  u64 scat_bytes[128];
+  u64 scat_bytes[256];
   TRY_HIP(hipMemcpyAsync(scat_bytes, d_nbytes, sizeof scat_bytes, hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < 128; ++k) {
     S.scatter_bytes += scat_bytes[k];
     if (k < 64) S.scatter_tab_bytes += scat_bytes[k];
+    if (k < 64) S.join_tab_bytes += scat_bytes[128 + k];
   }
   float ms = 0;
   if (!w2.empty()) {

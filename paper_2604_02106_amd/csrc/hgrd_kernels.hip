@@ -505,7 +505,7 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
               const uint32_t* __restrict__ cursor,
               const uint32_t* __restrict__ ovf,
               const uint32_t* __restrict__ done, const u64* __restrict__ l0keys,
-              const u64* __restrict__ l0cnt) {
+              const u64* __restrict__ l0cnt, u64* __restrict__ nbytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
   const BRun R = runs[blockIdx.x];
@@ -541,11 +541,13 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
   for (uint32_t k = threadIdx.x; k < R.b1 - R.b0; k += kJoinThreads)
     S.bn[k] = min(cursor[h.bucket0 + R.b0 + k], (uint32_t)CAP);
   uint32_t n = R.b0 < R.b1 ? min(cursor[h.bucket0 + R.b0], (uint32_t)CAP) : 0;
+  u64 nread = 0;  // record bytes read (thread 0)
   HGRD_FETCH(R.b0, n)
   __syncthreads();  // S.red, S.vote and S.bn ready
   const bool self = q.self != 0;
   for (uint32_t b = R.b0; b < R.b1; ++b) {
     bool go = n != 0;
+    nread += (u64)n * (is32 ? 8u : 16u);
     uint32_t i1[RPT], i2[RPT];
     bool sd[RPT];
     if (!l0ext) {
@@ -655,6 +657,7 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
     n = n1;
   }
   commit_join(S, &acc[h.q]);
+  if (threadIdx.x == 0 && nread) atomicAdd(&nbytes[blockIdx.x & 63], nread);
 }
 
 // ---------------------------------------------------------------------------
@@ -1074,8 +1077,9 @@ static int launch_bucket_t(hipStream_t st, uint32_t nruns, const BRun* runs,
                            const int64_t* loopvals, const QDesc* qd, QAcc* acc,
                            const unsigned char* recs, const uint32_t* cursor,
                            const uint32_t* ovf, const uint32_t* done,
-                           const u64* l0keys, const u64* l0cnt) {
-  // runs [0, n_tab) are of items whose instances have term tables
+                           const u64* l0keys, const u64* l0cnt, u64* nbytes) {
+  // runs [0, n_tab) are of items whose instances have term tables; record
+  // bytes read are counted in nbytes[0..63] and nbytes[64..127]
   size_t lds = sizeof(JoinLds<CAP, TBL>);
   for (uint32_t off = 0; off < nruns; off += 1u << 20) {
     uint32_t m = nruns - off < (1u << 20) ? nruns - off : (1u << 20);
@@ -1083,11 +1087,11 @@ static int launch_bucket_t(hipStream_t st, uint32_t nruns, const BRun* runs,
     if (mt)
       hipLaunchKernelGGL((k_bucket_join<CAP, TBL, true>), dim3(mt), dim3(kJoinThreads), lds,
                          st, runs + off, hitems, insts, code, params, loopvals, qd, acc,
-                         recs, cursor, ovf, done, l0keys, l0cnt);
+                         recs, cursor, ovf, done, l0keys, l0cnt, nbytes);
     if (m > mt)
       hipLaunchKernelGGL((k_bucket_join<CAP, TBL, false>), dim3(m - mt), dim3(kJoinThreads),
                          lds, st, runs + off + mt, hitems, insts, code, params, loopvals,
-                         qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
+                         qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, nbytes + 64);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -1211,12 +1215,12 @@ int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
                   const DInsn* code, const int64_t* params, const int64_t* loopvals,
                   const QDesc* qd, QAcc* acc, const unsigned char* recs,
                   const uint32_t* cursor, const uint32_t* ovf, const uint32_t* done,
-                  const u64* l0keys, const u64* l0cnt) {
+                  const u64* l0keys, const u64* l0cnt, u64* nbytes) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
-    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
-    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt);
+    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, nbytes);
+    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, nbytes);
+    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, nbytes);
   }
 }
 
