@@ -160,6 +160,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the pre-filtered plan and graph replay figures "
+                         "reported beside the headline (they run after the "
+                         "timed steps)")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--config", default="batched",
                     choices=("batched", "stress", "mixed", "learned"),
@@ -240,29 +244,31 @@ def main():
     res = [hg.result_dict(plan.out[k]) for k in range(len(wl.pairs))]
     assert res == e2e
     tstat = stats[-1]
-    # with the exact interval pre-filter (beside the headline)
-    pplan = hg.Plan(ctx, wl, max_device_bytes=args.wave_mib << 20, prefilter=1)
-    pres = pplan.execute()
-    assert pres == res
-    torch.cuda.synchronize()
-    log("pre-filtered plan checked")
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        pplan.execute(raw=True)
-        log("pre-filtered step %d done" % i)
-    torch.cuda.synchronize()
-    dt_pre = time.perf_counter() - t0
-    pre_units = ctx.stats()["prefiltered"]
-    pplan.close()
-    # the same plan replaying its captured graph (beside the headline)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        plan.execute(raw=True)
-        log("graph step %d done" % i)
-    torch.cuda.synchronize()
-    dt_graph = time.perf_counter() - t0
-    log("timed %d steps in %.3f s (graph replay %.3f s)" % (args.steps, dt, dt_graph))
+    dt_pre = dt_graph = pre_units = None
+    if not args.no_extras:
+        # with the exact interval pre-filter (beside the headline)
+        pplan = hg.Plan(ctx, wl, max_device_bytes=args.wave_mib << 20, prefilter=1)
+        pres = pplan.execute()
+        assert pres == res
+        torch.cuda.synchronize()
+        log("pre-filtered plan checked")
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            pplan.execute(raw=True)
+            log("pre-filtered step %d done" % i)
+        torch.cuda.synchronize()
+        dt_pre = time.perf_counter() - t0
+        pre_units = ctx.stats()["prefiltered"]
+        pplan.close()
+        # the same plan replaying its captured graph (beside the headline)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            plan.execute(raw=True)
+            log("graph step %d done" % i)
+        torch.cuda.synchronize()
+        dt_graph = time.perf_counter() - t0
+    log("timed %d steps in %.3f s" % (args.steps, dt))
     n = len(wl.pairs)
     evals = stats[-1]["evals"]
     racy = sum(r["verdict"] for r in res)
@@ -284,8 +290,8 @@ def main():
                    "scale": args.scale, "wave_mib": args.wave_mib or 1536},
         "evals_per_s_G": evals * args.steps / dt / 1e9,
         "end_to_end_queries_per_s": n / e2e_s,
-        "graph_replay_queries_per_s": n * args.steps / dt_graph,
-        "prefilter_queries_per_s": n * args.steps / dt_pre,
+        "graph_replay_queries_per_s": n * args.steps / dt_graph if dt_graph else None,
+        "prefilter_queries_per_s": n * args.steps / dt_pre if dt_pre else None,
         "prefilter_units": pre_units,
         "prepare_s": prep_s,
         "kernel_ms": {k: sum(s[k] for s in stats) / len(stats)
