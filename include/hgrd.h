@@ -172,9 +172,13 @@ typedef struct {
 typedef struct {
   uint32_t mode;       /* RD_MODE_EXACT (default) or RD_MODE_VERDICT */
   uint32_t order;      /* VERDICT tile order: RD_ORDER_LEX or RD_ORDER_MLP */
-  uint32_t prefilter;  /* 1: decide (pair, tuple) units whose two address
-                          ranges (bounds proven for the term tables) do not
-                          meet without enumerating them (exact); 0: off */
+  uint32_t prefilter;  /* 1: decide without enumeration (exact) the
+                          (pair, tuple) units whose two accesses share no
+                          address: their address ranges (bounds proven for
+                          the term tables) do not meet, or their address
+                          residues (every address = u + k G, G the gcd of
+                          the table terms' known factors) admit no common
+                          value; 0: off */
   uint32_t log_level;  /* 0 silent, 1 summary, 2 per-launch (stderr) */
   uint32_t lds_cap;    /* records per LDS join tile (1024, 1536 or 3072);
                           0 = the context's default (1024 until

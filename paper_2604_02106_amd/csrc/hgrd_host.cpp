@@ -924,6 +924,9 @@ struct Planner {
   std::vector<AccInst> dev_insts;
   std::vector<TabHost> tabs;  // per device instance
   std::vector<std::pair<int64_t, int64_t>> arange;  // address range, tables only
+  // address residue, tables only: every address is congruent to `second`
+  // modulo `first` (0: the single address `second`; 1: no information)
+  std::vector<std::pair<uint64_t, int64_t>> ares;
   std::vector<TabJob> tjobs;
   uint64_t tpool = 0;         // table entries
   bool use_tables = true;
@@ -1046,6 +1049,11 @@ struct Planner {
     T.never = never;
     T.on = 1;
     arange[inst] = {(int64_t)lo, (int64_t)hi};
+    // each term is a multiple of g * |mult| (1 when that product is not
+    // known exactly), so addr - u is a multiple of their gcd
+    uint64_t G = 0;
+    for (const STerm& t : L.terms) G = gcd64(G, gmul(t.g, uabs64(t.mult)));
+    ares[inst] = {G, (int64_t)L.u};
     // point order: iterations fastest when the address moves less along
     // them than along threads (consecutive points then share buckets)
     int64_t stride[3] = {0, 0, 0};
@@ -1203,6 +1211,7 @@ struct Planner {
     dev_insts.push_back(I);
     TabHost T;
     arange.push_back({0, -1});
+    ares.push_back({1, 0});
     tables_for(m, a, I, (uint32_t)ii.idx, T);
     tabs.push_back(T);
     return ii;
@@ -1556,11 +1565,19 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         continue;
       }
       if (o.prefilter && ia != ib && P.tabs[ia].on && P.tabs[ib].on) {
-        // exact pre-filter: the two accesses' address ranges over the whole
-        // launch box (term-table bounds) do not meet, so no pair conflicts
+        // exact pre-filters: no address of one access equals an address of
+        // the other, so no pair conflicts.  (1) The address ranges over the
+        // whole launch box (term-table bounds) do not meet.  (2) The
+        // residues are incompatible: addresses of a are u_a + k G_a, of b
+        // u_b + k G_b, and a common one needs gcd(G_a, G_b) | u_a - u_b.
         const auto& ra = P.arange[ia];
         const auto& rb = P.arange[ib];
-        if (ra.second < rb.first || rb.second < ra.first) {
+        const auto& ca = P.ares[ia];
+        const auto& cb = P.ares[ib];
+        const uint64_t g = gcd64(ca.first, cb.first);
+        const i128 du = (i128)ca.second - (i128)cb.second;
+        const bool apart = g == 0 ? du != 0 : (du % (i128)g) != 0;
+        if (ra.second < rb.first || rb.second < ra.first || apart) {
           ++plan->prefiltered;
           continue;
         }

@@ -69,3 +69,35 @@ def test_stress_full_size(hg):
         assert r["status"] == 0 and r["verdict"] == 0 and r["count"] == 0, r
         assert r["witness"] == (-1,) * 7
         assert r["evals"] == 2 * (1 << 30)
+
+
+def test_stress_prefilter_decides_near_misses(hg):
+    """Exact residue pre-filter: strided near misses (2f against 2f + 1)
+    share no residue modulo 2, so with the pre-filter on each of their
+    (pair, tuple) units is decided without enumeration; the blocked near
+    misses interleave block by block over the same address range and are
+    enumerated.  Every field stays equal to the oracle's.  The shifted
+    (racy) variant keeps every unit (residues and ranges then meet) and
+    equals the oracle's too."""
+    wl = configs.stress(n_pairs=16, grid=1 << 8)
+    strided = sum(len(wl.models[p[0]].param_sets)
+                  for k, p in enumerate(wl.pairs) if k % 2 == 0)
+    say("stress pre-filtered", len(wl.pairs), "strided units", strided)
+    got = hg.check_pairs(wl, prefilter=1)
+    want, _ = oracle.check_pairs(wl, "B", threads=8)
+    assert got == want
+    assert hg.default_context().stats()["prefiltered"] == strided
+    m = wl.models[0]
+    accs = list(m.accesses)
+    for k in range(1, len(accs), 2):
+        a = accs[k]
+        d = 1 if (k // 2) % 2 == 0 else -1
+        accs[k] = Access(a.array, a.kind, a.addr + c(d), a.guard, a.loops,
+                         a.bint, a.wint, a.scope, a.name)
+    m2 = Model(m.n_params, m.arrays, accs, m.launch, m.param_sets, loops=m.loops)
+    wl2 = Workload([m2], wl.pairs)
+    say("stress shifted pre-filtered")
+    got = hg.check_pairs(wl2, prefilter=1)
+    want, _ = oracle.check_pairs(wl2, "B", threads=8)
+    assert got == want
+    assert hg.default_context().stats()["prefiltered"] == 0
