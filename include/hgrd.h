@@ -178,7 +178,9 @@ typedef struct {
                           the term tables) do not meet, or their address
                           residues (every address = u + k G, G the gcd of
                           the table terms' known factors) admit no common
-                          value; 0: off */
+                          value, or (units of at least 2^18 points) the
+                          unions of their per-block address intervals do
+                          not meet; 0: off */
   uint32_t log_level;  /* 0 silent, 1 summary, 2 per-launch (stderr) */
   uint32_t lds_cap;    /* records per LDS join tile (1024, 1536 or 3072);
                           0 = the context's default (1024 until

@@ -927,6 +927,11 @@ struct Planner {
   // address residue, tables only: every address is congruent to `second`
   // modulo `first` (0: the single address `second`; 1: no information)
   std::vector<std::pair<uint64_t, int64_t>> ares;
+  // tables only: bounds of u plus the thread and iteration terms (a block's
+  // addresses lie in its block term plus these), and the block-term job
+  // (index into tjobs, -1: the address does not depend on the block)
+  std::vector<std::pair<int64_t, int64_t>> rrest;
+  std::vector<int32_t> bjob;
   std::vector<TabJob> tjobs;
   uint64_t tpool = 0;         // table entries
   bool use_tables = true;
@@ -1037,6 +1042,7 @@ struct Planner {
     if (entries > kMaxTabInst || tpool + entries > kMaxTabPool) return;
     T.base = tpool;
     for (TabJob& J : jobs) {
+      if (J.group == 0) bjob[inst] = (int32_t)tjobs.size();
       J.out_off = tpool;
       const uint32_t rel = (uint32_t)(tpool - T.base);
       if (J.group < 3) T.off[J.group] = rel;
@@ -1054,6 +1060,13 @@ struct Planner {
     uint64_t G = 0;
     for (const STerm& t : L.terms) G = gcd64(G, gmul(t.g, uabs64(t.mult)));
     ares[inst] = {G, (int64_t)L.u};
+    i128 rlo = L.u, rhi = L.u;
+    for (const STerm& t : L.terms)
+      if (t.group != 0) {
+        rlo += contrib_lo(t);
+        rhi += contrib_hi(t);
+      }
+    rrest[inst] = {(int64_t)rlo, (int64_t)rhi};
     // point order: iterations fastest when the address moves less along
     // them than along threads (consecutive points then share buckets)
     int64_t stride[3] = {0, 0, 0};
@@ -1212,6 +1225,8 @@ struct Planner {
     TabHost T;
     arange.push_back({0, -1});
     ares.push_back({1, 0});
+    rrest.push_back({0, -1});
+    bjob.push_back(-1);
     tables_for(m, a, I, (uint32_t)ii.idx, T);
     tabs.push_back(T);
     return ii;
@@ -1518,6 +1533,54 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   };
   std::vector<SItem> sitems;
   std::vector<HPlan> hplans;
+  // (3) of the pre-filter: per block, the addresses lie in the block term
+  // plus the bounds of the other terms; the unit is decided when the union
+  // of one access's block intervals misses the other's.  Only for large
+  // units (the block terms are evaluated here, one program run per block).
+  std::map<int32_t, std::vector<std::pair<int64_t, int64_t>>> bcache;
+  auto block_ranges = [&](int32_t x) -> const std::vector<std::pair<int64_t, int64_t>>* {
+    auto it = bcache.find(x);
+    if (it != bcache.end()) return &it->second;
+    std::vector<std::pair<int64_t, int64_t>> v;
+    const AccInst& I = P.dev_insts[x];
+    const TabJob& J = P.tjobs[P.bjob[x]];
+    const int64_t* pr = P.pool_params.data() + I.params_off;
+    const auto rest = P.rrest[x];
+    int64_t c[10];
+    bool ok = true;
+    for (uint32_t b = 0; b < I.nblk && ok; ++b) {
+      host_coords(I, P.pool_loops, b, 0, 0, c);
+      uint32_t err = 0;
+      const bool g = J.guard.absent || host_prog(P.code, J.guard, c, pr, 1, err) != 0;
+      const int64_t t = g && !J.val.absent ? host_prog(P.code, J.val, c, pr, 0, err) : 0;
+      if (err) ok = false;
+      if (g) v.push_back({t + rest.first, t + rest.second});
+    }
+    if (!ok) v.assign(1, {INT64_MIN, INT64_MAX});  // no claim
+    std::sort(v.begin(), v.end());
+    std::vector<std::pair<int64_t, int64_t>> m;
+    for (const auto& r : v) {
+      if (!m.empty() && r.first <= m.back().second) m.back().second = std::max(m.back().second, r.second);
+      else m.push_back(r);
+    }
+    return &(bcache[x] = std::move(m));
+  };
+  auto blocks_apart = [&](int32_t ia, int32_t ib) -> bool {
+    if (P.bjob[ia] < 0 || P.bjob[ib] < 0) return false;
+    const AccInst& A = P.dev_insts[ia];
+    const AccInst& B = P.dev_insts[ib];
+    if (A.nblk > (1u << 16) || B.nblk > (1u << 16)) return false;
+    if ((uint64_t)A.npts + B.npts < (1ull << 18)) return false;
+    const auto& x = *block_ranges(ia);
+    const auto& y = *block_ranges(ib);
+    size_t i = 0, j = 0;
+    while (i < x.size() && j < y.size()) {
+      if (x[i].second < y[j].first) ++i;
+      else if (y[j].second < x[i].first) ++j;
+      else return false;  // these intervals meet
+    }
+    return true;
+  };
   auto npts_of = [&](int32_t idx) -> uint64_t {
     return idx < 0 ? 0 : P.dev_insts[idx].npts;
   };
@@ -1570,6 +1633,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         // whole launch box (term-table bounds) do not meet.  (2) The
         // residues are incompatible: addresses of a are u_a + k G_a, of b
         // u_b + k G_b, and a common one needs gcd(G_a, G_b) | u_a - u_b.
+        // (3) The per-block intervals of a and b miss each other.
         const auto& ra = P.arange[ia];
         const auto& rb = P.arange[ib];
         const auto& ca = P.ares[ia];
@@ -1577,7 +1641,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         const uint64_t g = gcd64(ca.first, cb.first);
         const i128 du = (i128)ca.second - (i128)cb.second;
         const bool apart = g == 0 ? du != 0 : (du % (i128)g) != 0;
-        if (ra.second < rb.first || rb.second < ra.first || apart) {
+        if (ra.second < rb.first || rb.second < ra.first || apart ||
+            blocks_apart(ia, ib)) {
           ++plan->prefiltered;
           continue;
         }

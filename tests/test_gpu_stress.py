@@ -72,21 +72,20 @@ def test_stress_full_size(hg):
 
 
 def test_stress_prefilter_decides_near_misses(hg):
-    """Exact residue pre-filter: strided near misses (2f against 2f + 1)
-    share no residue modulo 2, so with the pre-filter on each of their
-    (pair, tuple) units is decided without enumeration; the blocked near
-    misses interleave block by block over the same address range and are
-    enumerated.  Every field stays equal to the oracle's.  The shifted
-    (racy) variant keeps every unit (residues and ranges then meet) and
+    """Exact pre-filters: strided near misses (2f against 2f + 1) share no
+    residue modulo 2; blocked ones interleave block by block over one
+    address range, and their per-block intervals miss each other.  With
+    the pre-filter on every (pair, tuple) unit is decided without
+    enumeration, and every field stays equal to the oracle's.  The shifted
+    (racy) variant keeps every unit (residues and intervals then meet) and
     equals the oracle's too."""
     wl = configs.stress(n_pairs=16, grid=1 << 8)
-    strided = sum(len(wl.models[p[0]].param_sets)
-                  for k, p in enumerate(wl.pairs) if k % 2 == 0)
-    say("stress pre-filtered", len(wl.pairs), "strided units", strided)
+    units = sum(len(wl.models[p[0]].param_sets) for p in wl.pairs)
+    say("stress pre-filtered", len(wl.pairs), "units", units)
     got = hg.check_pairs(wl, prefilter=1)
     want, _ = oracle.check_pairs(wl, "B", threads=8)
     assert got == want
-    assert hg.default_context().stats()["prefiltered"] == strided
+    assert hg.default_context().stats()["prefiltered"] == units
     m = wl.models[0]
     accs = list(m.accesses)
     for k in range(1, len(accs), 2):
