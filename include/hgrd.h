@@ -355,6 +355,17 @@ const char* rd_strerror(int status);
  * Returns 0 when they pass. */
 int rd_selftest(void);
 
+/* Host-only check of the exact pre-filter (rd_options.prefilter) on one
+ * (pair, tuple) unit: *decided = 1 when the unit of accesses access_a and
+ * access_b of `model` under tuple `set` would be decided without
+ * enumeration (the two accesses then share no address), else 0.  Returns
+ * RD_OK, 2 when an access has no instance for the tuple (errors, empty
+ * launch), or RD_EINVAL for bad arguments.  Touches no device. */
+int rd_prefilter_selftest(const rd_kernel_model* models, uint32_t n_models,
+                          const rd_launch_domain* launch, const rd_param_sets* params,
+                          uint32_t model, uint32_t access_a, uint32_t access_b,
+                          uint32_t set, uint32_t* decided);
+
 /* Host-side check of the term-table lowering of one access under one
  * parameter tuple (no device work): builds the tables as the device would,
  * then compares guard, address and interval ids at every point of the

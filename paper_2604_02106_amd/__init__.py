@@ -126,7 +126,8 @@ assert C.sizeof(rd_pair_result) == 88
 EXPORTS = ("rd_context_create", "rd_context_destroy", "rd_check_pairs",
            "rd_prepare", "rd_execute", "rd_plan_destroy", "rd_get_stats",
            "rd_strerror", "rd_selftest", "rd_tile_data", "rd_mlp_forward",
-           "rd_mlp_grad", "rd_mlp_train", "rd_autotune", "rd_table_selftest")
+           "rd_mlp_grad", "rd_mlp_train", "rd_autotune", "rd_table_selftest",
+           "rd_prefilter_selftest")
 
 _lib = None
 
@@ -181,6 +182,11 @@ def lib():
         L.rd_mlp_train.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_uint64, C.c_uint32, C.c_uint32, C.c_float,
                                    C.c_uint64, C.c_void_p, C.c_void_p]
+        L.rd_prefilter_selftest.restype = C.c_int
+        L.rd_prefilter_selftest.argtypes = [
+            C.POINTER(rd_kernel_model), C.c_uint32, C.POINTER(rd_launch_domain),
+            C.POINTER(rd_param_sets), C.c_uint32, C.c_uint32, C.c_uint32,
+            C.c_uint32, C.POINTER(C.c_uint32)]
         L.rd_table_selftest.restype = C.c_int
         L.rd_table_selftest.argtypes = [
             C.POINTER(rd_kernel_model), C.c_uint32, C.POINTER(rd_launch_domain),
@@ -402,6 +408,15 @@ def rd_autotune(ctx, workload, reps=3, mode=MODE_EXACT, order=ORDER_LEX,
     if st != RD_OK:
         raise RuntimeError("rd_autotune failed: %s" % rd_strerror(st))
     return best.lds_cap, best.max_device_bytes, ms.value
+
+
+def prefilter_selftest(workload, model, access_a, access_b, tuple_index, packed=None):
+    """rd_prefilter_selftest: (status, decided).  Host only."""
+    pk = packed or Packed(workload)
+    d = C.c_uint32()
+    st = lib().rd_prefilter_selftest(pk.models, pk.n_models, pk.launch, pk.params,
+                                     model, access_a, access_b, tuple_index, C.byref(d))
+    return st, d.value
 
 
 def table_selftest(workload, model, access, tuple_index, max_points=0, packed=None):

@@ -1231,6 +1231,73 @@ struct Planner {
     tabs.push_back(T);
     return ii;
   }
+
+  // Per-block address intervals of a table instance (sorted, merged): a
+  // block's addresses lie in its block term plus the bounds of the other
+  // terms (one program run per block).
+  std::map<int32_t, std::vector<std::pair<int64_t, int64_t>>> bcache;
+  const std::vector<std::pair<int64_t, int64_t>>& block_ranges(int32_t x) {
+    auto it = bcache.find(x);
+    if (it != bcache.end()) return it->second;
+    std::vector<std::pair<int64_t, int64_t>> v;
+    const AccInst& I = dev_insts[x];
+    const TabJob& J = tjobs[bjob[x]];
+    const int64_t* pr = pool_params.data() + I.params_off;
+    const auto rest = rrest[x];
+    int64_t c[10];
+    bool ok = true;
+    for (uint32_t b = 0; b < I.nblk && ok; ++b) {
+      host_coords(I, pool_loops, b, 0, 0, c);
+      uint32_t err = 0;
+      const bool g = J.guard.absent || host_prog(code, J.guard, c, pr, 1, err) != 0;
+      const int64_t t = g && !J.val.absent ? host_prog(code, J.val, c, pr, 0, err) : 0;
+      if (err) ok = false;
+      if (g) v.push_back({t + rest.first, t + rest.second});
+    }
+    if (!ok) v.assign(1, {INT64_MIN, INT64_MAX});  // no claim
+    std::sort(v.begin(), v.end());
+    std::vector<std::pair<int64_t, int64_t>> m;
+    for (const auto& r : v) {
+      if (!m.empty() && r.first <= m.back().second)
+        m.back().second = std::max(m.back().second, r.second);
+      else
+        m.push_back(r);
+    }
+    return bcache[x] = std::move(m);
+  }
+
+  // Exact pre-filter of a (pair, tuple) unit of two table instances: true
+  // when no address of one equals an address of the other.  (1) The address
+  // ranges over the whole launch box do not meet.  (2) The residues are
+  // incompatible: addresses of a are u_a + k G_a, of b u_b + k G_b, and a
+  // common one needs gcd(G_a, G_b) | u_a - u_b.  (3) For units of at least
+  // 2^18 points with at most 2^16 blocks per side: the unions of the
+  // per-block intervals miss each other.
+  bool apart(int32_t ia, int32_t ib) {
+    if (!tabs[ia].on || !tabs[ib].on) return false;
+    const auto& ra = arange[ia];
+    const auto& rb = arange[ib];
+    if (ra.second < rb.first || rb.second < ra.first) return true;
+    const auto& ca = ares[ia];
+    const auto& cb = ares[ib];
+    const uint64_t g = gcd64(ca.first, cb.first);
+    const i128 du = (i128)ca.second - (i128)cb.second;
+    if (g == 0 ? du != 0 : (du % (i128)g) != 0) return true;
+    if (bjob[ia] < 0 || bjob[ib] < 0) return false;
+    const AccInst& A = dev_insts[ia];
+    const AccInst& B = dev_insts[ib];
+    if (A.nblk > (1u << 16) || B.nblk > (1u << 16)) return false;
+    if ((uint64_t)A.npts + B.npts < (1ull << 18)) return false;
+    const auto& x = block_ranges(ia);
+    const auto& y = block_ranges(ib);
+    size_t i = 0, j = 0;
+    while (i < x.size() && j < y.size()) {
+      if (x[i].second < y[j].first) ++i;
+      else if (y[j].second < x[i].first) ++j;
+      else return false;  // these intervals meet
+    }
+    return true;
+  }
 };
 
 uint32_t class_mask(const rd_kernel_model& m, const rd_access& x,
@@ -1533,54 +1600,6 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   };
   std::vector<SItem> sitems;
   std::vector<HPlan> hplans;
-  // (3) of the pre-filter: per block, the addresses lie in the block term
-  // plus the bounds of the other terms; the unit is decided when the union
-  // of one access's block intervals misses the other's.  Only for large
-  // units (the block terms are evaluated here, one program run per block).
-  std::map<int32_t, std::vector<std::pair<int64_t, int64_t>>> bcache;
-  auto block_ranges = [&](int32_t x) -> const std::vector<std::pair<int64_t, int64_t>>* {
-    auto it = bcache.find(x);
-    if (it != bcache.end()) return &it->second;
-    std::vector<std::pair<int64_t, int64_t>> v;
-    const AccInst& I = P.dev_insts[x];
-    const TabJob& J = P.tjobs[P.bjob[x]];
-    const int64_t* pr = P.pool_params.data() + I.params_off;
-    const auto rest = P.rrest[x];
-    int64_t c[10];
-    bool ok = true;
-    for (uint32_t b = 0; b < I.nblk && ok; ++b) {
-      host_coords(I, P.pool_loops, b, 0, 0, c);
-      uint32_t err = 0;
-      const bool g = J.guard.absent || host_prog(P.code, J.guard, c, pr, 1, err) != 0;
-      const int64_t t = g && !J.val.absent ? host_prog(P.code, J.val, c, pr, 0, err) : 0;
-      if (err) ok = false;
-      if (g) v.push_back({t + rest.first, t + rest.second});
-    }
-    if (!ok) v.assign(1, {INT64_MIN, INT64_MAX});  // no claim
-    std::sort(v.begin(), v.end());
-    std::vector<std::pair<int64_t, int64_t>> m;
-    for (const auto& r : v) {
-      if (!m.empty() && r.first <= m.back().second) m.back().second = std::max(m.back().second, r.second);
-      else m.push_back(r);
-    }
-    return &(bcache[x] = std::move(m));
-  };
-  auto blocks_apart = [&](int32_t ia, int32_t ib) -> bool {
-    if (P.bjob[ia] < 0 || P.bjob[ib] < 0) return false;
-    const AccInst& A = P.dev_insts[ia];
-    const AccInst& B = P.dev_insts[ib];
-    if (A.nblk > (1u << 16) || B.nblk > (1u << 16)) return false;
-    if ((uint64_t)A.npts + B.npts < (1ull << 18)) return false;
-    const auto& x = *block_ranges(ia);
-    const auto& y = *block_ranges(ib);
-    size_t i = 0, j = 0;
-    while (i < x.size() && j < y.size()) {
-      if (x[i].second < y[j].first) ++i;
-      else if (y[j].second < x[i].first) ++j;
-      else return false;  // these intervals meet
-    }
-    return true;
-  };
   auto npts_of = [&](int32_t idx) -> uint64_t {
     return idx < 0 ? 0 : P.dev_insts[idx].npts;
   };
@@ -1634,15 +1653,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         // residues are incompatible: addresses of a are u_a + k G_a, of b
         // u_b + k G_b, and a common one needs gcd(G_a, G_b) | u_a - u_b.
         // (3) The per-block intervals of a and b miss each other.
-        const auto& ra = P.arange[ia];
-        const auto& rb = P.arange[ib];
-        const auto& ca = P.ares[ia];
-        const auto& cb = P.ares[ib];
-        const uint64_t g = gcd64(ca.first, cb.first);
-        const i128 du = (i128)ca.second - (i128)cb.second;
-        const bool apart = g == 0 ? du != 0 : (du % (i128)g) != 0;
-        if (ra.second < rb.first || rb.second < ra.first || apart ||
-            blocks_apart(ia, ib)) {
+        if (P.apart(ia, ib)) {
           ++plan->prefiltered;
           continue;
         }
@@ -2872,6 +2883,29 @@ int rd_mlp_train(rd_context* ctx, rd_mlp* w, const float* X, const float* Y,
   }
   TRY_HIP(hipMemcpyAsync(w, d.w, nw, hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
+  return RD_OK;
+}
+
+int rd_prefilter_selftest(const rd_kernel_model* models, uint32_t n_models,
+                          const rd_launch_domain* launch, const rd_param_sets* params,
+                          uint32_t model, uint32_t access_a, uint32_t access_b,
+                          uint32_t set, uint32_t* decided) {
+  if (!models || !launch || !params || !decided || model >= n_models) return RD_EINVAL;
+  const rd_kernel_model& M = models[model];
+  if (access_a >= M.n_acc || access_b >= M.n_acc || set >= params[model].n_sets)
+    return RD_EINVAL;
+  *decided = 0;
+  if (check_access(M, M.acc[access_a]) || check_access(M, M.acc[access_b])) return 2;
+  Planner P;
+  P.models = models;
+  P.launch = launch;
+  P.params = params;
+  P.dims.resize(n_models);
+  P.dims[model].resize(params[model].n_sets);
+  InstInfo& ia = P.inst(model, access_a, set);
+  InstInfo& ib = P.inst(model, access_b, set);
+  if (ia.err || ib.err || ia.idx < 0 || ib.idx < 0) return 2;
+  if (ia.idx != ib.idx) *decided = P.apart(ia.idx, ib.idx) ? 1u : 0u;
   return RD_OK;
 }
 
