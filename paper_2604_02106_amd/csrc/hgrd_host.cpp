@@ -1409,8 +1409,8 @@ struct rd_plan_impl {
   uint64_t evals = 0;
   uint32_t n_sitems = 0;
   uint32_t persist_grid = 0;  // workgroups of the persistent small join
-  uint32_t chunk_pts = 4096;  // points per partition workgroup
-  uint32_t run_buckets = 4;   // buckets per join workgroup
+  uint32_t chunk_pts = 16384; // points per partition workgroup
+  uint32_t run_buckets = 8;   // buckets per join workgroup
   uint32_t n_tabchunks = 0;   // term-table fill chunks
   uint64_t prefiltered = 0;   // (pair, tuple) units decided by the pre-filter
   uint32_t n_insts = 0, tab_insts = 0;
