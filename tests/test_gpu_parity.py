@@ -252,3 +252,25 @@ def test_prefilter_is_exact(hg):
         run_both(hg, wl, name, prefilter=1)
     st = hg.default_context().stats()
     say("prefiltered", st["prefiltered"])
+
+
+def test_batched_full_size_sampled(hg):
+    """The headline workload at full size (256 models x 16 pairs, seed 2002)
+    in the configuration bench.py times; a seeded random sample of pairs
+    whose domains the oracle enumerates in seconds (40 of at most 2^22
+    evaluations, 8 of 2^22..2^25, which take the HBM path) is compared with
+    the oracle field by field, and every status is OK."""
+    import numpy as np
+    wl = configs.batched(seed=2002)
+    say("batched full", len(wl.pairs))
+    got = hg.check_pairs(wl)
+    assert all(r["status"] == 0 for r in got)
+    rng = np.random.Generator(np.random.PCG64(11))
+    order = [int(k) for k in rng.permutation(len(wl.pairs))]
+    small = [k for k in order if got[k]["evals"] <= (1 << 22)][:40]
+    large = [k for k in order if (1 << 22) < got[k]["evals"] <= (1 << 25)][:8]
+    assert len(small) == 40 and len(large) == 8
+    idx = small + large
+    want, _ = oracle.check_pairs(wl.subset(idx), "B", threads=8)
+    compare([got[k] for k in idx], want, "batched full sample")
+    assert any(got[k]["verdict"] for k in idx)
