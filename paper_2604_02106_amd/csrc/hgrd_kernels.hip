@@ -187,9 +187,10 @@ __device__ __forceinline__ uint32_t bucket_of(const HItem& h, int64_t addr,
 
 // One workgroup takes one chunk of one side: it generates the points,
 // merges the chunk's records per bucket in LDS (open addressing on the
-// bucket id; each record gets its rank in its bucket from an LDS atomic),
-// reserves each bucket's run with one global atomic (all of a tile's
-// reservations in flight at once), then writes the runs.  Points follow
+// bucket id; a run of lanes holding one bucket claims the slot and its
+// ranks with one LDS atomic), reserves each bucket's run with one global
+// atomic (all of a tile's reservations in flight at once), then writes the
+// runs.  Points follow
 // address order closely (see iorder) and buckets keep blocks of 2^shift
 // addresses together, so a chunk touches few buckets and its writes are
 // runs of whole lines.  TAB: every instance of the launch has term tables
@@ -476,15 +477,10 @@ __global__ void k_apply_s0(uint32_t n, const L0Item* __restrict__ items,
 }
 
 // ---------------------------------------------------------------------------
-// Kernel: one workgroup per HBM bucket; load its records into LDS and join.
+// Kernel: join the records of HBM buckets in LDS.
 
 constexpr uint32_t kJoinThreads = 512;  // bucket-join workgroup size
 
-// One workgroup joins a run of buckets of one item.  The item's header
-// and query are loaded once per run; the next bucket's records are loaded
-// into registers while the current one is joined, and the counts are
-// committed once per run.  TAB: both instances of every item of the launch
-// have term tables (interval ids by lookup, no interpreter code).
 // Workgroups of the bucket join that the LDS of one CU holds (160 KiB):
 // the register budget of the table-path join is set so that as many fit by
 // registers too (the interpreter path keeps its registers: no spills).
@@ -493,6 +489,13 @@ constexpr uint32_t join_waves_per_simd() {
   return 2u * (uint32_t)(163840 / sizeof(JoinLds<CAP, TBL>));
 }
 
+// One workgroup joins a run of buckets of one item.  The item's header,
+// query and bucket counts are loaded once per run; the next bucket's
+// records are loaded into registers while the current one is joined; an
+// address pre-filter by signatures drops buckets (and records) that cannot
+// pair before any point id is decoded; the counts are committed once per
+// run.  TAB: both instances of every item of the launch have term tables
+// (interval ids by lookup, no interpreter code).
 template <int CAP, int TBL, bool TAB>
 __global__ void __launch_bounds__(kJoinThreads)
 __attribute__((amdgpu_waves_per_eu(TAB ? join_waves_per_simd<CAP, TBL>() : 1u)))
