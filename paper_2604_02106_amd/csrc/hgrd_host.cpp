@@ -43,6 +43,7 @@ constexpr int64_t kMaxBlock = 1024;
 constexpr int64_t kMaxGrid = 1ll << 26;
 constexpr int64_t kMaxPoints = 1ll << 31;
 constexpr uint32_t kChunkPts = 1024;
+constexpr uint32_t kL0ChunkPts = 8192;  // points per level-0 workgroup
 constexpr uint64_t kWaveBytes = 1536ull << 20;  // bucket bytes per partition wave
 constexpr uint64_t kFallbackRecords = 256ull << 20;
 constexpr uint64_t kMaxTabInst = 1ull << 24;  // table entries per instance
@@ -2402,8 +2403,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
         uint32_t idx = (uint32_t)l0.size();
         for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
           uint32_t np = plan->npts[side ? r.h.inst_j : r.h.inst_i];
-          for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
-            l0chunks.push_back({idx, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+          for (uint32_t p0 = 0; p0 < np; p0 += kL0ChunkPts)
+            l0chunks.push_back({idx, (uint32_t)side, p0, std::min(np, p0 + kL0ChunkPts)});
         }
         l0.push_back(li);
       }
