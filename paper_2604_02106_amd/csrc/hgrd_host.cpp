@@ -1426,6 +1426,8 @@ struct rd_plan_impl {
   std::vector<Wave> waves;
   std::vector<HItem> hitems;   // all waves, wave-local bucket numbering
   std::vector<uint64_t> hR;    // records bound per HBM item
+  std::vector<uint8_t> presplit;  // per HBM item: split by (address, block)
+                                  // without a first partition pass
   std::vector<uint8_t> herr_scan;  // error-scan-only items
   uint64_t max_key_bytes = 0, max_buckets = 0, max_items = 0;
   uint64_t wave_budget = 0;
@@ -1810,6 +1812,30 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   // tail); records cost 16 bytes of HBM traffic per point either way.
   const uint64_t budget = o.max_device_bytes ? o.max_device_bytes : ctx->wave_bytes;
   plan->wave_budget = budget;
+  // Global items whose addresses carry on average half a bucket of points
+  // or more overflow any bucket map (one address never spans buckets): they
+  // skip the first phase and go straight to the (address, block) split.
+  std::vector<HPlan> pre;
+  if (!plan->no_map) {
+    size_t w = 0;
+    for (size_t i = 0; i < hplans.size(); ++i) {
+      HPlan hp = hplans[i];
+      bool ps = false;
+      const uint32_t a = hp.h.inst_i, b = hp.h.inst_j;
+      if (hp.h.shared == 0 && tab_on[a] && tab_on[b]) {
+        const double lo = (double)std::min(P.arange[a].first, P.arange[b].first);
+        const double hi = (double)std::max(P.arange[a].second, P.arange[b].second);
+        if (hi >= lo && (double)hp.R >= (hi - lo + 1.0) * (cap / 2)) {
+          set_bucket_map(hp.h, tab_on, P.arange, P.dev_insts[a].nblk, Q[hp.h.q].qd.self,
+                         false, hp.R, cap, 0.6);
+          ps = hp.h.mode != 0;
+        }
+      }
+      if (ps) pre.push_back(hp);
+      else hplans[w++] = hplans[i];
+    }
+    hplans.resize(w);
+  }
   std::vector<Chunk> all_chunks;
   std::vector<BRun> all_runs;
   size_t pos = 0;
@@ -1848,6 +1874,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       uint32_t li = (uint32_t)plan->hitems.size();  // global item index
       plan->hitems.push_back(h);
       plan->hR.push_back(hplans[i].R);
+      plan->presplit.push_back(0);
       std::vector<BRun>& rdst =
           P.tabs[h.inst_i].on && P.tabs[h.inst_j].on ? all_runs : interp_runs;
       for (uint32_t b = 0; b < h.nbuckets; b += plan->run_buckets)
@@ -1875,6 +1902,13 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     plan->max_items = std::max<uint64_t>(plan->max_items, W.n_items);
     plan->waves.push_back(W);
     pos = end;
+  }
+  for (HPlan& hp : pre) {  // after every wave: no chunks, runs or buckets
+    hp.h.bucket0 = 0;
+    hp.h.rec_off = 0;
+    plan->hitems.push_back(hp.h);
+    plan->hR.push_back(hp.R);
+    plan->presplit.push_back(1);
   }
 
   // ---- upload descriptors -----------------------------------------------------
@@ -2325,7 +2359,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   std::vector<RItem> rit;
   std::vector<RItem> still;
   for (uint32_t i = 0; i < nh; ++i) {
-    if (!ovf[i] || plan->hitems[i].shared == 2) continue;
+    if ((!ovf[i] && !plan->presplit[i]) || plan->hitems[i].shared == 2) continue;
     RItem r{plan->hitems[i], plan->hR[i]};
     if (r.h.mode && r.h.shared == 0) {
       // a dense-map global item overflows only on heavy address groups,
