@@ -1812,8 +1812,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   // tail); records cost 16 bytes of HBM traffic per point either way.
   const uint64_t budget = o.max_device_bytes ? o.max_device_bytes : ctx->wave_bytes;
   plan->wave_budget = budget;
-  // Global items whose addresses carry on average half a bucket of points
-  // or more overflow any bucket map (one address never spans buckets): they
+  // Global items whose addresses carry on average a bucket of points or
+  // more overflow any bucket map (one address never spans buckets): they
   // skip the first phase and go straight to the (address, block) split.
   std::vector<HPlan> pre;
   if (!plan->no_map) {
@@ -1825,7 +1825,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       if (hp.h.shared == 0 && tab_on[a] && tab_on[b]) {
         const double lo = (double)std::min(P.arange[a].first, P.arange[b].first);
         const double hi = (double)std::max(P.arange[a].second, P.arange[b].second);
-        if (hi >= lo && (double)hp.R >= (hi - lo + 1.0) * (cap / 2)) {
+        if (hi >= lo && (double)hp.R >= (hi - lo + 1.0) * cap) {
           set_bucket_map(hp.h, tab_on, P.arange, P.dev_insts[a].nblk, Q[hp.h.q].qd.self,
                          false, hp.R, cap, 0.6);
           ps = hp.h.mode != 0;
