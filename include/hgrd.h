@@ -305,6 +305,8 @@ typedef struct {
                                  (k_bucket_join with term tables) */
   double join_tab_ms;        /* their summed duration */
   uint64_t join_tab_bytes;   /* record bytes they read */
+  uint64_t presplit_items;   /* items sent to the (address, block) split
+                                without a first partition pass */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

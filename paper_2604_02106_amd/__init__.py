@@ -118,7 +118,8 @@ class rd_stats(C.Structure):
                 ("scatter_bytes", C.c_uint64), ("fallback_records", C.c_uint64),
                 ("scatter_tab_ms", C.c_double), ("scatter_tab_bytes", C.c_uint64),
                 ("prefiltered", C.c_uint64), ("join_tab_launches", C.c_uint64),
-                ("join_tab_ms", C.c_double), ("join_tab_bytes", C.c_uint64)]
+                ("join_tab_ms", C.c_double), ("join_tab_bytes", C.c_uint64),
+                ("presplit_items", C.c_uint64)]
 
 
 assert C.sizeof(rd_pair_result) == 88

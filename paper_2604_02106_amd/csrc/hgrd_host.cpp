@@ -2397,6 +2397,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   std::vector<RItem> split_all, direct;
   for (auto& r : still) (r.h.shared == 0 ? split_all : direct).push_back(r);
   S.split_items = split_all.size();
+  S.presplit_items = 0;
+  for (uint8_t f : plan->presplit) S.presplit_items += f;
   for (size_t sp0 = 0; sp0 < split_all.size();) {
     std::vector<RItem> split;
     uint64_t bslots = 0;

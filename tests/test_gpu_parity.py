@@ -10,7 +10,7 @@ import sys
 import pytest
 
 import oracle
-from workloads import (Access, Array, Launch, Loop, Model, Workload, c, param,
+from workloads import (Access, Array, Launch, Loop, Model, Workload, c, param, emin,
                        tid, bid, bdim, loop, div, lt, GLOBAL, SHARED, WRITE,
                        READ, ATOMIC, SCOPE_BLOCK)
 from workloads import families as F, configs
@@ -141,6 +141,25 @@ def test_skew_paths(hg):
     st = H.default_context().stats()
     say("skew stats", {k: st[k] for k in ("retry_items", "split_items", "overflow_items")})
     assert st["split_items"] > 0 and st["overflow_items"] > 0
+    assert st["presplit_items"] > 0  # tid % 8 over 96 blocks: routed at once
+
+
+def test_overflow_then_split(hg):
+    """Addresses that average far below a bucket of points but hold hot
+    spots (every thread from 8 on shares one address per block, 4
+    iterations): the item is partitioned first, overflows, and is split by
+    (address, block); counts and witnesses equal the oracle's."""
+    m = Model(0, [Array(GLOBAL, 32)],
+              [Access(0, WRITE, emin(tid(), c(8)) + bid() * 16, loops=[0]),
+               Access(0, READ, emin(tid(), c(8)) + bid() * 16 + loop(0) * 0, loops=[0])],
+              Launch((64, 1, 1), (256, 1, 1), 32), [[]],
+              loops=[Loop(0, "lt", 4)])
+    wl = Workload([m], [(0, 0, 0, 7), (0, 0, 1, 7), (0, 1, 0, 6)])
+    run_both(hg, wl, "overflow then split")
+    st = hg.default_context().stats()
+    say("overflow stats", {k: st[k] for k in ("presplit_items", "split_items",
+                                               "retry_items", "overflow_items")})
+    assert st["presplit_items"] == 0 and st["split_items"] > 0
 
 
 def test_statuses(hg):
