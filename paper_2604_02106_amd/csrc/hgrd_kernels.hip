@@ -98,7 +98,9 @@ k_small_join(const SItem* __restrict__ items, const DevInst* __restrict__ insts,
 }
 
 // Persistent form: a grid sized to the machine pops items (largest first,
-// as the host orders them) from a work counter until none is left.
+// as the host orders them) from a work counter until none is left, a few
+// at a time (one counter round trip per kSmallPop items).
+constexpr uint32_t kSmallPop = 4;
 template <int CAP, int TBL>
 __global__ void __launch_bounds__(256)
 k_small_persist(const SItem* __restrict__ items, uint32_t n,
@@ -110,13 +112,16 @@ k_small_persist(const SItem* __restrict__ items, uint32_t n,
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
   __shared__ uint32_t cur;
   for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(cursor, 1u);
+    if (threadIdx.x == 0) cur = atomicAdd(cursor, kSmallPop);
     __syncthreads();
-    const uint32_t k = cur;
+    const uint32_t k0 = cur;
     __syncthreads();
-    if (k >= n) break;
-    small_item(S, items[k], insts, code, params, loopvals, qd, acc, done);
-    __syncthreads();
+    if (k0 >= n) break;
+    const uint32_t k1 = min(n, k0 + kSmallPop);
+    for (uint32_t k = k0; k < k1; ++k) {
+      small_item(S, items[k], insts, code, params, loopvals, qd, acc, done);
+      __syncthreads();
+    }
   }
 }
 
