@@ -43,7 +43,8 @@ constexpr int64_t kMaxBlock = 1024;
 constexpr int64_t kMaxGrid = 1ll << 26;
 constexpr int64_t kMaxPoints = 1ll << 31;
 constexpr uint32_t kChunkPts = 1024;
-constexpr uint32_t kL0ChunkPts = 8192;  // points per level-0 workgroup
+constexpr uint32_t kL0ChunkPts = 8192;  // points per level-0 and fallback
+                                        // generation workgroup
 constexpr uint64_t kWaveBytes = 1536ull << 20;  // bucket bytes per partition wave
 constexpr uint64_t kFallbackRecords = 256ull << 20;
 constexpr uint64_t kMaxTabInst = 1ull << 24;  // table entries per instance
@@ -2549,8 +2550,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       const FItem& f = fall[fpos + i];
       for (int side = 0; side < (f.self ? 1 : 2); ++side) {
         uint32_t np = plan->npts[side ? f.inst_j : f.inst_i];
-        for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
-          chunks.push_back({i, (uint32_t)side, p0, std::min(np, p0 + kChunkPts)});
+        for (uint32_t p0 = 0; p0 < np; p0 += kL0ChunkPts)
+          chunks.push_back({i, (uint32_t)side, p0, std::min(np, p0 + kL0ChunkPts)});
       }
     }
     uint64_t tbl = 1;
