@@ -287,7 +287,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc,
                    "queries": n, "evals_per_step": evals, "racy": racy,
-                   "scale": args.scale, "wave_mib": args.wave_mib or 1536},
+                   "scale": args.scale, "wave_mib": args.wave_mib or 3072},
         "evals_per_s_G": evals * args.steps / dt / 1e9,
         "end_to_end_queries_per_s": n / e2e_s,
         "graph_replay_queries_per_s": n * args.steps / dt_graph if dt_graph else None,

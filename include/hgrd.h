@@ -189,7 +189,7 @@ typedef struct {
                           the exact path; 0 = 256 */
   const rd_mlp* mlp;   /* weights for RD_ORDER_MLP (copied at prepare) */
   uint64_t max_device_bytes; /* HBM bucket bytes per partition wave;
-                                0 = the context's default (1536 MiB until
+                                0 = the context's default (3072 MiB until
                                 rd_autotune picks one) */
   void* stream;        /* hipStream_t every launch goes to; NULL = a
                           stream the context owns */
@@ -260,7 +260,7 @@ void rd_plan_destroy(rd_plan* plan);
 
 /* Batch autotuning: for the batch given (as rd_prepare), times rd_execute
  * for every LDS tile shape (1024, 1536, 3072 records) and partition-wave
- * size (384, 1536, 6144 MiB): one warm-up and `reps` timed runs each (1..16),
+ * size (768, 3072, 12288 MiB): one warm-up and `reps` timed runs each (1..16),
  * median wall time.  The fastest pair becomes the context's default for
  * plans whose options leave lds_cap and max_device_bytes at 0.  *best is a
  * copy of opt (or of zeroed options) with those two fields set; *best_ms

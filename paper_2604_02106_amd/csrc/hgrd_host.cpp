@@ -45,7 +45,7 @@ constexpr int64_t kMaxPoints = 1ll << 31;
 constexpr uint32_t kChunkPts = 1024;
 constexpr uint32_t kL0ChunkPts = 8192;  // points per level-0 and fallback
                                         // generation workgroup
-constexpr uint64_t kWaveBytes = 1536ull << 20;  // bucket bytes per partition wave
+constexpr uint64_t kWaveBytes = 3072ull << 20;  // bucket bytes per partition wave
 constexpr uint64_t kFallbackRecords = 256ull << 20;
 constexpr uint64_t kMaxTabInst = 1ull << 24;  // table entries per instance
 constexpr uint64_t kMaxTabPool = 1ull << 33;  // table entries per plan (64 GiB)
