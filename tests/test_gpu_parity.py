@@ -237,7 +237,7 @@ def test_autotune_picks_a_shape_and_keeps_results(hg):
     say("autotune")
     cap, wave, ms = hg.rd_autotune(ctx, wl, reps=1)
     say("autotune picked", cap, wave, ms)
-    assert cap in (1024, 1536, 3072) and wave in (384 << 20, 1536 << 20, 6144 << 20)
+    assert cap in (1024, 1536, 3072) and wave in (768 << 20, 3072 << 20, 12288 << 20)
     assert ms > 0
     want, _ = oracle.check_pairs(wl, "B", threads=8)
     compare(hg.rd_check_pairs(ctx, wl), want, "after autotune")
