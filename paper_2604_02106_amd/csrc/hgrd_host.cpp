@@ -2266,8 +2266,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   collect_waves();
 
   // ---- re-partition overflowed items ---------------------------------------
-  // Round 1 retries with more buckets (bucket loads vary with how many points
-  // share an address).  Round 2 splits global items by (address, block) into
+  // The first step retries with more buckets (bucket loads vary with how many points
+  // share an address).  The second splits global items by (address, block) into
   // bigger tiles, counting level 0 in address-count tables.  What still
   // overflows goes to the HBM fallback.
   struct RItem {
@@ -2393,7 +2393,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       if (rovf[i]) still.push_back(rit[i]);
   }
 
-  // round 2: split global items by (address, block); level 0 in tables,
+  // second step: split global items by (address, block); level 0 in tables,
   // in batches whose address-count tables stay within kL0Slots
   std::vector<RItem> split_all, direct;
   for (auto& r : still) (r.h.shared == 0 ? split_all : direct).push_back(r);
