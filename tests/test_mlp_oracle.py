@@ -1,7 +1,9 @@
-"""Pins of the float64 tile-scoring network reference: the analytic gradient
+"""Pins of the float64 tile-scoring network reference: forward, loss and
+gradient agree with torch float64 autograd; the analytic gradient
 agrees with central finite differences; the loss is the textbook binary
 cross-entropy of sigmoid(z); a step against the gradient lowers the loss."""
 import numpy as np
+import pytest
 
 from oracle import mlp
 
@@ -45,3 +47,43 @@ def test_descent_step_lowers_loss():
     g = mlp.grad(p, X, y)
     q = {k: p[k] - 0.05 * g[k] for k in p}
     assert mlp.loss(q, X, y) < l0
+
+
+def _torch_loss(p, X, y):
+    """The same network written with torch's own layers and loss, float64:
+    F.linear(x, W, b) = x W^T + b (output-major W), relu, and
+    binary_cross_entropy_with_logits (mean)."""
+    import torch
+    import torch.nn.functional as Fn
+    t = {k: torch.tensor(np.atleast_1d(v), dtype=torch.float64,
+                         requires_grad=True) for k, v in p.items()}
+    Xt = torch.tensor(X, dtype=torch.float64)
+    yt = torch.tensor(y, dtype=torch.float64)
+    h1 = torch.relu(Fn.linear(Xt, t["W1"], t["b1"]))
+    h2 = torch.relu(Fn.linear(h1, t["W2"], t["b2"]))
+    z = Fn.linear(h2, t["w3"].reshape(1, -1), t["b3"]).reshape(-1)
+    loss = Fn.binary_cross_entropy_with_logits(z, yt)
+    loss.backward()
+    return z.detach().numpy(), float(loss), {k: v.grad.numpy() for k, v in t.items()}
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_matches_torch_autograd(seed):
+    """forward, loss and every gradient against torch float64 autograd (an
+    implementation of the same textbook network that shares nothing with the
+    reference)."""
+    pytest.importorskip("torch")
+    p = mlp.init(seed)
+    # non-zero biases so that their layout and broadcast are exercised
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(0, 0.1, p[k].shape)
+    X, y = _data(96, seed)
+    z_t, l_t, g_t = _torch_loss(p, X, y)
+    z, _ = mlp.forward(p, X)
+    assert np.allclose(z, z_t, rtol=1e-10, atol=1e-12)
+    assert abs(mlp.loss(p, X, y) - l_t) <= 1e-10 * max(1.0, abs(l_t))
+    g = mlp.grad(p, X, y)
+    for k in g:
+        assert np.allclose(np.atleast_1d(g[k]), g_t[k].reshape(np.shape(np.atleast_1d(g[k]))),
+                           rtol=1e-10, atol=1e-12), k

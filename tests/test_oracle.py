@@ -397,3 +397,52 @@ def test_statuses():
     # an empty launch (a zero extent) has no points
     r = _one([Access(0, WRITE, c(0))], (0, 0), launch=Launch((param(0) - 3, 1, 1), (8, 1, 1)))
     assert r["status"] == 0 and r["verdict"] == 0
+
+
+@pytest.mark.parametrize("G,B,w", [(4, 64, 32), (3, 32, 8), (2, 16, 4)])
+def test_f1_in_loop_interval_ids(G, B, w):
+    """F1 inside a two-iteration loop i in {0, 1} whose addresses do not
+    depend on i; each conflicting thread pair of F1 then meets in 2 x 2
+    iteration pairs.  Derived by hand:
+      * wint = i, bint constant: inter-block ignores barriers (4 (G - 1));
+        intra-block needs equal bint only (4 G (B/w - 1)); intra-warp also
+        needs equal wint, so only i_p = i_q (2 G (B - B/w)).  Witness: p =
+        (b0, t1, i0) with q = (b0, t0, i0), same warp, equal wint.
+      * bint = i (a block barrier in the loop body): intra-block and
+        intra-warp both need i_p = i_q: [4 (G - 1), 2 G (B/w - 1),
+        2 G (B - B/w)]."""
+    g = bid(0) * bdim(0) + tid(0)
+    lp = [Loop(0, "lt", 2)]
+    for kw, want in (({"wint": loop(0)},
+                      [4 * (G - 1), 4 * G * (B // w - 1), 2 * G * (B - B // w)]),
+                     ({"bint": loop(0)},
+                      [4 * (G - 1), 2 * G * (B // w - 1), 2 * G * (B - B // w)])):
+        m = Model(0, [Array(GLOBAL, 32)],
+                  [Access(0, WRITE, g, None, [0], **kw),
+                   Access(0, WRITE, g + 1, None, [0], **kw)],
+                  Launch((G, 1, 1), (B, 1, 1), w), [[]], loops=lp)
+        r = both(Workload([m], [(0, 0, 1, 7)]))[0]
+        assert r["status"] == 0
+        assert r["by_class"] == want, (kw, r)
+        assert r["count"] == sum(want)
+        assert r["witness"] == (0, 0, 1, 0, 0, 0, 0)
+        assert r["witness_class"] == INTRA_WARP and r["w_addr"] == 1
+
+
+def test_error_precedence_five_loops():
+    """Status precedence (EINVAL > EUNSUPPORTED > EDIVZERO > ERANGE over the
+    errors of a pair), with one reading for an access that lists more loops
+    than the interface's four slots: that access is EUNSUPPORTED as a whole
+    (its loop list cannot be described, so its expressions, which may name
+    those loops, are not examined); the other access and the pair itself are
+    still examined, and an EINVAL there wins."""
+    loops = [Loop(0, "lt", 2)] * 5
+    five = Access(0, WRITE, E([("const", 1), ("add",)]), loops=[0, 1, 2, 3, 4])
+    ok = Access(0, WRITE, tid())
+    bad = Access(0, WRITE, E([("const", 1), ("add",)]))
+    assert _one([five], (0, 0), loops=loops)["status"] == -2
+    assert _one([five, ok], (0, 1), loops=loops)["status"] == -2
+    assert _one([five, bad], (0, 1), loops=loops)["status"] == -1
+    # a pair across arrays is EINVAL whatever the accesses hold
+    other = Access(1, WRITE, tid())
+    assert _one([five, other], (0, 1), loops=loops)["status"] == -1

@@ -119,6 +119,18 @@ def _log_uniform_int(rng, lo, hi):
     return int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
 
 
+def _host_widths(bx, gx, n):
+    """At least n distinct candidate widths a host program derives: powers
+    of two up to 128, then multiples of the block row width bx and the grid
+    row width bx * gx."""
+    out = [1, 2, 4, 8, 16, 32, 64, 128]
+    k = 1
+    while len(set(out)) < n or k <= 8:
+        out += [bx * k, bx * gx * k]
+        k += 1
+    return sorted(set(out))
+
+
 def batched(seed=2002, n_models=256, pairs_per_model=16, max_grid=1024,
             max_iters=64, max_sets=16, scale=1.0):
     """256 models x 16 pairs = 4096 queries of uneven size.
@@ -126,7 +138,7 @@ def batched(seed=2002, n_models=256, pairs_per_model=16, max_grid=1024,
     Per model: grid log-uniform in [1, max_grid] blocks (1-D or 2-D), block
     of 32..256 threads (1-D or 2-D), one loop of 1..max_iters iterations,
     parameters (W, N) as joint tuples from a host-derived set of 1..16
-    values (W a power of two or a multiple of the row width, N derived from
+    distinct values (W a power of two or a multiple of the row width, N derived from
     W: host class 3).  Address terms: tid/32, tid % W, row*W + col, affine
     in the global thread id and the loop variable.  Guards tid < N - k.
     int32 addresses.  Shared and global arrays alternate by model.  About
@@ -154,10 +166,11 @@ def batched(seed=2002, n_models=256, pairs_per_model=16, max_grid=1024,
         iters = max(1, _log_uniform_int(rng, 1, max_iters))
         space = SHARED if mi % 2 == 1 else GLOBAL
         nsets = int(rng.integers(1, max_sets + 1))
-        # host-derived parameter set: W from powers of two or row widths,
-        # N derived jointly from W (one host variable feeds both)
-        Ws = sorted(set(int(x) for x in rng.choice(
-            [1, 2, 4, 8, 16, 32, 64, 128, bx, bx * gx], size=nsets)))
+        # host-derived parameter set: nsets distinct W from powers of two and
+        # multiples of the row width, N derived jointly from W (one host
+        # variable feeds both)
+        Ws = sorted(int(x) for x in rng.choice(
+            _host_widths(bx, gx, max_sets), size=nsets, replace=False))
         sets = [[w, w * int(rng.integers(1, 5)) + bt // 2] for w in Ws]
         W, Np = param(0), param(1)
         row = bid(1) * bdim(1) + tid(1)
@@ -315,63 +328,82 @@ def sparse(seed=4004, n_queries=16384, G=256, B=256, racy_frac=0.5,
 # mixed: many queries of log-uniform domain size
 
 def mixed(seed=5005, n_queries=100000, log2_min=8, log2_max=28, racy_frac=0.10,
-          queries_per_model=16, max_sets=64):
+          queries_per_model=16, max_sets=64, self_frac=0.125):
     """Queries whose domain (points of one access over all its tuples) is
-    log-uniform in [2^log2_min, 2^log2_max]; 2-D and 3-D launches;
-    global and shared arrays mixed (one in three models shared); 1..max_sets
-    parameter tuples (W, N) per model derived from one host variable; about
-    10% of pairs planted racy (a non-injective map on both sides), the rest
-    race-free by an injective map with the two sides' ranges separated.
+    log-uniform in [2^log2_min, 2^log2_max] (mean about 1.94e7 points for
+    2^8..2^28, so about 3.9e12 evals for 100 000 queries); 2-D and 3-D
+    launches; global and shared arrays half and half (a quarter of the global
+    models on 64-bit arrays with bases of 2^33 and more); 1..max_sets
+    distinct parameter tuples (W, N) per model derived from one host
+    variable.  About racy_frac of the pairs are planted racy (a
+    non-injective map on both sides); the others are race-free in one of
+    three ways, a third each:
+
+      * near miss by range: the second access is the first shifted by the
+        exact size of its range (adjacent ranges, one element apart);
+      * interleaved: 2 f and 2 f + 1 for an injective f (ranges overlap,
+        residues differ);
+      * own element: both accesses (or a self-pair) use the same injective
+        map, so every address is reached by one point only and only a
+        thread meets itself; no range or residue test decides these, the
+        join has to run down to the thread level.
+
     Address forms are those of ``batched`` over the linear thread id, the
     linear block id and the loop variable.  Labels come from the oracle.
+    meta["evals"] holds each pair's evals (box points of both sides over
+    all tuples, a self-pair twice), known here from the launch constants.
     """
     rng = _rng(seed)
-    models, pairs, sizes = [], [], []
+    models, pairs, evals = [], [], []
+    lo, hi = np.log(2.0 ** log2_min), np.log(2.0 ** log2_max)
     q = 0
     while q < n_queries:
         nsets = int(rng.integers(1, max_sets + 1))
-        L = int(round(rng.uniform(log2_min, log2_max) - np.log2(nsets)))
-        L = max(L, min(log2_min, 5))
-        space = SHARED if len(models) % 3 == 2 else GLOBAL
-        # block: 2-D or 3-D, 32..1024 threads
+        D = float(np.exp(rng.uniform(lo, hi)))      # points per access, all tuples
+        space = SHARED if len(models) % 2 == 1 else GLOBAL
+        wide = space == GLOBAL and rng.random() < 0.25
+        # block: 2-D or 3-D, 8..1024 threads
         bx = int(rng.choice([8, 16, 32, 64]))
         by = int(rng.choice([1, 2, 4, 8]))
-        bz = int(rng.choice([1, 1, 2, 4])) if rng.random() < 0.4 else 1
+        bz = int(rng.choice([1, 2, 4])) if rng.random() < 0.4 else 1
         while bx * by * bz > 1024:
             bz = max(1, bz // 2)
             by = max(1, by // 2)
         bt = bx * by * bz
-        lb = int(np.log2(bt))
-        iters = 1 << int(rng.integers(0, max(1, min(6, L - lb)) + 1))
-        nblk = max(1, (1 << L) // (bt * iters))
-        if space == SHARED:
-            nblk = min(nblk, 1 << 16)
+        per_set = max(1.0, D / nsets)
+        imax = int(np.clip(np.floor(np.log2(max(1.0, per_set / bt))), 0, 6))
+        iters = 1 << int(rng.integers(0, imax + 1))
+        nblk = max(1, int(round(per_set / (bt * iters))))
         three = rng.random() < 0.3 and nblk >= 8
         if three:
-            gz = 1 << int(rng.integers(0, 3))
-            gx = max(1, nblk // (gz * 2))
-            gy = max(1, nblk // (gx * gz))
+            gz = 1 << int(rng.integers(1, 3))
+            gx = 1 << int(rng.integers(0, max(1, int(np.log2(nblk // gz)))))
+            gy = max(1, int(round(nblk / (gx * gz))))
         elif rng.random() < 0.5 and nblk >= 4:
             gx = 1 << int(rng.integers(1, max(2, int(np.log2(nblk)))))
             gx = min(gx, nblk)
-            gy, gz = max(1, nblk // gx), 1
+            gy, gz = max(1, int(round(nblk / gx))), 1
         else:
             gx, gy, gz = nblk, 1, 1
         nb = gx * gy * gz
-        Ws = sorted(set(int(x) for x in rng.choice(
-            [1, 2, 4, 8, 16, 32, 64, bx, bx * gx, 3, 5], size=nsets)))
+        Ws = sorted(int(x) for x in rng.choice(
+            _host_widths(bx, gx, max_sets), size=nsets, replace=False))
         sets = [[w, w * int(rng.integers(1, 5)) + bt // 2] for w in Ws]
         W, Np = param(0), param(1)
         tl = tid(0) + bdim(0) * (tid(1) + bdim(1) * tid(2))
         blin = bid(0) + c(gx) * (bid(1) + c(gy) * bid(2))
         gid = blin * bt + tl
         i = loop(0)
-        span = nb * bt * iters * 2 + 4096
+        rng_size = (nb if space == GLOBAL else 1) * bt * iters  # range of e_ok
+        base = (1 << 33) + int(rng.integers(0, 1 << 20)) * (1 << 24) if wide else 0
+        box = nb * bt * iters
         accs = []
         nq = min(queries_per_model, n_queries - q)
         for k in range(nq):
             racy = rng.random() < racy_frac
+            selfp = rng.random() < self_frac
             form = int(rng.integers(0, 3))
+            how = int(rng.integers(0, 3))
             guard = lt(tl, Np - int(rng.integers(0, 4))) if rng.random() < 0.3 else None
             if space == SHARED:
                 e_ok = [tl * iters + i, tl + bt * i, tl * 2 + i * (2 * bt)][form]
@@ -380,23 +412,33 @@ def mixed(seed=5005, n_queries=100000, log2_min=8, log2_max=28, racy_frac=0.10,
                 e_ok = [gid * iters + i, gid + c(nb * bt) * i,
                         blin * (bt * iters) + tl * iters + i][form]
                 e_bad = [gid // 32 + i * 4, tl % W + blin * W + i, tl + i * 16][form]
+            if base:
+                e_ok, e_bad = c(base) + e_ok, c(base) + e_bad
             kinds = [(WRITE, WRITE), (WRITE, READ), (READ, WRITE)]
             ka, kb = kinds[int(rng.integers(0, 3))]
+            if selfp:
+                accs.append(Access(0, WRITE, e_bad if racy else e_ok, guard, [0]))
+                a = len(accs) - 1
+                pairs.append((len(models), a, a, ALL_CLASSES))
+                evals.append(2 * nsets * box)
+                continue
             if racy:
                 ea, eb = e_bad, e_bad
+            elif how == 0:
+                ea, eb = e_ok, e_ok + rng_size
+            elif how == 1:
+                ea, eb = e_ok * 2 - c(base), e_ok * 2 - c(base) + 1
             else:
-                sep = int(rng.integers(2, 6)) * (span if space == GLOBAL
-                                                 else 2 * bt * iters + 4096)
-                ea, eb = e_ok, e_ok + sep
+                ea, eb = e_ok, e_ok
             accs.append(Access(0, ka, ea, guard, [0]))
             accs.append(Access(0, kb, eb, guard, [0]))
             pairs.append((len(models), len(accs) - 2, len(accs) - 1, ALL_CLASSES))
+            evals.append(2 * nsets * box)
         q += nq
-        models.append(Model(2, [Array(space, 32)], accs,
+        models.append(Model(2, [Array(space, 64 if wide else 32)], accs,
                             Launch((gx, gy, gz), (bx, by, bz), 32), sets,
                             loops=[Loop(0, "lt", iters, "add", 1)],
                             name="mixed%d" % len(models)))
-        sizes.append(nb * bt * iters * len(sets))
     return Workload(models, pairs, name="mixed",
                     meta={"seed": seed, "log2": (log2_min, log2_max),
-                          "sizes": sizes})
+                          "evals": evals})
