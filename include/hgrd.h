@@ -147,6 +147,75 @@ typedef struct {
   const int64_t* values;
 } rd_param_sets;
 
+/* ---- host domain (section 4, classes 1-5; section 6.3, Figure 8) ------
+ * What the host code of a program fixes about a launch, written as host
+ * variables and conditions, expanded into the finite parameter tuples that
+ * rd_check_pairs takes.  The five classes of host facts map as follows:
+ *   class 1 (asserts)           : `asserts`, conditions that hold in every
+ *                                 execution (assignments where one is 0 are
+ *                                 dropped);
+ *   class 2 (grid dimensions)   : `params` columns that the model's launch
+ *                                 domain reads as parameters (e.g. a column
+ *                                 hWidth / 16 used as gridDim.x);
+ *   class 3 (shared variables)  : several `params` columns computed from one
+ *                                 host variable keep their relation, since
+ *                                 every tuple comes from one assignment;
+ *   class 4 (host loop bounds)  : RD_HV_LOOP variables, one value per
+ *                                 iteration of the host loop;
+ *   class 5 (allocation sizes)  : `alloc_sizes`, sizes of allocations the
+ *                                 host makes, positive in every execution
+ *                                 (assignments where one is <= 0 are
+ *                                 dropped).
+ * Host variables are listed in program order.  Their expressions (and the
+ * asserts, sizes and parameter columns) live in `insns` and may use only
+ * RD_OP_CONST, RD_OP_PARAM k (the value of host variable k, k below the
+ * variable's own index; any k below n_vars elsewhere) and the operators. */
+enum {
+  RD_HV_INPUT = 0, /* an input the program reads: takes each of
+                      values[0 .. n_values) in turn (the caller's finite
+                      stand-in for an unknown value) */
+  RD_HV_EXPR = 1,  /* computed from earlier variables: `init` */
+  RD_HV_LOOP = 2   /* the iterator of a host loop, for (v = init; v <cmp>
+                      bound; v = v <upd> step), init/bound/step over earlier
+                      variables, at most 65536 iterations (cmp and upd as
+                      for rd_loop) */
+};
+
+typedef struct {
+  uint32_t kind;            /* RD_HV_* */
+  uint32_t cmp, upd;        /* RD_HV_LOOP */
+  uint32_t n_values;        /* RD_HV_INPUT */
+  const int64_t* values;    /* RD_HV_INPUT */
+  rd_expr init, bound, step;
+} rd_host_var;
+
+typedef struct {
+  const rd_insn* insns; uint32_t n_insns;
+  const rd_host_var* vars; uint32_t n_vars;
+  const rd_expr* asserts; uint32_t n_asserts;
+  const rd_expr* alloc_sizes; uint32_t n_alloc;
+  const rd_expr* params; uint32_t n_params;  /* one column per kernel
+                                                parameter */
+} rd_host_domain;
+
+/* Enumerates every assignment of the host variables (inputs over their
+ * values, loop iterators over their iterations, nested in program order,
+ * the first variable outermost), keeps those whose asserts are all nonzero
+ * and allocation sizes all positive, and evaluates the parameter columns
+ * of each.  Equal tuples are kept once (the first), in enumeration order.
+ * out->n_sets = the number of distinct tuples, out->values = buf (row-major,
+ * n_params values per tuple).  Host-only; no device work.
+ * Returns RD_OK; RD_ECAPACITY when n_sets x n_params exceeds cap_values
+ * (out->n_sets still holds the count needed, buf holds the first tuples
+ * that fit); RD_EINVAL for a NULL or malformed argument (a leaf other than
+ * CONST or PARAM, a variable read before it is set, a bad kind, cmp or
+ * upd); RD_EUNSUPPORTED for more than 65536 iterations of one host loop,
+ * more than 2^24 assignments, or expressions over the limits of model
+ * expressions; RD_EDIVZERO or RD_ERANGE when an expression divides by zero
+ * or overflows in some assignment (the host program would fail there). */
+int rd_expand_host_domain(const rd_host_domain* h, rd_param_sets* out,
+                          int64_t* buf, uint64_t cap_values);
+
 /* Race classes (Table 2). */
 enum { RD_INTER = 1, RD_INTRA_BLOCK = 2, RD_INTRA_WARP = 4 };
 
@@ -350,6 +419,16 @@ int rd_mlp_grad(rd_context* ctx, const rd_mlp* w, const float* x,
 int rd_mlp_train(rd_context* ctx, rd_mlp* w, const float* x, const float* y,
                  uint64_t n, uint32_t epochs, uint32_t batch, float lr,
                  uint64_t seed, float* epoch_loss, void* stream);
+
+/* Weights of the tile-scoring network on disk: a 32-byte header (the
+ * bytes "HGRDMLP1", then uint32 version 1, uint32 weight count 6337,
+ * uint32 feature version, uint32 reserved 0) followed by the weights as
+ * little-endian float32 in the rd_mlp layout.  rd_mlp_save writes the file
+ * (RD_EINVAL for NULL arguments or an unwritable path); rd_mlp_load reads
+ * it into *w and sets *feature_version (may be NULL) -- RD_EINVAL for a
+ * missing or short file, a wrong magic, version or count.  Host-only. */
+int rd_mlp_save(const rd_mlp* w, uint32_t feature_version, const char* path);
+int rd_mlp_load(rd_mlp* w, uint32_t* feature_version, const char* path);
 
 const char* rd_strerror(int status);
 

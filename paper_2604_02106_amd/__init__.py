@@ -78,6 +78,20 @@ class rd_access_pair(C.Structure):
                 ("class_mask", C.c_uint32)]
 
 
+class rd_host_var(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("cmp", C.c_uint32), ("upd", C.c_uint32),
+                ("n_values", C.c_uint32), ("values", C.POINTER(C.c_int64)),
+                ("init", rd_expr), ("bound", rd_expr), ("step", rd_expr)]
+
+
+class rd_host_domain(C.Structure):
+    _fields_ = [("insns", C.POINTER(rd_insn)), ("n_insns", C.c_uint32),
+                ("vars", C.POINTER(rd_host_var)), ("n_vars", C.c_uint32),
+                ("asserts", C.POINTER(rd_expr)), ("n_asserts", C.c_uint32),
+                ("alloc_sizes", C.POINTER(rd_expr)), ("n_alloc", C.c_uint32),
+                ("params", C.POINTER(rd_expr)), ("n_params", C.c_uint32)]
+
+
 N_MLP = 6337  # 32*64 + 64 + 64*64 + 64 + 64 + 1
 rd_mlp = C.c_float * N_MLP  # w1, b1, w2, b2, w3, b3 (include/hgrd.h)
 
@@ -128,7 +142,8 @@ EXPORTS = ("rd_context_create", "rd_context_destroy", "rd_check_pairs",
            "rd_prepare", "rd_execute", "rd_plan_destroy", "rd_get_stats",
            "rd_strerror", "rd_selftest", "rd_tile_data", "rd_mlp_forward",
            "rd_mlp_grad", "rd_mlp_train", "rd_autotune", "rd_table_selftest",
-           "rd_prefilter_selftest")
+           "rd_prefilter_selftest", "rd_expand_host_domain", "rd_mlp_save",
+           "rd_mlp_load")
 
 _lib = None
 
@@ -193,6 +208,14 @@ def lib():
             C.POINTER(rd_kernel_model), C.c_uint32, C.POINTER(rd_launch_domain),
             C.POINTER(rd_param_sets), C.c_uint32, C.c_uint32, C.c_uint32,
             C.c_uint64, C.POINTER(C.c_uint64)]
+        L.rd_expand_host_domain.restype = C.c_int
+        L.rd_expand_host_domain.argtypes = [C.POINTER(rd_host_domain),
+                                            C.POINTER(rd_param_sets),
+                                            C.POINTER(C.c_int64), C.c_uint64]
+        L.rd_mlp_save.restype = C.c_int
+        L.rd_mlp_save.argtypes = [C.c_void_p, C.c_uint32, C.c_char_p]
+        L.rd_mlp_load.restype = C.c_int
+        L.rd_mlp_load.argtypes = [C.c_void_p, C.POINTER(C.c_uint32), C.c_char_p]
         L.rd_selftest.restype = C.c_int
         L.rd_selftest.argtypes = []
         L.rd_get_stats.restype = C.c_int
@@ -528,3 +551,76 @@ def rd_mlp_train(ctx, w, X, Y, epochs=10, batch=4096, lr=1e-3, seed=0,
     if st != RD_OK:
         raise RuntimeError("rd_mlp_train failed: %s" % rd_strerror(st))
     return w, losses
+
+
+_HV_KIND = {"input": 0, "expr": 1, "loop": 2}
+
+
+def expand_host_domain(domain, cap_values=1 << 20):
+    """rd_expand_host_domain on a ``workloads.HostDomain``: the list of
+    parameter tuples (lists of ints).  Host only.  Raises on a non-OK
+    status (the status is in the message)."""
+    insns = []
+
+    def put(e):
+        if e is None:
+            return rd_expr(0, 0)
+        first = len(insns)
+        for t in e.code:
+            op = _OP.get(t[0], 0)
+            if t[0] == "const":
+                insns.append((op, 0, int(t[1])))
+            else:
+                insns.append((op, int(t[1]) if len(t) > 1 else 0, 0))
+        return rd_expr(first, len(e.code))
+
+    keep = []
+    hv = (rd_host_var * max(1, len(domain.vars)))()
+    for k, v in enumerate(domain.vars):
+        x = hv[k]
+        x.kind = _HV_KIND[v.kind]
+        x.cmp, x.upd = _CMP.get(v.cmp, 0), _UPD.get(v.upd, 0)
+        vals = (C.c_int64 * max(1, len(v.values)))(*v.values)
+        keep.append(vals)
+        x.n_values, x.values = len(v.values), vals
+        x.init, x.bound, x.step = put(v.init), put(v.bound), put(v.step)
+
+    def exprs(lst):
+        arr = (rd_expr * max(1, len(lst)))(*[put(e) for e in lst])
+        keep.append(arr)
+        return arr, len(lst)
+
+    h = rd_host_domain()
+    h.vars, h.n_vars = hv, len(domain.vars)
+    h.asserts, h.n_asserts = exprs(domain.asserts)
+    h.alloc_sizes, h.n_alloc = exprs(domain.alloc_sizes)
+    h.params, h.n_params = exprs(domain.params)
+    ins = (rd_insn * max(1, len(insns)))(
+        *[rd_insn(o, a & 0xFFFF, 0, v) for (o, a, v) in insns])
+    h.insns, h.n_insns = ins, len(insns)
+    out = rd_param_sets()
+    buf = (C.c_int64 * max(1, cap_values))()
+    st = lib().rd_expand_host_domain(C.byref(h), C.byref(out), buf, cap_values)
+    if st != RD_OK:
+        raise RuntimeError("rd_expand_host_domain failed: %s (%d)" % (rd_strerror(st), st))
+    n = len(domain.params)
+    return [[buf[r * n + k] for k in range(n)] for r in range(out.n_sets)]
+
+
+def mlp_save(w, path, feature_version):
+    """rd_mlp_save: writes the network's weights (N_MLP float32) to path."""
+    w = _as_f32(w, N_MLP)
+    st = lib().rd_mlp_save(w.ctypes.data, int(feature_version), os.fsencode(path))
+    if st != RD_OK:
+        raise RuntimeError("rd_mlp_save failed: %s" % rd_strerror(st))
+
+
+def mlp_load(path):
+    """rd_mlp_load: (weights as float32 array, feature version)."""
+    import numpy as np
+    w = np.zeros(N_MLP, dtype=np.float32)
+    fv = C.c_uint32()
+    st = lib().rd_mlp_load(w.ctypes.data, C.byref(fv), os.fsencode(path))
+    if st != RD_OK:
+        raise RuntimeError("rd_mlp_load failed on %s: %s" % (path, rd_strerror(st)))
+    return w, fv.value

@@ -17,6 +17,7 @@
 #include "../../include/hgrd.h"
 #include "hgrd_internal.h"
 #include "hgrd_launch.h"
+#include "hgrd_hostops.h"
 
 #include <algorithm>
 #include <array>
@@ -51,53 +52,6 @@ constexpr uint64_t kMaxTabInst = 1ull << 24;  // table entries per instance
 constexpr uint64_t kMaxTabPool = 1ull << 33;  // table entries per plan (64 GiB)
 constexpr uint64_t kL0Slots = 1ull << 29;     // address-count slots per split batch
 constexpr uint64_t kRetryBytes = 16ull << 30;  // bucket bytes of one retried item
-
-// ---------------------------------------------------------------------------
-// checked int64 arithmetic on the host (errors yield 0, evaluation goes on)
-
-int64_t hop(uint16_t op, int64_t a, int64_t b, uint32_t& err) {
-  int64_t r;
-  switch (op) {
-    case RD_OP_ADD:
-      if (__builtin_add_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
-      return r;
-    case RD_OP_SUB:
-      if (__builtin_sub_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
-      return r;
-    case RD_OP_MUL:
-      if (__builtin_mul_overflow(a, b, &r)) { err |= ERR_RANGE; return 0; }
-      return r;
-    case RD_OP_DIV:
-    case RD_OP_MOD:
-      if (b == 0) { err |= ERR_DIVZERO; return 0; }
-      if (a == INT64_MIN && b == -1) { err |= ERR_RANGE; return 0; }
-      return op == RD_OP_DIV ? a / b : a % b;
-    case RD_OP_SHL: {
-      if (b < 0 || b > 63) { err |= ERR_RANGE; return 0; }
-      int64_t s = (int64_t)((uint64_t)a << b);
-      if ((s >> b) != a) { err |= ERR_RANGE; return 0; }
-      return s;
-    }
-    case RD_OP_SHR:
-      if (b < 0 || b > 63) { err |= ERR_RANGE; return 0; }
-      return a >> b;
-    case RD_OP_AND: return a & b;
-    case RD_OP_OR: return a | b;
-    case RD_OP_XOR: return a ^ b;
-    case RD_OP_MIN: return std::min(a, b);
-    case RD_OP_MAX: return std::max(a, b);
-    case RD_OP_LT: return a < b;
-    case RD_OP_LE: return a <= b;
-    case RD_OP_EQ: return a == b;
-    case RD_OP_NE: return a != b;
-    case RD_OP_GE: return a >= b;
-    case RD_OP_GT: return a > b;
-    case RD_OP_LAND: return (a != 0) && (b != 0);
-    case RD_OP_LOR: return (a != 0) || (b != 0);
-  }
-  err |= ERR_INVAL;
-  return 0;
-}
 
 bool is_leaf(uint16_t op) { return op >= RD_OP_CONST && op <= RD_OP_LOOP; }
 bool is_binary(uint16_t op) { return op >= RD_OP_ADD && op <= RD_OP_LOR; }

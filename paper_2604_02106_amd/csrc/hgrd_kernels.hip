@@ -166,6 +166,8 @@ k_tabulate(const Chunk* __restrict__ chunks, const TabJob* __restrict__ jobs,
 // fixed-capacity HBM buckets chosen by a hash of the address (and of the
 // block for shared arrays, whose memory is per block).
 
+// 64-bit finalizer of MurmurHash3 (Austin Appleby's public-domain fmix64:
+// xor-shift 33, multiply, xor-shift 33, multiply, xor-shift 33).
 __device__ __forceinline__ u64 mix64(u64 x) {
   x ^= x >> 33;
   x *= 0xFF51AFD7ED558CCDull;

@@ -13,3 +13,4 @@ from .expr import (E, c, param, tid, bid, bdim, gdim, loop, div, mod, shl, shr,
 from .model import (Model, Workload, Access, Loop, Array, Launch, READ, WRITE,
                     ATOMIC, SCOPE_BLOCK, SCOPE_DEVICE, GLOBAL, SHARED, INTER,
                     INTRA_BLOCK, INTRA_WARP, ALL_CLASSES)
+from .hostdomain import HostDomain, HostVar

@@ -159,3 +159,55 @@ def k5_shift(sets, width=64, rows=64):
 def single(model, a, b, mask=ALL_CLASSES):
     """A one-pair workload."""
     return Workload([model], [(0, a, b, mask)], name=model.name)
+
+
+# ---------------------------------------------------------------------------
+# Host code of Figures 1-5 as host domains (section 4, classes 1-5).  Each
+# returns the domain; unknown inputs take the finite stand-in values given.
+# The parameter columns are those of the kernel model of the same figure.
+
+def k1_host(rows=(16, 32, 48), cols=(1, 16, 32, 48)):
+    """Figure 1 host code: rows and cols are inputs, the host asserts
+    rows == cols (class 1), and passes (rows, cols)."""
+    from .hostdomain import HostDomain, HostVar
+    return HostDomain([HostVar.input(rows), HostVar.input(cols)],
+                      params=[param(0), param(1)],
+                      asserts=[eq(param(0), param(1))], name="K1 host")
+
+
+def k2_host():
+    """Figure 2 host code: reduceFinal is launched with a grid of one block
+    (class 2); the model's one parameter is that grid extent."""
+    from .hostdomain import HostDomain
+    return HostDomain([], params=[c(1)], name="K2 host")
+
+
+def k3_host(h_width=(16, 32, 48), h_height=(32,)):
+    """Figure 3 host code: hWidth and hHeight are inputs; the grid is
+    (hWidth / 16, hHeight / 16) and the kernel's width parameter is hWidth
+    itself (class 3: both from one host variable).  Columns (width,
+    gridDim.x, gridDim.y)."""
+    from .hostdomain import HostDomain, HostVar
+    hw, hh = param(0), param(1)
+    return HostDomain([HostVar.input(h_width), HostVar.input(h_height)],
+                      params=[hw, hw // 16, hh // 16], name="K3 host")
+
+
+def k4_host(h_matrix_dim=(64,), step=16):
+    """Figure 4 host code: hMatrixDim is an input and the kernel's offset is
+    the iterator of for (hOffset = 0; hOffset < hMatrixDim; hOffset +=
+    step) (class 4; the printed loop elides its update, the block size is
+    used here).  Columns (dim, offset)."""
+    from .hostdomain import HostDomain, HostVar
+    return HostDomain([HostVar.input(h_matrix_dim),
+                       HostVar.loop(0, "lt", param(0), "add", step)],
+                      params=[param(0), param(1)], name="K4 host")
+
+
+def k5_host(pitches=(0, 256, 512)):
+    """Figure 5 host code: hRowSize is the pitch a pitched allocation
+    returns (stand-in values) and sizes that allocation, so it is positive
+    in every execution (class 5).  Column (rowSize)."""
+    from .hostdomain import HostDomain, HostVar
+    return HostDomain([HostVar.input(pitches)], params=[param(0)],
+                      alloc_sizes=[param(0)], name="K5 host")
