@@ -1,13 +1,16 @@
 """Benchmark: exact race queries per second on one MI355X.
 
-One step = one rd_execute of the whole batched-uneven workload (256 kernel
-models x 16 access pairs = 4096 queries, seed 2002) on a plan prepared once
-beforehand (its descriptors resident in HBM): every generate / partition /
-join kernel, witness pass 2 and the results copied back.  Prints one JSON
-line; the end-to-end rate (host lowering and upload included) is reported
-beside it.
+Default workload: the mixed batched workload at full size (100 000 queries
+over 6250 kernel models, per-query domain log-uniform in 2^8..2^28 points,
+1-64 parameter tuples per model, 2-D/3-D launches, global and shared arrays,
+10% racy; seed 5005; about 3.98e12 thread-access evaluations).  It runs as
+20 fixed batches of 5000 consecutive queries, each prepared once beforehand
+(descriptors and term tables resident in HBM); one step = one rd_execute of
+one batch: every generate / partition / filter / join kernel, the
+re-partition rounds, witness pass 2 and the results copied back.  The 20
+timed steps cover the workload exactly once.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--config ...]
 """
 import argparse
 import json
@@ -21,6 +24,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_scatter_batched_hbm.md")
 JOIN_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bucket_join_batched_hbm.md")
+MIXED_STEP = 5000  # queries per step of the mixed workload (20 steps cover it)
+# rd_stats fields of the table-path kernels timed per launch with HIP events
+# (the context's default LDS tile: 1024 records, 2048 table slots)
+KERNELS = (
+    ("k_scatter<true>", "scatter_launches", "scatter_tab_ms", "scatter_tab_bytes",
+     "generates every point and writes its record (8 B for int32 addresses, 16 B "
+     "for int64) into an HBM bucket"),
+    ("k_bucket_filter<1024>", "filter_tab_launches", "filter_tab_ms", "filter_tab_bytes",
+     "reads every record back and keeps the buckets holding an address of both "
+     "accesses (per-wavefront LDS hash table)"),
+    ("k_bucket_join<1024, 2048, true>", "join_tab_launches", "join_tab_ms",
+     "join_tab_bytes", "reads the records of the buckets the filter kept and "
+     "joins them in LDS level by level"),
+)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_02106_amd", "csrc", f)
                   for f in ("hgrd_kernels.hip", "hgrd_device.h", "hgrd_internal.h")]
 
@@ -154,22 +171,231 @@ def run_learned(args):
     print(json.dumps(line), flush=True)
 
 
+def kernel_rooflines(stats, traffic_files=None):
+    """Per table-path kernel: algorithmic record bytes per launch over the
+    mean launch duration, both from the timed steps (HIP events on the
+    library's stream around every launch), against the HBM peak."""
+    out = {}
+    for name, lk, mk, bk, what in KERNELS:
+        launches = sum(s[lk] for s in stats)
+        ms = sum(s[mk] for s in stats)
+        nbytes = sum(s[bk] for s in stats)
+        if not launches or ms <= 0:
+            continue
+        avg_ms = ms / launches
+        per_launch = nbytes / launches
+        achieved = per_launch / (avg_ms / 1e3) / 1e9
+        tfile = (traffic_files or {}).get(name)
+        out[name] = {"bound": "hbm", "kernel": name, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(tfile) if tfile else None,
+                     "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms,
+                     "launches_per_step": launches / len(stats),
+                     "ms_per_step": ms / len(stats), "work": what}
+    return out
+
+
+def golden_agreement(wl, results, name):
+    """Stored oracle results (tests/golden/, written by a script that calls
+    only the oracle) against the GPU results, field by field."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    try:
+        import make_goldens as G
+        gold = G.load(name)
+    except (OSError, ImportError):
+        return None
+    if G.digest(wl) != gold["digest"]:
+        return "generator differs from the goldens' workload"
+    agree = 0
+    for i, w in zip(gold["indices"], gold["results"]):
+        g = {f: results[i][f] for f in G.FIELDS}
+        agree += g == w
+    return "%d/%d stored oracle results identical to the GPU (%s)" % (
+        agree, len(gold["indices"]), name)
+
+
+def run_mixed(args):
+    """The headline: the mixed workload in fixed batches of MIXED_STEP
+    consecutive queries, one batch per step."""
+    import numpy as np
+    import torch
+    import paper_2604_02106_amd as hg
+    from workloads import configs
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    wl = configs.mixed(seed=5005, n_queries=int(100000 * args.scale))
+    n = len(wl.pairs)
+    nb = (n + MIXED_STEP - 1) // MIXED_STEP
+    batches = [wl.compact(range(i * MIXED_STEP, min(n, (i + 1) * MIXED_STEP)))
+               for i in range(nb)]
+    log("workload: %d models, %d queries, %d batches (%.1f s to generate)"
+        % (len(wl.models), n, nb, time.perf_counter() - t0))
+    ctx = hg.Context(0)
+    used = sorted(set([i % nb for i in range(args.warmup)] +
+                      [i % nb for i in range(args.steps)]))
+    plans = {}
+    t0 = time.perf_counter()
+    for i in used:
+        plans[i] = hg.Plan(ctx, batches[i], max_device_bytes=args.wave_mib << 20)
+        log("batch %d prepared" % i)
+    prep_s = time.perf_counter() - t0
+    for i in range(args.warmup):
+        plans[i % nb].execute(raw=True)
+        log("warmup %d (batch %d) done" % (i, i % nb))
+    # Timed steps: the first phase runs eagerly with HIP events around every
+    # partition, filter and join launch (the roofline figures come from
+    # these steps); each batch's results stay in its plan's buffer.
+    os.environ["HGRD_TIMING"] = "1"
+    stats, step_s = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        plans[i % nb].execute(raw=True)
+        step_s.append(time.perf_counter() - ts)
+        stats.append(ctx.stats())
+        log("step %d (batch %d) done in %.3f s" % (i, i % nb, step_s[-1]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del os.environ["HGRD_TIMING"]
+    queries = sum(len(batches[i % nb].pairs) for i in range(args.steps))
+    evals = sum(s["evals"] for s in stats)
+    results = {}
+    for i in used:
+        out = plans[i].out
+        results[i] = [hg.result_dict(out[k]) for k in range(len(batches[i].pairs))]
+    covered = [i for i in range(nb) if i in results]
+    flat = None
+    if len(covered) == nb:
+        flat = [r for i in range(nb) for r in results[i]]
+    racy = sum(r["verdict"] for i in covered for r in results[i])
+    line = {
+        "metric": "race queries/sec and thread-access evals/sec (G/s) at 100% oracle agreement",
+        "value": queries / dt,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1000 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "mixed batched: %d queries over %d kernel models, "
+                               "per-query domain log-uniform 2^8..2^28 points, 1-64 "
+                               "parameter tuples per model, 2-D/3-D launches, global "
+                               "(a quarter 64-bit) and shared arrays, 10%% racy, seed "
+                               "5005; %d batches of %d queries, one per step"
+                               % (n, len(wl.models), nb, MIXED_STEP),
+                   "queries_timed": queries, "evals_timed": evals, "racy": racy,
+                   "scale": args.scale, "wave_mib": args.wave_mib or 3072},
+        "evals_per_s_G": evals / dt / 1e9,
+        "prepare_s": prep_s,
+        "step_s": {"min": min(step_s), "max": max(step_s)},
+        "kernel_ms_steps": {k: sum(s[k] for s in stats) / len(stats) for k in (
+            "scatter_ms", "bucket_ms", "small_ms", "retry_ms", "fallback_ms",
+            "witness_ms", "verdict_ms", "split_ms", "waves_ms", "device_ms",
+            "total_ms")},
+        "items_per_step": {k: sum(s[k] for s in stats) / len(stats) for k in (
+            "small_items", "hbm_items", "retry_items", "split_items",
+            "overflow_items", "fallback_records", "buckets", "records")},
+    }
+    kr = kernel_rooflines(stats)
+    if kr:
+        dom = max(kr, key=lambda k: kr[k]["ms_per_step"])
+        line["roofline"] = kr[dom]
+        line["roofline_other_kernels"] = {k: v for k, v in kr.items() if k != dom}
+    if flat is not None:
+        line["golden_agreement"] = golden_agreement(wl, flat, "mixed_5005_sample.json.gz")
+    if not args.no_extras:
+        # the same batches replaying their captured graphs (the first
+        # execute of a plan above ran eagerly, so this captures, then the
+        # timed loop replays)
+        k = min(args.steps, 4)
+        for i in range(k):
+            plans[i % nb].execute(raw=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(k):
+            plans[i % nb].execute(raw=True)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        q = sum(len(batches[i % nb].pairs) for i in range(k))
+        line["graph_replay"] = {"queries_per_s": q / tg,
+                                "eager_queries_per_s": q / sum(step_s[:k]),
+                                "batches": k}
+        # VERDICT mode with the trained tile order on the first two batches
+        # against EXACT on the same batches (from the timed steps)
+        try:
+            from paper_2604_02106_amd import tile_mlp
+            w, _ = tile_mlp.load()
+            k = min(2, len(step_s))
+            vt, vres = 0.0, []
+            for i in range(k):
+                vp = hg.Plan(ctx, batches[i], mode=hg.MODE_VERDICT, order=hg.ORDER_MLP, mlp=w)
+                vp.execute(raw=True)
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                r = vp.execute()
+                vt += time.perf_counter() - ts
+                vres.append(r)
+                vp.close()
+            q = sum(len(batches[i].pairs) for i in range(k))
+            same = all(a["verdict"] == b["verdict"] and a["status"] == b["status"]
+                       for i in range(k) for a, b in zip(vres[i], results[i]))
+            line["verdict_mlp"] = {"queries_per_s": q / vt,
+                                   "exact_queries_per_s": q / sum(step_s[:k]),
+                                   "batches": k, "verdicts_equal_exact": same}
+        except (OSError, RuntimeError, AssertionError) as e:
+            line["verdict_mlp"] = "not run: %s" % e
+        # the plain checker: one query per call, on a random sample
+        rng = np.random.Generator(np.random.PCG64(17))
+        pick = [int(x) for x in rng.choice(len(batches[0].pairs), 64, replace=False)]
+        one = [batches[0].compact([p]) for p in pick]
+        hg.rd_check_pairs(ctx, one[0])
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        same = True
+        for p, w1 in zip(pick, one):
+            same &= hg.rd_check_pairs(ctx, w1)[0] == results[0][p]
+        line["plain_checker"] = {"queries_per_s": len(pick) / (time.perf_counter() - ts),
+                                 "sample": "%d queries of batch 0, one rd_check_pairs "
+                                           "call each" % len(pick),
+                                 "results_equal_batched": bool(same)}
+        # end to end: a fresh plan of batch 0 (lowering, upload, execute)
+        ts = time.perf_counter()
+        e2e = hg.rd_check_pairs(ctx, batches[0])
+        line["end_to_end_queries_per_s"] = len(batches[0].pairs) / (time.perf_counter() - ts)
+        line["end_to_end_equal"] = e2e == results[0]
+    if not args.no_cpu_baseline and 0 in results:
+        line["cpu_baseline"] = cpu_baseline(batches[0], results[0])
+        line["cpu_baseline"]["sample"] += " (batch 0 of the mixed workload)"
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 for the mixed workload, "
+                         "one pass over it; 5 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default 1 mixed, 2 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the pre-filtered plan and graph replay figures "
                          "reported beside the headline (they run after the "
                          "timed steps)")
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--config", default="batched",
+    ap.add_argument("--config", default="mixed",
                     choices=("batched", "stress", "mixed", "learned"),
-                    help="workload: batched uneven queries (the headline), "
-                         "race-free stress (128 pairs, 2^30 points per "
-                         "access), or mixed domain sizes")
+                    help="workload: mixed batched queries (the headline), "
+                         "batched uneven queries, race-free stress (128 "
+                         "pairs, 2^30 points per access), or the learned "
+                         "tile order on sparse witnesses")
     ap.add_argument("--wave-mib", type=int, default=0,
                     help="partition wave size in MiB (0: the library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -181,8 +407,14 @@ def main():
               "(queries shard across GPUs without exchange, see the design "
               "notes)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.steps is None:
+        args.steps = 20 if args.config == "mixed" else 5
+    if args.warmup is None:
+        args.warmup = 1 if args.config == "mixed" else 2
     if args.config == "learned":
         return run_learned(args)
+    if args.config == "mixed" and not args.calibrate_copy:
+        return run_mixed(args)
     import torch
     if args.calibrate_copy:
         # 8 GiB: far beyond the 256 MiB last-level cache, so the counters see
@@ -204,10 +436,6 @@ def main():
         desc = ("race-free stress: 128 access pairs, 2^30 points per access "
                 "(grid 65536 x block 256 x 64 iterations), int64 addresses, "
                 "strided and blocked near misses, seed 3003")
-    elif args.config == "mixed":
-        wl = configs.mixed(n_queries=int(100000 * args.scale))
-        desc = ("mixed: %d queries, per-query domain log-uniform 2^8..2^28 "
-                "points, 2-D/3-D launches, 1-64 tuples, seed 5005" % len(wl.pairs))
     else:
         wl = configs.batched(seed=2002, scale=args.scale)
         desc = ("batched uneven queries: 256 kernel models x 16 access pairs, "
@@ -304,33 +532,15 @@ def main():
                                             "overflow_items", "fallback_records",
                                             "buckets", "records", "scatter_bytes")},
     }
-    # dominant kernel: the table-path bucket join (records read back from
-    # HBM and joined in LDS); beside it the table-path partition kernel
-    # (records generated and written).  Both are timed with HIP events on
-    # the library's stream around every launch of the timed steps.
-    # (the context's default LDS tile: 1024 records, 2048 table slots)
-    for key, name, lk, mk, bk, tfile in (
-            ("roofline", "k_bucket_join<1024, 2048, true>", "join_tab_launches", "join_tab_ms",
-             "join_tab_bytes", JOIN_TRAFFIC_FILE),
-            ("roofline_partition", "k_scatter<true>", "scatter_launches",
-             "scatter_tab_ms", "scatter_tab_bytes", TRAFFIC_FILE)):
-        launches = sum(s[lk] for s in stats)
-        sms = sum(s[mk] for s in stats)
-        sbytes = sum(s[bk] for s in stats)
-        if not launches or sms <= 0:
-            continue
-        avg_ms = sms / launches
-        per_launch = sbytes / launches
-        achieved = per_launch / (avg_ms / 1e3) / 1e9
-        line[key] = {"bound": "hbm", "kernel": name,
-                     "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     # counters were taken on the batched workload only
-                     "traffic": (measured_traffic(tfile)
-                                 if args.config == "batched" else None),
-                     "bytes_per_launch": per_launch,
-                     "avg_launch_ms": avg_ms,
-                     "launches_per_step": launches / len(stats)}
+    kr = kernel_rooflines(stats, {"k_scatter<true>": TRAFFIC_FILE,
+                                  "k_bucket_join<1024, 2048, true>": JOIN_TRAFFIC_FILE}
+                          if args.config == "batched" else None)
+    if kr:
+        dom = max(kr, key=lambda k: kr[k]["ms_per_step"])
+        line["roofline"] = kr[dom]
+        line["roofline_other_kernels"] = {k: v for k, v in kr.items() if k != dom}
+    if args.config == "batched" and args.scale == 1.0:
+        line["golden_agreement"] = golden_agreement(wl, res, "batched_2002.json.gz")
     if not args.no_cpu_baseline and args.config == "batched":
         line["cpu_baseline"] = cpu_baseline(wl, res)
     print(json.dumps(line), flush=True)

@@ -228,7 +228,7 @@ typedef struct {
 
 /* ---- options ---------------------------------------------------------- */
 enum { RD_MODE_EXACT = 0, RD_MODE_VERDICT = 1 };
-enum { RD_ORDER_LEX = 0, RD_ORDER_MLP = 1 };
+enum { RD_ORDER_LEX = 0, RD_ORDER_MLP = 1, RD_ORDER_INTERVAL = 2 };
 
 /* The tile-scoring network of VERDICT mode: 32 tile features -> 64 -> 64 ->
  * 1 logit, ReLU, fp32.  Row-major, output-major weight matrices. */
@@ -240,7 +240,11 @@ typedef struct {
 
 typedef struct {
   uint32_t mode;       /* RD_MODE_EXACT (default) or RD_MODE_VERDICT */
-  uint32_t order;      /* VERDICT tile order: RD_ORDER_LEX or RD_ORDER_MLP */
+  uint32_t order;      /* VERDICT tile order: RD_ORDER_LEX (tile index),
+                          RD_ORDER_MLP (network score) or RD_ORDER_INTERVAL
+                          (tile index among the tiles whose two blocks'
+                          address ranges meet; disjoint tiles last, as for
+                          the network) */
   uint32_t prefilter;  /* 1: decide without enumeration (exact) the
                           (pair, tuple) units whose two accesses share no
                           address: their address ranges (bounds proven for
@@ -376,6 +380,11 @@ typedef struct {
   uint64_t join_tab_bytes;   /* record bytes they read */
   uint64_t presplit_items;   /* items sent to the (address, block) split
                                 without a first partition pass */
+  uint64_t filter_tab_launches; /* table-path address-filter launches
+                                   (k_bucket_filter before the table-path
+                                   join), timed in filter_tab_ms */
+  double filter_tab_ms;      /* their summed duration */
+  uint64_t filter_tab_bytes; /* record bytes they read */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libhgrd.so")
 RD_OK, RD_EINVAL, RD_EUNSUPPORTED, RD_ERANGE, RD_EDIVZERO = 0, -1, -2, -3, -4
 RD_ENOMEM, RD_EDEVICE, RD_ECAPACITY = -5, -6, -7
 MODE_EXACT, MODE_VERDICT = 0, 1
-ORDER_LEX, ORDER_MLP = 0, 1
+ORDER_LEX, ORDER_MLP, ORDER_INTERVAL = 0, 1, 2
 
 # opcode numbers of include/hgrd.h
 _OP = {"const": 1, "param": 2, "tid": 3, "bid": 4, "bdim": 5, "gdim": 6,
@@ -133,7 +133,9 @@ class rd_stats(C.Structure):
                 ("scatter_tab_ms", C.c_double), ("scatter_tab_bytes", C.c_uint64),
                 ("prefiltered", C.c_uint64), ("join_tab_launches", C.c_uint64),
                 ("join_tab_ms", C.c_double), ("join_tab_bytes", C.c_uint64),
-                ("presplit_items", C.c_uint64)]
+                ("presplit_items", C.c_uint64),
+                ("filter_tab_launches", C.c_uint64), ("filter_tab_ms", C.c_double),
+                ("filter_tab_bytes", C.c_uint64)]
 
 
 assert C.sizeof(rd_pair_result) == 88

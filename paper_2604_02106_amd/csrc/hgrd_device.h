@@ -344,7 +344,9 @@ struct JoinLds {
   uint32_t n;
   uint32_t err;
   uint32_t vote[3];          // block-wide votes (see block_vote)
-  uint32_t bn[kMaxRunBuckets];  // record counts of a bucket run
+  uint32_t bn[kMaxRunBuckets];  // record counts of the buckets to join
+  uint32_t bl[kMaxRunBuckets];  // their offsets in the run
+  uint32_t nbl;                 // how many
 };
 
 // Block-wide OR with one barrier (the library's __syncthreads_or costs

@@ -25,8 +25,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <memory>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -888,8 +890,12 @@ struct Planner {
   // (index into tjobs, -1: the address does not depend on the block)
   std::vector<std::pair<int64_t, int64_t>> rrest;
   std::vector<int32_t> bjob;
+  // tables only: address step from thread 0 to thread 1 and from block 0 to
+  // block 1 (0 when the group has one index or no term)
+  std::vector<std::array<int64_t, 2>> gstride;
   std::vector<TabJob> tjobs;
   uint64_t tpool = 0;         // table entries
+  uint64_t tab_budget = kMaxTabPool;  // table entries this planner may use
   bool use_tables = true;
 
   // Term tables of instance I (access a of model m); T.on = 0 when some
@@ -995,7 +1001,7 @@ struct Planner {
         entries += J.n;
       }
     }
-    if (entries > kMaxTabInst || tpool + entries > kMaxTabPool) return;
+    if (entries > kMaxTabInst || tpool + entries > tab_budget) return;
     T.base = tpool;
     for (TabJob& J : jobs) {
       if (J.group == 0) bjob[inst] = (int32_t)tjobs.size();
@@ -1027,13 +1033,16 @@ struct Planner {
     // them than along threads (consecutive points then share buckets)
     int64_t stride[3] = {0, 0, 0};
     for (const TabJob& J : jobs) {
-      if (J.group == 0 || J.group == 3 || J.val.absent || J.n < 2) continue;
+      if (J.group == 3 || J.val.absent || J.n < 2) continue;
       int64_t c[10];
       uint32_t e = 0;
-      host_coords(I, pool_loops, 0, J.group == 1 ? 1 : 0, J.group == 2 ? 1 : 0, c);
+      host_coords(I, pool_loops, J.group == 0 ? 1 : 0, J.group == 1 ? 1 : 0,
+                  J.group == 2 ? 1 : 0, c);
       const int64_t v1 = host_prog(this->code, J.val, c, pv, 0, e);
       host_coords(I, pool_loops, 0, 0, 0, c);
       const int64_t v0 = host_prog(this->code, J.val, c, pv, 0, e);
+      if (J.group < 2 && !e) gstride[inst][J.group ? 0 : 1] = v1 - v0;
+      if (J.group == 0) continue;
       if (!e) stride[J.group] = v1 > v0 ? v1 - v0 : v0 - v1;
       else stride[J.group] = INT64_MAX;
     }
@@ -1183,9 +1192,80 @@ struct Planner {
     ares.push_back({1, 0});
     rrest.push_back({0, -1});
     bjob.push_back(-1);
+    gstride.push_back({0, 0});
     tables_for(m, a, I, (uint32_t)ii.idx, T);
     tabs.push_back(T);
     return ii;
+  }
+
+  // Appends everything planner `o` lowered (it worked on models no other
+  // planner touched): its pools go after this planner's, and every offset
+  // and index into them is moved by the pool sizes before the append.
+  void absorb(Planner& o) {
+    const uint32_t code_off = (uint32_t)code.size();
+    const uint32_t par_off = (uint32_t)pool_params.size();
+    const uint32_t loop_off = (uint32_t)pool_loops.size();
+    const int32_t inst_off = (int32_t)dev_insts.size();
+    const int32_t job_off = (int32_t)tjobs.size();
+    const uint64_t tp_off = tpool;
+    auto fix = [&](Prog& p) {
+      if (!p.absent) p.off += code_off;
+    };
+    code.insert(code.end(), o.code.begin(), o.code.end());
+    pool_params.insert(pool_params.end(), o.pool_params.begin(), o.pool_params.end());
+    pool_loops.insert(pool_loops.end(), o.pool_loops.begin(), o.pool_loops.end());
+    for (AccInst I : o.dev_insts) {
+      fix(I.addr);
+      fix(I.guard);
+      fix(I.bint);
+      fix(I.wint);
+      I.params_off += par_off;
+      for (uint32_t k = 0; k < I.n_loops && k < 4; ++k) I.loop_off[k] += loop_off;
+      dev_insts.push_back(I);
+    }
+    for (TabHost T : o.tabs) {
+      if (T.on) T.base += tp_off;
+      tabs.push_back(T);
+    }
+    for (TabJob J : o.tjobs) {
+      J.inst += (uint32_t)inst_off;
+      J.out_off += tp_off;
+      fix(J.val);
+      fix(J.guard);
+      tjobs.push_back(J);
+    }
+    tpool += o.tpool;
+    arange.insert(arange.end(), o.arange.begin(), o.arange.end());
+    ares.insert(ares.end(), o.ares.begin(), o.ares.end());
+    rrest.insert(rrest.end(), o.rrest.begin(), o.rrest.end());
+    for (int32_t b : o.bjob) bjob.push_back(b < 0 ? b : b + job_off);
+    gstride.insert(gstride.end(), o.gstride.begin(), o.gstride.end());
+    for (size_t m = 0; m < o.dims.size() && m < dims.size(); ++m) {
+      bool any = false;
+      for (const DimInfo& d : o.dims[m]) any |= d.done;
+      if (!any) continue;
+      dims[m] = o.dims[m];
+      for (DimInfo& d : dims[m])
+        if (d.ok) d.params_off += par_off;
+    }
+    for (auto& kv : o.loops) {
+      std::vector<LoopInfo> v = kv.second;
+      for (LoopInfo& li : v)
+        if (li.ok) li.off += loop_off;
+      loops[kv.first] = v;
+    }
+    for (auto& kv : o.insts) {
+      std::vector<InstInfo> v = kv.second;
+      for (InstInfo& ii : v)
+        if (ii.idx >= 0) ii.idx += inst_off;
+      insts[kv.first] = v;
+    }
+    for (int w = 0; w < 4; ++w)
+      for (auto& kv : o.progs[w]) {
+        Prog p = kv.second;
+        fix(p);
+        progs[w][kv.first] = p;
+      }
   }
 
   // Per-block address intervals of a table instance (sorted, merged): a
@@ -1271,6 +1351,7 @@ uint32_t class_mask(const rd_kernel_model& m, const rd_access& x,
 struct QPlan {
   uint32_t host_err = 0;
   uint8_t trivial = 0;
+  uint8_t lower = 0;  // valid, non-trivial: its instances are lowered
   bool work = false;
   QDesc qd;
   uint64_t evals = 0;
@@ -1387,7 +1468,10 @@ struct rd_plan_impl {
   uint64_t max_key_bytes = 0, max_buckets = 0, max_items = 0;
   uint64_t wave_budget = 0;
   // VERDICT mode
-  bool verdict = false, use_mlp = false;
+  bool verdict = false;
+  uint32_t score_mode = 0;  // 0 plain order, 1 network, 2 interval order
+  std::vector<uint32_t> vinst_tab;  // table instances of VERDICT blocks
+  std::vector<BItem> bitems_interp; // VERDICT blocks of interpreted instances
   uint32_t K = 0;                  // tiles searched per search unit
   uint32_t n_vq = 0, n_bitems = 0, n_tchunks = 0, max_tiles = 0;
   uint64_t n_tiles = 0;
@@ -1439,7 +1523,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   rd_options o;
   memset(&o, 0, sizeof o);
   if (opt) o = *opt;
-  if (o.mode > RD_MODE_VERDICT || o.order > RD_ORDER_MLP) return RD_EINVAL;
+  if (o.mode > RD_MODE_VERDICT || o.order > RD_ORDER_INTERVAL) return RD_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
   rd_plan* plan = new rd_plan();
   std::unique_ptr<rd_plan> guard(plan);
@@ -1507,6 +1591,74 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     q.qd.warp = launch[pr.model].warp_size;
     q.qd.shared = M.arrays[A.array].space == RD_SHARED;
     if (q.qd.mask == 0) { q.trivial = 1; continue; }
+    q.lower = 1;
+  }
+
+  // ---- lowering of the instances the pairs use, in parallel ----------------
+  // Models are dealt to a fixed number of groups (so the plan does not
+  // depend on the host), each lowered by its own planner on a host thread,
+  // then appended to P in group order; P's memo then answers every
+  // instance query below.  Each group may use its share of the table pool.
+  {
+    constexpr uint32_t kGroups = 16;
+    std::vector<std::vector<uint32_t>> gpairs(kGroups);
+    std::vector<uint64_t> gcost(kGroups, 0);
+    std::vector<int32_t> mgroup(n_models, -1);
+    uint64_t lowered = 0;
+    for (uint32_t k = 0; k < n_pairs; ++k) {
+      if (!Q[k].lower) continue;
+      const uint32_t m = pairs[k].model;
+      if (mgroup[m] < 0) {
+        // the group with the least work so far
+        uint32_t g = 0;
+        for (uint32_t x = 1; x < kGroups; ++x)
+          if (gcost[x] < gcost[g]) g = x;
+        mgroup[m] = (int32_t)g;
+      }
+      const uint32_t g = (uint32_t)mgroup[m];
+      gpairs[g].push_back(k);
+      gcost[g] += params[m].n_sets;
+      lowered += params[m].n_sets;
+    }
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const uint32_t nthreads = lowered < 4096 ? 1u : std::min<uint32_t>(kGroups, hw);
+    if (nthreads > 1) {
+      std::vector<Planner> sub(kGroups);
+      for (Planner& G : sub) {
+        G.models = models;
+        G.launch = launch;
+        G.params = params;
+        G.dims.resize(n_models);
+        for (uint32_t m = 0; m < n_models; ++m) G.dims[m].resize(P.dims[m].size());
+        G.use_tables = P.use_tables;
+        G.tab_budget = kMaxTabPool / kGroups;
+      }
+      std::atomic<uint32_t> next{0};
+      auto work = [&]() {
+        for (;;) {
+          const uint32_t g = next.fetch_add(1);
+          if (g >= kGroups) return;
+          for (uint32_t k : gpairs[g]) {
+            const rd_access_pair& pr = pairs[k];
+            for (uint32_t s = 0; s < params[pr.model].n_sets; ++s) {
+              sub[g].inst(pr.model, pr.a, s);
+              if (pr.b != pr.a) sub[g].inst(pr.model, pr.b, s);
+            }
+          }
+        }
+      };
+      std::vector<std::thread> th;
+      for (uint32_t t = 1; t < nthreads; ++t) th.emplace_back(work);
+      work();
+      for (auto& t : th) t.join();
+      for (Planner& G : sub) P.absorb(G);
+    }
+  }
+
+  for (uint32_t k = 0; k < n_pairs; ++k) {
+    QPlan& q = Q[k];
+    if (!q.lower) continue;
+    const rd_access_pair& pr = pairs[k];
     const uint32_t ns = params[pr.model].n_sets;
     q.inst.assign(ns, {-1, -1});
     for (uint32_t s = 0; s < ns; ++s) {
@@ -1679,8 +1831,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   std::vector<TItem> titems;
   if (o.mode == RD_MODE_VERDICT) {
     plan->verdict = true;
-    plan->use_mlp = o.order == RD_ORDER_MLP;
-    if (plan->use_mlp && !o.mlp) return RD_EINVAL;
+    plan->score_mode = o.order == RD_ORDER_MLP ? 1u : o.order == RD_ORDER_INTERVAL ? 2u : 0u;
+    if (plan->score_mode == 1 && !o.mlp) return RD_EINVAL;
     plan->K = o.tile_budget ? o.tile_budget : 256;
     for (uint32_t k = 0; k < n_pairs; ++k) {
       QPlan& q = Q[k];
@@ -1710,13 +1862,19 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         v.inst_j = (uint32_t)q.inst[s].second;
         v.G = A.nblk;
         v.bb_i = (uint32_t)bitems.size();
-        for (uint32_t b = 0; b < A.nblk; ++b) bitems.push_back({v.inst_i, b, k, 0});
+        for (uint32_t b = 0; b < A.nblk; ++b)
+          bitems.push_back({v.inst_i, b, k, (uint32_t)bitems.size()});
         if (q.qd.self) {
           v.bb_j = v.bb_i;
         } else {
           v.bb_j = (uint32_t)bitems.size();
-          for (uint32_t b = 0; b < B.nblk; ++b) bitems.push_back({v.inst_j, b, k, 0});
+          for (uint32_t b = 0; b < B.nblk; ++b)
+            bitems.push_back({v.inst_j, b, k, (uint32_t)bitems.size()});
         }
+        v.st_i = P.gstride[v.inst_i][0];
+        v.sb_i = P.gstride[v.inst_i][1];
+        v.st_j = P.gstride[v.inst_j][0];
+        v.sb_j = P.gstride[v.inst_j][1];
         v.self = q.qd.self;
         v.tile0 = (uint32_t)plan->n_tiles;
         v.tpb_i = A.tpb;
@@ -1750,6 +1908,17 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     plan->n_vq = (uint32_t)vqs.size();
     plan->vqs = vqs;
     plan->n_bitems = (uint32_t)bitems.size();
+    // block bounds: instances with term tables from their tables (one lane
+    // per block), the others by generating every point of the block
+    std::vector<uint8_t> seen(P.dev_insts.size(), 0);
+    for (const BItem& b : bitems) {
+      if (P.tabs[b.inst].on) {
+        if (!seen[b.inst]) plan->vinst_tab.push_back(b.inst);
+        seen[b.inst] = 1;
+      } else {
+        plan->bitems_interp.push_back(b);
+      }
+    }
     plan->n_tchunks = (uint32_t)tchunks.size();
     plan->n_titems = (uint32_t)titems.size();
   }
@@ -1931,10 +2100,13 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     up("titems", titems.data(), titems.size() * sizeof(TItem));
     plan->buf("bbounds", std::max<size_t>(1, bitems.size()) * sizeof(BBound), &merr);
     plan->buf("scores", std::max<size_t>(1, plan->n_tiles) * 4, &merr);
-    if (plan->use_mlp) {
+    if (plan->score_mode) {
       plan->buf("order", std::max<size_t>(1, (size_t)vqs.size() * plan->K) * 4, &merr);
-      up("mlp_w", o.mlp, (size_t)mlp_num_weights() * 4);
+      if (plan->score_mode == 1) up("mlp_w", o.mlp, (size_t)mlp_num_weights() * 4);
     }
+    up("vinst", plan->vinst_tab.data(), plan->vinst_tab.size() * 4);
+    up("bitems_i", plan->bitems_interp.data(), plan->bitems_interp.size() * sizeof(BItem));
+    plan->buf("irange", std::max<size_t>(1, P.dev_insts.size()) * sizeof(InstRange), &merr);
     plan->buf("tout", std::max<size_t>(1, titems.size()) * sizeof(TOut), &merr);
     plan->buf("claim", std::max<size_t>(1, n_pairs) * 8, &merr);
   }
@@ -1946,7 +2118,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   plan->buf("ovf", std::max<size_t>(1, plan->hitems.size()) * 4, &merr);
   plan->buf("done", std::max<size_t>(1, n_pairs) * 4, &merr);
   plan->buf("pcursor", 4, &merr);
-  plan->buf("nbytes", 256 * 8, &merr);
+  plan->buf("nbytes", 512 * 8, &merr);
+  plan->buf("cand", std::max<uint64_t>(1, plan->max_buckets), &merr);
   plan->buf("out", std::max<size_t>(1, n_pairs) * sizeof(rd_pair_result), &merr);
   if (merr) return merr;
   *plan_out = guard.release();
@@ -1954,6 +2127,24 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
 }
 
 void rd_plan_destroy(rd_plan* plan) { delete plan; }
+
+// VERDICT block bounds: instances with term tables from their tables, the
+// others by generating their points.  Nonzero on a launch failure.
+static int verdict_bounds(rd_plan* plan, hipStream_t st) {
+  auto D = [&](const char* name) { return plan->dev[name].p; };
+  BBound* d_bb = (BBound*)D("bbounds");
+  if (!plan->vinst_tab.empty() &&
+      launch_block_bounds_tab(st, (const uint32_t*)D("vinst"), (uint32_t)plan->vinst_tab.size(),
+                              (const BItem*)D("bitems"), plan->n_bitems, D("insts"),
+                              (InstRange*)D("irange"), d_bb))
+    return 1;
+  if (!plan->bitems_interp.empty() &&
+      launch_block_bounds(st, (const BItem*)D("bitems_i"), (uint32_t)plan->bitems_interp.size(),
+                          D("insts"), (const DInsn*)D("code"), (const int64_t*)D("params"),
+                          (const int64_t*)D("loops"), (QAcc*)D("qacc"), d_bb))
+    return 1;
+  return 0;
+}
 
 int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   if (!ctx || !plan) return RD_EINVAL;
@@ -1989,6 +2180,10 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   // graph stays valid); later phases reuse the context's arena
   unsigned char* d_recs = (unsigned char*)D("recs");
   uint32_t* d_cursor = (uint32_t*)D("cursor");
+  uint8_t* d_cand = (uint8_t*)D("cand");
+  // the exact address filter in front of the bucket join (HGRD_NO_FILTER
+  // turns it off: every bucket is joined)
+  const bool use_filter = getenv("HGRD_NO_FILTER") == nullptr;
   uint32_t* d_done = (uint32_t*)D("done");
   uint32_t* d_pcursor = (uint32_t*)D("pcursor");
   u64* d_nbytes = (u64*)D("nbytes");
@@ -2009,7 +2204,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   // per wave: events before and after the table partition, after the
   // interpreted partition, after the table-path join and after the
   // interpreted join; whether table partition and table join ran
-  std::vector<std::array<uint32_t, 7>> wtimes;
+  std::vector<std::array<uint32_t, 8>> wtimes;
   auto wevent = [&](uint32_t k) -> hipEvent_t {
     while (ctx->wev.size() <= k) {
       hipEvent_t e = nullptr;
@@ -2025,15 +2220,17 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     const uint32_t wcap = (uint32_t)join_cap(wcfg);
     for (const auto& W : waves) {
       const uint32_t k = wev_n;
-      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr,
+                 e5 = nullptr;
       if (events) {
-        wev_n += 5;
+        wev_n += 6;
         e0 = wevent(k);
         e1 = wevent(k + 1);
         e2 = wevent(k + 2);
         e3 = wevent(k + 3);
         e4 = wevent(k + 4);
-        if (!e0 || !e1 || !e2 || !e3 || !e4) return RD_EDEVICE;
+        e5 = wevent(k + 5);
+        if (!e0 || !e1 || !e2 || !e3 || !e4 || !e5) return RD_EDEVICE;
       }
       if (launch_fill_u32(st, d_cursor, W.n_buckets, 0)) return RD_EDEVICE;
       // partition: instances with term tables, then the interpreted ones
@@ -2052,23 +2249,26 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
                          d_cursor, d_ovf, wcap, d_done, d_nbytes + 64))
         return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(e2, st));
-      // join: runs of items with term tables, then the interpreted ones
-      // (record bytes read counted in slots 128..191 and 192..255)
+      // address filter and join: runs of items with term tables, then the
+      // interpreted ones (record bytes the joins read are counted in slots
+      // 128..191 and 192..255, the filters' in 384..447)
+      uint8_t* cand = use_filter ? d_cand : nullptr;
       if (W.n_tab_runs &&
           launch_bucket(wcfg, st, W.n_tab_runs, d_bit + W.bitem_off, W.n_tab_runs, d_hit,
                         d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs,
-                        d_cursor, d_ovf, d_done, l0k, l0c, d_nbytes + 128))
+                        d_cursor, d_ovf, d_done, l0k, l0c, cand, d_nbytes + 128,
+                        events ? e5 : nullptr))
         return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(e3, st));
       if (W.n_runs > W.n_tab_runs &&
           launch_bucket(wcfg, st, W.n_runs - W.n_tab_runs, d_bit + W.bitem_off + W.n_tab_runs,
                         0, d_hit, d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs,
-                        d_cursor, d_ovf, d_done, l0k, l0c, d_nbytes + 128))
+                        d_cursor, d_ovf, d_done, l0k, l0c, cand, d_nbytes + 128, nullptr))
         return RD_EDEVICE;
       if (events) {
         TRY_HIP(hipEventRecord(e4, st));
         wtimes.push_back({k, k + 1, k + 2, k + 3, k + 4, W.n_tab_chunks ? 1u : 0u,
-                          W.n_tab_runs ? 1u : 0u});
+                          W.n_tab_runs ? 1u : 0u, k + 5});
       }
       if (W.n_buckets) S.join_launches += 1;
       S.buckets += W.n_buckets;
@@ -2087,9 +2287,16 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       }
       if (hipEventElapsedTime(&ms, ctx->wev[t[1]], ctx->wev[t[2]]) == hipSuccess)
         scatter_ms += ms;
-      if (hipEventElapsedTime(&ms, ctx->wev[t[2]], ctx->wev[t[3]]) == hipSuccess) {
+      if (hipEventElapsedTime(&ms, ctx->wev[t[2]], ctx->wev[t[3]]) == hipSuccess)
         bucket_ms += ms;
-        if (t[6]) {
+      // table-path runs: filter (t[2] .. t[7]) and join (t[7] .. t[3])
+      if (t[6]) {
+        if (use_filter &&
+            hipEventElapsedTime(&ms, ctx->wev[t[2]], ctx->wev[t[7]]) == hipSuccess) {
+          S.filter_tab_ms += ms;
+          S.filter_tab_launches += 1;
+        }
+        if (hipEventElapsedTime(&ms, ctx->wev[t[7]], ctx->wev[t[3]]) == hipSuccess) {
           S.join_tab_ms += ms;
           S.join_tab_launches += 1;
         }
@@ -2112,23 +2319,21 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       return RD_EDEVICE;
     if (launch_init_acc(st, n_pairs, d_acc)) return RD_EDEVICE;
     if (launch_fill_u32(st, d_done, n_pairs, 0)) return RD_EDEVICE;
-    if (launch_fill_u64(st, d_nbytes, 256, 0)) return RD_EDEVICE;
+    if (launch_fill_u64(st, d_nbytes, 512, 0)) return RD_EDEVICE;
     if (plan->verdict && plan->n_vq) {
       VQuery* d_vq = (VQuery*)D("vq");
       BBound* d_bb = (BBound*)D("bbounds");
       float* d_sc = (float*)D("scores");
-      uint32_t* d_order = plan->use_mlp ? (uint32_t*)D("order") : nullptr;
+      uint32_t* d_order = plan->score_mode ? (uint32_t*)D("order") : nullptr;
       TOut* d_tout = (TOut*)D("tout");
       u64* d_claim = (u64*)D("claim");
       if (events) TRY_HIP(hipEventRecord(ev[15], st));
-      if (launch_fill_u64(st, d_claim, n_pairs, kNoKey) ||
-          launch_block_bounds(st, (const BItem*)D("bitems"), plan->n_bitems, d_insts,
-                              d_code, d_params, d_loops, d_acc, d_bb) ||
+      if (launch_fill_u64(st, d_claim, n_pairs, kNoKey) || verdict_bounds(plan, st) ||
           launch_vq_span(st, d_vq, plan->n_vq, d_bb))
         return RD_EDEVICE;
-      if (plan->use_mlp) {
+      if (plan->score_mode) {
         if (launch_tile_scores(st, (const TChunk*)D("tchunks"), plan->n_tchunks, d_vq,
-                               d_bb, (const float*)D("mlp_w"), 1, d_sc) ||
+                               d_bb, (const float*)D("mlp_w"), plan->score_mode, d_sc) ||
             launch_topk(st, d_vq, plan->n_vq, d_sc, plan->K, plan->max_tiles, d_order))
           return RD_EDEVICE;
       }
@@ -2289,6 +2494,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     }
     d_recs = (unsigned char*)ctx->ensure("recs", std::max<uint64_t>(max_bytes, plan->max_key_bytes), &merr);
     d_cursor = (uint32_t*)ctx->ensure("cursor", std::max<uint64_t>(max_nbk, plan->max_buckets) * 4, &merr);
+    d_cand = (uint8_t*)ctx->ensure("cand", std::max<uint64_t>(max_nbk, plan->max_buckets), &merr);
     const uint32_t nr = (uint32_t)hs.size();
     HItem* d_rh = (HItem*)ctx->ensure("r_hitems", nr * sizeof(HItem), &merr);
     Chunk* d_rc = (Chunk*)ctx->ensure("r_chunks", chunks.size() * sizeof(Chunk), &merr);
@@ -2578,13 +2784,14 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   TRY_HIP(hipEventRecord(ev[1], st));
   if (n_pairs)
     TRY_HIP(hipMemcpyAsync(out, d_out, n_pairs * sizeof(rd_pair_result), hipMemcpyDeviceToHost, st));
-  u64 scat_bytes[256];
+  u64 scat_bytes[512];
   TRY_HIP(hipMemcpyAsync(scat_bytes, d_nbytes, sizeof scat_bytes, hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < 128; ++k) {
     S.scatter_bytes += scat_bytes[k];
     if (k < 64) S.scatter_tab_bytes += scat_bytes[k];
     if (k < 64) S.join_tab_bytes += scat_bytes[128 + k];
+    if (k < 64) S.filter_tab_bytes += scat_bytes[384 + k];
   }
   float ms = 0;
   if (!w2.empty()) {
@@ -2719,10 +2926,7 @@ int rd_tile_data(rd_context* ctx, const rd_kernel_model* models,
       launch_init_acc(st, n_pairs, d_acc) || launch_fill_u32(st, d_done, n_pairs, 0) ||
       launch_fill_u64(st, (u64*)D("claim"), n_pairs, kNoKey) ||
       launch_fill_u64(st, (u64*)d_tout, (u64)plan->n_titems * (sizeof(TOut) / 8), kNoKey) ||
-      launch_block_bounds(st, (const BItem*)D("bitems"), plan->n_bitems, D("insts"),
-                          (const DInsn*)D("code"), (const int64_t*)D("params"),
-                          (const int64_t*)D("loops"), d_acc, d_bb) ||
-      launch_vq_span(st, d_vq, plan->n_vq, d_bb) ||
+      verdict_bounds(plan, st) || launch_vq_span(st, d_vq, plan->n_vq, d_bb) ||
       launch_tile_features(st, (const TChunk*)D("tchunks"), plan->n_tchunks, d_vq, d_bb, d_feat))
     return RD_EDEVICE;
   // every tile is joined (no commit, so no query stops early)

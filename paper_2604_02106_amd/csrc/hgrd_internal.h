@@ -194,9 +194,17 @@ struct Chunk {
 
 // ---- VERDICT mode (learned tile order) --------------------------------------
 
-// Block-bounds work item: block `block` of access instance `inst` (query q).
+// Block-bounds work item: block `block` of access instance `inst` (query q);
+// its bounds go to BBound `out`.
 struct BItem {
-  uint32_t inst, block, q, pad;
+  uint32_t inst, block, q, out;
+};
+// Address bounds of the thread and iteration term tables of an instance:
+// smallest and largest valid entry and the number of valid entries (an
+// absent table counts as one entry of value 0 per thread or iteration).
+struct InstRange {
+  long long tmin, tmax, imin, imax;
+  uint32_t tcnt, icnt;
 };
 // Smallest and largest address of a block's guarded points, and their number.
 struct BBound {
@@ -211,6 +219,8 @@ struct VQuery {
   uint32_t tile0, tpb_i, tpb_j, nthr;
   uint32_t kinds, shared, is64, nsets;
   long long amin, amax;           // address span over both sides
+  long long st_i, sb_i, st_j, sb_j;  // address step per thread and per
+                                     // block of each side (0: unknown)
 };
 // Tiles [t0, t1) of search unit vq (scores / features).
 struct TChunk {

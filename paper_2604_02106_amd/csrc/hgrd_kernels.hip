@@ -484,6 +484,161 @@ __global__ void k_apply_s0(uint32_t n, const L0Item* __restrict__ items,
 }
 
 // ---------------------------------------------------------------------------
+// Kernel: exact address filter of HBM buckets, one wavefront per bucket.
+//
+// Every conflict needs two records of one bucket with equal addresses (and
+// equal blocks for shared arrays), one from each access (for a self pair:
+// two records).  Each wavefront owns one bucket at a time and a private
+// LDS hash table of record indices: side-a records are inserted, then
+// side-b records probe it (a self pair inserts every record and looks for
+// a duplicate).  The bucket goes on to the join only if some record finds
+// a partner; a bucket without one can hold no conflict at any level, so
+// skipping it is exact.  No barrier is needed: the table belongs to one
+// wavefront, whose LDS operations complete in program order.  Items split
+// by (address, block) (their level 0 is counted elsewhere) always go on.
+
+constexpr uint32_t kFilterThreads = 256;
+
+template <int CAP>
+struct FilterLds {
+  uint32_t owner[2 * CAP];  // record index + 1, 0 = empty
+  u64 key[CAP];             // record address
+  uint32_t blk[CAP];        // record block (shared arrays), else 0
+};
+
+template <int CAP>
+constexpr uint32_t filter_waves() {
+  return CAP <= 1024 ? 4u : (CAP <= 1536 ? 2u : 1u);
+}
+
+__device__ __forceinline__ uint32_t filter_slot(u64 a, uint32_t b, uint32_t mask) {
+  uint32_t x = (uint32_t)a * 0x9E3779B1u ^ (uint32_t)(a >> 32) * 0x85EBCA77u ^
+               b * 0xC2B2AE3Du;
+  x ^= x >> 15;
+  x *= 0x2C1B3C6Du;
+  x ^= x >> 12;
+  return x & mask;
+}
+
+template <int CAP>
+__global__ void __launch_bounds__(kFilterThreads)
+k_bucket_filter(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
+                const QDesc* __restrict__ qd, const unsigned char* __restrict__ recs,
+                const uint32_t* __restrict__ cursor, const uint32_t* __restrict__ ovf,
+                const uint32_t* __restrict__ done, uint8_t* __restrict__ cand,
+                u64* __restrict__ nbytes) {
+  constexpr uint32_t NW = filter_waves<CAP>();
+  constexpr int RPT = CAP / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  FilterLds<CAP>& T = reinterpret_cast<FilterLds<CAP>*>(smem)[wv];
+  const BRun R = runs[blockIdx.x];
+  const HItem h = hitems[R.item];
+  if (ovf[R.item] || done[h.q]) return;  // the join skips these runs too
+  const bool self = qd[h.q].self != 0;
+  const bool shared = h.shared == 1;
+  const bool is32 = h.is32 != 0;
+  const u64* r8 = reinterpret_cast<const u64*>(recs + h.rec_off);
+  const ulonglong2* r16 = reinterpret_cast<const ulonglong2*>(recs + h.rec_off);
+  u64 nread = 0;
+  for (uint32_t b = R.b0 + wv; b < R.b1; b += NW) {
+    const uint32_t gb = h.bucket0 + b;
+    if (h.shared == 3) {  // level 0 counted per address: always joined
+      if (lane == 0) cand[gb] = 1;
+      continue;
+    }
+    const uint32_t n = min(cursor[gb], (uint32_t)CAP);
+    nread += (u64)n * (is32 ? 8u : 16u);
+    u64 ad[RPT];
+    uint32_t pid[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const uint32_t r = (uint32_t)j * 64 + lane;
+      ad[j] = 0;
+      pid[j] = 0;
+      if (r < n) {
+        if (is32) {
+          const u64 v = r8[(u64)b * CAP + r];
+          ad[j] = (u64)(int64_t)(int32_t)(uint32_t)v;
+          pid[j] = (uint32_t)(v >> 32);
+        } else {
+          const ulonglong2 v = r16[(u64)b * CAP + r];
+          ad[j] = v.x;
+          pid[j] = (uint32_t)v.y;
+        }
+      }
+    }
+    // table of 2 * CAP slots, cleared with 16-byte stores
+    uint4* o4 = reinterpret_cast<uint4*>(T.owner);
+    static_assert((2 * CAP) % 256 == 0, "filter table clear");
+#pragma unroll
+    for (uint32_t k = 0; k < (2 * CAP) / 256; ++k) o4[k * 64 + lane] = make_uint4(0, 0, 0, 0);
+    uint32_t bk[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const uint32_t r = (uint32_t)j * 64 + lane;
+      bk[j] = 0;
+      if (shared && r < n) {
+        // shared memory is per block: the block joins the address
+        const uint32_t sd = pid[j] >> 31, p = pid[j] & 0x7FFFFFFFu;
+        const uint32_t m = sd ? h.tpb_m[1] : h.tpb_m[0];
+        const uint32_t sh = sd ? h.tpb_s[1] : h.tpb_s[0];
+        bk[j] = (__umulhi(m, p) + p) >> sh;
+      }
+      if (r < n) {
+        T.key[r] = ad[j];
+        T.blk[r] = bk[j];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    constexpr uint32_t mask = 2 * CAP - 1;
+    bool found = false;
+    // side a (every record of a self pair) inserts
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const uint32_t r = (uint32_t)j * 64 + lane;
+      if (r >= n || (!self && (pid[j] >> 31))) continue;
+      uint32_t sl = filter_slot(ad[j], bk[j], mask);
+      for (;;) {
+        const uint32_t o = atomicCAS(&T.owner[sl], 0u, r + 1);
+        if (o == 0) break;
+        if (T.key[o - 1] == ad[j] && T.blk[o - 1] == bk[j]) {
+          found |= self;  // a second record of the address
+          break;
+        }
+        sl = (sl + 1) & mask;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // side b probes
+    if (!self) {
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const uint32_t r = (uint32_t)j * 64 + lane;
+        if (r >= n || !(pid[j] >> 31)) continue;
+        uint32_t sl = filter_slot(ad[j], bk[j], mask);
+        for (;;) {
+          const uint32_t o = T.owner[sl];
+          if (o == 0) break;
+          if (T.key[o - 1] == ad[j] && T.blk[o - 1] == bk[j]) {
+            found = true;
+            break;
+          }
+          sl = (sl + 1) & mask;
+        }
+      }
+    }
+    const bool any = __ballot(found) != 0;
+    if (lane == 0) cand[gb] = any ? 1 : 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane == 0 && nread) atomicAdd(&nbytes[blockIdx.x & (kByteSlots - 1)], nread);
+}
+
+// ---------------------------------------------------------------------------
 // Kernel: join the records of HBM buckets in LDS.
 
 constexpr uint32_t kJoinThreads = 512;  // bucket-join workgroup size
@@ -515,7 +670,8 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
               const uint32_t* __restrict__ cursor,
               const uint32_t* __restrict__ ovf,
               const uint32_t* __restrict__ done, const u64* __restrict__ l0keys,
-              const u64* __restrict__ l0cnt, u64* __restrict__ nbytes) {
+              const u64* __restrict__ l0cnt, const uint8_t* __restrict__ cand,
+              u64* __restrict__ nbytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
   const BRun R = runs[blockIdx.x];
@@ -547,15 +703,28 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
       }                                                             \
     }                                                               \
   }
-  // record counts of the run's buckets, read once
-  for (uint32_t k = threadIdx.x; k < R.b1 - R.b0; k += kJoinThreads)
-    S.bn[k] = min(cursor[h.bucket0 + R.b0 + k], (uint32_t)CAP);
-  uint32_t n = R.b0 < R.b1 ? min(cursor[h.bucket0 + R.b0], (uint32_t)CAP) : 0;
+  // the run's buckets that the address filter passed (all of them without
+  // a filter), compacted by one wavefront, with their record counts
+  if (threadIdx.x < 64) {
+    const uint32_t k = threadIdx.x;
+    const bool c = k < R.b1 - R.b0 && (!cand || cand[h.bucket0 + R.b0 + k]);
+    const u64 bal = __ballot(c);
+    if (c) {
+      const uint32_t pos = (uint32_t)__popcll(bal & ((1ull << k) - 1));
+      S.bl[pos] = k;
+      S.bn[pos] = min(cursor[h.bucket0 + R.b0 + k], (uint32_t)CAP);
+    }
+    if (k == 0) S.nbl = (uint32_t)__popcll(bal);
+  }
+  __syncthreads();  // S.red, S.vote, S.bl, S.bn ready
+  const uint32_t nbl = S.nbl;
+  if (nbl == 0) return;
+  uint32_t n = S.bn[0];
   u64 nread = 0;  // record bytes read (thread 0)
-  HGRD_FETCH(R.b0, n)
-  __syncthreads();  // S.red, S.vote and S.bn ready
+  HGRD_FETCH(R.b0 + S.bl[0], n)
   const bool self = q.self != 0;
-  for (uint32_t b = R.b0; b < R.b1; ++b) {
+  for (uint32_t kb = 0; kb < nbl; ++kb) {
+    const uint32_t b = R.b0 + S.bl[kb];
     bool go = n != 0;
     nread += (u64)n * (is32 ? 8u : 16u);
     uint32_t i1[RPT], i2[RPT];
@@ -586,9 +755,11 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
       }
     }
     // the next bucket's records load while this one is joined
-    const uint32_t n1 = b + 1 < R.b1 ? S.bn[b + 1 - R.b0] : 0;
+    const bool more = kb + 1 < nbl;
+    const uint32_t n1 = more ? S.bn[kb + 1] : 0;
+    const uint32_t b1n = more ? R.b0 + S.bl[kb + 1] : 0;
     if (!l0ext) {
-      if (b + 1 < R.b1) HGRD_FETCH(b + 1, n1)
+      if (more) HGRD_FETCH(b1n, n1)
       __syncthreads();
       if (go) {
 #pragma unroll
@@ -604,9 +775,9 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
           any |= cand;
           S.tli[r] = (sd[j] ? kSide : 0u) | (cand ? 0u : kInactive);
         }
-        // tag b + 1 on the word of b's parity: the same word's previous
-        // vote (bucket b - 2) was read before this bucket's first barrier
-        go = block_vote(any, &S.vote[b & 1], b + 1);
+        // tag kb + 1 on the word of kb's parity: the same word's previous
+        // vote (bucket kb - 2) was read before this bucket's first barrier
+        go = block_vote(any, &S.vote[kb & 1], kb + 1);
       }
     }
     const uint32_t wsh = (q.warp & (q.warp - 1)) == 0 ? (uint32_t)__ffs((int)q.warp) - 1 : 32u;
@@ -658,7 +829,7 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
         }
       }
     }
-    if (l0ext && b + 1 < R.b1) HGRD_FETCH(b + 1, n1)
+    if (l0ext && more) HGRD_FETCH(b1n, n1)
 #undef HGRD_FETCH
     if (threadIdx.x == 0) S.n = n;
     __syncthreads();
@@ -1077,6 +1248,9 @@ static int set_lds_attrs() {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   HGRD_CHECK(hipFuncSetAttribute((const void*)k_bucket_join<CAP, TBL, false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  HGRD_CHECK(hipFuncSetAttribute(
+      (const void*)k_bucket_filter<CAP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(sizeof(FilterLds<CAP>) * filter_waves<CAP>())));
   return 0;
 }
 
@@ -1087,21 +1261,36 @@ static int launch_bucket_t(hipStream_t st, uint32_t nruns, const BRun* runs,
                            const int64_t* loopvals, const QDesc* qd, QAcc* acc,
                            const unsigned char* recs, const uint32_t* cursor,
                            const uint32_t* ovf, const uint32_t* done,
-                           const u64* l0keys, const u64* l0cnt, u64* nbytes) {
+                           const u64* l0keys, const u64* l0cnt, uint8_t* cand,
+                           u64* nbytes, hipEvent_t mid) {
   // runs [0, n_tab) are of items whose instances have term tables; record
-  // bytes read are counted in nbytes[0..63] and nbytes[64..127]
+  // bytes read by the join are counted in nbytes[0..63] and nbytes[64..127],
+  // by the address filter (when cand is given) in nbytes[256..319].  The
+  // filter runs over every run first; `mid` (optional) is recorded between
+  // filter and join.
   size_t lds = sizeof(JoinLds<CAP, TBL>);
+  if (cand) {
+    const size_t flds = sizeof(FilterLds<CAP>) * filter_waves<CAP>();
+    for (uint32_t off = 0; off < nruns; off += 1u << 20) {
+      uint32_t m = nruns - off < (1u << 20) ? nruns - off : (1u << 20);
+      hipLaunchKernelGGL(k_bucket_filter<CAP>, dim3(m), dim3(filter_waves<CAP>() * 64), flds,
+                         st, runs + off, hitems, qd, recs, cursor, ovf, done, cand,
+                         nbytes + 256);
+      HGRD_CHECK(hipGetLastError());
+    }
+  }
+  if (mid) HGRD_CHECK(hipEventRecord(mid, st));
   for (uint32_t off = 0; off < nruns; off += 1u << 20) {
     uint32_t m = nruns - off < (1u << 20) ? nruns - off : (1u << 20);
     uint32_t mt = off >= n_tab ? 0 : (n_tab - off < m ? n_tab - off : m);
     if (mt)
       hipLaunchKernelGGL((k_bucket_join<CAP, TBL, true>), dim3(mt), dim3(kJoinThreads), lds,
                          st, runs + off, hitems, insts, code, params, loopvals, qd, acc,
-                         recs, cursor, ovf, done, l0keys, l0cnt, nbytes);
+                         recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes);
     if (m > mt)
       hipLaunchKernelGGL((k_bucket_join<CAP, TBL, false>), dim3(m - mt), dim3(kJoinThreads),
                          lds, st, runs + off + mt, hitems, insts, code, params, loopvals,
-                         qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, nbytes + 64);
+                         qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes + 64);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -1225,12 +1414,13 @@ int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
                   const DInsn* code, const int64_t* params, const int64_t* loopvals,
                   const QDesc* qd, QAcc* acc, const unsigned char* recs,
                   const uint32_t* cursor, const uint32_t* ovf, const uint32_t* done,
-                  const u64* l0keys, const u64* l0cnt, u64* nbytes) {
+                  const u64* l0keys, const u64* l0cnt, uint8_t* cand, u64* nbytes,
+                  hipEvent_t mid) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, nbytes);
-    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, nbytes);
-    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, nbytes);
+    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, mid);
+    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, mid);
+    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, mid);
   }
 }
 

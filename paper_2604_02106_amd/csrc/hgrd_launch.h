@@ -49,7 +49,7 @@ int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
                   const QDesc* qd, QAcc* acc, const unsigned char* recs,
                   const uint32_t* cursor, const uint32_t* ovf, const uint32_t* done,
                   const unsigned long long* l0keys, const unsigned long long* l0cnt,
-                  unsigned long long* nbytes);
+                  uint8_t* cand, unsigned long long* nbytes, hipEvent_t mid);
 int launch_level0(hipStream_t st, const Chunk* chunks, uint32_t n,
                   const L0Item* items, const void* insts, const DInsn* code,
                   const int64_t* params, const int64_t* loopvals,
@@ -82,10 +82,13 @@ int launch_block_bounds(hipStream_t st, const BItem* items, uint32_t n,
                         const void* insts, const DInsn* code,
                         const int64_t* params, const int64_t* loopvals,
                         QAcc* acc, BBound* out);
+int launch_block_bounds_tab(hipStream_t st, const uint32_t* ilist, uint32_t ni,
+                            const BItem* items, uint32_t n, const void* insts,
+                            InstRange* ir, BBound* out);
 int launch_vq_span(hipStream_t st, VQuery* vq, uint32_t n, const BBound* bb);
 int launch_tile_scores(hipStream_t st, const TChunk* chunks, uint32_t n,
                        const VQuery* vq, const BBound* bb, const float* w,
-                       uint32_t use_mlp, float* scores);
+                       uint32_t mode, float* scores);
 int launch_tile_features(hipStream_t st, const TChunk* chunks, uint32_t n,
                          const VQuery* vq, const BBound* bb, float* feats);
 int launch_topk(hipStream_t st, const VQuery* vq, uint32_t nvq,

@@ -76,9 +76,97 @@ k_block_bounds(const BItem* __restrict__ items, const DevInst* __restrict__ inst
     b.mx = mx;
     b.cnt = cnt;
     b.pad = 0;
-    out[blockIdx.x] = b;
+    out[it.out] = b;
     if (err) atomicOr(&acc[it.q].err, err);
   }
+}
+
+// Bounds of the thread and iteration term tables of one instance (one
+// workgroup per instance).
+__global__ void __launch_bounds__(256)
+k_inst_ranges(const uint32_t* __restrict__ list, const DevInst* __restrict__ insts,
+              InstRange* __restrict__ out) {
+  const uint32_t x = list[blockIdx.x];
+  DevInst I;
+  load_inst(I, insts, x);
+  __shared__ long long smn[4], smx[4];
+  __shared__ uint32_t scnt[4];
+  InstRange r;
+  for (int g = 1; g <= 2; ++g) {
+    const uint32_t n = g == 1 ? I.a.nthr : I.a.niota;
+    long long mn = INT64_MAX, mx = INT64_MIN;
+    uint32_t cnt = 0;
+    if (I.toff[g] == kNoTab) {
+      mn = mx = 0;
+      cnt = threadIdx.x == 0 ? n : 0;
+    } else {
+      for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
+        const long long v = I.tpool[I.toff[g] + e];
+        if (v == INT64_MIN) continue;  // a guard conjunct of this group fails
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
+        ++cnt;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+      mn = a < mn ? a : mn;
+      mx = b > mx ? b : mx;
+      cnt += __shfl_xor(cnt, o, 64);
+    }
+    const uint32_t w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      smn[w] = mn;
+      smx[w] = mx;
+      scnt[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (uint32_t k = 1; k < (blockDim.x >> 6); ++k) {
+        mn = smn[k] < mn ? smn[k] : mn;
+        mx = smx[k] > mx ? smx[k] : mx;
+        cnt += scnt[k];
+      }
+      if (g == 1) { r.tmin = mn; r.tmax = mx; r.tcnt = cnt; }
+      else { r.imin = mn; r.imax = mx; r.icnt = cnt; }
+    }
+  }
+  if (threadIdx.x == 0) out[x] = r;
+}
+
+// Block bounds of instances with term tables, one lane per block: the
+// address is u + T_B[b] + T_T[t] + T_L[i] over the valid entries of each
+// table, so a block's smallest (largest) address is its block term plus the
+// smallest (largest) thread and iteration terms, and its point count the
+// product of the valid entries (no point of a table instance can fail, so
+// there is no error to record).  Items of interpreted instances are left
+// to k_block_bounds.
+__global__ void __launch_bounds__(256)
+k_block_bounds_tab(const BItem* __restrict__ items, uint32_t n,
+                   const DevInst* __restrict__ insts, const InstRange* __restrict__ ir,
+                   BBound* __restrict__ out) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const BItem it = items[k];
+  const DevInst& I = insts[it.inst];
+  if (!I.tab) return;
+  const InstRange r = ir[it.inst];
+  BBound b;
+  b.mn = 0;
+  b.mx = 0;
+  b.cnt = 0;
+  b.pad = 0;
+  const long long vb = I.toff[0] != kNoTab ? I.tpool[I.toff[0] + it.block] : 0;
+  if (!I.tnever && vb != INT64_MIN && r.tcnt && r.icnt) {
+    b.mn = I.tu + vb + r.tmin + r.imin;
+    b.mx = I.tu + vb + r.tmax + r.imax;
+    b.cnt = r.tcnt * r.icnt;
+  } else {
+    b.mn = INT64_MAX;
+    b.mx = INT64_MIN;
+  }
+  out[it.out] = b;
 }
 
 // Span of a search unit: the smallest and largest address over both sides.
@@ -102,6 +190,12 @@ k_vq_span(VQuery* __restrict__ vq, uint32_t n, const BBound* __restrict__ bb) {
 // 32 tile features (all in [-1, 1] or small positive values).
 
 __device__ __forceinline__ float flog2p(double x) { return (float)(log2(1.0 + x) / 64.0); }
+// sign(x) log2(1 + |x|) / 32
+__device__ __forceinline__ float slog(long long x) {
+  const double a = x < 0 ? -(double)x : (double)x;
+  const float m = (float)(log2(1.0 + a) / 32.0);
+  return x < 0 ? -m : m;
+}
 
 __device__ void tile_features(const VQuery& v, uint32_t b1, uint32_t b2,
                               const BBound& x, const BBound& y, float* f) {
@@ -136,18 +230,19 @@ __device__ void tile_features(const VQuery& v, uint32_t b1, uint32_t b2,
   f[17] = (float)(log2((double)v.tpb_i / v.nthr + 1.0) / 16.0);
   f[18] = v.self ? 1.f : 0.f;
   f[19] = (float)v.kinds / 8.f;
-  f[20] = v.shared ? 1.f : 0.f;
-  f[21] = v.is64 ? 1.f : 0.f;
+  // address steps per thread and per block of each side (sign and log)
+  f[20] = slog(v.st_i);
+  f[21] = slog(v.st_j);
   f[22] = ex && ey ? (float)(((double)x.mn - (double)y.mn) / span) : 0.f;
   f[23] = ex && ey ? (float)(((double)x.mx - (double)y.mx) / span) : 0.f;
   f[24] = ext1 > 0 ? (float)(x.cnt / ext1) : 0.f;
   f[25] = ext2 > 0 ? (float)(y.cnt / ext2) : 0.f;
-  f[26] = (float)v.sigma / (float)(v.nsets ? v.nsets : 1);
+  f[26] = slog(v.sb_i);
   f[27] = ext1 > 0 ? (float)(ov / ext1) : 0.f;
   f[28] = ext2 > 0 ? (float)(ov / ext2) : 0.f;
   f[29] = ex && ey ? (x.mn < y.mn ? -1.f : (x.mn > y.mn ? 1.f : 0.f)) : 0.f;
-  f[30] = (b1 + 1 == b2 || b2 + 1 == b1) ? 1.f : 0.f;
-  f[31] = 1.f;
+  f[30] = slog(v.sb_j);
+  f[31] = (v.st_i == v.st_j && v.sb_i == v.sb_j) ? 1.f : 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -184,30 +279,30 @@ __device__ __forceinline__ void stage_weights(float* sw, const float* __restrict
   __syncthreads();
 }
 
-// Scores of every tile of every search unit (LEX order: score = -index).
+// Scores of every tile of every search unit.  mode 1 (network): the
+// network's logit; mode 2 (interval order): minus the tile index; in both,
+// tiles whose blocks' address ranges are disjoint (no conflict possible)
+// score -inf, last in order.  mode 0 (plain order): minus the index.
 __global__ void __launch_bounds__(256)
 k_tile_scores(const TChunk* __restrict__ chunks, const VQuery* __restrict__ vq,
               const BBound* __restrict__ bb, const float* __restrict__ w,
-              uint32_t use_mlp, float* __restrict__ scores) {
+              uint32_t mode, float* __restrict__ scores) {
   __shared__ float sw[kNW];
-  if (use_mlp) stage_weights(sw, w);
+  if (mode == 1) stage_weights(sw, w);
   const TChunk ch = chunks[blockIdx.x];
   const VQuery v = vq[ch.vq];
   for (uint32_t t = ch.t0 + threadIdx.x; t < ch.t1; t += blockDim.x) {
-    float s;
-    if (use_mlp) {
+    float s = -(float)t;
+    if (mode != 0) {
       uint32_t b1 = t / v.G, b2 = t - b1 * v.G;
       const BBound x = bb[v.bb_i + b1], y = bb[v.bb_j + b2];
       if (!x.cnt || !y.cnt || x.mx < y.mn || y.mx < x.mn) {
-        // disjoint address ranges: no conflict in this tile, last in order
         s = -INFINITY;
-      } else {
+      } else if (mode == 1) {
         float f[kIn];
         tile_features(v, b1, b2, x, y, f);
         s = mlp_logit(sw, f);
       }
-    } else {
-      s = -(float)t;
     }
     scores[v.tile0 + t] = s;
   }
@@ -328,57 +423,137 @@ k_adam(float* __restrict__ w, float* __restrict__ g, float* __restrict__ m,
 
 // ---------------------------------------------------------------------------
 // Search order: the `K` best tiles of each search unit by (score desc,
-// index asc), by K rounds of a workgroup arg-max over unselected tiles.
+// index asc).  The tiles with a finite score (ranges that meet) are
+// gathered in LDS, sorted by a bitonic network, and the first K written;
+// the rest of the K ranks take the -inf tiles in index order.  More finite
+// tiles than the LDS holds: K rounds of a workgroup arg-max, each below
+// the previous pick in that order.
+constexpr uint32_t kTopCap = 4096;
+
+__device__ __forceinline__ bool tile_before(float sa, uint32_t ia, float sb, uint32_t ib) {
+  return sa > sb || (sa == sb && ia < ib);
+}
 
 __global__ void __launch_bounds__(256)
 k_topk(const VQuery* __restrict__ vq, const float* __restrict__ scores,
        uint32_t K, uint32_t* __restrict__ order) {
-  extern __shared__ uint32_t sel[];  // bitmap of selected tiles
+  __shared__ float ks[kTopCap];
+  __shared__ uint32_t ki[kTopCap];
+  __shared__ uint32_t cnt, base;
   __shared__ float bs[4];
   __shared__ uint32_t bi[4];
   const VQuery v = vq[blockIdx.x];
   const uint32_t nt = v.G * v.G;
-  const uint32_t nwords = (nt + 31) / 32;
-  for (uint32_t k = threadIdx.x; k < nwords; k += blockDim.x) sel[k] = 0;
-  __syncthreads();
   const uint32_t kk = K < nt ? K : nt;
   const float* sc = scores + v.tile0;
-  for (uint32_t r = 0; r < kk; ++r) {
-    float best = -INFINITY;
-    uint32_t bidx = 0xFFFFFFFFu;
-    for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
-      if ((sel[t >> 5] >> (t & 31)) & 1) continue;
-      float s = sc[t];
-      if (s > best || (s == best && t < bidx)) { best = s; bidx = t; }
+  uint32_t* out = order + (u64)blockIdx.x * K;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
+    const float s = sc[t];
+    if (s == -INFINITY) continue;
+    const uint32_t p = atomicAdd(&cnt, 1u);
+    if (p < kTopCap) {
+      ks[p] = s;
+      ki[p] = t;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      float s2 = __shfl_xor(best, o, 64);
-      uint32_t i2 = __shfl_xor(bidx, o, 64);
-      if (s2 > best || (s2 == best && i2 < bidx)) { best = s2; bidx = i2; }
+  }
+  __syncthreads();
+  const uint32_t c = cnt;
+  uint32_t nfin;
+  if (c <= kTopCap) {
+    uint32_t P = 1;
+    while (P < c) P <<= 1;
+    for (uint32_t k = c + threadIdx.x; k < P; k += blockDim.x) {
+      ks[k] = -INFINITY;
+      ki[k] = 0xFFFFFFFFu;
     }
-    const uint32_t w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { bs[w] = best; bi[w] = bidx; }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      for (uint32_t k = 1; k < (blockDim.x >> 6); ++k)
-        if (bs[k] > best || (bs[k] == best && bi[k] < bidx)) { best = bs[k]; bidx = bi[k]; }
-      if (best == -INFINITY) {
-        // every tile left scores -inf: the rest of the order is index order
-        uint32_t t = 0;
-        for (uint32_t r2 = r; r2 < kk; ++r2, ++t) {
-          while ((sel[t >> 5] >> (t & 31)) & 1) ++t;
-          order[(u64)blockIdx.x * K + r2] = t;
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+        for (uint32_t k = threadIdx.x; k < P; k += blockDim.x) {
+          const uint32_t j = k ^ stride;
+          if (j <= k) continue;
+          const bool up = (k & size) == 0;  // this run is sorted "before first"
+          const bool jb = tile_before(ks[j], ki[j], ks[k], ki[k]);
+          if (jb == up) {
+            const float ts = ks[k];
+            const uint32_t ti = ki[k];
+            ks[k] = ks[j];
+            ki[k] = ki[j];
+            ks[j] = ts;
+            ki[j] = ti;
+          }
         }
-        bs[0] = -INFINITY;
-      } else {
-        if (bidx == 0xFFFFFFFFu) bidx = 0;
-        order[(u64)blockIdx.x * K + r] = bidx;
-        sel[bidx >> 5] |= 1u << (bidx & 31);
-        bs[0] = best;
+        __syncthreads();
       }
     }
+    nfin = c < kk ? c : kk;
+    for (uint32_t r = threadIdx.x; r < nfin; r += blockDim.x) out[r] = ki[r];
+  } else {
+    // K rounds of arg-max below the previous pick
+    float ps = INFINITY;
+    uint32_t pi = 0;
+    bool first = true;
+    nfin = 0;
+    for (uint32_t r = 0; r < kk; ++r) {
+      float best = -INFINITY;
+      uint32_t bidx = 0xFFFFFFFFu;
+      for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
+        const float s = sc[t];
+        if (s == -INFINITY) continue;
+        if (!first && !tile_before(ps, pi, s, t)) continue;
+        if (bidx == 0xFFFFFFFFu || tile_before(s, t, best, bidx)) { best = s; bidx = t; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const float s2 = __shfl_xor(best, o, 64);
+        const uint32_t i2 = __shfl_xor(bidx, o, 64);
+        if (i2 != 0xFFFFFFFFu && (bidx == 0xFFFFFFFFu || tile_before(s2, i2, best, bidx))) {
+          best = s2;
+          bidx = i2;
+        }
+      }
+      const uint32_t w = threadIdx.x >> 6;
+      if ((threadIdx.x & 63) == 0) { bs[w] = best; bi[w] = bidx; }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (uint32_t k = 1; k < (blockDim.x >> 6); ++k)
+          if (bi[k] != 0xFFFFFFFFu && (bidx == 0xFFFFFFFFu || tile_before(bs[k], bi[k], best, bidx))) {
+            best = bs[k];
+            bidx = bi[k];
+          }
+        bs[0] = best;
+        bi[0] = bidx;
+        if (bidx != 0xFFFFFFFFu) out[r] = bidx;
+      }
+      __syncthreads();
+      if (bi[0] == 0xFFFFFFFFu) break;
+      ps = bs[0];
+      pi = bi[0];
+      first = false;
+      nfin = r + 1;
+      __syncthreads();
+    }
+  }
+  // the remaining ranks: -inf tiles in index order
+  if (threadIdx.x == 0) base = nfin;
+  __syncthreads();
+  for (uint32_t t0 = 0; t0 < nt; t0 += blockDim.x) {
+    if (base >= kk) break;
+    const uint32_t t = t0 + threadIdx.x;
+    const bool inf = t < nt && sc[t] == -INFINITY;
+    // rank of this tile among the -inf tiles of the chunk
+    const u64 bal = __ballot(inf);
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
-    if (bs[0] == -INFINITY) break;
+    if (lane == 0) bi[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t k = 0; k < w; ++k) before += bi[k];
+    const uint32_t pos = base + before + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+    if (inf && pos < kk) out[pos] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) base += bi[0] + bi[1] + bi[2] + bi[3];
     __syncthreads();
   }
 }
@@ -524,6 +699,23 @@ __global__ void k_verdict_commit(uint32_t n, const u64* __restrict__ claim,
     if (e_ != hipSuccess) return (int)e_; \
   } while (0)
 
+int launch_block_bounds_tab(hipStream_t st, const uint32_t* ilist, uint32_t ni,
+                            const BItem* items, uint32_t n, const void* insts,
+                            InstRange* ir, BBound* out) {
+  for (uint32_t off = 0; off < ni; off += 1u << 20) {
+    uint32_t m = ni - off < (1u << 20) ? ni - off : (1u << 20);
+    hipLaunchKernelGGL(k_inst_ranges, dim3(m), dim3(256), 0, st, ilist + off,
+                       (const DevInst*)insts, ir);
+    HGRD_CHECK(hipGetLastError());
+  }
+  if (n) {
+    hipLaunchKernelGGL(k_block_bounds_tab, dim3((n + 255) / 256), dim3(256), 0, st, items,
+                       n, (const DevInst*)insts, ir, out);
+    HGRD_CHECK(hipGetLastError());
+  }
+  return 0;
+}
+
 int launch_block_bounds(hipStream_t st, const BItem* items, uint32_t n,
                         const void* insts, const DInsn* code,
                         const int64_t* params, const int64_t* loopvals,
@@ -531,8 +723,7 @@ int launch_block_bounds(hipStream_t st, const BItem* items, uint32_t n,
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
     hipLaunchKernelGGL(k_block_bounds, dim3(m), dim3(256), 0, st, items + off,
-                       (const DevInst*)insts, code, params, loopvals, acc,
-                       out + off);
+                       (const DevInst*)insts, code, params, loopvals, acc, out);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -547,11 +738,11 @@ int launch_vq_span(hipStream_t st, VQuery* vq, uint32_t n, const BBound* bb) {
 
 int launch_tile_scores(hipStream_t st, const TChunk* chunks, uint32_t n,
                        const VQuery* vq, const BBound* bb, const float* w,
-                       uint32_t use_mlp, float* scores) {
+                       uint32_t mode, float* scores) {
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
     hipLaunchKernelGGL(k_tile_scores, dim3(m), dim3(256), 0, st, chunks + off,
-                       vq, bb, w, use_mlp, scores);
+                       vq, bb, w, mode, scores);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -572,8 +763,8 @@ int launch_topk(hipStream_t st, const VQuery* vq, uint32_t nvq,
                 const float* scores, uint32_t K, uint32_t max_tiles,
                 uint32_t* order) {
   if (!nvq) return 0;
-  size_t lds = ((max_tiles + 31) / 32) * 4;
-  hipLaunchKernelGGL(k_topk, dim3(nvq), dim3(256), lds, st, vq, scores, K, order);
+  (void)max_tiles;
+  hipLaunchKernelGGL(k_topk, dim3(nvq), dim3(256), 0, st, vq, scores, K, order);
   HGRD_CHECK(hipGetLastError());
   return 0;
 }
@@ -654,9 +845,6 @@ int launch_adam(hipStream_t st, float* w, float* g, float* m, float* v, float lr
 int mlp_num_weights() { return kNW; }
 
 int init_verdict_attributes() {
-  HGRD_CHECK(hipFuncSetAttribute((const void*)k_topk,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (1 << 20) / 8));
   HGRD_CHECK(hipFuncSetAttribute((const void*)k_tile_join<1024, 2048>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)sizeof(JoinLds<1024, 2048>)));

@@ -13,7 +13,7 @@ expression: the labels used by the tests come from the oracle.
 """
 import numpy as np
 
-from .expr import bid, bdim, tid, param, loop, c, lt, ge, emin, ne
+from .expr import bid, bdim, tid, param, loop, c, lt, ge, emin, ne, eq
 from .model import (Access, Array, Launch, Loop, Model, Workload, GLOBAL,
                     SHARED, READ, WRITE, ALL_CLASSES)
 
@@ -322,6 +322,44 @@ def sparse(seed=4004, n_queries=16384, G=256, B=256, racy_frac=0.5,
                             Launch((G, 1, 1), (B, 1, 1), 32), [[]],
                             name="sparse%d" % len(models)))
     return Workload(models, pairs, name="sparse", meta={"seed": seed, "G": G})
+
+
+def sparse_overlap(seed=4004, n_queries=16384, G=256, B=256, racy_frac=0.5,
+                   queries_per_model=64):
+    """Sparse witnesses among many overlapping tiles: the ranking problem of
+    the learned tile order.  Access a writes base + 2 B bid + 2 tid (even
+    addresses, block b1 covers [2 B b1, 2 B b1 + 2 B - 2]); access b writes
+    base + 2 B bid + 2 tid + 1 (odd addresses interleaved with block bid of
+    a: G tiles whose address ranges overlap but hold no conflict).  In a
+    racy query one block c_b of b is moved onto block c_a of a with even
+    addresses (its block term gains eq(bid, c_b) * (2 B (c_a - c_b) - 1)),
+    so exactly one tile out of G * G conflicts (B conflicting thread pairs,
+    inter-block), and it overlaps as the others do.  Global int32 arrays,
+    one tuple, no loops.
+    """
+    rng = _rng(seed)
+    models, pairs = [], []
+    for q0 in range(0, n_queries, queries_per_model):
+        accs = []
+        nq = min(queries_per_model, n_queries - q0)
+        for k in range(nq):
+            racy = rng.random() < racy_frac
+            ca = int(rng.integers(0, G))
+            cb = int(rng.integers(0, G))
+            if cb == ca:
+                cb = (ca + 1) % G
+            base = int(rng.integers(0, 1 << 20)) * 4
+            ea = c(base) + bid(0) * (2 * B) + tid(0) * 2
+            eb = c(base) + bid(0) * (2 * B) + tid(0) * 2 + 1
+            if racy:
+                eb = eb + eq(bid(0), cb) * (2 * B * (ca - cb) - 1)
+            accs.append(Access(0, WRITE, ea, name="overlap a"))
+            accs.append(Access(0, WRITE, eb, name="overlap b"))
+            pairs.append((len(models), 2 * k, 2 * k + 1, ALL_CLASSES))
+        models.append(Model(0, [Array(GLOBAL, 32)], accs,
+                            Launch((G, 1, 1), (B, 1, 1), 32), [[]],
+                            name="overlap%d" % len(models)))
+    return Workload(models, pairs, name="sparse_overlap", meta={"seed": seed, "G": G})
 
 
 # ---------------------------------------------------------------------------

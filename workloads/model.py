@@ -163,3 +163,18 @@ class Workload:
         """A workload with only the pairs in ``idx`` (models kept)."""
         return Workload(self.models, [self.pairs[i] for i in idx],
                         self.name + "[subset]", self.meta)
+
+    def compact(self, idx):
+        """A workload with only the pairs in ``idx`` and the models they
+        use, renumbered in order of first use (the same queries)."""
+        remap, models, pairs = {}, [], []
+        for i in idx:
+            m, a, b, k = self.pairs[i]
+            if m not in remap:
+                remap[m] = len(models)
+                models.append(self.models[m])
+            pairs.append((remap[m], a, b, k))
+        meta = dict(self.meta)
+        if "evals" in meta:
+            meta["evals"] = [meta["evals"][i] for i in idx]
+        return Workload(models, pairs, self.name + "[compact]", meta)
