@@ -2577,8 +2577,20 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     std::vector<Chunk> l0chunks;
     for (auto& r : split) {
       const QPlan& q = plan->Q[r.h.q];
+      // distinct addresses: at most the records, and at most the widths of
+      // the two proven address ranges when both instances have tables
+      uint64_t distinct = r.R;
+      if (plan->tab_on[r.h.inst_i] && plan->tab_on[r.h.inst_j]) {
+        auto width = [&](uint32_t inst) -> __int128 {
+          const auto& ar = plan->arange[inst];
+          return ar.second < ar.first ? 0 : (__int128)ar.second - ar.first + 1;
+        };
+        __int128 w = width(r.h.inst_i);
+        if (!q.qd.self) w += width(r.h.inst_j);
+        if (w < (__int128)distinct) distinct = std::max<uint64_t>(1, (uint64_t)w);
+      }
       uint64_t t = 1;
-      while (t < 2 * r.R) t <<= 1;
+      while (t < 2 * distinct) t <<= 1;
       r.h.shared = 3;
       r.h.l0_off = slots;
       r.h.l0_mask = (uint32_t)(t - 1);
