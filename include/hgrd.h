@@ -307,6 +307,33 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
                    const rd_param_sets* params, const rd_options* opt,
                    rd_pair_result* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * query as rd_check_pairs, same arguments, same results, but every device
+ * buffer it needs (descriptors, term tables, accumulators, HBM bucket
+ * records, re-partition and fallback scratch, results) comes from one
+ * fixed scratch area of RD_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends; the call makes no hipMalloc,
+ * hipFree or other allocating call, captures no graph and creates no event.
+ * `ctx` must come from rd_context_create (which looks the area up on its
+ * device).  Inputs stay caller-owned host memory, `out` caller-owned host
+ * memory of n_pairs entries, as for rd_check_pairs.  Without an explicit
+ * opt->max_device_bytes each partition wave takes an eighth of the area.
+ * Returns the statuses of rd_check_pairs, and RD_ECAPACITY (with a message
+ * on stderr naming the buffer that did not fit, `out` unspecified) when the
+ * batch needs more than the area: split the batch or use rd_check_pairs.
+ * The area keeps the last call's contents (every call clears what it
+ * reads first).  Calls on one GPU share its area: within one process they
+ * are serialised by a lock; work the caller overlaps with a call on the
+ * same area from outside the library (e.g. a replayed graph of an earlier
+ * call's kernels) races with it. */
+#define RD_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int rd_check_pairs_noalloc(rd_context* ctx, const rd_kernel_model* models,
+                           uint32_t n_models, const rd_access_pair* pairs,
+                           uint32_t n_pairs, const rd_launch_domain* launch,
+                           const rd_param_sets* params, const rd_options* opt,
+                           rd_pair_result* out);
+
 /* Two-step use of the same query: rd_prepare validates, lowers and plans
  * the batch and copies every descriptor to device memory; rd_execute runs
  * the kernels and returns the results, and may be called any number of

@@ -168,6 +168,8 @@ def lib():
             C.POINTER(rd_access_pair), C.c_uint32, C.POINTER(rd_launch_domain),
             C.POINTER(rd_param_sets), C.POINTER(rd_options),
             C.POINTER(rd_pair_result)]
+        L.rd_check_pairs_noalloc.restype = C.c_int
+        L.rd_check_pairs_noalloc.argtypes = L.rd_check_pairs.argtypes
         L.rd_prepare.restype = C.c_int
         L.rd_prepare.argtypes = [
             C.c_void_p, C.POINTER(rd_kernel_model), C.c_uint32,
@@ -416,6 +418,26 @@ def rd_check_pairs(ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
     if st != RD_OK:
         raise RuntimeError("rd_check_pairs failed: %s" % rd_strerror(st))
     return [result_dict(out[k]) for k in range(n)]
+
+
+def rd_check_pairs_noalloc(ctx, workload, mode=MODE_EXACT, order=ORDER_LEX,
+                           lds_cap=0, max_device_bytes=0, log_level=0, stream=None,
+                           packed=None, mlp=None, tile_budget=0, prefilter=0):
+    """rd_check_pairs inside the library's fixed scratch area (no device
+    allocation).  Returns (status, results): status is RD_OK or the
+    library's error (RD_ECAPACITY when the batch does not fit the area);
+    results is None unless the status is RD_OK."""
+    pk = packed or Packed(workload)
+    n = len(workload.pairs)
+    pairs = _pairs(workload)
+    out = (rd_pair_result * max(1, n))()
+    opt, keep = _options(mode, order, lds_cap, max_device_bytes, log_level,
+                         stream, mlp, tile_budget, prefilter)
+    st = lib().rd_check_pairs_noalloc(ctx.h, pk.models, pk.n_models, pairs, n,
+                                      pk.launch, pk.params, C.byref(opt), out)
+    if st != RD_OK:
+        return st, None
+    return st, [result_dict(out[k]) for k in range(n)]
 
 
 def rd_autotune(ctx, workload, reps=3, mode=MODE_EXACT, order=ORDER_LEX,

@@ -310,7 +310,37 @@ const uint16_t kUpdOp[] = {RD_OP_ADD, RD_OP_SUB, RD_OP_MUL, RD_OP_DIV,
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool own = true;  // false: carved from a caller's arena, never freed here
 };
+
+// Caller-provided device memory handed out front to back (256-byte
+// aligned).  Nothing is ever returned to it during a call; the caller
+// resets `used` between calls.
+struct Arena {
+  unsigned char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+
+// A named buffer of at least `bytes` from the arena: the one already
+// carved under that name when it is large enough, else a new piece.
+// RD_ECAPACITY (with a message naming the buffer) when the arena is full.
+void* arena_buf(Arena& A, DevBuf& b, const char* name, size_t bytes, int* err) {
+  if (bytes == 0) bytes = 256;
+  if (b.p && b.cap >= bytes) return b.p;
+  const size_t at = (A.used + 255) & ~(size_t)255;
+  if (at > A.cap || bytes > A.cap - at) {
+    fprintf(stderr,
+            "hgrd: the fixed scratch area (%zu bytes) cannot hold '%s' (%zu bytes, "
+            "%zu already in use)\n", A.cap, name, bytes, at);
+    if (!*err) *err = RD_ECAPACITY;
+    return nullptr;
+  }
+  b.p = A.base + at;
+  b.cap = bytes;
+  b.own = false;
+  A.used = at + bytes;
+  return b.p;
+}
 
 uint64_t next_prime(uint64_t n) {
   if (n <= 2) return 2;
@@ -374,6 +404,11 @@ double now_ms() {
 struct rd_context {
   int device = 0;
   std::map<std::string, DevBuf> bufs;
+  // While set (rd_check_pairs_noalloc), every device buffer of the context
+  // and of its plans is carved from this arena instead of hipMalloc;
+  // abufs names the arena's buffers and is emptied when the arena is unset.
+  Arena* arena = nullptr;
+  std::map<std::string, DevBuf> abufs;
   rd_stats stats;
   int cfg = 0;  // LDS tile shape: 1024 records, 2048 slots (rd_autotune may change it)
   uint32_t n_cu = 256;
@@ -382,6 +417,7 @@ struct rd_context {
   hipEvent_t ev[16];
   std::vector<hipEvent_t> wev;    // per-wave timing events
   void* ensure(const char* name, size_t bytes, int* err) {
+    if (arena) return arena_buf(*arena, abufs[name], name, bytes, err);
     DevBuf& b = bufs[name];
     if (bytes == 0) bytes = 256;
     if (b.cap < bytes) {
@@ -1405,7 +1441,8 @@ int rd_context_create(rd_context** ctx, int hip_device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess)
     c->n_cu = (uint32_t)prop.multiProcessorCount;
-  if (hipStreamCreate(&c->stream) != hipSuccess || init_kernel_attributes() != 0) {
+  if (hipStreamCreate(&c->stream) != hipSuccess || init_kernel_attributes() != 0 ||
+      noalloc_scratch_init(hip_device) != 0) {
     delete c;
     return RD_EDEVICE;
   }
@@ -1417,7 +1454,7 @@ void rd_context_destroy(rd_context* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   for (auto& kv : ctx->bufs)
-    if (kv.second.p) (void)hipFree(kv.second.p);
+    if (kv.second.p && kv.second.own) (void)hipFree(kv.second.p);
   for (auto& e : ctx->ev) (void)hipEventDestroy(e);
   for (auto& e : ctx->wev) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -1480,8 +1517,10 @@ struct rd_plan_impl {
   uint32_t n_vqueries_pairs = 0;
   std::vector<VQuery> vqs;
   std::map<std::string, DevBuf> dev;
+  Arena* arena = nullptr;  // the context's arena when the plan was made
   void* buf(const char* name, size_t bytes, int* err) {
     DevBuf& b = dev[name];
+    if (arena) return arena_buf(*arena, b, name, bytes, err);
     if (bytes == 0) bytes = 256;
     if (b.cap < bytes) {
       if (b.p) (void)hipFree(b.p);
@@ -1505,7 +1544,7 @@ struct rd_plan_impl {
   ~rd_plan_impl() {
     if (graph) (void)hipGraphExecDestroy(graph);
     for (auto& kv : dev)
-      if (kv.second.p) (void)hipFree(kv.second.p);
+      if (kv.second.p && kv.second.own) (void)hipFree(kv.second.p);
   }
 };
 
@@ -1527,6 +1566,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
   rd_plan* plan = new rd_plan();
   std::unique_ptr<rd_plan> guard(plan);
+  plan->arena = ctx->arena;
   plan->n_pairs = n_pairs;
   plan->st = o.stream ? (hipStream_t)o.stream : ctx->stream;
   plan->log_level = o.log_level;
@@ -2218,6 +2258,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
                        const BRun* d_bit, uint32_t* d_ovf, int wcfg,
                        const u64* l0k, const u64* l0c, bool events) -> int {
     const uint32_t wcap = (uint32_t)join_cap(wcfg);
+    events = events && !plan->arena;  // no event is created in an arena call
     for (const auto& W : waves) {
       const uint32_t k = wev_n;
       hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr,
@@ -2369,7 +2410,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
 
   TRY_HIP(hipEventRecord(ev[0], st));
   bool replayed = false;
-  if (!timing && !plan->graph_failed && !plan->graph) {
+  // (an arena call captures nothing: instantiating a graph allocates)
+  if (!timing && !plan->graph_failed && !plan->graph && !plan->arena) {
     // capture once; any failure falls back to eager launches for this plan
     hipGraph_t g = nullptr;
     bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -2850,6 +2892,41 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
   rd_plan_destroy(plan);
   return rc;
 }
+
+}  // extern "C"
+
+int hgrd::context_device(const rd_context* ctx) { return ctx->device; }
+
+// rd_check_pairs inside a caller's arena: the plan and every later phase
+// take their device buffers from it, no graph is captured and no event is
+// created.  Without an explicit wave size the partition waves get an
+// eighth of the arena (the first phase and a re-partition round each hold
+// one wave of buckets).
+int hgrd::check_pairs_in_arena(rd_context* ctx, void* base, size_t cap,
+                               const rd_kernel_model* models, uint32_t n_models,
+                               const rd_access_pair* pairs, uint32_t n_pairs,
+                               const rd_launch_domain* launch,
+                               const rd_param_sets* params, const rd_options* opt,
+                               rd_pair_result* out) {
+  if (!ctx || !base) return RD_EINVAL;
+  rd_options o;
+  memset(&o, 0, sizeof o);
+  if (opt) o = *opt;
+  if (!o.max_device_bytes) o.max_device_bytes = cap / 8;
+  Arena A;
+  A.base = (unsigned char*)base;
+  A.cap = cap;
+  ctx->arena = &A;
+  const int rc = rd_check_pairs(ctx, models, n_models, pairs, n_pairs, launch, params, &o, out);
+  // an error may leave kernels of this call in flight: the area is free
+  // again only once they have finished
+  if (rc != RD_OK) (void)hipStreamSynchronize(o.stream ? (hipStream_t)o.stream : ctx->stream);
+  ctx->arena = nullptr;
+  ctx->abufs.clear();
+  return rc;
+}
+
+extern "C" {
 
 int rd_autotune(rd_context* ctx, const rd_kernel_model* models,
                 uint32_t n_models, const rd_access_pair* pairs,

@@ -112,4 +112,18 @@ int launch_adam(hipStream_t st, float* w, float* g, float* m, float* v,
                 float lr, int t);
 int mlp_num_weights();
 
+// The fixed scratch area of rd_check_pairs_noalloc (hgrd_noalloc.cpp):
+// looks up its device address on `device` (the current device) once and
+// keeps it; nonzero when the lookup fails.
+int noalloc_scratch_init(int device);
+// The HIP device a context was created on.
+int context_device(const rd_context* ctx);
+// rd_check_pairs with every device buffer carved from [base, base + cap)
+// (hgrd_host.cpp); RD_ECAPACITY when the batch needs more.
+int check_pairs_in_arena(rd_context* ctx, void* base, size_t cap,
+                         const rd_kernel_model* models, uint32_t n_models,
+                         const rd_access_pair* pairs, uint32_t n_pairs,
+                         const rd_launch_domain* launch, const rd_param_sets* params,
+                         const rd_options* opt, rd_pair_result* out);
+
 }  // namespace hgrd
