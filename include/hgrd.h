@@ -412,6 +412,13 @@ typedef struct {
                                    join), timed in filter_tab_ms */
   double filter_tab_ms;      /* their summed duration */
   uint64_t filter_tab_bytes; /* record bytes they read */
+  uint64_t units_apart;      /* HBM items the unit filter decided: their two
+                                accesses share no address (proven address
+                                ranges apart, or residues that differ), so
+                                nothing of them is partitioned or joined;
+                                small items are decided the same way inside
+                                the LDS join (not counted).  The environment
+                                variable HGRD_NO_UNIT_FILTER turns it off */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

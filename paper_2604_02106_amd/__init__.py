@@ -135,7 +135,8 @@ class rd_stats(C.Structure):
                 ("join_tab_ms", C.c_double), ("join_tab_bytes", C.c_uint64),
                 ("presplit_items", C.c_uint64),
                 ("filter_tab_launches", C.c_uint64), ("filter_tab_ms", C.c_double),
-                ("filter_tab_bytes", C.c_uint64)]
+                ("filter_tab_bytes", C.c_uint64),
+                ("units_apart", C.c_uint64)]
 
 
 assert C.sizeof(rd_pair_result) == 88

@@ -304,6 +304,36 @@ __device__ __forceinline__ void load_inst(DevInst& D,
 }
 
 // ---------------------------------------------------------------------------
+// Exact unit test: two access instances of one tuple share no address when
+// their proven address ranges do not meet, or when their residues differ:
+// addresses of a are u_a + k G_a, of b u_b + k G_b, and a common one needs
+// gcd(G_a, G_b) | u_a - u_b.  False whenever nothing is known.
+
+__device__ __forceinline__ u64 gcd_u64(u64 a, u64 b) {
+  while (b) {
+    const u64 t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// x mod g in [0, g) for any int64 x and g > 0 (no signed overflow).
+__device__ __forceinline__ u64 mod_u64(long long x, u64 g) {
+  if (x >= 0) return (u64)x % g;
+  const u64 m = (u64)(-(x + 1));  // x = -(m + 1)
+  return g - 1 - m % g;
+}
+
+__device__ __forceinline__ bool facts_apart(const IFact& a, const IFact& b) {
+  if (!a.on || !b.on) return false;
+  if (a.hi < b.lo || b.hi < a.lo) return true;
+  const u64 g = gcd_u64(a.G, b.G);
+  if (g == 0) return a.u != b.u;
+  return mod_u64(a.u, g) != mod_u64(b.u, g);
+}
+
+// ---------------------------------------------------------------------------
 // Reductions.
 
 __device__ __forceinline__ u64 wave_sum(u64 v) {

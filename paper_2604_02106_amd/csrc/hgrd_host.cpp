@@ -2133,6 +2133,20 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   up("hitems", plan->hitems.data(), plan->hitems.size() * sizeof(HItem));
   up("chunks", all_chunks.data(), all_chunks.size() * sizeof(Chunk));
   up("runs", all_runs.data(), all_runs.size() * sizeof(BRun));
+  {
+    // proven facts per instance for the unit filter of rd_execute
+    std::vector<IFact> facts(std::max<size_t>(1, P.dev_insts.size()));
+    memset(facts.data(), 0, facts.size() * sizeof(IFact));
+    for (size_t i = 0; i < P.dev_insts.size(); ++i) {
+      if (!P.tabs[i].on) continue;
+      facts[i].lo = P.arange[i].first;
+      facts[i].hi = P.arange[i].second;
+      facts[i].G = P.ares[i].first;
+      facts[i].u = P.ares[i].second;
+      facts[i].on = 1;
+    }
+    up("ifacts", facts.data(), facts.size() * sizeof(IFact));
+  }
   if (plan->verdict) {
     up("vq", vqs.data(), vqs.size() * sizeof(VQuery));
     up("bitems", bitems.data(), bitems.size() * sizeof(BItem));
@@ -2224,6 +2238,10 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   // the exact address filter in front of the bucket join (HGRD_NO_FILTER
   // turns it off: every bucket is joined)
   const bool use_filter = getenv("HGRD_NO_FILTER") == nullptr;
+  // the unit filter (items whose accesses share no address do nothing;
+  // HGRD_NO_UNIT_FILTER turns it off)
+  const IFact* d_facts =
+      getenv("HGRD_NO_UNIT_FILTER") == nullptr ? (const IFact*)D("ifacts") : nullptr;
   uint32_t* d_done = (uint32_t*)D("done");
   uint32_t* d_pcursor = (uint32_t*)D("pcursor");
   u64* d_nbytes = (u64*)D("nbytes");
@@ -2390,7 +2408,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     if (plan->n_sitems) {
       if (events) TRY_HIP(hipEventRecord(ev[2], st));
       if (launch_small(cfg, st, d_sitems, plan->n_sitems, d_insts, d_code, d_params,
-                       d_loops, d_qd, d_acc, d_done, d_pcursor, plan->persist_grid))
+                       d_loops, d_qd, d_acc, d_done, d_pcursor, plan->persist_grid, d_facts))
         return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(ev[3], st));
       S.join_launches += 1;
@@ -2399,6 +2417,10 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     // order
     if (nh) {
       if (launch_fill_u32(st, d_ovf_all, nh, 0)) return RD_EDEVICE;
+      // items counted in nbytes[500]
+      if (d_facts && launch_unit_filter(st, nh, d_hitems_all, d_qd, d_facts, d_ovf_all,
+                                        d_nbytes + 500))
+        return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(ev[11], st));
       int rc = run_waves(plan->waves, d_hitems_all, d_chunks_all, d_runs_all,
                          d_ovf_all, cfg, nullptr, nullptr, events);
@@ -2562,6 +2584,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   std::vector<RItem> rit;
   std::vector<RItem> still;
   for (uint32_t i = 0; i < nh; ++i) {
+    if (ovf[i] == kApart) continue;  // decided by the unit filter
     if ((!ovf[i] && !plan->presplit[i]) || plan->hitems[i].shared == 2) continue;
     RItem r{plan->hitems[i], plan->hR[i]};
     if (r.h.mode && r.h.shared == 0) {
@@ -2841,6 +2864,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   u64 scat_bytes[512];
   TRY_HIP(hipMemcpyAsync(scat_bytes, d_nbytes, sizeof scat_bytes, hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
+  S.units_apart = scat_bytes[500];  // HBM items the unit filter decided
   for (int k = 0; k < 128; ++k) {
     S.scatter_bytes += scat_bytes[k];
     if (k < 64) S.scatter_tab_bytes += scat_bytes[k];

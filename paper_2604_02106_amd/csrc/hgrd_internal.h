@@ -124,6 +124,20 @@ __host__ __device__ inline unsigned long long pkey(uint32_t s, uint32_t b,
 }
 constexpr unsigned long long kNoKey = ~0ull;
 
+// Facts about one access instance that its lowering proved (instances
+// with term tables only): every address lies in [lo, hi] and is congruent
+// to u modulo G (G = 0: every address equals u).  on = 0: nothing known.
+struct IFact {
+  long long lo, hi;
+  unsigned long long G;
+  long long u;
+  uint32_t on, pad[3];
+};
+static_assert(sizeof(IFact) == 48, "IFact layout");
+// ovf mark of an HBM item whose two accesses share no address (decided by
+// the unit filter at the start of an execute): nothing to partition.
+constexpr uint32_t kApart = 0xFFFFFFFFu;
+
 // Work item joined in one workgroup's LDS: both sides of query q under
 // tuple `sigma`, blocks [b0, b1).
 struct SItem {

@@ -46,9 +46,14 @@ __device__ __forceinline__ void small_item(JoinLds<CAP, TBL>& S, const SItem& it
                                            const int64_t* __restrict__ loopvals,
                                            const QDesc* __restrict__ qd,
                                            QAcc* __restrict__ acc,
-                                           const uint32_t* __restrict__ done) {
+                                           const uint32_t* __restrict__ done,
+                                           const IFact* __restrict__ facts) {
   if (done[it.q]) return;
   const QDesc q = qd[it.q];
+  // two accesses proven never to share an address: nothing to join
+  if (facts && !q.self && it.inst_i != it.inst_j &&
+      facts_apart(facts[it.inst_i], facts[it.inst_j]))
+    return;
   if (threadIdx.x == 0) {
     S.n = 0;
     S.err = 0;
@@ -91,10 +96,11 @@ __global__ void __launch_bounds__(256)
 k_small_join(const SItem* __restrict__ items, const DevInst* __restrict__ insts,
              const DInsn* __restrict__ code, const int64_t* __restrict__ params,
              const int64_t* __restrict__ loopvals, const QDesc* __restrict__ qd,
-             QAcc* __restrict__ acc, const uint32_t* __restrict__ done) {
+             QAcc* __restrict__ acc, const uint32_t* __restrict__ done,
+             const IFact* __restrict__ facts) {
   extern __shared__ __align__(16) unsigned char smem[];
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
-  small_item(S, items[blockIdx.x], insts, code, params, loopvals, qd, acc, done);
+  small_item(S, items[blockIdx.x], insts, code, params, loopvals, qd, acc, done, facts);
 }
 
 // Persistent form: a grid sized to the machine pops items (largest first,
@@ -107,7 +113,8 @@ k_small_persist(const SItem* __restrict__ items, uint32_t n,
                 uint32_t* __restrict__ cursor, const DevInst* __restrict__ insts,
                 const DInsn* __restrict__ code, const int64_t* __restrict__ params,
                 const int64_t* __restrict__ loopvals, const QDesc* __restrict__ qd,
-                QAcc* __restrict__ acc, const uint32_t* __restrict__ done) {
+                QAcc* __restrict__ acc, const uint32_t* __restrict__ done,
+                const IFact* __restrict__ facts) {
   extern __shared__ __align__(16) unsigned char smem[];
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
   __shared__ uint32_t cur;
@@ -119,7 +126,7 @@ k_small_persist(const SItem* __restrict__ items, uint32_t n,
     if (k0 >= n) break;
     const uint32_t k1 = min(n, k0 + kSmallPop);
     for (uint32_t k = k0; k < k1; ++k) {
-      small_item(S, items[k], insts, code, params, loopvals, qd, acc, done);
+      small_item(S, items[k], insts, code, params, loopvals, qd, acc, done, facts);
       __syncthreads();
     }
   }
@@ -222,7 +229,7 @@ k_scatter(const Chunk* __restrict__ chunks, const HItem* __restrict__ hitems,
   __shared__ u64 sbytes;
   const Chunk ch = chunks[blockIdx.x];
   const HItem h = hitems[ch.item];
-  if (done[h.q]) return;
+  if (done[h.q] || ovf[ch.item] == kApart) return;
   DevInst I;
   load_inst(I, insts, ch.side ? h.inst_j : h.inst_i);
   uint32_t err = 0;
@@ -483,77 +490,146 @@ __global__ void k_apply_s0(uint32_t n, const L0Item* __restrict__ items,
   atomicAdd(&acc[items[k].q].cnt[0], s0[k]);
 }
 
+// Unit filter of the HBM items: an item whose two accesses are proven never
+// to share an address (facts_apart) is marked kApart in ovf, so that its
+// partition, address filter and join do nothing and no later phase takes
+// it up.  Error-scan items, self pairs and items without facts stay.  The
+// marked items are counted in *napart.
+__global__ void k_unit_filter(uint32_t n, const HItem* __restrict__ hitems,
+                              const QDesc* __restrict__ qd,
+                              const IFact* __restrict__ facts,
+                              uint32_t* __restrict__ ovf, u64* __restrict__ napart) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  bool apart = false;
+  if (k < n) {
+    const HItem h = hitems[k];
+    apart = h.shared != 2 && h.inst_i != h.inst_j && !qd[h.q].self &&
+            facts_apart(facts[h.inst_i], facts[h.inst_j]);
+    if (apart) ovf[k] = kApart;
+  }
+  const u64 c = (u64)__popcll(__ballot(apart));
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(napart, c);
+}
+
 // ---------------------------------------------------------------------------
-// Kernel: exact address filter of HBM buckets, one wavefront per bucket.
+// Kernel: exact filter of HBM buckets, one workgroup per run of buckets of
+// one item, all its threads on one bucket at a time.
 //
-// Every conflict needs two records of one bucket with equal addresses (and
-// equal blocks for shared arrays), one from each access (for a self pair:
-// two records).  Each wavefront owns one bucket at a time and a private
-// LDS hash table of record indices: side-a records are inserted, then
-// side-b records probe it (a self pair inserts every record and looks for
-// a duplicate).  The bucket goes on to the join only if some record finds
-// a partner; a bucket without one can hold no conflict at any level, so
-// skipping it is exact.  No barrier is needed: the table belongs to one
-// wavefront, whose LDS operations complete in program order.  Items split
-// by (address, block) (their level 0 is counted elsewhere) always go on.
+// A conflict needs two records of one bucket with equal addresses (and
+// equal blocks for shared arrays, whose memory is per block) that belong to
+// two different threads, one record from each access (for a self pair: any
+// two records).  The workgroup keeps an LDS open-addressing table of 2 CAP
+// 64-bit slots, a slot holding key << 32 | owner: key is the address itself
+// for a 32-bit global array, otherwise a 32-bit hash of the address (and
+// the block); owner is 1 + the thread id (block * threads per block +
+// thread) of the first side-a record that brought the key, or kMulti once
+// records of two different threads brought it.  Side-a records (every
+// record of a self pair) are inserted; a self-pair record that finds its
+// key there from another thread has a partner.  Side-b records then look
+// their key up and have a partner when it is there from another thread.
+// The bucket goes on to the join only if some record has a partner.  Keys
+// that only hash alike can keep a bucket but never drop one, so skipping a
+// bucket without partners is exact.  When thread ids of the launch do not
+// fit 32 bits, owners are kMulti from the start (an address test alone).
+// Items split by (address, block) (their level 0 is counted elsewhere)
+// always go on.
 
 constexpr uint32_t kFilterThreads = 256;
+constexpr uint32_t kMulti = 0xFFFFFFFFu;
 
 template <int CAP>
 struct FilterLds {
-  uint32_t owner[2 * CAP];  // record index + 1, 0 = empty
-  u64 key[CAP];             // record address
-  uint32_t blk[CAP];        // record block (shared arrays), else 0
+  u64 slot[2 * CAP];
+  uint32_t vote[2];
 };
 
-template <int CAP>
-constexpr uint32_t filter_waves() {
-  return CAP <= 1024 ? 4u : (CAP <= 1536 ? 2u : 1u);
+// What a record needs from its side's instance: points per block, the
+// point order inside a block and the thread / iteration extents.
+struct SideGeo {
+  uint32_t tpb, iorder, nthr, niota;
+  FastDiv f_tpb, f_nthr, f_niota;
+};
+
+__device__ __forceinline__ SideGeo side_geo(const DevInst* __restrict__ insts, uint32_t k) {
+  k = __builtin_amdgcn_readfirstlane(k);
+  const DevInst& I = insts[k];
+  SideGeo g;
+  g.tpb = I.a.tpb;
+  g.iorder = I.a.iorder;
+  g.nthr = I.a.nthr;
+  g.niota = I.a.niota;
+  g.f_nthr = I.f_nthr;
+  g.f_niota = I.f_niota;
+  g.f_tpb = make_fastdiv(g.tpb);
+  return g;
 }
 
-__device__ __forceinline__ uint32_t filter_slot(u64 a, uint32_t b, uint32_t mask) {
+// Block and thread of point index p (the block is the slowest coordinate).
+__device__ __forceinline__ void block_thread(const SideGeo& g, uint32_t p, uint32_t& b,
+                                             uint32_t& t) {
+  b = fdiv(p, g.f_tpb);
+  const uint32_t in = p - b * g.tpb;
+  if (g.iorder) t = fdiv(in, g.f_niota);
+  else t = in - fdiv(in, g.f_nthr) * g.nthr;
+}
+
+__device__ __forceinline__ uint32_t filter_key(u64 a, uint32_t b, bool exact32) {
+  if (exact32) return (uint32_t)a;
   uint32_t x = (uint32_t)a * 0x9E3779B1u ^ (uint32_t)(a >> 32) * 0x85EBCA77u ^
                b * 0xC2B2AE3Du;
   x ^= x >> 15;
   x *= 0x2C1B3C6Du;
   x ^= x >> 12;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t filter_slot(uint32_t key, uint32_t mask) {
+  uint32_t x = key * 0x9E3779B1u;
+  x ^= x >> 16;
+  x *= 0x85EBCA6Bu;
+  x ^= x >> 13;
   return x & mask;
 }
 
 template <int CAP>
 __global__ void __launch_bounds__(kFilterThreads)
 k_bucket_filter(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
-                const QDesc* __restrict__ qd, const unsigned char* __restrict__ recs,
+                const QDesc* __restrict__ qd, const DevInst* __restrict__ insts,
+                const unsigned char* __restrict__ recs,
                 const uint32_t* __restrict__ cursor, const uint32_t* __restrict__ ovf,
                 const uint32_t* __restrict__ done, uint8_t* __restrict__ cand,
                 u64* __restrict__ nbytes) {
-  constexpr uint32_t NW = filter_waves<CAP>();
-  constexpr int RPT = CAP / 64;
+  constexpr int RPT = CAP / kFilterThreads;
+  constexpr uint32_t mask = 2 * CAP - 1;
+  static_assert(CAP % kFilterThreads == 0, "filter records per thread");
+  static_assert((2 * CAP * 8) % (16 * kFilterThreads) == 0, "filter table clear");
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  FilterLds<CAP>& T = reinterpret_cast<FilterLds<CAP>*>(smem)[wv];
+  FilterLds<CAP>& T = *reinterpret_cast<FilterLds<CAP>*>(smem);
   const BRun R = runs[blockIdx.x];
   const HItem h = hitems[R.item];
   if (ovf[R.item] || done[h.q]) return;  // the join skips these runs too
+  if (h.shared == 3) {  // level 0 counted per address: always joined
+    for (uint32_t b = R.b0 + threadIdx.x; b < R.b1; b += kFilterThreads)
+      cand[h.bucket0 + b] = 1;
+    return;
+  }
   const bool self = qd[h.q].self != 0;
   const bool shared = h.shared == 1;
   const bool is32 = h.is32 != 0;
+  const bool exact32 = is32 && !shared;  // the key is the address itself
+  const SideGeo ga = side_geo(insts, h.inst_i);
+  const SideGeo gb = self ? ga : side_geo(insts, h.inst_j);
+  // thread ids below kMulti - 1 (same launch on both sides)
+  const uint32_t nblk = insts[__builtin_amdgcn_readfirstlane(h.inst_i)].a.nblk;
+  const bool tid_ok = (u64)nblk * ga.nthr < (u64)kMulti - 1;
   const u64* r8 = reinterpret_cast<const u64*>(recs + h.rec_off);
   const ulonglong2* r16 = reinterpret_cast<const ulonglong2*>(recs + h.rec_off);
-  u64 nread = 0;
-  for (uint32_t b = R.b0 + wv; b < R.b1; b += NW) {
-    const uint32_t gb = h.bucket0 + b;
-    if (h.shared == 3) {  // level 0 counted per address: always joined
-      if (lane == 0) cand[gb] = 1;
-      continue;
-    }
-    const uint32_t n = min(cursor[gb], (uint32_t)CAP);
-    nread += (u64)n * (is32 ? 8u : 16u);
-    u64 ad[RPT];
-    uint32_t pid[RPT];
+  u64 ad[RPT];
+  uint32_t pid[RPT];
+  auto fetch = [&](uint32_t b, uint32_t n) {
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      const uint32_t r = (uint32_t)j * 64 + lane;
+      const uint32_t r = (uint32_t)j * kFilterThreads + threadIdx.x;
       ad[j] = 0;
       pid[j] = 0;
       if (r < n) {
@@ -568,74 +644,89 @@ k_bucket_filter(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
         }
       }
     }
-    // table of 2 * CAP slots, cleared with 16-byte stores
-    uint4* o4 = reinterpret_cast<uint4*>(T.owner);
-    static_assert((2 * CAP) % 256 == 0, "filter table clear");
-#pragma unroll
-    for (uint32_t k = 0; k < (2 * CAP) / 256; ++k) o4[k * 64 + lane] = make_uint4(0, 0, 0, 0);
-    uint32_t bk[RPT];
+  };
+  if (threadIdx.x < 2) T.vote[threadIdx.x] = 0;  // ordered by the first barrier
+  u64 nread = 0;  // record bytes read (every thread counts; thread 0 adds)
+  uint32_t n = R.b0 < R.b1 ? min(cursor[h.bucket0 + R.b0], (uint32_t)CAP) : 0;
+  if (R.b0 < R.b1) fetch(R.b0, n);
+  for (uint32_t b = R.b0; b < R.b1; ++b) {
+    const uint32_t gbk = h.bucket0 + b;
+    nread += (u64)n * (is32 ? 8u : 16u);
+    // keys and owners of this bucket's records
+    uint32_t key[RPT], own[RPT];
+    bool sb[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      const uint32_t r = (uint32_t)j * 64 + lane;
-      bk[j] = 0;
-      if (shared && r < n) {
-        // shared memory is per block: the block joins the address
-        const uint32_t sd = pid[j] >> 31, p = pid[j] & 0x7FFFFFFFu;
-        const uint32_t m = sd ? h.tpb_m[1] : h.tpb_m[0];
-        const uint32_t sh = sd ? h.tpb_s[1] : h.tpb_s[0];
-        bk[j] = (__umulhi(m, p) + p) >> sh;
-      }
-      if (r < n) {
-        T.key[r] = ad[j];
-        T.blk[r] = bk[j];
-      }
+      sb[j] = (pid[j] >> 31) != 0;
+      const SideGeo& g = sb[j] ? gb : ga;
+      uint32_t bl, tl;
+      block_thread(g, pid[j] & 0x7FFFFFFFu, bl, tl);
+      key[j] = filter_key(ad[j], shared ? bl : 0u, exact32);
+      own[j] = tid_ok ? bl * ga.nthr + tl + 1 : kMulti;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    constexpr uint32_t mask = 2 * CAP - 1;
+    const uint32_t nb = n;
+    // the next bucket's records load while this one is filtered
+    if (b + 1 < R.b1) {
+      n = min(cursor[gbk + 1], (uint32_t)CAP);
+      fetch(b + 1, n);
+    }
+    // clear the table (the previous bucket's lookups ended at its vote)
+    uint4* t4 = reinterpret_cast<uint4*>(T.slot);
+#pragma unroll
+    for (uint32_t k = 0; k < (2 * CAP * 8) / (16 * kFilterThreads); ++k)
+      t4[k * kFilterThreads + threadIdx.x] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
     bool found = false;
     // side a (every record of a self pair) inserts
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      const uint32_t r = (uint32_t)j * 64 + lane;
-      if (r >= n || (!self && (pid[j] >> 31))) continue;
-      uint32_t sl = filter_slot(ad[j], bk[j], mask);
+      const uint32_t r = (uint32_t)j * kFilterThreads + threadIdx.x;
+      if (r >= nb || (!self && sb[j])) continue;
+      const u64 v = ((u64)key[j] << 32) | own[j];
+      uint32_t sl = filter_slot(key[j], mask);
       for (;;) {
-        const uint32_t o = atomicCAS(&T.owner[sl], 0u, r + 1);
+        u64 o = atomicCAS(&T.slot[sl], 0ull, v);
         if (o == 0) break;
-        if (T.key[o - 1] == ad[j] && T.blk[o - 1] == bk[j]) {
-          found |= self;  // a second record of the address
+        if ((uint32_t)(o >> 32) == key[j]) {
+          uint32_t ow = (uint32_t)o;
+          if (ow != own[j] || ow == kMulti) {
+            found |= self;
+            // two threads of side a hold the key (monotone: the owner only
+            // ever becomes kMulti, so a failed swap means it already is)
+            if (!self && ow != kMulti)
+              (void)atomicCAS(&T.slot[sl], o, ((u64)key[j] << 32) | kMulti);
+          }
           break;
         }
         sl = (sl + 1) & mask;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    // side b probes
+    __syncthreads();
+    // side b looks up
     if (!self) {
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
-        const uint32_t r = (uint32_t)j * 64 + lane;
-        if (r >= n || !(pid[j] >> 31)) continue;
-        uint32_t sl = filter_slot(ad[j], bk[j], mask);
+        const uint32_t r = (uint32_t)j * kFilterThreads + threadIdx.x;
+        if (r >= nb || !sb[j]) continue;
+        uint32_t sl = filter_slot(key[j], mask);
         for (;;) {
-          const uint32_t o = T.owner[sl];
+          const u64 o = T.slot[sl];
           if (o == 0) break;
-          if (T.key[o - 1] == ad[j] && T.blk[o - 1] == bk[j]) {
-            found = true;
+          if ((uint32_t)(o >> 32) == key[j]) {
+            const uint32_t ow = (uint32_t)o;
+            found |= ow != own[j] || ow == kMulti;
             break;
           }
           sl = (sl + 1) & mask;
         }
       }
     }
-    const bool any = __ballot(found) != 0;
-    if (lane == 0) cand[gb] = any ? 1 : 0;
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    // tag b + 1 on the word of b's parity (its previous vote, bucket b - 2,
+    // was read before this bucket's first barrier)
+    const bool any = block_vote(found, &T.vote[b & 1], b + 1);
+    if (threadIdx.x == 0) cand[gbk] = any ? 1 : 0;
   }
-  if (lane == 0 && nread) atomicAdd(&nbytes[blockIdx.x & (kByteSlots - 1)], nread);
+  if (threadIdx.x == 0 && nread) atomicAdd(&nbytes[blockIdx.x & (kByteSlots - 1)], nread);
 }
 
 // ---------------------------------------------------------------------------
@@ -1218,20 +1309,20 @@ static int launch_small_t(hipStream_t st, const SItem* items, uint32_t n,
                           const DevInst* insts, const DInsn* code,
                           const int64_t* params, const int64_t* loopvals,
                           const QDesc* qd, QAcc* acc, const uint32_t* done,
-                          uint32_t* cursor, uint32_t persist_grid) {
+                          uint32_t* cursor, uint32_t persist_grid, const IFact* facts) {
   size_t lds = sizeof(JoinLds<CAP, TBL>);
   if (cursor) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, cursor, 1u, 0u);
     hipLaunchKernelGGL((k_small_persist<CAP, TBL>), dim3(persist_grid), dim3(256),
                        lds, st, items, n, cursor, insts, code, params, loopvals,
-                       qd, acc, done);
+                       qd, acc, done, facts);
     HGRD_CHECK(hipGetLastError());
     return 0;
   }
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
     hipLaunchKernelGGL((k_small_join<CAP, TBL>), dim3(m), dim3(256), lds, st,
-                       items + off, insts, code, params, loopvals, qd, acc, done);
+                       items + off, insts, code, params, loopvals, qd, acc, done, facts);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -1250,7 +1341,7 @@ static int set_lds_attrs() {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   HGRD_CHECK(hipFuncSetAttribute(
       (const void*)k_bucket_filter<CAP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-      (int)(sizeof(FilterLds<CAP>) * filter_waves<CAP>())));
+      (int)sizeof(FilterLds<CAP>)));
   return 0;
 }
 
@@ -1270,11 +1361,11 @@ static int launch_bucket_t(hipStream_t st, uint32_t nruns, const BRun* runs,
   // filter and join.
   size_t lds = sizeof(JoinLds<CAP, TBL>);
   if (cand) {
-    const size_t flds = sizeof(FilterLds<CAP>) * filter_waves<CAP>();
+    const size_t flds = sizeof(FilterLds<CAP>);
     for (uint32_t off = 0; off < nruns; off += 1u << 20) {
       uint32_t m = nruns - off < (1u << 20) ? nruns - off : (1u << 20);
-      hipLaunchKernelGGL(k_bucket_filter<CAP>, dim3(m), dim3(filter_waves<CAP>() * 64), flds,
-                         st, runs + off, hitems, qd, recs, cursor, ovf, done, cand,
+      hipLaunchKernelGGL(k_bucket_filter<CAP>, dim3(m), dim3(kFilterThreads), flds,
+                         st, runs + off, hitems, qd, insts, recs, cursor, ovf, done, cand,
                          nbytes + 256);
       HGRD_CHECK(hipGetLastError());
     }
@@ -1357,12 +1448,13 @@ int join_cap(int cfg) { return cfg == 0 ? 1024 : cfg == 1 ? 1536 : 3072; }
 int launch_small(int cfg, hipStream_t st, const SItem* items, uint32_t n,
                  const void* insts, const DInsn* code, const int64_t* params,
                  const int64_t* loopvals, const QDesc* qd, QAcc* acc,
-                 const uint32_t* done, uint32_t* cursor, uint32_t persist_grid) {
+                 const uint32_t* done, uint32_t* cursor, uint32_t persist_grid,
+                 const IFact* facts) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_small_t<1024, 2048>(st, items, n, I, code, params, loopvals, qd, acc, done, cursor, persist_grid);
-    case 1: return launch_small_t<1536, 4096>(st, items, n, I, code, params, loopvals, qd, acc, done, cursor, persist_grid);
-    default: return launch_small_t<3072, 8192>(st, items, n, I, code, params, loopvals, qd, acc, done, cursor, persist_grid);
+    case 0: return launch_small_t<1024, 2048>(st, items, n, I, code, params, loopvals, qd, acc, done, cursor, persist_grid, facts);
+    case 1: return launch_small_t<1536, 4096>(st, items, n, I, code, params, loopvals, qd, acc, done, cursor, persist_grid, facts);
+    default: return launch_small_t<3072, 8192>(st, items, n, I, code, params, loopvals, qd, acc, done, cursor, persist_grid, facts);
   }
 }
 
@@ -1384,6 +1476,15 @@ int launch_tabulate(hipStream_t st, const Chunk* chunks, uint32_t n,
                        (const DevInst*)insts, code, params, loopvals, pool);
     HGRD_CHECK(hipGetLastError());
   }
+  return 0;
+}
+
+int launch_unit_filter(hipStream_t st, uint32_t n, const HItem* hitems, const QDesc* qd,
+                       const IFact* facts, uint32_t* ovf, unsigned long long* napart) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_unit_filter, dim3((n + 255) / 256), dim3(256), 0, st, n, hitems, qd,
+                     facts, ovf, napart);
+  HGRD_CHECK(hipGetLastError());
   return 0;
 }
 

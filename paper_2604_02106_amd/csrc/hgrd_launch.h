@@ -34,7 +34,10 @@ size_t w2item_size();
 int launch_small(int cfg, hipStream_t st, const SItem* items, uint32_t n,
                  const void* insts, const DInsn* code, const int64_t* params,
                  const int64_t* loopvals, const QDesc* qd, QAcc* acc,
-                 const uint32_t* done, uint32_t* cursor, uint32_t persist_grid);
+                 const uint32_t* done, uint32_t* cursor, uint32_t persist_grid,
+                 const IFact* facts);
+int launch_unit_filter(hipStream_t st, uint32_t n, const HItem* hitems, const QDesc* qd,
+                       const IFact* facts, uint32_t* ovf, unsigned long long* napart);
 int init_kernel_attributes();
 int init_verdict_attributes();
 int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n, bool tab,

@@ -273,6 +273,49 @@ def test_prefilter_is_exact(hg):
     say("prefiltered", st["prefiltered"])
 
 
+def test_unit_filter_is_exact(hg, monkeypatch):
+    """The unit filter of rd_execute (two accesses proven never to share an
+    address are neither partitioned nor joined) decides the mixed
+    workload's near-miss and interleaved pairs; every field equals the
+    oracle's with it and without it (HGRD_NO_UNIT_FILTER)."""
+    wl = configs.mixed(seed=96, n_queries=160, log2_max=19)
+    want, _ = oracle.check_pairs(wl, "B", threads=8)
+    say("unit filter on", len(wl.pairs))
+    compare(hg.check_pairs(wl), want, "unit filter on")
+    st = hg.default_context().stats()
+    say("units apart", st["units_apart"], "hbm items", st["hbm_items"])
+    assert st["units_apart"] > 0
+    monkeypatch.setenv("HGRD_NO_UNIT_FILTER", "1")
+    say("unit filter off")
+    compare(hg.check_pairs(wl), want, "unit filter off")
+    assert hg.default_context().stats()["units_apart"] == 0
+
+
+def test_bucket_filter_drops_own_thread_buckets(hg):
+    """Accesses that meet only in their own thread (both use one injective
+    map) hold equal addresses in every bucket, yet no conflict: the bucket
+    filter compares threads and passes no bucket to the join.  A map that
+    sends two threads to one address keeps its buckets."""
+    g = tid() + bid() * 256
+    m = Model(0, [Array(GLOBAL, 32), Array(GLOBAL, 64)],
+              [Access(0, WRITE, g, loops=[0]), Access(0, READ, g, loops=[0]),
+               Access(1, WRITE, c(1 << 40) + g * 4 + loop(0), loops=[0]),
+               Access(1, READ, c(1 << 40) + g * 4 + loop(0), loops=[0]),
+               Access(0, WRITE, g // 2, loops=[0]), Access(0, READ, g // 2, loops=[0])],
+              Launch((256, 1, 1), (256, 1, 1), 32), [[]], loops=[Loop(0, "lt", 4)])
+    own = Workload([m], [(0, 0, 1, 7), (0, 2, 3, 7)])
+    got = run_both(hg, own, "own thread")
+    assert not any(r["verdict"] for r in got)
+    st = hg.default_context().stats()
+    say("own thread stats", {k: st[k] for k in ("hbm_items", "join_tab_bytes",
+                                                "filter_tab_bytes")})
+    assert st["hbm_items"] > 0 and st["filter_tab_bytes"] > 0 and st["join_tab_bytes"] == 0
+    two = Workload([m], [(0, 4, 5, 7)])
+    got = run_both(hg, two, "two threads")
+    assert got[0]["verdict"] == 1
+    assert hg.default_context().stats()["join_tab_bytes"] > 0
+
+
 def test_batched_full_size_sampled(hg):
     """The headline workload at full size (256 models x 16 pairs, seed 2002)
     in the configuration bench.py times; a seeded random sample of pairs
