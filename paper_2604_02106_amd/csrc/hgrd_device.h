@@ -358,6 +358,7 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kInactive = 1u << 14;  // in tli
 constexpr uint32_t kSide = 1u << 15;      // in tli
+constexpr uint32_t kMultiThread = 1u << 31;  // in a group's count
 
 template <int CAP, int TBL>
 struct JoinLds {
@@ -530,6 +531,20 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
       gid[j] = h;
     }
     __syncthreads();
+    if (L == f) {
+      // groups holding records of two different threads are marked (bit 31
+      // of the count: counts stay below 2^15 per side); the others pair only
+      // a thread with itself, which is no conflict at any level
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const uint32_t r = tid + (uint32_t)j * NT;
+        if (tl[j] & kInactive) continue;
+        const uint32_t o = S.owner[gid[j]];
+        if (o != r && (S.blin[o] != S.blin[r] || ((S.tli[o] ^ tl[j]) & 0x3FF)))
+          atomicOr(&S.cnt[gid[j]], kMultiThread);
+      }
+      __syncthreads();
+    }
     const int sign = (L & 1) ? -1 : 1;
     const uint32_t cls = L < 2 ? 1u : (L < 4 ? 2u : 4u);
     bool any_local = false;
@@ -538,7 +553,8 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
     for (int j = 0; j < RPT; ++j) {
       const uint32_t r = tid + (uint32_t)j * NT;
       if (tl[j] & kInactive) continue;
-      const uint32_t c = S.cnt[gid[j]];
+      const uint32_t cw = S.cnt[gid[j]];
+      const uint32_t c = cw & ~kMultiThread;
       const bool sb = (tl[j] & kSide) != 0;
       // ordered pairs of the group: a self pair counts every record with
       // each of its group (itself included), a pair of two accesses each
@@ -546,11 +562,17 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
       if (self) s += c & 0xFFFF;
       else if (!sb) s += c >> 16;
       if (L == f) {
-        const bool cand = self ? ((c & 0xFFFF) >= 2) : ((c & 0xFFFF) && (c >> 16));
+        // a record can conflict only in a group with records of the other
+        // side (self pair: two records) and of two different threads; the
+        // others' pairs (none, or only a thread with itself) count zero in
+        // every class, so their share of S_f goes and they leave
+        const bool cand = (cw & kMultiThread) &&
+                          (self ? ((c & 0xFFFF) >= 2) : ((c & 0xFFFF) && (c >> 16)));
         if (!cand) {
           tl[j] |= kInactive;
           S.tli[r] = tl[j];
-          if (self) s -= 1;  // a lone record pairs only with itself
+          if (self) s -= c & 0xFFFF;
+          else if (!sb) s -= c >> 16;
           continue;
         }
         any_local = true;
