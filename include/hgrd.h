@@ -419,6 +419,12 @@ typedef struct {
                                 small items are decided the same way inside
                                 the LDS join (not counted).  The environment
                                 variable HGRD_NO_UNIT_FILTER turns it off */
+  uint64_t block_symmetric;  /* shared-array (pair, tuple) units joined on
+                                block 0 only: neither access's address nor
+                                guard depends on the block coordinates, so
+                                every block holds the same conflicts and the
+                                counts are block 0's times the blocks
+                                (HGRD_NO_SYMMETRY at rd_prepare turns it off) */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

@@ -136,7 +136,8 @@ class rd_stats(C.Structure):
                 ("presplit_items", C.c_uint64),
                 ("filter_tab_launches", C.c_uint64), ("filter_tab_ms", C.c_double),
                 ("filter_tab_bytes", C.c_uint64),
-                ("units_apart", C.c_uint64)]
+                ("units_apart", C.c_uint64),
+                ("block_symmetric", C.c_uint64)]
 
 
 assert C.sizeof(rd_pair_result) == 88

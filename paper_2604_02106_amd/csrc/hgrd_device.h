@@ -672,14 +672,15 @@ __device__ __forceinline__ bool sig_test(const JoinLds<CAP, TBL>& S, uint32_t i1
   return ((t[i1 >> 5] >> (i1 & 31)) & (t[i2 >> 5] >> (i2 & 31)) & 1u) != 0;
 }
 
-// Adds a join's results (S.red) to a query's accumulators (thread 0).
+// Adds a join's results (S.red) to a query's accumulators (thread 0), the
+// counts taken `mult` times (modulo 2^64, as the sum of mult copies).
 template <int CAP, int TBL>
 __device__ __forceinline__ void commit_join(const JoinLds<CAP, TBL>& S,
-                                            QAcc* __restrict__ acc) {
+                                            QAcc* __restrict__ acc, u64 mult = 1) {
   if (threadIdx.x == 0) {
-    if (S.red[0]) atomicAdd(&acc->cnt[0], S.red[0]);
-    if (S.red[1]) atomicAdd(&acc->cnt[1], S.red[1]);
-    if (S.red[2]) atomicAdd(&acc->cnt[2], S.red[2]);
+    if (S.red[0]) atomicAdd(&acc->cnt[0], S.red[0] * mult);
+    if (S.red[1]) atomicAdd(&acc->cnt[1], S.red[1] * mult);
+    if (S.red[2]) atomicAdd(&acc->cnt[2], S.red[2] * mult);
     if (S.red[3] != kNoKey) atomicMin(&acc->pmin, S.red[3]);
   }
 }

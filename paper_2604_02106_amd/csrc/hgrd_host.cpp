@@ -1482,6 +1482,7 @@ struct rd_plan_impl {
   bool no_map = false;          // hash buckets only
   uint64_t evals = 0;
   uint32_t n_sitems = 0;
+  uint64_t n_symmetric = 0;   // shared units joined on block 0 only
   uint32_t persist_grid = 0;  // workgroups of the persistent small join
   uint32_t chunk_pts = 16384; // points per partition workgroup
   uint32_t run_buckets = 8;   // buckets per join workgroup
@@ -1749,6 +1750,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     uint64_t R;
   };
   std::vector<SItem> sitems;
+  // block symmetry of shared-array units (HGRD_NO_SYMMETRY turns it off)
+  const bool block_sym = getenv("HGRD_NO_SYMMETRY") == nullptr;
   std::vector<HPlan> hplans;
   auto npts_of = [&](int32_t idx) -> uint64_t {
     return idx < 0 ? 0 : P.dev_insts[idx].npts;
@@ -1823,6 +1826,26 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         it.b0 = 0;
         it.b1 = R0.nblk;
         sitems.push_back(it);
+      } else if (q.qd.shared && per_block <= cap && block_sym &&
+                 P.tabs[ia].on && P.tabs[ib].on && P.tabs[ia].off[0] == kNoTab &&
+                 P.tabs[ib].off[0] == kNoTab) {
+        // block symmetry: shared memory belongs to one block, and neither
+        // access's address nor guard has a term in the block coordinates
+        // (interval ids depend on loop values only), so every block holds
+        // the same points and the same conflicts.  Block 0 is joined and its
+        // counts are taken nblk times; its witness, having the smallest
+        // block, is the smallest of all.
+        SItem it;
+        memset(&it, 0, sizeof it);
+        it.q = k;
+        it.sigma = s;
+        it.inst_i = (uint32_t)ia;
+        it.inst_j = (uint32_t)ib;
+        it.b0 = 0;
+        it.b1 = 1;
+        it.mult = R0.nblk;
+        sitems.push_back(it);
+        ++plan->n_symmetric;
       } else if (q.qd.shared && per_block <= cap) {
         uint32_t bpi = (uint32_t)(cap / per_block);
         for (uint32_t b0 = 0; b0 < R0.nblk; b0 += bpi) {
@@ -2214,6 +2237,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   S.evals = plan->evals;
   S.prefiltered = plan->prefiltered;
   S.small_items = plan->n_sitems;
+  S.block_symmetric = plan->n_symmetric;
   int merr = 0;
   auto D = [&](const char* name) { return plan->dev[name].p; };
   const DInsn* d_code = (const DInsn*)D("code");

@@ -143,7 +143,8 @@ constexpr uint32_t kApart = 0xFFFFFFFFu;
 struct SItem {
   uint32_t q, sigma, inst_i, inst_j;
   uint32_t b0, b1;
-  uint32_t pad0, pad1;
+  uint32_t mult;  // 0 or 1: as joined; k > 1: block 0 of k identical blocks
+  uint32_t pad1;  //   (its counts are taken k times)
 };
 
 // Work item partitioned through HBM.

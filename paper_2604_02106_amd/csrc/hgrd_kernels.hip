@@ -87,7 +87,7 @@ __device__ __forceinline__ void small_item(JoinLds<CAP, TBL>& S, const SItem& it
     return;
   }
   lds_join<256>(S, q, it.sigma);
-  commit_join(S, &acc[it.q]);
+  commit_join(S, &acc[it.q], it.mult > 1 ? (u64)it.mult : 1ull);
 }
 
 // One workgroup per item.

@@ -291,6 +291,34 @@ def test_unit_filter_is_exact(hg, monkeypatch):
     assert hg.default_context().stats()["units_apart"] == 0
 
 
+def test_block_symmetry_is_exact(hg, monkeypatch):
+    """Shared-array units whose address and guard do not depend on the
+    block are joined on block 0 and counted once per block; a unit whose
+    address does depend on the block is joined block by block.  Every
+    field equals the oracle's, with and without the shortcut."""
+    t = tid()
+    m = Model(2, [Array(SHARED, 32)],
+              [Access(0, WRITE, t // 32 + loop(0) * 8, lt(t, param(0)), [0]),
+               Access(0, READ, t % param(1) + loop(0), None, [0]),
+               Access(0, WRITE, t * 2 + loop(0), None, [0]),
+               Access(0, WRITE, t % 4 + bid() % 2, None, [0])],
+              Launch((37, 3, 1), (64, 2, 1), 32), [[100, 24], [128, 7]],
+              loops=[Loop(0, "lt", 3)])
+    wl = Workload([m], [(0, 0, 1, 7), (0, 0, 0, 7), (0, 1, 2, 7), (0, 2, 2, 7),
+                        (0, 3, 3, 7), (0, 3, 1, 7)])
+    want, _ = oracle.check_pairs(wl, "B", threads=8)
+    say("symmetry on")
+    compare(hg.check_pairs(wl), want, "symmetry on")
+    st = hg.default_context().stats()
+    say("block symmetric units", st["block_symmetric"])
+    assert st["block_symmetric"] >= 2 * 2  # at least the self pairs 0 and 3 of both tuples
+    assert sum(r["verdict"] for r in want) >= 3
+    monkeypatch.setenv("HGRD_NO_SYMMETRY", "1")
+    say("symmetry off")
+    compare(hg.check_pairs(wl), want, "symmetry off")
+    assert hg.default_context().stats()["block_symmetric"] == 0
+
+
 def test_bucket_filter_drops_own_thread_buckets(hg):
     """Accesses that meet only in their own thread (both use one injective
     map) hold equal addresses in every bucket, yet no conflict: the bucket
