@@ -412,10 +412,15 @@ typedef struct {
                                    join), timed in filter_tab_ms */
   double filter_tab_ms;      /* their summed duration */
   uint64_t filter_tab_bytes; /* record bytes they read */
-  uint64_t units_apart;      /* HBM items the unit filter decided: their two
-                                accesses share no address (proven address
-                                ranges apart, or residues that differ), so
-                                nothing of them is partitioned or joined;
+  uint64_t units_apart;      /* HBM items the unit filter decided free of
+                                conflicts: their two accesses share no
+                                address (proven address ranges apart, or
+                                residues that differ), or both compute their
+                                address with one expression that sends
+                                different threads to different addresses
+                                (a mixed-radix dependence test on its affine
+                                form), so nothing of them is partitioned or
+                                joined;
                                 small items are decided the same way inside
                                 the LDS join (not counted).  The environment
                                 variable HGRD_NO_UNIT_FILTER turns it off */
@@ -485,10 +490,14 @@ const char* rd_strerror(int status);
  * Returns 0 when they pass. */
 int rd_selftest(void);
 
-/* Host-only check of the exact pre-filter (rd_options.prefilter) on one
- * (pair, tuple) unit: *decided = 1 when the unit of accesses access_a and
- * access_b of `model` under tuple `set` would be decided without
- * enumeration (the two accesses then share no address), else 0.  Returns
+/* Host-only check of the exact pre-filters on one (pair, tuple) unit of
+ * accesses access_a and access_b of `model` under tuple `set`: bit 0 of
+ * *decided is set when the unit would be decided without enumeration by
+ * rd_options.prefilter and by the unit filter of rd_execute (the two
+ * accesses then share no address); bit 1 when the unit filter would
+ * decide it because both accesses compute their address with one
+ * expression that sends different threads to different addresses (a self
+ * pair included).  Returns
  * RD_OK, 2 when an access has no instance for the tuple (errors, empty
  * launch), or RD_EINVAL for bad arguments.  Touches no device. */
 int rd_prefilter_selftest(const rd_kernel_model* models, uint32_t n_models,

@@ -333,6 +333,17 @@ __device__ __forceinline__ bool facts_apart(const IFact& a, const IFact& b) {
   return mod_u64(a.u, g) != mod_u64(b.u, g);
 }
 
+// A (pair, tuple) unit holds no conflict when its two accesses share no
+// address (two different instances, facts_apart), or when both compute
+// their address with one expression (QDesc flag bit 2; a self pair always
+// does) that sends different threads to different addresses: a common
+// address then belongs to one thread only.
+__device__ __forceinline__ bool unit_free(const IFact& a, const IFact& b, uint32_t qflags,
+                                          bool distinct) {
+  if ((qflags & 4) && a.on && b.on && a.inj && b.inj) return true;
+  return distinct && facts_apart(a, b);
+}
+
 // ---------------------------------------------------------------------------
 // Reductions.
 

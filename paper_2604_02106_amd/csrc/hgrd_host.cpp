@@ -717,6 +717,43 @@ struct TermBuilder {
     }
   }
 
+  // Affine form of the tree below node i, times mu: adds mu times each
+  // coordinate's coefficient to c (tx ty tz bx by bz) and cl (loop
+  // positions); constant parts are left out.  False when some operation is
+  // not affine in the coordinates (a product of two non-constant values,
+  // division, remainder, min, max, comparisons, ...).
+  bool affine(int i, i128 mu, i128* c, i128* cl) const {
+    const TNode& n = nodes[i];
+    if (!n.groups) return true;
+    if (i128abs(mu) > ((i128)1 << 62)) return false;
+    switch (n.op) {
+      case RD_OP_TID: if (n.arg > 2) return false; c[n.arg] += mu; return true;
+      case RD_OP_BID: if (n.arg > 2) return false; c[3 + n.arg] += mu; return true;
+      case RD_OP_LOOP: {
+        const int p = loop_pos(&A, n.arg);
+        if (p < 0 || p > 3) return false;
+        cl[p] += mu;
+        return true;
+      }
+      case RD_OP_ADD: return affine(n.kid[0], mu, c, cl) && affine(n.kid[1], mu, c, cl);
+      case RD_OP_SUB: return affine(n.kid[0], mu, c, cl) && affine(n.kid[1], -mu, c, cl);
+      case RD_OP_NEG: return affine(n.kid[0], -mu, c, cl);
+      case RD_OP_MUL: {
+        const TNode& a = nodes[n.kid[0]];
+        const TNode& b = nodes[n.kid[1]];
+        if (!a.groups) return affine(n.kid[1], mu * a.val, c, cl);
+        if (!b.groups) return affine(n.kid[0], mu * b.val, c, cl);
+        return false;
+      }
+      case RD_OP_SHL: {
+        const TNode& b = nodes[n.kid[1]];
+        if (b.groups || b.val < 0 || b.val > 62) return false;
+        return affine(n.kid[0], mu * ((i128)1 << b.val), c, cl);
+      }
+      default: return false;
+    }
+  }
+
   bool decompose(int i, Lin& L, i128 mu) {
     const TNode& n = nodes[i];
     if (!n.groups) {
@@ -925,6 +962,7 @@ struct Planner {
   // addresses lie in its block term plus these), and the block-term job
   // (index into tjobs, -1: the address does not depend on the block)
   std::vector<std::pair<int64_t, int64_t>> rrest;
+  std::vector<uint8_t> tinj;  // tables only: thread-injective address (below)
   std::vector<int32_t> bjob;
   // tables only: address step from thread 0 to thread 1 and from block 0 to
   // block 1 (0 when the group has one index or no term)
@@ -933,6 +971,74 @@ struct Planner {
   uint64_t tpool = 0;         // table entries
   uint64_t tab_budget = kMaxTabPool;  // table entries this planner may use
   bool use_tables = true;
+
+  // Exact dependence test on an address that is affine in the coordinates
+  // (TermBuilder::affine): true when two points of different threads can
+  // never share an address.  The address is u + sum_k c_k x_k over the
+  // thread, block and loop coordinates (loop coordinates take their loop's
+  // values).  Each coordinate k with more
+  // than one value has a unit step s_k = |c_k| times the smallest distance
+  // between two of its values, and a span w_k = |c_k| (max - min).  Either
+  // of two mixed-radix arguments decides:
+  //   (1) ordered by s_k, the thread and block coordinates satisfy
+  //       m_k = s_k - sum_{j<k} w_j > 0; two different threads then differ
+  //       in the thread part by at least min_k m_k, and when that exceeds
+  //       the span of the whole loop part no loop values close the gap;
+  //   (2) ordered by s_k, all coordinates with c_k != 0 satisfy m_k > 0:
+  //       different coordinate tuples give different addresses, and two
+  //       different threads differ in a thread or block coordinate (all of
+  //       which must then have c_k != 0).
+  // A thread or block coordinate with more than one value and c_k = 0
+  // fails both (threads differing only there share addresses).  For a
+  // shared array (per_block) the block coordinates are left out: threads
+  // of different blocks never share its memory.
+  bool thread_injective(const i128* c, const i128* cl, const AccInst& I,
+                        bool per_block) const {
+    struct Co {
+      i128 step, span;
+    };
+    std::vector<Co> th, lp;  // thread/block coordinates, loop coordinates
+    for (int k = 0; k < 6; ++k) {
+      const i128 n = k < 3 ? I.dims[3 + k] : I.dims[k - 3];
+      if (n <= 1 || (per_block && k >= 3)) continue;
+      if (c[k] == 0) return false;
+      th.push_back({i128abs(c[k]), i128abs(c[k]) * (n - 1)});
+    }
+    for (uint32_t p = 0; p < I.n_loops && p < 4; ++p) {
+      if (cl[p] == 0 || I.loop_n[p] <= 1) continue;
+      std::vector<int64_t> v(pool_loops.begin() + I.loop_off[p],
+                             pool_loops.begin() + I.loop_off[p] + I.loop_n[p]);
+      std::sort(v.begin(), v.end());
+      i128 gap = -1;
+      for (size_t e = 1; e < v.size(); ++e) {
+        const i128 d = (i128)v[e] - v[e - 1];
+        if (gap < 0 || d < gap) gap = d;
+      }
+      lp.push_back({i128abs(cl[p]) * gap, i128abs(cl[p]) * ((i128)v.back() - v.front())});
+    }
+    // smallest margin of a mixed-radix ordering, -1 if some margin is <= 0
+    // (no coordinate with more than one value: +infinity, returned as 0)
+    auto margin = [](std::vector<Co> co) -> i128 {
+      std::sort(co.begin(), co.end(), [](const Co& a, const Co& b) { return a.step < b.step; });
+      i128 below = 0, m = 0;
+      for (const Co& e : co) {
+        const i128 mk = e.step - below;
+        if (mk <= 0) return -1;
+        if (m == 0 || mk < m) m = mk;
+        below += e.span;
+      }
+      return m;
+    };
+    const i128 mt = margin(th);
+    if (mt < 0) return false;
+    if (mt == 0) return true;  // one thread only
+    i128 lspan = 0;
+    for (const Co& e : lp) lspan += e.span;
+    if (lspan < mt) return true;  // (1)
+    std::vector<Co> all = th;
+    all.insert(all.end(), lp.begin(), lp.end());
+    return margin(all) > 0;  // (2)
+  }
 
   // Term tables of instance I (access a of model m); T.on = 0 when some
   // expression does not qualify.
@@ -961,6 +1067,8 @@ struct Planner {
     const i128 root_lo = tb.nodes.back().lo, root_hi = tb.nodes.back().hi;
     Lin L;
     if (!tb.decompose((int)tb.nodes.size() - 1, L, 1)) return;
+    i128 ac[6] = {0, 0, 0, 0, 0, 0}, acl[4] = {0, 0, 0, 0};
+    const bool aff = tb.affine((int)tb.nodes.size() - 1, 1, ac, acl);
     i128 tot = i128abs(L.u), lo = L.u, hi = L.u;
     for (const STerm& t : L.terms) {
       tot += contrib_abs(t);
@@ -1065,6 +1173,8 @@ struct Planner {
         rhi += contrib_hi(t);
       }
     rrest[inst] = {(int64_t)rlo, (int64_t)rhi};
+    tinj[inst] =
+        aff && thread_injective(ac, acl, I, M.arrays[A.array].space == RD_SHARED) ? 1 : 0;
     // point order: iterations fastest when the address moves less along
     // them than along threads (consecutive points then share buckets)
     int64_t stride[3] = {0, 0, 0};
@@ -1227,6 +1337,7 @@ struct Planner {
     arange.push_back({0, -1});
     ares.push_back({1, 0});
     rrest.push_back({0, -1});
+    tinj.push_back(0);
     bjob.push_back(-1);
     gstride.push_back({0, 0});
     tables_for(m, a, I, (uint32_t)ii.idx, T);
@@ -1274,6 +1385,7 @@ struct Planner {
     arange.insert(arange.end(), o.arange.begin(), o.arange.end());
     ares.insert(ares.end(), o.ares.begin(), o.ares.end());
     rrest.insert(rrest.end(), o.rrest.begin(), o.rrest.end());
+    tinj.insert(tinj.end(), o.tinj.begin(), o.tinj.end());
     for (int32_t b : o.bjob) bjob.push_back(b < 0 ? b : b + job_off);
     gstride.insert(gstride.end(), o.gstride.begin(), o.gstride.end());
     for (size_t m = 0; m < o.dims.size() && m < dims.size(); ++m) {
@@ -1371,6 +1483,20 @@ struct Planner {
     return true;
   }
 };
+
+// Accesses a and b of M compute their address with one and the same
+// expression (so, under one tuple, one function of the coordinates and
+// loop values).
+bool same_addr_expr(const rd_kernel_model& M, uint32_t a, uint32_t b) {
+  const rd_expr ea = M.acc[a].addr, eb = M.acc[b].addr;
+  if (ea.count != eb.count) return false;
+  for (uint32_t e = 0; e < ea.count; ++e) {
+    const rd_insn& x = M.insns[ea.first + e];
+    const rd_insn& y = M.insns[eb.first + e];
+    if (x.op != y.op || x.arg != y.arg || x.imm != y.imm) return false;
+  }
+  return true;
+}
 
 uint32_t class_mask(const rd_kernel_model& m, const rd_access& x,
                     const rd_access& y, uint32_t caller) {
@@ -1740,6 +1866,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
             fl &= ~(1u << c);
         }
       }
+      // bit 2: both accesses compute their address with the same expression
+      if (same_addr_expr(models[pr.model], pr.a, pr.b)) fl |= 4;
       q.qd.flags = fl;
     }
   }
@@ -2167,6 +2295,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       facts[i].G = P.ares[i].first;
       facts[i].u = P.ares[i].second;
       facts[i].on = 1;
+      facts[i].inj = P.tinj[i];
     }
     up("ifacts", facts.data(), facts.size() * sizeof(IFact));
   }
@@ -3239,6 +3368,10 @@ int rd_prefilter_selftest(const rd_kernel_model* models, uint32_t n_models,
   InstInfo& ib = P.inst(model, access_b, set);
   if (ia.err || ib.err || ia.idx < 0 || ib.idx < 0) return 2;
   if (ia.idx != ib.idx) *decided = P.apart(ia.idx, ib.idx) ? 1u : 0u;
+  // the unit filter's second test: one expression, thread-injective
+  if (same_addr_expr(M, access_a, access_b) && P.tabs[ia.idx].on && P.tabs[ib.idx].on &&
+      P.tinj[ia.idx] && P.tinj[ib.idx])
+    *decided |= 2u;
   return RD_OK;
 }
 

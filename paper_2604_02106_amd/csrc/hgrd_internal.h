@@ -103,7 +103,8 @@ struct QDesc {
   uint32_t flags;    // bit 0: both accesses have one and the same block-
                      // barrier interval id in every tuple (the block level
                      // groups equal the (address, block) groups); bit 1: the
-                     // same for the warp-barrier id
+                     // same for the warp-barrier id; bit 2: both accesses
+                     // compute their address with one expression
 };
 
 struct QAcc {
@@ -126,12 +127,13 @@ constexpr unsigned long long kNoKey = ~0ull;
 
 // Facts about one access instance that its lowering proved (instances
 // with term tables only): every address lies in [lo, hi] and is congruent
-// to u modulo G (G = 0: every address equals u).  on = 0: nothing known.
+// to u modulo G (G = 0: every address equals u); inj: two points of
+// different threads never share an address.  on = 0: nothing known.
 struct IFact {
   long long lo, hi;
   unsigned long long G;
   long long u;
-  uint32_t on, pad[3];
+  uint32_t on, inj, pad[2];
 };
 static_assert(sizeof(IFact) == 48, "IFact layout");
 // ovf mark of an HBM item whose two accesses share no address (decided by

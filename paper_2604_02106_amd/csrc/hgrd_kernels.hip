@@ -50,9 +50,9 @@ __device__ __forceinline__ void small_item(JoinLds<CAP, TBL>& S, const SItem& it
                                            const IFact* __restrict__ facts) {
   if (done[it.q]) return;
   const QDesc q = qd[it.q];
-  // two accesses proven never to share an address: nothing to join
-  if (facts && !q.self && it.inst_i != it.inst_j &&
-      facts_apart(facts[it.inst_i], facts[it.inst_j]))
+  // a unit proven free of conflicts: nothing to join
+  if (facts && unit_free(facts[it.inst_i], facts[it.inst_j], q.flags,
+                         !q.self && it.inst_i != it.inst_j))
     return;
   if (threadIdx.x == 0) {
     S.n = 0;
@@ -490,11 +490,11 @@ __global__ void k_apply_s0(uint32_t n, const L0Item* __restrict__ items,
   atomicAdd(&acc[items[k].q].cnt[0], s0[k]);
 }
 
-// Unit filter of the HBM items: an item whose two accesses are proven never
-// to share an address (facts_apart) is marked kApart in ovf, so that its
-// partition, address filter and join do nothing and no later phase takes
-// it up.  Error-scan items, self pairs and items without facts stay.  The
-// marked items are counted in *napart.
+// Unit filter of the HBM items: an item proven free of conflicts
+// (unit_free) is marked kApart in ovf, so that its partition, address
+// filter and join do nothing and no later phase takes it up.  Error-scan
+// items and items without facts stay.  The marked items are counted in
+// *napart.
 __global__ void k_unit_filter(uint32_t n, const HItem* __restrict__ hitems,
                               const QDesc* __restrict__ qd,
                               const IFact* __restrict__ facts,
@@ -503,8 +503,9 @@ __global__ void k_unit_filter(uint32_t n, const HItem* __restrict__ hitems,
   bool apart = false;
   if (k < n) {
     const HItem h = hitems[k];
-    apart = h.shared != 2 && h.inst_i != h.inst_j && !qd[h.q].self &&
-            facts_apart(facts[h.inst_i], facts[h.inst_j]);
+    const QDesc q = qd[h.q];
+    apart = h.shared != 2 && unit_free(facts[h.inst_i], facts[h.inst_j], q.flags,
+                                       !q.self && h.inst_i != h.inst_j);
     if (apart) ovf[k] = kApart;
   }
   const u64 c = (u64)__popcll(__ballot(apart));

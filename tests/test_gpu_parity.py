@@ -320,15 +320,17 @@ def test_block_symmetry_is_exact(hg, monkeypatch):
 
 
 def test_bucket_filter_drops_own_thread_buckets(hg):
-    """Accesses that meet only in their own thread (both use one injective
-    map) hold equal addresses in every bucket, yet no conflict: the bucket
-    filter compares threads and passes no bucket to the join.  A map that
-    sends two threads to one address keeps its buckets."""
+    """Accesses that meet only in their own thread (one injective map,
+    written as two different expressions so that the unit filter does not
+    decide the unit first) hold equal addresses in every bucket, yet no
+    conflict: the bucket filter compares threads and passes no bucket to
+    the join.  A map that sends two threads to one address keeps its
+    buckets."""
     g = tid() + bid() * 256
     m = Model(0, [Array(GLOBAL, 32), Array(GLOBAL, 64)],
-              [Access(0, WRITE, g, loops=[0]), Access(0, READ, g, loops=[0]),
+              [Access(0, WRITE, g, loops=[0]), Access(0, READ, (g + c(1)) - c(1), loops=[0]),
                Access(1, WRITE, c(1 << 40) + g * 4 + loop(0), loops=[0]),
-               Access(1, READ, c(1 << 40) + g * 4 + loop(0), loops=[0]),
+               Access(1, READ, c(1 << 40) + (g * 4 + loop(0)), loops=[0]),
                Access(0, WRITE, g // 2, loops=[0]), Access(0, READ, g // 2, loops=[0])],
               Launch((256, 1, 1), (256, 1, 1), 32), [[]], loops=[Loop(0, "lt", 4)])
     own = Workload([m], [(0, 0, 1, 7), (0, 2, 3, 7)])
