@@ -772,6 +772,10 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
   const QDesc q = qd[h.q];
   init_red(S);
   const bool l0ext = h.shared == 3;
+  // the signature pre-filter only when no exact bucket filter ran before
+  // (a bucket it passed holds records with partners, and the join's first
+  // level drops the others exactly)
+  const bool sig = cand == nullptr;
   const bool is32 = h.is32 != 0;
   constexpr int RPT = (CAP + kJoinThreads - 1) / kJoinThreads;
   u64 rx[RPT], ry[RPT];
@@ -825,7 +829,7 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
       // address and point id only (the point id waits in S.blin until the
       // records that may share an address with the other side are known);
       // the signature bitmap is cleared for this bucket
-      sig_clear<kJoinThreads>(S);
+      if (sig) sig_clear<kJoinThreads>(S);
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const uint32_t r = threadIdx.x + (uint32_t)j * kJoinThreads;
@@ -840,10 +844,11 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
           const uint32_t sh = sd[j] ? h.tpb_s[1] : h.tpb_s[0];
           salt = ((__umulhi(m, p) + p) >> sh) + 1;
         }
-        sig_index<TBL>(a, salt, i1[j], i2[j]);
+        if (sig) sig_index<TBL>(a, salt, i1[j], i2[j]);
         if (r >= n) continue;
         S.addr[r] = a;
         S.blin[r] = pid;
+        if (!sig) S.tli[r] = sd[j] ? kSide : 0u;  // every record active
       }
     }
     // the next bucket's records load while this one is joined
@@ -852,6 +857,8 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
     const uint32_t b1n = more ? R.b0 + S.bl[kb + 1] : 0;
     if (!l0ext) {
       if (more) HGRD_FETCH(b1n, n1)
+    }
+    if (!l0ext && sig) {
       __syncthreads();
       if (go) {
 #pragma unroll
