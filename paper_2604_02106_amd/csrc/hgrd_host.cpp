@@ -409,6 +409,30 @@ struct rd_context {
   // abufs names the arena's buffers and is emptied when the arena is unset.
   Arena* arena = nullptr;
   std::map<std::string, DevBuf> abufs;
+  // Partition scratch (bucket records, bucket cursors, filter marks) that
+  // every plan of the context shares: plans run one at a time on a
+  // context, so one buffer serves them all.  A buffer that must grow is
+  // retired, not freed, while plans (and their captured graphs) may still
+  // hold its address; retired buffers go with the context.
+  std::map<std::string, DevBuf> shared;
+  std::vector<void*> retired;
+  void* shared_buf(const char* name, size_t bytes, int* err) {
+    DevBuf& b = shared[name];
+    if (bytes == 0) bytes = 256;
+    if (b.cap >= bytes) return b.p;
+    if (b.p) retired.push_back(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      fprintf(stderr, "hgrd: device allocation of %zu bytes for '%s' failed\n", bytes, name);
+      b.p = nullptr;
+      *err = RD_ENOMEM;
+      return nullptr;
+    }
+    b.cap = bytes;
+    return b.p;
+  }
   rd_stats stats;
   int cfg = 0;  // LDS tile shape: 1024 records, 2048 slots (rd_autotune may change it)
   uint32_t n_cu = 256;
@@ -1581,6 +1605,9 @@ void rd_context_destroy(rd_context* ctx) {
   (void)hipSetDevice(ctx->device);
   for (auto& kv : ctx->bufs)
     if (kv.second.p && kv.second.own) (void)hipFree(kv.second.p);
+  for (auto& kv : ctx->shared)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (void* p : ctx->retired) (void)hipFree(p);
   for (auto& e : ctx->ev) (void)hipEventDestroy(e);
   for (auto& e : ctx->wev) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -1695,6 +1722,15 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   std::unique_ptr<rd_plan> guard(plan);
   plan->arena = ctx->arena;
   plan->n_pairs = n_pairs;
+  // log_level >= 1: the duration of each preparation phase on stderr
+  double t_phase = now_ms();
+  const char* phase = "start";
+  auto ptime = [&](const char* next) {
+    const double t = now_ms();
+    if (o.log_level >= 1) fprintf(stderr, "[hgrd] prepare %s: %.1f ms\n", phase, t - t_phase);
+    t_phase = t;
+    phase = next;
+  };
   plan->st = o.stream ? (hipStream_t)o.stream : ctx->stream;
   plan->log_level = o.log_level;
   int cfg = ctx->cfg;
@@ -1733,6 +1769,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   }
 
   // ---- per pair: validation, masks, instances -----------------------------
+  ptime("validate");
   std::vector<QPlan>& Q = plan->Q;
   Q.resize(n_pairs);
   for (uint32_t k = 0; k < n_pairs; ++k) {
@@ -1762,6 +1799,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   }
 
   // ---- lowering of the instances the pairs use, in parallel ----------------
+  ptime("lower");
   // Models are dealt to a fixed number of groups (so the plan does not
   // depend on the host), each lowered by its own planner on a host thread,
   // then appended to P in group order; P's memo then answers every
@@ -1873,6 +1911,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   }
 
   // ---- items ----------------------------------------------------------------
+  ptime("items");
   struct HPlan {
     HItem h;
     uint64_t R;
@@ -2016,6 +2055,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   plan->n_sitems = (uint32_t)sitems.size();
 
   // ---- VERDICT mode: search units, their blocks, tiles and rounds ----------
+  ptime("verdict");
   std::vector<VQuery> vqs;
   std::vector<BItem> bitems;
   std::vector<TChunk> tchunks;
@@ -2123,6 +2163,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     plan->run_buckets = std::max(1u, std::min(kMaxRunBuckets, (uint32_t)atoi(e)));
 
   // ---- waves of HBM items, bounded by the device budget --------------------
+  ptime("waves");
   // Large waves keep the partition and join launches few (each launch has a
   // tail); records cost 16 bytes of HBM traffic per point either way.
   const uint64_t budget = o.max_device_bytes ? o.max_device_bytes : ctx->wave_bytes;
@@ -2227,6 +2268,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   }
 
   // ---- upload descriptors -----------------------------------------------------
+  ptime("upload");
   int merr = 0;
   const size_t isz = devinst_size();
   const int64_t* d_tpool = (const int64_t*)plan->buf("tpool", std::max<uint64_t>(1, P.tpool) * 8, &merr);
@@ -2317,17 +2359,30 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     plan->buf("claim", std::max<size_t>(1, n_pairs) * 8, &merr);
   }
   plan->buf("qacc", std::max<size_t>(1, n_pairs) * sizeof(QAcc), &merr);
-  // scratch of the first phase belongs to the plan (a captured graph keeps
-  // these addresses)
-  plan->buf("recs", plan->max_key_bytes, &merr);
-  plan->buf("cursor", plan->max_buckets * 4, &merr);
+  // partition scratch of the first phase: shared by the context's plans
+  // (its addresses stay valid while a plan holds them, as a captured graph
+  // needs); in an arena call it is carved from the arena like the rest
+  auto scratch = [&](const char* name, size_t bytes) {
+    if (plan->arena) {
+      plan->buf(name, bytes, &merr);
+      return;
+    }
+    void* p = ctx->shared_buf(name, bytes, &merr);
+    DevBuf& b = plan->dev[name];
+    b.p = p;
+    b.cap = bytes;
+    b.own = false;
+  };
+  scratch("recs", plan->max_key_bytes);
+  scratch("cursor", plan->max_buckets * 4);
   plan->buf("ovf", std::max<size_t>(1, plan->hitems.size()) * 4, &merr);
   plan->buf("done", std::max<size_t>(1, n_pairs) * 4, &merr);
   plan->buf("pcursor", 4, &merr);
   plan->buf("nbytes", 512 * 8, &merr);
-  plan->buf("cand", std::max<uint64_t>(1, plan->max_buckets), &merr);
+  scratch("cand", std::max<uint64_t>(1, plan->max_buckets));
   plan->buf("out", std::max<size_t>(1, n_pairs) * sizeof(rd_pair_result), &merr);
   if (merr) return merr;
+  ptime("done");
   *plan_out = guard.release();
   return RD_OK;
 }
@@ -2709,9 +2764,13 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       max_nbk = std::max(max_nbk, nbk);
       pos = end;
     }
-    d_recs = (unsigned char*)ctx->ensure("recs", std::max<uint64_t>(max_bytes, plan->max_key_bytes), &merr);
-    d_cursor = (uint32_t*)ctx->ensure("cursor", std::max<uint64_t>(max_nbk, plan->max_buckets) * 4, &merr);
-    d_cand = (uint8_t*)ctx->ensure("cand", std::max<uint64_t>(max_nbk, plan->max_buckets), &merr);
+    // the first phase is over: its partition scratch serves again
+    auto rbuf = [&](const char* name, size_t bytes) {
+      return plan->arena ? ctx->ensure(name, bytes, &merr) : ctx->shared_buf(name, bytes, &merr);
+    };
+    d_recs = (unsigned char*)rbuf("recs", std::max<uint64_t>(max_bytes, plan->max_key_bytes));
+    d_cursor = (uint32_t*)rbuf("cursor", std::max<uint64_t>(max_nbk, plan->max_buckets) * 4);
+    d_cand = (uint8_t*)rbuf("cand", std::max<uint64_t>(max_nbk, plan->max_buckets));
     const uint32_t nr = (uint32_t)hs.size();
     HItem* d_rh = (HItem*)ctx->ensure("r_hitems", nr * sizeof(HItem), &merr);
     Chunk* d_rc = (Chunk*)ctx->ensure("r_chunks", chunks.size() * sizeof(Chunk), &merr);
