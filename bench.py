@@ -302,6 +302,11 @@ def run_mixed(args):
         "items_per_step": {k: sum(s[k] for s in stats) / len(stats) for k in (
             "small_items", "hbm_items", "retry_items", "split_items",
             "overflow_items", "fallback_records", "buckets", "records")},
+        # exact shortcuts inside the timed steps: HBM (pair, tuple) units the
+        # unit filter proved free of conflicts (nothing partitioned), and
+        # shared-array units joined on block 0 only (block symmetry)
+        "exact_shortcuts_per_step": {k: sum(s[k] for s in stats) / len(stats) for k in (
+            "units_apart", "block_symmetric")},
     }
     kr = kernel_rooflines(stats)
     if kr:
@@ -365,11 +370,37 @@ def run_mixed(args):
                                  "sample": "%d queries of batch 0, one rd_check_pairs "
                                            "call each" % len(pick),
                                  "results_equal_batched": bool(same)}
-        # end to end: a fresh plan of batch 0 (lowering, upload, execute)
+        # end to end: a fresh plan of batch 0 through the C ABI (lowering,
+        # upload, execute, results), its Python marshalling timed apart
         ts = time.perf_counter()
-        e2e = hg.rd_check_pairs(ctx, batches[0])
+        pk0 = hg.Packed(batches[0])
+        line["python_marshal_s"] = time.perf_counter() - ts
+        ts = time.perf_counter()
+        e2e = hg.rd_check_pairs(ctx, batches[0], packed=pk0)
         line["end_to_end_queries_per_s"] = len(batches[0].pairs) / (time.perf_counter() - ts)
         line["end_to_end_equal"] = e2e == results[0]
+        # the same two batches with the exact shortcuts off (unit filter and
+        # block symmetry): every unit enumerated
+        k = min(2, len(step_s))
+        os.environ["HGRD_NO_SYMMETRY"] = "1"
+        os.environ["HGRD_NO_UNIT_FILTER"] = "1"
+        try:
+            tp, same = 0.0, True
+            for i in range(k):
+                pp = hg.Plan(ctx, batches[i], max_device_bytes=args.wave_mib << 20)
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                r = pp.execute()
+                tp += time.perf_counter() - ts
+                same &= r == results[i]
+                pp.close()
+        finally:
+            del os.environ["HGRD_NO_SYMMETRY"]
+            del os.environ["HGRD_NO_UNIT_FILTER"]
+        q = sum(len(batches[i].pairs) for i in range(k))
+        line["without_exact_shortcuts"] = {"queries_per_s": q / tp,
+                                           "with_queries_per_s": q / sum(step_s[:k]),
+                                           "batches": k, "results_equal": bool(same)}
     if not args.no_cpu_baseline and 0 in results:
         line["cpu_baseline"] = cpu_baseline(batches[0], results[0])
         line["cpu_baseline"]["sample"] += " (batch 0 of the mixed workload)"

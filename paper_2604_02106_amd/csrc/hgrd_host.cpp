@@ -2192,16 +2192,19 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     }
     hplans.resize(w);
   }
-  std::vector<Chunk> all_chunks;
-  std::vector<BRun> all_runs;
+  // Chunks and runs are described compactly, one spec per (item, side) and
+  // per item in launch order, and expanded on the device at the end of
+  // rd_prepare (k_expand): a batch can have tens of millions of them.
+  std::vector<ExpandSpec> chunk_specs, run_specs;
+  uint64_t n_all_chunks = 0, n_all_runs = 0;
   size_t pos = 0;
   while (pos < hplans.size()) {
     rd_plan_impl::Wave W;
     memset(&W, 0, sizeof W);
     W.first_item = (uint32_t)plan->hitems.size();
     W.hitem_off = plan->hitems.size();
-    W.chunk_off = all_chunks.size();
-    W.bitem_off = all_runs.size();
+    W.chunk_off = n_all_chunks;
+    W.bitem_off = n_all_runs;
     size_t end = pos;
     uint64_t bytes = 0, nbk = 0;
     while (end < hplans.size()) {
@@ -2223,34 +2226,41 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       nbk += nbuckets;
       ++end;
     }
-    std::vector<Chunk> interp;  // chunks of instances without tables go last
-    std::vector<BRun> interp_runs;  // so do runs of items without tables
+    // chunks and runs of items with term tables first, then the others
+    std::vector<ExpandSpec> interp, interp_runs;
+    uint64_t tab_chunks = 0, tab_runs = 0, oth_chunks = 0, oth_runs = 0;
     for (size_t i = pos; i < end; ++i) {
       const HItem& h = hplans[i].h;
       uint32_t li = (uint32_t)plan->hitems.size();  // global item index
       plan->hitems.push_back(h);
       plan->hR.push_back(hplans[i].R);
       plan->presplit.push_back(0);
-      std::vector<BRun>& rdst =
-          P.tabs[h.inst_i].on && P.tabs[h.inst_j].on ? all_runs : interp_runs;
-      for (uint32_t b = 0; b < h.nbuckets; b += plan->run_buckets)
-        rdst.push_back({li, b, std::min(h.nbuckets, b + plan->run_buckets), 0});
+      const bool tr = P.tabs[h.inst_i].on && P.tabs[h.inst_j].on;
+      const uint32_t nr = (h.nbuckets + plan->run_buckets - 1) / plan->run_buckets;
+      if (nr) {
+        (tr ? run_specs : interp_runs).push_back({li, 0, h.nbuckets, plan->run_buckets, 0});
+        (tr ? tab_runs : oth_runs) += nr;
+      }
       const QPlan& q = Q[h.q];
       for (int side = 0; side < (q.qd.self || h.shared == 2 ? 1 : 2); ++side) {
         uint32_t inst = side ? h.inst_j : h.inst_i;
         uint32_t np = P.dev_insts[inst].npts;
-        std::vector<Chunk>& dst = P.tabs[inst].on ? all_chunks : interp;
-        for (uint32_t p0 = 0; p0 < np; p0 += plan->chunk_pts)
-          dst.push_back({li, (uint32_t)side, p0, std::min(np, p0 + plan->chunk_pts)});
+        const uint32_t nc = (np + plan->chunk_pts - 1) / plan->chunk_pts;
+        if (!nc) continue;
+        (P.tabs[inst].on ? chunk_specs : interp).push_back(
+            {li, (uint32_t)side, np, plan->chunk_pts, 0});
+        (P.tabs[inst].on ? tab_chunks : oth_chunks) += nc;
       }
     }
-    W.n_tab_chunks = (uint32_t)(all_chunks.size() - W.chunk_off);
-    all_chunks.insert(all_chunks.end(), interp.begin(), interp.end());
-    W.n_tab_runs = (uint32_t)(all_runs.size() - W.bitem_off);
-    all_runs.insert(all_runs.end(), interp_runs.begin(), interp_runs.end());
+    chunk_specs.insert(chunk_specs.end(), interp.begin(), interp.end());
+    run_specs.insert(run_specs.end(), interp_runs.begin(), interp_runs.end());
+    W.n_tab_chunks = (uint32_t)tab_chunks;
+    W.n_tab_runs = (uint32_t)tab_runs;
     W.n_items = (uint32_t)(end - pos);
-    W.n_runs = (uint32_t)(all_runs.size() - W.bitem_off);
-    W.n_chunks = (uint32_t)(all_chunks.size() - W.chunk_off);
+    W.n_runs = (uint32_t)(tab_runs + oth_runs);
+    W.n_chunks = (uint32_t)(tab_chunks + oth_chunks);
+    n_all_chunks += W.n_chunks;
+    n_all_runs += W.n_runs;
     W.n_buckets = (uint32_t)nbk;
     W.key_bytes = bytes;
     plan->max_key_bytes = std::max(plan->max_key_bytes, bytes);
@@ -2324,8 +2334,27 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   up("evals", evals.data(), n_pairs * 8);
   up("sitems", sitems.data(), sitems.size() * sizeof(SItem));
   up("hitems", plan->hitems.data(), plan->hitems.size() * sizeof(HItem));
-  up("chunks", all_chunks.data(), all_chunks.size() * sizeof(Chunk));
-  up("runs", all_runs.data(), all_runs.size() * sizeof(BRun));
+  {
+    // every chunk and run, expanded on the device from their specs
+    auto expand = [&](std::vector<ExpandSpec>& sp, const char* name, uint64_t total,
+                      bool runs) {
+      uint64_t at = 0;
+      for (ExpandSpec& e : sp) {
+        e.first = at;
+        at += (e.n + e.per - 1) / e.per;
+      }
+      void* out = plan->buf(name, std::max<uint64_t>(1, total) * 16, &merr);
+      if (merr || sp.empty()) return;
+      const char* sname = runs ? "run_specs" : "chunk_specs";
+      void* d = up(sname, sp.data(), sp.size() * sizeof(ExpandSpec));
+      if (merr || !d) return;
+      if (launch_expand(plan->st, (const ExpandSpec*)d, (uint32_t)sp.size(), total, runs, out) ||
+          hipStreamSynchronize(plan->st) != hipSuccess)
+        merr = RD_EDEVICE;
+    };
+    expand(chunk_specs, "chunks", n_all_chunks, false);
+    expand(run_specs, "runs", n_all_runs, true);
+  }
   {
     // proven facts per instance for the unit filter of rd_execute
     std::vector<IFact> facts(std::max<size_t>(1, P.dev_insts.size()));

@@ -209,6 +209,16 @@ struct Chunk {
   uint32_t p0, p1;  // point index range
 };
 
+// Compact description of consecutive chunks or bucket runs: [0, n) (points
+// of one side, or buckets of one item) cut into pieces of `per`, which
+// become entries first, first + 1, ... of the Chunk (item, side, p0, p1)
+// or BRun (item, b0, b1) array.
+struct ExpandSpec {
+  uint32_t item, side, n, per;
+  unsigned long long first;
+};
+static_assert(sizeof(ExpandSpec) == 24, "ExpandSpec layout");
+
 // ---- VERDICT mode (learned tile order) --------------------------------------
 
 // Block-bounds work item: block `block` of access instance `inst` (query q);

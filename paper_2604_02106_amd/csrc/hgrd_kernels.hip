@@ -1487,6 +1487,35 @@ int launch_tabulate(hipStream_t st, const Chunk* chunks, uint32_t n,
   return 0;
 }
 
+// One thread per output entry: the spec holding it by binary search over
+// the specs' first entries, then its slice.
+__global__ void k_expand(const ExpandSpec* __restrict__ specs, uint32_t n, u64 total,
+                         bool runs, uint4* __restrict__ out) {
+  for (u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (u64)gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = n - 1;  // the last spec whose first entry is <= e
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (specs[mid].first <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    const ExpandSpec sp = specs[lo];
+    const uint32_t a = (uint32_t)(e - sp.first) * sp.per;
+    const uint32_t b = min(sp.n, a + sp.per);
+    out[e] = runs ? make_uint4(sp.item, a, b, 0u) : make_uint4(sp.item, sp.side, a, b);
+  }
+}
+
+int launch_expand(hipStream_t st, const ExpandSpec* specs, uint32_t n, u64 total, bool runs,
+                  void* out) {
+  if (n == 0 || total == 0) return 0;
+  const u64 blocks = (total + 255) / 256;
+  hipLaunchKernelGGL(k_expand, dim3((uint32_t)(blocks < 65536 ? blocks : 65536)), dim3(256), 0,
+                     st, specs, n, total, runs, (uint4*)out);
+  HGRD_CHECK(hipGetLastError());
+  return 0;
+}
+
 int launch_unit_filter(hipStream_t st, uint32_t n, const HItem* hitems, const QDesc* qd,
                        const IFact* facts, uint32_t* ovf, unsigned long long* napart) {
   if (n == 0) return 0;

@@ -36,6 +36,10 @@ int launch_small(int cfg, hipStream_t st, const SItem* items, uint32_t n,
                  const int64_t* loopvals, const QDesc* qd, QAcc* acc,
                  const uint32_t* done, uint32_t* cursor, uint32_t persist_grid,
                  const IFact* facts);
+// Writes every Chunk (runs = false) or BRun (runs = true) the specs
+// describe (`total` in all, 16 bytes each) to `out`.
+int launch_expand(hipStream_t st, const ExpandSpec* specs, uint32_t n, unsigned long long total,
+                  bool runs, void* out);
 int launch_unit_filter(hipStream_t st, uint32_t n, const HItem* hitems, const QDesc* qd,
                        const IFact* facts, uint32_t* ovf, unsigned long long* napart);
 int init_kernel_attributes();
