@@ -2515,18 +2515,25 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     const uint32_t wcap = (uint32_t)join_cap(wcfg);
     events = events && !plan->arena;  // no event is created in an arena call
     for (const auto& W : waves) {
+      // e0..e4: markers around the stages; ke: start and stop of the
+      // table-path partition, filter and join kernels, taken by their
+      // dispatch packets (markers between kernels can be timestamped before
+      // the previous kernel has finished)
       const uint32_t k = wev_n;
-      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr,
-                 e5 = nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr;
+      hipEvent_t ke[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
       if (events) {
-        wev_n += 6;
+        wev_n += 11;
         e0 = wevent(k);
         e1 = wevent(k + 1);
         e2 = wevent(k + 2);
         e3 = wevent(k + 3);
         e4 = wevent(k + 4);
-        e5 = wevent(k + 5);
-        if (!e0 || !e1 || !e2 || !e3 || !e4 || !e5) return RD_EDEVICE;
+        for (int x = 0; x < 6; ++x) {
+          ke[x] = wevent(k + 5 + x);
+          if (!ke[x]) return RD_EDEVICE;
+        }
+        if (!e0 || !e1 || !e2 || !e3 || !e4) return RD_EDEVICE;
       }
       if (launch_fill_u32(st, d_cursor, W.n_buckets, 0)) return RD_EDEVICE;
       // partition: instances with term tables, then the interpreted ones
@@ -2535,7 +2542,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       if (W.n_tab_chunks &&
           launch_scatter(st, d_chk + W.chunk_off, W.n_tab_chunks, true, d_hit, d_insts,
                          d_code, d_params, d_loops, d_acc, d_recs,
-                         d_cursor, d_ovf, wcap, d_done, d_nbytes))
+                         d_cursor, d_ovf, wcap, d_done, d_nbytes, ke[0], ke[1]))
         return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(e1, st));
       if (W.n_chunks > W.n_tab_chunks &&
@@ -2553,7 +2560,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
           launch_bucket(wcfg, st, W.n_tab_runs, d_bit + W.bitem_off, W.n_tab_runs, d_hit,
                         d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs,
                         d_cursor, d_ovf, d_done, l0k, l0c, cand, d_nbytes + 128,
-                        events ? e5 : nullptr))
+                        events ? ke + 2 : nullptr))
         return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(e3, st));
       if (W.n_runs > W.n_tab_runs &&
@@ -2563,8 +2570,11 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
         return RD_EDEVICE;
       if (events) {
         TRY_HIP(hipEventRecord(e4, st));
-        wtimes.push_back({k, k + 1, k + 2, k + 3, k + 4, W.n_tab_chunks ? 1u : 0u,
-                          W.n_tab_runs ? 1u : 0u, k + 5});
+        // per-kernel figures only for the first phase (the context's tile
+        // shape); re-partition rounds use other tile shapes
+        const uint32_t first = wcfg == cfg && d_hit == d_hitems_all;
+        wtimes.push_back({k, k + 1, k + 2, k + 3, k + 4, first && W.n_tab_chunks ? 1u : 0u,
+                          first && W.n_tab_runs ? 1u : 0u, k + 5});
       }
       if (W.n_buckets) S.join_launches += 1;
       S.buckets += W.n_buckets;
@@ -2574,25 +2584,25 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   auto collect_waves = [&]() {
     for (const auto& t : wtimes) {
       float ms = 0;
-      if (hipEventElapsedTime(&ms, ctx->wev[t[0]], ctx->wev[t[1]]) == hipSuccess) {
+      if (hipEventElapsedTime(&ms, ctx->wev[t[0]], ctx->wev[t[1]]) == hipSuccess)
         scatter_ms += ms;
-        if (t[5]) {
-          S.scatter_tab_ms += ms;
-          S.scatter_launches += 1;
-        }
+      // t[7]..t[7] + 5: start and stop of the table-path partition, filter
+      // and join kernels
+      if (t[5] && hipEventElapsedTime(&ms, ctx->wev[t[7]], ctx->wev[t[7] + 1]) == hipSuccess) {
+        S.scatter_tab_ms += ms;
+        S.scatter_launches += 1;
       }
       if (hipEventElapsedTime(&ms, ctx->wev[t[1]], ctx->wev[t[2]]) == hipSuccess)
         scatter_ms += ms;
       if (hipEventElapsedTime(&ms, ctx->wev[t[2]], ctx->wev[t[3]]) == hipSuccess)
         bucket_ms += ms;
-      // table-path runs: filter (t[2] .. t[7]) and join (t[7] .. t[3])
       if (t[6]) {
         if (use_filter &&
-            hipEventElapsedTime(&ms, ctx->wev[t[2]], ctx->wev[t[7]]) == hipSuccess) {
+            hipEventElapsedTime(&ms, ctx->wev[t[7] + 2], ctx->wev[t[7] + 3]) == hipSuccess) {
           S.filter_tab_ms += ms;
           S.filter_tab_launches += 1;
         }
-        if (hipEventElapsedTime(&ms, ctx->wev[t[7]], ctx->wev[t[3]]) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, ctx->wev[t[7] + 4], ctx->wev[t[7] + 5]) == hipSuccess) {
           S.join_tab_ms += ms;
           S.join_tab_launches += 1;
         }

@@ -25,6 +25,7 @@
 // the expression code, loop tables and launch extents are uniform and live
 // in scalar registers.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 #include "hgrd_internal.h"
 #include "hgrd_launch.h"
@@ -1361,31 +1362,50 @@ static int launch_bucket_t(hipStream_t st, uint32_t nruns, const BRun* runs,
                            const unsigned char* recs, const uint32_t* cursor,
                            const uint32_t* ovf, const uint32_t* done,
                            const u64* l0keys, const u64* l0cnt, uint8_t* cand,
-                           u64* nbytes, hipEvent_t mid) {
+                           u64* nbytes, const hipEvent_t* kev) {
   // runs [0, n_tab) are of items whose instances have term tables; record
   // bytes read by the join are counted in nbytes[0..63] and nbytes[64..127],
   // by the address filter (when cand is given) in nbytes[256..319].  The
   // filter runs over every run first; `mid` (optional) is recorded between
   // filter and join.
   size_t lds = sizeof(JoinLds<CAP, TBL>);
+  // kev (optional): start and stop events of the filter, then of the join
+  // of the first n_tab runs, taken by the dispatch packets themselves
+  const hipEvent_t f0 = kev ? kev[0] : nullptr, f1 = kev ? kev[1] : nullptr;
+  const hipEvent_t j0 = kev ? kev[2] : nullptr, j1 = kev ? kev[3] : nullptr;
   if (cand) {
     const size_t flds = sizeof(FilterLds<CAP>);
     for (uint32_t off = 0; off < nruns; off += 1u << 20) {
       uint32_t m = nruns - off < (1u << 20) ? nruns - off : (1u << 20);
-      hipLaunchKernelGGL(k_bucket_filter<CAP>, dim3(m), dim3(kFilterThreads), flds,
-                         st, runs + off, hitems, qd, insts, recs, cursor, ovf, done, cand,
-                         nbytes + 256);
+      const hipEvent_t a = off == 0 ? f0 : nullptr;
+      const hipEvent_t b = off + m == nruns ? f1 : nullptr;
+      if (a || b)
+        hipExtLaunchKernelGGL(k_bucket_filter<CAP>, dim3(m), dim3(kFilterThreads), flds, st, a,
+                              b, 0, runs + off, hitems, qd, insts, recs, cursor, ovf, done,
+                              cand, nbytes + 256);
+      else
+        hipLaunchKernelGGL(k_bucket_filter<CAP>, dim3(m), dim3(kFilterThreads), flds,
+                           st, runs + off, hitems, qd, insts, recs, cursor, ovf, done, cand,
+                           nbytes + 256);
       HGRD_CHECK(hipGetLastError());
     }
   }
-  if (mid) HGRD_CHECK(hipEventRecord(mid, st));
   for (uint32_t off = 0; off < nruns; off += 1u << 20) {
     uint32_t m = nruns - off < (1u << 20) ? nruns - off : (1u << 20);
     uint32_t mt = off >= n_tab ? 0 : (n_tab - off < m ? n_tab - off : m);
-    if (mt)
-      hipLaunchKernelGGL((k_bucket_join<CAP, TBL, true>), dim3(mt), dim3(kJoinThreads), lds,
-                         st, runs + off, hitems, insts, code, params, loopvals, qd, acc,
-                         recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes);
+    if (mt) {
+      const hipEvent_t a = off == 0 ? j0 : nullptr;
+      const hipEvent_t b = off + mt == n_tab ? j1 : nullptr;
+      if (a || b)
+        hipExtLaunchKernelGGL((k_bucket_join<CAP, TBL, true>), dim3(mt), dim3(kJoinThreads), lds,
+                              st, a, b, 0, runs + off, hitems, insts, code, params, loopvals, qd,
+                              acc, recs, cursor, ovf, done, l0keys, l0cnt, (const uint8_t*)cand,
+                              nbytes);
+      else
+        hipLaunchKernelGGL((k_bucket_join<CAP, TBL, true>), dim3(mt), dim3(kJoinThreads), lds,
+                           st, runs + off, hitems, insts, code, params, loopvals, qd, acc,
+                           recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes);
+    }
     if (m > mt)
       hipLaunchKernelGGL((k_bucket_join<CAP, TBL, false>), dim3(m - mt), dim3(kJoinThreads),
                          lds, st, runs + off + mt, hitems, insts, code, params, loopvals,
@@ -1530,11 +1550,18 @@ int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n, bool tab,
                    const int64_t* params, const int64_t* loopvals, QAcc* acc,
                    unsigned char* recs, uint32_t* cursor,
                    uint32_t* ovf, uint32_t capb, const uint32_t* done,
-                   unsigned long long* nbytes) {
-  // tab: every chunk's instance has term tables
+                   unsigned long long* nbytes, hipEvent_t t0, hipEvent_t t1) {
+  // tab: every chunk's instance has term tables; t0, t1 (optional): start
+  // and stop events taken by the dispatch packets themselves
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
-    if (tab)
+    const hipEvent_t a = off == 0 ? t0 : nullptr;
+    const hipEvent_t b = off + m == n ? t1 : nullptr;
+    if (tab && (a || b))
+      hipExtLaunchKernelGGL(k_scatter<true>, dim3(m), dim3(kScatterThreads), 0, st, a, b, 0,
+                            chunks + off, hitems, (const DevInst*)insts, code, params,
+                            loopvals, acc, recs, cursor, ovf, capb, done, nbytes);
+    else if (tab)
       hipLaunchKernelGGL(k_scatter<true>, dim3(m), dim3(kScatterThreads), 0, st, chunks + off,
                          hitems, (const DevInst*)insts, code, params, loopvals,
                          acc, recs, cursor, ovf, capb, done, nbytes);
@@ -1553,12 +1580,12 @@ int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
                   const QDesc* qd, QAcc* acc, const unsigned char* recs,
                   const uint32_t* cursor, const uint32_t* ovf, const uint32_t* done,
                   const u64* l0keys, const u64* l0cnt, uint8_t* cand, u64* nbytes,
-                  hipEvent_t mid) {
+                  const hipEvent_t* kev) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, mid);
-    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, mid);
-    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, mid);
+    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, kev);
+    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, kev);
+    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, kev);
   }
 }
 

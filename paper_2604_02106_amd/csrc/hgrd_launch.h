@@ -49,14 +49,15 @@ int launch_scatter(hipStream_t st, const Chunk* chunks, uint32_t n, bool tab,
                    const int64_t* params, const int64_t* loopvals, QAcc* acc,
                    unsigned char* recs, uint32_t* cursor,
                    uint32_t* ovf, uint32_t capb, const uint32_t* done,
-                   unsigned long long* nbytes);
+                   unsigned long long* nbytes, hipEvent_t t0 = nullptr,
+                   hipEvent_t t1 = nullptr);
 int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
                   uint32_t n_tab, const HItem* hitems, const void* insts,
                   const DInsn* code, const int64_t* params, const int64_t* loopvals,
                   const QDesc* qd, QAcc* acc, const unsigned char* recs,
                   const uint32_t* cursor, const uint32_t* ovf, const uint32_t* done,
                   const unsigned long long* l0keys, const unsigned long long* l0cnt,
-                  uint8_t* cand, unsigned long long* nbytes, hipEvent_t mid);
+                  uint8_t* cand, unsigned long long* nbytes, const hipEvent_t* kev);
 int launch_level0(hipStream_t st, const Chunk* chunks, uint32_t n,
                   const L0Item* items, const void* insts, const DInsn* code,
                   const int64_t* params, const int64_t* loopvals,
