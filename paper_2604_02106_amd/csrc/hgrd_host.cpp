@@ -1665,6 +1665,7 @@ struct rd_plan_impl {
   std::vector<BItem> bitems_interp; // VERDICT blocks of interpreted instances
   uint32_t K = 0;                  // tiles searched per search unit
   uint32_t n_vq = 0, n_bitems = 0, n_tchunks = 0, max_tiles = 0;
+  uint32_t max_g = 0;  // most blocks per side of a search unit
   uint64_t n_tiles = 0;
   std::vector<std::pair<uint32_t, uint32_t>> rounds;  // [item lo, item hi)
   uint32_t n_titems = 0;
@@ -2120,6 +2121,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
           tchunks.push_back({(uint32_t)vqs.size(), t0, std::min(nt, t0 + 4096), 0});
         plan->n_tiles += nt;
         plan->max_tiles = std::max(plan->max_tiles, nt);
+        plan->max_g = std::max(plan->max_g, v.G);
         vqs.push_back(v);
       }
     }
@@ -2376,7 +2378,6 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     up("tchunks", tchunks.data(), tchunks.size() * sizeof(TChunk));
     up("titems", titems.data(), titems.size() * sizeof(TItem));
     plan->buf("bbounds", std::max<size_t>(1, bitems.size()) * sizeof(BBound), &merr);
-    plan->buf("scores", std::max<size_t>(1, plan->n_tiles) * 4, &merr);
     if (plan->score_mode) {
       plan->buf("order", std::max<size_t>(1, (size_t)vqs.size() * plan->K) * 4, &merr);
       if (plan->score_mode == 1) up("mlp_w", o.mlp, (size_t)mlp_num_weights() * 4);
@@ -2629,7 +2630,6 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     if (plan->verdict && plan->n_vq) {
       VQuery* d_vq = (VQuery*)D("vq");
       BBound* d_bb = (BBound*)D("bbounds");
-      float* d_sc = (float*)D("scores");
       uint32_t* d_order = plan->score_mode ? (uint32_t*)D("order") : nullptr;
       TOut* d_tout = (TOut*)D("tout");
       u64* d_claim = (u64*)D("claim");
@@ -2638,15 +2638,15 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
           launch_vq_span(st, d_vq, plan->n_vq, d_bb))
         return RD_EDEVICE;
       if (plan->score_mode) {
-        if (launch_tile_scores(st, (const TChunk*)D("tchunks"), plan->n_tchunks, d_vq,
-                               d_bb, (const float*)D("mlp_w"), plan->score_mode, d_sc) ||
-            launch_topk(st, d_vq, plan->n_vq, d_sc, plan->K, plan->max_tiles, d_order))
+        if (launch_tile_rank(st, d_vq, plan->n_vq, d_bb, (const float*)D("mlp_w"),
+                             plan->score_mode, plan->K, plan->max_g, d_facts, d_qd, d_order))
           return RD_EDEVICE;
       }
       for (auto& rr : plan->rounds) {
         if (launch_tile_join(cfg, st, (const TItem*)D("titems"), rr.first,
                              rr.second - rr.first, d_vq, d_order, plan->K, d_insts,
-                             d_code, d_params, d_loops, d_qd, d_done, d_tout, d_claim, d_bb) ||
+                             d_code, d_params, d_loops, d_qd, d_done, d_tout, d_claim, d_bb,
+                             d_facts) ||
             launch_verdict_commit(st, n_pairs, d_claim, d_tout, d_acc, d_done))
           return RD_EDEVICE;
       }
@@ -3299,7 +3299,7 @@ int rd_tile_data(rd_context* ctx, const rd_kernel_model* models,
                          rr.second - rr.first, d_vq, nullptr, plan->K, D("insts"),
                          (const DInsn*)D("code"), (const int64_t*)D("params"),
                          (const int64_t*)D("loops"), (const QDesc*)D("qdesc"), d_done,
-                         d_tout, (u64*)D("claim"), d_bb))
+                         d_tout, (u64*)D("claim"), d_bb, nullptr))
       return RD_EDEVICE;
   std::vector<TOut> tout(plan->n_titems);
   std::vector<QAcc> acc(n_pairs);

@@ -99,6 +99,12 @@ int launch_tile_scores(hipStream_t st, const TChunk* chunks, uint32_t n,
                        uint32_t mode, float* scores);
 int launch_tile_features(hipStream_t st, const TChunk* chunks, uint32_t n,
                          const VQuery* vq, const BBound* bb, float* feats);
+// Tile order of every search unit (mode 1 network, 2 interval order):
+// candidates are the tiles whose blocks' address ranges meet; K slots per
+// unit in order[] (kNoTile when fewer).  max_g: the largest G of the units.
+int launch_tile_rank(hipStream_t st, const VQuery* vq, uint32_t nvq, const BBound* bb,
+                     const float* w, uint32_t mode, uint32_t K, uint32_t max_g,
+                     const IFact* facts, const QDesc* qd, uint32_t* order);
 int launch_topk(hipStream_t st, const VQuery* vq, uint32_t nvq,
                 const float* scores, uint32_t K, uint32_t max_tiles,
                 uint32_t* order);
@@ -107,7 +113,8 @@ int launch_tile_join(int cfg, hipStream_t st, const TItem* items, uint32_t item0
                      uint32_t K, const void* insts, const DInsn* code,
                      const int64_t* params, const int64_t* loopvals,
                      const QDesc* qd, uint32_t* done, TOut* tout,
-                     unsigned long long* claim, const BBound* bb);
+                     unsigned long long* claim, const BBound* bb,
+                     const IFact* facts);
 int launch_verdict_commit(hipStream_t st, uint32_t n,
                           const unsigned long long* claim, const TOut* tout,
                           QAcc* acc, uint32_t* done);

@@ -559,6 +559,101 @@ k_topk(const VQuery* __restrict__ vq, const float* __restrict__ scores,
 }
 
 // ---------------------------------------------------------------------------
+// Tile order of one search unit per workgroup (network or interval order):
+// the blocks' address bounds of both sides are staged in LDS, every tile
+// whose two blocks' address ranges meet becomes a candidate (the others
+// hold no conflict and are never searched), the candidates are scored in a
+// compacted list (every lane busy: mode 1 runs the network on each, mode 2
+// keeps index order) and sorted by (score descending, index); the first K
+// go to order[], the rest of the K slots get kNoTile.  A unit the unit
+// filter proves free of conflicts gets no tile at all.  At most kTopCap
+// candidates per unit (the first ones in index order).
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+__global__ void __launch_bounds__(256)
+k_tile_rank(const VQuery* __restrict__ vq, const BBound* __restrict__ bb,
+            const float* __restrict__ w, uint32_t mode, uint32_t K,
+            const IFact* __restrict__ facts, const QDesc* __restrict__ qd,
+            uint32_t* __restrict__ order) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float cs[kTopCap];
+  __shared__ uint32_t ci[kTopCap];
+  __shared__ uint32_t ncand;
+  const VQuery v = vq[blockIdx.x];
+  const uint32_t G = v.G;
+  uint32_t* out = order + (u64)blockIdx.x * K;
+  const QDesc q = qd[v.q];
+  if (facts && unit_free(facts[v.inst_i], facts[v.inst_j], q.flags,
+                         !q.self && v.inst_i != v.inst_j)) {
+    for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) out[r] = kNoTile;
+    return;
+  }
+  // LDS: [weights (mode 1)] bounds of side a, then of side b
+  float* sw = reinterpret_cast<float*>(smem);
+  BBound* ba = reinterpret_cast<BBound*>(smem + (mode == 1 ? ((kNW * 4 + 15) & ~15) : 0));
+  BBound* bbb = ba + G;
+  if (mode == 1)
+    for (int k = threadIdx.x; k < kNW; k += blockDim.x) sw[k] = w[k];
+  for (uint32_t b = threadIdx.x; b < G; b += blockDim.x) {
+    ba[b] = bb[v.bb_i + b];
+    bbb[b] = bb[v.bb_j + b];
+  }
+  if (threadIdx.x == 0) ncand = 0;
+  __syncthreads();
+  // candidates, rows in index order
+  for (uint32_t b1 = 0; b1 < G; ++b1) {
+    const BBound x = ba[b1];
+    if (!x.cnt) continue;
+    for (uint32_t b2 = threadIdx.x; b2 < G; b2 += blockDim.x) {
+      const BBound y = bbb[b2];
+      if (!y.cnt || x.mx < y.mn || y.mx < x.mn) continue;
+      const uint32_t p = atomicAdd(&ncand, 1u);
+      if (p < kTopCap) ci[p] = b1 * G + b2;
+    }
+  }
+  __syncthreads();
+  const uint32_t n = ncand < kTopCap ? ncand : kTopCap;
+  for (uint32_t c = threadIdx.x; c < n; c += blockDim.x) {
+    float sc = 0.f;  // interval order: by index alone
+    if (mode == 1) {
+      const uint32_t t = ci[c];
+      const uint32_t b1 = t / G, b2 = t - b1 * G;
+      float f[kIn];
+      tile_features(v, b1, b2, ba[b1], bbb[b2], f);
+      sc = mlp_logit(sw, f);
+    }
+    cs[c] = sc;
+  }
+  uint32_t P = 1;
+  while (P < n) P <<= 1;
+  for (uint32_t k = n + threadIdx.x; k < P; k += blockDim.x) {
+    cs[k] = -INFINITY;
+    ci[k] = kNoTile;
+  }
+  __syncthreads();
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t k = threadIdx.x; k < P; k += blockDim.x) {
+        const uint32_t j = k ^ stride;
+        if (j <= k) continue;
+        const bool up = (k & size) == 0;
+        const bool jb = tile_before(cs[j], ci[j], cs[k], ci[k]);
+        if (jb == up) {
+          const float ts = cs[k];
+          const uint32_t ti = ci[k];
+          cs[k] = cs[j];
+          ci[k] = ci[j];
+          cs[j] = ts;
+          ci[j] = ti;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t r = threadIdx.x; r < K; r += blockDim.x) out[r] = r < n ? ci[r] : kNoTile;
+}
+
+// ---------------------------------------------------------------------------
 // Tile search: join block b1 of access a with block b2 of access b in LDS.
 // A query already resolved skips its tiles.  A conflicting tile records its
 // counts and a witness pair from inside the tile, and claims the query by
@@ -572,7 +667,8 @@ k_tile_join(const TItem* __restrict__ items, const VQuery* __restrict__ vq,
             const int64_t* __restrict__ params,
             const int64_t* __restrict__ loopvals, const QDesc* __restrict__ qd,
             uint32_t* __restrict__ done, TOut* __restrict__ tout,
-            u64* __restrict__ claim, uint32_t item0, const BBound* __restrict__ bb) {
+            u64* __restrict__ claim, uint32_t item0, const BBound* __restrict__ bb,
+            const IFact* __restrict__ facts) {
   extern __shared__ __align__(16) unsigned char smem[];
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
   __shared__ uint32_t pidx_star;
@@ -582,6 +678,11 @@ k_tile_join(const TItem* __restrict__ items, const VQuery* __restrict__ vq,
   if (done[v.q]) return;
   const QDesc q = qd[v.q];
   const uint32_t tile = order ? order[(u64)it.vq * K + it.rank] : it.rank;
+  if (tile == kNoTile) return;  // fewer candidate tiles than ranks
+  // plain order: a unit proven free of conflicts searches nothing
+  if (!order && facts && unit_free(facts[v.inst_i], facts[v.inst_j], q.flags,
+                                   !q.self && v.inst_i != v.inst_j))
+    return;
   const uint32_t b1 = tile / v.G, b2 = tile - (tile / v.G) * v.G;
   {
     // a tile whose blocks' address ranges are disjoint holds no conflict
@@ -759,6 +860,18 @@ int launch_tile_features(hipStream_t st, const TChunk* chunks, uint32_t n,
   return 0;
 }
 
+int launch_tile_rank(hipStream_t st, const VQuery* vq, uint32_t nvq, const BBound* bb,
+                     const float* w, uint32_t mode, uint32_t K, uint32_t max_g,
+                     const IFact* facts, const QDesc* qd, uint32_t* order) {
+  if (!nvq) return 0;
+  const size_t lds = (mode == 1 ? ((kNW * 4 + 15) & ~(size_t)15) : 0) +
+                     2 * (size_t)max_g * sizeof(BBound);
+  hipLaunchKernelGGL(k_tile_rank, dim3(nvq), dim3(256), lds, st, vq, bb, w, mode, K, facts,
+                     qd, order);
+  HGRD_CHECK(hipGetLastError());
+  return 0;
+}
+
 int launch_topk(hipStream_t st, const VQuery* vq, uint32_t nvq,
                 const float* scores, uint32_t K, uint32_t max_tiles,
                 uint32_t* order) {
@@ -775,13 +888,13 @@ static int launch_tile_join_t(hipStream_t st, const TItem* items, uint32_t item0
                               uint32_t K, const void* insts, const DInsn* code,
                               const int64_t* params, const int64_t* loopvals,
                               const QDesc* qd, uint32_t* done, TOut* tout,
-                              u64* claim, const BBound* bb) {
+                              u64* claim, const BBound* bb, const IFact* facts) {
   size_t lds = sizeof(JoinLds<CAP, TBL>);
   for (uint32_t off = 0; off < n; off += 1u << 20) {
     uint32_t m = n - off < (1u << 20) ? n - off : (1u << 20);
     hipLaunchKernelGGL((k_tile_join<CAP, TBL>), dim3(m), dim3(256), lds, st,
                        items, vq, order, K, (const DevInst*)insts, code, params,
-                       loopvals, qd, done, tout, claim, item0 + off, bb);
+                       loopvals, qd, done, tout, claim, item0 + off, bb, facts);
     HGRD_CHECK(hipGetLastError());
   }
   return 0;
@@ -792,11 +905,11 @@ int launch_tile_join(int cfg, hipStream_t st, const TItem* items, uint32_t item0
                      uint32_t K, const void* insts, const DInsn* code,
                      const int64_t* params, const int64_t* loopvals,
                      const QDesc* qd, uint32_t* done, TOut* tout,
-                     unsigned long long* claim, const BBound* bb) {
+                     unsigned long long* claim, const BBound* bb, const IFact* facts) {
   switch (cfg) {
-    case 0: return launch_tile_join_t<1024, 2048>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim, bb);
-    case 1: return launch_tile_join_t<1536, 4096>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim, bb);
-    default: return launch_tile_join_t<3072, 8192>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim, bb);
+    case 0: return launch_tile_join_t<1024, 2048>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim, bb, facts);
+    case 1: return launch_tile_join_t<1536, 4096>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim, bb, facts);
+    default: return launch_tile_join_t<3072, 8192>(st, items, item0, n, vq, order, K, insts, code, params, loopvals, qd, done, tout, claim, bb, facts);
   }
 }
 
@@ -845,6 +958,10 @@ int launch_adam(hipStream_t st, float* w, float* g, float* m, float* v, float lr
 int mlp_num_weights() { return kNW; }
 
 int init_verdict_attributes() {
+  // tile ranking: weights and the bounds of both sides of up to 1024 blocks
+  HGRD_CHECK(hipFuncSetAttribute((const void*)k_tile_rank,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(((kNW * 4 + 15) & ~15) + 2 * 1024 * sizeof(BBound))));
   HGRD_CHECK(hipFuncSetAttribute((const void*)k_tile_join<1024, 2048>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)sizeof(JoinLds<1024, 2048>)));

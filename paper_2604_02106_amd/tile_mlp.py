@@ -17,7 +17,7 @@ import paper_2604_02106_amd as hg
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT = os.path.join(HERE, "weights", "tile_mlp")
-FEATURE_VERSION = 1
+FEATURE_VERSION = 2  # 32 features incl. per-thread / per-block address steps
 
 
 def init_weights(seed=0):
@@ -31,10 +31,13 @@ def init_weights(seed=0):
 
 
 def training_workloads(seed=4005):
-    """Sparse-witness queries (small grids) plus batched-style models."""
+    """Sparse-witness queries with disjoint and with overlapping tiles
+    (small grids) plus batched-style models; evaluation uses other seeds."""
     from workloads import configs
     wls = [configs.sparse(seed=seed, n_queries=256, G=32, B=64,
                           queries_per_model=32),
+           configs.sparse_overlap(seed=seed, n_queries=256, G=32, B=64,
+                                  queries_per_model=32),
            configs.batched(seed=seed + 1, n_models=32, scale=0.02, max_iters=4)]
     return wls
 

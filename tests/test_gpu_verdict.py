@@ -142,28 +142,38 @@ def test_tile_labels_match_brute_force(hg):
 
 def test_training_lowers_loss_and_mlp_order_gains(hg):
     """Train on tile labels of training workloads (seed 4005), then on
-    held-out sparse-witness queries (seed 4004) compare the tiles examined
-    before the first witness: learned order against LEX."""
+    held-out queries whose tiles all overlap but one conflicts (seed 4004)
+    compare the tiles examined before the first witness: the trained
+    network against plain index order (LEX), index order after the tiles
+    proven disjoint (interval order), and the same network untrained."""
     ctx = hg.default_context()
     from paper_2604_02106_amd import tile_mlp
     say("train")
     w, losses, info = tile_mlp.train(ctx, epochs=12, seed=1)
     assert losses[-1] < 0.5 * losses[0], losses
-    wl = configs.sparse(seed=4004, n_queries=256, G=64, B=64, queries_per_model=32)
-    res = {}
-    for order in (0, 1):
-        say("gain order", order)
-        plan = hg.Plan(ctx, wl, mode=hg.MODE_VERDICT, order=order,
-                       mlp=w if order else None, tile_budget=4096)
-        got = plan.execute()
-        res[order] = (got, plan.tiles())
+    G = 64
+    wl = configs.sparse_overlap(seed=4004, n_queries=256, G=G, B=64, queries_per_model=32)
+    arms = {"lex": (hg.ORDER_LEX, None), "interval": (hg.ORDER_INTERVAL, None),
+            "trained": (hg.ORDER_MLP, w)}
+    # the same network untrained: 8 random initialisations (one of them may
+    # happen to rank the lone off-diagonal overlapping tile first)
+    for s in range(8):
+        arms["untrained %d" % s] = (hg.ORDER_MLP, tile_mlp.init_weights(100 + s))
     want, _ = oracle.check_pairs(wl, "B", threads=8)
     racy = [k for k, r in enumerate(want) if r["verdict"]]
     assert len(racy) > 50
-    for order in (0, 1):
-        got, tiles = res[order]
-        assert [g["verdict"] for g in got] == [r["verdict"] for r in want]
-    t_lex = np.array([res[0][1][k] or 4097 for k in racy])
-    t_mlp = np.array([res[1][1][k] or 4097 for k in racy])
-    say("median tiles LEX %s MLP %s" % (np.median(t_lex), np.median(t_mlp)))
-    assert np.median(t_mlp) <= 4 and np.median(t_lex) > 100
+    med = {}
+    for name, (order, wt) in arms.items():
+        say("gain arm", name)
+        plan = hg.Plan(ctx, wl, mode=hg.MODE_VERDICT, order=order, mlp=wt,
+                       tile_budget=G * G)
+        got = plan.execute()
+        tiles = plan.tiles()
+        assert [g["verdict"] for g in got] == [r["verdict"] for r in want], name
+        t = np.array([tiles[k] or G * G + 1 for k in racy])
+        med[name] = float(np.median(t))
+    untrained = float(np.mean([med["untrained %d" % s] for s in range(8)]))
+    say("median tiles to the witness", med, "untrained mean", untrained)
+    assert med["trained"] <= 4
+    assert med["interval"] > 8 and med["lex"] > 100
+    assert untrained >= 4 * max(1.0, med["trained"])
