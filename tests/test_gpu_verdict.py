@@ -117,6 +117,31 @@ def test_mlp_forward_and_gradient_match_float64(hg):
     assert np.allclose(g_gpu, g_ref, rtol=1e-4, atol=1e-5 * scale)
 
 
+def test_adam_steps_match_closed_form(hg):
+    """Two full-batch steps of rd_mlp_train (Adam, beta1 0.9, beta2 0.999,
+    eps 1e-8, bias-corrected) against the same two steps in float64 with
+    the reference network's gradients."""
+    ctx = hg.default_context()
+    rng = np.random.Generator(np.random.PCG64(6))
+    X = rng.normal(size=(256, 32)).astype(np.float32)
+    Y = (rng.random(256) < 0.4).astype(np.float32)
+    w0 = ref.flatten(ref.init(11)).astype(np.float32)
+    lr = 1e-3
+    w_gpu, _ = hg.rd_mlp_train(ctx, w0, X, Y, epochs=2, batch=256, lr=lr, seed=3)
+    b1, b2, eps = 0.9, 0.999, 1e-8
+    w = w0.astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    for t in (1, 2):
+        g = ref.flatten(ref.grad(ref.unflatten(w), X.astype(np.float64), Y.astype(np.float64)))
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        w = w - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+    moved = np.abs(w - w0) > 0.5 * lr
+    assert moved.mean() > 0.5  # most weights take about lr per step
+    assert np.allclose(w_gpu, w, rtol=0, atol=2e-2 * lr)
+
+
 def test_tile_labels_match_brute_force(hg):
     ctx = hg.default_context()
     wl = configs.sparse(seed=12, n_queries=8, G=8, B=16, queries_per_model=8)
