@@ -430,6 +430,11 @@ typedef struct {
                                 every block holds the same conflicts and the
                                 counts are block 0's times the blocks
                                 (HGRD_NO_SYMMETRY at rd_prepare turns it off) */
+  uint64_t fallback_groups;  /* records the fallback wrote: lanes of one
+                                wavefront with equal (address, block,
+                                iteration, warp, intervals) share one record
+                                that carries its lane mask, so this is at most
+                                the points of the fallback items */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

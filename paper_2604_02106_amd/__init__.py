@@ -137,7 +137,8 @@ class rd_stats(C.Structure):
                 ("filter_tab_launches", C.c_uint64), ("filter_tab_ms", C.c_double),
                 ("filter_tab_bytes", C.c_uint64),
                 ("units_apart", C.c_uint64),
-                ("block_symmetric", C.c_uint64)]
+                ("block_symmetric", C.c_uint64),
+                ("fallback_groups", C.c_uint64)]
 
 
 assert C.sizeof(rd_pair_result) == 88

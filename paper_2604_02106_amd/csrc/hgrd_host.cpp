@@ -3053,7 +3053,9 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     g.item = (uint32_t*)ctx->ensure("g_item", n * 4, &merr);
     g.slot = (uint32_t*)ctx->ensure("g_slot", n * 4, &merr);
     g.part = ctx->ensure("g_part", n * 8, &merr);
-    uint32_t* owner = (uint32_t*)ctx->ensure("g_owner", tbl * 4, &merr);
+    g.mult = (uint32_t*)ctx->ensure("g_mult", n * 4, &merr);
+    g.lanes = ctx->ensure("g_lanes", n * 8, &merr);
+    void* owner = ctx->ensure("g_owner", tbl * 8, &merr);
     void* cnt = ctx->ensure("g_cnt", tbl * 8, &merr);
     void* gS = ctx->ensure("g_S", (size_t)nf * 64, &merr);
     uint32_t* gcount = (uint32_t*)ctx->ensure("g_count", (size_t)nf * 4, &merr);
@@ -3072,6 +3074,9 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     float ms = 0;
     (void)hipEventElapsedTime(&ms, ev[7], ev[8]);
     fallback_ms += ms;
+    std::vector<uint32_t> written(nf);
+    TRY_HIP(hipMemcpy(written.data(), gcount, nf * 4, hipMemcpyDeviceToHost));
+    for (uint32_t w : written) S.fallback_groups += w;
     fpos = fend;
   }
 

@@ -948,16 +948,31 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
 // every prefix level is aggregated in an HBM hash table keyed by (item,
 // level key).  Each workgroup first merges its tile of records in an LDS
 // table, so a hot key costs one global atomic per workgroup, not per point.
+//
+// Records are compressed within a wavefront: the lanes of one wavefront
+// hold consecutive points, and when those are consecutive threads of one
+// block and iteration (the instance's thread-fastest point order), lanes
+// with equal addresses in one warp of the analysed program are matched
+// (one ballot per distinct key) and written as one record: the first
+// lane's point, the number of points (mult) and the lanes' mask relative to
+// the first lane (thread tlin + k for bit k).  All points of a record share
+// every key field up to the warp and the warp-barrier interval (one block,
+// one iteration, so the same interval ids; one warp), so levels 0-4 count
+// it with weight mult; the thread level (5) takes its lanes one by one.  A
+// hot address (every thread on one element, as in a final reduction step)
+// then costs one record per warp and wavefront instead of one per point.
 
 struct GRec {
   u64* addr;
   uint32_t* blin;
-  uint32_t* tli;
+  uint32_t* tli;   // ilin << 16 | side << 15 | tlin of the first lane
   uint32_t* bw;
   uint32_t* w;
   uint32_t* item;  // fallback item index, 0xFFFFFFFF: empty slot
   uint32_t* slot;
   long long* part;
+  uint32_t* mult;  // points in the record
+  u64* lanes;      // bit k: thread tlin + k
 };
 
 __global__ void __launch_bounds__(256)
@@ -970,53 +985,84 @@ k_gen_linear(const Chunk* __restrict__ chunks, const FItem* __restrict__ fitems,
   const FItem f = fitems[ch.item];
   DevInst I;
   load_inst(I, insts, ch.side ? f.inst_j : f.inst_i);
+  const bool match = I.a.iorder == 0;  // lanes are consecutive threads of a row
+  const uint32_t lane = threadIdx.x & 63;
   uint32_t err = 0;
   for (uint32_t base = ch.p0; base < ch.p1; base += blockDim.x) {
     uint32_t pidx = base + threadIdx.x;
     bool valid = false;
-    Point pt;
-    PointIds id;
+    Point pt{0, 0, 0};
+    PointIds id{0, 0, 0};
     if (pidx < ch.p1) {
       id = decode(I, pidx);
       valid = point_eval(I, id, code, params, loopvals, pt, err);
     }
-    u64 bal = __ballot(valid);
-    if (bal == 0) continue;
-    uint32_t lane = threadIdx.x & 63;
-    uint32_t leader = __ffsll((long long)bal) - 1;
+    const uint32_t wp = valid ? id.tlin / f.warp : 0;
+    // match: a lane leads the group of pending lanes equal to it in
+    // (address, block, iteration, warp, intervals); with threads fastest in
+    // the point order, lane l + k of such a group is thread tlin + k
+    bool pending = valid, lead = false;
+    u64 mine_mask = 0;
+    for (;;) {
+      const u64 P = __ballot(pending);
+      if (!P) break;
+      const int l = __ffsll((long long)P) - 1;
+      const u64 a = (u64)__shfl((long long)pt.addr, l, 64);
+      const uint32_t b = (uint32_t)__shfl((int)id.blin, l, 64);
+      const uint32_t il = (uint32_t)__shfl((int)id.ilin, l, 64);
+      const uint32_t ww = (uint32_t)__shfl((int)wp, l, 64);
+      const uint32_t iv = (uint32_t)__shfl((int)((pt.bint << 16) | pt.wint), l, 64);
+      const bool mine =
+          pending && (match ? ((u64)pt.addr == a && id.blin == b && id.ilin == il &&
+                               wp == ww && ((pt.bint << 16) | pt.wint) == iv)
+                            : lane == (uint32_t)l);
+      const u64 M = __ballot(mine);
+      if (lane == (uint32_t)l) {
+        lead = true;
+        mine_mask = M >> l;
+      }
+      if (mine) pending = false;
+    }
+    const u64 Lb = __ballot(lead);
+    if (Lb == 0) continue;
+    const uint32_t leader = __ffsll((long long)Lb) - 1;
     uint32_t b0 = 0;
-    if (lane == leader) b0 = atomicAdd(&count[ch.item], (uint32_t)__popcll(bal));
+    if (lane == leader) b0 = atomicAdd(&count[ch.item], (uint32_t)__popcll(Lb));
     b0 = (uint32_t)__builtin_amdgcn_readlane((int)b0, (int)leader);
-    if (valid) {
-      uint32_t k = b0 + __popcll(bal & ((1ull << lane) - 1));
+    if (lead) {
+      uint32_t k = b0 + __popcll(Lb & ((1ull << lane) - 1));
       if (k < f.cap) {
         u64 r = f.off + k;
         rec.addr[r] = (u64)pt.addr;
         rec.blin[r] = id.blin;
         rec.tli[r] = (id.ilin << 16) | (ch.side << 15) | id.tlin;
         rec.bw[r] = (pt.bint << 16) | pt.wint;
-        rec.w[r] = id.tlin / f.warp;
+        rec.w[r] = wp;
         rec.item[r] = ch.item;
         rec.part[r] = 0;
+        rec.mult[r] = (uint32_t)__popcll(mine_mask);
+        rec.lanes[r] = mine_mask;
       }
     }
   }
 }
 
-__device__ __forceinline__ bool g_level_eq(const GRec& g, int L, u64 x, u64 y) {
+// Key equality of (record x, lane kx) and (record y, lane ky) at level L
+// (lanes matter at the thread level only).
+__device__ __forceinline__ bool g_level_eq(const GRec& g, int L, u64 x, uint32_t kx, u64 y,
+                                           uint32_t ky) {
   if (g.item[x] != g.item[y]) return false;
   if (g.addr[x] != g.addr[y]) return false;
   if (L >= 1 && g.blin[x] != g.blin[y]) return false;
   if (L >= 2 && (g.bw[x] >> 16) != (g.bw[y] >> 16)) return false;
   if (L >= 3 && g.w[x] != g.w[y]) return false;
   if (L >= 4 && (g.bw[x] & 0xFFFF) != (g.bw[y] & 0xFFFF)) return false;
-  if (L >= 5 && (g.tli[x] & 0x3FF) != (g.tli[y] & 0x3FF)) return false;
+  if (L >= 5 && (g.tli[x] & 0x3FF) + kx != (g.tli[y] & 0x3FF) + ky) return false;
   return true;
 }
-
-__device__ __forceinline__ uint32_t g_hash(const GRec& g, int L, u64 r) {
+__device__ __forceinline__ uint32_t g_hash(const GRec& g, int L, u64 r, uint32_t k) {
   return level_hash(L, g.addr[r] ^ ((u64)g.item[r] * 0x2545F4914F6CDD1Dull),
-                    g.blin[r], g.bw[r], g.w[r], g.tli[r] & 0x3FF);
+                    g.blin[r], g.bw[r], g.w[r], (g.tli[r] & 0x3FF) + k);
 }
 
 __device__ __forceinline__ bool uses_level(uint32_t mask, int L) {
@@ -1029,10 +1075,11 @@ constexpr int kGLocal = 2048; // LDS table slots
 // Inserts every record at level L.  S[item * 8 + L] += pair contributions.
 __global__ void __launch_bounds__(256)
 k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
-          uint32_t* __restrict__ owner, u64* __restrict__ cnt, u64 tbl_mask,
+          u64* __restrict__ owner, u64* __restrict__ cnt, u64 tbl_mask,
           u64* __restrict__ S) {
   __shared__ uint32_t lown[kGLocal];
-  __shared__ uint32_t lcnt[kGLocal];
+  __shared__ uint32_t lca[kGLocal];  // side-a (self: all) points of the local group
+  __shared__ uint32_t lcb[kGLocal];  // side-b points
   __shared__ uint32_t lgs[kGLocal];
   // level sums of the items of this workgroup's records, merged in LDS so a
   // big item does not serialise on one global counter
@@ -1044,10 +1091,53 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
     sitem[tid] = kEmpty;
     ssum[tid] = 0;
   }
+  // adds a group's points (li on side a, lj on side b) to the global table
+  // and the level sum of item it
+  auto add_global = [&](u64 r, uint32_t k, uint32_t it, bool self, u64 li, u64 lj) -> u64 {
+    u64 h = g_hash(g, L, r, k) & tbl_mask;
+    const u64 me = (r << 6) | k;
+    for (;;) {
+      const u64 o = atomicCAS(&owner[h], ~0ull, me);
+      if (o == ~0ull || g_level_eq(g, L, o >> 6, (uint32_t)(o & 63), r, k)) break;
+      h = (h + 1) & tbl_mask;
+    }
+    const u64 old = atomicAdd(&cnt[h], self ? li : (li | (lj << 32)));
+    u64 contrib;
+    if (self) contrib = 2 * old * li + li * li;  // (old + k)^2 - old^2
+    else contrib = li * (old >> 32) + lj * (old & 0xFFFFFFFFull) + li * lj;
+    if (contrib) {
+      const uint32_t sl = it % kSlots;
+      uint32_t prev = atomicCAS(&sitem[sl], kEmpty, it);
+      if (prev == kEmpty || prev == it) atomicAdd(&ssum[sl], contrib);
+      else atomicAdd(&S[(u64)it * 8 + L], contrib);
+    }
+    return h;
+  };
+  __syncthreads();
   for (u64 t0 = (u64)blockIdx.x * kGTile; t0 < n; t0 += (u64)gridDim.x * kGTile) {
+    if (L == 5) {
+      // thread level: every lane of a record is its own key; thread groups
+      // are small, so lanes go straight to the global table
+#pragma unroll
+      for (int j = 0; j < kGTile / 256; ++j) {
+        const u64 r = t0 + j * 256 + tid;
+        if (r >= n) continue;
+        const uint32_t it = g.item[r];
+        if (it == kEmpty) continue;
+        const FItem f = fitems[it];
+        if (!uses_level(f.mask, L)) continue;
+        const bool sb = ((g.tli[r] >> 15) & 1) != 0;
+        for (u64 m = g.lanes[r]; m; m &= m - 1) {
+          const uint32_t k = (uint32_t)__ffsll((long long)m) - 1;
+          add_global(r, k, it, f.self, (f.self || !sb) ? 1 : 0, (f.self || !sb) ? 0 : 1);
+        }
+      }
+      continue;
+    }
     for (uint32_t k = tid; k < kGLocal; k += blockDim.x) {
       lown[k] = kEmpty;
-      lcnt[k] = 0;
+      lca[k] = 0;
+      lcb[k] = 0;
     }
     __syncthreads();
     uint16_t ls[kGTile / 256];
@@ -1060,15 +1150,16 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
       if (it == kEmpty) continue;
       const FItem f = fitems[it];
       if (!uses_level(f.mask, L)) continue;
-      uint32_t h = g_hash(g, L, r) & (kGLocal - 1);
+      uint32_t h = g_hash(g, L, r, 0) & (kGLocal - 1);
       const uint32_t lr = (uint32_t)(r - t0);
       for (;;) {
         uint32_t o = atomicCAS(&lown[h], kEmpty, lr);
-        if (o == kEmpty || g_level_eq(g, L, t0 + o, r)) break;
+        if (o == kEmpty || g_level_eq(g, L, t0 + o, 0, r, 0)) break;
         h = (h + 1) & (kGLocal - 1);
       }
       uint32_t side = (g.tli[r] >> 15) & 1;
-      atomicAdd(&lcnt[h], (f.self || !side) ? 1u : 0x10000u);
+      // a record weighs its points (levels 0-4 hold all of its lanes)
+      atomicAdd((f.self || !side) ? &lca[h] : &lcb[h], g.mult[r]);
       ls[j] = (uint16_t)h;
     }
     __syncthreads();
@@ -1079,25 +1170,7 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
       u64 r = t0 + lr;
       const uint32_t it = g.item[r];
       const FItem f = fitems[it];
-      u64 h = g_hash(g, L, r) & tbl_mask;
-      for (;;) {
-        uint32_t o = atomicCAS(&owner[h], kEmpty, (uint32_t)r);
-        if (o == kEmpty || g_level_eq(g, L, o, r)) break;
-        h = (h + 1) & tbl_mask;
-      }
-      uint32_t c = lcnt[k];
-      u64 li = c & 0xFFFF, lj = c >> 16;
-      u64 old = atomicAdd(&cnt[h], f.self ? li : (li | (lj << 32)));
-      u64 contrib;
-      if (f.self) contrib = 2 * old * li + li * li;  // (old + k)^2 - old^2
-      else contrib = li * (old >> 32) + lj * (old & 0xFFFFFFFFull) + li * lj;
-      if (contrib) {
-        const uint32_t sl = it % kSlots;
-        uint32_t prev = atomicCAS(&sitem[sl], kEmpty, it);
-        if (prev == kEmpty || prev == it) atomicAdd(&ssum[sl], contrib);
-        else atomicAdd(&S[(u64)it * 8 + L], contrib);
-      }
-      lgs[k] = (uint32_t)h;
+      lgs[k] = (uint32_t)add_global(r, 0, it, f.self, lca[k], lcb[k]);
     }
     __syncthreads();
 #pragma unroll
@@ -1107,11 +1180,14 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
     }
     __syncthreads();
   }
+  __syncthreads();
   if (tid < kSlots && sitem[tid] != kEmpty && ssum[tid])
     atomicAdd(&S[(u64)sitem[tid] * 8 + L], ssum[tid]);
 }
 
-// Adds +-(partners at level L) to every record of side a (self: all).
+// Adds +-(partners at level L < 5) to every record of side a (self: all):
+// the group at such a level holds all of a record's lanes, so the figure
+// is the same for each of them.
 __global__ void __launch_bounds__(256)
 k_gpartner(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
            const u64* __restrict__ cnt) {
@@ -1130,9 +1206,13 @@ k_gpartner(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
   }
 }
 
-// Witness candidates of the fallback records.
+// Witness candidates of the fallback records: the first lane of a record
+// whose partner count is positive.  With the thread level in an item's
+// classes, each lane subtracts its own thread group's other-side count,
+// looked up in the level-5 table (the last one built, still in place).
 __global__ void __launch_bounds__(256)
-k_gfinish(GRec g, u64 n, const FItem* __restrict__ fitems,
+k_gfinish(GRec g, u64 n, const FItem* __restrict__ fitems, const u64* __restrict__ owner,
+          const u64* __restrict__ cnt, u64 tbl_mask, bool level5,
           QAcc* __restrict__ acc) {
   for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < n;
        r += (u64)gridDim.x * blockDim.x) {
@@ -1141,9 +1221,28 @@ k_gfinish(GRec g, u64 n, const FItem* __restrict__ fitems,
     const FItem f = fitems[it];
     uint32_t tl = g.tli[r];
     if (!f.self && (tl & kSide)) continue;
-    if (g.part[r] > 0) {
-      u64 k = pkey(f.sigma, g.blin[r], tl & 0x3FF, tl >> 16);
-      if (k < acc[f.q].pmin) atomicMin(&acc[f.q].pmin, k);
+    const bool l5 = level5 && uses_level(f.mask, 5);
+    for (u64 m = g.lanes[r]; m; m &= m - 1) {
+      const uint32_t k = (uint32_t)__ffsll((long long)m) - 1;
+      long long part = g.part[r];
+      if (l5) {
+        u64 h = g_hash(g, 5, r, k) & tbl_mask;
+        for (;;) {
+          const u64 o = owner[h];
+          if (o == ~0ull) break;  // (never: every lane was inserted)
+          if (g_level_eq(g, 5, o >> 6, (uint32_t)(o & 63), r, k)) {
+            const u64 c = cnt[h];
+            part -= f.self ? (long long)c : (long long)(c >> 32);
+            break;
+          }
+          h = (h + 1) & tbl_mask;
+        }
+      }
+      if (part > 0) {
+        u64 key = pkey(f.sigma, g.blin[r], (tl & 0x3FF) + k, tl >> 16);
+        if (key < acc[f.q].pmin) atomicMin(&acc[f.q].pmin, key);
+        break;  // later lanes have larger keys
+      }
     }
   }
 }
@@ -1600,10 +1699,10 @@ int launch_fallback(hipStream_t st, const Chunk* chunks, uint32_t nchunks,
                     const FItem* fitems, uint32_t nitems, uint32_t used_levels,
                     const void* insts, const DInsn* code, const int64_t* params,
                     const int64_t* loopvals, GRecPtrs gp, u64 n,
-                    uint32_t* count, uint32_t* owner, void* cnt, u64 tbl,
+                    uint32_t* count, void* owner, void* cnt, u64 tbl,
                     void* S, QAcc* acc) {
   GRec g{(u64*)gp.addr, gp.blin, gp.tli, gp.bw, gp.w, gp.item, gp.slot,
-         (long long*)gp.part};
+         (long long*)gp.part, gp.mult, (u64*)gp.lanes};
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, st,
                      gp.item, (uint32_t)n, kEmpty);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, count, nitems, 0u);
@@ -1618,18 +1717,21 @@ int launch_fallback(hipStream_t st, const Chunk* chunks, uint32_t nchunks,
   HGRD_CHECK(hipGetLastError());
   for (int L = 0; L < 6; ++L) {
     if (!((used_levels >> L) & 1)) continue;
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(tbl, 256)), dim3(256), 0, st,
-                       owner, (uint32_t)tbl, kEmpty);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(tbl, 256)), dim3(256), 0, st,
+                       (u64*)owner, tbl, ~0ull);
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(tbl, 256)), dim3(256), 0, st,
                        (u64*)cnt, tbl, 0ull);
     hipLaunchKernelGGL(k_ginsert, dim3(grid_for(n, kGTile)), dim3(256), 0, st, g,
-                       n, L, fitems, owner, (u64*)cnt, tbl - 1, (u64*)S);
-    hipLaunchKernelGGL(k_gpartner, dim3(grid_for(n, 256)), dim3(256), 0, st, g,
-                       n, L, fitems, (const u64*)cnt);
+                       n, L, fitems, (u64*)owner, (u64*)cnt, tbl - 1, (u64*)S);
+    // the thread level is applied per lane by the finish kernel
+    if (L < 5)
+      hipLaunchKernelGGL(k_gpartner, dim3(grid_for(n, 256)), dim3(256), 0, st, g,
+                         n, L, fitems, (const u64*)cnt);
     HGRD_CHECK(hipGetLastError());
   }
   hipLaunchKernelGGL(k_gfinish, dim3(grid_for(n, 256)), dim3(256), 0, st, g, n,
-                     fitems, acc);
+                     fitems, (const u64*)owner, (const u64*)cnt, tbl - 1,
+                     ((used_levels >> 5) & 1) != 0, acc);
   hipLaunchKernelGGL(k_gcounts, dim3((nitems + 255) / 256), dim3(256), 0, st,
                      nitems, fitems, (const u64*)S, acc);
   HGRD_CHECK(hipGetLastError());

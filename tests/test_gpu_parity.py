@@ -139,8 +139,12 @@ def test_skew_paths(hg):
     run_both(hg, Workload([m], pairs), "skew")
     import paper_2604_02106_amd as H
     st = H.default_context().stats()
-    say("skew stats", {k: st[k] for k in ("retry_items", "split_items", "overflow_items")})
+    say("skew stats", {k: st[k] for k in ("retry_items", "split_items", "overflow_items",
+                                          "fallback_records", "fallback_groups")})
     assert st["split_items"] > 0 and st["overflow_items"] > 0
+    # every lane of a warp writes address 0 in access 3, so the lanes of one
+    # warp share one fallback record there
+    assert 0 < st["fallback_groups"] * 2 <= st["fallback_records"]
     assert st["presplit_items"] > 0  # tid % 8 over 96 blocks: routed at once
 
 
