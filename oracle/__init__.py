@@ -51,11 +51,15 @@ class OLoop(C.Structure):
                 ("cmp", C.c_int32), ("upd", C.c_int32)]
 
 
+class OSync(C.Structure):
+    _fields_ = [("addr", OExpr), ("array", C.c_int32), ("scope", C.c_int32)]
+
+
 class OAccess(C.Structure):
     _fields_ = [("array", C.c_int32), ("kind", C.c_int32), ("scope", C.c_int32),
                 ("n_loops", C.c_int32), ("loops", C.c_int32 * 8),
                 ("addr", OExpr), ("guard", OExpr), ("bint", OExpr),
-                ("wint", OExpr)]
+                ("wint", OExpr), ("acq", OSync), ("rel", OSync)]
 
 
 class OModel(C.Structure):
@@ -151,6 +155,10 @@ class _Packed:
                 oa.loops[i] = k
             oa.addr, oa.guard = put(a.addr), put(a.guard)
             oa.bint, oa.wint = put(a.bint), put(a.wint)
+            for k in ("acq", "rel"):
+                sy = getattr(a, k, None)
+                if sy is not None:
+                    setattr(oa, k, OSync(put(sy.addr), sy.array, _SCOPE[sy.scope]))
             accs.append(oa)
         self.acc = (OAccess * max(1, len(accs)))(*accs)
         grid = [put(x) for x in model.launch.grid]

@@ -24,7 +24,20 @@
  *     warp-barrier intervals also match;
  *   - host-fixed values (sections 4 and 6.3, classes 1-5) arrive as finite
  *     parameter tuples; each tuple is one launch, so conflicts never cross
- *     tuples.
+ *     tuples;
+ *   - acquire-release synchronisation (section 6.5, Figure 9, Table 2's
+ *     highlighted constraint; appendix A, Figure 10): an access may name
+ *     the acquire and the release around it (address expression, array,
+ *     scope).  At each point, for a required scope, syn() is the lock when
+ *     acquire and release both reach that scope and hit the same address,
+ *     else the release for a write (producer), else the acquire for a read
+ *     (consumer), else none.  The required scope is device for an
+ *     inter-block conflict and block for the other two.  A conflicting
+ *     point pair is no race when both points have a syn() at the required
+ *     scope and the two hit the same address of the same array (joint
+ *     reading: the inequality is one more conjunct of the same constraint
+ *     set).  A lock or flag in shared memory is one per block, so it never
+ *     orders threads of two blocks.
  * The paper hands these constraints to a SAT solver (section 6.4).  Here the
  * domains are finite, so the oracle decides them by enumeration and also
  * reports exact per-class counts of ordered conflicting point pairs and the
@@ -36,8 +49,11 @@
  *     (addr, block, bint, warp, wint, thread) and count pairs with equal key
  *     prefixes: the number of (p, q) with equal key K is the sum over key
  *     groups of n_i * n_j (an equi-join cardinality).  Class counts are
- *     differences of such sums.  The witness is found in two passes: the
- *     smallest p with a partner, then the smallest partner q of that p.
+ *     differences of such sums.  Synchronised pairs are counted the same way
+ *     over the points that have a syn() at the class's scope, with the
+ *     synchronisation (array, address) added to each key, and subtracted.
+ *     The witness is found in two passes: the smallest p with a partner,
+ *     then the smallest partner q of that p.
  *
  * Integer semantics are C's on int64 (truncating '/', '%' with the sign of
  * the dividend, arithmetic '>>', comparisons giving 0/1).  An operation that
@@ -80,10 +96,13 @@ typedef struct { int64_t op, arg; } OTok;
 typedef struct { int32_t first, count; } OExpr;
 typedef struct { int32_t space, addr_bits; } OArray;
 typedef struct { OExpr init, bound, step; int32_t cmp, upd; } OLoop;
+/* acquire or release: addr.count 0 = none */
+typedef struct { OExpr addr; int32_t array, scope; } OSync;
 typedef struct {
   int32_t array, kind, scope, n_loops;
   int32_t loops[8];
   OExpr addr, guard, bint, wint;
+  OSync acq, rel;
 } OAccess;
 typedef struct {
   const OTok* toks; int32_t n_toks;
@@ -257,6 +276,13 @@ static int check_access(const OModel* m, const OAccess* a) {
     for (int j = 0; j < i; ++j) if (a->loops[j] == a->loops[i]) return E_INVAL;
   }
   if (a->addr.count == 0) return E_INVAL;
+  const OSync* so[2] = {&a->acq, &a->rel};
+  for (int k = 0; k < 2; ++k) {
+    if (so[k]->addr.count == 0) continue;
+    if (so[k]->array < 0 || so[k]->array >= m->n_arrays) return E_INVAL;
+    if (so[k]->scope != SC_BLOCK && so[k]->scope != SC_DEVICE) return E_INVAL;
+    err |= check_expr(m, so[k]->addr, 3, a);
+  }
   err |= check_expr(m, a->addr, 3, a);
   err |= check_expr(m, a->guard, 3, a);
   err |= check_expr(m, a->bint, 2, a);
@@ -276,11 +302,15 @@ static int check_access(const OModel* m, const OAccess* a) {
 /* ------------------------------------------------------------------------ */
 /* Enumerating the points of one access for one parameter tuple.            */
 
+/* sa[k], sv[k]: array and address of the point's syn() at scope k (0
+ * block, 1 device); sa[k] = -1: none. */
 typedef struct {
   int64_t addr;
   uint32_t blin, tlin, ilin;
   uint16_t bint, wint;
   uint8_t side;
+  int32_t sa[2];
+  int64_t sv[2];
 } OPoint;
 
 typedef struct { OPoint* p; int64_t n, cap; } OPoints;
@@ -352,6 +382,30 @@ static int64_t loop_values(const OModel* m, const OLoop* l, const int64_t* param
   return n;
 }
 
+/* syn() of Figures 9 and 10 at one point for required scope `scope`:
+ * the acquire and release count only when their scope is at least as wide.
+ * acqv, relv: their addresses at this point. */
+static void syn_at(const OModel* m, const OAccess* a, int64_t acqv, int64_t relv,
+                   int scope, int32_t* arr, int64_t* val) {
+  int have_a = a->acq.addr.count && a->acq.scope >= scope;
+  int have_r = a->rel.addr.count && a->rel.scope >= scope;
+  *arr = -1;
+  *val = 0;
+  if (have_a && have_r && a->acq.array == a->rel.array && acqv == relv) {
+    *arr = a->acq.array;  /* lock: acquire and release on one address */
+    *val = acqv;
+  } else if (a->kind == K_WRITE && have_r) {
+    *arr = a->rel.array;  /* producer */
+    *val = relv;
+  } else if (a->kind == K_READ && have_a) {
+    *arr = a->acq.array;  /* consumer */
+    *val = acqv;
+  }
+  /* shared memory is one per block: such a lock or flag never orders two
+   * blocks, and device scope is only asked for inter-block conflicts */
+  if (scope == SC_DEVICE && *arr >= 0 && m->arrays[*arr].space == SP_SHARED) *arr = -1;
+}
+
 /* All points of access a under tuple s, in lexicographic (blin, tlin, ilin)
  * order.  Returns the box size (points before guards) and appends the points
  * whose guard holds. */
@@ -406,6 +460,14 @@ static int64_t enumerate(const OModel* m, const OAccess* a, int32_t s, int side,
           int64_t addr = eval(m, a->addr, &env, 0, &e);
           int64_t bi = eval(m, a->bint, &env, 0, &e);
           int64_t wi = eval(m, a->wint, &env, 0, &e);
+          int64_t sval[2] = {0, 0};
+          const OSync* so[2] = {&a->acq, &a->rel};
+          for (int k = 0; k < 2; ++k) {
+            if (so[k]->addr.count == 0) continue;
+            sval[k] = eval(m, so[k]->addr, &env, 0, &e);
+            if (m->arrays[so[k]->array].addr_bits == 32 &&
+                (sval[k] < INT32_MIN || sval[k] > INT32_MAX)) e |= E_RANGE;
+          }
           if (is32 && (addr < INT32_MIN || addr > INT32_MAX)) e |= E_RANGE;
           if (bi < 0 || bi >= INTERVAL_LIMIT || wi < 0 || wi >= INTERVAL_LIMIT) e |= E_UNSUP;
           *err |= e;
@@ -418,6 +480,7 @@ static int64_t enumerate(const OModel* m, const OAccess* a, int32_t s, int side,
           pt.bint = (uint16_t)bi;
           pt.wint = (uint16_t)wi;
           pt.side = (uint8_t)side;
+          for (int k = 0; k < 2; ++k) syn_at(m, a, sval[0], sval[1], k, &pt.sa[k], &pt.sv[k]);
           push_point(out, pt);
         }
       }
@@ -453,6 +516,10 @@ static int conflict_class(const OPoint* p, const OPoint* q, int64_t warp, int ma
   if (!(cls & mask)) return 0;
   if (cls == C_BLOCK && p->bint != q->bint) return 0;
   if (cls == C_WARP && (p->bint != q->bint || p->wint != q->wint)) return 0;
+  /* Table 2: a race also needs addr(syn(Ai)) != addr(syn(Aj)); the scope
+   * asked of syn() is device for inter-block, block otherwise (app. A) */
+  int k = cls == C_INTER ? SC_DEVICE : SC_BLOCK;
+  if (p->sa[k] >= 0 && p->sa[k] == q->sa[k] && p->sv[k] == q->sv[k]) return 0;
   return cls;
 }
 
@@ -533,6 +600,21 @@ static int full_cmp(const void* pa, const void* pb) {
   return key_cmp_level((const OPoint*)pa, (const OPoint*)pb, t_warp, 5);
 }
 
+/* order of point indices by (level key, syn() array and address at scope
+ * t_scope), for the synchronised group sums */
+static __thread const OPoint* t_pts;
+static __thread int t_level, t_scope;
+
+static int sync_cmp(const void* pa, const void* pb) {
+  const OPoint* a = &t_pts[*(const int64_t*)pa];
+  const OPoint* b = &t_pts[*(const int64_t*)pb];
+  int c = key_cmp_level(a, b, t_warp, t_level);
+  if (c) return c;
+  if (a->sa[t_scope] != b->sa[t_scope]) return a->sa[t_scope] < b->sa[t_scope] ? -1 : 1;
+  if (a->sv[t_scope] != b->sv[t_scope]) return a->sv[t_scope] < b->sv[t_scope] ? -1 : 1;
+  return 0;
+}
+
 /* lexicographic point order (blin, tlin, ilin) */
 static int point_less(const OPoint* a, const OPoint* b) {
   if (a->blin != b->blin) return a->blin < b->blin;
@@ -579,9 +661,40 @@ static void pair_b(const OModel* m, const OAccess* x, const OAccess* y, int self
         g0 = g1;
       }
     }
-    if (mask & C_INTER) r->by_class[0] += S[0] - S[1];
-    if (mask & C_BLOCK) r->by_class[1] += S[2] - S[3];
-    if (mask & C_WARP) r->by_class[2] += S[4] - S[5];
+    /* synchronised pairs: the same group sums over the points whose syn()
+     * reaches the class's scope, with the synchronisation array and address
+     * added to the key; they are subtracted from the counts and partners */
+    uint64_t T[6] = {0, 0, 0, 0, 0, 0};
+    int64_t* ix = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    for (int level = 0; level < 6; ++level) {
+      int cls = level < 2 ? C_INTER : level < 4 ? C_BLOCK : C_WARP;
+      if (!(cls & mask)) continue;
+      int k = cls == C_INTER ? SC_DEVICE : SC_BLOCK;
+      int64_t ns = 0;
+      for (int64_t i = 0; i < n; ++i) if (d.p[i].sa[k] >= 0) ix[ns++] = i;
+      t_pts = d.p;
+      t_level = level;
+      t_scope = k;
+      qsort(ix, (size_t)ns, sizeof(int64_t), sync_cmp);
+      int64_t g0 = 0;
+      while (g0 < ns) {
+        int64_t g1 = g0 + 1;
+        while (g1 < ns && sync_cmp(&ix[g0], &ix[g1]) == 0) ++g1;
+        uint64_t c0 = 0, c1 = 0;
+        for (int64_t x = g0; x < g1; ++x) { if (d.p[ix[x]].side == 0) ++c0; else ++c1; }
+        uint64_t nj = self ? c0 : c1;
+        T[level] += c0 * nj;
+        for (int64_t x = g0; x < g1; ++x) {
+          if (d.p[ix[x]].side != 0) continue;
+          if (level % 2 == 0) partners[ix[x]] -= nj; else partners[ix[x]] += nj;
+        }
+        g0 = g1;
+      }
+    }
+    free(ix);
+    if (mask & C_INTER) r->by_class[0] += (S[0] - S[1]) - (T[0] - T[1]);
+    if (mask & C_BLOCK) r->by_class[1] += (S[2] - S[3]) - (T[2] - T[3]);
+    if (mask & C_WARP) r->by_class[2] += (S[4] - S[5]) - (T[4] - T[5]);
     /* witness pass 1: smallest p (in this tuple) with a partner */
     if (!have_p) {
       for (int64_t k = 0; k < n; ++k) {
@@ -723,6 +836,7 @@ int oracle_conflict_class(int64_t addr_p, uint32_t b_p, uint32_t t_p, uint32_t b
                           int64_t warp, int32_t mask) {
   OPoint p, q;
   memset(&p, 0, sizeof p); memset(&q, 0, sizeof q);
+  p.sa[0] = p.sa[1] = q.sa[0] = q.sa[1] = -1;  /* no synchronisation */
   p.addr = addr_p; p.blin = b_p; p.tlin = t_p; p.bint = (uint16_t)bint_p; p.wint = (uint16_t)wint_p;
   q.addr = addr_q; q.blin = b_q; q.tlin = t_q; q.bint = (uint16_t)bint_q; q.wint = (uint16_t)wint_q;
   return conflict_class(&p, &q, warp, mask);

@@ -10,7 +10,7 @@ marshalling code.
 from .expr import (E, c, param, tid, bid, bdim, gdim, loop, div, mod, shl, shr,
                    band, bor, bxor, emin, emax, lt, le, eq, ne, ge, gt, land,
                    lor, lnot, neg, OPS)
-from .model import (Model, Workload, Access, Loop, Array, Launch, READ, WRITE,
+from .model import (Model, Workload, Access, Sync, Loop, Array, Launch, READ, WRITE,
                     ATOMIC, SCOPE_BLOCK, SCOPE_DEVICE, GLOBAL, SHARED, INTER,
                     INTRA_BLOCK, INTRA_WARP, ALL_CLASSES)
 from .hostdomain import HostDomain, HostVar

@@ -10,6 +10,9 @@ A kernel model describes one analysed GPU kernel as the race query sees it:
   branch condition under which the access executes), and two barrier-interval
   ids, ``bint`` (block barriers) and ``wint`` (warp barriers), that stand for
   the dominance checks of section 6.1;
+* optionally, the acquire and release that guard an access (section 6.5,
+  Figure 9; appendix A): the address expression of each, the array holding
+  the lock or flag, and its scope;
 * launch geometry (grid and block extents as expressions over parameters,
   section 6.3 class 2) and the warp size;
 * host-fixed parameter tuples: each tuple is one launch, and its values are
@@ -63,15 +66,35 @@ class Loop:
                 "step": self.step.to_json()}
 
 
+class Sync:
+    """An acquire (atomicCAS then fence) or release (fence then atomicExch)
+    around an access: the address it synchronises on, in array ``array``,
+    and its scope, the narrower of its atomic's and its fence's."""
+
+    def __init__(self, array, addr, scope=SCOPE_DEVICE):
+        assert scope in SCOPES
+        self.array, self.addr, self.scope = int(array), lift(addr), scope
+
+    def to_json(self):
+        return {"array": self.array, "addr": self.addr.to_json(),
+                "scope": self.scope}
+
+    @staticmethod
+    def from_json(j):
+        return None if j is None else Sync(j["array"], E.from_json(j["addr"]),
+                                           j["scope"])
+
+
 class Access:
     def __init__(self, array, kind, addr, guard=None, loops=(), bint=None,
-                 wint=None, scope=SCOPE_DEVICE, name=""):
+                 wint=None, scope=SCOPE_DEVICE, name="", acq=None, rel=None):
         assert kind in KINDS and scope in SCOPES
         self.array, self.kind, self.scope = int(array), kind, scope
         self.addr, self.guard = lift(addr), _opt(guard)
         self.loops = [int(k) for k in loops]
         self.bint, self.wint = _opt(bint), _opt(wint)
         self.name = name
+        self.acq, self.rel = acq, rel
 
     def to_json(self):
         j = {"array": self.array, "kind": self.kind, "scope": self.scope,
@@ -81,6 +104,10 @@ class Access:
             j[k] = None if v is None else v.to_json()
         if self.name:
             j["name"] = self.name
+        for k in ("acq", "rel"):
+            v = getattr(self, k)
+            if v is not None:
+                j[k] = v.to_json()
         return j
 
 
@@ -128,7 +155,9 @@ class Model:
             op = lambda k: None if a.get(k) is None else E.from_json(a[k])
             accs.append(Access(a["array"], a["kind"], E.from_json(a["addr"]),
                                op("guard"), a["loops"], op("bint"), op("wint"),
-                               a["scope"], a.get("name", "")))
+                               a["scope"], a.get("name", ""),
+                               Sync.from_json(a.get("acq")),
+                               Sync.from_json(a.get("rel"))))
         la = j["launch"]
         launch = Launch([E.from_json(x) for x in la["grid"]],
                         [E.from_json(x) for x in la["block"]], la["warp"])

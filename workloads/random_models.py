@@ -129,3 +129,67 @@ def rand_workload(seed, n_models=4, pairs_per_model=6):
             mask = 7 if rng.random() < 0.7 else int(rng.integers(0, 8))
             pairs.append((mi, a, b, mask))
     return Workload(models, pairs, name="rand%d" % seed)
+
+
+def _sync_addr(rng, loops_acc):
+    """A synchronisation address that often coincides between threads."""
+    r = int(rng.integers(0, 8))
+    if r == 0:
+        return c(int(rng.integers(0, 2)))
+    if r == 1:
+        return mod(tid(0), 2)
+    if r == 2:
+        return bid(0)
+    if r == 3:
+        return mod(tid(0) + bid(0), 2)
+    if r == 4 and loops_acc:
+        return loop(int(rng.choice(loops_acc)))
+    if r == 5:
+        return div(tid(0), 2)
+    return mod(rand_expr(rng, 1, loops_acc), 3)
+
+
+def rand_sync_model(rng, n_acc=4):
+    """A random small model whose accesses are guarded by random acquires
+    and releases (section 6.5): locks, producer/consumer flags, mismatched
+    pairs, block and device scopes, in a global and a shared lock array."""
+    from .model import Sync
+    m = rand_model(rng, n_acc)
+    m.arrays = m.arrays + [Array(GLOBAL, 64), Array(SHARED, 32)]
+    for a in m.accesses:
+        r = rng.random()
+        if r < 0.2:
+            continue
+        arr = int(rng.integers(2, 4))
+        sc = lambda: SCOPE_BLOCK if rng.random() < 0.3 else SCOPE_DEVICE
+        if r < 0.55:
+            # a lock: acquire and release on one address
+            e = _sync_addr(rng, a.loops)
+            a.acq, a.rel = Sync(arr, e, sc()), Sync(arr, e, sc())
+        else:
+            if rng.random() < 0.75:
+                a.acq = Sync(arr, _sync_addr(rng, a.loops), sc())
+            if rng.random() < 0.75:
+                arr2 = arr if rng.random() < 0.7 else 5 - arr
+                a.rel = Sync(arr2, _sync_addr(rng, a.loops), sc())
+    return m
+
+
+def rand_sync_workload(seed, n_models=4, pairs_per_model=6):
+    """Random tiny models with synchronisation, random pairs on one array."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    models, pairs = [], []
+    for mi in range(n_models):
+        m = rand_sync_model(rng)
+        models.append(m)
+        for _ in range(pairs_per_model):
+            a = int(rng.integers(0, len(m.accesses)))
+            if rng.random() < 0.25:
+                b = a
+            else:
+                same = [k for k, x in enumerate(m.accesses)
+                        if x.array == m.accesses[a].array]
+                b = int(rng.choice(same))
+            mask = 7 if rng.random() < 0.7 else int(rng.integers(0, 8))
+            pairs.append((mi, a, b, mask))
+    return Workload(models, pairs, name="randsync%d" % seed)
