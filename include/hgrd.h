@@ -62,7 +62,7 @@ enum {
  *   launch extents          : CONST, PARAM
  *   loop init/bound/step    : + BDIM, GDIM
  *   bint, wint              : + LOOP (loops enclosing the access)
- *   addr, guard             : + TID, BID
+ *   addr, guard, acq, rel   : + TID, BID
  * Limits: at most 256 instructions and a stack depth of 16. */
 enum {
   RD_OP_CONST = 1, RD_OP_PARAM = 2, RD_OP_TID = 3, RD_OP_BID = 4,
@@ -106,16 +106,42 @@ typedef struct {
   uint32_t cmp, upd;
 } rd_loop;
 
+/* An acquire (atomicCAS then fence) or a release (fence then atomicExch)
+ * around an access (section 6.5, Figure 9; appendix A).  `addr` is the
+ * address it operates on, an expression over the same leaves as the
+ * access's address (count 0: none), in array `array` (any space; a 32-bit
+ * array's addresses must fit int32 like data addresses).  `scope` is the
+ * narrower of its atomic's and its fence's scopes (RD_SCOPE_*). */
+typedef struct {
+  rd_expr addr;
+  uint32_t array, scope;
+} rd_sync;
+
 /* One static load, store or atomic (section 6.1, "Generating access
  * pairs").  `loops` lists the enclosing model loops, outermost first (at
  * most 4); the iteration index is row-major over them.  `bint` and `wint`
  * are barrier-interval ids in [0, 65536): two points of one block can race
  * only if their bint are equal (a block barrier between them otherwise,
- * section 6.1), and within one warp only if their wint are also equal. */
+ * section 6.1), and within one warp only if their wint are also equal.
+ *
+ * `acq` and `rel`: the acquire that dominates the access and the release
+ * that post-dominates it, if any (section 6.5; the control-flow search for
+ * them is the caller's).  At each point and for a required scope (device
+ * for an inter-block conflict, block for intra-block and intra-warp ones;
+ * appendix A, Figure 10) only operations at least that wide are seen, and
+ * syn() is the lock when both are seen and hit one address of one array,
+ * else the release of a write (producer), else the acquire of a read
+ * (consumer), else none (Figure 9).  A conflicting point pair is no race
+ * when both points have a syn() and the two hit the same address of the
+ * same array (Table 2's last constraint, taken jointly with the others).
+ * A lock or flag in a shared array is one per block, so it never orders
+ * threads of two blocks.  Pairs with an acquire or release on either
+ * access are joined by the HBM aggregation path whatever their size. */
 typedef struct {
   uint32_t array, kind, scope, n_loops;
   uint32_t loops[4];
   rd_expr addr, guard, bint, wint;
+  rd_sync acq, rel;
 } rd_access;
 
 typedef struct {
@@ -435,6 +461,9 @@ typedef struct {
                                 iteration, warp, intervals) share one record
                                 that carries its lane mask, so this is at most
                                 the points of the fallback items */
+  uint64_t sync_records;     /* point bound of the (pair, tuple) units with an
+                                acquire or release, joined by the fallback
+                                path with the synchronisation levels */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

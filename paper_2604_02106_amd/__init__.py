@@ -48,11 +48,16 @@ class rd_loop(C.Structure):
                 ("cmp", C.c_uint32), ("upd", C.c_uint32)]
 
 
+class rd_sync(C.Structure):
+    _fields_ = [("addr", rd_expr), ("array", C.c_uint32), ("scope", C.c_uint32)]
+
+
 class rd_access(C.Structure):
     _fields_ = [("array", C.c_uint32), ("kind", C.c_uint32),
                 ("scope", C.c_uint32), ("n_loops", C.c_uint32),
                 ("loops", C.c_uint32 * 4), ("addr", rd_expr),
-                ("guard", rd_expr), ("bint", rd_expr), ("wint", rd_expr)]
+                ("guard", rd_expr), ("bint", rd_expr), ("wint", rd_expr),
+                ("acq", rd_sync), ("rel", rd_sync)]
 
 
 class rd_kernel_model(C.Structure):
@@ -138,7 +143,8 @@ class rd_stats(C.Structure):
                 ("filter_tab_bytes", C.c_uint64),
                 ("units_apart", C.c_uint64),
                 ("block_symmetric", C.c_uint64),
-                ("fallback_groups", C.c_uint64)]
+                ("fallback_groups", C.c_uint64),
+                ("sync_records", C.c_uint64)]
 
 
 assert C.sizeof(rd_pair_result) == 88
@@ -302,6 +308,11 @@ class Packed:
                     x.loops[i] = lk
                 x.addr, x.guard = put(a.addr), put(a.guard)
                 x.bint, x.wint = put(a.bint), put(a.wint)
+                for name in ("acq", "rel"):
+                    sy = getattr(a, name, None)
+                    if sy is not None:
+                        setattr(x, name, rd_sync(put(sy.addr), sy.array,
+                                                 _SCOPE[sy.scope]))
             ld = self.launch[mi]
             for d in range(3):
                 ld.grid[d] = put(m.launch.grid[d])

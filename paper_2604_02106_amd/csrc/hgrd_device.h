@@ -271,6 +271,49 @@ __device__ __forceinline__ bool point_eval(const DevInst& I, const PointIds& id,
   return eval_point(I, code, params, R, pt, err);
 }
 
+// syn() of an access at one point (section 6.5, Figures 9 and 10): bit 0
+// of the result when the access has one at block scope, bit 1 at device
+// scope (only operations at least that wide are seen); `val` gets its
+// address.  Where both bits are set the address is the same: the operations
+// seen at device scope are among those seen at block scope, and a lock's
+// acquire and release hit one address.  The array never depends on the
+// point (a lock needs acquire and release in one array), so the pair's
+// flags say whether two syn() can match at all.
+__device__ __forceinline__ uint32_t point_syn(const DevInst& I, const PointIds& id,
+                                              const DInsn* __restrict__ code,
+                                              const int64_t* __restrict__ params,
+                                              const int64_t* __restrict__ loopvals,
+                                              int64_t& val, uint32_t& err) {
+  const uint32_t f = I.a.syn;
+  val = 0;
+  if (!(f & (kSynAcq | kSynRel))) return 0;
+  Regs R;
+  set_coords(I, id, loopvals, R);
+  const int64_t* pr = params + I.a.params_off;
+  uint32_t e = 0;
+  const int64_t va = (f & kSynAcq) ? run_prog(code, I.a.acq, R, pr, 0, e) : 0;
+  const int64_t vr = (f & kSynRel) ? run_prog(code, I.a.rel, R, pr, 0, e) : 0;
+  if ((f & kSynAcq32) && (va < INT32_MIN || va > INT32_MAX)) e |= ERR_RANGE;
+  if ((f & kSynRel32) && (vr < INT32_MIN || vr > INT32_MAX)) e |= ERR_RANGE;
+  err |= e;
+  uint32_t bits = 0;
+  for (int s = 0; s < 2; ++s) {
+    const bool A = (f & kSynAcq) && (s == 0 || (f & kSynAcqDev));
+    const bool Rl = (f & kSynRel) && (s == 0 || (f & kSynRelDev));
+    if (A && Rl && (f & kSynSameArr) && va == vr) {
+      bits |= 1u << s;  // lock
+      val = va;
+    } else if ((f & kSynWrite) && Rl) {
+      bits |= 1u << s;  // producer
+      val = vr;
+    } else if ((f & kSynRead) && A) {
+      bits |= 1u << s;  // consumer
+      val = va;
+    }
+  }
+  return bits;
+}
+
 // Interval ids of a point already known to be present.
 __device__ __forceinline__ void point_iv(const DevInst& I, const PointIds& id,
                                          const DInsn* __restrict__ code,

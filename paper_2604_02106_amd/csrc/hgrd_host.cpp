@@ -111,6 +111,8 @@ uint32_t check_expr(const rd_kernel_model& m, rd_expr e, int ctx,
   return 0;
 }
 
+uint32_t syn_flags(const rd_kernel_model& m, const rd_access& a);
+
 uint32_t check_access(const rd_kernel_model& m, const rd_access& a) {
   if (a.array >= m.n_arrays || !m.arrays) return ERR_INVAL;
   const rd_array& arr = m.arrays[a.array];
@@ -127,7 +129,13 @@ uint32_t check_access(const rd_kernel_model& m, const rd_access& a) {
       if (a.loops[j] == a.loops[i]) return ERR_INVAL;
   }
   if (a.addr.count == 0) return ERR_INVAL;
-  uint32_t err = check_expr(m, a.addr, CTX_POINT, &a) |
+  for (const rd_sync* y : {&a.acq, &a.rel}) {
+    if (y->addr.count == 0) continue;
+    if (y->array >= m.n_arrays || y->scope > RD_SCOPE_DEVICE) return ERR_INVAL;
+  }
+  uint32_t err = check_expr(m, a.acq.addr, CTX_POINT, &a) |
+                 check_expr(m, a.rel.addr, CTX_POINT, &a) |
+                 check_expr(m, a.addr, CTX_POINT, &a) |
                  check_expr(m, a.guard, CTX_POINT, &a) |
                  check_expr(m, a.bint, CTX_IV, &a) |
                  check_expr(m, a.wint, CTX_IV, &a);
@@ -972,7 +980,7 @@ struct Planner {
   std::vector<std::vector<DimInfo>> dims;                 // [model][set]
   std::map<std::pair<uint32_t, uint32_t>, std::vector<LoopInfo>> loops;  // (model, loop) -> per set
   std::map<std::pair<uint32_t, uint32_t>, std::vector<InstInfo>> insts;  // (model, acc) -> per set
-  std::map<std::pair<uint32_t, uint32_t>, Prog> progs[4];
+  std::map<std::pair<uint32_t, uint32_t>, Prog> progs[6];
   std::vector<DInsn> code;
   std::vector<int64_t> pool_params;
   std::vector<int64_t> pool_loops;
@@ -1295,7 +1303,8 @@ struct Planner {
     auto it = progs[which].find(key);
     if (it != progs[which].end()) return it->second;
     const rd_access& A = models[m].acc[a];
-    rd_expr e = which == 0 ? A.addr : which == 1 ? A.guard : which == 2 ? A.bint : A.wint;
+    const rd_expr ex[6] = {A.addr, A.guard, A.bint, A.wint, A.acq.addr, A.rel.addr};
+    const rd_expr e = ex[which];
     Prog p = compile(models[m], e, A, code);
     progs[which][key] = p;
     return p;
@@ -1341,6 +1350,9 @@ struct Planner {
     I.guard = prog(m, a, 1);
     I.bint = prog(m, a, 2);
     I.wint = prog(m, a, 3);
+    I.acq = prog(m, a, 4);
+    I.rel = prog(m, a, 5);
+    I.syn = syn_flags(M, A);
     for (int k = 0; k < 6; ++k) I.dims[k] = (int32_t)d.d[k];
     I.nblk = (uint32_t)nblk;
     I.nthr = (uint32_t)nthr;
@@ -1390,6 +1402,8 @@ struct Planner {
       fix(I.guard);
       fix(I.bint);
       fix(I.wint);
+      fix(I.acq);
+      fix(I.rel);
       I.params_off += par_off;
       for (uint32_t k = 0; k < I.n_loops && k < 4; ++k) I.loop_off[k] += loop_off;
       dev_insts.push_back(I);
@@ -1432,7 +1446,7 @@ struct Planner {
         if (ii.idx >= 0) ii.idx += inst_off;
       insts[kv.first] = v;
     }
-    for (int w = 0; w < 4; ++w)
+    for (int w = 0; w < 6; ++w)
       for (auto& kv : o.progs[w]) {
         Prog p = kv.second;
         fix(p);
@@ -1522,6 +1536,56 @@ bool same_addr_expr(const rd_kernel_model& M, uint32_t a, uint32_t b) {
   return true;
 }
 
+// Per-access facts for the device's syn() (section 6.5, Figures 9 and 10):
+// which of acquire and release exist, which reach device scope, whether
+// they share an array (so a lock is possible), the access kind, and which
+// addresses must fit int32.
+uint32_t syn_flags(const rd_kernel_model& m, const rd_access& a) {
+  uint32_t f = 0;
+  if (a.acq.addr.count) {
+    f |= kSynAcq;
+    if (a.acq.scope == RD_SCOPE_DEVICE) f |= kSynAcqDev;
+    if (m.arrays[a.acq.array].addr_bits == 32) f |= kSynAcq32;
+  }
+  if (a.rel.addr.count) {
+    f |= kSynRel;
+    if (a.rel.scope == RD_SCOPE_DEVICE) f |= kSynRelDev;
+    if (m.arrays[a.rel.array].addr_bits == 32) f |= kSynRel32;
+  }
+  if ((f & kSynAcq) && (f & kSynRel) && a.acq.array == a.rel.array) f |= kSynSameArr;
+  if (a.kind == RD_WRITE) f |= kSynWrite;
+  if (a.kind == RD_READ) f |= kSynRead;
+  return f;
+}
+
+// The array of an access's syn() at scope `dev` (0 block, 1 device), or -1
+// when it has none at any point: a lock needs one array for acquire and
+// release, so the array never depends on the point.
+int64_t syn_array(const rd_access& a, int dev) {
+  const bool A = a.acq.addr.count && (!dev || a.acq.scope == RD_SCOPE_DEVICE);
+  const bool R = a.rel.addr.count && (!dev || a.rel.scope == RD_SCOPE_DEVICE);
+  if (A && R && a.acq.array == a.rel.array) return a.acq.array;
+  if (a.kind == RD_WRITE && R) return a.rel.array;
+  if (a.kind == RD_READ && A) return a.acq.array;
+  return -1;
+}
+
+// Pair-level synchronisation flags: kQSync when either access has an
+// acquire or release (the pair goes to the HBM aggregation path); kQSyncBlk
+// / kQSyncDev when points of the two can share a syn() at block / device
+// scope (same array; device scope also needs a global array, since shared
+// memory is one per block).
+uint32_t pair_sync(const rd_kernel_model& m, const rd_access& x, const rd_access& y) {
+  uint32_t f = 0;
+  if (x.acq.addr.count || x.rel.addr.count || y.acq.addr.count || y.rel.addr.count)
+    f |= kQSync;
+  const int64_t b0 = syn_array(x, 0), b1 = syn_array(y, 0);
+  if (b0 >= 0 && b0 == b1) f |= kQSyncBlk;
+  const int64_t d0 = syn_array(x, 1), d1 = syn_array(y, 1);
+  if (d0 >= 0 && d0 == d1 && m.arrays[d0].space == RD_GLOBAL) f |= kQSyncDev;
+  return f;
+}
+
 uint32_t class_mask(const rd_kernel_model& m, const rd_access& x,
                     const rd_access& y, uint32_t caller) {
   uint32_t mask = caller & 7u;
@@ -1536,6 +1600,7 @@ uint32_t class_mask(const rd_kernel_model& m, const rd_access& x,
 
 struct QPlan {
   uint32_t host_err = 0;
+  uint32_t sync = 0;  // kQSync* flags
   uint8_t trivial = 0;
   uint8_t lower = 0;  // valid, non-trivial: its instances are lowered
   bool work = false;
@@ -1628,6 +1693,13 @@ struct rd_plan_impl {
   uint32_t log_level = 0;
   hipStream_t st = nullptr;
   std::vector<QPlan> Q;
+  // (pair, tuple) units of pairs with an acquire or release: joined by the
+  // HBM aggregation path with the synchronisation levels
+  struct SyncUnit {
+    uint32_t q, sigma, inst_i, inst_j, scan;
+    uint64_t R;
+  };
+  std::vector<SyncUnit> sync_units;
   std::vector<uint32_t> npts;  // per device instance
   std::vector<uint8_t> tab_on;  // per device instance: has term tables
   std::vector<uint32_t> nblk;   // per device instance: blocks
@@ -1796,6 +1868,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     q.qd.warp = launch[pr.model].warp_size;
     q.qd.shared = M.arrays[A.array].space == RD_SHARED;
     if (q.qd.mask == 0) { q.trivial = 1; continue; }
+    q.sync = pair_sync(M, A, B);
     q.lower = 1;
   }
 
@@ -1950,6 +2023,22 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     for (uint32_t s = 0; s < q.inst.size(); ++s) {
       int32_t ia = q.inst[s].first, ib = q.inst[s].second;
       if (ia < 0 && ib < 0) continue;
+      if (q.sync) {
+        // acquire/release on the pair: the HBM aggregation path, whose
+        // records carry each point's synchronisation address and which
+        // scans every point's expressions for errors (one side only, with
+        // nothing joined, when the other has no points)
+        rd_plan_impl::SyncUnit u;
+        u.q = k;
+        u.sigma = s;
+        u.scan = ia < 0 || ib < 0;
+        u.inst_i = (uint32_t)(ia >= 0 ? ia : ib);
+        u.inst_j = (uint32_t)(u.scan ? u.inst_i : (uint32_t)ib);
+        u.R = u.scan ? npts_of((int32_t)u.inst_i)
+                     : npts_of(ia) + (q.qd.self ? 0 : npts_of(ib));
+        plan->sync_units.push_back(u);
+        continue;
+      }
       if (ia < 0 || ib < 0) {
         // one side has no points because its loops failed: the pair already
         // carries that error, but the other side's points are still scanned
@@ -2068,7 +2157,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     plan->K = o.tile_budget ? o.tile_budget : 256;
     for (uint32_t k = 0; k < n_pairs; ++k) {
       QPlan& q = Q[k];
-      if (!q.work || q.host_err || q.trivial || q.qd.shared || q.inst.empty()) continue;
+      if (!q.work || q.host_err || q.trivial || q.qd.shared || q.inst.empty() || q.sync)
+        continue;
       bool ok = true;
       for (auto& pr : q.inst) {
         if (pr.first < 0 || pr.second < 0) { ok = false; break; }
@@ -3020,6 +3110,22 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     fall.push_back(f);
   }
   S.overflow_items = fall.size();
+  for (const auto& u : plan->sync_units) {
+    const QPlan& q = plan->Q[u.q];
+    FItem f;
+    memset(&f, 0, sizeof f);
+    f.q = u.q;
+    f.sigma = u.sigma;
+    f.inst_i = u.inst_i;
+    f.inst_j = u.inst_j;
+    f.self = u.scan ? 1 : q.qd.self;
+    f.mask = u.scan ? 0 : q.qd.mask;
+    f.warp = q.qd.warp;
+    f.cap = (uint32_t)u.R;
+    f.sync = q.sync;
+    S.sync_records += u.R;
+    fall.push_back(f);
+  }
   size_t fpos = 0;
   while (fpos < fall.size()) {
     size_t fend = fpos;
@@ -3030,6 +3136,12 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       n += fall[fend].cap;
       uint32_t m = fall[fend].mask;
       used |= (m & 1 ? 0x03u : 0) | (m & 2 ? 0x0Cu : 0) | (m & 4 ? 0x30u : 0);
+      // synchronised pairs: levels 6-11 are levels 0-5 with the
+      // synchronisation address added, over points with a syn() at the
+      // class's scope
+      const uint32_t y = fall[fend].sync;
+      if (y & kQSyncDev) used |= (m & 1 ? 0x03u : 0) << 6;
+      if (y & kQSyncBlk) used |= ((m & 2 ? 0x0Cu : 0) | (m & 4 ? 0x30u : 0)) << 6;
       ++fend;
     }
     const uint32_t nf = (uint32_t)(fend - fpos);
@@ -3055,9 +3167,15 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     g.part = ctx->ensure("g_part", n * 8, &merr);
     g.mult = (uint32_t*)ctx->ensure("g_mult", n * 4, &merr);
     g.lanes = ctx->ensure("g_lanes", n * 8, &merr);
+    const bool synced = (used >> 6) != 0;
+    g.skey = synced ? ctx->ensure("g_skey", n * 8, &merr) : nullptr;
     void* owner = ctx->ensure("g_owner", tbl * 8, &merr);
     void* cnt = ctx->ensure("g_cnt", tbl * 8, &merr);
-    void* gS = ctx->ensure("g_S", (size_t)nf * 64, &merr);
+    // the synchronisation levels build their own table, so that both
+    // thread-level tables are there for the witness scan
+    void* owner2 = synced ? ctx->ensure("g_owner2", tbl * 8, &merr) : nullptr;
+    void* cnt2 = synced ? ctx->ensure("g_cnt2", tbl * 8, &merr) : nullptr;
+    void* gS = ctx->ensure("g_S", (size_t)nf * 128, &merr);
     uint32_t* gcount = (uint32_t*)ctx->ensure("g_count", (size_t)nf * 4, &merr);
     FItem* d_f = (FItem*)ctx->ensure("fb_items", nf * sizeof(FItem), &merr);
     Chunk* d_ch = (Chunk*)ctx->ensure("fb_chunks", chunks.size() * sizeof(Chunk), &merr);
@@ -3066,8 +3184,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     TRY_HIP(hipMemcpyAsync(d_ch, chunks.data(), chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
     TRY_HIP(hipEventRecord(ev[7], st));
     if (launch_fallback(st, d_ch, (uint32_t)chunks.size(), d_f, nf, used, d_insts,
-                        d_code, d_params, d_loops, g, n, gcount, owner, cnt, tbl,
-                        gS, d_acc))
+                        d_code, d_params, d_loops, g, n, gcount, owner, cnt,
+                        owner2, cnt2, tbl, gS, d_acc))
       return RD_EDEVICE;
     TRY_HIP(hipEventRecord(ev[8], st));
     TRY_HIP(hipEventSynchronize(ev[8]));
@@ -3086,7 +3204,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     TRY_HIP(hipMemcpyAsync(acc.data(), d_acc, n_pairs * sizeof(QAcc), hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
   struct W2 {
-    uint32_t q, inst_i, inst_j, p0, p1, pad0, pad1, pad2;
+    uint32_t q, inst_i, inst_j, p0, p1, sync, pad1, pad2;
   };
   std::vector<W2> w2;
   for (uint32_t k = 0; k < n_pairs; ++k) {
@@ -3099,7 +3217,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     if (ia < 0 || ib < 0) continue;
     uint32_t np = plan->npts[ib];
     for (uint32_t p0 = 0; p0 < np; p0 += kChunkPts)
-      w2.push_back({k, (uint32_t)ia, (uint32_t)ib, p0, std::min(np, p0 + kChunkPts), 0, 0, 0});
+      w2.push_back({k, (uint32_t)ia, (uint32_t)ib, p0, std::min(np, p0 + kChunkPts), q.sync,
+                    0, 0});
   }
   double w2_ms = 0;
   if (!w2.empty()) {

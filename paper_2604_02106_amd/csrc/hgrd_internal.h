@@ -49,9 +49,19 @@ constexpr uint32_t ERR_DIVZERO = 1, ERR_RANGE = 2, ERR_UNSUP = 4, ERR_INVAL = 8;
 // property); reported as RD_EDEVICE for the pair
 constexpr uint32_t ERR_INTERNAL = 16;
 
+// AccInst::syn flags: the access's acquire and release (section 6.5).
+constexpr uint32_t kSynAcq = 1, kSynRel = 2, kSynAcqDev = 4, kSynRelDev = 8,
+                   kSynSameArr = 16, kSynWrite = 32, kSynRead = 64,
+                   kSynAcq32 = 128, kSynRel32 = 256;
+// Pair synchronisation flags (FItem::sync, witness pass 2): an acquire or
+// release on either access; points can share a syn() at block / device
+// scope.
+constexpr uint32_t kQSync = 1, kQSyncBlk = 2, kQSyncDev = 4;
+
 // One access under one parameter tuple.
 struct alignas(16) AccInst {
   Prog addr, guard, bint, wint;  // 32 B
+  Prog acq, rel;                 // acquire / release addresses (absent: none)
   int32_t dims[6];               // gx gy gz bx by bz
   uint32_t nblk, nthr, niota;    // |grid|, |block|, |iterations|
   uint32_t n_loops;
@@ -63,9 +73,9 @@ struct alignas(16) AccInst {
   uint32_t tpb;                  // nthr * niota (points per block)
   uint32_t iorder;               // point order inside a block: 0 thread
                                  // fastest, 1 iteration fastest
-  uint32_t pad_;
+  uint32_t syn;                  // kSyn* flags
 };
-static_assert(sizeof(AccInst) == 128, "AccInst layout");
+static_assert(sizeof(AccInst) == 144, "AccInst layout");
 
 // Term tables of one instance.  When an expression is proven free of
 // errors over the whole launch box it is split into a uniform part and one
@@ -201,6 +211,7 @@ struct FItem {
   uint32_t q, sigma, inst_i, inst_j;
   uint32_t self, mask, warp, cap;
   unsigned long long off;
+  uint32_t sync, pad;  // kQSync* flags of the pair
 };
 
 // A slice of one side's points, generated and scattered by one workgroup.

@@ -973,6 +973,8 @@ struct GRec {
   long long* part;
   uint32_t* mult;  // points in the record
   u64* lanes;      // bit k: thread tlin + k
+  u64* skey;       // synchronisation address (pairs with acquire/release);
+                   // tli bit 10: a syn() at block scope, bit 11: at device
 };
 
 __global__ void __launch_bounds__(256)
@@ -980,12 +982,13 @@ k_gen_linear(const Chunk* __restrict__ chunks, const FItem* __restrict__ fitems,
              const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
              const int64_t* __restrict__ params,
              const int64_t* __restrict__ loopvals, GRec rec,
-             uint32_t* __restrict__ count) {
+             uint32_t* __restrict__ count, QAcc* __restrict__ acc) {
   const Chunk ch = chunks[blockIdx.x];
   const FItem f = fitems[ch.item];
   DevInst I;
   load_inst(I, insts, ch.side ? f.inst_j : f.inst_i);
   const bool match = I.a.iorder == 0;  // lanes are consecutive threads of a row
+  const bool syn = (I.a.syn & (kSynAcq | kSynRel)) != 0;
   const uint32_t lane = threadIdx.x & 63;
   uint32_t err = 0;
   for (uint32_t base = ch.p0; base < ch.p1; base += blockDim.x) {
@@ -993,9 +996,12 @@ k_gen_linear(const Chunk* __restrict__ chunks, const FItem* __restrict__ fitems,
     bool valid = false;
     Point pt{0, 0, 0};
     PointIds id{0, 0, 0};
+    int64_t sv = 0;
+    uint32_t sb = 0;
     if (pidx < ch.p1) {
       id = decode(I, pidx);
       valid = point_eval(I, id, code, params, loopvals, pt, err);
+      if (valid && syn) sb = point_syn(I, id, code, params, loopvals, sv, err);
     }
     const uint32_t wp = valid ? id.tlin / f.warp : 0;
     // match: a lane leads the group of pending lanes equal to it in
@@ -1012,9 +1018,12 @@ k_gen_linear(const Chunk* __restrict__ chunks, const FItem* __restrict__ fitems,
       const uint32_t il = (uint32_t)__shfl((int)id.ilin, l, 64);
       const uint32_t ww = (uint32_t)__shfl((int)wp, l, 64);
       const uint32_t iv = (uint32_t)__shfl((int)((pt.bint << 16) | pt.wint), l, 64);
+      const int64_t v = (int64_t)__shfl((long long)sv, l, 64);
+      const uint32_t vb = (uint32_t)__shfl((int)sb, l, 64);
       const bool mine =
           pending && (match ? ((u64)pt.addr == a && id.blin == b && id.ilin == il &&
-                               wp == ww && ((pt.bint << 16) | pt.wint) == iv)
+                               wp == ww && ((pt.bint << 16) | pt.wint) == iv &&
+                               sv == v && sb == vb)
                             : lane == (uint32_t)l);
       const u64 M = __ballot(mine);
       if (lane == (uint32_t)l) {
@@ -1035,7 +1044,8 @@ k_gen_linear(const Chunk* __restrict__ chunks, const FItem* __restrict__ fitems,
         u64 r = f.off + k;
         rec.addr[r] = (u64)pt.addr;
         rec.blin[r] = id.blin;
-        rec.tli[r] = (id.ilin << 16) | (ch.side << 15) | id.tlin;
+        rec.tli[r] = (id.ilin << 16) | (ch.side << 15) | (sb << 10) | id.tlin;
+        if (rec.skey) rec.skey[r] = (u64)sv;
         rec.bw[r] = (pt.bint << 16) | pt.wint;
         rec.w[r] = wp;
         rec.item[r] = ch.item;
@@ -1045,14 +1055,26 @@ k_gen_linear(const Chunk* __restrict__ chunks, const FItem* __restrict__ fitems,
       }
     }
   }
+  // evaluation errors (items of synchronised pairs come here unscanned)
+  for (int o = 32; o; o >>= 1) err |= (uint32_t)__shfl_xor((int)err, o, 64);
+  if (lane == 0 && err) atomicOr(&acc[f.q].err, err);
 }
 
+// Levels 0-5 group records by (address, block, bint, warp, wint, thread)
+// prefixes.  Levels 6-11 are the same groups with the synchronisation
+// address added, over the records whose points have a syn() at the class's
+// scope (device for levels 6 and 7, the inter-block class; block for 8-11):
+// their pairs are the synchronised ones, subtracted from the conflicts.
 // Key equality of (record x, lane kx) and (record y, lane ky) at level L
 // (lanes matter at the thread level only).
 __device__ __forceinline__ bool g_level_eq(const GRec& g, int L, u64 x, uint32_t kx, u64 y,
                                            uint32_t ky) {
   if (g.item[x] != g.item[y]) return false;
   if (g.addr[x] != g.addr[y]) return false;
+  if (L >= 6) {
+    if (g.skey[x] != g.skey[y]) return false;
+    L -= 6;
+  }
   if (L >= 1 && g.blin[x] != g.blin[y]) return false;
   if (L >= 2 && (g.bw[x] >> 16) != (g.bw[y] >> 16)) return false;
   if (L >= 3 && g.w[x] != g.w[y]) return false;
@@ -1061,12 +1083,26 @@ __device__ __forceinline__ bool g_level_eq(const GRec& g, int L, u64 x, uint32_t
   return true;
 }
 __device__ __forceinline__ uint32_t g_hash(const GRec& g, int L, u64 r, uint32_t k) {
-  return level_hash(L, g.addr[r] ^ ((u64)g.item[r] * 0x2545F4914F6CDD1Dull),
-                    g.blin[r], g.bw[r], g.w[r], (g.tli[r] & 0x3FF) + k);
+  u64 a = g.addr[r] ^ ((u64)g.item[r] * 0x2545F4914F6CDD1Dull);
+  if (L >= 6) {
+    a ^= g.skey[r] * 0xD6E8FEB86659FD93ull;
+    L -= 6;
+  }
+  return level_hash(L, a, g.blin[r], g.bw[r], g.w[r], (g.tli[r] & 0x3FF) + k);
 }
 
-__device__ __forceinline__ bool uses_level(uint32_t mask, int L) {
-  return (mask >> (L >> 1)) & 1;
+// Level L counts for item f: its class is in the mask and, for a
+// synchronisation level, the pair's points can share a syn() at that scope.
+__device__ __forceinline__ bool level_on(const FItem& f, int L) {
+  const int b = L >= 6 ? L - 6 : L;
+  if (!((f.mask >> (b >> 1)) & 1)) return false;
+  return L < 6 || (f.sync & (b < 2 ? kQSyncDev : kQSyncBlk)) != 0;
+}
+
+// Record r takes part in level L (synchronisation levels: its points have
+// a syn() at the level's scope).
+__device__ __forceinline__ bool rec_on(const GRec& g, u64 r, int L) {
+  return L < 6 || ((g.tli[r] >> (L < 8 ? 11 : 10)) & 1) != 0;
 }
 
 constexpr int kGTile = 1024;  // records per workgroup step
@@ -1109,13 +1145,13 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
       const uint32_t sl = it % kSlots;
       uint32_t prev = atomicCAS(&sitem[sl], kEmpty, it);
       if (prev == kEmpty || prev == it) atomicAdd(&ssum[sl], contrib);
-      else atomicAdd(&S[(u64)it * 8 + L], contrib);
+      else atomicAdd(&S[(u64)it * 16 + L], contrib);
     }
     return h;
   };
   __syncthreads();
   for (u64 t0 = (u64)blockIdx.x * kGTile; t0 < n; t0 += (u64)gridDim.x * kGTile) {
-    if (L == 5) {
+    if (L == 5 || L == 11) {
       // thread level: every lane of a record is its own key; thread groups
       // are small, so lanes go straight to the global table
 #pragma unroll
@@ -1125,7 +1161,7 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
         const uint32_t it = g.item[r];
         if (it == kEmpty) continue;
         const FItem f = fitems[it];
-        if (!uses_level(f.mask, L)) continue;
+        if (!level_on(f, L) || !rec_on(g, r, L)) continue;
         const bool sb = ((g.tli[r] >> 15) & 1) != 0;
         for (u64 m = g.lanes[r]; m; m &= m - 1) {
           const uint32_t k = (uint32_t)__ffsll((long long)m) - 1;
@@ -1149,7 +1185,7 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
       uint32_t it = g.item[r];
       if (it == kEmpty) continue;
       const FItem f = fitems[it];
-      if (!uses_level(f.mask, L)) continue;
+      if (!level_on(f, L) || !rec_on(g, r, L)) continue;
       uint32_t h = g_hash(g, L, r, 0) & (kGLocal - 1);
       const uint32_t lr = (uint32_t)(r - t0);
       for (;;) {
@@ -1182,22 +1218,24 @@ k_ginsert(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
   }
   __syncthreads();
   if (tid < kSlots && sitem[tid] != kEmpty && ssum[tid])
-    atomicAdd(&S[(u64)sitem[tid] * 8 + L], ssum[tid]);
+    atomicAdd(&S[(u64)sitem[tid] * 16 + L], ssum[tid]);
 }
 
-// Adds +-(partners at level L < 5) to every record of side a (self: all):
-// the group at such a level holds all of a record's lanes, so the figure
-// is the same for each of them.
+// Adds +-(partners at level L, not a thread level) to every record of side
+// a (self: all): the group at such a level holds all of a record's lanes,
+// so the figure is the same for each of them.  Synchronisation levels
+// count with the opposite sign.
 __global__ void __launch_bounds__(256)
 k_gpartner(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
            const u64* __restrict__ cnt) {
-  const long long sign = (L & 1) ? -1 : 1;
+  long long sign = (L & 1) ? -1 : 1;
+  if (L >= 6) sign = -sign;  // (L - 6) & 1 == L & 1
   for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < n;
        r += (u64)gridDim.x * blockDim.x) {
     uint32_t it = g.item[r];
     if (it == kEmpty) continue;
     const FItem f = fitems[it];
-    if (!uses_level(f.mask, L)) continue;
+    if (!level_on(f, L) || !rec_on(g, r, L)) continue;
     uint32_t side = (g.tli[r] >> 15) & 1;
     if (!f.self && side) continue;
     u64 c = cnt[g.slot[r]];
@@ -1206,13 +1244,32 @@ k_gpartner(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
   }
 }
 
+// Other-side points in the thread-level group of (record r, lane k) at
+// level L (5 or 11), from that level's table (built last for its half).
+__device__ __forceinline__ long long g_thread_count(const GRec& g, int L, u64 r, uint32_t k,
+                                                    bool self, const u64* __restrict__ owner,
+                                                    const u64* __restrict__ cnt, u64 tbl_mask) {
+  u64 h = g_hash(g, L, r, k) & tbl_mask;
+  for (;;) {
+    const u64 o = owner[h];
+    if (o == ~0ull) return 0;  // (never: every lane was inserted)
+    if (g_level_eq(g, L, o >> 6, (uint32_t)(o & 63), r, k)) {
+      const u64 c = cnt[h];
+      return self ? (long long)c : (long long)(c >> 32);
+    }
+    h = (h + 1) & tbl_mask;
+  }
+}
+
 // Witness candidates of the fallback records: the first lane of a record
-// whose partner count is positive.  With the thread level in an item's
-// classes, each lane subtracts its own thread group's other-side count,
-// looked up in the level-5 table (the last one built, still in place).
+// whose partner count is positive.  With a thread level in an item's
+// classes, each lane subtracts its own thread group's other-side count
+// (level 5, table A) and adds back its synchronised share (level 11,
+// table B); both tables were the last built in their halves.
 __global__ void __launch_bounds__(256)
 k_gfinish(GRec g, u64 n, const FItem* __restrict__ fitems, const u64* __restrict__ owner,
-          const u64* __restrict__ cnt, u64 tbl_mask, bool level5,
+          const u64* __restrict__ cnt, const u64* __restrict__ owner2,
+          const u64* __restrict__ cnt2, u64 tbl_mask, uint32_t used,
           QAcc* __restrict__ acc) {
   for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < n;
        r += (u64)gridDim.x * blockDim.x) {
@@ -1221,23 +1278,13 @@ k_gfinish(GRec g, u64 n, const FItem* __restrict__ fitems, const u64* __restrict
     const FItem f = fitems[it];
     uint32_t tl = g.tli[r];
     if (!f.self && (tl & kSide)) continue;
-    const bool l5 = level5 && uses_level(f.mask, 5);
+    const bool l5 = ((used >> 5) & 1) && level_on(f, 5);
+    const bool l11 = ((used >> 11) & 1) && level_on(f, 11) && rec_on(g, r, 11);
     for (u64 m = g.lanes[r]; m; m &= m - 1) {
       const uint32_t k = (uint32_t)__ffsll((long long)m) - 1;
       long long part = g.part[r];
-      if (l5) {
-        u64 h = g_hash(g, 5, r, k) & tbl_mask;
-        for (;;) {
-          const u64 o = owner[h];
-          if (o == ~0ull) break;  // (never: every lane was inserted)
-          if (g_level_eq(g, 5, o >> 6, (uint32_t)(o & 63), r, k)) {
-            const u64 c = cnt[h];
-            part -= f.self ? (long long)c : (long long)(c >> 32);
-            break;
-          }
-          h = (h + 1) & tbl_mask;
-        }
-      }
+      if (l5) part -= g_thread_count(g, 5, r, k, f.self, owner, cnt, tbl_mask);
+      if (l11) part += g_thread_count(g, 11, r, k, f.self, owner2, cnt2, tbl_mask);
       if (part > 0) {
         u64 key = pkey(f.sigma, g.blin[r], (tl & 0x3FF) + k, tl >> 16);
         if (key < acc[f.q].pmin) atomicMin(&acc[f.q].pmin, key);
@@ -1253,10 +1300,11 @@ __global__ void k_gcounts(uint32_t nitems, const FItem* __restrict__ fitems,
   uint32_t it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= nitems) return;
   const FItem f = fitems[it];
-  const u64* s = S + (u64)it * 8;
-  if (f.mask & 1) atomicAdd(&acc[f.q].cnt[0], s[0] - s[1]);
-  if (f.mask & 2) atomicAdd(&acc[f.q].cnt[1], s[2] - s[3]);
-  if (f.mask & 4) atomicAdd(&acc[f.q].cnt[2], s[4] - s[5]);
+  const u64* s = S + (u64)it * 16;
+  // conflicts minus synchronised pairs (levels 6-11 are zero without them)
+  if (f.mask & 1) atomicAdd(&acc[f.q].cnt[0], (s[0] - s[1]) - (s[6] - s[7]));
+  if (f.mask & 2) atomicAdd(&acc[f.q].cnt[1], (s[2] - s[3]) - (s[8] - s[9]));
+  if (f.mask & 4) atomicAdd(&acc[f.q].cnt[2], (s[4] - s[5]) - (s[10] - s[11]));
 }
 
 __global__ void k_fill_u64(u64* __restrict__ p, u64 n, u64 v) {
@@ -1270,7 +1318,7 @@ __global__ void k_fill_u64(u64* __restrict__ p, u64 n, u64 v) {
 // that conflicts with it.
 
 struct W2Item {
-  uint32_t q, inst_i, inst_j, p0, p1, pad0, pad1, pad2;
+  uint32_t q, inst_i, inst_j, p0, p1, sync, pad1, pad2;  // sync: kQSync* flags
 };
 
 __global__ void __launch_bounds__(256)
@@ -1288,6 +1336,10 @@ k_witness2(const W2Item* __restrict__ items, const DevInst* __restrict__ insts,
   // p*: every lane evaluates the same point
   Point P;
   uint32_t e = 0;
+  // synchronisation: p*'s syn() (bits: block, device scope) and address
+  const bool sy = (it.sync & (kQSyncBlk | kQSyncDev)) != 0;
+  int64_t pv = 0;
+  uint32_t pbits = 0;
   {
     DevInst I;
     load_inst(I, insts, it.inst_i);
@@ -1296,6 +1348,7 @@ k_witness2(const W2Item* __restrict__ items, const DevInst* __restrict__ insts,
     id.tlin = pt_;
     id.ilin = pi;
     point_eval(I, id, code, params, loopvals, P, e);
+    if (sy) pbits = point_syn(I, id, code, params, loopvals, pv, e);
   }
   const uint32_t pw = pt_ / q.warp;
   if (it.p0 == 0 && threadIdx.x == 0) acc[it.q].waddr = P.addr;
@@ -1318,6 +1371,15 @@ k_witness2(const W2Item* __restrict__ items, const DevInst* __restrict__ insts,
     if (!(cls & q.mask)) continue;
     if (cls != 1 && Q.bint != P.bint) continue;
     if (cls == 4 && Q.wint != P.wint) continue;
+    if (sy) {
+      // no race when both syn() at the class's scope hit one address
+      const uint32_t need = cls == 1 ? 2u : 1u;
+      if (it.sync & (cls == 1 ? kQSyncDev : kQSyncBlk)) {
+        int64_t qv;
+        const uint32_t qbits = point_syn(J, id, code, params, loopvals, qv, err);
+        if ((pbits & need) && (qbits & need) && pv == qv) continue;
+      }
+    }
     u64 k = pkey(ps, id.blin, id.tlin, id.ilin);
     best = k < best ? k : best;
   }
@@ -1699,39 +1761,42 @@ int launch_fallback(hipStream_t st, const Chunk* chunks, uint32_t nchunks,
                     const FItem* fitems, uint32_t nitems, uint32_t used_levels,
                     const void* insts, const DInsn* code, const int64_t* params,
                     const int64_t* loopvals, GRecPtrs gp, u64 n,
-                    uint32_t* count, void* owner, void* cnt, u64 tbl,
-                    void* S, QAcc* acc) {
+                    uint32_t* count, void* owner, void* cnt, void* owner2, void* cnt2,
+                    u64 tbl, void* S, QAcc* acc) {
   GRec g{(u64*)gp.addr, gp.blin, gp.tli, gp.bw, gp.w, gp.item, gp.slot,
-         (long long*)gp.part, gp.mult, (u64*)gp.lanes};
+         (long long*)gp.part, gp.mult, (u64*)gp.lanes, (u64*)gp.skey};
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, st,
                      gp.item, (uint32_t)n, kEmpty);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, count, nitems, 0u);
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((u64)nitems * 8, 256)), dim3(256),
-                     0, st, (u64*)S, (u64)nitems * 8, 0ull);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((u64)nitems * 16, 256)), dim3(256),
+                     0, st, (u64*)S, (u64)nitems * 16, 0ull);
   for (uint32_t off = 0; off < nchunks; off += 1u << 20) {
     uint32_t m = nchunks - off < (1u << 20) ? nchunks - off : (1u << 20);
     hipLaunchKernelGGL(k_gen_linear, dim3(m), dim3(256), 0, st, chunks + off,
                        fitems, (const DevInst*)insts, code, params, loopvals, g,
-                       count);
+                       count, acc);
   }
   HGRD_CHECK(hipGetLastError());
-  for (int L = 0; L < 6; ++L) {
+  for (int L = 0; L < 12; ++L) {
     if (!((used_levels >> L) & 1)) continue;
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(tbl, 256)), dim3(256), 0, st,
-                       (u64*)owner, tbl, ~0ull);
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(tbl, 256)), dim3(256), 0, st,
-                       (u64*)cnt, tbl, 0ull);
+    // levels 0-5 use table A, the synchronisation levels table B
+    u64* ow = (u64*)(L < 6 ? owner : owner2);
+    u64* ct = (u64*)(L < 6 ? cnt : cnt2);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(tbl, 256)), dim3(256), 0, st, ow, tbl,
+                       ~0ull);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(tbl, 256)), dim3(256), 0, st, ct, tbl,
+                       0ull);
     hipLaunchKernelGGL(k_ginsert, dim3(grid_for(n, kGTile)), dim3(256), 0, st, g,
-                       n, L, fitems, (u64*)owner, (u64*)cnt, tbl - 1, (u64*)S);
-    // the thread level is applied per lane by the finish kernel
-    if (L < 5)
+                       n, L, fitems, ow, ct, tbl - 1, (u64*)S);
+    // the thread levels are applied per lane by the finish kernel
+    if (L != 5 && L != 11)
       hipLaunchKernelGGL(k_gpartner, dim3(grid_for(n, 256)), dim3(256), 0, st, g,
-                         n, L, fitems, (const u64*)cnt);
+                         n, L, fitems, (const u64*)ct);
     HGRD_CHECK(hipGetLastError());
   }
   hipLaunchKernelGGL(k_gfinish, dim3(grid_for(n, 256)), dim3(256), 0, st, g, n,
-                     fitems, (const u64*)owner, (const u64*)cnt, tbl - 1,
-                     ((used_levels >> 5) & 1) != 0, acc);
+                     fitems, (const u64*)owner, (const u64*)cnt, (const u64*)owner2,
+                     (const u64*)cnt2, tbl - 1, used_levels, acc);
   hipLaunchKernelGGL(k_gcounts, dim3((nitems + 255) / 256), dim3(256), 0, st,
                      nitems, fitems, (const u64*)S, acc);
   HGRD_CHECK(hipGetLastError());

@@ -19,6 +19,7 @@ struct GRecPtrs {
   void* part;
   uint32_t* mult;  // points per record
   void* lanes;     // u64 per record: bit k = thread tlin + k of the record
+  void* skey;      // i64 per record: synchronisation address (or null)
 };
 
 size_t devinst_size();
@@ -72,7 +73,8 @@ int launch_fallback(hipStream_t st, const Chunk* chunks, uint32_t nchunks,
                     const FItem* fitems, uint32_t nitems, uint32_t used_levels,
                     const void* insts, const DInsn* code, const int64_t* params,
                     const int64_t* loopvals, GRecPtrs gp, unsigned long long n,
-                    uint32_t* count, void* owner, void* cnt,
+                    uint32_t* count, void* owner, void* cnt, void* owner2,
+                    void* cnt2,
                     unsigned long long tbl, void* S, QAcc* acc);
 int launch_witness2(hipStream_t st, const void* items, uint32_t n,
                     const void* insts, const DInsn* code, const int64_t* params,

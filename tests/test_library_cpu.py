@@ -37,7 +37,8 @@ def test_struct_sizes():
     import paper_2604_02106_amd as hg
     assert C.sizeof(hg.rd_pair_result) == 88
     assert C.sizeof(hg.rd_insn) == 16
-    assert C.sizeof(hg.rd_access) == 64
+    assert C.sizeof(hg.rd_access) == 96
+    assert C.sizeof(hg.rd_sync) == 16
     assert C.sizeof(hg.rd_options) == 48
     assert C.sizeof(hg.rd_mlp) == 4 * 6337
 
