@@ -429,6 +429,65 @@ def run_mixed(args):
     print(json.dumps(line), flush=True)
 
 
+def run_synced(args):
+    """Synchronisation-aware queries: the synced workload (mixed queries of
+    2^8..2^22 points per access with lock and producer/consumer patterns
+    around the accesses) in fixed batches, against the same batches with the
+    acquires and releases removed (the plain path)."""
+    import copy
+    import torch
+    import paper_2604_02106_amd as hg
+    from workloads import configs
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    step_q = 1000
+    wl = configs.synced(seed=6006, n_queries=int(4000 * args.scale))
+    plain = copy.deepcopy(wl)
+    for m in plain.models:
+        for a in m.accesses:
+            a.acq = a.rel = None
+    n = len(wl.pairs)
+    nb = (n + step_q - 1) // step_q
+    ctx = hg.Context(0)
+    out = {}
+    for name, w in (("synced", wl), ("plain", plain)):
+        batches = [w.compact(range(i * step_q, min(n, (i + 1) * step_q))) for i in range(nb)]
+        plans = [hg.Plan(ctx, b) for b in batches]
+        for i in range(args.warmup):
+            plans[i % nb].execute(raw=True)
+        torch.cuda.synchronize()
+        stats, res = [], []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            res.append(plans[i % nb].execute())
+            stats.append(ctx.stats())
+            log("%s step %d done" % (name, i))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        q = sum(len(batches[i % nb].pairs) for i in range(args.steps))
+        out[name] = {"queries_per_s": q / dt, "ms_per_step": dt * 1000 / args.steps,
+                     "evals_per_s_G": sum(s["evals"] for s in stats) / dt / 1e9,
+                     "fallback_ms_per_step": sum(s["fallback_ms"] for s in stats) / len(stats),
+                     "sync_records_per_step": sum(s["sync_records"] for s in stats) / len(stats),
+                     "racy": sum(r["verdict"] for rr in res for r in rr)}
+        if name == "synced":
+            sres, sb = res[0], batches[0]
+        for p in plans:
+            p.close()
+    line = {"metric": "synchronisation-aware race queries/sec", "value":
+            out["synced"]["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "dtype": "int64",
+            "data": "synthetic",
+            "config": {"workload": "synced: %d mixed queries of 2^8..2^22 points per "
+                                   "access with lock / producer-consumer patterns, "
+                                   "seed 6006; batches of %d" % (n, step_q)},
+            "synced": out["synced"], "plain_same_queries": out["plain"]}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(sb, sres)
+        line["cpu_baseline"]["sample"] += " (batch 0 of the synced workload)"
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -444,7 +503,7 @@ def main():
                          "timed steps)")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--config", default="mixed",
-                    choices=("batched", "stress", "mixed", "learned"),
+                    choices=("batched", "stress", "mixed", "learned", "synced"),
                     help="workload: mixed batched queries (the headline), "
                          "batched uneven queries, race-free stress (128 "
                          "pairs, 2^30 points per access), or the learned "
@@ -466,6 +525,8 @@ def main():
         args.warmup = 1 if args.config == "mixed" else 2
     if args.config == "learned":
         return run_learned(args)
+    if args.config == "synced":
+        return run_synced(args)
     if args.config == "mixed" and not args.calibrate_copy:
         return run_mixed(args)
     import torch

@@ -464,6 +464,12 @@ typedef struct {
   uint64_t sync_records;     /* point bound of the (pair, tuple) units with an
                                 acquire or release, joined by the fallback
                                 path with the synchronisation levels */
+  uint64_t sync_decided;     /* such units decided conflict-free before any
+                                join (the unit filter's tests at rd_prepare:
+                                addresses apart, or one thread-injective
+                                address expression) when every expression of
+                                both accesses, acquire and release addresses
+                                included, is proven error-free */
 } rd_stats;
 
 int rd_get_stats(const rd_context* ctx, rd_stats* out);

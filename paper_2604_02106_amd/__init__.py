@@ -144,7 +144,8 @@ class rd_stats(C.Structure):
                 ("units_apart", C.c_uint64),
                 ("block_symmetric", C.c_uint64),
                 ("fallback_groups", C.c_uint64),
-                ("sync_records", C.c_uint64)]
+                ("sync_records", C.c_uint64),
+                ("sync_decided", C.c_uint64)]
 
 
 assert C.sizeof(rd_pair_result) == 88

@@ -1226,6 +1226,22 @@ struct Planner {
     }
     const bool t_moves = I.nthr > 1, i_moves = I.niota > 1;
     dev_insts[inst].iorder = i_moves && (!t_moves || stride[2] < stride[1]) ? 1 : 0;
+    // acquire and release addresses that interval bounds prove error-free
+    // over the box (and inside int32 for 32-bit lock arrays)
+    bool ss = true;
+    for (const rd_sync* y : {&A.acq, &A.rel}) {
+      if (!y->addr.count) continue;
+      if (!tb.build(y->addr)) {
+        ss = false;
+        break;
+      }
+      const TNode& r = tb.nodes.back();
+      if (M.arrays[y->array].addr_bits == 32 && (r.lo < INT32_MIN || r.hi > INT32_MAX)) {
+        ss = false;
+        break;
+      }
+    }
+    T.syn_safe = ss ? 1 : 0;
   }
 
   DimInfo& dim(uint32_t m, uint32_t s) {
@@ -1708,6 +1724,7 @@ struct rd_plan_impl {
   uint64_t evals = 0;
   uint32_t n_sitems = 0;
   uint64_t n_symmetric = 0;   // shared units joined on block 0 only
+  uint64_t sync_decided = 0;  // synchronised units decided conflict-free
   uint32_t persist_grid = 0;  // workgroups of the persistent small join
   uint32_t chunk_pts = 16384; // points per partition workgroup
   uint32_t run_buckets = 8;   // buckets per join workgroup
@@ -1993,6 +2010,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   std::vector<SItem> sitems;
   // block symmetry of shared-array units (HGRD_NO_SYMMETRY turns it off)
   const bool block_sym = getenv("HGRD_NO_SYMMETRY") == nullptr;
+  // unit filter decisions for synchronised pairs (HGRD_NO_UNIT_FILTER)
+  const bool unit_filter = getenv("HGRD_NO_UNIT_FILTER") == nullptr;
   std::vector<HPlan> hplans;
   auto npts_of = [&](int32_t idx) -> uint64_t {
     return idx < 0 ? 0 : P.dev_insts[idx].npts;
@@ -2023,6 +2042,16 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     for (uint32_t s = 0; s < q.inst.size(); ++s) {
       int32_t ia = q.inst[s].first, ib = q.inst[s].second;
       if (ia < 0 && ib < 0) continue;
+      if (q.sync && unit_filter && ia >= 0 && ib >= 0 && P.tabs[ia].on && P.tabs[ib].on &&
+          P.tabs[ia].syn_safe && P.tabs[ib].syn_safe &&
+          ((ia != ib && P.apart(ia, ib)) || ((q.qd.flags & 4) && P.tinj[ia] && P.tinj[ib]))) {
+        // no address is shared, or each address is reached by one thread
+        // only: no conflict, so nothing to synchronise either, and no
+        // expression of either access can fail (term tables, acquire and
+        // release addresses proven error-free); the unit filter's decision
+        ++plan->sync_decided;
+        continue;
+      }
       if (q.sync) {
         // acquire/release on the pair: the HBM aggregation path, whose
         // records carry each point's synchronisation address and which
@@ -2542,6 +2571,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   S.prefiltered = plan->prefiltered;
   S.small_items = plan->n_sitems;
   S.block_symmetric = plan->n_symmetric;
+  S.sync_decided = plan->sync_decided;
   int merr = 0;
   auto D = [&](const char* name) { return plan->dev[name].p; };
   const DInsn* d_code = (const DInsn*)D("code");

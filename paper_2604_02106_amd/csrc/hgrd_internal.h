@@ -93,6 +93,7 @@ struct TabHost {
   uint32_t iv_const;
   uint32_t never;     // a uniform guard conjunct is false
   uint32_t on;        // tables in use for this instance
+  uint32_t syn_safe;  // acquire/release addresses proven error-free
 };
 
 // One table to fill: entries [0, n) of group `group` (0 blocks, 1 threads,

@@ -154,3 +154,25 @@ def test_sync_statuses(hg):
     m = Model(0, ARRAYS, accs, Launch((2, 1, 1), (8, 1, 1), 4), [[]])
     got = run_both(hg, Workload([m], [(0, k, k, 7) for k in range(4)]), "sync statuses")
     assert [r["status"] for r in got] == [-4, -3, -1, 0]
+
+
+def test_sync_units_decided_without_a_join(hg):
+    """Synchronised units whose accesses share no address (ranges apart) or
+    use one thread-injective address are decided before any join when every
+    expression is proven error-free; a lock address that may divide by zero
+    keeps its unit on the join path (its error must be found)."""
+    B = 64
+    gid = tid() + bid() * B
+    accs = [
+        Access(0, WRITE, gid, **lock(c(0))),                        # 0
+        Access(0, READ, gid + 100000, **lock(c(0))),                # 1: apart from 0
+        Access(0, WRITE, gid, **lock(tid() // (tid() - 3))),        # 2: may fail
+        Access(0, WRITE, gid * 2, **lock(mod(tid(), 2))),           # 3: injective
+    ]
+    m = Model(0, ARRAYS, accs, Launch((16, 1, 1), (B, 1, 1), 32), [[]])
+    wl = Workload([m], [(0, 0, 1, 7), (0, 3, 3, 7), (0, 2, 2, 7), (0, 0, 0, 7)])
+    got = run_both(hg, wl, "sync decided")
+    assert [r["status"] for r in got] == [0, 0, -4, 0]
+    st = hg.default_context().stats()
+    say("sync decided", st["sync_decided"], "sync records", st["sync_records"])
+    assert st["sync_decided"] >= 3

@@ -480,3 +480,55 @@ def mixed(seed=5005, n_queries=100000, log2_min=8, log2_max=28, racy_frac=0.10,
     return Workload(models, pairs, name="mixed",
                     meta={"seed": seed, "log2": (log2_min, log2_max),
                           "evals": evals})
+
+
+# ---------------------------------------------------------------------------
+# synchronised workload: the mixed queries with acquire/release around them
+
+def synced(seed=6006, n_queries=4000, log2_min=8, log2_max=22):
+    """The mixed workload's queries (domains log-uniform in
+    [2^log2_min, 2^log2_max] points per access) with each access guarded by
+    one of the acquire/release patterns of section 6.5 (Figure 9) and
+    appendix A, drawn per access:
+
+      * a global lock L[0] at device scope (orders every pair);
+      * a lock per block L[blockIdx.x] (orders pairs inside a block);
+      * a lock by thread parity L[threadIdx.x % 2];
+      * a block-scoped lock L[0] (too narrow for inter-block pairs);
+      * a lock word in shared memory (one per block);
+      * producer/consumer: a write releases flag F[blockIdx.x], a read
+        acquires F[blockIdx.x] (or, one time in four, F[blockIdx.x + 1]);
+      * nothing (a fifth of the accesses).
+
+    Locks and flags live in two extra arrays of each model (global 64-bit,
+    shared 32-bit).  meta["evals"] is the mixed workload's.
+    """
+    from .model import Sync
+    from .expr import mod
+    wl = mixed(seed=seed, n_queries=n_queries, log2_min=log2_min, log2_max=log2_max)
+    rng = _rng(seed + 1)
+    for m in wl.models:
+        gl, sh = len(m.arrays), len(m.arrays) + 1
+        m.arrays = m.arrays + [Array(GLOBAL, 64), Array(SHARED, 32)]
+        for a in m.accesses:
+            k = int(rng.integers(0, 8))
+            dev, blk = "device", "block"
+            lock = lambda arr, e, sc=dev: (Sync(arr, e, sc), Sync(arr, e, sc))
+            if k == 0:
+                a.acq, a.rel = lock(gl, c(0))
+            elif k == 1:
+                a.acq, a.rel = lock(gl, bid(0))
+            elif k == 2:
+                a.acq, a.rel = lock(gl, mod(tid(0), 2))
+            elif k == 3:
+                a.acq, a.rel = lock(gl, c(0), blk)
+            elif k == 4:
+                a.acq, a.rel = lock(sh, c(0), blk)
+            elif k in (5, 6):
+                off = 1 if rng.random() < 0.25 else 0
+                if a.kind == WRITE:
+                    a.rel = Sync(gl, bid(0), dev)
+                else:
+                    a.acq = Sync(gl, bid(0) + off, dev)
+    wl.name = "synced"
+    return wl
