@@ -489,6 +489,16 @@ __device__ __forceinline__ bool level_eq(const JoinLds<CAP, TBL>& S, int L,
 // and the caller has put each side-a record's level-0 partner count in
 // S.part.  Then S.red[0] gets -S_1 (inter = S_0 - S_1 modulo 2^64) and no
 // record is filtered out.
+//
+// gmult = G > 1: the records are block 0 of a global array's G blocks that
+// hold the same points up to the block (no block term in either access):
+// an address group of block 0 stands for G such groups, so S_0 is G times
+// block 0's (S.red[0] = G S_0 - S_1; the caller multiplies every count by G
+// again, giving G^2 S_0 - G S_1), and a record's address-level partners
+// include the other blocks' copies.  Partner counts only decide "any
+// partner": the address level adds 2 nj instead of G nj (the inter share
+// (G - 1) nj and nj have the same sign), and no record is filtered out
+// (a record alone in block 0 still pairs with its copies).
 __device__ __forceinline__ uint32_t key_slot(uint32_t k, uint32_t b, uint32_t tbl) {
   uint32_t x = k * 0x9E3779B1u ^ b * 0x85EBCA77u;
   x ^= x >> 16;
@@ -499,7 +509,7 @@ __device__ __forceinline__ uint32_t key_slot(uint32_t k, uint32_t b, uint32_t tb
 
 template <uint32_t NT, int CAP, int TBL>
 __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
-                         bool l0ext = false) {
+                         bool l0ext = false, uint32_t gmult = 1) {
   constexpr int RPT = (CAP + NT - 1) / NT;
   const uint32_t tid = threadIdx.x;
   const uint32_t n = S.n;
@@ -510,7 +520,8 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
   if (mask & 2) used |= 0x0C;
   if (mask & 4) used |= 0x30;
   if (used == 0 || n == 0) return;
-  const int f = l0ext ? 99 : __ffs(used) - 1;  // filter level (none: 99)
+  // filter level (none: 99)
+  const int f = l0ext || (gmult > 1 && (used & 1)) ? 99 : __ffs(used) - 1;
   // a level whose groups equal the previous level's (constant, equal
   // interval ids) is not recomputed: its sums and counts are the previous
   // level's
@@ -633,10 +644,10 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
       }
       if (!self && sb) continue;
       const int32_t nj = (int32_t)(self ? (c & 0xFFFF) : (c >> 16));
-      if (cls & mask) S.part[r] += sign * nj;
+      if (cls & mask) S.part[r] += sign * nj * (L == 0 && gmult > 1 ? 2 : 1);
       if (twin && ((cls << 1) & mask)) S.part[r] -= sign * nj;  // level L + 1
     }
-    Sl[L] = s;
+    Sl[L] = L == 0 ? s * gmult : s;
     P = L;
     if (L == f) {
       any = block_vote(any_local, &S.vote[2], 1u);

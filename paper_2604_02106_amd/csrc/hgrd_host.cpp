@@ -2112,6 +2112,27 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         it.b0 = 0;
         it.b1 = R0.nblk;
         sitems.push_back(it);
+      } else if (!q.qd.shared && per_block <= cap && block_sym && R0.nblk > 1 &&
+                 P.tabs[ia].on && P.tabs[ib].on && P.tabs[ia].off[0] == kNoTab &&
+                 P.tabs[ib].off[0] == kNoTab) {
+        // block symmetry of a global array: neither access's address nor
+        // guard has a block term, so every block holds the same points at
+        // the same addresses.  Block 0 is joined; its address groups stand
+        // for G identical groups (S_0 = G^2 S_0(block 0), every other level
+        // G times block 0's), and its witness, in the smallest block, is
+        // the smallest of all.
+        SItem it;
+        memset(&it, 0, sizeof it);
+        it.q = k;
+        it.sigma = s;
+        it.inst_i = (uint32_t)ia;
+        it.inst_j = (uint32_t)ib;
+        it.b0 = 0;
+        it.b1 = 1;
+        it.mult = R0.nblk;
+        it.gsym = 1;
+        sitems.push_back(it);
+        ++plan->n_symmetric;
       } else if (q.qd.shared && per_block <= cap && block_sym &&
                  P.tabs[ia].on && P.tabs[ib].on && P.tabs[ia].off[0] == kNoTab &&
                  P.tabs[ib].off[0] == kNoTab) {

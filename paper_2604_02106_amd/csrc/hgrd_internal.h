@@ -157,7 +157,9 @@ struct SItem {
   uint32_t q, sigma, inst_i, inst_j;
   uint32_t b0, b1;
   uint32_t mult;  // 0 or 1: as joined; k > 1: block 0 of k identical blocks
-  uint32_t pad1;  //   (its counts are taken k times)
+                  //   (its counts are taken k times)
+  uint32_t gsym;  // 1: a global array's k identical blocks; the address-only
+                  //   level also pairs block 0 with the other k - 1 blocks
 };
 
 // Work item partitioned through HBM.

@@ -87,7 +87,7 @@ __device__ __forceinline__ void small_item(JoinLds<CAP, TBL>& S, const SItem& it
     if (threadIdx.x == 0) atomicOr(&acc[it.q].err, S.err);
     return;
   }
-  lds_join<256>(S, q, it.sigma);
+  lds_join<256>(S, q, it.sigma, false, it.gsym && it.mult > 1 ? it.mult : 1u);
   commit_join(S, &acc[it.q], it.mult > 1 ? (u64)it.mult : 1ull);
 }
 

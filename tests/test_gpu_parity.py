@@ -323,6 +323,38 @@ def test_block_symmetry_is_exact(hg, monkeypatch):
     assert hg.default_context().stats()["block_symmetric"] == 0
 
 
+def test_global_block_symmetry_is_exact(hg, monkeypatch):
+    """Global-array units whose address and guard do not depend on the
+    block are joined on block 0: its address groups stand for G identical
+    groups (inter-block pairs G^2 S_0 - G S_1, the other classes G times
+    block 0's).  Covers an access whose points are alone in block 0 (every
+    point still races with its copies in the other blocks), masks without
+    the inter-block class, a one-block tuple, and a unit with a block term.
+    Every field equals the oracle's, with and without the shortcut."""
+    t = tid()
+    m = Model(2, [Array(GLOBAL, 32)],
+              [Access(0, WRITE, t // 32 + loop(0) * 8, lt(t, param(0)), [0]),
+               Access(0, READ, t % param(1) + loop(0), None, [0]),
+               Access(0, WRITE, t * 2 + loop(0) * 1000, None, [0]),
+               Access(0, WRITE, t % 4 + bid() % 2, None, [0])],
+              Launch((param(1), 1, 1), (64, 2, 1), 32), [[100, 24], [128, 7], [50, 1]],
+              loops=[Loop(0, "lt", 3)])
+    wl = Workload([m], [(0, 0, 1, 7), (0, 0, 0, 7), (0, 1, 2, 7), (0, 2, 2, 7),
+                        (0, 3, 3, 7), (0, 3, 1, 7), (0, 0, 1, 6), (0, 2, 2, 1),
+                        (0, 1, 2, 4)])
+    want, _ = oracle.check_pairs(wl, "B", threads=8)
+    say("global symmetry on")
+    compare(hg.check_pairs(wl), want, "global symmetry on")
+    st = hg.default_context().stats()
+    say("block symmetric units", st["block_symmetric"])
+    assert st["block_symmetric"] >= 6
+    assert want[3]["by_class"][0] > 0  # lone points in block 0 race with their copies
+    monkeypatch.setenv("HGRD_NO_SYMMETRY", "1")
+    say("global symmetry off")
+    compare(hg.check_pairs(wl), want, "global symmetry off")
+    assert hg.default_context().stats()["block_symmetric"] == 0
+
+
 def test_bucket_filter_drops_own_thread_buckets(hg):
     """Accesses that meet only in their own thread (one injective map,
     written as two different expressions so that the unit filter does not
