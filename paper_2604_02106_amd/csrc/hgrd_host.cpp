@@ -1717,6 +1717,7 @@ struct rd_plan_impl {
   };
   std::vector<SyncUnit> sync_units;
   std::vector<uint32_t> npts;  // per device instance
+  std::vector<uint32_t> tpb;   // per device instance: points per block
   std::vector<uint8_t> tab_on;  // per device instance: has term tables
   std::vector<uint32_t> nblk;   // per device instance: blocks
   std::vector<std::pair<int64_t, int64_t>> arange;  // address range (tables)
@@ -2029,6 +2030,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       if (!P.tabs[x].on) return 0;
       const double span = (double)P.arange[x].second - (double)P.arange[x].first + 1.0;
       if (span < 1) return 0;
+      // shared arrays and block-symmetric units: points of one block
       const double pts = shared ? P.dev_insts[x].tpb : P.dev_insts[x].npts;
       dens = std::max(dens, pts / span);
     }
@@ -2132,6 +2134,29 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         it.mult = R0.nblk;
         it.gsym = 1;
         sitems.push_back(it);
+        ++plan->n_symmetric;
+      } else if (!q.qd.shared && block_sym && R0.nblk > 1 && P.tabs[ia].on &&
+                 P.tabs[ib].on && P.tabs[ia].off[0] == kNoTab &&
+                 P.tabs[ib].off[0] == kNoTab) {
+        // the same symmetry for a block too large for one LDS tile: block
+        // 0's points alone go through the HBM partition (the first tpb
+        // points of each side, the block being slowest in the point order),
+        // and the joins scale as above.  Overflow goes to the fallback (a
+        // split by (address, block) has nothing to split in one block).
+        HPlan hp;
+        memset(&hp, 0, sizeof hp);
+        hp.h.q = k;
+        hp.h.sigma = s;
+        hp.h.inst_i = (uint32_t)ia;
+        hp.h.inst_j = (uint32_t)ib;
+        hp.h.shared = 0;
+        hp.h.is32 = R0.is32;
+        hp.h.gmult = R0.nblk;
+        hp.h.shift = item_shift(ia, ib, q.qd.self, true);
+        fastdiv_consts(P.dev_insts[ia].tpb, &hp.h.tpb_m[0], &hp.h.tpb_s[0]);
+        fastdiv_consts(P.dev_insts[ib].tpb, &hp.h.tpb_m[1], &hp.h.tpb_s[1]);
+        hp.R = per_block;
+        hplans.push_back(hp);
         ++plan->n_symmetric;
       } else if (q.qd.shared && per_block <= cap && block_sym &&
                  P.tabs[ia].on && P.tabs[ib].on && P.tabs[ia].off[0] == kNoTab &&
@@ -2320,7 +2345,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       HPlan hp = hplans[i];
       bool ps = false;
       const uint32_t a = hp.h.inst_i, b = hp.h.inst_j;
-      if (hp.h.shared == 0 && tab_on[a] && tab_on[b]) {
+      if (hp.h.shared == 0 && hp.h.gmult <= 1 && tab_on[a] && tab_on[b]) {
         const double lo = (double)std::min(P.arange[a].first, P.arange[b].first);
         const double hi = (double)std::max(P.arange[a].second, P.arange[b].second);
         if (hi >= lo && (double)hp.R >= (hi - lo + 1.0) * cap) {
@@ -2355,7 +2380,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
           hp.h.shared == 2 ? 0
                            : std::max<uint64_t>(1, (hp.R * 100 + cap * 55 - 1) / (cap * 55));
       if (hp.h.shared != 2 && !plan->no_map) {
-        set_bucket_map(hp.h, tab_on, P.arange, P.dev_insts[hp.h.inst_i].nblk,
+        set_bucket_map(hp.h, tab_on, P.arange,
+                       hp.h.gmult > 1 ? 1u : P.dev_insts[hp.h.inst_i].nblk,
                        Q[hp.h.q].qd.self, hp.h.shared == 1, hp.R, cap, 0.6);
         if (hp.h.mode) nbuckets = hp.h.nbuckets;
       }
@@ -2386,7 +2412,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       const QPlan& q = Q[h.q];
       for (int side = 0; side < (q.qd.self || h.shared == 2 ? 1 : 2); ++side) {
         uint32_t inst = side ? h.inst_j : h.inst_i;
-        uint32_t np = P.dev_insts[inst].npts;
+        // block-symmetric units: block 0's points only
+        uint32_t np = h.gmult > 1 ? P.dev_insts[inst].tpb : P.dev_insts[inst].npts;
         const uint32_t nc = (np + plan->chunk_pts - 1) / plan->chunk_pts;
         if (!nc) continue;
         (P.tabs[inst].on ? chunk_specs : interp).push_back(
@@ -2438,9 +2465,11 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   plan->n_insts = (uint32_t)P.dev_insts.size();
   plan->npts.resize(P.dev_insts.size());
   plan->nblk.resize(P.dev_insts.size());
+  plan->tpb.resize(P.dev_insts.size());
   for (size_t i = 0; i < P.dev_insts.size(); ++i) {
     plan->npts[i] = P.dev_insts[i].npts;
     plan->nblk[i] = P.dev_insts[i].nblk;
+    plan->tpb[i] = P.dev_insts[i].tpb;
   }
   plan->tab_on = tab_on;
   plan->arange = P.arange;
@@ -2922,7 +2951,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
         const QPlan& q = plan->Q[h.q];
         for (int side = 0; side < (q.qd.self ? 1 : 2); ++side) {
           const uint32_t inst = side ? h.inst_j : h.inst_i;
-          uint32_t np = plan->npts[inst];
+          uint32_t np = h.gmult > 1 ? plan->tpb[inst] : plan->npts[inst];
           std::vector<Chunk>& dst = plan->tab_on[inst] ? chunks : interp;
           for (uint32_t p0 = 0; p0 < np; p0 += plan->chunk_pts)
             dst.push_back({li, (uint32_t)side, p0, std::min(np, p0 + plan->chunk_pts)});
@@ -3013,7 +3042,9 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   // second step: split global items by (address, block); level 0 in tables,
   // in batches whose address-count tables stay within kL0Slots
   std::vector<RItem> split_all, direct;
-  for (auto& r : still) (r.h.shared == 0 ? split_all : direct).push_back(r);
+  // block-symmetric units hold one block: nothing for the (address, block)
+  // split to split, so they go to the fallback
+  for (auto& r : still) (r.h.shared == 0 && r.h.gmult <= 1 ? split_all : direct).push_back(r);
   S.split_items = split_all.size();
   S.presplit_items = 0;
   for (uint8_t f : plan->presplit) S.presplit_items += f;
@@ -3054,7 +3085,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
       r.h.nbuckets = (uint32_t)std::max<uint64_t>(1, (r.R * 100 + scap * 55 - 1) / (scap * 55));
       r.h.shift = 0;
       if (!plan->no_map)
-        set_bucket_map(r.h, plan->tab_on, plan->arange, plan->nblk[r.h.inst_i],
+        set_bucket_map(r.h, plan->tab_on, plan->arange,
+                       r.h.gmult > 1 ? 1u : plan->nblk[r.h.inst_i],
                        q.qd.self, true, r.R, scap, 0.5);
       L0Item li;
       memset(&li, 0, sizeof li);
@@ -3154,6 +3186,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     f.mask = q.qd.mask;
     f.warp = q.qd.warp;
     f.cap = (uint32_t)direct[i].R;
+    f.gmult = h.gmult;
     S.fallback_records += direct[i].R;
     if (plan->log_level >= 2)
       fprintf(stderr, "hgrd: fallback item pair=%u tuple=%u shared=%u points=%llu buckets=%u\n",
@@ -3200,7 +3233,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     for (uint32_t i = 0; i < nf; ++i) {
       const FItem& f = fall[fpos + i];
       for (int side = 0; side < (f.self ? 1 : 2); ++side) {
-        uint32_t np = plan->npts[side ? f.inst_j : f.inst_i];
+        const uint32_t inst = side ? f.inst_j : f.inst_i;
+        uint32_t np = f.gmult > 1 ? plan->tpb[inst] : plan->npts[inst];
         for (uint32_t p0 = 0; p0 < np; p0 += kL0ChunkPts)
           chunks.push_back({i, (uint32_t)side, p0, std::min(np, p0 + kL0ChunkPts)});
       }

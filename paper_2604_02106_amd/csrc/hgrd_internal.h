@@ -184,8 +184,13 @@ struct HItem {
   long long lo;
   unsigned long long fm;
   uint32_t tpb_s[2];           // and shifts
+  // gmult = G > 1: block 0 of a global array's G identical blocks (no block
+  // term in either access); only block 0's points are generated, the
+  // address-only level stands for G groups and every count is taken G times
+  uint32_t gmult;
+  uint32_t pad_[3];
 };
-static_assert(sizeof(HItem) == 96, "HItem layout");
+static_assert(sizeof(HItem) == 112, "HItem layout");
 // A run of buckets [b0, b1) of one HBM item, joined by one workgroup.
 constexpr uint32_t kMaxRunBuckets = 64;  // buckets per join workgroup at most
 struct BRun {
@@ -214,7 +219,8 @@ struct FItem {
   uint32_t q, sigma, inst_i, inst_j;
   uint32_t self, mask, warp, cap;
   unsigned long long off;
-  uint32_t sync, pad;  // kQSync* flags of the pair
+  uint32_t sync;   // kQSync* flags of the pair
+  uint32_t gmult;  // as HItem::gmult
 };
 
 // A slice of one side's points, generated and scattered by one workgroup.

@@ -610,7 +610,10 @@ k_bucket_filter(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
   const BRun R = runs[blockIdx.x];
   const HItem h = hitems[R.item];
   if (ovf[R.item] || done[h.q]) return;  // the join skips these runs too
-  if (h.shared == 3) {  // level 0 counted per address: always joined
+  // level 0 counted per address, or block 0 of identical blocks with the
+  // inter-block class (a record pairs with its copies in other blocks):
+  // always joined
+  if (h.shared == 3 || (h.gmult > 1 && (qd[h.q].mask & 1))) {
     for (uint32_t b = R.b0 + threadIdx.x; b < R.b1; b += kFilterThreads)
       cand[h.bucket0 + b] = 1;
     return;
@@ -776,7 +779,8 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
   // the signature pre-filter only when no exact bucket filter ran before
   // (a bucket it passed holds records with partners, and the join's first
   // level drops the others exactly)
-  const bool sig = cand == nullptr;
+  const uint32_t gmult = h.gmult > 1 ? h.gmult : 1u;
+  const bool sig = cand == nullptr && !(gmult > 1 && (q.mask & 1));
   const bool is32 = h.is32 != 0;
   constexpr int RPT = (CAP + kJoinThreads - 1) / kJoinThreads;
   u64 rx[RPT], ry[RPT];
@@ -933,11 +937,11 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
 #undef HGRD_FETCH
     if (threadIdx.x == 0) S.n = n;
     __syncthreads();
-    if (go) lds_join<kJoinThreads>(S, q, h.sigma, l0ext);
+    if (go) lds_join<kJoinThreads>(S, q, h.sigma, l0ext, gmult);
     __syncthreads();
     n = n1;
   }
-  commit_join(S, &acc[h.q]);
+  commit_join(S, &acc[h.q], gmult);
   if (threadIdx.x == 0 && nread) atomicAdd(&nbytes[blockIdx.x & 63], nread);
 }
 
@@ -1240,6 +1244,9 @@ k_gpartner(GRec g, u64 n, int L, const FItem* __restrict__ fitems,
     if (!f.self && side) continue;
     u64 c = cnt[g.slot[r]];
     long long nj = f.self ? (long long)c : (long long)(c >> 32);
+    // block 0 of identical blocks: the address level also counts the other
+    // blocks' copies (only the sign of a partner count matters: 2 nj)
+    if (L == 0 && f.gmult > 1) nj *= 2;
     g.part[r] += sign * nj;
   }
 }
@@ -1301,10 +1308,12 @@ __global__ void k_gcounts(uint32_t nitems, const FItem* __restrict__ fitems,
   if (it >= nitems) return;
   const FItem f = fitems[it];
   const u64* s = S + (u64)it * 16;
-  // conflicts minus synchronised pairs (levels 6-11 are zero without them)
-  if (f.mask & 1) atomicAdd(&acc[f.q].cnt[0], (s[0] - s[1]) - (s[6] - s[7]));
-  if (f.mask & 2) atomicAdd(&acc[f.q].cnt[1], (s[2] - s[3]) - (s[8] - s[9]));
-  if (f.mask & 4) atomicAdd(&acc[f.q].cnt[2], (s[4] - s[5]) - (s[10] - s[11]));
+  // conflicts minus synchronised pairs (levels 6-11 are zero without them);
+  // block 0 of G identical blocks: G^2 S_0 - G S_1, the others G times
+  const u64 G = f.gmult > 1 ? f.gmult : 1;
+  if (f.mask & 1) atomicAdd(&acc[f.q].cnt[0], G * (G * s[0] - s[1]) - (s[6] - s[7]));
+  if (f.mask & 2) atomicAdd(&acc[f.q].cnt[1], G * (s[2] - s[3]) - (s[8] - s[9]));
+  if (f.mask & 4) atomicAdd(&acc[f.q].cnt[2], G * (s[4] - s[5]) - (s[10] - s[11]));
 }
 
 __global__ void k_fill_u64(u64* __restrict__ p, u64 n, u64 v) {

@@ -355,6 +355,34 @@ def test_global_block_symmetry_is_exact(hg, monkeypatch):
     assert hg.default_context().stats()["block_symmetric"] == 0
 
 
+def test_global_block_symmetry_large_blocks(hg, monkeypatch):
+    """The same symmetry for blocks larger than one LDS tile: block 0's
+    points alone are partitioned through HBM and joined with the scaled
+    address level; a block-0 address held by more points than a bucket
+    overflows to the fallback, which scales the same way."""
+    t = tid(0) + tid(1) * 256
+    m = Model(1, [Array(GLOBAL, 32)],
+              [Access(0, WRITE, t + loop(0) * 16, None, [0]),
+               Access(0, READ, t // 4 + loop(0), lt(t, param(0)), [0]),
+               Access(0, WRITE, c(5) + loop(0) * 0, None, [0]),
+               Access(0, WRITE, t * 16 + loop(0), None, [0])],
+              Launch((3, 1, 1), (256, 4, 1), 32), [[700], [1024]],
+              loops=[Loop(0, "lt", 16)])
+    wl = Workload([m], [(0, 0, 0, 7), (0, 0, 1, 7), (0, 2, 2, 7), (0, 2, 0, 7),
+                        (0, 3, 3, 7), (0, 3, 0, 5), (0, 0, 1, 6)])
+    want, _ = oracle.check_pairs(wl, "B", threads=8)
+    say("global symmetry, large blocks")
+    compare(hg.check_pairs(wl), want, "global symmetry large")
+    st = hg.default_context().stats()
+    say("symmetric", st["block_symmetric"], "overflow", st["overflow_items"],
+        "hbm", st["hbm_items"])
+    assert st["block_symmetric"] >= 10 and st["overflow_items"] > 0
+    assert sum(r["verdict"] for r in want) >= 4
+    monkeypatch.setenv("HGRD_NO_SYMMETRY", "1")
+    say("global symmetry, large blocks, off")
+    compare(hg.check_pairs(wl), want, "global symmetry large off")
+
+
 def test_bucket_filter_drops_own_thread_buckets(hg):
     """Accesses that meet only in their own thread (one injective map,
     written as two different expressions so that the unit filter does not
