@@ -247,6 +247,62 @@ enum { RD_INTER = 1, RD_INTRA_BLOCK = 2, RD_INTRA_WARP = 4 };
 
 /* An access pair: two accesses of one model on the same array, and the
  * classes the caller wants checked (RD_INTER | RD_INTRA_BLOCK | ...). */
+/* ---- kernel body (section 6.1 "Avoiding race checks"; section 6.5) -----
+ * A structured kernel body as a flat statement list, from which the
+ * barrier-interval ids of every access and the acquire and release around
+ * it are derived (rd_derive_body).  RD_ST_IF opens a two-way branch (its
+ * condition is not modelled: the accesses' guards carry it), RD_ST_ELSE
+ * switches to the other way, RD_ST_LOOP opens the body of model loop
+ * `arg`, RD_ST_END closes the innermost open construct.  RD_ST_CAS and
+ * RD_ST_EXCH are atomics on `addr` (an expression of the model's pool, over
+ * the leaves of an access address, loops only those enclosing the
+ * statement) in array `array` at `scope`; RD_ST_FENCE is a fence at
+ * `scope`.  An acquire is a CAS followed by a fence, a release a fence
+ * followed by an Exch (section 2). */
+enum {
+  RD_ST_ACCESS = 1,   /* arg: access index of the model (at most once) */
+  RD_ST_BARRIER,      /* block barrier (syncthreads) */
+  RD_ST_WARP_BARRIER, /* warp barrier (syncwarp) */
+  RD_ST_IF, RD_ST_ELSE, RD_ST_END,
+  RD_ST_LOOP,         /* arg: model loop index */
+  RD_ST_CAS, RD_ST_EXCH, RD_ST_FENCE
+};
+typedef struct {
+  uint32_t kind, arg, array, scope;
+  rd_expr addr;
+} rd_stmt;
+
+/* Derives, for every access the body names, its enclosing loops, `bint`,
+ * `wint`, `acq` and `rel` (the model's other accesses are copied as they
+ * are) into acc_out[m->n_acc]; the new expressions follow a copy of the
+ * model's instruction pool in insns_out (*n_insns_out entries), so a model
+ * with insns = insns_out and acc = acc_out is the derived one.
+ *   bint: the number of counted block barriers the thread has executed
+ *   before the access (wint: warp barriers).  A barrier counts when it is
+ *   outside every branch (a barrier is reached by all threads only in
+ *   uniform code; one under a branch proves nothing, as it dominates no
+ *   later access) and each enclosing loop is an ADD loop compared with LT
+ *   or LE or a SUB loop compared with GT or GE (trip count and iteration
+ *   index then have closed forms); two points of one block are separated
+ *   by a barrier exactly when their counts differ.
+ *   acq: the nearest fence that dominates the access, then the nearest CAS
+ *   that dominates that fence (Figure 10's backward search); rel: the
+ *   nearest fence that post-dominates the access, then the nearest Exch
+ *   after it; each with the narrower of its two scopes.  A statement
+ *   dominates (post-dominates) an access when it sits directly in a
+ *   sequence that contains the access, before (after) it; a statement
+ *   inside a branch or a loop body that does not contain the access does
+ *   neither.  The nearest pair is taken whatever its scope.
+ * Host only.  Returns RD_OK; RD_EINVAL for a malformed body (unbalanced or
+ * misplaced IF/ELSE/END, a bad loop, access, array or scope, an access
+ * named twice, a bad atomic address); RD_EUNSUPPORTED when an access sits
+ * in more than 4 loops or a derived expression exceeds the expression
+ * limits; RD_ECAPACITY when cap_insns is too small (*n_insns_out holds the
+ * size needed). */
+int rd_derive_body(const rd_kernel_model* m, const rd_stmt* body, uint32_t n_stmts,
+                   rd_access* acc_out, rd_insn* insns_out, uint32_t cap_insns,
+                   uint32_t* n_insns_out);
+
 typedef struct {
   uint32_t model, a, b;
   uint32_t class_mask;

@@ -78,6 +78,11 @@ class rd_param_sets(C.Structure):
                 ("values", C.POINTER(C.c_int64))]
 
 
+class rd_stmt(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("arg", C.c_uint32), ("array", C.c_uint32),
+                ("scope", C.c_uint32), ("addr", rd_expr)]
+
+
 class rd_access_pair(C.Structure):
     _fields_ = [("model", C.c_uint32), ("a", C.c_uint32), ("b", C.c_uint32),
                 ("class_mask", C.c_uint32)]
@@ -155,7 +160,7 @@ EXPORTS = ("rd_context_create", "rd_context_destroy", "rd_check_pairs",
            "rd_strerror", "rd_selftest", "rd_tile_data", "rd_mlp_forward",
            "rd_mlp_grad", "rd_mlp_train", "rd_autotune", "rd_table_selftest",
            "rd_prefilter_selftest", "rd_expand_host_domain", "rd_mlp_save",
-           "rd_mlp_load")
+           "rd_mlp_load", "rd_derive_body")
 
 _lib = None
 
@@ -222,6 +227,11 @@ def lib():
             C.POINTER(rd_kernel_model), C.c_uint32, C.POINTER(rd_launch_domain),
             C.POINTER(rd_param_sets), C.c_uint32, C.c_uint32, C.c_uint32,
             C.c_uint64, C.POINTER(C.c_uint64)]
+        L.rd_derive_body.restype = C.c_int
+        L.rd_derive_body.argtypes = [C.POINTER(rd_kernel_model), C.POINTER(rd_stmt),
+                                     C.c_uint32, C.POINTER(rd_access),
+                                     C.POINTER(rd_insn), C.c_uint32,
+                                     C.POINTER(C.c_uint32)]
         L.rd_expand_host_domain.restype = C.c_int
         L.rd_expand_host_domain.argtypes = [C.POINTER(rd_host_domain),
                                             C.POINTER(rd_param_sets),
@@ -271,11 +281,14 @@ class Context:
 
 
 class Packed:
-    """C image of a workload's models, launch domains and parameter tuples."""
+    """C image of a workload's models, launch domains and parameter tuples.
+    ``extra`` (optional): model index -> list of expressions put into that
+    model's instruction pool after its own; their rd_expr in self.extra."""
 
-    def __init__(self, workload):
+    def __init__(self, workload, extra=None):
         n = len(workload.models)
         self.keep = []
+        self.extra = {}
         self.models = (rd_kernel_model * max(1, n))()
         self.launch = (rd_launch_domain * max(1, n))()
         self.params = (rd_param_sets * max(1, n))()
@@ -314,6 +327,8 @@ class Packed:
                     if sy is not None:
                         setattr(x, name, rd_sync(put(sy.addr), sy.array,
                                                  _SCOPE[sy.scope]))
+            if extra and mi in extra:
+                self.extra[mi] = [put(e) for e in extra[mi]]
             ld = self.launch[mi]
             for d in range(3):
                 ld.grid[d] = put(m.launch.grid[d])
@@ -644,6 +659,72 @@ def expand_host_domain(domain, cap_values=1 << 20):
         raise RuntimeError("rd_expand_host_domain failed: %s (%d)" % (rd_strerror(st), st))
     n = len(domain.params)
     return [[buf[r * n + k] for k in range(n)] for r in range(out.n_sets)]
+
+
+_ST = {"access": 1, "barrier": 2, "warp_barrier": 3, "if": 4, "else": 5, "end": 6,
+       "loop": 7, "cas": 8, "exch": 9, "fence": 10}
+_OP_NAME = {v: k for k, v in _OP.items()}
+_KIND_NAME = {v: k for k, v in _KIND.items()}
+_SCOPE_NAME = {v: k for k, v in _SCOPE.items()}
+
+
+def derive_body(model, body, cap_insns=1 << 16):
+    """rd_derive_body on a ``workloads.Model`` and a kernel body given as a
+    list of statements: ("access", k), ("barrier",), ("warp_barrier",),
+    ("if",), ("else",), ("end",), ("loop", k), ("cas", array, addr, scope),
+    ("exch", array, addr, scope), ("fence", scope).  Returns the derived
+    model (a new ``workloads.Model``).  Host only.  Raises on a non-OK
+    status (the status is in the message)."""
+    from workloads import E, Model, Access, Sync, Workload
+    exprs = [st[2] for st in body if st[0] in ("cas", "exch")]
+    pk = Packed(Workload([model], []), extra={0: exprs})
+    stm = (rd_stmt * max(1, len(body)))()
+    ex = iter(pk.extra.get(0, []))
+    for k, st in enumerate(body):
+        x = stm[k]
+        x.kind = _ST[st[0]]
+        if st[0] in ("access", "loop"):
+            x.arg = int(st[1])
+        elif st[0] in ("cas", "exch"):
+            x.array, x.scope, x.addr = int(st[1]), _SCOPE[st[3]], next(ex)
+        elif st[0] == "fence":
+            x.scope = _SCOPE[st[1]]
+    n_acc = len(model.accesses)
+    acc = (rd_access * max(1, n_acc))()
+    pool = (rd_insn * max(1, cap_insns))()
+    n = C.c_uint32(0)
+    st = lib().rd_derive_body(C.byref(pk.models[0]), stm, len(body), acc, pool,
+                              cap_insns, C.byref(n))
+    if st != RD_OK:
+        raise RuntimeError("rd_derive_body failed: %s (%d)" % (rd_strerror(st), st))
+
+    def expr_of(e):
+        if e.count == 0:
+            return None
+        code = []
+        for i in range(e.first, e.first + e.count):
+            t = pool[i]
+            name = _OP_NAME[t.op]
+            if name == "const":
+                code.append(("const", int(t.imm)))
+            elif t.op < 16:
+                code.append((name, int(t.arg)))
+            else:
+                code.append((name,))
+        return E(code)
+
+    accs = []
+    for k, a in enumerate(model.accesses):
+        x = acc[k]
+        syn = []
+        for y in (x.acq, x.rel):
+            syn.append(None if y.addr.count == 0 else
+                       Sync(y.array, expr_of(y.addr), _SCOPE_NAME[y.scope]))
+        accs.append(Access(x.array, _KIND_NAME[x.kind], expr_of(x.addr), expr_of(x.guard),
+                           [int(x.loops[i]) for i in range(x.n_loops)], expr_of(x.bint),
+                           expr_of(x.wint), _SCOPE_NAME[x.scope], a.name, syn[0], syn[1]))
+    return Model(model.n_params, model.arrays, accs, model.launch, model.param_sets,
+                 loops=model.loops, name=model.name)
 
 
 def mlp_save(w, path, feature_version):
