@@ -468,9 +468,16 @@ def run_synced(args):
     nb = (n + step_q - 1) // step_q
     ctx = hg.Context(0)
     out = {}
-    for name, w in (("synced", wl), ("plain", plain)):
+    for name, w in (("synced", wl), ("synced_fallback", wl), ("plain", plain)):
         batches = [w.compact(range(i * step_q, min(n, (i + 1) * step_q))) for i in range(nb)]
-        plans = [hg.Plan(ctx, b) for b in batches]
+        # synced_fallback: every synchronised unit through the HBM
+        # aggregation path instead of the LDS joins
+        if name == "synced_fallback":
+            os.environ["HGRD_SYNC_FALLBACK"] = "1"
+        try:
+            plans = [hg.Plan(ctx, b) for b in batches]
+        finally:
+            os.environ.pop("HGRD_SYNC_FALLBACK", None)
         for i in range(args.warmup):
             plans[i % nb].execute(raw=True)
         torch.cuda.synchronize()
@@ -487,6 +494,7 @@ def run_synced(args):
                      "evals_per_s_G": sum(s["evals"] for s in stats) / dt / 1e9,
                      "fallback_ms_per_step": sum(s["fallback_ms"] for s in stats) / len(stats),
                      "sync_records_per_step": sum(s["sync_records"] for s in stats) / len(stats),
+                     "hbm_items_per_step": sum(s["hbm_items"] for s in stats) / len(stats),
                      "racy": sum(r["verdict"] for rr in res for r in rr)}
         if name == "synced":
             sres, sb = res[0], batches[0]
@@ -499,7 +507,8 @@ def run_synced(args):
             "config": {"workload": "synced: %d mixed queries of 2^8..2^22 points per "
                                    "access with lock / producer-consumer patterns, "
                                    "seed 6006; batches of %d" % (n, step_q)},
-            "synced": out["synced"], "plain_same_queries": out["plain"]}
+            "synced": out["synced"], "synced_all_fallback": out["synced_fallback"],
+            "plain_same_queries": out["plain"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sb, sres)
         line["cpu_baseline"]["sample"] += " (batch 0 of the synced workload)"

@@ -412,6 +412,8 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kInactive = 1u << 14;  // in tli
 constexpr uint32_t kSide = 1u << 15;      // in tli
+// in tli of synchronised joins: the point has a syn() at block / device scope
+constexpr uint32_t kSynBlkBit = 1u << 10, kSynDevBit = 1u << 11;
 constexpr uint32_t kMultiThread = 1u << 31;  // in a group's count
 
 template <int CAP, int TBL>
@@ -507,9 +509,20 @@ __device__ __forceinline__ uint32_t key_slot(uint32_t k, uint32_t b, uint32_t tb
   return x & (tbl - 1);
 }
 
-template <uint32_t NT, int CAP, int TBL>
+// SYN (pairs with acquire/release, section 6.5): skey[r] holds record r's
+// synchronisation address and tli bits 10/11 whether it has a syn() at
+// block / device scope.  After each conflict level L the same groups are
+// split by the synchronisation address over the active records with a
+// syn() at the level's scope (device for the inter-block levels, block for
+// the others), when the pair's flags (QDesc bits 3/4) say two of them can
+// match: those sums T_L are the synchronised pairs, subtracted from the
+// class counts (inter = S_0 - S_1 - (T_0 - T_1), ...) and, with the
+// opposite sign, from the partner counts.  The key of a record at T_L is
+// its S_L slot and its synchronisation address.
+template <uint32_t NT, int CAP, int TBL, bool SYN = false>
 __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
-                         bool l0ext = false, uint32_t gmult = 1) {
+                         bool l0ext = false, uint32_t gmult = 1,
+                         const u64* __restrict__ skey = nullptr) {
   constexpr int RPT = (CAP + NT - 1) / NT;
   const uint32_t tid = threadIdx.x;
   const uint32_t n = S.n;
@@ -539,12 +552,64 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
     if (!l0ext && r < n) S.part[r] = 0;
   }
   if (tid == 0) S.vote[2] = 0;  // the filter level's vote (after a barrier)
+  u64 Tl[6] = {0, 0, 0, 0, 0, 0};
+  // synchronised pairs of level L (SYN): groups (S_L slot, sync address)
+  auto tpass = [&](int L) {
+    const uint32_t cls = L < 2 ? 1u : (L < 4 ? 2u : 4u);
+    const uint32_t need = L < 2 ? (qd.flags & 16u) : (qd.flags & 8u);
+    const uint32_t bit = L < 2 ? kSynDevBit : kSynBlkBit;
+    if (!(cls & mask) || !need) return;
+    for (uint32_t k = tid; k < TBL; k += NT) {
+      S.owner[k] = kEmpty;
+      S.cnt[k] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const uint32_t r = tid + (uint32_t)j * NT;
+      if ((tl[j] & kInactive) || !(tl[j] & bit)) continue;
+      S.key[r] = gid[j];
+    }
+    __syncthreads();
+    uint32_t tg[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const uint32_t r = tid + (uint32_t)j * NT;
+      tg[j] = kEmpty;
+      if ((tl[j] & kInactive) || !(tl[j] & bit)) continue;
+      const u64 v = skey[r];
+      uint32_t h = key_slot(gid[j], (uint32_t)v ^ (uint32_t)(v >> 32), TBL);
+      for (;;) {
+        const uint32_t o = atomicCAS(&S.owner[h], kEmpty, r);
+        if (o == kEmpty || (S.key[o] == gid[j] && skey[o] == v)) break;
+        h = (h + 1) & (TBL - 1);
+      }
+      atomicAdd(&S.cnt[h], (self || !(tl[j] & kSide)) ? 1u : 0x10000u);
+      tg[j] = h;
+    }
+    __syncthreads();
+    const int sign = (L & 1) ? -1 : 1;
+    u64 t = 0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const uint32_t r = tid + (uint32_t)j * NT;
+      if (tg[j] == kEmpty) continue;
+      const uint32_t c = S.cnt[tg[j]];
+      if (!self && (tl[j] & kSide)) continue;
+      const uint32_t nj = self ? (c & 0xFFFF) : (c >> 16);
+      t += nj;
+      S.part[r] -= sign * (int32_t)nj;
+    }
+    Tl[L] = t;
+    __syncthreads();
+  };
   bool any = true;
   int P = -1;  // last computed level
   for (int L = 0; L < 6; ++L) {
     if (!((used >> L) & 1)) continue;
     if ((L == 2 && same2) || (L == 4 && same4)) {
       Sl[L] = Sl[L - 1];
+      // the level's groups are the previous level's: its slots stand
+      if (SYN) tpass(L);
       continue;
     }
     const bool twin = (L == 1 && same2) || (L == 3 && same4);
@@ -655,12 +720,13 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
     } else {
       __syncthreads();
     }
+    if (SYN) tpass(L);
   }
   if (!any) return;
-  // class counts: reduce S_L over the block
-  u64 c0 = (mask & 1) ? Sl[0] - Sl[1] : 0;  // l0ext: Sl[0] = 0, so -S_1
-  u64 c1 = (mask & 2) ? Sl[2] - Sl[3] : 0;
-  u64 c2 = (mask & 4) ? Sl[4] - Sl[5] : 0;
+  // class counts: reduce S_L over the block (minus synchronised pairs)
+  u64 c0 = (mask & 1) ? (Sl[0] - Sl[1]) - (Tl[0] - Tl[1]) : 0;  // l0ext: Sl[0] = 0, so -S_1
+  u64 c1 = (mask & 2) ? (Sl[2] - Sl[3]) - (Tl[2] - Tl[3]) : 0;
+  u64 c2 = (mask & 4) ? (Sl[4] - Sl[5]) - (Tl[4] - Tl[5]) : 0;
   u64 best = kNoKey;
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {

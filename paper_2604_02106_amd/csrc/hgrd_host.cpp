@@ -1737,6 +1737,7 @@ struct rd_plan_impl {
     uint32_t n_tab_chunks;  // the first n_tab_chunks chunks have term tables
     uint32_t n_runs;        // bucket runs (one join workgroup each)
     uint32_t n_tab_runs;    // the first n_tab_runs runs are of items with tables
+    uint32_t n_sync_runs;   // the last n_sync_runs runs are of synchronised items
     uint64_t key_bytes;
     uint64_t hitem_off, chunk_off, bitem_off;  // element offsets in the plan pools
   };
@@ -1998,6 +1999,9 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       }
       // bit 2: both accesses compute their address with the same expression
       if (same_addr_expr(models[pr.model], pr.a, pr.b)) fl |= 4;
+      // bits 3, 4: synchronised pairs whose syn() can match (block, device)
+      if (q.sync & kQSyncBlk) fl |= 8;
+      if (q.sync & kQSyncDev) fl |= 16;
       q.qd.flags = fl;
     }
   }
@@ -2013,6 +2017,9 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   const bool block_sym = getenv("HGRD_NO_SYMMETRY") == nullptr;
   // unit filter decisions for synchronised pairs (HGRD_NO_UNIT_FILTER)
   const bool unit_filter = getenv("HGRD_NO_UNIT_FILTER") == nullptr;
+  // synchronised units through the LDS joins when they qualify
+  // (HGRD_SYNC_FALLBACK sends them all to the HBM aggregation path)
+  const bool sync_lds = getenv("HGRD_SYNC_FALLBACK") == nullptr;
   std::vector<HPlan> hplans;
   auto npts_of = [&](int32_t idx) -> uint64_t {
     return idx < 0 ? 0 : P.dev_insts[idx].npts;
@@ -2052,6 +2059,28 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         // expression of either access can fail (term tables, acquire and
         // release addresses proven error-free); the unit filter's decision
         ++plan->sync_decided;
+        continue;
+      }
+      if (q.sync && sync_lds && cfg < 2 && ia >= 0 && ib >= 0 && P.tabs[ia].on && P.tabs[ib].on &&
+          P.tabs[ia].syn_safe && P.tabs[ib].syn_safe) {
+        // acquire/release on the pair, every expression proven error-free:
+        // partitioned through HBM and joined in LDS with the
+        // synchronisation levels (a bucket that overflows goes to the
+        // fallback)
+        HPlan hp;
+        memset(&hp, 0, sizeof hp);
+        hp.h.q = k;
+        hp.h.sigma = s;
+        hp.h.inst_i = (uint32_t)ia;
+        hp.h.inst_j = (uint32_t)ib;
+        hp.h.shared = q.qd.shared;
+        hp.h.is32 = P.dev_insts[ia].is32;
+        hp.h.sync = 1;
+        hp.h.shift = item_shift(ia, ib, q.qd.self, q.qd.shared);
+        fastdiv_consts(P.dev_insts[ia].tpb, &hp.h.tpb_m[0], &hp.h.tpb_s[0]);
+        fastdiv_consts(P.dev_insts[ib].tpb, &hp.h.tpb_m[1], &hp.h.tpb_s[1]);
+        hp.R = npts_of(ia) + (q.qd.self ? 0 : npts_of(ib));
+        hplans.push_back(hp);
         continue;
       }
       if (q.sync) {
@@ -2345,7 +2374,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       HPlan hp = hplans[i];
       bool ps = false;
       const uint32_t a = hp.h.inst_i, b = hp.h.inst_j;
-      if (hp.h.shared == 0 && hp.h.gmult <= 1 && tab_on[a] && tab_on[b]) {
+      if (hp.h.shared == 0 && hp.h.gmult <= 1 && !hp.h.sync && tab_on[a] && tab_on[b]) {
         const double lo = (double)std::min(P.arange[a].first, P.arange[b].first);
         const double hi = (double)std::max(P.arange[a].second, P.arange[b].second);
         if (hi >= lo && (double)hp.R >= (hi - lo + 1.0) * cap) {
@@ -2395,8 +2424,8 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       ++end;
     }
     // chunks and runs of items with term tables first, then the others
-    std::vector<ExpandSpec> interp, interp_runs;
-    uint64_t tab_chunks = 0, tab_runs = 0, oth_chunks = 0, oth_runs = 0;
+    std::vector<ExpandSpec> interp, interp_runs, sync_runs;
+    uint64_t tab_chunks = 0, tab_runs = 0, oth_chunks = 0, oth_runs = 0, syn_runs = 0;
     for (size_t i = pos; i < end; ++i) {
       const HItem& h = hplans[i].h;
       uint32_t li = (uint32_t)plan->hitems.size();  // global item index
@@ -2405,7 +2434,10 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
       plan->presplit.push_back(0);
       const bool tr = P.tabs[h.inst_i].on && P.tabs[h.inst_j].on;
       const uint32_t nr = (h.nbuckets + plan->run_buckets - 1) / plan->run_buckets;
-      if (nr) {
+      if (nr && h.sync) {
+        sync_runs.push_back({li, 0, h.nbuckets, plan->run_buckets, 0});
+        syn_runs += nr;
+      } else if (nr) {
         (tr ? run_specs : interp_runs).push_back({li, 0, h.nbuckets, plan->run_buckets, 0});
         (tr ? tab_runs : oth_runs) += nr;
       }
@@ -2423,10 +2455,12 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     }
     chunk_specs.insert(chunk_specs.end(), interp.begin(), interp.end());
     run_specs.insert(run_specs.end(), interp_runs.begin(), interp_runs.end());
+    run_specs.insert(run_specs.end(), sync_runs.begin(), sync_runs.end());
     W.n_tab_chunks = (uint32_t)tab_chunks;
     W.n_tab_runs = (uint32_t)tab_runs;
+    W.n_sync_runs = (uint32_t)syn_runs;
     W.n_items = (uint32_t)(end - pos);
-    W.n_runs = (uint32_t)(tab_runs + oth_runs);
+    W.n_runs = (uint32_t)(tab_runs + oth_runs + syn_runs);
     W.n_chunks = (uint32_t)(tab_chunks + oth_chunks);
     n_all_chunks += W.n_chunks;
     n_all_runs += W.n_runs;
@@ -2734,10 +2768,17 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
                         events ? ke + 2 : nullptr))
         return RD_EDEVICE;
       if (events) TRY_HIP(hipEventRecord(e3, st));
-      if (W.n_runs > W.n_tab_runs &&
-          launch_bucket(wcfg, st, W.n_runs - W.n_tab_runs, d_bit + W.bitem_off + W.n_tab_runs,
+      const uint32_t n_oth = W.n_runs - W.n_tab_runs - W.n_sync_runs;
+      if (n_oth &&
+          launch_bucket(wcfg, st, n_oth, d_bit + W.bitem_off + W.n_tab_runs,
                         0, d_hit, d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs,
                         d_cursor, d_ovf, d_done, l0k, l0c, cand, d_nbytes + 128, nullptr))
+        return RD_EDEVICE;
+      if (W.n_sync_runs &&
+          launch_bucket(wcfg, st, W.n_sync_runs,
+                        d_bit + W.bitem_off + W.n_runs - W.n_sync_runs, W.n_sync_runs, d_hit,
+                        d_insts, d_code, d_params, d_loops, d_qd, d_acc, d_recs, d_cursor,
+                        d_ovf, d_done, l0k, l0c, cand, d_nbytes + 128, nullptr, true))
         return RD_EDEVICE;
       if (events) {
         TRY_HIP(hipEventRecord(e4, st));
@@ -3008,6 +3049,12 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     if (ovf[i] == kApart) continue;  // decided by the unit filter
     if ((!ovf[i] && !plan->presplit[i]) || plan->hitems[i].shared == 2) continue;
     RItem r{plan->hitems[i], plan->hR[i]};
+    if (r.h.sync) {
+      // the synchronisation levels live in the LDS joins and the fallback:
+      // an overflowing synchronised item goes to the fallback
+      still.push_back(r);
+      continue;
+    }
     if (r.h.mode && r.h.shared == 0) {
       // a dense-map global item overflows only on heavy address groups,
       // which more buckets do not spread: split it right away
@@ -3044,7 +3091,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   std::vector<RItem> split_all, direct;
   // block-symmetric units hold one block: nothing for the (address, block)
   // split to split, so they go to the fallback
-  for (auto& r : still) (r.h.shared == 0 && r.h.gmult <= 1 ? split_all : direct).push_back(r);
+  for (auto& r : still)
+    (r.h.shared == 0 && r.h.gmult <= 1 && !r.h.sync ? split_all : direct).push_back(r);
   S.split_items = split_all.size();
   S.presplit_items = 0;
   for (uint8_t f : plan->presplit) S.presplit_items += f;
@@ -3187,6 +3235,7 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     f.warp = q.qd.warp;
     f.cap = (uint32_t)direct[i].R;
     f.gmult = h.gmult;
+    f.sync = h.sync ? q.sync : 0;
     S.fallback_records += direct[i].R;
     if (plan->log_level >= 2)
       fprintf(stderr, "hgrd: fallback item pair=%u tuple=%u shared=%u points=%llu buckets=%u\n",

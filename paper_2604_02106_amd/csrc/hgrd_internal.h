@@ -115,7 +115,9 @@ struct QDesc {
                      // barrier interval id in every tuple (the block level
                      // groups equal the (address, block) groups); bit 1: the
                      // same for the warp-barrier id; bit 2: both accesses
-                     // compute their address with one expression
+                     // compute their address with one expression; bits 3, 4:
+                     // syn() of the two accesses can match at block / device
+                     // scope (acquire/release, section 6.5)
 };
 
 struct QAcc {
@@ -188,7 +190,10 @@ struct HItem {
   // term in either access); only block 0's points are generated, the
   // address-only level stands for G groups and every count is taken G times
   uint32_t gmult;
-  uint32_t pad_[3];
+  uint32_t sync;  // 1: a pair with acquire/release (joined with the
+                  //   synchronisation levels; never split, overflow to the
+                  //   fallback)
+  uint32_t pad_[2];
 };
 static_assert(sizeof(HItem) == 112, "HItem layout");
 // A run of buckets [b0, b1) of one HBM item, joined by one workgroup.

@@ -754,9 +754,9 @@ constexpr uint32_t join_waves_per_simd() {
 // pair before any point id is decoded; the counts are committed once per
 // run.  TAB: both instances of every item of the launch have term tables
 // (interval ids by lookup, no interpreter code).
-template <int CAP, int TBL, bool TAB>
+template <int CAP, int TBL, bool TAB, bool SYN = false>
 __global__ void __launch_bounds__(kJoinThreads)
-__attribute__((amdgpu_waves_per_eu(TAB ? join_waves_per_simd<CAP, TBL>() : 1u)))
+__attribute__((amdgpu_waves_per_eu(TAB && !SYN ? join_waves_per_simd<CAP, TBL>() : 1u)))
 k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
               const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
               const int64_t* __restrict__ params,
@@ -770,6 +770,8 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
               u64* __restrict__ nbytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   JoinLds<CAP, TBL>& S = *reinterpret_cast<JoinLds<CAP, TBL>*>(smem);
+  // SYN: the records' synchronisation addresses after the join's LDS
+  u64* skey = SYN ? reinterpret_cast<u64*>(smem + sizeof(JoinLds<CAP, TBL>)) : nullptr;
   const BRun R = runs[blockIdx.x];
   const HItem h = hitems[R.item];
   if (ovf[R.item] || done[h.q]) return;
@@ -919,6 +921,14 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
           S.addr[r] = (u64)a;
           S.blin[r] = id.blin;
           S.tli[r] = (id.ilin << 16) | (side << 15) | id.tlin;
+          if (SYN) {
+            // syn() of the point (its addresses are proven error-free)
+            int64_t v;
+            uint32_t e2 = 0;
+            const uint32_t b = point_syn(I, id, code, params, loopvals, v, e2);
+            skey[r] = (u64)v;
+            S.tli[r] |= b << 10;
+          }
           S.bw[r] = (bi << 16) | wi;
           S.w[r] = (uint16_t)(wsh < 32 ? id.tlin >> wsh : id.tlin / q.warp);
           if (l0ext) {
@@ -937,7 +947,7 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
 #undef HGRD_FETCH
     if (threadIdx.x == 0) S.n = n;
     __syncthreads();
-    if (go) lds_join<kJoinThreads>(S, q, h.sigma, l0ext, gmult);
+    if (go) lds_join<kJoinThreads, CAP, TBL, SYN>(S, q, h.sigma, l0ext, gmult, skey);
     __syncthreads();
     n = n1;
   }
@@ -1518,6 +1528,12 @@ static int set_lds_attrs() {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   HGRD_CHECK(hipFuncSetAttribute((const void*)k_bucket_join<CAP, TBL, false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  // the synchronised join also holds a synchronisation address per record
+  // (the largest tile shape has no room for it: its items use the fallback)
+  if (lds + CAP * (int)sizeof(u64) <= 160 * 1024)
+    HGRD_CHECK(hipFuncSetAttribute((const void*)k_bucket_join<CAP, TBL, true, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   lds + CAP * (int)sizeof(u64)));
   HGRD_CHECK(hipFuncSetAttribute(
       (const void*)k_bucket_filter<CAP>, hipFuncAttributeMaxDynamicSharedMemorySize,
       (int)sizeof(FilterLds<CAP>)));
@@ -1532,8 +1548,10 @@ static int launch_bucket_t(hipStream_t st, uint32_t nruns, const BRun* runs,
                            const unsigned char* recs, const uint32_t* cursor,
                            const uint32_t* ovf, const uint32_t* done,
                            const u64* l0keys, const u64* l0cnt, uint8_t* cand,
-                           u64* nbytes, const hipEvent_t* kev) {
-  // runs [0, n_tab) are of items whose instances have term tables; record
+                           u64* nbytes, const hipEvent_t* kev, bool syn = false) {
+  // syn: every run is of a synchronised item with term tables (joined with
+  // the synchronisation levels, no per-kernel events).
+  // Otherwise runs [0, n_tab) are of items whose instances have term tables; record
   // bytes read by the join are counted in nbytes[0..63] and nbytes[64..127],
   // by the address filter (when cand is given) in nbytes[256..319].  The
   // filter runs over every run first; `mid` (optional) is recorded between
@@ -1559,6 +1577,18 @@ static int launch_bucket_t(hipStream_t st, uint32_t nruns, const BRun* runs,
                            nbytes + 256);
       HGRD_CHECK(hipGetLastError());
     }
+  }
+  if (syn) {
+    if (lds + CAP * sizeof(u64) > 160 * 1024) return 1;  // never planned so
+    for (uint32_t off = 0; off < nruns; off += 1u << 20) {
+      uint32_t m = nruns - off < (1u << 20) ? nruns - off : (1u << 20);
+      hipLaunchKernelGGL((k_bucket_join<CAP, TBL, true, true>), dim3(m), dim3(kJoinThreads),
+                         lds + CAP * sizeof(u64), st, runs + off, hitems, insts, code, params,
+                         loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand,
+                         nbytes + 64);
+      HGRD_CHECK(hipGetLastError());
+    }
+    return 0;
   }
   for (uint32_t off = 0; off < nruns; off += 1u << 20) {
     uint32_t m = nruns - off < (1u << 20) ? nruns - off : (1u << 20);
@@ -1750,12 +1780,12 @@ int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
                   const QDesc* qd, QAcc* acc, const unsigned char* recs,
                   const uint32_t* cursor, const uint32_t* ovf, const uint32_t* done,
                   const u64* l0keys, const u64* l0cnt, uint8_t* cand, u64* nbytes,
-                  const hipEvent_t* kev) {
+                  const hipEvent_t* kev, bool syn) {
   const DevInst* I = (const DevInst*)insts;
   switch (cfg) {
-    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, kev);
-    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, kev);
-    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, kev);
+    case 0: return launch_bucket_t<1024, 2048>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, kev, syn);
+    case 1: return launch_bucket_t<1536, 4096>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, kev, syn);
+    default: return launch_bucket_t<3072, 8192>(st, nruns, runs, n_tab, hitems, I, code, params, loopvals, qd, acc, recs, cursor, ovf, done, l0keys, l0cnt, cand, nbytes, kev, syn);
   }
 }
 

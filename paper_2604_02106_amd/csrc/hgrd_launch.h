@@ -60,7 +60,8 @@ int launch_bucket(int cfg, hipStream_t st, uint32_t nruns, const BRun* runs,
                   const QDesc* qd, QAcc* acc, const unsigned char* recs,
                   const uint32_t* cursor, const uint32_t* ovf, const uint32_t* done,
                   const unsigned long long* l0keys, const unsigned long long* l0cnt,
-                  uint8_t* cand, unsigned long long* nbytes, const hipEvent_t* kev);
+                  uint8_t* cand, unsigned long long* nbytes, const hipEvent_t* kev,
+                  bool syn = false);
 int launch_level0(hipStream_t st, const Chunk* chunks, uint32_t n,
                   const L0Item* items, const void* insts, const DInsn* code,
                   const int64_t* params, const int64_t* loopvals,

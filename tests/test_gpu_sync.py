@@ -74,9 +74,18 @@ def pin_models(G, B, w):
     return Workload([m], [(0, a, b, 7) for (a, b) in pairs])
 
 
+@pytest.fixture(params=["lds", "fallback"])
+def sync_path(request, monkeypatch):
+    """Synchronised units through the LDS joins (those that qualify) or
+    all through the HBM aggregation path."""
+    if request.param == "fallback":
+        monkeypatch.setenv("HGRD_SYNC_FALLBACK", "1")
+    return request.param
+
+
 @pytest.mark.parametrize("G,B,w", [(4, 16, 4), (3, 8, 2), (2, 32, 8), (40, 256, 32)])
-def test_sync_pins(hg, G, B, w):
-    got = run_both(hg, pin_models(G, B, w), "sync pins G=%d B=%d w=%d" % (G, B, w))
+def test_sync_pins(hg, G, B, w, sync_path):
+    got = run_both(hg, pin_models(G, B, w), "sync pins G=%d B=%d w=%d %s" % (G, B, w, sync_path))
     full = [G * (G - 1) * B * B, G * B * (B - w), G * B * (w - 1)]
     assert got[0]["by_class"] == full
     assert got[1]["by_class"] == [0, 0, 0]
@@ -84,16 +93,20 @@ def test_sync_pins(hg, G, B, w):
     assert got[5]["by_class"] == [full[0] // 2, G * B * (B - w) // 2, G * B * w // 2]
     assert got[7]["by_class"] == [0, (G - 1) * (B - w), (G - 1) * (w - 1)]
     assert got[7]["witness"] == (0, 1, 0, 0, 1, 1, 0)
-    import paper_2604_02106_amd as H
-    assert H.default_context().stats()["sync_records"] > 0
+    st = hg.default_context().stats()
+    say("sync records", st["sync_records"], "hbm items", st["hbm_items"])
+    if sync_path == "fallback":
+        assert st["sync_records"] > 0
+    else:
+        assert st["sync_records"] == 0 and st["hbm_items"] > 0
 
 
 @pytest.mark.parametrize("seed", range(30))
-def test_sync_random(hg, seed):
-    run_both(hg, rand_sync_workload(seed), "sync rand seed=%d" % seed)
+def test_sync_random(hg, seed, sync_path):
+    run_both(hg, rand_sync_workload(seed), "sync rand seed=%d %s" % (seed, sync_path))
 
 
-def test_sync_batched_with_plain_pairs(hg):
+def test_sync_batched_with_plain_pairs(hg, sync_path):
     """Synchronised and plain pairs in one call: each goes its own way and
     the results are the oracle's."""
     models, pairs = [], []
@@ -105,7 +118,7 @@ def test_sync_batched_with_plain_pairs(hg):
     run_both(hg, Workload(models, pairs), "sync batch")
 
 
-def test_sync_large(hg):
+def test_sync_large(hg, sync_path):
     """Launches of tens of thousands of points per side, with loops and
     barrier-interval ids: lock by thread parity inside a loop, a lock per
     iteration, producer/consumer with the consumer on the wrong flag in
@@ -125,7 +138,7 @@ def test_sync_large(hg):
     m = Model(0, arrays, accs, Launch((96, 1, 1), (256, 1, 1), 32), [[]], loops=loops)
     wl = Workload([m], [(0, 0, 0, 7), (0, 1, 1, 7), (0, 2, 3, 7), (0, 4, 4, 7),
                         (0, 4, 5, 7), (0, 0, 1, 7)])
-    got = run_both(hg, wl, "sync large")
+    got = run_both(hg, wl, "sync large %s" % sync_path)
     assert all(r["status"] == 0 for r in got)
     assert sum(r["verdict"] for r in got) >= 3
 
