@@ -35,7 +35,7 @@ KERNELS = (
     ("k_bucket_filter<1024>", "filter_tab_launches", "filter_tab_ms", "filter_tab_bytes",
      "reads every record back and keeps the buckets holding an address of both "
      "accesses (per-wavefront LDS hash table)"),
-    ("k_bucket_join<1024, 2048, true>", "join_tab_launches", "join_tab_ms",
+    ("k_bucket_join<1024, 2048, true, false>", "join_tab_launches", "join_tab_ms",
      "join_tab_bytes", "reads the records of the buckets the filter kept and "
      "joins them in LDS level by level"),
 )
@@ -44,7 +44,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_02106_amd", "csrc", f)
 
 
 LIMITER = {
-    "k_bucket_join<1024, 2048, true>":
+    "k_bucket_join<1024, 2048, true, false>":
         "LDS hash joins level by level with workgroup barriers between levels "
         "(latency- and barrier-bound, not HBM: counters read 0.70x the record "
         "bytes from HBM)",
@@ -348,7 +348,7 @@ def run_mixed(args):
         "exact_shortcuts_per_step": {k: sum(s[k] for s in stats) / len(stats) for k in (
             "units_apart", "block_symmetric")},
     }
-    kr = kernel_rooflines(stats, {"k_bucket_join<1024, 2048, true>": MIXED_TRAFFIC_FILE})
+    kr = kernel_rooflines(stats, {"k_bucket_join<1024, 2048, true, false>": MIXED_TRAFFIC_FILE})
     if kr:
         dom = max(kr, key=lambda k: kr[k]["ms_per_step"])
         line["roofline"] = kr[dom]
