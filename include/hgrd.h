@@ -94,9 +94,23 @@ enum { RD_CMP_LT = 0, RD_CMP_LE, RD_CMP_GT, RD_CMP_GE, RD_CMP_NE };
 enum { RD_UPD_ADD = 0, RD_UPD_SUB, RD_UPD_MUL, RD_UPD_DIV, RD_UPD_SHL,
        RD_UPD_SHR };
 
+/* Arrays with the same nonzero `alias` are views of one memory (two
+ * pointers into one buffer; the paper is silent on aliasing): element k of
+ * such an array is element base + k of the memory, so an access's effective
+ * address is base + its address (an overflow is RD_ERANGE), and accesses
+ * on two views may form a pair.  Views of one memory must share the space
+ * (else the pair is RD_EINVAL); acquires and releases on two views of one
+ * memory at one effective address are one lock.  alias = 0: a memory of
+ * its own (base is ignored).  For a 32-bit array the effective address must
+ * fit int32.  A vector access of w elements (e.g. float4 against float) is
+ * modelled as an access inside an extra model loop j in [0, w) with address
+ * a + j: its counts are then of element pairs. */
 typedef struct {
   uint32_t space;     /* RD_GLOBAL or RD_SHARED (shared: one per block) */
   uint32_t addr_bits; /* 32: addresses must fit int32; 64 */
+  uint32_t alias;     /* memory id shared by views (< 2^24), 0: none */
+  uint32_t pad;
+  int64_t base;       /* the view's first element in the memory */
 } rd_array;
 
 /* for (v = init; v <cmp> bound; v = v <upd> step); init, bound and step

@@ -43,7 +43,8 @@ class OExpr(C.Structure):
 
 
 class OArray(C.Structure):
-    _fields_ = [("space", C.c_int32), ("addr_bits", C.c_int32)]
+    _fields_ = [("space", C.c_int32), ("addr_bits", C.c_int32), ("alias", C.c_int32),
+                ("pad", C.c_int32), ("base", C.c_int64)]
 
 
 class OLoop(C.Structure):
@@ -140,7 +141,8 @@ class _Packed:
             return OExpr(first, len(e.code))
 
         self.arrays = (OArray * max(1, len(model.arrays)))(
-            *[OArray(_SPACE[a.space], a.addr_bits) for a in model.arrays])
+            *[OArray(_SPACE[a.space], a.addr_bits, getattr(a, "alias", 0), 0,
+                     getattr(a, "base", 0)) for a in model.arrays])
         loops = []
         for l in model.loops:
             loops.append(OLoop(put(l.init), put(l.bound), put(l.step),

@@ -94,7 +94,9 @@ enum { E_DIVZERO = 1, E_RANGE = 2, E_UNSUP = 4, E_INVAL = 8 };
 
 typedef struct { int64_t op, arg; } OTok;
 typedef struct { int32_t first, count; } OExpr;
-typedef struct { int32_t space, addr_bits; } OArray;
+/* alias != 0: a view of memory `alias` whose element 0 is the memory's
+ * element `base` (views with one alias and space share their elements) */
+typedef struct { int32_t space, addr_bits, alias, pad; int64_t base; } OArray;
 typedef struct { OExpr init, bound, step; int32_t cmp, upd; } OLoop;
 /* acquire or release: addr.count 0 = none */
 typedef struct { OExpr addr; int32_t array, scope; } OSync;
@@ -265,7 +267,8 @@ static int check_access(const OModel* m, const OAccess* a) {
   if (a->array < 0 || a->array >= m->n_arrays) return E_INVAL;
   const OArray* arr = &m->arrays[a->array];
   if ((arr->space != SP_GLOBAL && arr->space != SP_SHARED) ||
-      (arr->addr_bits != 32 && arr->addr_bits != 64)) return E_INVAL;
+      (arr->addr_bits != 32 && arr->addr_bits != 64) ||
+      arr->alias < 0 || arr->alias >= (1 << 24)) return E_INVAL;
   if (a->kind < K_READ || a->kind > K_ATOMIC) return E_INVAL;
   if (a->scope != SC_BLOCK && a->scope != SC_DEVICE) return E_INVAL;
   if (a->n_loops < 0) return E_INVAL;
@@ -302,14 +305,14 @@ static int check_access(const OModel* m, const OAccess* a) {
 /* ------------------------------------------------------------------------ */
 /* Enumerating the points of one access for one parameter tuple.            */
 
-/* sa[k], sv[k]: array and address of the point's syn() at scope k (0
- * block, 1 device); sa[k] = -1: none. */
+/* sa[k], sv[k]: memory and effective address of the point's syn() at
+ * scope k (0 block, 1 device); sa[k] = -1: none. */
 typedef struct {
   int64_t addr;
   uint32_t blin, tlin, ilin;
   uint16_t bint, wint;
   uint8_t side;
-  int32_t sa[2];
+  int64_t sa[2];
   int64_t sv[2];
 } OPoint;
 
@@ -382,28 +385,47 @@ static int64_t loop_values(const OModel* m, const OLoop* l, const int64_t* param
   return n;
 }
 
+/* Memory identity of an array: its own, or the aliased memory of its views
+ * (same alias id and space). */
+static int64_t memory_id(const OModel* m, int32_t array) {
+  const OArray* a = &m->arrays[array];
+  if (!a->alias) return array;
+  return ((int64_t)1 << 40) | ((int64_t)a->space << 32) | a->alias;
+}
+
+/* Effective address in the array's memory: base + address for a view. */
+static int64_t effective(const OModel* m, int32_t array, int64_t addr, int* err) {
+  const OArray* a = &m->arrays[array];
+  if (!a->alias || !a->base) return addr;
+  int64_t r;
+  if (__builtin_add_overflow(addr, a->base, &r)) { *err |= E_RANGE; return 0; }
+  return r;
+}
+
 /* syn() of Figures 9 and 10 at one point for required scope `scope`:
  * the acquire and release count only when their scope is at least as wide.
  * acqv, relv: their addresses at this point. */
 static void syn_at(const OModel* m, const OAccess* a, int64_t acqv, int64_t relv,
-                   int scope, int32_t* arr, int64_t* val) {
+                   int scope, int64_t* mem, int64_t* val) {
   int have_a = a->acq.addr.count && a->acq.scope >= scope;
   int have_r = a->rel.addr.count && a->rel.scope >= scope;
-  *arr = -1;
+  int32_t arr = -1;
   *val = 0;
-  if (have_a && have_r && a->acq.array == a->rel.array && acqv == relv) {
-    *arr = a->acq.array;  /* lock: acquire and release on one address */
+  if (have_a && have_r && memory_id(m, a->acq.array) == memory_id(m, a->rel.array) &&
+      acqv == relv) {
+    arr = a->acq.array;  /* lock: acquire and release on one address */
     *val = acqv;
   } else if (a->kind == K_WRITE && have_r) {
-    *arr = a->rel.array;  /* producer */
+    arr = a->rel.array;  /* producer */
     *val = relv;
   } else if (a->kind == K_READ && have_a) {
-    *arr = a->acq.array;  /* consumer */
+    arr = a->acq.array;  /* consumer */
     *val = acqv;
   }
   /* shared memory is one per block: such a lock or flag never orders two
    * blocks, and device scope is only asked for inter-block conflicts */
-  if (scope == SC_DEVICE && *arr >= 0 && m->arrays[*arr].space == SP_SHARED) *arr = -1;
+  if (scope == SC_DEVICE && arr >= 0 && m->arrays[arr].space == SP_SHARED) arr = -1;
+  *mem = arr >= 0 ? memory_id(m, arr) : -1;
 }
 
 /* All points of access a under tuple s, in lexicographic (blin, tlin, ilin)
@@ -457,14 +479,14 @@ static int64_t enumerate(const OModel* m, const OAccess* a, int32_t s, int side,
           int64_t guard = eval(m, a->guard, &env, 1, err);
           if (guard == 0) continue;
           int e = 0;
-          int64_t addr = eval(m, a->addr, &env, 0, &e);
+          int64_t addr = effective(m, a->array, eval(m, a->addr, &env, 0, &e), &e);
           int64_t bi = eval(m, a->bint, &env, 0, &e);
           int64_t wi = eval(m, a->wint, &env, 0, &e);
           int64_t sval[2] = {0, 0};
           const OSync* so[2] = {&a->acq, &a->rel};
           for (int k = 0; k < 2; ++k) {
             if (so[k]->addr.count == 0) continue;
-            sval[k] = eval(m, so[k]->addr, &env, 0, &e);
+            sval[k] = effective(m, so[k]->array, eval(m, so[k]->addr, &env, 0, &e), &e);
             if (m->arrays[so[k]->array].addr_bits == 32 &&
                 (sval[k] < INT32_MIN || sval[k] > INT32_MAX)) e |= E_RANGE;
           }
@@ -739,7 +761,9 @@ static void check_one(const OModel* models, int32_t n_models, const OPair* pr,
   err |= check_access(m, x);
   err |= check_access(m, y);
   if (!(err & E_INVAL)) {
-    if (x->array != y->array) err |= E_INVAL;
+    /* one memory: the same array or two views of one aliased memory */
+    if (x->array != y->array && memory_id(m, x->array) != memory_id(m, y->array))
+      err |= E_INVAL;
     if (m->warp < 1 || m->warp > 1024) err |= E_INVAL;
     if (m->n_sets < 0) err |= E_INVAL;
     for (int d = 0; d < 3; ++d) {

@@ -40,7 +40,8 @@ class rd_expr(C.Structure):
 
 
 class rd_array(C.Structure):
-    _fields_ = [("space", C.c_uint32), ("addr_bits", C.c_uint32)]
+    _fields_ = [("space", C.c_uint32), ("addr_bits", C.c_uint32), ("alias", C.c_uint32),
+                ("pad", C.c_uint32), ("base", C.c_int64)]
 
 
 class rd_loop(C.Structure):
@@ -308,7 +309,8 @@ class Packed:
                 return rd_expr(first, len(e.code))
 
             arrays = (rd_array * max(1, len(m.arrays)))(
-                *[rd_array(_SPACE[a.space], a.addr_bits) for a in m.arrays])
+                *[rd_array(_SPACE[a.space], a.addr_bits, getattr(a, "alias", 0), 0,
+                           getattr(a, "base", 0)) for a in m.arrays])
             loops = (rd_loop * max(1, len(m.loops)))()
             for k, l in enumerate(m.loops):
                 loops[k] = rd_loop(put(l.init), put(l.bound), put(l.step),

@@ -113,10 +113,70 @@ uint32_t check_expr(const rd_kernel_model& m, rd_expr e, int ctx,
 
 uint32_t syn_flags(const rd_kernel_model& m, const rd_access& a);
 
+// The memory an array belongs to: its own (the array index) or the memory
+// its alias id names, shared by every view with that id and space.
+int64_t memory_of(const rd_kernel_model& m, uint32_t array) {
+  const rd_array& a = m.arrays[array];
+  if (!a.alias) return array;
+  return ((int64_t)1 << 40) | ((int64_t)a.space << 32) | a.alias;
+}
+
+// Models with the effective addresses of aliased views: an access address
+// (or an acquire's or release's) on a view with a nonzero base becomes
+// base + address, appended to a copy of the model's instruction pool.  The
+// base is an immediate operand, so the device program takes no extra
+// register.  Expressions are validated on the caller's models.
+struct ModelViews {
+  std::vector<std::vector<rd_insn>> insns;
+  std::vector<std::vector<rd_access>> acc;
+  std::vector<rd_kernel_model> m;
+};
+void build_views(const rd_kernel_model* models, uint32_t n, ModelViews& V) {
+  V.m.assign(models, models + n);
+  V.insns.resize(n);
+  V.acc.resize(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const rd_kernel_model& M = models[i];
+    bool any = false;
+    for (uint32_t k = 0; M.arrays && k < M.n_arrays; ++k)
+      any |= M.arrays[k].alias != 0 && M.arrays[k].base != 0;
+    if (!any || (M.n_acc && !M.acc) || (M.n_insns && !M.insns)) continue;
+    V.insns[i].assign(M.insns, M.insns + M.n_insns);
+    V.acc[i].assign(M.acc, M.acc + M.n_acc);
+    auto shift = [&](rd_expr& e, uint32_t arr) {
+      if (arr >= M.n_arrays || e.count == 0 || (uint64_t)e.first + e.count > M.n_insns) return;
+      const rd_array& A = M.arrays[arr];
+      if (!A.alias || !A.base) return;
+      std::vector<rd_insn>& P = V.insns[i];
+      const uint32_t first = (uint32_t)P.size();
+      P.insert(P.end(), M.insns + e.first, M.insns + e.first + e.count);
+      rd_insn c, add;
+      memset(&c, 0, sizeof c);
+      memset(&add, 0, sizeof add);
+      c.op = RD_OP_CONST;
+      c.imm = A.base;
+      add.op = RD_OP_ADD;
+      P.push_back(c);
+      P.push_back(add);
+      e.first = first;
+      e.count += 2;
+    };
+    for (rd_access& A : V.acc[i]) {
+      shift(A.addr, A.array);
+      shift(A.acq.addr, A.acq.array);
+      shift(A.rel.addr, A.rel.array);
+    }
+    V.m[i].insns = V.insns[i].data();
+    V.m[i].n_insns = (uint32_t)V.insns[i].size();
+    V.m[i].acc = V.acc[i].data();
+  }
+}
+
 uint32_t check_access(const rd_kernel_model& m, const rd_access& a) {
   if (a.array >= m.n_arrays || !m.arrays) return ERR_INVAL;
   const rd_array& arr = m.arrays[a.array];
-  if (arr.space > RD_SHARED || (arr.addr_bits != 32 && arr.addr_bits != 64))
+  if (arr.space > RD_SHARED || (arr.addr_bits != 32 && arr.addr_bits != 64) ||
+      arr.alias >= (1u << 24))
     return ERR_INVAL;
   if (a.kind > RD_ATOMIC) return ERR_INVAL;
   if (a.scope > RD_SCOPE_DEVICE) return ERR_INVAL;
@@ -1568,7 +1628,9 @@ uint32_t syn_flags(const rd_kernel_model& m, const rd_access& a) {
     if (a.rel.scope == RD_SCOPE_DEVICE) f |= kSynRelDev;
     if (m.arrays[a.rel.array].addr_bits == 32) f |= kSynRel32;
   }
-  if ((f & kSynAcq) && (f & kSynRel) && a.acq.array == a.rel.array) f |= kSynSameArr;
+  if ((f & kSynAcq) && (f & kSynRel) &&
+      memory_of(m, a.acq.array) == memory_of(m, a.rel.array))
+    f |= kSynSameArr;
   if (a.kind == RD_WRITE) f |= kSynWrite;
   if (a.kind == RD_READ) f |= kSynRead;
   return f;
@@ -1577,10 +1639,10 @@ uint32_t syn_flags(const rd_kernel_model& m, const rd_access& a) {
 // The array of an access's syn() at scope `dev` (0 block, 1 device), or -1
 // when it has none at any point: a lock needs one array for acquire and
 // release, so the array never depends on the point.
-int64_t syn_array(const rd_access& a, int dev) {
+int64_t syn_array(const rd_access& a, int dev, const rd_kernel_model& m) {
   const bool A = a.acq.addr.count && (!dev || a.acq.scope == RD_SCOPE_DEVICE);
   const bool R = a.rel.addr.count && (!dev || a.rel.scope == RD_SCOPE_DEVICE);
-  if (A && R && a.acq.array == a.rel.array) return a.acq.array;
+  if (A && R && memory_of(m, a.acq.array) == memory_of(m, a.rel.array)) return a.acq.array;
   if (a.kind == RD_WRITE && R) return a.rel.array;
   if (a.kind == RD_READ && A) return a.acq.array;
   return -1;
@@ -1595,10 +1657,13 @@ uint32_t pair_sync(const rd_kernel_model& m, const rd_access& x, const rd_access
   uint32_t f = 0;
   if (x.acq.addr.count || x.rel.addr.count || y.acq.addr.count || y.rel.addr.count)
     f |= kQSync;
-  const int64_t b0 = syn_array(x, 0), b1 = syn_array(y, 0);
-  if (b0 >= 0 && b0 == b1) f |= kQSyncBlk;
-  const int64_t d0 = syn_array(x, 1), d1 = syn_array(y, 1);
-  if (d0 >= 0 && d0 == d1 && m.arrays[d0].space == RD_GLOBAL) f |= kQSyncDev;
+  const int64_t b0 = syn_array(x, 0, m), b1 = syn_array(y, 0, m);
+  if (b0 >= 0 && b1 >= 0 && memory_of(m, (uint32_t)b0) == memory_of(m, (uint32_t)b1))
+    f |= kQSyncBlk;
+  const int64_t d0 = syn_array(x, 1, m), d1 = syn_array(y, 1, m);
+  if (d0 >= 0 && d1 >= 0 && memory_of(m, (uint32_t)d0) == memory_of(m, (uint32_t)d1) &&
+      m.arrays[d0].space == RD_GLOBAL)
+    f |= kQSyncDev;
   return f;
 }
 
@@ -1837,8 +1902,12 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     plan->persist_grid = per_cu * ctx->n_cu;
   }
 
+  // effective addresses of aliased views (validation stays on `models`)
+  ModelViews views;
+  build_views(models, n_models, views);
+  const rd_kernel_model* vmodels = views.m.data();
   Planner P;
-  P.models = models;
+  P.models = vmodels;
   P.launch = launch;
   P.params = params;
   P.dims.resize(n_models);
@@ -1877,7 +1946,10 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     const rd_access& A = M.acc[pr.a];
     const rd_access& B = M.acc[pr.b];
     uint32_t e = check_access(M, A) | check_access(M, B);
-    if (!(e & ERR_INVAL) && A.array != B.array) e |= ERR_INVAL;
+    // one memory: the same array, or two views of one aliased memory
+    if (!(e & ERR_INVAL) && A.array != B.array &&
+        memory_of(M, A.array) != memory_of(M, B.array))
+      e |= ERR_INVAL;
     if (!(e & ERR_INVAL)) e |= model_err[pr.model];
     if (e & ERR_INVAL) e = ERR_INVAL;
     q.host_err = e;
@@ -1923,7 +1995,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     if (nthreads > 1) {
       std::vector<Planner> sub(kGroups);
       for (Planner& G : sub) {
-        G.models = models;
+        G.models = vmodels;
         G.launch = launch;
         G.params = params;
         G.dims.resize(n_models);
@@ -1998,7 +2070,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         }
       }
       // bit 2: both accesses compute their address with the same expression
-      if (same_addr_expr(models[pr.model], pr.a, pr.b)) fl |= 4;
+      if (same_addr_expr(vmodels[pr.model], pr.a, pr.b)) fl |= 4;
       // bits 3, 4: synchronised pairs whose syn() can match (block, device)
       if (q.sync & kQSyncBlk) fl |= 8;
       if (q.sync & kQSyncDev) fl |= 16;

@@ -13,12 +13,15 @@ workload, next to this script):
                          [8,12) [12,16) [16,20) [20,24) [24,28.2] a fixed
                          number of queries drawn with seed 55, at least 50 in
                          the top band (2^24..2^28 points per access)
+  synced_6006.json.gz    every one of the 4000 pairs of the synchronised
+                         workload (mixed queries of 2^8..2^22 points under
+                         lock and producer/consumer patterns, seed 6006)
 
 Each file holds the workload's digest (sha256 of its JSON), the pair
 indices, and per pair: status, verdict, count, by_class[3], classes,
 witness_class, flags, witness[7], w_addr, evals.
 
-    python tests/golden/make_goldens.py [batched] [mixed] [--threads N]
+    python tests/golden/make_goldens.py [batched] [mixed] [synced] [--threads N]
 """
 import gzip
 import hashlib
@@ -118,7 +121,8 @@ def main():
     threads = os.cpu_count() or 1
     if "--threads" in args:
         threads = int(args[args.index("--threads") + 1])
-    what = [a for a in args if a in ("batched", "mixed")] or ["batched", "mixed"]
+    what = [a for a in args if a in ("batched", "mixed", "synced")] or [
+        "batched", "mixed", "synced"]
     if "batched" in what:
         wl = configs.batched(seed=2002)
         idx = list(range(len(wl.pairs)))
@@ -132,6 +136,12 @@ def main():
         write("mixed_5005_sample.json.gz", wl, idx, res, secs, threads,
               {"generator": "configs.mixed(seed=5005)", "sample_seed": 55,
                "bands": MIXED_BANDS})
+    if "synced" in what:
+        wl = configs.synced(seed=6006)
+        idx = list(range(len(wl.pairs)))
+        res, secs = run(wl, idx, threads)
+        write("synced_6006.json.gz", wl, idx, res, secs, threads,
+              {"generator": "configs.synced(seed=6006)"})
 
 
 if __name__ == "__main__":

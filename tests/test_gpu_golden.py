@@ -85,3 +85,19 @@ def test_mixed_sample(hg):
     res = hg.check_pairs(wl.compact(range(lo, hi)))
     _check([res[idx[k] - lo] for k in steps[s]], [gold["results"][k] for k in steps[s]],
            [idx[k] for k in steps[s]], "mixed step %d" % s)
+
+
+@pytest.mark.parametrize("path", ["lds", "fallback"])
+def test_synced_every_pair(hg, monkeypatch, path):
+    """All 4000 pairs of the synchronised workload against the oracle's
+    stored results, through the LDS joins (where they qualify) and all
+    through the HBM aggregation path."""
+    gold = G.load("synced_6006.json.gz")
+    wl = configs.synced(seed=6006)
+    assert G.digest(wl) == gold["digest"], "generator changed since the goldens were written"
+    if path == "fallback":
+        monkeypatch.setenv("HGRD_SYNC_FALLBACK", "1")
+    say("synced golden", len(wl.pairs), path)
+    got = hg.check_pairs(wl)
+    _check(got, gold["results"], gold["indices"], "synced " + path)
+    assert sum(r["verdict"] for r in got) > 100

@@ -38,6 +38,7 @@ def test_struct_sizes():
     assert C.sizeof(hg.rd_pair_result) == 88
     assert C.sizeof(hg.rd_insn) == 16
     assert C.sizeof(hg.rd_access) == 96
+    assert C.sizeof(hg.rd_array) == 24
     assert C.sizeof(hg.rd_sync) == 16
     assert C.sizeof(hg.rd_options) == 48
     assert C.sizeof(hg.rd_mlp) == 4 * 6337

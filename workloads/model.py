@@ -44,12 +44,19 @@ def _opt(e):
 
 
 class Array:
-    def __init__(self, space=GLOBAL, addr_bits=64):
+    """An array; arrays with the same nonzero ``alias`` are views of one
+    memory, element k of the view being element base + k of the memory."""
+
+    def __init__(self, space=GLOBAL, addr_bits=64, alias=0, base=0):
         assert space in SPACES and addr_bits in (32, 64)
         self.space, self.addr_bits = space, addr_bits
+        self.alias, self.base = int(alias), int(base)
 
     def to_json(self):
-        return {"space": self.space, "addr_bits": self.addr_bits}
+        j = {"space": self.space, "addr_bits": self.addr_bits}
+        if self.alias:
+            j["alias"], j["base"] = self.alias, self.base
+        return j
 
 
 class Loop:
@@ -147,7 +154,8 @@ class Model:
 
     @staticmethod
     def from_json(j):
-        arrays = [Array(a["space"], a["addr_bits"]) for a in j["arrays"]]
+        arrays = [Array(a["space"], a["addr_bits"], a.get("alias", 0), a.get("base", 0))
+                  for a in j["arrays"]]
         loops = [Loop(E.from_json(l["init"]), l["cmp"], E.from_json(l["bound"]),
                       l["upd"], E.from_json(l["step"])) for l in j["loops"]]
         accs = []
