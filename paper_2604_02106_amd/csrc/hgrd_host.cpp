@@ -2096,6 +2096,28 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
   auto npts_of = [&](int32_t idx) -> uint64_t {
     return idx < 0 ? 0 : P.dev_insts[idx].npts;
   };
+  // Dense items: every side (one for a self pair) has at least dense_min
+  // points per address of its proven range on average (per block for
+  // shared arrays); their buckets nearly all hold partners, so the address
+  // filter is not worth its read (HGRD_DENSE sets dense_min; 0 turns it
+  // off).  Counting points rather than threads measured better on the
+  // mixed workload (7 520 against 7 265 queries/s), though an access that
+  // meets only itself across iterations then skips a filter that would
+  // have dropped all its buckets.
+  double dense_min = 1.5;
+  if (const char* e = getenv("HGRD_DENSE")) dense_min = atof(e);
+  auto dense_item = [&](int32_t ia, int32_t ib, bool self, bool shared) -> bool {
+    if (dense_min <= 0) return false;
+    for (int32_t x : {ia, ib}) {
+      if (self && x == ib && ia == ib) continue;
+      if (!P.tabs[x].on) return false;
+      const double span = (double)P.arange[x].second - (double)P.arange[x].first + 1.0;
+      if (span < 1) return false;
+      const double pts = shared ? P.dev_insts[x].tpb : P.dev_insts[x].npts;
+      if (pts / span < dense_min) return false;
+    }
+    return true;
+  };
   // Bucket shift of an HBM item: blocks of 2^shift consecutive addresses
   // should hold about block_recs records, from the density (points per
   // address of the tabulated range; per block for shared arrays) of the
@@ -2305,6 +2327,7 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
         fastdiv_consts(P.dev_insts[ia].tpb, &hp.h.tpb_m[0], &hp.h.tpb_s[0]);
         fastdiv_consts(P.dev_insts[ib].tpb, &hp.h.tpb_m[1], &hp.h.tpb_s[1]);
         hp.R = tot;
+        hp.h.dense = dense_item(ia, ib, q.qd.self, q.qd.shared) ? 1u : 0u;
         hplans.push_back(hp);
       }
     }

@@ -193,7 +193,10 @@ struct HItem {
   uint32_t sync;  // 1: a pair with acquire/release (joined with the
                   //   synchronisation levels; never split, overflow to the
                   //   fallback)
-  uint32_t pad_[2];
+  uint32_t dense; // 1: both accesses put several points on an address on
+                  //   average: the address filter would pass nearly every
+                  //   bucket, so it passes them all without reading them
+  uint32_t pad_;
 };
 static_assert(sizeof(HItem) == 112, "HItem layout");
 // A run of buckets [b0, b1) of one HBM item, joined by one workgroup.

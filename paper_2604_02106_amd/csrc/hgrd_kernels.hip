@@ -610,10 +610,10 @@ k_bucket_filter(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
   const BRun R = runs[blockIdx.x];
   const HItem h = hitems[R.item];
   if (ovf[R.item] || done[h.q]) return;  // the join skips these runs too
-  // level 0 counted per address, or block 0 of identical blocks with the
-  // inter-block class (a record pairs with its copies in other blocks):
-  // always joined
-  if (h.shared == 3 || (h.gmult > 1 && (qd[h.q].mask & 1))) {
+  // level 0 counted per address, block 0 of identical blocks with the
+  // inter-block class (a record pairs with its copies in other blocks), or
+  // a dense item (its buckets nearly all pass): always joined
+  if (h.shared == 3 || h.dense || (h.gmult > 1 && (qd[h.q].mask & 1))) {
     for (uint32_t b = R.b0 + threadIdx.x; b < R.b1; b += kFilterThreads)
       cand[h.bucket0 + b] = 1;
     return;
