@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhgrd.so")
 SOURCES = ["hgrd_kernels.hip", "hgrd_verdict.hip", "hgrd_host.cpp", "hgrd_hostdom.cpp",
-           "hgrd_noalloc.cpp", "hgrd_body.cpp"]
+           "hgrd_noalloc.cpp", "hgrd_body.cpp", "hgrd_tools.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed fp32 instructions are kept out of all device code
 DEV_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

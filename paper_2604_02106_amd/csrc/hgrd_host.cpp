@@ -14,1690 +14,8 @@
 // aggregation instead.  The lexicographically smallest witness is found in
 // two passes: the smallest p with a partner comes out of the joins, then
 // one pass over the other access finds the smallest partner q.
-#include "../../include/hgrd.h"
-#include "hgrd_internal.h"
-#include "hgrd_launch.h"
-#include "hgrd_hostops.h"
+#include "hgrd_lower.h"
 
-#include <algorithm>
-#include <array>
-#include <chrono>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <atomic>
-#include <map>
-#include <memory>
-#include <thread>
-#include <string>
-#include <vector>
-
-using namespace hgrd;
-using u64 = unsigned long long;
-
-namespace {
-
-constexpr uint32_t kMaxInsns = 256;
-constexpr uint32_t kMaxDepth = 16;
-constexpr uint32_t kMaxLoopsPerAccess = 4;
-constexpr uint32_t kMaxIters = 65536;
-constexpr uint32_t kMaxSets = 4096;
-constexpr int64_t kMaxBlock = 1024;
-constexpr int64_t kMaxGrid = 1ll << 26;
-constexpr int64_t kMaxPoints = 1ll << 31;
-constexpr uint32_t kChunkPts = 1024;
-constexpr uint32_t kL0ChunkPts = 8192;  // points per level-0 and fallback
-                                        // generation workgroup
-constexpr uint64_t kWaveBytes = 3072ull << 20;  // bucket bytes per partition wave
-constexpr uint64_t kFallbackRecords = 256ull << 20;
-constexpr uint64_t kMaxTabInst = 1ull << 24;  // table entries per instance
-constexpr uint64_t kMaxTabPool = 1ull << 33;  // table entries per plan (64 GiB)
-constexpr uint64_t kL0Slots = 1ull << 29;     // address-count slots per split batch
-constexpr uint64_t kRetryBytes = 16ull << 30;  // bucket bytes of one retried item
-
-bool is_leaf(uint16_t op) { return op >= RD_OP_CONST && op <= RD_OP_LOOP; }
-bool is_binary(uint16_t op) { return op >= RD_OP_ADD && op <= RD_OP_LOR; }
-bool is_unary(uint16_t op) { return op == RD_OP_NEG || op == RD_OP_LNOT; }
-
-// where leaves may appear
-enum Ctx { CTX_LAUNCH = 0, CTX_LOOP = 1, CTX_IV = 2, CTX_POINT = 3 };
-
-int loop_pos(const rd_access* a, uint32_t loop) {
-  if (!a) return -1;
-  for (uint32_t i = 0; i < a->n_loops && i < 8; ++i)
-    if (a->loops[i] == loop) return (int)i;
-  return -1;
-}
-
-// Structural check: ERR_INVAL for malformed, ERR_UNSUP for over-limit.
-uint32_t check_expr(const rd_kernel_model& m, rd_expr e, int ctx,
-                    const rd_access* a) {
-  if (e.count == 0) return 0;
-  if ((uint64_t)e.first + e.count > m.n_insns || !m.insns) return ERR_INVAL;
-  uint32_t depth = 0, maxd = 0;
-  for (uint32_t k = 0; k < e.count; ++k) {
-    const rd_insn& t = m.insns[e.first + k];
-    if (is_leaf(t.op)) {
-      switch (t.op) {
-        case RD_OP_CONST: break;
-        case RD_OP_PARAM:
-          if (t.arg >= m.n_params) return ERR_INVAL;
-          break;
-        case RD_OP_BDIM:
-        case RD_OP_GDIM:
-          if (ctx < CTX_LOOP || t.arg > 2) return ERR_INVAL;
-          break;
-        case RD_OP_TID:
-        case RD_OP_BID:
-          if (ctx < CTX_POINT || t.arg > 2) return ERR_INVAL;
-          break;
-        case RD_OP_LOOP:
-          if (ctx < CTX_IV || loop_pos(a, t.arg) < 0) return ERR_INVAL;
-          break;
-      }
-      ++depth;
-    } else if (is_unary(t.op)) {
-      if (depth < 1) return ERR_INVAL;
-    } else if (is_binary(t.op)) {
-      if (depth < 2) return ERR_INVAL;
-      --depth;
-    } else {
-      return ERR_INVAL;
-    }
-    maxd = std::max(maxd, depth);
-  }
-  if (depth != 1) return ERR_INVAL;
-  if (e.count > kMaxInsns || maxd > kMaxDepth) return ERR_UNSUP;
-  return 0;
-}
-
-uint32_t syn_flags(const rd_kernel_model& m, const rd_access& a);
-
-// The memory an array belongs to: its own (the array index) or the memory
-// its alias id names, shared by every view with that id and space.
-int64_t memory_of(const rd_kernel_model& m, uint32_t array) {
-  const rd_array& a = m.arrays[array];
-  if (!a.alias) return array;
-  return ((int64_t)1 << 40) | ((int64_t)a.space << 32) | a.alias;
-}
-
-// Models with the effective addresses of aliased views: an access address
-// (or an acquire's or release's) on a view with a nonzero base becomes
-// base + address, appended to a copy of the model's instruction pool.  The
-// base is an immediate operand, so the device program takes no extra
-// register.  Expressions are validated on the caller's models.
-struct ModelViews {
-  std::vector<std::vector<rd_insn>> insns;
-  std::vector<std::vector<rd_access>> acc;
-  std::vector<rd_kernel_model> m;
-};
-void build_views(const rd_kernel_model* models, uint32_t n, ModelViews& V) {
-  V.m.assign(models, models + n);
-  V.insns.resize(n);
-  V.acc.resize(n);
-  for (uint32_t i = 0; i < n; ++i) {
-    const rd_kernel_model& M = models[i];
-    bool any = false;
-    for (uint32_t k = 0; M.arrays && k < M.n_arrays; ++k)
-      any |= M.arrays[k].alias != 0 && M.arrays[k].base != 0;
-    if (!any || (M.n_acc && !M.acc) || (M.n_insns && !M.insns)) continue;
-    V.insns[i].assign(M.insns, M.insns + M.n_insns);
-    V.acc[i].assign(M.acc, M.acc + M.n_acc);
-    auto shift = [&](rd_expr& e, uint32_t arr) {
-      if (arr >= M.n_arrays || e.count == 0 || (uint64_t)e.first + e.count > M.n_insns) return;
-      const rd_array& A = M.arrays[arr];
-      if (!A.alias || !A.base) return;
-      std::vector<rd_insn>& P = V.insns[i];
-      const uint32_t first = (uint32_t)P.size();
-      P.insert(P.end(), M.insns + e.first, M.insns + e.first + e.count);
-      rd_insn c, add;
-      memset(&c, 0, sizeof c);
-      memset(&add, 0, sizeof add);
-      c.op = RD_OP_CONST;
-      c.imm = A.base;
-      add.op = RD_OP_ADD;
-      P.push_back(c);
-      P.push_back(add);
-      e.first = first;
-      e.count += 2;
-    };
-    for (rd_access& A : V.acc[i]) {
-      shift(A.addr, A.array);
-      shift(A.acq.addr, A.acq.array);
-      shift(A.rel.addr, A.rel.array);
-    }
-    V.m[i].insns = V.insns[i].data();
-    V.m[i].n_insns = (uint32_t)V.insns[i].size();
-    V.m[i].acc = V.acc[i].data();
-  }
-}
-
-uint32_t check_access(const rd_kernel_model& m, const rd_access& a) {
-  if (a.array >= m.n_arrays || !m.arrays) return ERR_INVAL;
-  const rd_array& arr = m.arrays[a.array];
-  if (arr.space > RD_SHARED || (arr.addr_bits != 32 && arr.addr_bits != 64) ||
-      arr.alias >= (1u << 24))
-    return ERR_INVAL;
-  if (a.kind > RD_ATOMIC) return ERR_INVAL;
-  if (a.scope > RD_SCOPE_DEVICE) return ERR_INVAL;
-  if (a.n_loops > kMaxLoopsPerAccess) {
-    return ERR_UNSUP;
-  }
-  for (uint32_t i = 0; i < a.n_loops; ++i) {
-    if (a.loops[i] >= m.n_loops || !m.loops) return ERR_INVAL;
-    for (uint32_t j = 0; j < i; ++j)
-      if (a.loops[j] == a.loops[i]) return ERR_INVAL;
-  }
-  if (a.addr.count == 0) return ERR_INVAL;
-  for (const rd_sync* y : {&a.acq, &a.rel}) {
-    if (y->addr.count == 0) continue;
-    if (y->array >= m.n_arrays || y->scope > RD_SCOPE_DEVICE) return ERR_INVAL;
-  }
-  uint32_t err = check_expr(m, a.acq.addr, CTX_POINT, &a) |
-                 check_expr(m, a.rel.addr, CTX_POINT, &a) |
-                 check_expr(m, a.addr, CTX_POINT, &a) |
-                 check_expr(m, a.guard, CTX_POINT, &a) |
-                 check_expr(m, a.bint, CTX_IV, &a) |
-                 check_expr(m, a.wint, CTX_IV, &a);
-  for (uint32_t i = 0; i < a.n_loops; ++i) {
-    const rd_loop& l = m.loops[a.loops[i]];
-    if (!l.init.count || !l.bound.count || !l.step.count) return ERR_INVAL;
-    if (l.cmp > RD_CMP_NE || l.upd > RD_UPD_SHR) return ERR_INVAL;
-    err |= check_expr(m, l.init, CTX_LOOP, &a) |
-           check_expr(m, l.bound, CTX_LOOP, &a) |
-           check_expr(m, l.step, CTX_LOOP, &a);
-  }
-  return (err & ERR_INVAL) ? ERR_INVAL : err;
-}
-
-// Host evaluation of a uniform expression.  dims = {gx, gy, gz, bx, by, bz}.
-int64_t heval(const rd_kernel_model& m, rd_expr e, const int64_t* params,
-              const int64_t* dims, int64_t dflt, uint32_t& err) {
-  if (e.count == 0) return dflt;
-  int64_t st[kMaxDepth + 1];
-  int sp = 0;
-  for (uint32_t k = 0; k < e.count; ++k) {
-    const rd_insn& t = m.insns[e.first + k];
-    switch (t.op) {
-      case RD_OP_CONST: st[sp++] = t.imm; break;
-      case RD_OP_PARAM: st[sp++] = params[t.arg]; break;
-      case RD_OP_GDIM: st[sp++] = dims ? dims[t.arg] : 0; break;
-      case RD_OP_BDIM: st[sp++] = dims ? dims[3 + t.arg] : 0; break;
-      case RD_OP_NEG:
-        if (st[sp - 1] == INT64_MIN) { err |= ERR_RANGE; st[sp - 1] = 0; }
-        else st[sp - 1] = -st[sp - 1];
-        break;
-      case RD_OP_LNOT: st[sp - 1] = st[sp - 1] == 0; break;
-      default: {
-        int64_t b = st[--sp];
-        st[sp - 1] = hop(t.op, st[sp - 1], b, err);
-      }
-    }
-  }
-  return st[0];
-}
-
-// Compiles a postfix expression to device three-address code.
-// Leaves stay operand descriptors; only intermediate values take a stack
-// register, so the register index of a value is its stack position.
-Prog compile(const rd_kernel_model& m, rd_expr e, const rd_access& a,
-             std::vector<DInsn>& pool) {
-  Prog p;
-  memset(&p, 0, sizeof p);
-  if (e.count == 0) {
-    p.absent = 1;
-    return p;
-  }
-  p.off = (uint32_t)pool.size();
-  struct Opnd {
-    uint8_t mode;
-    uint16_t idx;
-    int64_t imm;
-  };
-  std::vector<Opnd> st;
-  auto emit = [&](uint8_t op, uint8_t dst, Opnd x, Opnd y) {
-    DInsn in;
-    in.op = op;
-    in.dst = dst;
-    in.ma = x.mode;
-    in.mb = y.mode;
-    in.a = x.idx;
-    in.b = y.idx;
-    in.imm = x.mode == M_IMM ? x.imm : y.imm;
-    pool.push_back(in);
-  };
-  static const uint8_t kBin[] = {D_ADD, D_SUB, D_MUL, D_DIV, D_MOD, D_SHL,
-                                 D_SHR, D_AND, D_OR,  D_XOR, D_MIN, D_MAX,
-                                 D_LT,  D_LE,  D_EQ,  D_NE,  D_GE,  D_GT,
-                                 D_LAND, D_LOR};
-  const uint16_t np = (uint16_t)m.n_params;
-  for (uint32_t k = 0; k < e.count; ++k) {
-    const rd_insn& t = m.insns[e.first + k];
-    switch (t.op) {
-      case RD_OP_CONST: st.push_back({M_IMM, 0, t.imm}); break;
-      case RD_OP_PARAM: st.push_back({M_PARAM, t.arg, 0}); break;
-      case RD_OP_GDIM: st.push_back({M_PARAM, (uint16_t)(np + t.arg), 0}); break;
-      case RD_OP_BDIM: st.push_back({M_PARAM, (uint16_t)(np + 3 + t.arg), 0}); break;
-      case RD_OP_TID: st.push_back({M_COORD, (uint16_t)(kCoordTid + t.arg), 0}); break;
-      case RD_OP_BID: st.push_back({M_COORD, (uint16_t)(kCoordBid + t.arg), 0}); break;
-      case RD_OP_LOOP:
-        st.push_back({M_COORD, (uint16_t)(kCoordLoop + loop_pos(&a, t.arg)), 0});
-        break;
-      case RD_OP_NEG:
-      case RD_OP_LNOT: {
-        Opnd x = st.back();
-        st.pop_back();
-        uint8_t d = (uint8_t)st.size();
-        emit(t.op == RD_OP_NEG ? D_NEG : D_LNOT, d, x, {M_IMM, 0, x.imm});
-        st.push_back({M_REG, d, 0});
-        break;
-      }
-      default: {
-        Opnd y = st.back();
-        st.pop_back();
-        Opnd x = st.back();
-        st.pop_back();
-        uint8_t d = (uint8_t)st.size();
-        if (x.mode == M_IMM && y.mode == M_IMM) {
-          emit(D_MOV, d, x, x);
-          x = {M_REG, d, 0};
-        }
-        emit(kBin[t.op - RD_OP_ADD], d, x, y);
-        st.push_back({M_REG, d, 0});
-      }
-    }
-  }
-  Opnd r = st.back();
-  if (r.mode != M_REG) {
-    emit(D_MOV, 0, r, r);
-    p.res = 0;
-  } else {
-    p.res = (uint8_t)r.idx;
-  }
-  p.n = (uint16_t)(pool.size() - p.off);
-  return p;
-}
-
-// Host interpreter of compiled programs (same semantics as the device's).
-static int64_t host_prog(const std::vector<DInsn>& code, const Prog& p,
-                         const int64_t* coords, const int64_t* params,
-                         int64_t dflt, uint32_t& err) {
-  static const uint16_t kOp[] = {0, RD_OP_ADD, RD_OP_SUB, RD_OP_MUL, RD_OP_DIV,
-                                 RD_OP_MOD, RD_OP_SHL, RD_OP_SHR, RD_OP_AND,
-                                 RD_OP_OR, RD_OP_XOR, RD_OP_MIN, RD_OP_MAX,
-                                 RD_OP_LT, RD_OP_LE, RD_OP_EQ, RD_OP_NE,
-                                 RD_OP_GE, RD_OP_GT, RD_OP_LAND, RD_OP_LOR};
-  if (p.absent) return dflt;
-  int64_t st[kMaxStack];
-  for (uint32_t k = 0; k < p.n; ++k) {
-    const DInsn& in = code[p.off + k];
-    auto opnd = [&](uint8_t mode, uint16_t i) -> int64_t {
-      return mode == M_REG ? st[i] : mode == M_IMM ? in.imm
-             : mode == M_PARAM ? params[i] : coords[i];
-    };
-    const int64_t a = opnd(in.ma, in.a), b = opnd(in.mb, in.b);
-    int64_t r;
-    if (in.op == D_MOV) r = a;
-    else if (in.op == D_NEG) r = hop(RD_OP_SUB, 0, a, err);
-    else if (in.op == D_LNOT) r = a == 0;
-    else r = hop(kOp[in.op], a, b, err);
-    st[in.dst] = r;
-  }
-  return st[p.res];
-}
-
-static void host_coords(const AccInst& I, const std::vector<int64_t>& loops,
-                        uint32_t blin, uint32_t tlin, uint32_t ilin, int64_t* c) {
-  c[0] = tlin % I.dims[3];
-  c[1] = (tlin / I.dims[3]) % I.dims[4];
-  c[2] = tlin / (I.dims[3] * I.dims[4]);
-  c[3] = blin % I.dims[0];
-  c[4] = (blin / I.dims[0]) % I.dims[1];
-  c[5] = blin / (I.dims[0] * I.dims[1]);
-  c[6] = c[7] = c[8] = c[9] = 0;
-  uint32_t rem = ilin;
-  for (int k = (int)I.n_loops - 1; k >= 0; --k) {
-    c[6 + k] = loops[I.loop_off[k] + rem % I.loop_n[k]];
-    rem /= I.loop_n[k];
-  }
-}
-
-bool cmp_holds(uint32_t cmp, int64_t v, int64_t bound) {
-  switch (cmp) {
-    case RD_CMP_LT: return v < bound;
-    case RD_CMP_LE: return v <= bound;
-    case RD_CMP_GT: return v > bound;
-    case RD_CMP_GE: return v >= bound;
-    default: return v != bound;
-  }
-}
-
-const uint16_t kUpdOp[] = {RD_OP_ADD, RD_OP_SUB, RD_OP_MUL, RD_OP_DIV,
-                           RD_OP_SHL, RD_OP_SHR};
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-  bool own = true;  // false: carved from a caller's arena, never freed here
-};
-
-// Caller-provided device memory handed out front to back (256-byte
-// aligned).  Nothing is ever returned to it during a call; the caller
-// resets `used` between calls.
-struct Arena {
-  unsigned char* base = nullptr;
-  size_t cap = 0, used = 0;
-};
-
-// A named buffer of at least `bytes` from the arena: the one already
-// carved under that name when it is large enough, else a new piece.
-// RD_ECAPACITY (with a message naming the buffer) when the arena is full.
-void* arena_buf(Arena& A, DevBuf& b, const char* name, size_t bytes, int* err) {
-  if (bytes == 0) bytes = 256;
-  if (b.p && b.cap >= bytes) return b.p;
-  const size_t at = (A.used + 255) & ~(size_t)255;
-  if (at > A.cap || bytes > A.cap - at) {
-    fprintf(stderr,
-            "hgrd: the fixed scratch area (%zu bytes) cannot hold '%s' (%zu bytes, "
-            "%zu already in use)\n", A.cap, name, bytes, at);
-    if (!*err) *err = RD_ECAPACITY;
-    return nullptr;
-  }
-  b.p = A.base + at;
-  b.cap = bytes;
-  b.own = false;
-  A.used = at + bytes;
-  return b.p;
-}
-
-uint64_t next_prime(uint64_t n) {
-  if (n <= 2) return 2;
-  for (uint64_t c = n | 1;; c += 2) {
-    bool prime = true;
-    for (uint64_t d = 3; d * d <= c; d += 2)
-      if (c % d == 0) {
-        prime = false;
-        break;
-      }
-    if (prime) return c;
-  }
-}
-
-// Bucket map of an HBM item whose instances have term tables: the dense key
-// ((addr - lo) >> shift) + blin * kb modulo a prime bucket count (mode 1),
-// when the key stays below 2^32; else the hash (mode 0).  per_block: keys
-// carry the block (shared arrays, split items).
-void set_bucket_map(HItem& h, const std::vector<uint8_t>& tab_on,
-                    const std::vector<std::pair<int64_t, int64_t>>& arange,
-                    uint32_t nblk, bool self, bool per_block, uint64_t R,
-                    uint32_t cap, double load) {
-  h.mode = 0;
-  h.kb = 0;
-  h.lo = 0;
-  h.fm = 0;
-  __int128 lo = 0, hi = -1;
-  bool first = true;
-  (void)self;  // a self pair names its one instance twice
-  for (uint32_t x : {h.inst_i, h.inst_j}) {
-    if (!tab_on[x]) return;
-    const auto& r = arange[x];
-    if (first || r.first < lo) lo = r.first;
-    if (first || r.second > hi) hi = r.second;
-    first = false;
-  }
-  if (hi < lo || hi - lo >= ((__int128)1 << 62)) return;
-  const __int128 kr = ((hi - lo) >> h.shift) + 1;
-  const __int128 kmax = per_block ? kr * nblk : kr;
-  if (kmax >= ((__int128)1 << 32)) return;
-  uint64_t nb = (uint64_t)((double)R / (cap * load)) + 1;
-  nb = nb <= 1 ? 1 : next_prime(nb);
-  if (nb >= (1ull << 31)) return;
-  h.mode = 1;
-  h.lo = (long long)lo;
-  h.kb = per_block ? (uint32_t)kr : 0;
-  h.nbuckets = (uint32_t)nb;
-  h.fm = ~0ull / nb + 1;
-}
-
-double now_ms() {
-  return std::chrono::duration<double, std::milli>(
-             std::chrono::steady_clock::now().time_since_epoch())
-      .count();
-}
-
-}  // namespace
-
-// ---------------------------------------------------------------------------
-
-struct rd_context {
-  int device = 0;
-  std::map<std::string, DevBuf> bufs;
-  // While set (rd_check_pairs_noalloc), every device buffer of the context
-  // and of its plans is carved from this arena instead of hipMalloc;
-  // abufs names the arena's buffers and is emptied when the arena is unset.
-  Arena* arena = nullptr;
-  std::map<std::string, DevBuf> abufs;
-  // Partition scratch (bucket records, bucket cursors, filter marks) that
-  // every plan of the context shares: plans run one at a time on a
-  // context, so one buffer serves them all.  A buffer that must grow is
-  // retired, not freed, while plans (and their captured graphs) may still
-  // hold its address; retired buffers go with the context.
-  std::map<std::string, DevBuf> shared;
-  std::vector<void*> retired;
-  void* shared_buf(const char* name, size_t bytes, int* err) {
-    DevBuf& b = shared[name];
-    if (bytes == 0) bytes = 256;
-    if (b.cap >= bytes) return b.p;
-    if (b.p) retired.push_back(b.p);
-    b.p = nullptr;
-    b.cap = 0;
-    if (hipMalloc(&b.p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      fprintf(stderr, "hgrd: device allocation of %zu bytes for '%s' failed\n", bytes, name);
-      b.p = nullptr;
-      *err = RD_ENOMEM;
-      return nullptr;
-    }
-    b.cap = bytes;
-    return b.p;
-  }
-  rd_stats stats;
-  int cfg = 0;  // LDS tile shape: 1024 records, 2048 slots (rd_autotune may change it)
-  uint32_t n_cu = 256;
-  uint64_t wave_bytes = kWaveBytes;  // default partition wave size
-  hipStream_t stream = nullptr;  // used when the caller passes no stream
-  hipEvent_t ev[16];
-  std::vector<hipEvent_t> wev;    // per-wave timing events
-  void* ensure(const char* name, size_t bytes, int* err) {
-    if (arena) return arena_buf(*arena, abufs[name], name, bytes, err);
-    DevBuf& b = bufs[name];
-    if (bytes == 0) bytes = 256;
-    if (b.cap < bytes) {
-      if (b.p) (void)hipFree(b.p);
-      b.p = nullptr;
-      size_t want = std::max(bytes, b.cap + b.cap / 2);
-      if (hipMalloc(&b.p, want) != hipSuccess) {
-        b.cap = 0;
-        if (hipMalloc(&b.p, bytes) != hipSuccess) {
-          (void)hipGetLastError();
-          fprintf(stderr, "hgrd: device allocation of %zu bytes for '%s' failed\n", bytes,
-                  name);
-          b.p = nullptr;
-          *err = RD_ENOMEM;
-          return nullptr;
-        }
-        want = bytes;
-      }
-      b.cap = want;
-    }
-    return b.p;
-  }
-};
-
-namespace {
-
-// Per (model, tuple): launch extents.
-// ---------------------------------------------------------------------------
-// Term tables (lowering of one access under one tuple).
-//
-// An expression qualifies when interval bounds over the launch box prove
-// that no operation in it can fail (overflow, zero divisor, shift count,
-// INT64_MIN / -1), so the interpreter would never flag an error for it.
-// It is then rewritten, in exact integer arithmetic, as a uniform constant
-// plus a sum of terms that each depend on one coordinate group only (block
-// ids, thread ids or loop values): sums and differences split, products
-// and left shifts by uniform values distribute, and a truncating division
-// or remainder by a positive uniform d splits when every term but those of
-// one group is a multiple of d and both parts are non-negative.  Each
-// group's terms are tabulated over the group's linear index.
-
-using i128 = __int128;
-constexpr i128 kI64Lo = INT64_MIN, kI64Hi = INT64_MAX;
-
-struct TNode {
-  uint16_t op = 0, arg = 0;
-  int64_t imm = 0;
-  int kid[2] = {-1, -1};
-  uint32_t start = 0;   // first postfix index of the subtree
-  uint8_t groups = 0;   // bit 0 blocks, bit 1 threads, bit 2 loop values
-  int64_t val = 0;      // value of a uniform node
-  i128 lo = 0, hi = 0;  // value range over the box
-  uint64_t g = 1;       // every value of the node is a multiple of g (0: always 0)
-};
-
-inline uint64_t gcd64(uint64_t a, uint64_t b) {
-  while (b) {
-    const uint64_t t = a % b;
-    a = b;
-    b = t;
-  }
-  return a;
-}
-inline uint64_t uabs64(int64_t v) { return v < 0 ? 0 - (uint64_t)v : (uint64_t)v; }
-// product of two divisors, 1 (always a divisor) when it does not fit
-inline uint64_t gmul(uint64_t a, uint64_t b) {
-  const unsigned __int128 p = (unsigned __int128)a * b;
-  return p >> 62 ? 1 : (uint64_t)p;
-}
-
-inline bool fits64(i128 v) { return v >= kI64Lo && v <= kI64Hi; }
-inline i128 i128abs(i128 v) { return v < 0 ? -v : v; }
-
-// Range of `op` over operand ranges; false if the operation may fail.
-bool range_op(uint16_t op, i128 al, i128 ah, i128 bl, i128 bh, i128& lo, i128& hi) {
-  auto corners = [&](i128 c0, i128 c1, i128 c2, i128 c3) {
-    lo = std::min(std::min(c0, c1), std::min(c2, c3));
-    hi = std::max(std::max(c0, c1), std::max(c2, c3));
-  };
-  switch (op) {
-    case RD_OP_ADD: lo = al + bl; hi = ah + bh; return fits64(lo) && fits64(hi);
-    case RD_OP_SUB: lo = al - bh; hi = ah - bl; return fits64(lo) && fits64(hi);
-    case RD_OP_MUL:
-      corners(al * bl, al * bh, ah * bl, ah * bh);
-      return fits64(lo) && fits64(hi);
-    case RD_OP_DIV:
-      if (bl <= 0 && bh >= 0) return false;
-      if (al == kI64Lo && bl <= -1 && bh >= -1) return false;
-      corners(al / bl, al / bh, ah / bl, ah / bh);
-      return true;
-    case RD_OP_MOD: {
-      if (bl <= 0 && bh >= 0) return false;
-      if (al == kI64Lo && bl <= -1 && bh >= -1) return false;
-      const i128 m = std::max(i128abs(bl), i128abs(bh)) - 1;
-      lo = al >= 0 ? 0 : std::max(al, -m);
-      hi = ah <= 0 ? 0 : std::min(ah, m);
-      return true;
-    }
-    case RD_OP_SHL:
-      if (bl < 0 || bh > 63) return false;
-      corners(al * ((i128)1 << (int)bl), al * ((i128)1 << (int)bh),
-              ah * ((i128)1 << (int)bl), ah * ((i128)1 << (int)bh));
-      return fits64(lo) && fits64(hi);
-    case RD_OP_SHR:
-      if (bl < 0 || bh > 63) return false;
-      corners(al >> (int)bl, al >> (int)bh, ah >> (int)bl, ah >> (int)bh);
-      return true;
-    case RD_OP_AND:
-    case RD_OP_OR:
-    case RD_OP_XOR:
-      if (al >= 0 && bl >= 0) {
-        i128 m = std::max(ah, bh), p = 1;
-        while (p <= m) p <<= 1;
-        lo = 0;
-        hi = op == RD_OP_AND ? std::min(ah, bh) : p - 1;
-      } else {
-        lo = kI64Lo;
-        hi = kI64Hi;
-      }
-      return true;
-    case RD_OP_MIN: lo = std::min(al, bl); hi = std::min(ah, bh); return true;
-    case RD_OP_MAX: lo = std::max(al, bl); hi = std::max(ah, bh); return true;
-    default: lo = 0; hi = 1; return true;  // comparisons and logic
-  }
-}
-
-// One term: value of `code` (in [lo, hi]) times `mult`, of group `group`.
-struct STerm {
-  std::vector<rd_insn> code;
-  int64_t mult = 1;
-  i128 lo = 0, hi = 0;
-  int group = 0;
-  uint64_t g = 1;  // every value of `code` is a multiple of g
-};
-
-struct Lin {
-  i128 u = 0;
-  std::vector<STerm> terms;
-};
-
-inline i128 contrib_lo(const STerm& t) { return std::min(t.lo * t.mult, t.hi * t.mult); }
-inline i128 contrib_hi(const STerm& t) { return std::max(t.lo * t.mult, t.hi * t.mult); }
-inline i128 contrib_abs(const STerm& t) {
-  return std::max(i128abs(t.lo), i128abs(t.hi)) * i128abs((i128)t.mult);
-}
-
-inline rd_insn mk_insn(uint16_t op, int64_t imm = 0, uint16_t arg = 0) {
-  rd_insn t;
-  memset(&t, 0, sizeof t);
-  t.op = op;
-  t.arg = arg;
-  t.imm = imm;
-  return t;
-}
-
-struct TermBuilder {
-  const rd_kernel_model& M;
-  const rd_access& A;
-  const int64_t* pv;
-  const int64_t* dims;
-  const int64_t* lmin;
-  const int64_t* lmax;
-  const uint64_t* lgcd;  // per loop position: gcd of its values
-  std::vector<TNode> nodes;
-  const rd_insn* ins = nullptr;
-
-  // Builds the tree of `e` with groups, uniform values and ranges; false if
-  // some operation may fail anywhere in the box.
-  bool build(rd_expr e) {
-    nodes.clear();
-    ins = M.insns + e.first;
-    std::vector<int> st;
-    for (uint32_t k = 0; k < e.count; ++k) {
-      const rd_insn& t = ins[k];
-      TNode n;
-      n.op = t.op;
-      n.arg = t.arg;
-      n.imm = t.imm;
-      n.start = k;
-      if (is_leaf(t.op)) {
-        switch (t.op) {
-          case RD_OP_CONST: n.val = t.imm; break;
-          case RD_OP_PARAM: n.val = pv[t.arg]; break;
-          case RD_OP_GDIM: n.val = dims[t.arg]; break;
-          case RD_OP_BDIM: n.val = dims[3 + t.arg]; break;
-          case RD_OP_TID: n.groups = 2; n.lo = 0; n.hi = dims[3 + t.arg] - 1; break;
-          case RD_OP_BID: n.groups = 1; n.lo = 0; n.hi = dims[t.arg] - 1; break;
-          case RD_OP_LOOP: {
-            const int p = loop_pos(&A, t.arg);
-            n.groups = 4;
-            n.lo = lmin[p];
-            n.hi = lmax[p];
-            n.g = lgcd[p];
-            break;
-          }
-        }
-        if (n.groups == 0) {
-          n.lo = n.hi = n.val;
-          n.g = uabs64(n.val);
-        }
-      } else if (is_unary(t.op)) {
-        const TNode& c = nodes[st.back()];
-        n.kid[0] = st.back();
-        st.pop_back();
-        n.start = c.start;
-        n.groups = c.groups;
-        if (t.op == RD_OP_NEG) {
-          if (c.lo == kI64Lo) return false;
-          n.lo = -c.hi;
-          n.hi = -c.lo;
-        } else {
-          n.lo = 0;
-          n.hi = 1;
-        }
-        n.g = t.op == RD_OP_NEG ? c.g : 1;
-        if (!n.groups) {
-          n.val = t.op == RD_OP_NEG ? -c.val : (c.val == 0);
-          n.lo = n.hi = n.val;
-          n.g = uabs64(n.val);
-        }
-      } else {
-        n.kid[1] = st.back();
-        st.pop_back();
-        n.kid[0] = st.back();
-        st.pop_back();
-        const TNode& a = nodes[n.kid[0]];
-        const TNode& b = nodes[n.kid[1]];
-        n.start = a.start;
-        n.groups = a.groups | b.groups;
-        if (!n.groups) {
-          uint32_t err = 0;
-          n.val = hop(t.op, a.val, b.val, err);
-          if (err) return false;
-          n.lo = n.hi = n.val;
-          n.g = uabs64(n.val);
-        } else {
-          if (!range_op(t.op, a.lo, a.hi, b.lo, b.hi, n.lo, n.hi)) return false;
-          switch (t.op) {
-            case RD_OP_ADD:
-            case RD_OP_SUB:
-            case RD_OP_MIN:
-            case RD_OP_MAX: n.g = gcd64(a.g, b.g); break;
-            case RD_OP_MUL: n.g = gmul(a.g, b.g); break;
-            case RD_OP_SHL:
-              n.g = b.groups ? 1 : gmul(a.g, 1ull << (b.val & 63));
-              break;
-            default: n.g = 1;
-          }
-        }
-      }
-      st.push_back((int)nodes.size());
-      nodes.push_back(n);
-    }
-    return true;
-  }
-
-  void subtree(int i, std::vector<rd_insn>& out) const {
-    const TNode& n = nodes[i];
-    uint32_t end = (uint32_t)i;  // node index == its postfix position
-    for (uint32_t k = n.start; k <= end; ++k) out.push_back(ins[k]);
-  }
-
-  static bool single(uint8_t g) { return g == 1 || g == 2 || g == 4; }
-  static int gidx(uint8_t g) { return g == 1 ? 0 : g == 2 ? 1 : 2; }
-
-  bool add_term(Lin& L, std::vector<rd_insn>&& code, i128 lo, i128 hi, int group, i128 mu,
-                uint64_t g = 1) {
-    if (!fits64(mu)) return false;
-    if (mu == 0) return true;
-    STerm t;
-    t.code = std::move(code);
-    t.mult = (int64_t)mu;
-    t.lo = lo;
-    t.hi = hi;
-    t.group = group;
-    t.g = g;
-    if (!fits64(contrib_abs(t))) return false;
-    L.terms.push_back(std::move(t));
-    return true;
-  }
-
-  // Postfix of sum(term * mult) + u over `ts` (at least one term or u).
-  static void emit_sum(const std::vector<const STerm*>& ts, i128 u, std::vector<rd_insn>& out) {
-    bool first = true;
-    for (const STerm* t : ts) {
-      out.insert(out.end(), t->code.begin(), t->code.end());
-      if (t->mult != 1) {
-        out.push_back(mk_insn(RD_OP_CONST, t->mult));
-        out.push_back(mk_insn(RD_OP_MUL));
-      }
-      if (!first) out.push_back(mk_insn(RD_OP_ADD));
-      first = false;
-    }
-    if (u != 0 || first) {
-      out.push_back(mk_insn(RD_OP_CONST, (int64_t)u));
-      if (!first) out.push_back(mk_insn(RD_OP_ADD));
-    }
-  }
-
-  // Affine form of the tree below node i, times mu: adds mu times each
-  // coordinate's coefficient to c (tx ty tz bx by bz) and cl (loop
-  // positions); constant parts are left out.  False when some operation is
-  // not affine in the coordinates (a product of two non-constant values,
-  // division, remainder, min, max, comparisons, ...).
-  bool affine(int i, i128 mu, i128* c, i128* cl) const {
-    const TNode& n = nodes[i];
-    if (!n.groups) return true;
-    if (i128abs(mu) > ((i128)1 << 62)) return false;
-    switch (n.op) {
-      case RD_OP_TID: if (n.arg > 2) return false; c[n.arg] += mu; return true;
-      case RD_OP_BID: if (n.arg > 2) return false; c[3 + n.arg] += mu; return true;
-      case RD_OP_LOOP: {
-        const int p = loop_pos(&A, n.arg);
-        if (p < 0 || p > 3) return false;
-        cl[p] += mu;
-        return true;
-      }
-      case RD_OP_ADD: return affine(n.kid[0], mu, c, cl) && affine(n.kid[1], mu, c, cl);
-      case RD_OP_SUB: return affine(n.kid[0], mu, c, cl) && affine(n.kid[1], -mu, c, cl);
-      case RD_OP_NEG: return affine(n.kid[0], -mu, c, cl);
-      case RD_OP_MUL: {
-        const TNode& a = nodes[n.kid[0]];
-        const TNode& b = nodes[n.kid[1]];
-        if (!a.groups) return affine(n.kid[1], mu * a.val, c, cl);
-        if (!b.groups) return affine(n.kid[0], mu * b.val, c, cl);
-        return false;
-      }
-      case RD_OP_SHL: {
-        const TNode& b = nodes[n.kid[1]];
-        if (b.groups || b.val < 0 || b.val > 62) return false;
-        return affine(n.kid[0], mu * ((i128)1 << b.val), c, cl);
-      }
-      default: return false;
-    }
-  }
-
-  bool decompose(int i, Lin& L, i128 mu) {
-    const TNode& n = nodes[i];
-    if (!n.groups) {
-      L.u += mu * (i128)n.val;
-      return fits64(L.u);
-    }
-    if (single(n.groups)) {
-      std::vector<rd_insn> code;
-      subtree(i, code);
-      return add_term(L, std::move(code), n.lo, n.hi, gidx(n.groups), mu, n.g);
-    }
-    const TNode* a = n.kid[0] >= 0 ? &nodes[n.kid[0]] : nullptr;
-    const TNode* b = n.kid[1] >= 0 ? &nodes[n.kid[1]] : nullptr;
-    switch (n.op) {
-      case RD_OP_ADD: return decompose(n.kid[0], L, mu) && decompose(n.kid[1], L, mu);
-      case RD_OP_SUB: return decompose(n.kid[0], L, mu) && decompose(n.kid[1], L, -mu);
-      case RD_OP_NEG: return decompose(n.kid[0], L, -mu);
-      case RD_OP_MUL:
-        if (!a->groups) return fits64(mu * a->val) && decompose(n.kid[1], L, mu * a->val);
-        if (!b->groups) return fits64(mu * b->val) && decompose(n.kid[0], L, mu * b->val);
-        return false;
-      case RD_OP_SHL:
-        if (b->groups || b->val < 0 || b->val > 62) return false;
-        return fits64(mu << (int)b->val) && decompose(n.kid[0], L, mu << (int)b->val);
-      case RD_OP_DIV:
-      case RD_OP_MOD: {
-        if (b->groups || b->val <= 0) return false;
-        const int64_t d = b->val;
-        Lin in;
-        if (!decompose(n.kid[0], in, 1)) return false;
-        std::vector<const STerm*> xs, ys;
-        i128 xlo = 0, ylo = in.u, yhi = in.u;
-        int yg = -1;
-        for (const STerm& t : in.terms) {
-          // divisible when (multiple of g) * mult is always a multiple of d
-          if (gmul(t.g, uabs64(t.mult)) % (uint64_t)d == 0 && t.g != 1 ? true
-              : t.mult % d == 0) {
-            xs.push_back(&t);
-            xlo += contrib_lo(t);
-          } else {
-            if (yg >= 0 && yg != t.group) return split_small_rest(n, in, L, mu, d);
-            yg = t.group;
-            ys.push_back(&t);
-            ylo += contrib_lo(t);
-            yhi += contrib_hi(t);
-          }
-        }
-        if (xlo < 0 || ylo < 0) return split_small_rest(n, in, L, mu, d);
-        i128 yabs = i128abs(in.u);
-        for (const STerm* t : ys) yabs += contrib_abs(*t);
-        if (yabs > kI64Hi) return false;
-        if (n.op == RD_OP_DIV)
-          for (const STerm* t : xs) {
-            // t = v * mult with d | g * mult: t / d = (v / d1) * (mult / gm),
-            // gm = gcd(d, |mult|), d1 = d / gm dividing every v
-            const uint64_t gm = gcd64((uint64_t)d, uabs64(t->mult));
-            const int64_t d1 = (int64_t)((uint64_t)d / gm);
-            std::vector<rd_insn> code = t->code;
-            i128 lo = t->lo, hi = t->hi;
-            uint64_t g = t->g;
-            if (d1 != 1) {
-              code.push_back(mk_insn(RD_OP_CONST, d1));
-              code.push_back(mk_insn(RD_OP_DIV));
-              lo /= d1;
-              hi /= d1;
-              g = g / (uint64_t)d1;
-            }
-            if (!add_term(L, std::move(code), lo, hi, t->group,
-                          mu * (i128)(t->mult / (int64_t)gm), g))
-              return false;
-          }
-        if (ys.empty()) {  // uniform remainder part
-          L.u += mu * (n.op == RD_OP_DIV ? in.u / d : in.u % d);
-          return fits64(L.u);
-        }
-        std::vector<rd_insn> code;
-        emit_sum(ys, in.u, code);
-        code.push_back(mk_insn(RD_OP_CONST, d));
-        code.push_back(mk_insn(n.op));
-        const i128 lo = n.op == RD_OP_DIV ? ylo / d : 0;
-        const i128 hi = n.op == RD_OP_DIV ? yhi / d : std::min(yhi, (i128)d - 1);
-        return add_term(L, std::move(code), lo, hi, yg, mu);
-      }
-      default:
-        return false;
-    }
-  }
-
-  // Second way to split X + Y by a positive d: X (the uniform part and the
-  // terms of one group) is a multiple of some g with g | d and X >= 0, and
-  // Y (the terms of one other group) lies in [0, g).  Then no multiple of d
-  // falls inside (X, X + Y], so (X + Y) / d = X / d and (X + Y) % d =
-  // X % d + Y.
-  bool split_small_rest(const TNode& n, const Lin& in, Lin& L, i128 mu, int64_t d) {
-    for (int gy = 0; gy < 3; ++gy) {
-      std::vector<const STerm*> xs, ys;
-      int gx = -1;
-      bool ok = true;
-      i128 xlo = in.u, ylo = 0, yhi = 0, xabs = i128abs(in.u);
-      uint64_t g = uabs64((int64_t)in.u);
-      for (const STerm& t : in.terms) {
-        if (t.group == gy) {
-          ys.push_back(&t);
-          ylo += contrib_lo(t);
-          yhi += contrib_hi(t);
-        } else {
-          if (gx >= 0 && gx != t.group) { ok = false; break; }
-          gx = t.group;
-          xs.push_back(&t);
-          xlo += contrib_lo(t);
-          xabs += contrib_abs(t);
-          g = gcd64(g, gmul(t.g, uabs64(t.mult)));
-        }
-      }
-      if (!ok || ys.empty() || xs.empty() || xabs > kI64Hi) continue;
-      if (g == 0 || (uint64_t)d % g != 0 || xlo < 0 || ylo < 0 || yhi >= (i128)g) continue;
-      // X / d or X % d as one term of group gx
-      std::vector<rd_insn> code;
-      emit_sum(xs, in.u, code);
-      code.push_back(mk_insn(RD_OP_CONST, d));
-      code.push_back(mk_insn(n.op));
-      i128 xhi = in.u;
-      for (const STerm* t : xs) xhi += contrib_hi(*t);
-      if (n.op == RD_OP_DIV) return add_term(L, std::move(code), xlo / d, xhi / d, gx, mu);
-      if (!add_term(L, std::move(code), 0, std::min(xhi, (i128)d - 1), gx, mu)) return false;
-      for (const STerm* t : ys) {
-        std::vector<rd_insn> c2 = t->code;
-        if (!add_term(L, std::move(c2), t->lo, t->hi, t->group, mu * (i128)t->mult, t->g))
-          return false;
-      }
-      return true;
-    }
-    return false;
-  }
-
-  // Guard as a conjunction of single-group (or uniform) conjuncts.
-  bool conjuncts(int i, std::vector<rd_insn> (&c)[3], bool& never) {
-    const TNode& n = nodes[i];
-    if (n.op == RD_OP_LAND && n.groups && !single(n.groups))
-      return conjuncts(n.kid[0], c, never) && conjuncts(n.kid[1], c, never);
-    if (!n.groups) {
-      if (n.val == 0) never = true;
-      return true;
-    }
-    if (!single(n.groups)) return false;
-    std::vector<rd_insn>& out = c[gidx(n.groups)];
-    const bool first = out.empty();
-    subtree(i, out);
-    if (!first) out.push_back(mk_insn(RD_OP_LAND));
-    return true;
-  }
-};
-
-// Largest stack depth of a postfix sequence.
-uint32_t postfix_depth(const std::vector<rd_insn>& code) {
-  uint32_t d = 0, m = 0;
-  for (const rd_insn& t : code) {
-    if (is_leaf(t.op)) ++d;
-    else if (is_binary(t.op)) --d;
-    m = std::max(m, d);
-  }
-  return m;
-}
-
-struct DimInfo {
-  bool done = false;
-  uint32_t err = 0;
-  bool ok = false;       // non-empty and within limits
-  int64_t d[6];
-  uint32_t params_off;   // offset of [params..., gx, gy, gz, bx, by, bz]
-};
-
-struct LoopInfo {
-  bool done = false;
-  uint32_t err = 0;
-  bool ok = false;
-  uint32_t off = 0, n = 0;
-};
-
-struct InstInfo {
-  bool done = false;
-  uint32_t err = 0;   // errors from extents and loops of this access
-  int32_t idx = -1;   // device instance, -1: no points
-  uint64_t box = 0;   // points counted in evals
-  uint32_t npts = 0;
-};
-
-struct Planner {
-  const rd_kernel_model* models;
-  const rd_launch_domain* launch;
-  const rd_param_sets* params;
-  std::vector<std::vector<DimInfo>> dims;                 // [model][set]
-  std::map<std::pair<uint32_t, uint32_t>, std::vector<LoopInfo>> loops;  // (model, loop) -> per set
-  std::map<std::pair<uint32_t, uint32_t>, std::vector<InstInfo>> insts;  // (model, acc) -> per set
-  std::map<std::pair<uint32_t, uint32_t>, Prog> progs[6];
-  std::vector<DInsn> code;
-  std::vector<int64_t> pool_params;
-  std::vector<int64_t> pool_loops;
-  std::vector<AccInst> dev_insts;
-  std::vector<TabHost> tabs;  // per device instance
-  std::vector<std::pair<int64_t, int64_t>> arange;  // address range, tables only
-  // address residue, tables only: every address is congruent to `second`
-  // modulo `first` (0: the single address `second`; 1: no information)
-  std::vector<std::pair<uint64_t, int64_t>> ares;
-  // tables only: bounds of u plus the thread and iteration terms (a block's
-  // addresses lie in its block term plus these), and the block-term job
-  // (index into tjobs, -1: the address does not depend on the block)
-  std::vector<std::pair<int64_t, int64_t>> rrest;
-  std::vector<uint8_t> tinj;  // tables only: thread-injective address (below)
-  std::vector<int32_t> bjob;
-  // tables only: address step from thread 0 to thread 1 and from block 0 to
-  // block 1 (0 when the group has one index or no term)
-  std::vector<std::array<int64_t, 2>> gstride;
-  std::vector<TabJob> tjobs;
-  uint64_t tpool = 0;         // table entries
-  uint64_t tab_budget = kMaxTabPool;  // table entries this planner may use
-  bool use_tables = true;
-
-  // Exact dependence test on an address that is affine in the coordinates
-  // (TermBuilder::affine): true when two points of different threads can
-  // never share an address.  The address is u + sum_k c_k x_k over the
-  // thread, block and loop coordinates (loop coordinates take their loop's
-  // values).  Each coordinate k with more
-  // than one value has a unit step s_k = |c_k| times the smallest distance
-  // between two of its values, and a span w_k = |c_k| (max - min).  Either
-  // of two mixed-radix arguments decides:
-  //   (1) ordered by s_k, the thread and block coordinates satisfy
-  //       m_k = s_k - sum_{j<k} w_j > 0; two different threads then differ
-  //       in the thread part by at least min_k m_k, and when that exceeds
-  //       the span of the whole loop part no loop values close the gap;
-  //   (2) ordered by s_k, all coordinates with c_k != 0 satisfy m_k > 0:
-  //       different coordinate tuples give different addresses, and two
-  //       different threads differ in a thread or block coordinate (all of
-  //       which must then have c_k != 0).
-  // A thread or block coordinate with more than one value and c_k = 0
-  // fails both (threads differing only there share addresses).  For a
-  // shared array (per_block) the block coordinates are left out: threads
-  // of different blocks never share its memory.
-  bool thread_injective(const i128* c, const i128* cl, const AccInst& I,
-                        bool per_block) const {
-    struct Co {
-      i128 step, span;
-    };
-    std::vector<Co> th, lp;  // thread/block coordinates, loop coordinates
-    for (int k = 0; k < 6; ++k) {
-      const i128 n = k < 3 ? I.dims[3 + k] : I.dims[k - 3];
-      if (n <= 1 || (per_block && k >= 3)) continue;
-      if (c[k] == 0) return false;
-      th.push_back({i128abs(c[k]), i128abs(c[k]) * (n - 1)});
-    }
-    for (uint32_t p = 0; p < I.n_loops && p < 4; ++p) {
-      if (cl[p] == 0 || I.loop_n[p] <= 1) continue;
-      std::vector<int64_t> v(pool_loops.begin() + I.loop_off[p],
-                             pool_loops.begin() + I.loop_off[p] + I.loop_n[p]);
-      std::sort(v.begin(), v.end());
-      i128 gap = -1;
-      for (size_t e = 1; e < v.size(); ++e) {
-        const i128 d = (i128)v[e] - v[e - 1];
-        if (gap < 0 || d < gap) gap = d;
-      }
-      lp.push_back({i128abs(cl[p]) * gap, i128abs(cl[p]) * ((i128)v.back() - v.front())});
-    }
-    // smallest margin of a mixed-radix ordering, -1 if some margin is <= 0
-    // (no coordinate with more than one value: +infinity, returned as 0)
-    auto margin = [](std::vector<Co> co) -> i128 {
-      std::sort(co.begin(), co.end(), [](const Co& a, const Co& b) { return a.step < b.step; });
-      i128 below = 0, m = 0;
-      for (const Co& e : co) {
-        const i128 mk = e.step - below;
-        if (mk <= 0) return -1;
-        if (m == 0 || mk < m) m = mk;
-        below += e.span;
-      }
-      return m;
-    };
-    const i128 mt = margin(th);
-    if (mt < 0) return false;
-    if (mt == 0) return true;  // one thread only
-    i128 lspan = 0;
-    for (const Co& e : lp) lspan += e.span;
-    if (lspan < mt) return true;  // (1)
-    std::vector<Co> all = th;
-    all.insert(all.end(), lp.begin(), lp.end());
-    return margin(all) > 0;  // (2)
-  }
-
-  // Term tables of instance I (access a of model m); T.on = 0 when some
-  // expression does not qualify.
-  void tables_for(uint32_t m, uint32_t a, const AccInst& I, uint32_t inst, TabHost& T) {
-    memset(&T, 0, sizeof T);
-    for (int g = 0; g < 3; ++g) T.off[g] = kNoTab;
-    T.iv_off = kNoTab;
-    if (!use_tables) return;
-    const rd_kernel_model& M = models[m];
-    const rd_access& A = M.acc[a];
-    const int64_t* pv = pool_params.data() + I.params_off;
-    int64_t dims[6], lmin[4] = {0, 0, 0, 0}, lmax[4] = {0, 0, 0, 0};
-    uint64_t lgcd[4] = {1, 1, 1, 1};
-    for (int k = 0; k < 6; ++k) dims[k] = I.dims[k];
-    for (uint32_t k = 0; k < I.n_loops; ++k) {
-      const int64_t* v = pool_loops.data() + I.loop_off[k];
-      lmin[k] = *std::min_element(v, v + I.loop_n[k]);
-      lmax[k] = *std::max_element(v, v + I.loop_n[k]);
-      uint64_t g = 0;
-      for (uint32_t e = 0; e < I.loop_n[k]; ++e) g = gcd64(g, uabs64(v[e]));
-      lgcd[k] = g;
-    }
-    TermBuilder tb{M, A, pv, dims, lmin, lmax, lgcd};
-    // address
-    if (!tb.build(A.addr)) return;
-    const i128 root_lo = tb.nodes.back().lo, root_hi = tb.nodes.back().hi;
-    Lin L;
-    if (!tb.decompose((int)tb.nodes.size() - 1, L, 1)) return;
-    i128 ac[6] = {0, 0, 0, 0, 0, 0}, acl[4] = {0, 0, 0, 0};
-    const bool aff = tb.affine((int)tb.nodes.size() - 1, 1, ac, acl);
-    i128 tot = i128abs(L.u), lo = L.u, hi = L.u;
-    for (const STerm& t : L.terms) {
-      tot += contrib_abs(t);
-      lo += contrib_lo(t);
-      hi += contrib_hi(t);
-    }
-    if (tot > kI64Hi) return;
-    if (I.is32 && !(root_lo >= INT32_MIN && root_hi <= INT32_MAX) &&
-        !(lo >= INT32_MIN && hi <= INT32_MAX))
-      return;
-    // guard
-    std::vector<rd_insn> conj[3];
-    bool never = false;
-    if (A.guard.count) {
-      if (!tb.build(A.guard)) return;
-      if (!tb.conjuncts((int)tb.nodes.size() - 1, conj, never)) return;
-    }
-    // interval ids
-    int64_t ivc[2] = {0, 0};
-    bool ivtab = false;
-    const rd_expr ive[2] = {A.bint, A.wint};
-    for (int w = 0; w < 2; ++w) {
-      if (!ive[w].count) continue;
-      if (!tb.build(ive[w])) return;
-      const TNode& r = tb.nodes.back();
-      if (r.lo < 0 || r.hi > 65535) return;
-      if (r.groups) ivtab = true;
-      else ivc[w] = r.val;
-    }
-    // programs and table jobs
-    const uint32_t gsize[3] = {I.nblk, I.nthr, I.niota};
-    std::vector<TabJob> jobs;
-    uint64_t entries = 0;
-    if (!never) {
-      rd_kernel_model tm = M;
-      for (int g = 0; g < 3; ++g) {
-        std::vector<const STerm*> ts;
-        for (const STerm& t : L.terms)
-          if (t.group == g) ts.push_back(&t);
-        if (ts.empty() && conj[g].empty()) continue;
-        TabJob J;
-        memset(&J, 0, sizeof J);
-        J.inst = inst;
-        J.group = (uint32_t)g;
-        J.n = gsize[g];
-        J.val.absent = 1;
-        J.guard.absent = 1;
-        if (!ts.empty()) {
-          std::vector<rd_insn> code;
-          TermBuilder::emit_sum(ts, 0, code);
-          if (postfix_depth(code) > (uint32_t)kMaxStack) return;
-          tm.insns = code.data();
-          tm.n_insns = (uint32_t)code.size();
-          J.val = compile(tm, rd_expr{0, (uint32_t)code.size()}, A, this->code);
-        }
-        if (!conj[g].empty()) {
-          if (postfix_depth(conj[g]) > (uint32_t)kMaxStack) return;
-          tm.insns = conj[g].data();
-          tm.n_insns = (uint32_t)conj[g].size();
-          J.guard = compile(tm, rd_expr{0, (uint32_t)conj[g].size()}, A, this->code);
-        }
-        jobs.push_back(J);
-        entries += J.n;
-      }
-      if (ivtab) {
-        TabJob J;
-        memset(&J, 0, sizeof J);
-        J.inst = inst;
-        J.group = 3;
-        J.n = I.niota;
-        J.val.absent = 1;
-        J.guard.absent = 1;
-        jobs.push_back(J);
-        entries += J.n;
-      }
-    }
-    if (entries > kMaxTabInst || tpool + entries > tab_budget) return;
-    T.base = tpool;
-    for (TabJob& J : jobs) {
-      if (J.group == 0) bjob[inst] = (int32_t)tjobs.size();
-      J.out_off = tpool;
-      const uint32_t rel = (uint32_t)(tpool - T.base);
-      if (J.group < 3) T.off[J.group] = rel;
-      else T.iv_off = rel;
-      tpool += J.n;
-      tjobs.push_back(J);
-    }
-    T.u = (int64_t)L.u;
-    T.iv_const = (uint32_t)ivc[0] | ((uint32_t)ivc[1] << 16);
-    T.never = never;
-    T.on = 1;
-    arange[inst] = {(int64_t)lo, (int64_t)hi};
-    // each term is a multiple of g * |mult| (1 when that product is not
-    // known exactly), so addr - u is a multiple of their gcd
-    uint64_t G = 0;
-    for (const STerm& t : L.terms) G = gcd64(G, gmul(t.g, uabs64(t.mult)));
-    ares[inst] = {G, (int64_t)L.u};
-    i128 rlo = L.u, rhi = L.u;
-    for (const STerm& t : L.terms)
-      if (t.group != 0) {
-        rlo += contrib_lo(t);
-        rhi += contrib_hi(t);
-      }
-    rrest[inst] = {(int64_t)rlo, (int64_t)rhi};
-    tinj[inst] =
-        aff && thread_injective(ac, acl, I, M.arrays[A.array].space == RD_SHARED) ? 1 : 0;
-    // point order: iterations fastest when the address moves less along
-    // them than along threads (consecutive points then share buckets)
-    int64_t stride[3] = {0, 0, 0};
-    for (const TabJob& J : jobs) {
-      if (J.group == 3 || J.val.absent || J.n < 2) continue;
-      int64_t c[10];
-      uint32_t e = 0;
-      host_coords(I, pool_loops, J.group == 0 ? 1 : 0, J.group == 1 ? 1 : 0,
-                  J.group == 2 ? 1 : 0, c);
-      const int64_t v1 = host_prog(this->code, J.val, c, pv, 0, e);
-      host_coords(I, pool_loops, 0, 0, 0, c);
-      const int64_t v0 = host_prog(this->code, J.val, c, pv, 0, e);
-      if (J.group < 2 && !e) gstride[inst][J.group ? 0 : 1] = v1 - v0;
-      if (J.group == 0) continue;
-      if (!e) stride[J.group] = v1 > v0 ? v1 - v0 : v0 - v1;
-      else stride[J.group] = INT64_MAX;
-    }
-    const bool t_moves = I.nthr > 1, i_moves = I.niota > 1;
-    dev_insts[inst].iorder = i_moves && (!t_moves || stride[2] < stride[1]) ? 1 : 0;
-    // acquire and release addresses that interval bounds prove error-free
-    // over the box (and inside int32 for 32-bit lock arrays)
-    bool ss = true;
-    for (const rd_sync* y : {&A.acq, &A.rel}) {
-      if (!y->addr.count) continue;
-      if (!tb.build(y->addr)) {
-        ss = false;
-        break;
-      }
-      const TNode& r = tb.nodes.back();
-      if (M.arrays[y->array].addr_bits == 32 && (r.lo < INT32_MIN || r.hi > INT32_MAX)) {
-        ss = false;
-        break;
-      }
-    }
-    T.syn_safe = ss ? 1 : 0;
-  }
-
-  DimInfo& dim(uint32_t m, uint32_t s) {
-    DimInfo& d = dims[m][s];
-    if (d.done) return d;
-    d.done = true;
-    const rd_kernel_model& M = models[m];
-    const rd_launch_domain& L = launch[m];
-    const int64_t* pv = params[m].values + (uint64_t)s * M.n_params;
-    bool nonempty = true;
-    for (int k = 0; k < 3; ++k) {
-      d.d[k] = heval(M, L.grid[k], pv, nullptr, 1, d.err);
-      d.d[3 + k] = heval(M, L.block[k], pv, nullptr, 1, d.err);
-      if (d.d[k] < 1 || d.d[3 + k] < 1) nonempty = false;
-    }
-    if (!nonempty) return d;
-    for (int k = 3; k < 6; ++k)
-      if (d.d[k] > kMaxBlock) { d.err |= ERR_UNSUP; return d; }
-    if (d.d[3] * d.d[4] > kMaxBlock || d.d[3] * d.d[4] * d.d[5] > kMaxBlock) {
-      d.err |= ERR_UNSUP;
-      return d;
-    }
-    for (int k = 0; k < 3; ++k)
-      if (d.d[k] >= kMaxGrid) { d.err |= ERR_UNSUP; return d; }
-    if (d.d[0] * d.d[1] >= kMaxGrid || d.d[0] * d.d[1] * d.d[2] >= kMaxGrid) {
-      d.err |= ERR_UNSUP;
-      return d;
-    }
-    d.ok = true;
-    d.params_off = (uint32_t)pool_params.size();
-    for (uint32_t k = 0; k < M.n_params; ++k) pool_params.push_back(pv[k]);
-    for (int k = 0; k < 6; ++k) pool_params.push_back(d.d[k]);
-    return d;
-  }
-
-  LoopInfo& loop(uint32_t m, uint32_t l, uint32_t s, const DimInfo& d) {
-    auto& v = loops[{m, l}];
-    if (v.empty()) v.resize(params[m].n_sets);
-    LoopInfo& li = v[s];
-    if (li.done) return li;
-    li.done = true;
-    const rd_kernel_model& M = models[m];
-    const rd_loop& L = M.loops[l];
-    const int64_t* pv = params[m].values + (uint64_t)s * M.n_params;
-    uint32_t e = 0;
-    int64_t x = heval(M, L.init, pv, d.d, 0, e);
-    int64_t bound = heval(M, L.bound, pv, d.d, 0, e);
-    int64_t step = heval(M, L.step, pv, d.d, 0, e);
-    if (e) { li.err = e; return li; }
-    li.off = (uint32_t)pool_loops.size();
-    uint32_t n = 0;
-    while (cmp_holds(L.cmp, x, bound)) {
-      if (n == kMaxIters) {
-        li.err |= ERR_UNSUP;
-        pool_loops.resize(li.off);
-        return li;
-      }
-      pool_loops.push_back(x);
-      ++n;
-      uint32_t ue = 0;
-      x = hop(kUpdOp[L.upd], x, step, ue);
-      if (ue) {
-        li.err |= ue;
-        pool_loops.resize(li.off);
-        return li;
-      }
-    }
-    li.n = n;
-    li.ok = true;
-    return li;
-  }
-
-  Prog prog(uint32_t m, uint32_t a, int which) {
-    auto key = std::make_pair(m, a);
-    auto it = progs[which].find(key);
-    if (it != progs[which].end()) return it->second;
-    const rd_access& A = models[m].acc[a];
-    const rd_expr ex[6] = {A.addr, A.guard, A.bint, A.wint, A.acq.addr, A.rel.addr};
-    const rd_expr e = ex[which];
-    Prog p = compile(models[m], e, A, code);
-    progs[which][key] = p;
-    return p;
-  }
-
-  InstInfo& inst(uint32_t m, uint32_t a, uint32_t s) {
-    auto& v = insts[{m, a}];
-    if (v.empty()) v.resize(params[m].n_sets);
-    InstInfo& ii = v[s];
-    if (ii.done) return ii;
-    ii.done = true;
-    DimInfo& d = dim(m, s);
-    ii.err |= d.err;
-    if (!d.ok) return ii;
-    const rd_kernel_model& M = models[m];
-    const rd_access& A = M.acc[a];
-    uint64_t niota = 1;
-    uint32_t ln[4] = {1, 1, 1, 1}, lo[4] = {0, 0, 0, 0};
-    for (uint32_t k = 0; k < A.n_loops; ++k) {
-      LoopInfo& li = loop(m, A.loops[k], s, d);
-      ii.err |= li.err;
-      if (!li.ok) return ii;
-      ln[k] = li.n;
-      lo[k] = li.off;
-      niota *= li.n;
-      if (niota > kMaxIters) {
-        ii.err |= ERR_UNSUP;
-        return ii;
-      }
-    }
-    uint64_t nblk = (uint64_t)(d.d[0] * d.d[1] * d.d[2]);
-    uint64_t nthr = (uint64_t)(d.d[3] * d.d[4] * d.d[5]);
-    uint64_t box = nblk * nthr * niota;
-    if (box >= (uint64_t)kMaxPoints) {
-      ii.err |= ERR_UNSUP;
-      return ii;
-    }
-    ii.box = box;
-    if (box == 0) return ii;
-    AccInst I;
-    memset(&I, 0, sizeof I);
-    I.addr = prog(m, a, 0);
-    I.guard = prog(m, a, 1);
-    I.bint = prog(m, a, 2);
-    I.wint = prog(m, a, 3);
-    I.acq = prog(m, a, 4);
-    I.rel = prog(m, a, 5);
-    I.syn = syn_flags(M, A);
-    for (int k = 0; k < 6; ++k) I.dims[k] = (int32_t)d.d[k];
-    I.nblk = (uint32_t)nblk;
-    I.nthr = (uint32_t)nthr;
-    I.niota = (uint32_t)niota;
-    I.n_loops = A.n_loops;
-    for (int k = 0; k < 4; ++k) {
-      I.loop_n[k] = ln[k];
-      I.loop_off[k] = lo[k];
-    }
-    I.params_off = d.params_off;
-    I.is32 = M.arrays[A.array].addr_bits == 32;
-    I.npts = (uint32_t)box;
-    I.tpb = (uint32_t)(nthr * niota);
-    ii.idx = (int32_t)dev_insts.size();
-    ii.npts = (uint32_t)box;
-    dev_insts.push_back(I);
-    TabHost T;
-    arange.push_back({0, -1});
-    ares.push_back({1, 0});
-    rrest.push_back({0, -1});
-    tinj.push_back(0);
-    bjob.push_back(-1);
-    gstride.push_back({0, 0});
-    tables_for(m, a, I, (uint32_t)ii.idx, T);
-    tabs.push_back(T);
-    return ii;
-  }
-
-  // Appends everything planner `o` lowered (it worked on models no other
-  // planner touched): its pools go after this planner's, and every offset
-  // and index into them is moved by the pool sizes before the append.
-  void absorb(Planner& o) {
-    const uint32_t code_off = (uint32_t)code.size();
-    const uint32_t par_off = (uint32_t)pool_params.size();
-    const uint32_t loop_off = (uint32_t)pool_loops.size();
-    const int32_t inst_off = (int32_t)dev_insts.size();
-    const int32_t job_off = (int32_t)tjobs.size();
-    const uint64_t tp_off = tpool;
-    auto fix = [&](Prog& p) {
-      if (!p.absent) p.off += code_off;
-    };
-    code.insert(code.end(), o.code.begin(), o.code.end());
-    pool_params.insert(pool_params.end(), o.pool_params.begin(), o.pool_params.end());
-    pool_loops.insert(pool_loops.end(), o.pool_loops.begin(), o.pool_loops.end());
-    for (AccInst I : o.dev_insts) {
-      fix(I.addr);
-      fix(I.guard);
-      fix(I.bint);
-      fix(I.wint);
-      fix(I.acq);
-      fix(I.rel);
-      I.params_off += par_off;
-      for (uint32_t k = 0; k < I.n_loops && k < 4; ++k) I.loop_off[k] += loop_off;
-      dev_insts.push_back(I);
-    }
-    for (TabHost T : o.tabs) {
-      if (T.on) T.base += tp_off;
-      tabs.push_back(T);
-    }
-    for (TabJob J : o.tjobs) {
-      J.inst += (uint32_t)inst_off;
-      J.out_off += tp_off;
-      fix(J.val);
-      fix(J.guard);
-      tjobs.push_back(J);
-    }
-    tpool += o.tpool;
-    arange.insert(arange.end(), o.arange.begin(), o.arange.end());
-    ares.insert(ares.end(), o.ares.begin(), o.ares.end());
-    rrest.insert(rrest.end(), o.rrest.begin(), o.rrest.end());
-    tinj.insert(tinj.end(), o.tinj.begin(), o.tinj.end());
-    for (int32_t b : o.bjob) bjob.push_back(b < 0 ? b : b + job_off);
-    gstride.insert(gstride.end(), o.gstride.begin(), o.gstride.end());
-    for (size_t m = 0; m < o.dims.size() && m < dims.size(); ++m) {
-      bool any = false;
-      for (const DimInfo& d : o.dims[m]) any |= d.done;
-      if (!any) continue;
-      dims[m] = o.dims[m];
-      for (DimInfo& d : dims[m])
-        if (d.ok) d.params_off += par_off;
-    }
-    for (auto& kv : o.loops) {
-      std::vector<LoopInfo> v = kv.second;
-      for (LoopInfo& li : v)
-        if (li.ok) li.off += loop_off;
-      loops[kv.first] = v;
-    }
-    for (auto& kv : o.insts) {
-      std::vector<InstInfo> v = kv.second;
-      for (InstInfo& ii : v)
-        if (ii.idx >= 0) ii.idx += inst_off;
-      insts[kv.first] = v;
-    }
-    for (int w = 0; w < 6; ++w)
-      for (auto& kv : o.progs[w]) {
-        Prog p = kv.second;
-        fix(p);
-        progs[w][kv.first] = p;
-      }
-  }
-
-  // Per-block address intervals of a table instance (sorted, merged): a
-  // block's addresses lie in its block term plus the bounds of the other
-  // terms (one program run per block).
-  std::map<int32_t, std::vector<std::pair<int64_t, int64_t>>> bcache;
-  const std::vector<std::pair<int64_t, int64_t>>& block_ranges(int32_t x) {
-    auto it = bcache.find(x);
-    if (it != bcache.end()) return it->second;
-    std::vector<std::pair<int64_t, int64_t>> v;
-    const AccInst& I = dev_insts[x];
-    const TabJob& J = tjobs[bjob[x]];
-    const int64_t* pr = pool_params.data() + I.params_off;
-    const auto rest = rrest[x];
-    int64_t c[10];
-    bool ok = true;
-    for (uint32_t b = 0; b < I.nblk && ok; ++b) {
-      host_coords(I, pool_loops, b, 0, 0, c);
-      uint32_t err = 0;
-      const bool g = J.guard.absent || host_prog(code, J.guard, c, pr, 1, err) != 0;
-      const int64_t t = g && !J.val.absent ? host_prog(code, J.val, c, pr, 0, err) : 0;
-      if (err) ok = false;
-      if (g) v.push_back({t + rest.first, t + rest.second});
-    }
-    if (!ok) v.assign(1, {INT64_MIN, INT64_MAX});  // no claim
-    std::sort(v.begin(), v.end());
-    std::vector<std::pair<int64_t, int64_t>> m;
-    for (const auto& r : v) {
-      if (!m.empty() && r.first <= m.back().second)
-        m.back().second = std::max(m.back().second, r.second);
-      else
-        m.push_back(r);
-    }
-    return bcache[x] = std::move(m);
-  }
-
-  // Exact pre-filter of a (pair, tuple) unit of two table instances: true
-  // when no address of one equals an address of the other.  (1) The address
-  // ranges over the whole launch box do not meet.  (2) The residues are
-  // incompatible: addresses of a are u_a + k G_a, of b u_b + k G_b, and a
-  // common one needs gcd(G_a, G_b) | u_a - u_b.  (3) For units of at least
-  // 2^18 points with at most 2^16 blocks per side: the unions of the
-  // per-block intervals miss each other.
-  bool apart(int32_t ia, int32_t ib) {
-    if (!tabs[ia].on || !tabs[ib].on) return false;
-    const auto& ra = arange[ia];
-    const auto& rb = arange[ib];
-    if (ra.second < rb.first || rb.second < ra.first) return true;
-    const auto& ca = ares[ia];
-    const auto& cb = ares[ib];
-    const uint64_t g = gcd64(ca.first, cb.first);
-    const i128 du = (i128)ca.second - (i128)cb.second;
-    if (g == 0 ? du != 0 : (du % (i128)g) != 0) return true;
-    if (bjob[ia] < 0 || bjob[ib] < 0) return false;
-    const AccInst& A = dev_insts[ia];
-    const AccInst& B = dev_insts[ib];
-    if (A.nblk > (1u << 16) || B.nblk > (1u << 16)) return false;
-    if ((uint64_t)A.npts + B.npts < (1ull << 18)) return false;
-    const auto& x = block_ranges(ia);
-    const auto& y = block_ranges(ib);
-    size_t i = 0, j = 0;
-    while (i < x.size() && j < y.size()) {
-      if (x[i].second < y[j].first) ++i;
-      else if (y[j].second < x[i].first) ++j;
-      else return false;  // these intervals meet
-    }
-    return true;
-  }
-};
-
-// Accesses a and b of M compute their address with one and the same
-// expression (so, under one tuple, one function of the coordinates and
-// loop values).
-bool same_addr_expr(const rd_kernel_model& M, uint32_t a, uint32_t b) {
-  const rd_expr ea = M.acc[a].addr, eb = M.acc[b].addr;
-  if (ea.count != eb.count) return false;
-  for (uint32_t e = 0; e < ea.count; ++e) {
-    const rd_insn& x = M.insns[ea.first + e];
-    const rd_insn& y = M.insns[eb.first + e];
-    if (x.op != y.op || x.arg != y.arg || x.imm != y.imm) return false;
-  }
-  return true;
-}
-
-// Per-access facts for the device's syn() (section 6.5, Figures 9 and 10):
-// which of acquire and release exist, which reach device scope, whether
-// they share an array (so a lock is possible), the access kind, and which
-// addresses must fit int32.
-uint32_t syn_flags(const rd_kernel_model& m, const rd_access& a) {
-  uint32_t f = 0;
-  if (a.acq.addr.count) {
-    f |= kSynAcq;
-    if (a.acq.scope == RD_SCOPE_DEVICE) f |= kSynAcqDev;
-    if (m.arrays[a.acq.array].addr_bits == 32) f |= kSynAcq32;
-  }
-  if (a.rel.addr.count) {
-    f |= kSynRel;
-    if (a.rel.scope == RD_SCOPE_DEVICE) f |= kSynRelDev;
-    if (m.arrays[a.rel.array].addr_bits == 32) f |= kSynRel32;
-  }
-  if ((f & kSynAcq) && (f & kSynRel) &&
-      memory_of(m, a.acq.array) == memory_of(m, a.rel.array))
-    f |= kSynSameArr;
-  if (a.kind == RD_WRITE) f |= kSynWrite;
-  if (a.kind == RD_READ) f |= kSynRead;
-  return f;
-}
-
-// The array of an access's syn() at scope `dev` (0 block, 1 device), or -1
-// when it has none at any point: a lock needs one array for acquire and
-// release, so the array never depends on the point.
-int64_t syn_array(const rd_access& a, int dev, const rd_kernel_model& m) {
-  const bool A = a.acq.addr.count && (!dev || a.acq.scope == RD_SCOPE_DEVICE);
-  const bool R = a.rel.addr.count && (!dev || a.rel.scope == RD_SCOPE_DEVICE);
-  if (A && R && memory_of(m, a.acq.array) == memory_of(m, a.rel.array)) return a.acq.array;
-  if (a.kind == RD_WRITE && R) return a.rel.array;
-  if (a.kind == RD_READ && A) return a.acq.array;
-  return -1;
-}
-
-// Pair-level synchronisation flags: kQSync when either access has an
-// acquire or release (the pair goes to the HBM aggregation path); kQSyncBlk
-// / kQSyncDev when points of the two can share a syn() at block / device
-// scope (same array; device scope also needs a global array, since shared
-// memory is one per block).
-uint32_t pair_sync(const rd_kernel_model& m, const rd_access& x, const rd_access& y) {
-  uint32_t f = 0;
-  if (x.acq.addr.count || x.rel.addr.count || y.acq.addr.count || y.rel.addr.count)
-    f |= kQSync;
-  const int64_t b0 = syn_array(x, 0, m), b1 = syn_array(y, 0, m);
-  if (b0 >= 0 && b1 >= 0 && memory_of(m, (uint32_t)b0) == memory_of(m, (uint32_t)b1))
-    f |= kQSyncBlk;
-  const int64_t d0 = syn_array(x, 1, m), d1 = syn_array(y, 1, m);
-  if (d0 >= 0 && d1 >= 0 && memory_of(m, (uint32_t)d0) == memory_of(m, (uint32_t)d1) &&
-      m.arrays[d0].space == RD_GLOBAL)
-    f |= kQSyncDev;
-  return f;
-}
-
-uint32_t class_mask(const rd_kernel_model& m, const rd_access& x,
-                    const rd_access& y, uint32_t caller) {
-  uint32_t mask = caller & 7u;
-  if (x.kind == RD_READ && y.kind == RD_READ) return 0;  // section 6.1
-  if (x.kind == RD_ATOMIC && y.kind == RD_ATOMIC) {      // appendix A.2
-    if (x.scope == RD_SCOPE_DEVICE && y.scope == RD_SCOPE_DEVICE) return 0;
-    mask &= RD_INTER;
-  }
-  if (m.arrays[x.array].space == RD_SHARED) mask &= ~(uint32_t)RD_INTER;
-  return mask;
-}
-
-struct QPlan {
-  uint32_t host_err = 0;
-  uint32_t sync = 0;  // kQSync* flags
-  uint8_t trivial = 0;
-  uint8_t lower = 0;  // valid, non-trivial: its instances are lowered
-  bool work = false;
-  QDesc qd;
-  uint64_t evals = 0;
-  std::vector<std::pair<int32_t, int32_t>> inst;  // per set
-};
-
-#define TRY_HIP(x)                  \
-  do {                              \
-    if ((x) != hipSuccess) {        \
-      return RD_EDEVICE;            \
-    }                               \
-  } while (0)
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
 
@@ -1766,100 +84,6 @@ int rd_get_stats(const rd_context* ctx, rd_stats* out) {
   return RD_OK;
 }
 
-// A prepared batch: everything rd_execute needs, already in device memory.
-struct rd_plan_impl {
-  uint32_t n_pairs = 0;
-  int cfg = 1;
-  uint32_t cap = 1536;
-  uint32_t log_level = 0;
-  hipStream_t st = nullptr;
-  std::vector<QPlan> Q;
-  // (pair, tuple) units of pairs with an acquire or release: joined by the
-  // HBM aggregation path with the synchronisation levels
-  struct SyncUnit {
-    uint32_t q, sigma, inst_i, inst_j, scan;
-    uint64_t R;
-  };
-  std::vector<SyncUnit> sync_units;
-  std::vector<uint32_t> npts;  // per device instance
-  std::vector<uint32_t> tpb;   // per device instance: points per block
-  std::vector<uint8_t> tab_on;  // per device instance: has term tables
-  std::vector<uint32_t> nblk;   // per device instance: blocks
-  std::vector<std::pair<int64_t, int64_t>> arange;  // address range (tables)
-  bool no_map = false;          // hash buckets only
-  uint64_t evals = 0;
-  uint32_t n_sitems = 0;
-  uint64_t n_symmetric = 0;   // shared units joined on block 0 only
-  uint64_t sync_decided = 0;  // synchronised units decided conflict-free
-  uint32_t persist_grid = 0;  // workgroups of the persistent small join
-  uint32_t chunk_pts = 16384; // points per partition workgroup
-  uint32_t run_buckets = 8;   // buckets per join workgroup
-  uint32_t n_tabchunks = 0;   // term-table fill chunks
-  uint64_t prefiltered = 0;   // (pair, tuple) units decided by the pre-filter
-  uint32_t n_insts = 0, tab_insts = 0;
-  struct Wave {
-    uint32_t first_item, n_items, n_chunks, n_buckets;
-    uint32_t n_tab_chunks;  // the first n_tab_chunks chunks have term tables
-    uint32_t n_runs;        // bucket runs (one join workgroup each)
-    uint32_t n_tab_runs;    // the first n_tab_runs runs are of items with tables
-    uint32_t n_sync_runs;   // the last n_sync_runs runs are of synchronised items
-    uint64_t key_bytes;
-    uint64_t hitem_off, chunk_off, bitem_off;  // element offsets in the plan pools
-  };
-  std::vector<Wave> waves;
-  std::vector<HItem> hitems;   // all waves, wave-local bucket numbering
-  std::vector<uint64_t> hR;    // records bound per HBM item
-  std::vector<uint8_t> presplit;  // per HBM item: split by (address, block)
-                                  // without a first partition pass
-  std::vector<uint8_t> herr_scan;  // error-scan-only items
-  uint64_t max_key_bytes = 0, max_buckets = 0, max_items = 0;
-  uint64_t wave_budget = 0;
-  // VERDICT mode
-  bool verdict = false;
-  uint32_t score_mode = 0;  // 0 plain order, 1 network, 2 interval order
-  std::vector<uint32_t> vinst_tab;  // table instances of VERDICT blocks
-  std::vector<BItem> bitems_interp; // VERDICT blocks of interpreted instances
-  uint32_t K = 0;                  // tiles searched per search unit
-  uint32_t n_vq = 0, n_bitems = 0, n_tchunks = 0, max_tiles = 0;
-  uint32_t max_g = 0;  // most blocks per side of a search unit
-  uint64_t n_tiles = 0;
-  std::vector<std::pair<uint32_t, uint32_t>> rounds;  // [item lo, item hi)
-  uint32_t n_titems = 0;
-  uint32_t n_vqueries_pairs = 0;
-  std::vector<VQuery> vqs;
-  std::map<std::string, DevBuf> dev;
-  Arena* arena = nullptr;  // the context's arena when the plan was made
-  void* buf(const char* name, size_t bytes, int* err) {
-    DevBuf& b = dev[name];
-    if (arena) return arena_buf(*arena, b, name, bytes, err);
-    if (bytes == 0) bytes = 256;
-    if (b.cap < bytes) {
-      if (b.p) (void)hipFree(b.p);
-      b.p = nullptr;
-      b.cap = 0;
-      if (hipMalloc(&b.p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        fprintf(stderr, "hgrd: device allocation of %zu bytes for '%s' failed\n", bytes, name);
-        b.p = nullptr;
-        *err = RD_ENOMEM;
-        return nullptr;
-      }
-      b.cap = bytes;
-    }
-    return b.p;
-  }
-  // the first phase of rd_execute (everything before the first host round
-  // trip), captured once and replayed
-  hipGraphExec_t graph = nullptr;
-  bool graph_failed = false;
-  ~rd_plan_impl() {
-    if (graph) (void)hipGraphExecDestroy(graph);
-    for (auto& kv : dev)
-      if (kv.second.p && kv.second.own) (void)hipFree(kv.second.p);
-  }
-};
-
-struct rd_plan : rd_plan_impl {};
 
 int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
                uint32_t n_models, const rd_access_pair* pairs,
@@ -2717,23 +941,6 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
 
 void rd_plan_destroy(rd_plan* plan) { delete plan; }
 
-// VERDICT block bounds: instances with term tables from their tables, the
-// others by generating their points.  Nonzero on a launch failure.
-static int verdict_bounds(rd_plan* plan, hipStream_t st) {
-  auto D = [&](const char* name) { return plan->dev[name].p; };
-  BBound* d_bb = (BBound*)D("bbounds");
-  if (!plan->vinst_tab.empty() &&
-      launch_block_bounds_tab(st, (const uint32_t*)D("vinst"), (uint32_t)plan->vinst_tab.size(),
-                              (const BItem*)D("bitems"), plan->n_bitems, D("insts"),
-                              (InstRange*)D("irange"), d_bb))
-    return 1;
-  if (!plan->bitems_interp.empty() &&
-      launch_block_bounds(st, (const BItem*)D("bitems_i"), (uint32_t)plan->bitems_interp.size(),
-                          D("insts"), (const DInsn*)D("code"), (const int64_t*)D("params"),
-                          (const int64_t*)D("loops"), (QAcc*)D("qacc"), d_bb))
-    return 1;
-  return 0;
-}
 
 int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   if (!ctx || !plan) return RD_EINVAL;
@@ -3553,381 +1760,3 @@ int hgrd::check_pairs_in_arena(rd_context* ctx, void* base, size_t cap,
   ctx->abufs.clear();
   return rc;
 }
-
-extern "C" {
-
-int rd_autotune(rd_context* ctx, const rd_kernel_model* models,
-                uint32_t n_models, const rd_access_pair* pairs,
-                uint32_t n_pairs, const rd_launch_domain* launch,
-                const rd_param_sets* params, const rd_options* opt,
-                uint32_t reps, rd_options* best, double* best_ms) {
-  if (!ctx || !best) return RD_EINVAL;
-  rd_options base;
-  memset(&base, 0, sizeof base);
-  if (opt) base = *opt;
-  reps = std::max(1u, std::min(reps, 16u));
-  std::vector<rd_pair_result> out(std::max<uint32_t>(1, n_pairs));
-  static const uint64_t kWaves[3] = {kWaveBytes / 4, kWaveBytes, kWaveBytes * 4};
-  double t_best = 1e300;
-  rd_options o_best = base;
-  for (int cfg = 0; cfg < 3; ++cfg) {
-    for (uint64_t wb : kWaves) {
-      rd_options o = base;
-      o.lds_cap = (uint32_t)join_cap(cfg);
-      o.max_device_bytes = wb;
-      rd_plan* plan = nullptr;
-      int rc = rd_prepare(ctx, models, n_models, pairs, n_pairs, launch, params, &o, &plan);
-      if (rc != RD_OK) return rc;
-      rc = rd_execute(ctx, plan, out.data());  // warm-up (and graph capture)
-      std::vector<double> ts;
-      for (uint32_t r = 0; rc == RD_OK && r < reps; ++r) {
-        const double t0 = now_ms();
-        rc = rd_execute(ctx, plan, out.data());
-        ts.push_back(now_ms() - t0);
-      }
-      rd_plan_destroy(plan);
-      if (rc != RD_OK) return rc;
-      std::sort(ts.begin(), ts.end());
-      const double t = ts[ts.size() / 2];
-      if (t < t_best) {
-        t_best = t;
-        o_best = o;
-      }
-    }
-  }
-  ctx->cfg = o_best.lds_cap <= 1024 ? 0 : o_best.lds_cap <= 1536 ? 1 : 2;
-  ctx->wave_bytes = o_best.max_device_bytes;
-  *best = o_best;
-  if (best_ms) *best_ms = t_best;
-  return RD_OK;
-}
-
-// ---------------------------------------------------------------------------
-// Tile data and the tile-scoring network.
-
-int rd_tile_data(rd_context* ctx, const rd_kernel_model* models,
-                 uint32_t n_models, const rd_access_pair* pairs,
-                 uint32_t n_pairs, const rd_launch_domain* launch,
-                 const rd_param_sets* params, const rd_options* opt,
-                 uint64_t max_rows, float* feats, float* labels, uint32_t* ids,
-                 uint64_t* n_rows) {
-  if (!ctx || !n_rows) return RD_EINVAL;
-  rd_options o;
-  memset(&o, 0, sizeof o);
-  if (opt) o = *opt;
-  o.mode = RD_MODE_VERDICT;
-  o.order = RD_ORDER_LEX;
-  o.tile_budget = 1u << 20;
-  rd_plan* plan = nullptr;
-  int rc = rd_prepare(ctx, models, n_models, pairs, n_pairs, launch, params, &o, &plan);
-  if (rc != RD_OK) return rc;
-  std::unique_ptr<rd_plan> guard(plan);
-  *n_rows = plan->n_tiles;
-  if (plan->n_tiles > max_rows) return RD_ECAPACITY;
-  if (!plan->n_tiles) return RD_OK;
-  hipStream_t st = plan->st;
-  auto D = [&](const char* name) { return plan->dev[name].p; };
-  int merr = 0;
-  uint32_t* d_done = (uint32_t*)ctx->ensure("done", std::max<size_t>(1, n_pairs) * 4, &merr);
-  float* d_feat = (float*)ctx->ensure("td_feats", plan->n_tiles * 32 * 4, &merr);
-  if (merr) return merr;
-  VQuery* d_vq = (VQuery*)D("vq");
-  BBound* d_bb = (BBound*)D("bbounds");
-  TOut* d_tout = (TOut*)D("tout");
-  QAcc* d_acc = (QAcc*)D("qacc");
-  if ((plan->n_tabchunks &&
-       launch_tabulate(st, (const Chunk*)D("tabchunks"), plan->n_tabchunks,
-                       (const TabJob*)D("tabjobs"), D("insts"), (const DInsn*)D("code"),
-                       (const int64_t*)D("params"), (const int64_t*)D("loops"),
-                       (int64_t*)D("tpool"))) ||
-      launch_init_acc(st, n_pairs, d_acc) || launch_fill_u32(st, d_done, n_pairs, 0) ||
-      launch_fill_u64(st, (u64*)D("claim"), n_pairs, kNoKey) ||
-      launch_fill_u64(st, (u64*)d_tout, (u64)plan->n_titems * (sizeof(TOut) / 8), kNoKey) ||
-      verdict_bounds(plan, st) || launch_vq_span(st, d_vq, plan->n_vq, d_bb) ||
-      launch_tile_features(st, (const TChunk*)D("tchunks"), plan->n_tchunks, d_vq, d_bb, d_feat))
-    return RD_EDEVICE;
-  // every tile is joined (no commit, so no query stops early)
-  for (auto& rr : plan->rounds)
-    if (launch_tile_join(plan->cfg, st, (const TItem*)D("titems"), rr.first,
-                         rr.second - rr.first, d_vq, nullptr, plan->K, D("insts"),
-                         (const DInsn*)D("code"), (const int64_t*)D("params"),
-                         (const int64_t*)D("loops"), (const QDesc*)D("qdesc"), d_done,
-                         d_tout, (u64*)D("claim"), d_bb, nullptr))
-      return RD_EDEVICE;
-  std::vector<TOut> tout(plan->n_titems);
-  std::vector<QAcc> acc(n_pairs);
-  TRY_HIP(hipMemcpyAsync(tout.data(), d_tout, tout.size() * sizeof(TOut), hipMemcpyDeviceToHost, st));
-  if (n_pairs) TRY_HIP(hipMemcpyAsync(acc.data(), d_acc, n_pairs * sizeof(QAcc), hipMemcpyDeviceToHost, st));
-  if (feats)
-    TRY_HIP(hipMemcpyAsync(feats, d_feat, plan->n_tiles * 32 * 4, hipMemcpyDeviceToHost, st));
-  TRY_HIP(hipStreamSynchronize(st));
-  // tile items are (unit, rank = tile index); map each to its row
-  std::vector<int8_t> lab(plan->n_tiles, 0);
-  std::vector<uint32_t> tiles_of_item;
-  {
-    std::vector<TItem> titems(plan->n_titems);
-    TRY_HIP(hipMemcpy(titems.data(), D("titems"), titems.size() * sizeof(TItem), hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < titems.size(); ++i) {
-      const VQuery& v = plan->vqs[titems[i].vq];
-      lab[v.tile0 + titems[i].rank] = tout[i].pkey != kNoKey ? 1 : 0;
-    }
-  }
-  for (const VQuery& v : plan->vqs) {
-    uint32_t nt = v.G * v.G;
-    bool bad = acc[v.q].err != 0;
-    for (uint32_t t = 0; t < nt; ++t) {
-      uint64_t row = (uint64_t)v.tile0 + t;
-      if (labels) labels[row] = bad ? -1.f : (float)lab[row];
-      if (ids) {
-        ids[row * 4 + 0] = v.q;
-        ids[row * 4 + 1] = v.sigma;
-        ids[row * 4 + 2] = t / v.G;
-        ids[row * 4 + 3] = t % v.G;
-      }
-    }
-  }
-  return RD_OK;
-}
-
-namespace {
-struct MlpDev {
-  float *w, *g, *m, *v, *loss;
-};
-int mlp_dev(rd_context* ctx, MlpDev& d) {
-  int merr = 0;
-  const size_t nw = (size_t)mlp_num_weights() * 4;
-  d.w = (float*)ctx->ensure("mlp_w", nw, &merr);
-  d.g = (float*)ctx->ensure("mlp_g", nw, &merr);
-  d.m = (float*)ctx->ensure("mlp_m", nw, &merr);
-  d.v = (float*)ctx->ensure("mlp_v", nw, &merr);
-  d.loss = (float*)ctx->ensure("mlp_loss", 256, &merr);
-  return merr;
-}
-}  // namespace
-
-int rd_mlp_forward(rd_context* ctx, const rd_mlp* w, const float* X, uint64_t n,
-                   float* logits, void* stream) {
-  if (!ctx || !w || (n && (!X || !logits))) return RD_EINVAL;
-  if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
-  hipStream_t st = (hipStream_t)stream;
-  MlpDev d;
-  int merr = mlp_dev(ctx, d);
-  float* dx = (float*)ctx->ensure("mlp_x", n * 32 * 4, &merr);
-  float* dz = (float*)ctx->ensure("mlp_z", n * 4, &merr);
-  if (merr) return merr;
-  TRY_HIP(hipMemcpyAsync(d.w, w, (size_t)mlp_num_weights() * 4, hipMemcpyHostToDevice, st));
-  if (n) TRY_HIP(hipMemcpyAsync(dx, X, n * 32 * 4, hipMemcpyHostToDevice, st));
-  if (launch_mlp_forward(st, dx, n, d.w, dz)) return RD_EDEVICE;
-  if (n) TRY_HIP(hipMemcpyAsync(logits, dz, n * 4, hipMemcpyDeviceToHost, st));
-  TRY_HIP(hipStreamSynchronize(st));
-  return RD_OK;
-}
-
-int rd_mlp_grad(rd_context* ctx, const rd_mlp* w, const float* X, const float* Y,
-                uint64_t n, rd_mlp* grad, float* loss, void* stream) {
-  if (!ctx || !w || !grad || !loss || (n && (!X || !Y))) return RD_EINVAL;
-  if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
-  hipStream_t st = (hipStream_t)stream;
-  MlpDev d;
-  int merr = mlp_dev(ctx, d);
-  float* dx = (float*)ctx->ensure("mlp_x", n * 32 * 4, &merr);
-  float* dy = (float*)ctx->ensure("mlp_y", n * 4, &merr);
-  if (merr) return merr;
-  const size_t nw = (size_t)mlp_num_weights() * 4;
-  TRY_HIP(hipMemcpyAsync(d.w, w, nw, hipMemcpyHostToDevice, st));
-  TRY_HIP(hipMemsetAsync(d.g, 0, nw, st));
-  TRY_HIP(hipMemsetAsync(d.loss, 0, 4, st));
-  if (n) {
-    TRY_HIP(hipMemcpyAsync(dx, X, n * 32 * 4, hipMemcpyHostToDevice, st));
-    TRY_HIP(hipMemcpyAsync(dy, Y, n * 4, hipMemcpyHostToDevice, st));
-  }
-  if (launch_mlp_grad(st, dx, dy, n, d.w, d.g, d.loss)) return RD_EDEVICE;
-  TRY_HIP(hipMemcpyAsync(grad, d.g, nw, hipMemcpyDeviceToHost, st));
-  TRY_HIP(hipMemcpyAsync(loss, d.loss, 4, hipMemcpyDeviceToHost, st));
-  TRY_HIP(hipStreamSynchronize(st));
-  return RD_OK;
-}
-
-int rd_mlp_train(rd_context* ctx, rd_mlp* w, const float* X, const float* Y,
-                 uint64_t n, uint32_t epochs, uint32_t batch, float lr,
-                 uint64_t seed, float* epoch_loss, void* stream) {
-  if (!ctx || !w || !n || !X || !Y || !batch || !epochs) return RD_EINVAL;
-  if (hipSetDevice(ctx->device) != hipSuccess) return RD_EDEVICE;
-  hipStream_t st = (hipStream_t)stream;
-  MlpDev d;
-  int merr = mlp_dev(ctx, d);
-  float* dx = (float*)ctx->ensure("mlp_x", n * 32 * 4, &merr);
-  float* dy = (float*)ctx->ensure("mlp_y", n * 4, &merr);
-  if (merr) return merr;
-  const size_t nw = (size_t)mlp_num_weights() * 4;
-  TRY_HIP(hipMemcpyAsync(d.w, w, nw, hipMemcpyHostToDevice, st));
-  TRY_HIP(hipMemsetAsync(d.g, 0, nw, st));
-  TRY_HIP(hipMemsetAsync(d.m, 0, nw, st));
-  TRY_HIP(hipMemsetAsync(d.v, 0, nw, st));
-  std::vector<uint64_t> perm(n);
-  for (uint64_t i = 0; i < n; ++i) perm[i] = i;
-  std::vector<float> xs(n * 32), ys(n);
-  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
-  int t = 0;
-  for (uint32_t e = 0; e < epochs; ++e) {
-    for (uint64_t i = n - 1; i > 0; --i) {  // Fisher-Yates with xorshift64
-      x ^= x << 13; x ^= x >> 7; x ^= x << 17;
-      uint64_t j = x % (i + 1);
-      std::swap(perm[i], perm[j]);
-    }
-    for (uint64_t i = 0; i < n; ++i) {
-      memcpy(&xs[i * 32], &X[perm[i] * 32], 32 * 4);
-      ys[i] = Y[perm[i]];
-    }
-    TRY_HIP(hipMemcpyAsync(dx, xs.data(), n * 32 * 4, hipMemcpyHostToDevice, st));
-    TRY_HIP(hipMemcpyAsync(dy, ys.data(), n * 4, hipMemcpyHostToDevice, st));
-    TRY_HIP(hipMemsetAsync(d.loss, 0, 4, st));
-    uint64_t nb = 0;
-    for (uint64_t off = 0; off < n; off += batch, ++nb) {
-      uint64_t m = std::min<uint64_t>(batch, n - off);
-      if (launch_mlp_grad(st, dx + off * 32, dy + off, m, d.w, d.g, d.loss) ||
-          launch_adam(st, d.w, d.g, d.m, d.v, lr, ++t))
-        return RD_EDEVICE;
-    }
-    float l = 0;
-    TRY_HIP(hipMemcpyAsync(&l, d.loss, 4, hipMemcpyDeviceToHost, st));
-    TRY_HIP(hipStreamSynchronize(st));
-    if (epoch_loss) epoch_loss[e] = l / (float)nb;
-  }
-  TRY_HIP(hipMemcpyAsync(w, d.w, nw, hipMemcpyDeviceToHost, st));
-  TRY_HIP(hipStreamSynchronize(st));
-  return RD_OK;
-}
-
-int rd_prefilter_selftest(const rd_kernel_model* models, uint32_t n_models,
-                          const rd_launch_domain* launch, const rd_param_sets* params,
-                          uint32_t model, uint32_t access_a, uint32_t access_b,
-                          uint32_t set, uint32_t* decided) {
-  if (!models || !launch || !params || !decided || model >= n_models) return RD_EINVAL;
-  const rd_kernel_model& M = models[model];
-  if (access_a >= M.n_acc || access_b >= M.n_acc || set >= params[model].n_sets)
-    return RD_EINVAL;
-  *decided = 0;
-  if (check_access(M, M.acc[access_a]) || check_access(M, M.acc[access_b])) return 2;
-  Planner P;
-  P.models = models;
-  P.launch = launch;
-  P.params = params;
-  P.dims.resize(n_models);
-  P.dims[model].resize(params[model].n_sets);
-  InstInfo& ia = P.inst(model, access_a, set);
-  InstInfo& ib = P.inst(model, access_b, set);
-  if (ia.err || ib.err || ia.idx < 0 || ib.idx < 0) return 2;
-  if (ia.idx != ib.idx) *decided = P.apart(ia.idx, ib.idx) ? 1u : 0u;
-  // the unit filter's second test: one expression, thread-injective
-  if (same_addr_expr(M, access_a, access_b) && P.tabs[ia.idx].on && P.tabs[ib.idx].on &&
-      P.tinj[ia.idx] && P.tinj[ib.idx])
-    *decided |= 2u;
-  return RD_OK;
-}
-
-int rd_table_selftest(const rd_kernel_model* models, uint32_t n_models,
-                      const rd_launch_domain* launch, const rd_param_sets* params,
-                      uint32_t model, uint32_t access, uint32_t set,
-                      uint64_t max_points, uint64_t* n_checked) {
-  if (!models || !launch || !params || model >= n_models) return RD_EINVAL;
-  if (access >= models[model].n_acc || set >= params[model].n_sets) return RD_EINVAL;
-  if (check_access(models[model], models[model].acc[access])) return 2;
-  Planner P;
-  P.models = models;
-  P.launch = launch;
-  P.params = params;
-  P.dims.resize(n_models);
-  P.dims[model].resize(params[model].n_sets);
-  InstInfo& ii = P.inst(model, access, set);
-  if (ii.err || ii.idx < 0) return 2;
-  const AccInst& I = P.dev_insts[ii.idx];
-  const TabHost& T = P.tabs[ii.idx];
-  if (!T.on) return 1;
-  // fill the tables as the device does
-  std::vector<int64_t> pool(P.tpool + 1);
-  const int64_t* pr = P.pool_params.data() + I.params_off;
-  int64_t c[10];
-  for (const TabJob& J : P.tjobs) {
-    for (uint32_t e = 0; e < J.n; ++e) {
-      host_coords(I, P.pool_loops, J.group == 0 ? e : 0, J.group == 1 ? e : 0,
-                  J.group >= 2 ? e : 0, c);
-      uint32_t err = 0;
-      int64_t v;
-      if (J.group == 3) {
-        v = host_prog(P.code, I.bint, c, pr, 0, err) |
-            (host_prog(P.code, I.wint, c, pr, 0, err) << 16);
-      } else {
-        bool g = J.guard.absent || host_prog(P.code, J.guard, c, pr, 1, err) != 0;
-        v = g ? host_prog(P.code, J.val, c, pr, 0, err) : INT64_MIN;
-      }
-      if (err) return -2;  // a table program failed: the proof was wrong
-      pool[J.out_off + e] = v;
-    }
-  }
-  // every box point: tables against the interpreter on the original programs
-  const uint64_t npts = std::min<uint64_t>(I.npts, max_points ? max_points : I.npts);
-  for (uint64_t k = 0; k < npts; ++k) {
-    const uint64_t pidx = I.npts <= max_points || !max_points
-                              ? k : (k * 2654435761ull) % I.npts;
-    const uint32_t tlin = (uint32_t)(pidx % I.nthr);
-    const uint32_t rest = (uint32_t)(pidx / I.nthr);
-    const uint32_t ilin = rest % I.niota, blin = rest / I.niota;
-    host_coords(I, P.pool_loops, blin, tlin, ilin, c);
-    uint32_t err = 0;
-    const bool g0 = host_prog(P.code, I.guard, c, pr, 1, err) != 0;
-    int64_t a0 = 0, b0 = 0, w0 = 0;
-    if (g0) {
-      a0 = host_prog(P.code, I.addr, c, pr, 0, err);
-      b0 = host_prog(P.code, I.bint, c, pr, 0, err);
-      w0 = host_prog(P.code, I.wint, c, pr, 0, err);
-      if (I.is32 && (a0 < INT32_MIN || a0 > INT32_MAX)) err |= ERR_RANGE;
-      if (b0 < 0 || b0 > 65535 || w0 < 0 || w0 > 65535) err |= ERR_UNSUP;
-    }
-    if (err) return -3;  // the interpreter fails where tables were allowed
-    bool g1 = !T.never;
-    int64_t a1 = T.u;
-    const uint32_t gi[3] = {blin, tlin, ilin};
-    for (int g = 0; g < 3 && g1; ++g) {
-      if (T.off[g] == kNoTab) continue;
-      const int64_t v = pool[T.base + T.off[g] + gi[g]];
-      if (v == INT64_MIN) g1 = false;
-      else a1 += v;
-    }
-    if (g0 != g1) return -4;
-    if (g0) {
-      const uint32_t iv = T.iv_off != kNoTab ? (uint32_t)pool[T.base + T.iv_off + ilin] : T.iv_const;
-      if (a0 != a1) return -5;
-      if ((uint32_t)b0 != (iv & 0xFFFF) || (uint32_t)w0 != (iv >> 16)) return -6;
-    }
-  }
-  if (n_checked) *n_checked = npts;
-  return 0;
-}
-
-int rd_selftest(void) {
-  // constant-divisor helper used by the kernels: numerators below 2^31
-  static const uint32_t ds[] = {1, 2, 3, 5, 7, 10, 31, 32, 33, 63, 64, 100,
-                                255, 256, 257, 1000, 1023, 1024, 4095, 65535,
-                                65536, 65537, 1000003, 16777216, 67108863};
-  static const uint32_t ns[] = {0, 1, 2, 3, 1023, 1024, 65535, 65536,
-                                1000000, 16777215, 2147483646u, 2147483647u};
-  for (uint32_t d : ds) {
-    for (uint32_t n : ns)
-      if (!fastdiv_check(n, d)) return -1;
-    for (uint32_t k = 0; k < 4096; ++k) {
-      uint64_t n = (uint64_t)k * d + (k % 3 == 0 ? 0 : k % 3 == 1 ? d - 1 : d / 2);
-      if (n < (1ull << 31) && !fastdiv_check((uint32_t)n, d)) return -1;
-    }
-  }
-  uint64_t x = 88172645463325252ull;
-  for (int k = 0; k < 1000000; ++k) {
-    x ^= x << 13; x ^= x >> 7; x ^= x << 17;
-    uint32_t d = (uint32_t)(x % 67108863u) + 1;
-    uint32_t n = (uint32_t)(x >> 33);
-    if (!fastdiv_check(n, d)) return -1;
-  }
-  return 0;
-}
-
-}  // extern "C"
