@@ -350,6 +350,28 @@ class Packed:
             self.keep += [ins, arrays, loops, accs, vals]
         self.n_models = n
 
+    @classmethod
+    def concat(cls, packs):
+        """One image of several images' models, in order: model k of
+        packs[j] becomes model sum(len(packs[:j])) + k (the parts keep
+        owning the arrays the models point to; the result keeps them)."""
+        self = cls.__new__(cls)
+        n = sum(p.n_models for p in packs)
+        self.keep = list(packs)
+        self.extra = {}
+        self.models = (rd_kernel_model * max(1, n))()
+        self.launch = (rd_launch_domain * max(1, n))()
+        self.params = (rd_param_sets * max(1, n))()
+        k = 0
+        for p in packs:
+            for i in range(p.n_models):
+                self.models[k] = p.models[i]
+                self.launch[k] = p.launch[i]
+                self.params[k] = p.params[i]
+                k += 1
+        self.n_models = n
+        return self
+
 
 def _stream_handle(stream):
     if stream is not None:
@@ -397,6 +419,7 @@ class Plan:
         self.ctx = ctx
         self.n = len(workload.pairs)
         pk = Packed(workload)
+        self.packed = pk
         pairs = _pairs(workload)
         opt, keep = _options(mode, order, lds_cap, max_device_bytes, log_level,
                              stream, mlp, tile_budget, prefilter)

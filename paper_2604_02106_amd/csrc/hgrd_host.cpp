@@ -66,6 +66,7 @@ int rd_context_create(rd_context** ctx, int hip_device) {
 
 void rd_context_destroy(rd_context* ctx) {
   if (!ctx) return;
+  rd_context_destroy(ctx->aux);
   (void)hipSetDevice(ctx->device);
   for (auto& kv : ctx->bufs)
     if (kv.second.p && kv.second.own) (void)hipFree(kv.second.p);
@@ -837,9 +838,13 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     evals[k] = Q[k].evals;
     plan->evals += Q[k].evals;
   }
+  // copies on the plan's stream, finished before the source may go (the
+  // null stream would also wait for other contexts' work on the device)
   auto up = [&](const char* name, const void* src, size_t bytes) -> void* {
     void* d = plan->buf(name, bytes, &merr);
-    if (d && bytes && hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+    if (d && bytes &&
+        (hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, plan->st) != hipSuccess ||
+         hipStreamSynchronize(plan->st) != hipSuccess))
       merr = RD_EDEVICE;
     return d;
   };
@@ -1629,7 +1634,8 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
     (void)hipEventElapsedTime(&ms, ev[7], ev[8]);
     fallback_ms += ms;
     std::vector<uint32_t> written(nf);
-    TRY_HIP(hipMemcpy(written.data(), gcount, nf * 4, hipMemcpyDeviceToHost));
+    TRY_HIP(hipMemcpyAsync(written.data(), gcount, nf * 4, hipMemcpyDeviceToHost, st));
+    TRY_HIP(hipStreamSynchronize(st));
     for (uint32_t w : written) S.fallback_groups += w;
     fpos = fend;
   }
@@ -1714,17 +1720,64 @@ int rd_execute(rd_context* ctx, rd_plan* plan, rd_pair_result* out) {
   return RD_OK;
 }
 
+// More pairs than one batch: consecutive batches of pairs, each prepared
+// and executed as a plan of its own (a pair's result does not depend on
+// the other pairs of its plan).  Batch k + 1 is prepared on a host thread,
+// on a second context of the same device that ctx keeps, while batch k
+// executes: the host lowering and the descriptor uploads of one batch
+// overlap the device work of the other, and each context serves one
+// thread at a time.  The stats are the sums over the batches, total_ms
+// the whole call.
 int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
                    uint32_t n_models, const rd_access_pair* pairs,
                    uint32_t n_pairs, const rd_launch_domain* launch,
                    const rd_param_sets* params, const rd_options* opt,
                    rd_pair_result* out) {
+  if (!ctx) return RD_EINVAL;
   if (n_pairs && !out) return RD_EINVAL;
-  rd_plan* plan = nullptr;
-  int rc = rd_prepare(ctx, models, n_models, pairs, n_pairs, launch, params, opt, &plan);
-  if (rc != RD_OK) return rc;
-  rc = rd_execute(ctx, plan, out);
-  rd_plan_destroy(plan);
+  uint64_t B = kBatchPairs;
+  if (const char* e = getenv("HGRD_BATCH_PAIRS")) B = strtoull(e, nullptr, 10);
+  if (B == 0 || n_pairs <= B || ctx->arena || (opt && opt->stream) || !pairs) {
+    rd_plan* plan = nullptr;
+    int rc = rd_prepare(ctx, models, n_models, pairs, n_pairs, launch, params, opt, &plan);
+    if (rc != RD_OK) return rc;
+    rc = rd_execute(ctx, plan, out);
+    rd_plan_destroy(plan);
+    return rc;
+  }
+  const double t0 = now_ms();
+  if (!ctx->aux) {
+    const int rc = rd_context_create(&ctx->aux, ctx->device);
+    if (rc != RD_OK) return rc;
+  }
+  ctx->aux->cfg = ctx->cfg;
+  ctx->aux->wave_bytes = ctx->wave_bytes;
+  rd_context* C[2] = {ctx, ctx->aux};
+  rd_stats total;
+  memset(&total, 0, sizeof total);
+  const uint32_t nb = (uint32_t)((n_pairs + B - 1) / B);
+  auto count = [&](uint32_t k) { return (uint32_t)std::min<uint64_t>(B, n_pairs - k * B); };
+  rd_plan* cur = nullptr;
+  int rc = rd_prepare(C[0], models, n_models, pairs, count(0), launch, params, opt, &cur);
+  for (uint32_t k = 0; rc == RD_OK && k < nb; ++k) {
+    rd_plan* next = nullptr;
+    int rc_next = RD_OK;
+    std::thread th;
+    if (k + 1 < nb)
+      th = std::thread([&, k] {
+        rc_next = rd_prepare(C[(k + 1) & 1], models, n_models, pairs + (k + 1) * B, count(k + 1),
+                             launch, params, opt, &next);
+      });
+    rc = rd_execute(C[k & 1], cur, out + k * B);
+    add_stats(total, C[k & 1]->stats);
+    rd_plan_destroy(cur);
+    if (th.joinable()) th.join();
+    if (rc == RD_OK) rc = rc_next;
+    cur = next;
+  }
+  if (cur) rd_plan_destroy(cur);
+  total.total_ms = now_ms() - t0;
+  ctx->stats = total;
   return rc;
 }
 

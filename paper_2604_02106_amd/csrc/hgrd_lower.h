@@ -452,6 +452,31 @@ void set_bucket_map(HItem& h, const std::vector<uint8_t>& tab_on,
   h.fm = ~0ull / nb + 1;
 }
 
+// Pairs per plan of a pipelined rd_check_pairs (HGRD_BATCH_PAIRS overrides
+// it; 0: one plan for every pair).
+constexpr uint64_t kBatchPairs = 4096;
+
+// Sums the stats of one batch into `a` (every field is a count or a
+// duration).
+void add_stats(rd_stats& a, const rd_stats& b) {
+  static_assert(sizeof(rd_stats) == 41 * 8, "rd_stats: sum every field");
+#define HGRD_ADD(f) a.f += b.f
+  HGRD_ADD(total_ms); HGRD_ADD(device_ms); HGRD_ADD(join_ms); HGRD_ADD(scatter_ms);
+  HGRD_ADD(witness_ms); HGRD_ADD(evals); HGRD_ADD(records); HGRD_ADD(small_items);
+  HGRD_ADD(hbm_items); HGRD_ADD(overflow_items); HGRD_ADD(buckets);
+  HGRD_ADD(join_launches); HGRD_ADD(join_kernel_ms); HGRD_ADD(small_ms);
+  HGRD_ADD(bucket_ms); HGRD_ADD(fallback_ms); HGRD_ADD(retry_ms); HGRD_ADD(retry_items);
+  HGRD_ADD(waves_ms); HGRD_ADD(verdict_ms); HGRD_ADD(verdict_units); HGRD_ADD(split_ms);
+  HGRD_ADD(split_items); HGRD_ADD(scatter_launches); HGRD_ADD(scatter_bytes);
+  HGRD_ADD(fallback_records); HGRD_ADD(scatter_tab_ms); HGRD_ADD(scatter_tab_bytes);
+  HGRD_ADD(prefiltered); HGRD_ADD(join_tab_launches); HGRD_ADD(join_tab_ms);
+  HGRD_ADD(join_tab_bytes); HGRD_ADD(presplit_items); HGRD_ADD(filter_tab_launches);
+  HGRD_ADD(filter_tab_ms); HGRD_ADD(filter_tab_bytes); HGRD_ADD(units_apart);
+  HGRD_ADD(block_symmetric); HGRD_ADD(fallback_groups); HGRD_ADD(sync_records);
+  HGRD_ADD(sync_decided);
+#undef HGRD_ADD
+}
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
              std::chrono::steady_clock::now().time_since_epoch())
@@ -495,6 +520,9 @@ struct rd_context {
     return b.p;
   }
   rd_stats stats;
+  // second context of the same device: rd_check_pairs prepares the next
+  // batch of pairs on it while the current one executes here
+  rd_context* aux = nullptr;
   int cfg = 0;  // LDS tile shape: 1024 records, 2048 slots (rd_autotune may change it)
   uint32_t n_cu = 256;
   uint64_t wave_bytes = kWaveBytes;  // default partition wave size

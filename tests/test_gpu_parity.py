@@ -265,6 +265,27 @@ def test_mixed_config_small(hg):
     assert any(r["verdict"] for r in got)
 
 
+def test_pipelined_batches_match_one_plan(hg, monkeypatch):
+    """rd_check_pairs with more pairs than one batch prepares batch k + 1 on
+    a second context while batch k executes: every field equals the
+    oracle's and the one-plan results at several batch sizes, and the
+    stats are the sums over the batches."""
+    wl = configs.mixed(seed=97, n_queries=240, log2_max=17)
+    want, _ = oracle.check_pairs(wl, "B", threads=8)
+    monkeypatch.setenv("HGRD_BATCH_PAIRS", "0")
+    say("one plan", len(wl.pairs))
+    compare(hg.check_pairs(wl), want, "one plan")
+    one = hg.default_context().stats()
+    for b in ("37", "100", "239"):
+        monkeypatch.setenv("HGRD_BATCH_PAIRS", b)
+        say("batches of", b)
+        compare(hg.check_pairs(wl), want, "batches of " + b)
+        st = hg.default_context().stats()
+        for k in ("evals", "small_items", "hbm_items", "units_apart", "block_symmetric"):
+            assert st[k] == one[k], (b, k, st[k], one[k])
+        assert st["total_ms"] > 0
+
+
 def test_prefilter_is_exact(hg):
     """The interval pre-filter decides (pair, tuple) units whose address
     ranges cannot meet; every field stays equal to the oracle's."""

@@ -42,6 +42,29 @@ def test_struct_sizes():
     assert C.sizeof(hg.rd_sync) == 16
     assert C.sizeof(hg.rd_options) == 48
     assert C.sizeof(hg.rd_mlp) == 4 * 6337
+    assert C.sizeof(hg.rd_stats) == 41 * 8
+
+
+def test_packed_concat_keeps_every_model():
+    """Packed.concat lays several images' models end to end: each model's
+    descriptor and the instructions it points to are the part's."""
+    import paper_2604_02106_amd as hg
+    from workloads import configs
+    wl = configs.mixed(seed=11, n_queries=40, log2_max=12)
+    parts = [hg.Packed(wl.compact(range(0, 17))), hg.Packed(wl.compact(range(17, 40)))]
+    pk = hg.Packed.concat(parts)
+    assert pk.n_models == parts[0].n_models + parts[1].n_models
+    k = 0
+    for p in parts:
+        for i in range(p.n_models):
+            a, b = pk.models[k], p.models[i]
+            assert (a.n_insns, a.n_arrays, a.n_loops, a.n_acc, a.n_params) == \
+                   (b.n_insns, b.n_arrays, b.n_loops, b.n_acc, b.n_params)
+            assert [(a.insns[j].op, a.insns[j].imm) for j in range(a.n_insns)] == \
+                   [(b.insns[j].op, b.insns[j].imm) for j in range(b.n_insns)]
+            assert pk.launch[k].warp_size == p.launch[i].warp_size
+            assert pk.params[k].n_sets == p.params[i].n_sets
+            k += 1
 
 
 def test_no_device_fails_loudly():
