@@ -48,8 +48,8 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_02106_amd", "csrc", f)
 LIMITER = {
     "k_bucket_join<1024, 2048, true, false>":
         "LDS hash joins level by level with workgroup barriers between levels "
-        "(latency- and barrier-bound, not HBM: counters read 0.70x the record "
-        "bytes from HBM)",
+        "(latency- and barrier-bound, not HBM: waves wait about half their "
+        "cycles, scalar instructions outnumber vector ones)",
     "k_scatter<true>": "vector ALU issue (decode, table lookups, bucket map, run claims)",
     "k_bucket_filter<1024>": "LDS hash probes per record",
 }
@@ -227,11 +227,15 @@ def kernel_rooflines(stats, traffic_files=None):
         tfile = (traffic_files or {}).get(name)
         # priced against HBM: records are the kernel's only HBM traffic; what
         # holds it below that bound is stated in "limiter"
+        traffic = measured_traffic(tfile) if tfile else None
+        limiter = LIMITER.get(name)
+        if traffic and limiter:
+            limiter += "; counters: HBM traffic %.2fx the record bytes" % (traffic / per_launch)
         out[name] = {"bound": "hbm", "kernel": name, "achieved": achieved,
-                     "limiter": LIMITER.get(name),
+                     "limiter": limiter,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(tfile) if tfile else None,
+                     "traffic": traffic,
                      "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms,
                      "launches_per_step": launches / len(stats),
                      "ms_per_step": ms / len(stats), "work": what}

@@ -396,7 +396,15 @@ int rd_context_create(rd_context** ctx, int hip_device);
 void rd_context_destroy(rd_context* ctx);
 
 /* Decides every pair (see the conventions above).  `launch` and `params`
- * are per model.  `opt` may be NULL.  `out` has n_pairs entries. */
+ * are per model.  `opt` may be NULL.  `out` has n_pairs entries.
+ * More than 4096 pairs (the environment variable HGRD_BATCH_PAIRS sets
+ * the batch; 0 turns batching off) are decided in consecutive batches of
+ * pairs, each its own plan: batch k + 1 is prepared on a host thread, on a
+ * second context of the same device that ctx creates on first use and
+ * keeps until rd_context_destroy, while batch k runs on ctx's stream, so
+ * host lowering overlaps device work.  Not when opt->stream is set (one
+ * plan, in stream order).  The results are those of one plan; rd_get_stats
+ * then reports the sums over the batches (total_ms: the whole call). */
 int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
                    uint32_t n_models, const rd_access_pair* pairs,
                    uint32_t n_pairs, const rd_launch_domain* launch,
