@@ -64,9 +64,10 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def measured_traffic(path):
-    """HBM bytes per launch of a kernel from its committed counter summary,
-    if it was taken on the current kernel sources (else None)."""
+def measured_traffic(path, field="traffic bytes per launch"):
+    """HBM bytes per launch of a kernel from its committed counter summary
+    (or another figure of it), if it was taken on the current kernel
+    sources (else None)."""
     try:
         text = open(path).read()
     except OSError:
@@ -79,7 +80,7 @@ def measured_traffic(path):
     if fields.get("source digest") != kernel_digest():
         return None
     try:
-        return float(fields["traffic bytes per launch"])
+        return float(fields[field])
     except (KeyError, ValueError):
         return None
 
@@ -228,9 +229,11 @@ def kernel_rooflines(stats, traffic_files=None):
         # priced against HBM: records are the kernel's only HBM traffic; what
         # holds it below that bound is stated in "limiter"
         traffic = measured_traffic(tfile) if tfile else None
+        alg = measured_traffic(tfile, "algorithmic bytes per launch (same steps)") \
+            if tfile else None
         limiter = LIMITER.get(name)
-        if traffic and limiter:
-            limiter += "; counters: HBM traffic %.2fx the record bytes" % (traffic / per_launch)
+        if traffic and alg and limiter:
+            limiter += "; counters: HBM traffic %.2fx the record bytes" % (traffic / alg)
         out[name] = {"bound": "hbm", "kernel": name, "achieved": achieved,
                      "limiter": limiter,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
