@@ -3,6 +3,7 @@
 // prefix-group join.  See hgrd_kernels.hip for the method.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 #include <string.h>
 #include "hgrd_internal.h"
@@ -541,6 +542,18 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
   const bool same2 = (qd.flags & 1) && ((used >> 1) & 1) && ((used >> 2) & 1);
   const bool same4 = (qd.flags & 2) && ((used >> 3) & 1) && ((used >> 4) & 1);
   u64 Sl[6] = {0, 0, 0, 0, 0, 0};
+  // The table holds one 64-bit word per slot: side-a (self: every) count in
+  // bits 0-15, side-b count in 16-31, owner record in 32-43, generation in
+  // 44-47, the two-thread mark in bit 48.  Every level (and synchronisation
+  // pass) joins with a generation of its own, so a word of an older one is
+  // an empty slot: the table is cleared once per call, not per level, and a
+  // level's keys are written during the previous level's count pass.
+  static_assert(CAP <= 4096, "owner field");
+  using JL = JoinLds<CAP, TBL>;
+  static_assert(offsetof(JL, owner) % 8 == 0 && offsetof(JL, cnt) == offsetof(JL, owner) + 4 * TBL,
+                "owner and cnt form TBL aligned 64-bit words");
+  u64* slot = reinterpret_cast<u64*>(S.owner);  // owner and cnt: TBL words
+  uint32_t gen = 0;
   // per record of this thread: tli (kInactive also past the end) and the
   // table slot of its group at the last computed level
   uint32_t tl[RPT], gid[RPT];
@@ -551,25 +564,63 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
     gid[j] = 0;
     if (!l0ext && r < n) S.part[r] = 0;
   }
+  for (uint32_t k = tid; k < TBL; k += NT) slot[k] = 0;
   if (tid == 0) S.vote[2] = 0;  // the filter level's vote (after a barrier)
+  // levels computed (not skipped as equal to the previous one) and whose
+  // key is the previous computed level's slot and the one field they add
+  // (a skipped level between adds a field that is one constant for every
+  // record)
+  bool comp[6], incl[6];
+  {
+    int P = -1;
+    for (int L = 0; L < 6; ++L) {
+      comp[L] = ((used >> L) & 1) && !((L == 2 && same2) || (L == 4 && same4));
+      incl[L] = comp[L] && P >= 0 &&
+                (L == P + 1 || (L == 3 && P == 1 && same2) || (L == 5 && P == 3 && same4));
+      if (comp[L]) P = L;
+    }
+  }
+  // one record's field at level L (the part its key adds to the previous
+  // level's slot)
+  auto field = [&](int L, uint32_t r, uint32_t t) -> uint32_t {
+    if (L == 2) return S.bw[r] >> 16;
+    if (L == 3) return S.w[r];
+    if (L == 4) return S.bw[r] & 0xFFFF;
+    if (L == 5) return t & 0x3FF;
+    return 0;  // L == 1: the block is compared beside the key
+  };
+  // inserts record r with key test eq(owner) from slot h on; returns the
+  // group's slot (the first record of a group claims an empty slot with its
+  // count, the others add theirs)
+  auto insert = [&](uint32_t h, uint32_t r, u64 add, auto&& eq) -> uint32_t {
+    const u64 mine = ((u64)gen << 44) | ((u64)r << 32) | add;
+    u64 o = slot[h];
+    for (;;) {
+      if (((uint32_t)(o >> 44) & 0xF) != gen) {
+        const u64 prev = atomicCAS(&slot[h], o, mine);
+        if (prev == o) return h;
+        o = prev;  // claimed meanwhile (a claim is final within a level)
+        continue;
+      }
+      if (eq((uint32_t)(o >> 32) & 0xFFF)) {
+        atomicAdd(&slot[h], add);
+        return h;
+      }
+      h = (h + 1) & (TBL - 1);
+      o = slot[h];
+    }
+  };
+  __syncthreads();
   u64 Tl[6] = {0, 0, 0, 0, 0, 0};
-  // synchronised pairs of level L (SYN): groups (S_L slot, sync address)
+  // synchronised pairs of level L (SYN): groups (S_L slot, sync address);
+  // a record's S_L slot is its key >> 16 (written in that level's count
+  // pass)
   auto tpass = [&](int L) {
     const uint32_t cls = L < 2 ? 1u : (L < 4 ? 2u : 4u);
     const uint32_t need = L < 2 ? (qd.flags & 16u) : (qd.flags & 8u);
     const uint32_t bit = L < 2 ? kSynDevBit : kSynBlkBit;
     if (!(cls & mask) || !need) return;
-    for (uint32_t k = tid; k < TBL; k += NT) {
-      S.owner[k] = kEmpty;
-      S.cnt[k] = 0;
-    }
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      const uint32_t r = tid + (uint32_t)j * NT;
-      if ((tl[j] & kInactive) || !(tl[j] & bit)) continue;
-      S.key[r] = gid[j];
-    }
-    __syncthreads();
+    ++gen;
     uint32_t tg[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
@@ -577,14 +628,10 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
       tg[j] = kEmpty;
       if ((tl[j] & kInactive) || !(tl[j] & bit)) continue;
       const u64 v = skey[r];
-      uint32_t h = key_slot(gid[j], (uint32_t)v ^ (uint32_t)(v >> 32), TBL);
-      for (;;) {
-        const uint32_t o = atomicCAS(&S.owner[h], kEmpty, r);
-        if (o == kEmpty || (S.key[o] == gid[j] && skey[o] == v)) break;
-        h = (h + 1) & (TBL - 1);
-      }
-      atomicAdd(&S.cnt[h], (self || !(tl[j] & kSide)) ? 1u : 0x10000u);
-      tg[j] = h;
+      const uint32_t g = gid[j];
+      tg[j] = insert(key_slot(g, (uint32_t)v ^ (uint32_t)(v >> 32), TBL), r,
+                     (self || !(tl[j] & kSide)) ? 1ull : 0x10000ull,
+                     [&](uint32_t o) { return (S.key[o] >> 16) == g && skey[o] == v; });
     }
     __syncthreads();
     const int sign = (L & 1) ? -1 : 1;
@@ -593,7 +640,7 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
     for (int j = 0; j < RPT; ++j) {
       const uint32_t r = tid + (uint32_t)j * NT;
       if (tg[j] == kEmpty) continue;
-      const uint32_t c = S.cnt[tg[j]];
+      const uint32_t c = (uint32_t)slot[tg[j]];
       if (!self && (tl[j] & kSide)) continue;
       const uint32_t nj = self ? (c & 0xFFFF) : (c >> 16);
       t += nj;
@@ -603,78 +650,53 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
     __syncthreads();
   };
   bool any = true;
-  int P = -1;  // last computed level
   for (int L = 0; L < 6; ++L) {
     if (!((used >> L) & 1)) continue;
-    if ((L == 2 && same2) || (L == 4 && same4)) {
+    if (!comp[L]) {
       Sl[L] = Sl[L - 1];
       // the level's groups are the previous level's: its slots stand
       if (SYN) tpass(L);
       continue;
     }
     const bool twin = (L == 1 && same2) || (L == 3 && same4);
-    // incremental key: L adds one field to P (a skipped level between adds
-    // a field that is one constant for every record)
-    const bool inc = P >= 0 && (L == P + 1 || (L == 3 && P == 1 && same2) ||
-                                (L == 5 && P == 3 && same4));
-    for (uint32_t k = tid; k < TBL; k += NT) {
-      S.owner[k] = kEmpty;
-      S.cnt[k] = 0;
-    }
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      const uint32_t r = tid + (uint32_t)j * NT;
-      if ((tl[j] & kInactive) || !inc) continue;
-      uint32_t fld;
-      if (L == 1) {
-        fld = 0;
-      } else if (L == 2) {
-        fld = S.bw[r] >> 16;
-      } else if (L == 3) {
-        fld = S.w[r];
-      } else if (L == 4) {
-        fld = S.bw[r] & 0xFFFF;
-      } else {
-        fld = tl[j] & 0x3FF;
-      }
-      S.key[r] = (gid[j] << 16) | fld;
-    }
-    __syncthreads();
+    const bool inc = incl[L];
+    ++gen;
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const uint32_t r = tid + (uint32_t)j * NT;
       if (tl[j] & kInactive) continue;
-      const uint32_t kr = inc ? S.key[r] : 0u;
-      const uint32_t kb = inc && L == 1 ? S.blin[r] : 0u;
-      uint32_t h = inc ? key_slot(kr, kb, TBL)
-                       : level_hash(L, S.addr[r], S.blin[r], S.bw[r], S.w[r],
-                                    tl[j] & 0x3FF) & (TBL - 1);
-      for (;;) {
-        const uint32_t o = atomicCAS(&S.owner[h], kEmpty, r);
-        if (o == kEmpty) break;
-        if (inc ? (S.key[o] == kr && (L != 1 || S.blin[o] == kb))
-                : level_eq(S, L, o, r))
-          break;
-        h = (h + 1) & (TBL - 1);
+      const u64 add = (self || !(tl[j] & kSide)) ? 1ull : 0x10000ull;
+      if (inc) {
+        const uint32_t kr = S.key[r];
+        const uint32_t kb = L == 1 ? S.blin[r] : 0u;
+        gid[j] = insert(key_slot(kr, kb, TBL), r, add, [&](uint32_t o) {
+          return S.key[o] == kr && (L != 1 || S.blin[o] == kb);
+        });
+      } else {
+        gid[j] = insert(level_hash(L, S.addr[r], S.blin[r], S.bw[r], S.w[r], tl[j] & 0x3FF) &
+                            (TBL - 1),
+                        r, add, [&](uint32_t o) { return level_eq(S, L, o, r); });
       }
-      atomicAdd(&S.cnt[h], (self || !(tl[j] & kSide)) ? 1u : 0x10000u);
-      gid[j] = h;
     }
     __syncthreads();
     if (L == f) {
-      // groups holding records of two different threads are marked (bit 31
-      // of the count: counts stay below 2^15 per side); the others pair only
-      // a thread with itself, which is no conflict at any level
+      // groups holding records of two different threads are marked (bit 48
+      // of the word); the others pair only a thread with itself, which is no
+      // conflict at any level
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const uint32_t r = tid + (uint32_t)j * NT;
         if (tl[j] & kInactive) continue;
-        const uint32_t o = S.owner[gid[j]];
+        const uint32_t o = (uint32_t)(slot[gid[j]] >> 32) & 0xFFF;
         if (o != r && (S.blin[o] != S.blin[r] || ((S.tli[o] ^ tl[j]) & 0x3FF)))
-          atomicOr(&S.cnt[gid[j]], kMultiThread);
+          atomicOr(&slot[gid[j]], 1ull << 48);
       }
       __syncthreads();
     }
+    // the next computed level, whose keys this count pass writes
+    int nx = L + 1;
+    while (nx < 6 && !comp[nx]) ++nx;
+    const bool nx_inc = nx < 6 && incl[nx];
     const int sign = (L & 1) ? -1 : 1;
     const uint32_t cls = L < 2 ? 1u : (L < 4 ? 2u : 4u);
     bool any_local = false;
@@ -683,8 +705,8 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
     for (int j = 0; j < RPT; ++j) {
       const uint32_t r = tid + (uint32_t)j * NT;
       if (tl[j] & kInactive) continue;
-      const uint32_t cw = S.cnt[gid[j]];
-      const uint32_t c = cw & ~kMultiThread;
+      const u64 cw = slot[gid[j]];
+      const uint32_t c = (uint32_t)cw;
       const bool sb = (tl[j] & kSide) != 0;
       // ordered pairs of the group: a self pair counts every record with
       // each of its group (itself included), a pair of two accesses each
@@ -696,7 +718,7 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
         // side (self pair: two records) and of two different threads; the
         // others' pairs (none, or only a thread with itself) count zero in
         // every class, so their share of S_f goes and they leave
-        const bool cand = (cw & kMultiThread) &&
+        const bool cand = ((cw >> 48) & 1) &&
                           (self ? ((c & 0xFFFF) >= 2) : ((c & 0xFFFF) && (c >> 16)));
         if (!cand) {
           tl[j] |= kInactive;
@@ -707,13 +729,14 @@ __device__ void lds_join(JoinLds<CAP, TBL>& S, const QDesc& qd, uint32_t sigma,
         }
         any_local = true;
       }
+      // key of the next level (and S_L slot of the synchronisation pass)
+      S.key[r] = (gid[j] << 16) | (nx_inc ? field(nx, r, tl[j]) : 0u);
       if (!self && sb) continue;
       const int32_t nj = (int32_t)(self ? (c & 0xFFFF) : (c >> 16));
       if (cls & mask) S.part[r] += sign * nj * (L == 0 && gmult > 1 ? 2 : 1);
       if (twin && ((cls << 1) & mask)) S.part[r] -= sign * nj;  // level L + 1
     }
     Sl[L] = L == 0 ? s * gmult : s;
-    P = L;
     if (L == f) {
       any = block_vote(any_local, &S.vote[2], 1u);
       if (!any) break;
