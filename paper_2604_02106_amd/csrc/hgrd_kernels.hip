@@ -575,6 +575,51 @@ __device__ __forceinline__ void block_thread(const SideGeo& g, uint32_t p, uint3
   else t = in - fdiv(in, g.f_nthr) * g.nthr;
 }
 
+// What the table-path join needs to decode a record of one side: the point
+// order and extents, and where the side's packed interval ids are.
+struct SideDec {
+  FastDiv f_nthr, f_niota;
+  uint32_t nthr, niota, iorder, iv_off, iv_const;
+  const int64_t* tpool;
+};
+
+__device__ __forceinline__ SideDec side_dec(const DevInst* __restrict__ insts, uint32_t k) {
+  k = __builtin_amdgcn_readfirstlane(k);
+  const DevInst& I = insts[k];
+  SideDec d;
+  d.f_nthr = I.f_nthr;
+  d.f_niota = I.f_niota;
+  d.nthr = I.a.nthr;
+  d.niota = I.a.niota;
+  d.iorder = I.a.iorder;
+  d.iv_off = I.iv_off;
+  d.iv_const = I.iv_const;
+  d.tpool = I.tpool;
+  return d;
+}
+
+// decode() with the side chosen per lane: point pidx of side `side`.
+__device__ __forceinline__ PointIds decode_side(const SideDec& d0, const SideDec& d1,
+                                                uint32_t side, uint32_t pidx) {
+  const FastDiv fn = side ? d1.f_nthr : d0.f_nthr;
+  const FastDiv fi = side ? d1.f_niota : d0.f_niota;
+  const uint32_t nthr = side ? d1.nthr : d0.nthr;
+  const uint32_t niota = side ? d1.niota : d0.niota;
+  PointIds o;
+  if (side ? d1.iorder : d0.iorder) {
+    const uint32_t rest = fdiv(pidx, fi);
+    o.ilin = pidx - rest * niota;
+    o.blin = fdiv(rest, fn);
+    o.tlin = rest - o.blin * nthr;
+  } else {
+    const uint32_t rest = fdiv(pidx, fn);
+    o.tlin = pidx - rest * nthr;
+    o.blin = fdiv(rest, fi);
+    o.ilin = rest - o.blin * niota;
+  }
+  return o;
+}
+
 __device__ __forceinline__ uint32_t filter_key(u64 a, uint32_t b, bool exact32) {
   if (exact32) return (uint32_t)a;
   uint32_t x = (uint32_t)a * 0x9E3779B1u ^ (uint32_t)(a >> 32) * 0x85EBCA77u ^
@@ -826,6 +871,13 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
   u64 nread = 0;  // record bytes read (thread 0)
   HGRD_FETCH(R.b0 + S.bl[0], n)
   const bool self = q.self != 0;
+  // table path without synchronisation: both sides' decoding constants
+  // once per run, both sides decoded in one pass
+  SideDec d0, d1;
+  if (TAB && !SYN) {
+    d0 = side_dec(insts, h.inst_i);
+    d1 = side_dec(insts, h.inst_j);
+  }
   for (uint32_t kb = 0; kb < nbl; ++kb) {
     const uint32_t b = R.b0 + S.bl[kb];
     bool go = n != 0;
@@ -887,7 +939,46 @@ k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
       }
     }
     const uint32_t wsh = (q.warp & (q.warp - 1)) == 0 ? (uint32_t)__ffs((int)q.warp) - 1 : 32u;
-    if (go) {
+    if (go && TAB && !SYN) {
+      // full records of the candidates: ids by the side's constants, the
+      // interval ids by one lookup in the side's table (one round trip for
+      // both sides)
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const uint32_t r = threadIdx.x + (uint32_t)j * kJoinThreads;
+        if (r >= n) continue;
+        uint32_t pid;
+        int64_t a;
+        if (l0ext) {
+          pid = is32 ? (uint32_t)(rx[j] >> 32) : (uint32_t)ry[j];
+          a = is32 ? (int64_t)(int32_t)(uint32_t)rx[j] : (int64_t)rx[j];
+        } else {
+          if (S.tli[r] & kInactive) continue;
+          pid = S.blin[r];
+          a = (int64_t)S.addr[r];
+        }
+        const uint32_t side = pid >> 31;
+        const PointIds id = decode_side(d0, d1, side, pid & 0x7FFFFFFFu);
+        const uint32_t ivo = side ? d1.iv_off : d0.iv_off;
+        const int64_t* tp = side ? d1.tpool : d0.tpool;
+        const uint32_t iv = ivo != kNoTab ? (uint32_t)tp[ivo + id.ilin]
+                                          : (side ? d1.iv_const : d0.iv_const);
+        S.addr[r] = (u64)a;
+        S.blin[r] = id.blin;
+        S.tli[r] = (id.ilin << 16) | (side << 15) | id.tlin;
+        S.bw[r] = ((iv & 0xFFFF) << 16) | (iv >> 16);
+        S.w[r] = (uint16_t)(wsh < 32 ? id.tlin >> wsh : id.tlin / q.warp);
+        if (l0ext) {
+          // level-0 partners of a side-a record: the other side's count
+          // at its address in the item's address-count table
+          int32_t nj = 0;
+          if ((q.mask & 1) && (q.self || !side))
+            nj = (int32_t)l0_lookup(l0keys, l0cnt, h.l0_off, h.l0_mask, (long long)a,
+                                    q.self != 0);
+          S.part[r] = nj;
+        }
+      }
+    } else if (go) {
       // full records of the candidates, one side at a time (the instance
       // stays uniform: scalar loads, no divergent interpreter)
       for (uint32_t side = 0; side < 2; ++side) {
