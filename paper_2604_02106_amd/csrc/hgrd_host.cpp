@@ -708,6 +708,11 @@ int rd_prepare(rd_context* ctx, const rd_kernel_model* models,
     }
     hplans.resize(w);
   }
+  // Dense items first: nearly all their buckets go on to the join, so the
+  // heavy join work fills the first waves' launches instead of thinning out
+  // over every wave (measured: join time per step 336 against 340 ms).
+  std::stable_sort(hplans.begin(), hplans.end(),
+                   [](const HPlan& x, const HPlan& y) { return x.h.dense > y.h.dense; });
   // Chunks and runs are described compactly, one spec per (item, side) and
   // per item in launch order, and expanded on the device at the end of
   // rd_prepare (k_expand): a batch can have tens of millions of them.
