@@ -101,6 +101,31 @@ def test_sync_pins(hg, G, B, w, sync_path):
         assert st["sync_records"] == 0 and st["hbm_items"] > 0
 
 
+def test_sync_every_level_and_pass(hg, sync_path):
+    """Every level of the LDS join computed (barrier and warp-barrier
+    interval ids that change with the iteration, so no level repeats the
+    previous one), all three classes asked, and device- and block-scope
+    acquires and releases on the records, so a synchronisation pass follows
+    each level: the join uses its most table generations; every field
+    equals the oracle's."""
+    loops = [Loop(0, "lt", 3)]
+    iv = dict(loops=[0], bint=loop(0), wint=loop(0) * 2 + 1)
+    accs = [
+        Access(0, WRITE, tid() % 16, **iv, **lock(mod(tid(), 2))),                  # 0
+        Access(0, READ, tid() % 16, **iv, **lock(c(0), sa=BLK, sr=BLK)),            # 1
+        Access(0, WRITE, (tid() + 1) % 16, **iv, **lock(mod(tid(), 2), sa=DEV, sr=BLK)),  # 2
+    ]
+    m = Model(0, ARRAYS, accs, Launch((6, 1, 1), (64, 1, 1), 16), [[]], loops=loops)
+    wl = Workload([m], [(0, 0, 0, 7), (0, 0, 1, 7), (0, 1, 2, 7), (0, 0, 2, 7), (0, 2, 2, 7)])
+    got = run_both(hg, wl, "sync every level %s" % sync_path)
+    # threads 16 apart share an address and a parity lock: no race in (0, 0)
+    assert got[0]["verdict"] == 0 and all(r["verdict"] for r in got[1:])
+    st = hg.default_context().stats()
+    say("sync records", st["sync_records"], "hbm items", st["hbm_items"])
+    if sync_path == "lds":
+        assert st["sync_records"] == 0 and st["hbm_items"] > 0
+
+
 @pytest.mark.parametrize("seed", range(30))
 def test_sync_random(hg, seed, sync_path):
     run_both(hg, rand_sync_workload(seed), "sync rand seed=%d %s" % (seed, sync_path))
