@@ -402,8 +402,8 @@ void rd_context_destroy(rd_context* ctx);
  * pairs, each its own plan: batch k + 1 is prepared on a host thread, on a
  * second context of the same device that ctx creates on first use and
  * keeps until rd_context_destroy, while batch k runs on ctx's stream, so
- * host lowering overlaps device work.  Not when opt->stream is set (one
- * plan, in stream order).  The results are those of one plan; rd_get_stats
+ * host lowering overlaps device work.  Not when opt->stream is set, nor
+ * when that second context cannot be created (then one plan for all).  The results are those of one plan; rd_get_stats
  * then reports the sums over the batches (total_ms: the whole call). */
 int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
                    uint32_t n_models, const rd_access_pair* pairs,

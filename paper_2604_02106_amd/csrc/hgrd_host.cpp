@@ -1742,7 +1742,11 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
   if (n_pairs && !out) return RD_EINVAL;
   uint64_t B = kBatchPairs;
   if (const char* e = getenv("HGRD_BATCH_PAIRS")) B = strtoull(e, nullptr, 10);
-  if (B == 0 || n_pairs <= B || ctx->arena || (opt && opt->stream) || !pairs) {
+  // (a second context that cannot be created leaves one plan for all)
+  if (B && n_pairs > B && !ctx->arena && !(opt && opt->stream) && pairs && !ctx->aux &&
+      rd_context_create(&ctx->aux, ctx->device) != RD_OK)
+    ctx->aux = nullptr;
+  if (B == 0 || n_pairs <= B || ctx->arena || (opt && opt->stream) || !pairs || !ctx->aux) {
     rd_plan* plan = nullptr;
     int rc = rd_prepare(ctx, models, n_models, pairs, n_pairs, launch, params, opt, &plan);
     if (rc != RD_OK) return rc;
@@ -1751,10 +1755,6 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
     return rc;
   }
   const double t0 = now_ms();
-  if (!ctx->aux) {
-    const int rc = rd_context_create(&ctx->aux, ctx->device);
-    if (rc != RD_OK) return rc;
-  }
   ctx->aux->cfg = ctx->cfg;
   ctx->aux->wave_bytes = ctx->wave_bytes;
   rd_context* C[2] = {ctx, ctx->aux};
