@@ -784,12 +784,13 @@ k_bucket_filter(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
 
 constexpr uint32_t kJoinThreads = 512;  // bucket-join workgroup size
 
-// Workgroups of the bucket join that the LDS of one CU holds (160 KiB):
-// the register budget of the table-path join is set so that as many fit by
+// Workgroups of the bucket join that the LDS of one CU holds (160 KiB; the
+// synchronised join also holds a synchronisation address per record): the
+// register budget of the table-path joins is set so that as many fit by
 // registers too (the interpreter path keeps its registers: no spills).
-template <int CAP, int TBL>
+template <int CAP, int TBL, bool SYN = false>
 constexpr uint32_t join_waves_per_simd() {
-  return 2u * (uint32_t)(163840 / sizeof(JoinLds<CAP, TBL>));
+  return 2u * (uint32_t)(163840 / (sizeof(JoinLds<CAP, TBL>) + (SYN ? CAP * sizeof(u64) : 0)));
 }
 
 // One workgroup joins a run of buckets of one item.  The item's header,
@@ -801,7 +802,7 @@ constexpr uint32_t join_waves_per_simd() {
 // (interval ids by lookup, no interpreter code).
 template <int CAP, int TBL, bool TAB, bool SYN = false>
 __global__ void __launch_bounds__(kJoinThreads)
-__attribute__((amdgpu_waves_per_eu(TAB && !SYN ? join_waves_per_simd<CAP, TBL>() : 1u)))
+__attribute__((amdgpu_waves_per_eu(TAB ? join_waves_per_simd<CAP, TBL, SYN>() : 1u)))
 k_bucket_join(const BRun* __restrict__ runs, const HItem* __restrict__ hitems,
               const DevInst* __restrict__ insts, const DInsn* __restrict__ code,
               const int64_t* __restrict__ params,
