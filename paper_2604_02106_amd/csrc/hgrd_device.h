@@ -483,9 +483,10 @@ __device__ __forceinline__ bool level_eq(const JoinLds<CAP, TBL>& S, int L,
 // Level L groups refine level L - 1 groups, so after the first level a
 // record's group at L is (its group at the previous level, the one field
 // that L adds): the previous group's table slot and that field make a
-// 32-bit key (the block, 32 bits itself, is compared beside the key).  Each
-// insert then costs one compare-and-swap and one read; the first level
-// compares the fields themselves.
+// 32-bit key (the block, 32 bits itself, is compared beside the key),
+// written during the previous level's count pass.  An insert reads its
+// slot, then claims it with one compare-and-swap or compares the owner's
+// key and adds its count; the first level compares the fields themselves.
 //
 // l0ext: the records hold whole (address, block) groups but not whole
 // address groups; level 0 (S_0, the address-only sums) is counted elsewhere
