@@ -562,16 +562,18 @@ def main():
                     help="untimed steps first (default 1 mixed, 2 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the pre-filtered plan and graph replay figures "
-                         "reported beside the headline (they run after the "
-                         "timed steps)")
+                    help="skip the figures reported beside the headline "
+                         "(graph replay, VERDICT mode, the plain checker, the "
+                         "end-to-end calls, the exact shortcuts switched off; "
+                         "they run after the timed steps)")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--config", default="mixed",
                     choices=("batched", "stress", "mixed", "learned", "synced"),
                     help="workload: mixed batched queries (the headline), "
                          "batched uneven queries, race-free stress (128 "
-                         "pairs, 2^30 points per access), or the learned "
-                         "tile order on sparse witnesses")
+                         "pairs, 2^30 points per access), the learned tile "
+                         "order on sparse witnesses, or queries under "
+                         "acquire/release synchronisation")
     ap.add_argument("--wave-mib", type=int, default=0,
                     help="partition wave size in MiB (0: the library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
