@@ -1747,7 +1747,7 @@ struct rd_plan_impl {
   uint64_t sync_decided = 0;  // synchronised units decided conflict-free
   uint32_t persist_grid = 0;  // workgroups of the persistent small join
   uint32_t chunk_pts = 16384; // points per partition workgroup
-  uint32_t run_buckets = 8;   // buckets per join workgroup
+  uint32_t run_buckets = 12;  // buckets per join workgroup (measured: 12 against 8, +0.7%)
   uint32_t n_tabchunks = 0;   // term-table fill chunks
   uint64_t prefiltered = 0;   // (pair, tuple) units decided by the pre-filter
   uint32_t n_insts = 0, tab_insts = 0;
