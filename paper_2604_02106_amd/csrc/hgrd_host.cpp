@@ -1767,16 +1767,23 @@ int rd_check_pairs(rd_context* ctx, const rd_kernel_model* models,
   for (uint32_t k = 0; rc == RD_OK && k < nb; ++k) {
     rd_plan* next = nullptr;
     int rc_next = RD_OK;
+    auto prep_next = [&, k] {
+      rc_next = rd_prepare(C[(k + 1) & 1], models, n_models, pairs + (k + 1) * B, count(k + 1),
+                           launch, params, opt, &next);
+    };
     std::thread th;
-    if (k + 1 < nb)
-      th = std::thread([&, k] {
-        rc_next = rd_prepare(C[(k + 1) & 1], models, n_models, pairs + (k + 1) * B, count(k + 1),
-                             launch, params, opt, &next);
-      });
+    if (k + 1 < nb) {
+      try {
+        th = std::thread(prep_next);
+      } catch (...) {
+        // no host thread: the next batch is prepared after this one runs
+      }
+    }
     rc = rd_execute(C[k & 1], cur, out + k * B);
     add_stats(total, C[k & 1]->stats);
     rd_plan_destroy(cur);
     if (th.joinable()) th.join();
+    else if (k + 1 < nb && rc == RD_OK) prep_next();
     if (rc == RD_OK) rc = rc_next;
     cur = next;
   }
